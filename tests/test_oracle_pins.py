@@ -1,0 +1,439 @@
+"""Pins of the FP64 oracle against facts fixed by the paper or by the
+mathematics, independent of the oracle's own formulas (CPU only)."""
+import math
+
+import numpy as np
+import pytest
+
+import fas_inputs as fi
+from oracle import gas, fas, smoother, precond, residual
+from oracle.geometry import Level, NG, build_levels
+
+GAMMA = 1.4
+
+
+def _solver(x, y, topo, nw, model=0, mach=0.8, alpha=0.0, L=1, u=None, **kw):
+    par = fas.Params(model=model, mach=mach, alpha_deg=alpha, n_levels=L, **kw)
+    nj, ni = x.shape[0] - 1, x.shape[1] - 1
+    if u is None:
+        u = fi.uniform_state(ni, nj, mach, alpha)
+    return fas.Solver(x, y, topo, nw, par, u)
+
+
+def _flux_scale(lev):
+    """Sum of face lengths of every cell (to make F*Omega dimensionless)."""
+    li = np.hypot(lev.Sxi[0], lev.Sxi[1])
+    lj = np.hypot(lev.Seta[0], lev.Seta[1])
+    return (li[:, :-1] + li[:, 1:]) + (lj[:-1, :] + lj[1:, :])
+
+
+# ---------------------------------------------------------------- P1 free stream
+def test_freestream_preserved_box():
+    x, y = fi.box_grid(16, 12, ratio=1.2)
+    S = _solver(x, y, fi.BOX, 0, mach=0.8, alpha=0.0)
+    F = S.residual(0)
+    lev = S.levels[0]
+    rel = np.abs(F).max(axis=0) * lev.vol / _flux_scale(lev)
+    assert rel.max() < 1e-14
+
+
+@pytest.mark.parametrize("model,alpha", [(0, 0.0), (1, 0.0), (1, 2.5)])
+def test_freestream_preserved_cgrid(model, alpha):
+    """Uniform flow: every cell except the two wall rows of the airfoil
+    columns (where the wall is inconsistent with the uniform state) has
+    F = 0, including the wake cut and the outflow/far-field boundaries."""
+    x, y = fi.cgrid(64, 32, 8)
+    S = _solver(x, y, fi.CGRID, 8, model=model, alpha=alpha, reynolds=1e7)
+    F = S.residual(0)
+    lev = S.levels[0]
+    rel = np.abs(F).max(axis=0) * lev.vol / _flux_scale(lev)
+    mask = np.ones_like(rel, dtype=bool)
+    wall = ~lev.cut_mask()
+    mask[:2, wall] = False
+    if model == 1:
+        # the first wake cells share the trailing-edge vertex with the
+        # no-slip wall, whose dual cell sees the wall's velocity gradient
+        mask[:2, [7, 56]] = False
+    assert rel[mask].max() < 1e-13
+    assert rel[~mask].max() > 1e-6          # the wall really is felt
+
+
+# ---------------------------------------------------------------- P2 conservation
+@pytest.mark.parametrize("topo", [fi.BOX, fi.CGRID])
+def test_conservation_interior_faces_cancel(topo):
+    """A perturbation kept 4 cells away from every boundary leaves all
+    boundary fluxes at their free-stream values, whose sum over the closed
+    boundary vanishes; so sum_c Omega_c F_c = 0 up to rounding."""
+    if topo == fi.BOX:
+        x, y = fi.box_grid(24, 20)
+        ni, nj, nw = 24, 20, 0
+        region = (slice(5, 14), slice(5, 18))
+    else:
+        x, y = fi.cgrid(64, 32, 8)
+        ni, nj, nw = 64, 32, 8
+        region = (slice(0, 10), np.r_[4:8, 56:60])      # around the wake cut
+    u = fi.uniform_state(ni, nj, 0.8, 0.0)
+    rng = np.random.default_rng(7)
+    pert = np.zeros_like(u)
+    jj, ii = np.meshgrid(np.arange(nj), np.arange(ni), indexing="ij")
+    m = np.zeros((nj, ni), dtype=bool)
+    m[region[0], region[1]] = True
+    pert[:, m] = rng.uniform(-0.02, 0.02, size=(4, m.sum()))
+    u = u * (1.0 + pert)
+    S = _solver(x, y, topo, nw, model=0, u=u)
+    F = S.residual(0)
+    lev = S.levels[0]
+    tot = (F * lev.vol).sum(axis=(1, 2))
+    scale = (np.abs(F) * lev.vol).sum(axis=(1, 2))
+    assert np.all(np.abs(tot) <= 1e-13 * scale + 1e-300)
+    assert scale.min() > 0.0
+
+
+# ---------------------------------------------------------------- P3 Jacobian
+def _random_states(n, seed=3):
+    rng = np.random.default_rng(seed)
+    rho = rng.uniform(0.5, 2.0, n)
+    vx = rng.uniform(-1.5, 1.5, n)
+    vy = rng.uniform(-1.5, 1.5, n)
+    p = rng.uniform(0.3, 3.0, n)
+    U = fi.primitive_to_conservative(rho, vx, vy, p)
+    th = rng.uniform(0, 2 * np.pi, n)
+    return U, np.cos(th), np.sin(th)
+
+
+def test_flux_jacobian_complex_step():
+    U, nx, ny = _random_states(40)
+    A = gas.flux_jacobian(U, nx, ny)
+    h = 1e-30
+    for k in range(4):
+        Uc = U.astype(complex)
+        Uc[k] += 1j * h
+        p = (GAMMA - 1.0) * (Uc[3] - 0.5 * (Uc[1] * Uc[1] + Uc[2] * Uc[2]) / Uc[0])
+        Fn = gas.normal_flux(Uc, p, nx, ny)
+        col = Fn.imag / h
+        assert np.allclose(A[:, :, k], col.T, rtol=1e-13, atol=1e-13)
+
+
+def test_euler_flux_homogeneity():
+    """F.n = A_n u, an exact property of the Euler flux (degree-1 homogeneous)."""
+    U, nx, ny = _random_states(40)
+    A = gas.flux_jacobian(U, nx, ny)
+    Fn = gas.normal_flux(U, gas.pressure(U), nx, ny)
+    assert np.allclose(np.einsum("nij,jn->in", A, U), Fn, rtol=1e-13, atol=1e-13)
+
+
+def test_eigensystem_and_splitting():
+    U, nx, ny = _random_states(40)
+    A = gas.flux_jacobian(U, nx, ny)
+    lam, R, L, a = gas.eigensystem(U, nx, ny)
+    assert np.allclose(np.einsum("nij,njk->nik", R, L), np.eye(4), atol=1e-12)
+    assert np.allclose(np.einsum("nij,njk->nik", A, R), R * lam[:, None, :], atol=1e-12)
+    Ap, Am = gas.split_jacobians(U, nx, ny, 0.0)
+    assert np.allclose(Ap + Am, A, atol=1e-13)
+    for n in range(U.shape[1]):
+        # |A| against an independent eigen-decomposition (numpy)
+        w, V = np.linalg.eig(A[n])
+        absA = (V * np.abs(w)) @ np.linalg.inv(V)
+        assert np.allclose(Ap[n] - Am[n], absA.real, atol=1e-11)
+        assert np.linalg.eigvals(Ap[n]).real.min() > -1e-12
+        assert np.linalg.eigvals(Am[n]).real.max() < 1e-12
+
+
+# ---------------------------------------------------------------- P4 cutoff
+def test_cutoff_continuous_value_and_slope():
+    a = np.array([1.3])
+    d = 0.5
+    ad = a[0] * d
+    eps = 1e-7
+    lo = gas.cutoff_abs(np.array([[ad - eps]]), a, d)[0, 0]
+    hi = gas.cutoff_abs(np.array([[ad + eps]]), a, d)[0, 0]
+    mid = gas.cutoff_abs(np.array([[ad]]), a, d)[0, 0]
+    assert mid == pytest.approx(ad, abs=1e-15)
+    assert (hi - lo) / (2 * eps) == pytest.approx(1.0, abs=1e-6)
+    assert gas.cutoff_abs(np.array([[0.0]]), a, d)[0, 0] == pytest.approx(0.5 * ad)
+
+
+# ---------------------------------------------------------------- P5 gradients
+@pytest.mark.parametrize("topo", [fi.BOX, fi.CGRID])
+def test_green_gauss_exact_for_linear_fields(topo):
+    if topo == fi.BOX:
+        x, y = fi.box_grid(12, 10, ratio=1.3)
+        lev = Level(x, y, topo, 0)
+    else:
+        x, y = fi.cgrid(32, 16, 4)
+        lev = Level(x, y, topo, 4)
+    phi = 0.3 + 1.7 * lev.xc - 2.9 * lev.yc
+    (gx, gy), = residual.vertex_gradients(lev, [phi])
+    # rounding: O(1) coordinates differenced over dual cells 1e-6 thick
+    tol = 1e-11 if topo == fi.BOX else 1e-9
+    assert np.allclose(gx, 1.7, rtol=tol, atol=0)
+    assert np.allclose(gy, -2.9, rtol=tol, atol=0)
+
+
+# ---------------------------------------------------------------- P6 frame invariance
+def test_rotation_invariance():
+    x, y = fi.box_grid(16, 12)
+    u = fi.box_initial_state(x, y, mach=0.7, alpha_deg=0.0)
+    th = 0.37
+    c, s = math.cos(th), math.sin(th)
+    S0 = _solver(x, y, fi.BOX, 0, model=0, mach=0.7, alpha=0.0, u=u)
+    ur = u.copy()
+    ur[1] = c * u[1] - s * u[2]
+    ur[2] = s * u[1] + c * u[2]
+    S1 = _solver(c * x - s * y, s * x + c * y, fi.BOX, 0, model=0, mach=0.7,
+                 alpha=math.degrees(th), u=ur)
+    F0 = S0.residual(0)
+    F1 = S1.residual(0)
+    F0r = F0.copy()
+    F0r[1] = c * F0[1] - s * F0[2]
+    F0r[2] = s * F0[1] + c * F0[2]
+    scale = np.abs(F0).max()
+    assert np.abs(F1 - F0r).max() < 1e-11 * scale
+
+
+# ---------------------------------------------------------------- P7 symmetry
+@pytest.mark.parametrize("model", [0, 1])
+def test_mirror_symmetry_cgrid(model):
+    """Symmetric section at alpha = 0: the residual of the mirrored state
+    is the mirrored residual (i -> ni-1-i, y -> -y)."""
+    ni, nj, nw = 64, 32, 8
+    x, y = fi.cgrid(ni, nj, nw)
+    u = fi.perturbed_state(fi.uniform_state(ni, nj, 0.8, 0.0), 0.01, seed=5)
+    um = u[:, :, ::-1].copy()
+    um[2] = -um[2]
+    S0 = _solver(x, y, fi.CGRID, nw, model=model, u=u)
+    S1 = _solver(x, y, fi.CGRID, nw, model=model, u=um)
+    F0 = S0.residual(0)
+    F1 = S1.residual(0)
+    Fm = F0[:, :, ::-1].copy()
+    Fm[2] = -Fm[2]
+    scale = np.abs(F0).max(axis=0)
+    assert np.all(np.abs(F1 - Fm).max(axis=0) <= 1e-10 * scale + 1e-12 * scale.max())
+
+
+# ---------------------------------------------------------------- P8 / P9 SGS
+@pytest.mark.parametrize("topo,ni,nj,nw", [(fi.BOX, 6, 4, 0), (fi.CGRID, 12, 4, 2)])
+def test_sgs_matches_dense_solve(topo, ni, nj, nw):
+    x, y = fi.box_grid(ni, nj) if topo == fi.BOX else fi.cgrid(ni, nj, nw)
+    u = fi.perturbed_state(fi.uniform_state(ni, nj, 0.8, 1.0), 0.02, seed=1)
+    S = _solver(x, y, topo, nw, model=0, alpha=1.0, u=u, cfl=50.0, cfl_ramp=50.0)
+    _, dts, _, B = S.prepare(0)
+    rng = np.random.default_rng(2)
+    r = rng.standard_normal((4, nj, ni))
+    DL, DD, DU = B.dense()
+    P = DL @ np.linalg.solve(DD, DU)
+    rc = np.moveaxis(r, 0, -1).reshape(-1)
+    xd = np.linalg.solve(P, rc)
+    xs = np.moveaxis(B.apply(r), 0, -1).reshape(-1)
+    assert np.abs(xs - xd).max() <= 1e-13 * np.abs(xd).max()
+    if topo == fi.CGRID:       # the cut coupling is really in the operator
+        assert np.count_nonzero(DU[:4, 4 * (ni - 1):4 * ni]) > 0
+
+
+def test_hyperplane_order_is_bitwise_lexicographic():
+    ni, nj, nw = 32, 8, 4
+    x, y = fi.cgrid(ni, nj, nw)
+    u = fi.perturbed_state(fi.uniform_state(ni, nj, 0.8, 1.0), 0.02, seed=1)
+    S = _solver(x, y, fi.CGRID, nw, model=0, alpha=1.0, u=u)
+    _, _, _, B = S.prepare(0)
+    r = np.random.default_rng(4).standard_normal((4, nj, ni))
+    assert np.array_equal(B.forward(r), B.forward(r, hyperplane=True))
+
+
+def test_cartesian_blocks_match_printed_formulas():
+    """On an unjittered Cartesian box the blocks reduce to eqs.
+    "d-l-u-matrices-W": L = -(eta dt*/Omega)(dy A+ + dx B+),
+    U = (eta dt*/Omega)(dy A- + dx B-), D = I + (eta dt*/Omega)[dy (A+ - A-)
+    + dx (B+ - B-)] with A, B the x / y Jacobians at the face states."""
+    ni, nj = 5, 4
+    x, y = fi.box_grid(ni, nj, ratio=1.0, jitter=0.0)
+    u = fi.perturbed_state(fi.uniform_state(ni, nj, 0.8, 3.0), 0.03, seed=9)
+    S = _solver(x, y, fi.BOX, 0, model=0, alpha=3.0, u=u)
+    _, dts, _, B = S.prepare(0)
+    Up = S.padded(0, u)
+    dx, dy = 1.0 / ni, 1.0 / nj
+    eta = S.par.eta
+    j, i = 2, 2
+    c = eta * dts[j, i] / (dx * dy)
+    def split(UL, UR, nx, ny):
+        return gas.split_jacobians(0.5 * (UL + UR), nx, ny, S.par.d_cut)
+    P = NG
+    C = Up[:, P + j, P + i]
+    Ap_w, Am_w = split(Up[:, P + j, P + i - 1], C, 1.0, 0.0)
+    Ap_e, Am_e = split(C, Up[:, P + j, P + i + 1], 1.0, 0.0)
+    Bp_s, Bm_s = split(Up[:, P + j - 1, P + i], C, 0.0, 1.0)
+    Bp_n, Bm_n = split(C, Up[:, P + j + 1, P + i], 0.0, 1.0)
+    cidx = j * ni + i
+    assert np.allclose(B.B[cidx, 0], -c * dy * Ap_w, rtol=1e-12, atol=1e-12 * c)
+    assert np.allclose(B.B[cidx, 2], -c * dx * Bp_s, rtol=1e-12, atol=1e-12 * c)
+    assert np.allclose(B.B[cidx, 1], c * dy * Am_e, rtol=1e-12, atol=1e-12 * c)
+    assert np.allclose(B.B[cidx, 3], c * dx * Bm_n, rtol=1e-12, atol=1e-12 * c)
+    D = np.eye(4) + c * (dy * (Ap_e - Am_w) + dx * (Bp_n - Bm_s))
+    assert np.allclose(B.D[cidx], D, rtol=1e-12, atol=1e-12 * c)
+
+
+# ---------------------------------------------------------------- P10 stage logic
+@pytest.mark.parametrize("scheme", [smoother.AW3, smoother.PARK3J])
+def test_three_stage_amplification_closed_form(scheme):
+    """Periodic scalar advection u_t + u_x = 0, central f^c, fourth-difference
+    f^v, uniform dt*, exact W = I + eta dt* H (or P = H).  One iteration of
+    the low-storage algorithm on a Fourier mode multiplies it by the
+    printed 3-stage operator G (Section 5.2) with scalar symbols."""
+    n = 16
+    eps4 = 0.07
+    I = np.eye(n)
+    E = np.roll(I, 1, axis=1)          # (E u)_j = u_{j+1}
+    Em = E.T
+    Hc = 0.5 * (E - Em)
+    Hv = eps4 * (E @ E - 4 * E + 6 * I - 4 * Em + Em @ Em)
+    dts, eta = 0.9, 0.8
+    alpha, beta, aw = smoother.SCHEMES[scheme]
+    if aw:
+        W = I + eta * dts * (Hc + Hv)
+        inc = lambda r: np.linalg.solve(W, dts * r)
+        Pinv = np.linalg.inv(W) * dts
+    else:
+        P = Hc + Hv + 0.3 * I
+        inc = lambda r: dts * np.linalg.solve(P, r)
+        Pinv = dts * np.linalg.inv(P)
+    for k in (1, 3, 6):
+        th = 2 * np.pi * k / n
+        mode = np.exp(1j * th * np.arange(n))
+        out = smoother.additive_iteration(mode, lambda v: (Hc @ v, Hv @ v), inc, alpha, beta)
+        g = out[0] / mode[0]
+        assert np.allclose(out, g * mode, atol=1e-13)
+        # scalar symbols of P^-1 H_c, P^-1 H_v (dt* already inside)
+        hc = (Pinv @ Hc @ mode)[0] / mode[0]
+        hv = (Pinv @ Hv @ mode)[0] / mode[0]
+        a1, a2, a3 = alpha
+        b2, b3 = beta[1], beta[2]
+        G = 1 - a3 * ((hc + b3 * hv) * (1 - a2 * ((hc + b2 * hv) * (1 - a1 * (hc + hv))
+                                                   + (1 - b2) * hv))
+                      + (1 - b3) * (b2 * hv * (1 - a1 * (hc + hv)) + (1 - b2) * hv))
+        assert abs(g - G) < 1e-13
+
+
+def test_local_time_step_ordering_reading():
+    """With a cell-varying dt*, applying W^-1 to dt* F (the W step of the
+    locally time-stepped problem) gives a convergent linear smoother with
+    the exact W on a stretched box, while dt* (W^-1 F) does not."""
+    ni, nj = 12, 12
+    x, y = fi.box_grid(ni, nj, ratio=2.0)
+    u0 = fi.uniform_state(ni, nj, 0.8, 1.0)
+    S = _solver(x, y, fi.BOX, 0, model=0, alpha=1.0, u=u0, cfl=1e4, cfl_ramp=1e4)
+    _, dts, mutp, B = S.prepare(0)
+    n = 4 * ni * nj
+    v0 = np.moveaxis(u0, 0, -1).reshape(-1)
+
+    def split_lin(v):
+        uu = np.moveaxis(v.reshape(nj, ni, 4), -1, 0)
+        Fc, Fv = S.split(0, uu, mutp)
+        return np.moveaxis(Fc, 0, -1).reshape(-1), np.moveaxis(Fv, 0, -1).reshape(-1)
+    Jc = np.zeros((n, n))
+    Jv = np.zeros((n, n))
+    h = 1e-7
+    for k in range(n):
+        e = np.zeros(n)
+        e[k] = h * max(1.0, abs(v0[k]))
+        a1, b1 = split_lin(v0 + e)
+        a2, b2 = split_lin(v0 - e)
+        Jc[:, k] = (a1 - a2) / (2 * e[k])
+        Jv[:, k] = (b1 - b2) / (2 * e[k])
+    dt = np.moveaxis(np.broadcast_to(dts, (4, nj, ni)), 0, -1).reshape(-1)
+    W = np.eye(n) + 0.5 * dt[:, None] * (Jc + Jv)
+    Wi = np.linalg.inv(W)
+    al, be, _ = smoother.SCHEMES[smoother.AW3]
+
+    def rho(inc):
+        M = np.zeros((n, n))
+        for k in range(n):
+            e = np.zeros(n)
+            e[k] = 1.0
+            M[:, k] = smoother.additive_iteration(e, lambda v: (Jc @ v, Jv @ v), inc, al, be)
+        return np.abs(np.linalg.eigvals(M)).max()
+    assert rho(lambda r: Wi @ (dt * r)) < 0.6
+    assert rho(lambda r: dt * (Wi @ r)) > 1.0
+
+
+# ---------------------------------------------------------------- FAS pins
+def test_transfers_constants_and_conservation():
+    x, y = fi.cgrid(32, 16, 4)
+    lev = build_levels(x, y, fi.CGRID, 4, 2)
+    v = np.random.default_rng(3).standard_normal((4, 16, 32))
+    r = fas.restrict(lev[0], lev[1], v)
+    assert np.allclose((r * lev[1].vol).sum(axis=(1, 2)), (v * lev[0].vol).sum(axis=(1, 2)),
+                       rtol=1e-13)
+    c = np.ones((4, 8, 16)) * np.array([1.0, 2.0, -3.0, 0.5])[:, None, None]
+    assert np.allclose(fas.prolong(lev[0], lev[1], c), np.repeat(np.repeat(c, 2, 1), 2, 2))
+    assert np.allclose(fas.restrict(lev[0], lev[1], np.repeat(np.repeat(c, 2, 1), 2, 2)), c)
+
+
+def test_coarse_forcing_identity():
+    """At the start of coarse smoothing F_c(R u) - s_c = -R r_f."""
+    ni, nj, nw = 32, 16, 4
+    x, y = fi.cgrid(ni, nj, nw)
+    u = fi.perturbed_state(fi.uniform_state(ni, nj, 0.8, 1.0), 0.01, seed=3)
+    S = _solver(x, y, fi.CGRID, nw, model=1, alpha=1.0, L=2, u=u)
+    seen = {}
+    orig = S.cycle
+
+    def spy(l=0):
+        if l == 1 and "v" not in seen:
+            seen["v"] = S.residual(1)
+            F = S.residual(0, u=seen.get("uf"))
+            seen["Rr"] = fas.restrict(S.levels[0], S.levels[1], -F)
+        return orig(l)
+    S.cycle = spy
+    S.smooth(0)
+    seen["uf"] = S.u(0)
+    S.smooth = lambda l=0, cfl=None: None      # isolate the transfer step
+    orig(0)
+    v, Rr = seen["v"], seen["Rr"]
+    assert np.abs(v + Rr).max() <= 1e-12 * np.abs(Rr).max()
+
+
+def test_fas_single_level_equals_smoother():
+    x, y = fi.box_grid(12, 10)
+    u = fi.box_initial_state(x, y)
+    A = _solver(x, y, fi.BOX, 0, model=0, u=u)
+    B = _solver(x, y, fi.BOX, 0, model=0, u=u)
+    A.cycle(0)
+    B.smooth(0)
+    assert np.array_equal(A.u(0), B.u(0))
+
+
+# ---------------------------------------------------------------- P16 scaling
+def test_nondimensionalisation_reproduces_printed_time_step():
+    """Section 6.4 prints dt = 0.486822 for the RAE case (M = 0.75,
+    reduced frequency 0.202 = omega c / (2 V), 36 steps per period)."""
+    uinf = gas.freestream(0.75, 0.0)
+    V = uinf[1]
+    omega = 2.0 * 0.202 * V / 1.0
+    dt = 2.0 * np.pi / omega / 36.0
+    assert dt == pytest.approx(0.486822, abs=1e-6)      # printed to 6 digits
+
+
+def test_printed_dfa_states_are_mach_08():
+    """Section 5.4: (1, sqrt2/2, sqrt2/2, 3.290) and (1, 1, 0, 3.290) are
+    Mach 0.8 states (to the printed digits)."""
+    for U in (np.array([1.0, math.sqrt(0.5), math.sqrt(0.5), 3.290]),
+              np.array([1.0, 1.0, 0.0, 3.290])):
+        p = gas.pressure(U)
+        a = math.sqrt(GAMMA * p / U[0])
+        assert math.hypot(U[1], U[2]) / U[0] / a == pytest.approx(0.8, abs=1e-4)
+
+
+# ---------------------------------------------------------------- BL sanity
+def test_baldwin_lomax_zero_in_uniform_flow_and_nonnegative():
+    ni, nj, nw = 64, 32, 8
+    x, y = fi.cgrid(ni, nj, nw)
+    S = _solver(x, y, fi.CGRID, nw, model=1, alpha=1.0)
+    Up = S.padded(0, S.u(0))
+    mut = residual.baldwin_lomax(S.levels[0], Up, S.par)
+    assert np.all(mut >= 0.0)
+    cut = S.levels[0].cut_mask()
+    assert np.all(mut[:, cut][2:] == 0.0) or np.abs(mut[:, cut]).max() < 1e-30
+    u = fi.perturbed_state(S.u(0), 0.05, seed=11)
+    Up = S.padded(0, u)
+    mut = residual.baldwin_lomax(S.levels[0], Up, S.par)
+    assert np.all(np.isfinite(mut)) and np.all(mut >= 0.0) and mut.max() > 0.0
