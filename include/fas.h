@@ -1,0 +1,152 @@
+/*
+ * fas.h - C ABI of the MI355X library for preconditioned FAS smoothers of
+ * the 2-D cell-centred finite-volume Euler / Baldwin-Lomax RANS equations
+ * (Birken, Bull, Jameson, "Preconditioned smoothers for the full
+ * approximation scheme for the RANS equations").
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - Every call returns fas_status (FAS_OK = 0, negative on error) and never
+ *   throws.  fas_last_error() returns a message for the calling thread.
+ * - Grid node arrays are HOST pointers, (nj+1) x (ni+1), I fastest.
+ * - Every other array argument is a DEVICE pointer on the state's device,
+ *   laid out as [4][nj][ni] (component, j, i with i fastest; components
+ *   rho, rho*u, rho*v, rho*E) for per-cell vectors, [nj][ni] for scalars.
+ *   Caller arrays are read or written during the call (or the stream work it
+ *   enqueues) and never retained.
+ * - Work is enqueued on the stream given to fas_state_create; a call returns
+ *   once its work is enqueued unless it returns host values (n_done, ...),
+ *   which synchronise that stream.
+ * - Level 0 is the finest level; level l has ni/2^l x nj/2^l cells.
+ * - Nondimensionalisation: rho_inf = 1, p_inf = 1, |v_inf| = M sqrt(gamma),
+ *   chord 1 (it reproduces the paper's physical time step 0.486822 of
+ *   Section 6.4).
+ */
+#ifndef FAS_H
+#define FAS_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    FAS_OK = 0,
+    FAS_EINVAL = -1,          /* bad argument, shape or parameter */
+    FAS_ENOMEM = -2,          /* device allocation failed */
+    FAS_EDEVICE = -3,         /* HIP runtime error */
+    FAS_DIVERGED = -4,        /* non-finite residual norm */
+    FAS_NOT_CONVERGED = -6    /* cycle cap reached before the requested drop */
+} fas_status;
+
+enum { FAS_BOX = 0, FAS_CGRID = 1 };          /* grid topology */
+enum { FAS_EULER = 0, FAS_RANS_BL = 1 };       /* model */
+enum {                                         /* smoother (Table "RK smoothers") */
+    FAS_AW3 = 0, FAS_PARK3J = 1, FAS_AW5J = 2, FAS_AW51 = 3, FAS_AW52 = 4, FAS_PARK51 = 5
+};
+
+#define FAS_PARAMS_VERSION 1
+
+typedef struct {
+    int32_t version;        /* FAS_PARAMS_VERSION */
+    int32_t model;          /* FAS_EULER | FAS_RANS_BL */
+    int32_t scheme;         /* FAS_AW3 ... */
+    int32_t n_ramp;         /* cycles run at c* = cfl_ramp at the start of a solve */
+    double  eta;            /* W ~ I + eta dt* J (Section 4.2) */
+    double  d_cut;          /* eigenvalue cutoff fraction d of eq. "cutoff" */
+    double  cfl;            /* pseudo CFL number c* */
+    double  cfl_ramp;       /* start-up c* (Section 6: 20 for two iterations) */
+    double  ramp_growth;    /* >1: c* grows by this factor per cycle after the ramp */
+    double  kappa2c;        /* coarse-level first-order dissipation coefficient */
+    double  mach, alpha_deg, reynolds, prandtl, prandtl_t;
+    int32_t n_levels;       /* multigrid levels (1 = single grid) */
+    int32_t cycle_gamma;    /* 1: V-cycle, 2: W-cycle (Section 3) */
+    int32_t nu1;            /* pre-smoothing iterations per level */
+    int32_t precond_fp32;   /* 1: SGS blocks and sweeps in FP32 */
+} fas_params;
+
+typedef struct fas_grid_s *fas_grid;     /* opaque, library owned */
+typedef struct fas_state_s *fas_state;   /* opaque, bound to one device and stream */
+
+/* Fill *p with defaults: AW3, robust mode (eta 0.5, d 0.5, c* 1e4). */
+void fas_params_default(fas_params *p);
+
+/*
+ * Grid of ni x nj cells from host node arrays (Section 2: structured
+ * cell-centred finite volumes; Section 3: n_levels of 2x2 agglomeration).
+ * topology FAS_CGRID: i runs lower wake -> airfoil -> upper wake, j from
+ * the wall / wake cut outward, cells (i,0) and (ni-1-i,0) are neighbours
+ * across the cut for i < n_wake or i >= ni - n_wake.  FAS_BOX: slip wall at
+ * j = 0, far field elsewhere.  ni, nj (and n_wake) must be divisible by
+ * 2^(n_levels-1); nj <= 512 (one sweep row per thread).  The grid is
+ * bound to the current HIP device.  Errors: FAS_EINVAL, FAS_ENOMEM.
+ */
+fas_status fas_grid_create(int32_t topology, int32_t ni, int32_t nj, int32_t n_wake,
+                           const double *x_nodes, const double *y_nodes,
+                           int32_t n_levels, fas_grid *out);
+void fas_grid_destroy(fas_grid g);
+
+/*
+ * State of one flow case on grid g, initialised with the fine-level
+ * solution u0 (device, [4][nj][ni]).  stream is a hipStream_t (NULL: the
+ * default stream).  p->n_levels must not exceed the grid's levels.
+ */
+fas_status fas_state_create(fas_grid g, const fas_params *p, const double *u0,
+                            void *stream, fas_state *out);
+void fas_state_destroy(fas_state s);
+fas_status fas_state_set_params(fas_state s, const fas_params *p);
+
+/* Copy in / out the fine-level solution, and (nullable) the eddy viscosity
+ * of the last fine-level smoother iteration ([nj][ni]). */
+fas_status fas_set_state(fas_state s, const double *u);
+fas_status fas_get_state(fas_state s, double *u, double *mu_t);
+/* Solution and FAS source term of any level ([4][nj_l][ni_l]; source may be NULL). */
+fas_status fas_get_level(fas_state s, int32_t level, double *u, double *source);
+
+/*
+ * F_l(u_l) - s_l per unit volume on a level (eqs. "nonlin-eq",
+ * "nonlin-eq-steady" and "coarse-nonlin-eq"; s = 0 on level 0), with the
+ * eddy viscosity evaluated at u_l.  F_out: device [4][nj_l][ni_l].
+ */
+fas_status fas_residual(fas_state s, int32_t level, double *F_out);
+
+/*
+ * n_iter smoother iterations on one level (Section 4: low-storage additive
+ * W / preconditioned ARK stages with the block SGS preconditioner of
+ * Section 4.4).  c* follows the ramp of the state's cycle counter.
+ */
+fas_status fas_smooth(fas_state s, int32_t level, int32_t n_iter);
+
+/*
+ * x = P^-1 r with the SGS preconditioner built at the current state of a
+ * level (eq. "sgs-precon"), r and x device [4][nj_l][ni_l].  For tests and
+ * analysis.
+ */
+fas_status fas_sgs_apply(fas_state s, int32_t level, const double *r, double *x);
+
+/*
+ * FAS cycles (Section 3) until the RMS of the density component of the
+ * fine residual has dropped by drop_orders (<= 0: run max_cycles) or
+ * max_cycles were run.  res_hist (host, may be NULL) receives the norm
+ * before the first and after every cycle (max_cycles + 1 entries).
+ * Returns FAS_OK, FAS_NOT_CONVERGED or FAS_DIVERGED; *n_done cycles ran.
+ */
+fas_status fas_cycle(fas_state s, int32_t max_cycles, double drop_orders,
+                     double *res_hist, int32_t *n_done);
+
+/*
+ * One physical time step of BDF2 dual time stepping (eq. "nonlin-eq";
+ * implicit Euler on the first step, Section 6), with the far-field angle
+ * of attack set to alpha_deg, inner FAS cycles as in fas_cycle.
+ */
+fas_status fas_dual_time_step(fas_state s, double dt, double alpha_deg, int32_t max_inner,
+                              double drop_orders, double *res_hist, int32_t *n_inner);
+
+/* Message of the last failing call on this thread (never NULL). */
+const char *fas_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FAS_H */

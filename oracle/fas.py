@@ -51,7 +51,7 @@ class Params:
     n_levels: int = 1
     cycle_gamma: int = 1
     nu1: int = 1
-    kappa2c: float = 0.25
+    kappa2c: float = 0.125
     mach: float = 0.8
     alpha_deg: float = 0.0
     reynolds: float = 1.0e7

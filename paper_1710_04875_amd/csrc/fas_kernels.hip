@@ -1,0 +1,1206 @@
+// HIP kernels (gfx950) of the preconditioned FAS smoother.
+//
+// Paper: Birken, Bull, Jameson, "Preconditioned smoothers for the full
+// approximation scheme for the RANS equations".  Each kernel names the
+// section / equation it implements.  Layout: fas_internal.h.
+#include "fas_internal.h"
+
+#include <cmath>
+
+namespace fas {
+
+namespace {
+
+constexpr int TPB = 256;
+constexpr double SUTH = 110.4 / 288.15;
+constexpr double BL_APLUS = 26.0, BL_CCP = 1.6, BL_CKLEB = 0.3, BL_CWK = 0.25,
+                 BL_KAPPA = 0.4, BL_K = 0.0168;
+
+inline int nblocks(int n, int t = TPB) { return (n + t - 1) / t; }
+
+__device__ inline bool decode(const Lay &L, int s, int &i, int &j) {
+    if (s >= L.NS) return false;
+    int H = s / L.NJ;
+    int J = s - H * L.NJ;
+    int I = H - J;
+    if (I < 0 || I >= L.NI) return false;
+    i = I - NG;
+    j = J - NG;
+    return true;
+}
+
+__device__ inline bool interior(const Lay &L, int i, int j) {
+    return i >= 0 && i < L.ni && j >= 0 && j < L.nj;
+}
+
+__device__ inline bool cut_col(const Lay &L, int i) {
+    return L.topo == 1 && (i < L.nw || i >= L.ni - L.nw);
+}
+
+__device__ inline double pres(double r, double mx, double my, double E) {
+    return (GAM - 1.0) * (E - 0.5 * (mx * mx + my * my) / r);
+}
+
+__device__ inline double sutherland(double T, double mu_inf) {
+    return ((mu_inf * (T * sqrt(T))) * (1.0 + SUTH)) / (T + SUTH);
+}
+
+__device__ inline void ld4(const double *a, int NS, int s, double v[4]) {
+#pragma unroll
+    for (int k = 0; k < 4; ++k) v[k] = a[k * NS + s];
+}
+
+// ------------------------------------------------------------------ geometry
+// Section 2 (finite volumes on a structured mesh), Section 3 (agglomerated
+// coarse levels: coarse face = sum of child faces, coarse volume = sum of
+// child volumes).
+__global__ void k_geom_interior(Lay L, const double *xn, const double *yn, double *geo,
+                                const double *volf, Lay Lf) {
+    int s = blockIdx.x * blockDim.x + threadIdx.x;
+    int i, j;
+    if (!decode(L, s, i, j)) return;
+    const int NS = L.NS, W = L.ni + 1;
+    auto X = [&](int I, int J) { return xn[J * W + I]; };
+    auto Y = [&](int I, int J) { return yn[J * W + I]; };
+    if (i >= 0 && i <= L.ni && j >= 0 && j < L.nj) {
+        double dx = X(i, j + 1) - X(i, j);
+        double dy = Y(i, j + 1) - Y(i, j);
+        geo[G_SXI_X * NS + s] = dy;
+        geo[G_SXI_Y * NS + s] = -dx;
+    }
+    if (i >= 0 && i < L.ni && j >= 0 && j <= L.nj) {
+        double dx = X(i + 1, j) - X(i, j);
+        double dy = Y(i + 1, j) - Y(i, j);
+        geo[G_SETA_X * NS + s] = -dy;
+        geo[G_SETA_Y * NS + s] = dx;
+    }
+    if (!interior(L, i, j)) return;
+    double vol;
+    if (volf == nullptr) {
+        double d1x = X(i + 1, j + 1) - X(i, j), d1y = Y(i + 1, j + 1) - Y(i, j);
+        double d2x = X(i, j + 1) - X(i + 1, j), d2y = Y(i, j + 1) - Y(i + 1, j);
+        vol = 0.5 * (d1x * d2y - d1y * d2x);
+    } else {
+        double v00 = volf[Lf.slot(2 * i, 2 * j)], v10 = volf[Lf.slot(2 * i + 1, 2 * j)];
+        double v01 = volf[Lf.slot(2 * i, 2 * j + 1)], v11 = volf[Lf.slot(2 * i + 1, 2 * j + 1)];
+        vol = ((v00 + v10) + v01) + v11;
+    }
+    geo[G_VOL * NS + s] = vol;
+    geo[G_XC * NS + s] = 0.25 * (((X(i, j) + X(i + 1, j)) + X(i + 1, j + 1)) + X(i, j + 1));
+    geo[G_YC * NS + s] = 0.25 * (((Y(i, j) + Y(i + 1, j)) + Y(i + 1, j + 1)) + Y(i, j + 1));
+    double wx = Y(i, j + 1) - Y(i, j), wy = -(X(i, j + 1) - X(i, j));
+    double ex = Y(i + 1, j + 1) - Y(i + 1, j), ey = -(X(i + 1, j + 1) - X(i + 1, j));
+    double sx = -(Y(i + 1, j) - Y(i, j)), sy = X(i + 1, j) - X(i, j);
+    double nx = -(Y(i + 1, j + 1) - Y(i, j + 1)), ny = X(i + 1, j + 1) - X(i, j + 1);
+    geo[G_SB0 * NS + s] = 0.5 * (wx + ex);
+    geo[G_SB1 * NS + s] = 0.5 * (wy + ey);
+    geo[G_SB2 * NS + s] = 0.5 * (sx + nx);
+    geo[G_SB3 * NS + s] = 0.5 * (sy + ny);
+    double mx = 0.5 * (X(i, 0) + X(i + 1, 0)), my = 0.5 * (Y(i, 0) + Y(i + 1, 0));
+    double cx = geo[G_XC * NS + s] - mx, cy = geo[G_YC * NS + s] - my;
+    geo[G_WD * NS + s] = sqrt(cx * cx + cy * cy);
+}
+
+__device__ inline void reflect(double &cx, double &cy, double mx, double my, double sx, double sy) {
+    double ln = sqrt(sx * sx + sy * sy);
+    double nx = sx / ln, ny = sy / ln;
+    double dist = (cx - mx) * nx + (cy - my) * ny;
+    cx = cx - 2.0 * dist * nx;
+    cy = cy - 2.0 * dist * ny;
+}
+
+// centre of the cell (i, j) for interior i and j in [-2, nj+2), plus the
+// slot of the interior cell whose metrics it copies
+__device__ void jrow_geom(const Lay &L, const double *xn, const double *yn, const double *geo,
+                          int i, int j, double &cx, double &cy, int &msrc) {
+    const int NS = L.NS, W = L.ni + 1;
+    if (j >= 0 && j < L.nj) {
+        int s = L.slot(i, j);
+        cx = geo[G_XC * NS + s];
+        cy = geo[G_YC * NS + s];
+        msrc = s;
+        return;
+    }
+    if (j < 0) {
+        int k = -1 - j;
+        if (cut_col(L, i)) {
+            int s = L.slot(L.ni - 1 - i, k);
+            cx = geo[G_XC * NS + s];
+            cy = geo[G_YC * NS + s];
+            msrc = s;
+            return;
+        }
+        int s = L.slot(i, k);
+        cx = geo[G_XC * NS + s];
+        cy = geo[G_YC * NS + s];
+        msrc = s;
+        double mx = 0.5 * (xn[i] + xn[i + 1]), my = 0.5 * (yn[i] + yn[i + 1]);
+        int f = L.slot(i, 0);
+        reflect(cx, cy, mx, my, geo[G_SETA_X * NS + f], geo[G_SETA_Y * NS + f]);
+        return;
+    }
+    int k = j - L.nj;
+    int s = L.slot(i, L.nj - 1 - k);
+    cx = geo[G_XC * NS + s];
+    cy = geo[G_YC * NS + s];
+    msrc = s;
+    double mx = 0.5 * (xn[L.nj * W + i] + xn[L.nj * W + i + 1]);
+    double my = 0.5 * (yn[L.nj * W + i] + yn[L.nj * W + i + 1]);
+    int f = L.slot(i, L.nj);
+    reflect(cx, cy, mx, my, geo[G_SETA_X * NS + f], geo[G_SETA_Y * NS + f]);
+}
+
+__global__ void k_geom_ghost(Lay L, const double *xn, const double *yn, double *geo) {
+    int s = blockIdx.x * blockDim.x + threadIdx.x;
+    int i, j;
+    if (!decode(L, s, i, j) || interior(L, i, j)) return;
+    const int NS = L.NS, W = L.ni + 1;
+    double cx, cy;
+    int msrc;
+    if (i >= 0 && i < L.ni) {
+        jrow_geom(L, xn, yn, geo, i, j, cx, cy, msrc);
+    } else {
+        int jc = min(max(j, 0), L.nj - 1);
+        int isrc, I;
+        double sgn;
+        if (i < 0) { isrc = -1 - i; I = 0; sgn = 1.0; }
+        else { isrc = L.ni - 1 - (i - L.ni); I = L.ni; sgn = 1.0; }
+        (void)sgn;
+        jrow_geom(L, xn, yn, geo, isrc, j, cx, cy, msrc);
+        double mx = 0.5 * (xn[jc * W + I] + xn[(jc + 1) * W + I]);
+        double my = 0.5 * (yn[jc * W + I] + yn[(jc + 1) * W + I]);
+        int f = L.slot(I, jc);
+        reflect(cx, cy, mx, my, geo[G_SXI_X * NS + f], geo[G_SXI_Y * NS + f]);
+    }
+    geo[G_XC * NS + s] = cx;
+    geo[G_YC * NS + s] = cy;
+    geo[G_SB0 * NS + s] = geo[G_SB0 * NS + msrc];
+    geo[G_SB1 * NS + s] = geo[G_SB1 * NS + msrc];
+    geo[G_SB2 * NS + s] = geo[G_SB2 * NS + msrc];
+    geo[G_SB3 * NS + s] = geo[G_SB3 * NS + msrc];
+    geo[G_VOL * NS + s] = geo[G_VOL * NS + msrc];
+}
+
+// ---------------------------------------------------------- boundary states
+// Section 2: no-slip walls and far-field conditions by Riemann invariants;
+// two ghost layers, layer k from interior cell k; wake-cut ghosts are the
+// partner cells.
+__device__ void farfield(const double ui[4], const double uinf[4], double nx, double ny, double out[4]) {
+    const double g1 = GAM - 1.0;
+    double rho = ui[0];
+    double vx = ui[1] / rho, vy = ui[2] / rho;
+    double p = pres(ui[0], ui[1], ui[2], ui[3]);
+    double a = sqrt(GAM * p / rho);
+    double rinf = uinf[0];
+    double vxf = uinf[1] / rinf, vyf = uinf[2] / rinf;
+    double pf = pres(uinf[0], uinf[1], uinf[2], uinf[3]);
+    double af = sqrt(GAM * pf / rinf);
+    double vn = vx * nx + vy * ny;
+    double vnf = vxf * nx + vyf * ny;
+    double rp = vn + 2.0 * a / g1;
+    double rm = vnf - 2.0 * af / g1;
+    double vnb = 0.5 * (rp + rm);
+    double ab = 0.25 * g1 * (rp - rm);
+    bool outf = vnb > 0.0;
+    double sent = outf ? p / pow(rho, GAM) : pf / pow(rinf, GAM);
+    double tx = outf ? vx - vn * nx : vxf - vnf * nx;
+    double ty = outf ? vy - vn * ny : vyf - vnf * ny;
+    double base = ab * ab / (GAM * sent);
+    double rhob = base * base * sqrt(base);
+    double pb = rhob * ab * ab / GAM;
+    double ub = tx + vnb * nx, vb = ty + vnb * ny;
+    out[0] = rhob;
+    out[1] = rhob * ub;
+    out[2] = rhob * vb;
+    out[3] = pb / g1 + 0.5 * rhob * (ub * ub + vb * vb);
+}
+
+__device__ inline void unit(double sx, double sy, double &nx, double &ny) {
+    double ln = sqrt(sx * sx + sy * sy);
+    nx = sx / ln;
+    ny = sy / ln;
+}
+
+// state of cell (i, j), i interior, j in [-2, nj+2)
+__device__ void jrow_state(const Lay &L, const double *geo, const double *u, const Phys &ph,
+                           int noslip, int i, int j, double out[4]) {
+    const int NS = L.NS;
+    if (j >= 0 && j < L.nj) {
+        ld4(u, NS, L.slot(i, j), out);
+        return;
+    }
+    if (j < 0) {
+        int k = -1 - j;
+        if (cut_col(L, i)) {
+            ld4(u, NS, L.slot(L.ni - 1 - i, k), out);
+            return;
+        }
+        double ui[4];
+        ld4(u, NS, L.slot(i, k), ui);
+        if (noslip) {
+            out[0] = ui[0];
+            out[1] = -ui[1];
+            out[2] = -ui[2];
+            out[3] = ui[3];
+        } else {
+            int f = L.slot(i, 0);
+            double nx, ny;
+            unit(geo[G_SETA_X * NS + f], geo[G_SETA_Y * NS + f], nx, ny);
+            double mn = ui[1] * nx + ui[2] * ny;
+            out[0] = ui[0];
+            out[1] = ui[1] - 2.0 * mn * nx;
+            out[2] = ui[2] - 2.0 * mn * ny;
+            out[3] = ui[3];
+        }
+        return;
+    }
+    int k = j - L.nj;
+    double ui[4];
+    ld4(u, NS, L.slot(i, L.nj - 1 - k), ui);
+    int f = L.slot(i, L.nj);
+    double nx, ny;
+    unit(geo[G_SETA_X * NS + f], geo[G_SETA_Y * NS + f], nx, ny);
+    farfield(ui, ph.uinf, nx, ny, out);
+}
+
+__global__ void k_ghost_state(Lay L, const double *geo, double *u, Phys ph, int noslip) {
+    int s = blockIdx.x * blockDim.x + threadIdx.x;
+    int i, j;
+    if (!decode(L, s, i, j) || interior(L, i, j)) return;
+    const int NS = L.NS;
+    double out[4];
+    if (i >= 0 && i < L.ni) {
+        jrow_state(L, geo, u, ph, noslip, i, j, out);
+    } else {
+        int jc = min(max(j, 0), L.nj - 1);
+        double src[4], nx, ny;
+        if (i < 0) {
+            jrow_state(L, geo, u, ph, noslip, -1 - i, j, src);
+            int f = L.slot(0, jc);
+            unit(-geo[G_SXI_X * NS + f], -geo[G_SXI_Y * NS + f], nx, ny);
+        } else {
+            jrow_state(L, geo, u, ph, noslip, L.ni - 1 - (i - L.ni), j, src);
+            int f = L.slot(L.ni, jc);
+            unit(geo[G_SXI_X * NS + f], geo[G_SXI_Y * NS + f], nx, ny);
+        }
+        farfield(src, ph.uinf, nx, ny, out);
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k) u[k * NS + s] = out[k];
+}
+
+// eddy viscosity ghosts: zero at walls, copy at far field, partner at the cut
+__device__ double jrow_mut(const Lay &L, const double *mut, int i, int j) {
+    if (j >= 0 && j < L.nj) return mut[L.slot(i, j)];
+    if (j < 0) {
+        int k = -1 - j;
+        if (cut_col(L, i)) return mut[L.slot(L.ni - 1 - i, k)];
+        return 0.0;
+    }
+    return mut[L.slot(i, L.nj - 1 - (j - L.nj))];
+}
+
+__global__ void k_mut_ghosts(Lay L, double *mut) {
+    int s = blockIdx.x * blockDim.x + threadIdx.x;
+    int i, j;
+    if (!decode(L, s, i, j) || interior(L, i, j)) return;
+    double v;
+    if (i >= 0 && i < L.ni) v = jrow_mut(L, mut, i, j);
+    else if (i < 0) v = jrow_mut(L, mut, -1 - i, j);
+    else v = jrow_mut(L, mut, L.ni - 1 - (i - L.ni), j);
+    mut[s] = v;
+}
+
+// ------------------------------------------------------- per-cell quantities
+// Section 2: p, sensor quantity (entropy p/rho^gamma for RANS, pressure for
+// Euler), spectral radii r = |v.S| + a|S| and the multidimensional
+// correction of eq. "spectralcorrection"; temperature T = p / rho.
+__global__ void k_cell_quantities(Lay L, const double *geo, const double *u, double *cq, int rans) {
+    int s = blockIdx.x * blockDim.x + threadIdx.x;
+    int i, j;
+    if (!decode(L, s, i, j)) return;
+    const int NS = L.NS;
+    double r = u[s], mx = u[NS + s], my = u[2 * NS + s], E = u[3 * NS + s];
+    double vx = mx / r, vy = my / r;
+    double p = pres(r, mx, my, E);
+    double a = sqrt(GAM * p / r);
+    double q = rans ? p / pow(r, GAM) : p;
+    double sb0 = geo[G_SB0 * NS + s], sb1 = geo[G_SB1 * NS + s];
+    double sb2 = geo[G_SB2 * NS + s], sb3 = geo[G_SB3 * NS + s];
+    double rxi = fabs(vx * sb0 + vy * sb1) + a * sqrt(sb0 * sb0 + sb1 * sb1);
+    double reta = fabs(vx * sb2 + vy * sb3) + a * sqrt(sb2 * sb2 + sb3 * sb3);
+    double t = reta / rxi;
+    double rtxi = rxi * (1.0 + cbrt(t * t));
+    t = rxi / reta;
+    double rteta = reta * (1.0 + cbrt(t * t));
+    cq[Q_P * NS + s] = p;
+    cq[Q_Q * NS + s] = q;
+    cq[Q_RXI * NS + s] = rtxi;
+    cq[Q_RETA * NS + s] = rteta;
+    cq[Q_T * NS + s] = p / r;
+}
+
+// Section 4.1: dt* = c* Omega / (r_xi + r_eta)
+__global__ void k_local_time_step(Lay L, const double *geo, const double *u, double *dts, double cfl) {
+    int s = blockIdx.x * blockDim.x + threadIdx.x;
+    int i, j;
+    if (!decode(L, s, i, j) || !interior(L, i, j)) return;
+    const int NS = L.NS;
+    double r = u[s], mx = u[NS + s], my = u[2 * NS + s], E = u[3 * NS + s];
+    double vx = mx / r, vy = my / r;
+    double p = pres(r, mx, my, E);
+    double a = sqrt(GAM * p / r);
+    double sb0 = geo[G_SB0 * NS + s], sb1 = geo[G_SB1 * NS + s];
+    double sb2 = geo[G_SB2 * NS + s], sb3 = geo[G_SB3 * NS + s];
+    double rxi = fabs(vx * sb0 + vy * sb1) + a * sqrt(sb0 * sb0 + sb1 * sb1);
+    double reta = fabs(vx * sb2 + vy * sb3) + a * sqrt(sb2 * sb2 + sb3 * sb3);
+    dts[s] = cfl * geo[G_VOL * NS + s] / (rxi + reta);
+}
+
+// Section 2: velocity and temperature gradients at vertices, Green-Gauss
+// over the quadrilateral of the four surrounding cell centres.
+__global__ void k_vertex_gradients(Lay L, const double *geo, const double *u, const double *cq,
+                                   double *vg) {
+    int s = blockIdx.x * blockDim.x + threadIdx.x;
+    int i, j;
+    if (!decode(L, s, i, j)) return;
+    if (i < 0 || i > L.ni || j < 0 || j > L.nj) return;
+    const int NS = L.NS, NJ = L.NJ;
+    const int c[4] = {s - (2 * NJ + 1), s - (NJ + 1), s, s - NJ};   // SW, SE, NE, NW
+    double X[4], Y[4], U[4], V[4], T[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        X[k] = geo[G_XC * NS + c[k]];
+        Y[k] = geo[G_YC * NS + c[k]];
+        double r = u[c[k]];
+        U[k] = u[NS + c[k]] / r;
+        V[k] = u[2 * NS + c[k]] / r;
+        T[k] = cq[Q_T * NS + c[k]];
+    }
+    double A = 0.5 * ((X[2] - X[0]) * (Y[3] - Y[1]) - (Y[2] - Y[0]) * (X[3] - X[1]));
+    double g[6] = {0, 0, 0, 0, 0, 0};
+    const double *phi[3] = {U, V, T};
+#pragma unroll
+    for (int f = 0; f < 3; ++f) {
+        double gx = 0.0, gy = 0.0;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            int a = e, b = (e + 1) & 3;
+            double m = 0.5 * (phi[f][a] + phi[f][b]);
+            double tx = m * (Y[b] - Y[a]);
+            double ty = m * (X[a] - X[b]);
+            if (e == 0) { gx = tx; gy = ty; }
+            else { gx = gx + tx; gy = gy + ty; }
+        }
+        g[2 * f] = gx / A;
+        g[2 * f + 1] = gy / A;
+    }
+#pragma unroll
+    for (int k = 0; k < 6; ++k) vg[k * NS + s] = g[k];
+}
+
+// Baldwin-Lomax algebraic eddy viscosity (Section 2), one workgroup per
+// i-column, j-cells walked from the wall / wake cut outward.  Ties in the
+// maximum of F and the first inner/outer crossover go to the lowest j; the
+// search is limited to the inner half of the column.
+constexpr int BL_TPB = 256;
+__global__ __launch_bounds__(BL_TPB) void k_baldwin_lomax(Lay L, const double *geo, const double *u,
+                                                          const double *cq, const double *vg,
+                                                          double *mut, Phys ph) {
+    extern __shared__ double sh[];
+    const int nj = L.nj, NS = L.NS, NJ = L.NJ;
+    double *Fs = sh, *ys = sh + nj, *sp = sh + 2 * nj, *mi = sh + 3 * nj, *mo = sh + 4 * nj;
+    __shared__ double s_fmax, s_ymax, s_udif;
+    __shared__ int s_jc;
+    const int i = blockIdx.x;
+    const bool cut = cut_col(L, i);
+    auto omega = [&](int jj) {
+        int s = L.slot(i, jj);
+        int v0 = s, v1 = s + NJ, v2 = s + 2 * NJ + 1, v3 = s + NJ + 1;   // (i,j),(i+1,j),(i+1,j+1),(i,j+1)
+        double w0 = vg[V_VX * NS + v0] - vg[V_UY * NS + v0];
+        double w1 = vg[V_VX * NS + v1] - vg[V_UY * NS + v1];
+        double w2 = vg[V_VX * NS + v2] - vg[V_UY * NS + v2];
+        double w3 = vg[V_VX * NS + v3] - vg[V_UY * NS + v3];
+        return fabs(0.25 * (((w0 + w1) + w2) + w3));
+    };
+    const int s0 = L.slot(i, 0);
+    const double muw = sutherland(cq[Q_T * NS + s0], ph.mu_inf);
+    const double rhow = u[s0];
+    const double tauw = muw * omega(0);
+    const double sq = sqrt(rhow * tauw);
+    for (int jj = threadIdx.x; jj < nj; jj += blockDim.x) {
+        int s = L.slot(i, jj);
+        double r = u[s];
+        double vx = u[NS + s] / r, vy = u[2 * NS + s] / r;
+        double om = omega(jj);
+        double y = geo[G_WD * NS + s];
+        double damp = 1.0;
+        if (!cut) {
+            double yplus = y * sq / muw;
+            damp = 1.0 - exp(-yplus / BL_APLUS);
+        }
+        Fs[jj] = y * om * damp;
+        ys[jj] = y;
+        sp[jj] = sqrt(vx * vx + vy * vy);
+        double l = BL_KAPPA * y * damp;
+        mi[jj] = r * (l * l) * om;
+    }
+    __syncthreads();
+    const int jb = nj / 2;
+    if (threadIdx.x == 0) {
+        int jm = 0;
+        double fbest = Fs[0], smax = sp[0], smin = sp[0];
+        for (int jj = 1; jj < jb; ++jj) {
+            if (Fs[jj] > fbest) { fbest = Fs[jj]; jm = jj; }
+            smax = fmax(smax, sp[jj]);
+            smin = fmin(smin, sp[jj]);
+        }
+        s_fmax = fbest;
+        s_ymax = ys[jm];
+        s_udif = smax - smin;
+    }
+    __syncthreads();
+    const double fm = s_fmax, ymax = s_ymax, udif = s_udif;
+    const double fwake = fm > 0.0 ? fmin(ymax * fm, BL_CWK * ymax * udif * udif / fm) : 0.0;
+    for (int jj = threadIdx.x; jj < nj; jj += blockDim.x) {
+        double t = BL_CKLEB * ys[jj] / ymax;
+        double t2 = t * t;
+        double fk = 1.0 / (1.0 + 5.5 * (t2 * t2 * t2));
+        double r = u[L.slot(i, jj)];
+        mo[jj] = r * BL_K * BL_CCP * fwake * fk;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int jc = jb;
+        for (int jj = 0; jj < jb; ++jj)
+            if (mi[jj] >= mo[jj]) { jc = jj; break; }
+        s_jc = jc;
+    }
+    __syncthreads();
+    const int jc = s_jc;
+    for (int jj = threadIdx.x; jj < nj; jj += blockDim.x)
+        mut[L.slot(i, jj)] = jj < jc ? mi[jj] : mo[jj];
+}
+
+// -------------------------------------------------------------- residual
+// JST face flux (Section 2) split into the central part (f^c) and the
+// artificial dissipation / viscous part (f^v) of eq. "split-rhs".
+struct FaceOut {
+    double C[4], V[4];
+};
+
+__device__ void face_flux(const Lay &L, const double *geo, const double *u, const double *cq,
+                          const double *vg, const double *mut, const Phys &ph, const ResArgs &a,
+                          int sL, int sR, int off, double sx, double sy, int gL, int gR, bool wall,
+                          FaceOut &o) {
+    const int NS = L.NS;
+    double UL[4], UR[4];
+    ld4(u, NS, sL, UL);
+    ld4(u, NS, sR, UR);
+    double pL = cq[Q_P * NS + sL], pR = cq[Q_P * NS + sR];
+    if (wall) {
+        double pw = 0.5 * (pL + pR);
+        o.C[0] = 0.0;
+        o.C[1] = pw * sx;
+        o.C[2] = pw * sy;
+        o.C[3] = 0.0;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) o.V[k] = 0.0;
+    } else {
+        double qsL = UL[1] * sx + UL[2] * sy, vsL = qsL / UL[0];
+        double qsR = UR[1] * sx + UR[2] * sy, vsR = qsR / UR[0];
+        double FL[4] = {qsL, UL[1] * vsL + pL * sx, UL[2] * vsL + pL * sy, (UL[3] + pL) * vsL};
+        double FR[4] = {qsR, UR[1] * vsR + pR * sx, UR[2] * vsR + pR * sy, (UR[3] + pR) * vsR};
+#pragma unroll
+        for (int k = 0; k < 4; ++k) o.C[k] = 0.5 * (FL[k] + FR[k]);
+        const int rp = (off == L.NJ ? Q_RXI : Q_RETA) * NS;
+        double rf = fmax(cq[rp + sL], cq[rp + sR]);
+        double wL[4] = {UL[0], UL[1], UL[2], UL[3] + pL};
+        double wR[4] = {UR[0], UR[1], UR[2], UR[3] + pR};
+        double d[4];
+        if (a.fine) {
+            const double *q = cq + Q_Q * NS;
+            double qLL = q[sL - off], qL = q[sL], qR = q[sR], qRR = q[sR + off];
+            double sLs = fabs(((qR - 2.0 * qL) + qLL) / (((qR + 2.0 * qL) + qLL) + 0.001));
+            double sRs = fabs(((qRR - 2.0 * qR) + qL) / (((qRR + 2.0 * qR) + qL) + 0.001));
+            double sf = fmin(0.25, fmax(sLs, sRs));
+            double e2 = sf * rf;
+            double e4 = fmax(0.0, rf / 32.0 - 2.0 * e2);
+            double ULL[4], URR[4];
+            ld4(u, NS, sL - off, ULL);
+            ld4(u, NS, sR + off, URR);
+            double pLL = cq[Q_P * NS + sL - off], pRR = cq[Q_P * NS + sR + off];
+            double wLL[4] = {ULL[0], ULL[1], ULL[2], ULL[3] + pLL};
+            double wRR[4] = {URR[0], URR[1], URR[2], URR[3] + pRR};
+#pragma unroll
+            for (int k = 0; k < 4; ++k)
+                d[k] = e2 * (wR[k] - wL[k]) - e4 * (((wRR[k] - 3.0 * wR[k]) + 3.0 * wL[k]) - wLL[k]);
+        } else {
+            double e2 = ph.kappa2c * rf;
+#pragma unroll
+            for (int k = 0; k < 4; ++k) d[k] = e2 * (wR[k] - wL[k]);
+        }
+#pragma unroll
+        for (int k = 0; k < 4; ++k) o.V[k] = -d[k];
+    }
+    if (a.viscous) {
+        // Section 2: face gradient = mean of the two end-vertex gradients
+        double fux = 0.5 * (vg[V_UX * NS + gL] + vg[V_UX * NS + gR]);
+        double fuy = 0.5 * (vg[V_UY * NS + gL] + vg[V_UY * NS + gR]);
+        double fwx = 0.5 * (vg[V_VX * NS + gL] + vg[V_VX * NS + gR]);
+        double fwy = 0.5 * (vg[V_VY * NS + gL] + vg[V_VY * NS + gR]);
+        double fTx = 0.5 * (vg[V_TX * NS + gL] + vg[V_TX * NS + gR]);
+        double fTy = 0.5 * (vg[V_TY * NS + gL] + vg[V_TY * NS + gR]);
+        double fvx = 0.5 * (UL[1] / UL[0] + UR[1] / UR[0]);
+        double fvy = 0.5 * (UL[2] / UL[0] + UR[2] / UR[0]);
+        double fT = 0.5 * (cq[Q_T * NS + sL] + cq[Q_T * NS + sR]);
+        double mu = sutherland(fT, ph.mu_inf);
+        double mt = 0.5 * (mut[sL] + mut[sR]);
+        double mue = mu + mt;
+        double kc = (mu / ph.pr + mt / ph.prt) * (GAM / (GAM - 1.0));
+        double div = fux + fwy;
+        double txx = mue * (2.0 * fux - (2.0 / 3.0) * div);
+        double tyy = mue * (2.0 * fwy - (2.0 / 3.0) * div);
+        double txy = mue * (fuy + fwx);
+        double qx = kc * fTx, qy = kc * fTy;
+        double G1 = txx * sx + txy * sy;
+        double G2 = txy * sx + tyy * sy;
+        double G3 = ((fvx * txx + fvy * txy) + qx) * sx + ((fvx * txy + fvy * tyy) + qy) * sy;
+        o.V[1] = o.V[1] - G1;
+        o.V[2] = o.V[2] - G2;
+        o.V[3] = o.V[3] - G3;
+    }
+}
+
+template <typename BT>
+__global__ __launch_bounds__(TPB) void k_residual(Lay L, const double *geo, const double *u,
+                                                  const double *cq, const double *vg,
+                                                  const double *mut, const double *un,
+                                                  const double *unm1, const double *src, Phys ph,
+                                                  ResArgs a, double *F, double *acc,
+                                                  const double *dts, const BT *blk, BT *g) {
+    int s = blockIdx.x * blockDim.x + threadIdx.x;
+    int i, j;
+    if (!decode(L, s, i, j) || !interior(L, i, j)) return;
+    const int NS = L.NS, NJ = L.NJ;
+    FaceOut w, e, so, n;
+    face_flux(L, geo, u, cq, vg, mut, ph, a, s - NJ, s, NJ, geo[G_SXI_X * NS + s],
+              geo[G_SXI_Y * NS + s], s, s + NJ + 1, false, w);
+    face_flux(L, geo, u, cq, vg, mut, ph, a, s, s + NJ, NJ, geo[G_SXI_X * NS + s + NJ],
+              geo[G_SXI_Y * NS + s + NJ], s + NJ, s + 2 * NJ + 1, false, e);
+    bool wall = (j == 0) && !cut_col(L, i);
+    face_flux(L, geo, u, cq, vg, mut, ph, a, s - NJ - 1, s, NJ + 1, geo[G_SETA_X * NS + s],
+              geo[G_SETA_Y * NS + s], s, s + NJ, wall, so);
+    face_flux(L, geo, u, cq, vg, mut, ph, a, s, s + NJ + 1, NJ + 1,
+              geo[G_SETA_X * NS + s + NJ + 1], geo[G_SETA_Y * NS + s + NJ + 1], s + NJ + 1,
+              s + 2 * NJ + 1, false, n);
+    const double vol = geo[G_VOL * NS + s];
+    double Fc[4], Fv[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        double fc = (e.C[k] - w.C[k]) + (n.C[k] - so.C[k]);
+        double fv = (e.V[k] - w.V[k]) + (n.V[k] - so.V[k]);
+        Fc[k] = fc / vol;
+        Fv[k] = fv / vol;
+    }
+    if (a.bdf) {
+        double uu[4], u1[4];
+        ld4(u, NS, s, uu);
+        ld4(un, NS, s, u1);
+        if (a.bdf == 2) {
+            double u2[4];
+            ld4(unm1, NS, s, u2);
+#pragma unroll
+            for (int k = 0; k < 4; ++k) Fc[k] = Fc[k] + ((3.0 * uu[k] - 4.0 * u1[k]) + u2[k]) / (2.0 * a.dt);
+        } else {
+#pragma unroll
+            for (int k = 0; k < 4; ++k) Fc[k] = Fc[k] + (uu[k] - u1[k]) / a.dt;
+        }
+    }
+    if (a.forcing) {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) Fc[k] = Fc[k] - src[k * NS + s];
+    }
+    if (a.mode == 0) {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) F[k * NS + s] = Fc[k] + Fv[k];
+        return;
+    }
+    double r[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        double av = Fv[k];
+        if (a.stage > 0) av = a.beta * Fv[k] + (1.0 - a.beta) * acc[k * NS + s];
+        acc[k * NS + s] = av;
+        r[k] = Fc[k] + av;
+    }
+    if (a.aw) {
+        double d = dts[s];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) r[k] = d * r[k];
+    }
+    BT rb[4] = {(BT)r[0], (BT)r[1], (BT)r[2], (BT)r[3]};
+#pragma unroll
+    for (int rr = 0; rr < 4; ++rr) {
+        BT acc4 = (BT)0;
+#pragma unroll
+        for (int c = 0; c < 4; ++c) acc4 = fma(blk[(BLK_DINV + rr * 4 + c) * NS + s], rb[c], acc4);
+        g[rr * NS + s] = acc4;
+    }
+}
+
+// -------------------------------------------------- preconditioner blocks
+// Section 4.4: A+- = (A +- |A|_c)/2 at the arithmetic mean of the two cell
+// states, |A|_c = R |Lambda|_c R^-1 with the cutoff of eq. "cutoff"; here
+// |A|_c = |l1| I + (|l3| - |l1|) r3 l3^T + (|l4| - |l1|) r4 l4^T (same
+// matrix, the two acoustic projections written out).
+__device__ void split_face(const double UL[4], const double UR[4], double sx, double sy, double d,
+                           double Ap[16], double Am[16]) {
+    double ln = sqrt(sx * sx + sy * sy);
+    double nx = sx / ln, ny = sy / ln;
+    double U0 = 0.5 * (UL[0] + UR[0]), U1 = 0.5 * (UL[1] + UR[1]);
+    double U2 = 0.5 * (UL[2] + UR[2]), U3 = 0.5 * (UL[3] + UR[3]);
+    double uu = U1 / U0, vv = U2 / U0;
+    double p = pres(U0, U1, U2, U3);
+    double a = sqrt(GAM * p / U0);
+    double H = (U3 + p) / U0;
+    const double g1 = GAM - 1.0;
+    double q2 = uu * uu + vv * vv;
+    double phi = 0.5 * g1 * q2;
+    double V = uu * nx + vv * ny;
+    double A[16] = {0.0, nx, ny, 0.0,
+                    phi * nx - uu * V, V - (GAM - 2.0) * uu * nx, uu * ny - g1 * vv * nx, g1 * nx,
+                    phi * ny - vv * V, vv * nx - g1 * uu * ny, V - (GAM - 2.0) * vv * ny, g1 * ny,
+                    V * (phi - H), H * nx - g1 * uu * V, H * ny - g1 * vv * V, GAM * V};
+    double lam[3] = {V, V + a, V - a};
+    double al[3];
+    double ad = a * d;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        double m = fabs(lam[k]);
+        al[k] = (d > 0.0 && m <= ad) ? 0.5 * (ad + m * m / ad) : m;
+    }
+    double b = g1 / (a * a);
+    double r3[4] = {1.0, uu + a * nx, vv + a * ny, H + a * V};
+    double r4[4] = {1.0, uu - a * nx, vv - a * ny, H - a * V};
+    double l3[4] = {0.5 * (0.5 * b * q2 - V / a), 0.5 * (nx / a - b * uu), 0.5 * (ny / a - b * vv), 0.5 * b};
+    double l4[4] = {0.5 * (0.5 * b * q2 + V / a), 0.5 * (-nx / a - b * uu), 0.5 * (-ny / a - b * vv), 0.5 * b};
+    double c3 = al[1] - al[0], c4 = al[2] - al[0];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            double absA = (r == c ? al[0] : 0.0) + c3 * r3[r] * l3[c] + c4 * r4[r] * l4[c];
+            Ap[r * 4 + c] = ln * (0.5 * (A[r * 4 + c] + absA));
+            Am[r * 4 + c] = ln * (0.5 * (A[r * 4 + c] - absA));
+        }
+    }
+}
+
+// scalar thin-layer estimate of the viscous flux Jacobian of a face
+__device__ double visc_face(const Lay &L, const double *geo, const double *u, const double *cq,
+                            const double *mut, const Phys &ph, int sL, int sR, double sx, double sy) {
+    const int NS = L.NS;
+    double rf = 0.5 * (u[sL] + u[sR]);
+    double Tf = 0.5 * (cq[Q_T * NS + sL] + cq[Q_T * NS + sR]);
+    double mue = sutherland(Tf, ph.mu_inf) + 0.5 * (mut[sL] + mut[sR]);
+    double s2 = sx * sx + sy * sy;
+    double vf = 0.5 * (geo[G_VOL * NS + sL] + geo[G_VOL * NS + sR]);
+    return ((mue * (GAM / ph.pr)) * s2) / (rf * vf);
+}
+
+__device__ void face_blocks(const Lay &L, const double *geo, const double *u, const double *cq,
+                            const double *mut, const Phys &ph, int viscous, int sL, int sR,
+                            int plane_x, int plane_y, int sf, double Ap[16], double Am[16]) {
+    const int NS = L.NS;
+    double UL[4], UR[4];
+    ld4(u, NS, sL, UL);
+    ld4(u, NS, sR, UR);
+    double sx = geo[plane_x * NS + sf], sy = geo[plane_y * NS + sf];
+    split_face(UL, UR, sx, sy, ph.d_cut, Ap, Am);
+    if (viscous) {
+        double v = visc_face(L, geo, u, cq, mut, ph, sL, sR, sx, sy);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            Ap[k * 5] = Ap[k * 5] + v;
+            Am[k * 5] = Am[k * 5] - v;
+        }
+    }
+}
+
+template <typename BT>
+__global__ __launch_bounds__(TPB) void k_blocks(Lay L, const double *geo, const double *u,
+                                                const double *cq, const double *mut,
+                                                const double *dts, Phys ph, int aw, double tau,
+                                                int viscous, BT *blk) {
+    int s = blockIdx.x * blockDim.x + threadIdx.x;
+    int i, j;
+    if (!decode(L, s, i, j) || !interior(L, i, j)) return;
+    const int NS = L.NS, NJ = L.NJ;
+    double c, diag;
+    if (aw) {
+        double e = ph.eta * dts[s];
+        c = e / geo[G_VOL * NS + s];
+        diag = 1.0 + tau * e;
+    } else {
+        c = 1.0 / geo[G_VOL * NS + s];
+        diag = tau;
+    }
+    double Ap[16], Am[16], acc[16];
+    // pass 1: D = c (((Xp_e - Xm_w) + Ep_n) - Em_s) + diag I
+    face_blocks(L, geo, u, cq, mut, ph, viscous, s, s + NJ, G_SXI_X, G_SXI_Y, s + NJ, Ap, Am);
+#pragma unroll
+    for (int k = 0; k < 16; ++k) acc[k] = Ap[k];
+    face_blocks(L, geo, u, cq, mut, ph, viscous, s - NJ, s, G_SXI_X, G_SXI_Y, s, Ap, Am);
+#pragma unroll
+    for (int k = 0; k < 16; ++k) acc[k] = acc[k] - Am[k];
+    face_blocks(L, geo, u, cq, mut, ph, viscous, s, s + NJ + 1, G_SETA_X, G_SETA_Y, s + NJ + 1, Ap, Am);
+#pragma unroll
+    for (int k = 0; k < 16; ++k) acc[k] = acc[k] + Ap[k];
+    face_blocks(L, geo, u, cq, mut, ph, viscous, s - NJ - 1, s, G_SETA_X, G_SETA_Y, s, Ap, Am);
+#pragma unroll
+    for (int k = 0; k < 16; ++k) acc[k] = acc[k] - Am[k];
+    double D[16], Di[16];
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+        D[k] = c * acc[k];
+        Di[k] = (k % 5 == 0) ? 1.0 : 0.0;
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k) D[k * 5] = D[k * 5] + diag;
+    // Gauss-Jordan inverse without pivoting
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        double piv = 1.0 / D[k * 5];
+#pragma unroll
+        for (int cc = 0; cc < 4; ++cc) {
+            D[k * 4 + cc] *= piv;
+            Di[k * 4 + cc] *= piv;
+        }
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            if (r == k) continue;
+            double f = D[r * 4 + k];
+#pragma unroll
+            for (int cc = 0; cc < 4; ++cc) {
+                D[r * 4 + cc] = fma(-f, D[k * 4 + cc], D[r * 4 + cc]);
+                Di[r * 4 + cc] = fma(-f, Di[k * 4 + cc], Di[r * 4 + cc]);
+            }
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < 16; ++k) blk[(BLK_DINV + k) * NS + s] = (BT)Di[k];
+    // pass 2: M_slot = D^-1 B_slot
+    const bool has[4] = {i > 0, i < L.ni - 1, j > 0 || cut_col(L, i), j < L.nj - 1};
+#pragma unroll
+    for (int sl = 0; sl < 4; ++sl) {
+        double B[16];
+        if (has[sl]) {
+            if (sl == 0) {
+                face_blocks(L, geo, u, cq, mut, ph, viscous, s - NJ, s, G_SXI_X, G_SXI_Y, s, Ap, Am);
+                for (int k = 0; k < 16; ++k) B[k] = -(c * Ap[k]);
+            } else if (sl == 1) {
+                face_blocks(L, geo, u, cq, mut, ph, viscous, s, s + NJ, G_SXI_X, G_SXI_Y, s + NJ, Ap, Am);
+                for (int k = 0; k < 16; ++k) B[k] = c * Am[k];
+            } else if (sl == 2) {
+                face_blocks(L, geo, u, cq, mut, ph, viscous, s - NJ - 1, s, G_SETA_X, G_SETA_Y, s, Ap, Am);
+                for (int k = 0; k < 16; ++k) B[k] = -(c * Ap[k]);
+            } else {
+                face_blocks(L, geo, u, cq, mut, ph, viscous, s, s + NJ + 1, G_SETA_X, G_SETA_Y,
+                            s + NJ + 1, Ap, Am);
+                for (int k = 0; k < 16; ++k) B[k] = c * Am[k];
+            }
+        }
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+#pragma unroll
+            for (int cc = 0; cc < 4; ++cc) {
+                double m = 0.0;
+                if (has[sl]) {
+#pragma unroll
+                    for (int k = 0; k < 4; ++k) m = fma(Di[r * 4 + k], B[k * 4 + cc], m);
+                }
+                blk[(BLK_M + sl * 16 + r * 4 + cc) * NS + s] = (BT)m;
+            }
+        }
+    }
+}
+
+// ------------------------------------------------------------- SGS sweeps
+// Eq. "sgs-precon": x = P^-1 r, P = (D+L) D^-1 (D+U), by a forward and a
+// backward block Gauss-Seidel sweep.  With g = D^-1 r and M = D^-1 B:
+//     forward  (ascending i+j):  y_c = g_c - sum_{nb earlier} M_{c,nb} y_nb
+//     backward (descending):     x_c = y_c - sum_{nb later}   M_{c,nb} x_nb
+// One workgroup walks the hyperplanes h = i + j; thread j owns row j, keeps
+// its west / east neighbour in registers and takes the south / north value
+// from the neighbouring thread through LDS, so the exact Gauss-Seidel
+// dependency order is kept with one barrier per hyperplane.  The wake-cut
+// partner (same row 0, earlier or later hyperplane) is kept in LDS.
+template <typename T>
+__device__ inline void mv_sub(const T *blk, int plane0, int NS, int s, const T v[4], T out[4]) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        T a = out[r];
+#pragma unroll
+        for (int c = 0; c < 4; ++c) a = fma(-blk[(plane0 + r * 4 + c) * NS + s], v[c], a);
+        out[r] = a;
+    }
+}
+
+template <typename T, int BS>
+__global__ __launch_bounds__(BS) void k_sgs(Lay L, const T *blk, const T *g, T *y, SweepArgs a) {
+    __shared__ T nbuf[2][BS][4];
+    extern __shared__ unsigned char smem[];
+    T *row0 = reinterpret_cast<T *>(smem);          // n_wake x 4
+    const int j = threadIdx.x;
+    const int ni = L.ni, nj = L.nj, NS = L.NS, nw = L.nw;
+    const bool active = j < nj;
+    const int H = ni + nj - 1;
+    // forward sweep
+    T yw[4] = {0, 0, 0, 0};
+    for (int h = 0; h < H; ++h) {
+        const int i = h - j;
+        if (active && i >= 0 && i < ni) {
+            const int s = L.slot(i, j);
+            T v[4];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) v[k] = g[k * NS + s];
+            if (i > 0) mv_sub(blk, BLK_M + 0, NS, s, yw, v);
+            if (j > 0) {
+                T ys[4];
+#pragma unroll
+                for (int k = 0; k < 4; ++k) ys[k] = nbuf[(h - 1) & 1][j - 1][k];
+                mv_sub(blk, BLK_M + 32, NS, s, ys, v);
+            } else if (L.topo == 1 && i >= ni - nw) {
+                T yp[4];
+                const int p = ni - 1 - i;
+#pragma unroll
+                for (int k = 0; k < 4; ++k) yp[k] = row0[p * 4 + k];
+                mv_sub(blk, BLK_M + 32, NS, s, yp, v);
+            }
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                nbuf[h & 1][j][k] = v[k];
+                y[k * NS + s] = v[k];
+                yw[k] = v[k];
+            }
+            if (j == 0 && L.topo == 1 && i < nw) {
+#pragma unroll
+                for (int k = 0; k < 4; ++k) row0[i * 4 + k] = v[k];
+            }
+        }
+        __syncthreads();
+    }
+    // backward sweep (+ stage update)
+    T xe[4] = {0, 0, 0, 0};
+    for (int h = H - 1; h >= 0; --h) {
+        const int i = h - j;
+        if (active && i >= 0 && i < ni) {
+            const int s = L.slot(i, j);
+            T v[4];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) v[k] = y[k * NS + s];
+            if (i < ni - 1) mv_sub(blk, BLK_M + 16, NS, s, xe, v);
+            if (j == 0 && L.topo == 1 && i < nw) {
+                T xp[4];
+                const int p = ni - 1 - i - (ni - nw);
+#pragma unroll
+                for (int k = 0; k < 4; ++k) xp[k] = row0[p * 4 + k];
+                mv_sub(blk, BLK_M + 32, NS, s, xp, v);
+            }
+            if (j < nj - 1) {
+                T xn[4];
+#pragma unroll
+                for (int k = 0; k < 4; ++k) xn[k] = nbuf[(h + 1) & 1][j + 1][k];
+                mv_sub(blk, BLK_M + 48, NS, s, xn, v);
+            }
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                nbuf[h & 1][j][k] = v[k];
+                xe[k] = v[k];
+            }
+            if (j == 0 && L.topo == 1 && i >= ni - nw) {
+#pragma unroll
+                for (int k = 0; k < 4; ++k) row0[(i - (ni - nw)) * 4 + k] = v[k];
+            }
+            if (a.xout) {
+#pragma unroll
+                for (int k = 0; k < 4; ++k) a.xout[k * NS + s] = (double)v[k];
+            }
+            if (a.update) {
+                if (a.aw) {
+#pragma unroll
+                    for (int k = 0; k < 4; ++k)
+                        a.u[k * NS + s] = a.u0[k * NS + s] - a.alpha * (double)v[k];
+                } else {
+                    const double d = a.dts[s];
+#pragma unroll
+                    for (int k = 0; k < 4; ++k)
+                        a.u[k * NS + s] = a.u0[k * NS + s] - a.alpha * (d * (double)v[k]);
+                }
+            }
+        }
+        __syncthreads();
+    }
+}
+
+template <typename BT>
+__global__ void k_dinv(Lay L, const BT *blk, const double *r, BT *g) {
+    int s = blockIdx.x * blockDim.x + threadIdx.x;
+    int i, j;
+    if (!decode(L, s, i, j) || !interior(L, i, j)) return;
+    const int NS = L.NS;
+    BT rb[4] = {(BT)r[s], (BT)r[NS + s], (BT)r[2 * NS + s], (BT)r[3 * NS + s]};
+#pragma unroll
+    for (int rr = 0; rr < 4; ++rr) {
+        BT a = (BT)0;
+#pragma unroll
+        for (int c = 0; c < 4; ++c) a = fma(blk[(BLK_DINV + rr * 4 + c) * NS + s], rb[c], a);
+        g[rr * NS + s] = a;
+    }
+}
+
+// ------------------------------------------------------------ transfers
+// Section 3: restriction = volume-weighted agglomeration of 2x2 cells.
+__global__ void k_restrict(Lay Lf, Lay Lc, const double *geof, const double *geoc, const double *vf,
+                           double *vc, double *vc2) {
+    int s = blockIdx.x * blockDim.x + threadIdx.x;
+    int i, j;
+    if (!decode(Lc, s, i, j) || !interior(Lc, i, j)) return;
+    const int NSf = Lf.NS, NSc = Lc.NS;
+    int c00 = Lf.slot(2 * i, 2 * j), c10 = Lf.slot(2 * i + 1, 2 * j);
+    int c01 = Lf.slot(2 * i, 2 * j + 1), c11 = Lf.slot(2 * i + 1, 2 * j + 1);
+    double v00 = geof[G_VOL * NSf + c00], v10 = geof[G_VOL * NSf + c10];
+    double v01 = geof[G_VOL * NSf + c01], v11 = geof[G_VOL * NSf + c11];
+    double vol = geoc[G_VOL * NSc + s];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        double w00 = vf[k * NSf + c00] * v00, w10 = vf[k * NSf + c10] * v10;
+        double w01 = vf[k * NSf + c01] * v01, w11 = vf[k * NSf + c11] * v11;
+        double r = (((w00 + w10) + w01) + w11) / vol;
+        vc[k * NSc + s] = r;
+        if (vc2) vc2[k * NSc + s] = r;
+    }
+}
+
+// Section 3: bilinear prolongation of the coarse correction, weights
+// 9/16 (parent), 3/16, 3/16, 1/16 towards the fine cell's side; the wake-cut
+// partner across the cut, the parent's value where a neighbour is missing.
+__global__ void k_prolong(Lay Lf, Lay Lc, const double *uc, const double *utc, double *uf) {
+    int s = blockIdx.x * blockDim.x + threadIdx.x;
+    int i, j;
+    if (!decode(Lf, s, i, j) || !interior(Lf, i, j)) return;
+    const int NSc = Lc.NS, NSf = Lf.NS;
+    int I = i / 2, J = j / 2;
+    int In = I + ((i & 1) ? 1 : -1), Jn = J + ((j & 1) ? 1 : -1);
+    bool vi = In >= 0 && In < Lc.ni, vj = Jn >= 0 && Jn < Lc.nj;
+    int s0 = Lc.slot(I, J);
+    int s1 = vi ? Lc.slot(In, J) : s0;
+    int s2 = s0, s3 = s0;
+    if (vj) s2 = Lc.slot(I, Jn);
+    else if (Jn < 0 && cut_col(Lc, I)) s2 = Lc.slot(Lc.ni - 1 - I, 0);
+    if (vi && vj) s3 = Lc.slot(In, Jn);
+    else if (vi && Jn < 0 && cut_col(Lc, In)) s3 = Lc.slot(Lc.ni - 1 - In, 0);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        double e0 = uc[k * NSc + s0] - utc[k * NSc + s0];
+        double e1 = uc[k * NSc + s1] - utc[k * NSc + s1];
+        double e2 = uc[k * NSc + s2] - utc[k * NSc + s2];
+        double e3 = uc[k * NSc + s3] - utc[k * NSc + s3];
+        double pe = (((9.0 * e0 + 3.0 * e1) + 3.0 * e2) + e3) * 0.0625;
+        uf[k * NSf + s] = uf[k * NSf + s] + pe;
+    }
+}
+
+__global__ void k_axpby(Lay L, double a, const double *x, double b, const double *y, double *out, int nc) {
+    int s = blockIdx.x * blockDim.x + threadIdx.x;
+    int i, j;
+    if (!decode(L, s, i, j) || !interior(L, i, j)) return;
+    for (int k = 0; k < nc; ++k) {
+        int o = k * L.NS + s;
+        out[o] = (y == nullptr) ? a * x[o] : a * x[o] + b * y[o];
+    }
+}
+
+__global__ void k_pack(Lay L, const double *p, double *n, int nc) {
+    int t = blockIdx.x * blockDim.x + threadIdx.x;
+    int N = L.ni * L.nj;
+    if (t >= N) return;
+    int j = t / L.ni, i = t - j * L.ni;
+    int s = L.slot(i, j);
+    for (int k = 0; k < nc; ++k) n[k * N + t] = p[k * L.NS + s];
+}
+
+__global__ void k_unpack(Lay L, const double *n, double *p, int nc) {
+    int t = blockIdx.x * blockDim.x + threadIdx.x;
+    int N = L.ni * L.nj;
+    if (t >= N) return;
+    int j = t / L.ni, i = t - j * L.ni;
+    int s = L.slot(i, j);
+    for (int k = 0; k < nc; ++k) p[k * L.NS + s] = n[k * N + t];
+}
+
+// RMS of the density component of F over interior cells; fixed-order
+// two-pass reduction (deterministic).
+constexpr int RED_BLOCKS = 128;
+__global__ __launch_bounds__(TPB) void k_norm1(Lay L, const double *F, double *red) {
+    __shared__ double sh[TPB];
+    double a = 0.0;
+    for (int s = blockIdx.x * blockDim.x + threadIdx.x; s < L.NS; s += gridDim.x * blockDim.x) {
+        int i, j;
+        if (decode(L, s, i, j) && interior(L, i, j)) a += F[s] * F[s];
+    }
+    sh[threadIdx.x] = a;
+    __syncthreads();
+    for (int w = TPB / 2; w > 0; w >>= 1) {
+        if (threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) red[blockIdx.x] = sh[0];
+}
+
+__global__ void k_norm2(const double *red, int n, double count, double *out) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    double a = 0.0;
+    for (int k = 0; k < n; ++k) a += red[k];
+    *out = sqrt(a / count);
+}
+
+}  // namespace
+
+// =================================================================== launchers
+void launch_geom_interior(const Lay &L, const double *xn, const double *yn, double *geo,
+                          const double *vol_children, const Lay *Lf, const double *geo_f,
+                          hipStream_t st) {
+    (void)vol_children;
+    Lay lf = Lf ? *Lf : L;
+    const double *vf = geo_f ? geo_f + (size_t)G_VOL * lf.NS : nullptr;
+    hipLaunchKernelGGL(k_geom_interior, dim3(nblocks(L.NS)), dim3(TPB), 0, st, L, xn, yn, geo, vf, lf);
+}
+
+void launch_geom_ghost(const Lay &L, const double *xn, const double *yn, double *geo, hipStream_t st) {
+    hipLaunchKernelGGL(k_geom_ghost, dim3(nblocks(L.NS)), dim3(TPB), 0, st, L, xn, yn, geo);
+}
+
+void launch_ghost_state(const Lay &L, const double *geo, double *u, const Phys &ph, int noslip,
+                        hipStream_t st) {
+    hipLaunchKernelGGL(k_ghost_state, dim3(nblocks(L.NS)), dim3(TPB), 0, st, L, geo, u, ph, noslip);
+}
+
+void launch_cell_quantities(const Lay &L, const double *geo, const double *u, double *cq, int rans,
+                            hipStream_t st) {
+    hipLaunchKernelGGL(k_cell_quantities, dim3(nblocks(L.NS)), dim3(TPB), 0, st, L, geo, u, cq, rans);
+}
+
+void launch_vertex_gradients(const Lay &L, const double *geo, const double *u, const double *cq,
+                             double *vg, hipStream_t st) {
+    hipLaunchKernelGGL(k_vertex_gradients, dim3(nblocks(L.NS)), dim3(TPB), 0, st, L, geo, u, cq, vg);
+}
+
+void launch_baldwin_lomax(const Lay &L, const double *geo, const double *u, const double *cq,
+                          const double *vg, double *mut, const Phys &ph, hipStream_t st) {
+    size_t shm = (size_t)5 * L.nj * sizeof(double);
+    hipLaunchKernelGGL(k_baldwin_lomax, dim3(L.ni), dim3(BL_TPB), shm, st, L, geo, u, cq, vg, mut, ph);
+}
+
+void launch_mut_ghosts(const Lay &L, double *mut, hipStream_t st) {
+    hipLaunchKernelGGL(k_mut_ghosts, dim3(nblocks(L.NS)), dim3(TPB), 0, st, L, mut);
+}
+
+void launch_local_time_step(const Lay &L, const double *geo, const double *u, double *dts,
+                            double cfl, hipStream_t st) {
+    hipLaunchKernelGGL(k_local_time_step, dim3(nblocks(L.NS)), dim3(TPB), 0, st, L, geo, u, dts, cfl);
+}
+
+void launch_residual(const Lay &L, const double *geo, const double *u, const double *cq,
+                     const double *vg, const double *mut, const double *un, const double *unm1,
+                     const double *src, const Phys &ph, const ResArgs &a, double *F, double *acc,
+                     const double *dts, const void *blk, void *g, hipStream_t st) {
+    if (a.fp32)
+        hipLaunchKernelGGL(k_residual<float>, dim3(nblocks(L.NS)), dim3(TPB), 0, st, L, geo, u, cq,
+                           vg, mut, un, unm1, src, ph, a, F, acc, dts, (const float *)blk, (float *)g);
+    else
+        hipLaunchKernelGGL(k_residual<double>, dim3(nblocks(L.NS)), dim3(TPB), 0, st, L, geo, u, cq,
+                           vg, mut, un, unm1, src, ph, a, F, acc, dts, (const double *)blk,
+                           (double *)g);
+}
+
+void launch_blocks(const Lay &L, const double *geo, const double *u, const double *cq,
+                   const double *mut, const double *dts, const Phys &ph, int aw, double tau,
+                   int viscous, int fp32, void *blk, hipStream_t st) {
+    if (fp32)
+        hipLaunchKernelGGL(k_blocks<float>, dim3(nblocks(L.NS)), dim3(TPB), 0, st, L, geo, u, cq, mut,
+                           dts, ph, aw, tau, viscous, (float *)blk);
+    else
+        hipLaunchKernelGGL(k_blocks<double>, dim3(nblocks(L.NS)), dim3(TPB), 0, st, L, geo, u, cq,
+                           mut, dts, ph, aw, tau, viscous, (double *)blk);
+}
+
+template <typename T>
+static void sgs_dispatch(const Lay &L, const void *blk, const void *g, void *y, const SweepArgs &a,
+                         hipStream_t st) {
+    size_t shm = (size_t)(L.nw > 0 ? L.nw : 1) * 4 * sizeof(T);
+    if (L.nj <= 64)
+        hipLaunchKernelGGL((k_sgs<T, 64>), dim3(1), dim3(64), shm, st, L, (const T *)blk,
+                           (const T *)g, (T *)y, a);
+    else if (L.nj <= 128)
+        hipLaunchKernelGGL((k_sgs<T, 128>), dim3(1), dim3(128), shm, st, L, (const T *)blk,
+                           (const T *)g, (T *)y, a);
+    else if (L.nj <= 256)
+        hipLaunchKernelGGL((k_sgs<T, 256>), dim3(1), dim3(256), shm, st, L, (const T *)blk,
+                           (const T *)g, (T *)y, a);
+    else
+        hipLaunchKernelGGL((k_sgs<T, 512>), dim3(1), dim3(512), shm, st, L, (const T *)blk,
+                           (const T *)g, (T *)y, a);
+}
+
+void launch_sgs(const Lay &L, const void *blk, const void *g, void *y, const SweepArgs &a, int fp32,
+                hipStream_t st) {
+    if (fp32) sgs_dispatch<float>(L, blk, g, y, a, st);
+    else sgs_dispatch<double>(L, blk, g, y, a, st);
+}
+
+void launch_dinv(const Lay &L, const void *blk, const double *r, void *g, int fp32, hipStream_t st) {
+    if (fp32)
+        hipLaunchKernelGGL(k_dinv<float>, dim3(nblocks(L.NS)), dim3(TPB), 0, st, L, (const float *)blk, r,
+                           (float *)g);
+    else
+        hipLaunchKernelGGL(k_dinv<double>, dim3(nblocks(L.NS)), dim3(TPB), 0, st, L, (const double *)blk, r,
+                           (double *)g);
+}
+
+void launch_restrict(const Lay &Lf, const Lay &Lc, const double *geo_f, const double *geo_c,
+                     const double *vf, double *vc, double *vc_copy, hipStream_t st) {
+    hipLaunchKernelGGL(k_restrict, dim3(nblocks(Lc.NS)), dim3(TPB), 0, st, Lf, Lc, geo_f, geo_c, vf,
+                       vc, vc_copy);
+}
+
+void launch_prolong(const Lay &Lf, const Lay &Lc, const double *uc, const double *utc, double *uf,
+                    hipStream_t st) {
+    hipLaunchKernelGGL(k_prolong, dim3(nblocks(Lf.NS)), dim3(TPB), 0, st, Lf, Lc, uc, utc, uf);
+}
+
+void launch_axpby_interior(const Lay &L, double a, const double *x, double b, const double *y,
+                           double *out, int ncomp, hipStream_t st) {
+    hipLaunchKernelGGL(k_axpby, dim3(nblocks(L.NS)), dim3(TPB), 0, st, L, a, x, b, y, out, ncomp);
+}
+
+void launch_pack(const Lay &L, const double *padded, double *natural, int ncomp, hipStream_t st) {
+    hipLaunchKernelGGL(k_pack, dim3(nblocks(L.ni * L.nj)), dim3(TPB), 0, st, L, padded, natural, ncomp);
+}
+
+void launch_unpack(const Lay &L, const double *natural, double *padded, int ncomp, hipStream_t st) {
+    hipLaunchKernelGGL(k_unpack, dim3(nblocks(L.ni * L.nj)), dim3(TPB), 0, st, L, natural, padded, ncomp);
+}
+
+int norm_scratch_size(const Lay &L) {
+    (void)L;
+    return RED_BLOCKS;
+}
+
+void launch_norm(const Lay &L, const double *F, double *red, double *out, hipStream_t st) {
+    hipLaunchKernelGGL(k_norm1, dim3(RED_BLOCKS), dim3(TPB), 0, st, L, F, red);
+    hipLaunchKernelGGL(k_norm2, dim3(1), dim3(64), 0, st, red, RED_BLOCKS, (double)L.ni * L.nj, out);
+}
+
+}  // namespace fas

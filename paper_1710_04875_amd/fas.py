@@ -1,0 +1,242 @@
+"""ctypes binding of the HIP library (include/fas.h).
+
+Argument marshalling only: every step of the solver runs in the library's
+kernels.  Device arrays are torch tensors on the current HIP device
+(float64, [4][nj][ni]); work is enqueued on torch's current stream.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass, fields
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libfas.so")
+
+FAS_OK, FAS_EINVAL, FAS_ENOMEM, FAS_EDEVICE, FAS_DIVERGED, FAS_NOT_CONVERGED = 0, -1, -2, -3, -4, -6
+FAS_BOX, FAS_CGRID = 0, 1
+FAS_EULER, FAS_RANS_BL = 0, 1
+FAS_AW3, FAS_PARK3J, FAS_AW5J, FAS_AW51, FAS_AW52, FAS_PARK51 = range(6)
+PARAMS_VERSION = 1
+
+_lib = None
+
+
+class FasError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__("fas status %d: %s" % (status, msg))
+        self.status = status
+
+
+class _Params(ctypes.Structure):
+    _fields_ = [
+        ("version", ctypes.c_int32), ("model", ctypes.c_int32), ("scheme", ctypes.c_int32),
+        ("n_ramp", ctypes.c_int32),
+        ("eta", ctypes.c_double), ("d_cut", ctypes.c_double), ("cfl", ctypes.c_double),
+        ("cfl_ramp", ctypes.c_double), ("ramp_growth", ctypes.c_double), ("kappa2c", ctypes.c_double),
+        ("mach", ctypes.c_double), ("alpha_deg", ctypes.c_double), ("reynolds", ctypes.c_double),
+        ("prandtl", ctypes.c_double), ("prandtl_t", ctypes.c_double),
+        ("n_levels", ctypes.c_int32), ("cycle_gamma", ctypes.c_int32), ("nu1", ctypes.c_int32),
+        ("precond_fp32", ctypes.c_int32),
+    ]
+
+
+@dataclass
+class Params:
+    """Mirror of fas_params (defaults: AW3, robust mode)."""
+    model: int = FAS_EULER
+    scheme: int = FAS_AW3
+    n_ramp: int = 2
+    eta: float = 0.5
+    d_cut: float = 0.5
+    cfl: float = 1.0e4
+    cfl_ramp: float = 20.0
+    ramp_growth: float = 1.0
+    kappa2c: float = 0.125
+    mach: float = 0.8
+    alpha_deg: float = 0.0
+    reynolds: float = 1.0e7
+    prandtl: float = 0.75
+    prandtl_t: float = 0.9
+    n_levels: int = 1
+    cycle_gamma: int = 1
+    nu1: int = 1
+    precond_fp32: int = 0
+
+    def c(self) -> _Params:
+        p = _Params()
+        p.version = PARAMS_VERSION
+        for f in fields(self):
+            setattr(p, f.name, getattr(self, f.name))
+        return p
+
+
+EXPORTS = [
+    "fas_params_default", "fas_grid_create", "fas_grid_destroy", "fas_state_create",
+    "fas_state_destroy", "fas_state_set_params", "fas_set_state", "fas_get_state",
+    "fas_get_level", "fas_residual", "fas_smooth", "fas_sgs_apply", "fas_cycle",
+    "fas_dual_time_step", "fas_last_error",
+]
+
+
+def load(path: str = LIB_PATH):
+    """Load libfas.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError("HIP library %s not built; run python -m paper_1710_04875_amd.build" % path)
+    lib = ctypes.CDLL(path)
+    vp, dp, ip = ctypes.c_void_p, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int32)
+    i32, f64 = ctypes.c_int32, ctypes.c_double
+    sig = {
+        "fas_params_default": (None, [ctypes.POINTER(_Params)]),
+        "fas_grid_create": (i32, [i32, i32, i32, i32, dp, dp, i32, ctypes.POINTER(vp)]),
+        "fas_grid_destroy": (None, [vp]),
+        "fas_state_create": (i32, [vp, ctypes.POINTER(_Params), vp, vp, ctypes.POINTER(vp)]),
+        "fas_state_destroy": (None, [vp]),
+        "fas_state_set_params": (i32, [vp, ctypes.POINTER(_Params)]),
+        "fas_set_state": (i32, [vp, vp]),
+        "fas_get_state": (i32, [vp, vp, vp]),
+        "fas_get_level": (i32, [vp, i32, vp, vp]),
+        "fas_residual": (i32, [vp, i32, vp]),
+        "fas_smooth": (i32, [vp, i32, i32]),
+        "fas_sgs_apply": (i32, [vp, i32, vp, vp]),
+        "fas_cycle": (i32, [vp, i32, f64, dp, ip]),
+        "fas_dual_time_step": (i32, [vp, f64, f64, i32, f64, dp, ip]),
+        "fas_last_error": (ctypes.c_char_p, []),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = lib
+    return lib
+
+
+def _check(st, allow=()):
+    if st != FAS_OK and st not in allow:
+        raise FasError(st, _lib.fas_last_error().decode())
+    return st
+
+
+def _dptr(t):
+    import torch
+    assert t.is_cuda and t.dtype == torch.float64 and t.is_contiguous()
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream():
+    import torch
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+class Grid:
+    """Structured grid with its agglomerated levels (host node arrays)."""
+
+    def __init__(self, topology, x, y, n_wake=0, n_levels=1):
+        lib = load()
+        x = np.ascontiguousarray(x, dtype=np.float64)
+        y = np.ascontiguousarray(y, dtype=np.float64)
+        self.nj, self.ni = x.shape[0] - 1, x.shape[1] - 1
+        self.topology, self.n_wake, self.n_levels = topology, n_wake, n_levels
+        h = ctypes.c_void_p()
+        _check(lib.fas_grid_create(topology, self.ni, self.nj, n_wake,
+                                   x.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                   y.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                   n_levels, ctypes.byref(h)))
+        self.h = h
+
+    def __del__(self):
+        if getattr(self, "h", None) and _lib is not None:
+            _lib.fas_grid_destroy(self.h)
+            self.h = None
+
+
+class State:
+    """One flow case on a Grid; every call enqueues on torch's current stream."""
+
+    def __init__(self, grid: Grid, params: Params, u0):
+        import torch
+        lib = load()
+        self.grid = grid
+        self.params = params
+        self.device = u0.device
+        u0 = u0.to(torch.float64).contiguous()
+        h = ctypes.c_void_p()
+        self._pc = params.c()
+        _check(lib.fas_state_create(grid.h, ctypes.byref(self._pc), _dptr(u0), _stream(), ctypes.byref(h)))
+        self.h = h
+        self._keep = u0
+
+    def __del__(self):
+        if getattr(self, "h", None) and _lib is not None:
+            _lib.fas_state_destroy(self.h)
+            self.h = None
+
+    def shape(self, level=0):
+        return (4, self.grid.nj >> level, self.grid.ni >> level)
+
+    def set_params(self, params: Params):
+        self.params = params
+        self._pc = params.c()
+        _check(_lib.fas_state_set_params(self.h, ctypes.byref(self._pc)))
+
+    def set_state(self, u):
+        u = u.to(torch_dtype()).contiguous()
+        _check(_lib.fas_set_state(self.h, _dptr(u)))
+        self._keep = u
+
+    def get_state(self, with_mut=False):
+        import torch
+        u = torch.empty(self.shape(), dtype=torch.float64, device=self.device)
+        mut = torch.empty(self.shape()[1:], dtype=torch.float64, device=self.device) if with_mut else None
+        _check(_lib.fas_get_state(self.h, _dptr(u), _dptr(mut) if with_mut else None))
+        return (u, mut) if with_mut else u
+
+    def get_level(self, level):
+        import torch
+        u = torch.empty(self.shape(level), dtype=torch.float64, device=self.device)
+        s = torch.empty(self.shape(level), dtype=torch.float64, device=self.device)
+        _check(_lib.fas_get_level(self.h, level, _dptr(u), _dptr(s)))
+        return u, s
+
+    def residual(self, level=0):
+        import torch
+        F = torch.empty(self.shape(level), dtype=torch.float64, device=self.device)
+        _check(_lib.fas_residual(self.h, level, _dptr(F)))
+        return F
+
+    def smooth(self, level=0, n_iter=1):
+        _check(_lib.fas_smooth(self.h, level, n_iter))
+
+    def sgs_apply(self, r, level=0):
+        import torch
+        r = r.to(torch.float64).contiguous()
+        x = torch.empty_like(r)
+        _check(_lib.fas_sgs_apply(self.h, level, _dptr(r), _dptr(x)))
+        return x
+
+    def cycle(self, max_cycles, drop_orders=0.0):
+        hist = np.zeros(max_cycles + 1)
+        n = ctypes.c_int32(0)
+        st = _check(_lib.fas_cycle(self.h, max_cycles, drop_orders,
+                                   hist.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), ctypes.byref(n)),
+                    allow=(FAS_NOT_CONVERGED, FAS_DIVERGED))
+        return hist[:n.value + 1], st
+
+    def dual_time_step(self, dt, alpha_deg, max_inner, drop_orders):
+        hist = np.zeros(max_inner + 1)
+        n = ctypes.c_int32(0)
+        st = _check(_lib.fas_dual_time_step(self.h, dt, alpha_deg, max_inner, drop_orders,
+                                            hist.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                            ctypes.byref(n)),
+                    allow=(FAS_NOT_CONVERGED, FAS_DIVERGED))
+        return hist[:n.value + 1], st
+
+
+def torch_dtype():
+    import torch
+    return torch.float64
