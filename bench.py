@@ -1,0 +1,244 @@
+#!/usr/bin/env python3
+"""Benchmark: AW3 + SGS FAS V-cycles on the steady RANS C-grid (one GPU).
+
+Workload: 256 x 128 algebraic C-grid around a 10 %-thick symmetric NACA
+4-digit section (wall spacing 1e-6 chord), Re = 1e7, M = 0.8, angle of
+attack drawn from U[0, 2] deg (seed 3), Baldwin-Lomax RANS, FAS V-cycle on
+3 levels, AW3 smoother with the SGS preconditioner, robust mode (d = 0.5,
+eta = 0.5, c* = 1e4).  A step is one FAS cycle including the residual-norm
+evaluation.  value = fine cells x cycles / s (one fine-level AW3 iteration
+per V-cycle: "cell-iters/s"), FP64 residual, FP64 preconditioner.  Also
+reported: the same with the FP32 preconditioner, the time to a 6-order
+residual drop for both, the roofline of the dominant kernel, and the CPU
+oracle on a bounded sample of the same workload.
+
+python bench.py [--gpus 1] [--steps K] [--warmup W]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+# algorithmic HBM bytes per cell of one SGS launch (forward + backward
+# sweep of one stage, FP64, blocks recomputed): 144 + 144
+SWEEP_BYTES_PER_CELL = 288.0
+# one residual evaluation per stage: u 32 + geometry 40 + f 32 + blended
+# accumulator 2 x 32 on average (440 B over three stages)
+RESIDUAL_BYTES_PER_CELL = 440.0 / 3.0
+
+
+def log(msg):
+    print("[bench] " + msg, file=sys.stderr, flush=True)
+
+
+def workload_params(fas, fp32=False):
+    import fas_inputs as fi
+    case = fi.steady_cgrid_case()
+    p = fas.Params(model=fas.FAS_RANS_BL, scheme=fas.FAS_AW3, mach=case.mach,
+                   alpha_deg=case.alpha_deg, reynolds=case.reynolds, n_levels=3,
+                   cycle_gamma=1, nu1=1, eta=0.5, d_cut=0.5, cfl=1.0e4, cfl_ramp=1.0,
+                   n_ramp=4, ramp_growth=1.5, kappa2c=0.125, precond_fp32=1 if fp32 else 0)
+    return case, p
+
+
+def level_cells(ni, nj, levels):
+    return [(ni >> l) * (nj >> l) for l in range(levels)]
+
+
+def run_gpu(fas, torch, steps, warmup, fp32, drop_cap):
+    case, p = workload_params(fas, fp32)
+    x, y = case.grid()
+    u0 = torch.from_numpy(case.initial_state(x, y)).cuda()
+    g = fas.Grid(case.topology, x, y, case.n_wake, p.n_levels)
+    out = {}
+    # throughput: warmup cycles, then K timed cycles with kernel timing on
+    st = fas.State(g, p, u0)
+    st.cycle(warmup)
+    st.profile(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    hist, status = st.cycle(steps)
+    torch.cuda.synchronize()
+    t = time.perf_counter() - t0
+    prof = st.profile_read()
+    st.profile(False)
+    n = len(hist) - 1
+    N = case.ni * case.nj
+    out["ms_per_step"] = 1e3 * t / max(n, 1)
+    out["value"] = N * n / t
+    out["steps_done"] = n
+    out["prof"] = prof
+    out["status"] = status
+    if getattr(run_gpu, "no_drop", False):
+        out["drop"] = None
+        out["final_state"] = st.get_state().cpu().numpy()
+        out["case"] = case
+        out["params"] = p
+        return out
+    # time to a 6-order drop from the initial state
+    st2 = fas.State(g, p, u0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    h2, status2 = st2.cycle(drop_cap, 6.0)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter() - t0
+    drop = math.log10(h2[0] / h2.min()) if len(h2) > 1 and h2.min() > 0 else 0.0
+    reached = bool(len(h2) > 1 and h2[-1] <= h2[0] * 1e-6)
+    out["drop"] = {"reached": reached, "seconds": t2 if reached else None,
+                   "cycles": len(h2) - 1, "orders_reached": round(drop, 3),
+                   "seconds_run": round(t2, 4),
+                   "avg_rate": round(float((h2[-1] / h2[0]) ** (1.0 / max(len(h2) - 1, 1))), 4)}
+    out["final_state"] = st2.get_state().cpu().numpy()
+    out["case"] = case
+    out["params"] = p
+    return out
+
+
+def sweep_roofline(res, case, levels):
+    ms, cnt = res["prof"]["sweep"]
+    cells = level_cells(case.ni, case.nj, levels)
+    # per cycle one AW3 iteration on every level: 3 sweep launches per level
+    per_cycle = 3.0 * sum(cells) * SWEEP_BYTES_PER_CELL
+    cycles = res["steps_done"]
+    achieved = per_cycle * cycles / (ms * 1e-3) / 1e9 if ms > 0 else 0.0
+    return {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": None,
+            "kernel": "k_sgs (forward + backward hyperplane SGS sweep)",
+            "avg_launch_us": round(1e3 * ms / max(cnt, 1), 3), "launches": cnt,
+            "algorithmic_bytes_per_cell": SWEEP_BYTES_PER_CELL}
+
+
+def load_traffic(kernel_key):
+    """Measured HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE,
+    calibrated) if the committed counter summary matches these sources."""
+    path = os.path.join(ROOT, "profiles", "traffic_%s.json" % kernel_key)
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        d = json.load(f)
+    src = os.path.join(ROOT, "paper_1710_04875_amd", "csrc", "fas_kernels.hip")
+    h = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+    if d.get("kernels_sha") != h:
+        return None
+    return d.get("bytes_per_launch")
+
+
+def cpu_baseline(seconds_target=15.0):
+    """The oracle (numpy + C sweep, single thread) on the first cycles of
+    the same workload."""
+    import numpy as np
+    from threadpoolctl import threadpool_limits
+    import fas_inputs as fi
+    from oracle import fas as ofas
+    case = fi.steady_cgrid_case()
+    x, y = case.grid()
+    u0 = case.initial_state(x, y)
+    op = ofas.Params(model=1, scheme=0, mach=case.mach, alpha_deg=case.alpha_deg,
+                     reynolds=case.reynolds, n_levels=3, cycle_gamma=1, nu1=1, eta=0.5, d_cut=0.5,
+                     cfl=1e4, cfl_ramp=1.0, n_ramp=4, ramp_growth=1.5, kappa2c=0.125)
+    with threadpool_limits(limits=1):
+        S = ofas.Solver(x, y, case.topology, case.n_wake, op, u0)
+        t0 = time.perf_counter()
+        n = 0
+        while time.perf_counter() - t0 < seconds_target and n < 200:
+            S.cycle(0)
+            S.n_cycles += 1
+            n += 1
+        t = time.perf_counter() - t0
+    return {"value": case.ni * case.nj * n / t, "unit": "cell-iters/s", "cores": 1, "kind": "oracle",
+            "sample": "first %d FAS V-cycles of the 256x128 RANS C-grid workload (%.1f s, numpy + C "
+                      "sweep, one thread)" % (n, t)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--drop-cap", type=int, default=300)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-fp32", action="store_true")
+    ap.add_argument("--no-drop", action="store_true", help="skip the time-to-drop runs")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="only copy a 256 MiB buffer 5 times (HBM counter calibration)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+              "(--gpus %d requested)" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+    if args.calibrate_copy:
+        a = torch.ones(32 * 1024 * 1024, dtype=torch.float64, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(5):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"calibration_copy_bytes_read": a.numel() * 8, "copies": 5}))
+        return
+    from paper_1710_04875_amd import fas
+    fas.load()
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    run_gpu.no_drop = args.no_drop
+    log("fp64 preconditioner run")
+    r64 = run_gpu(fas, torch, args.steps, args.warmup, False, args.drop_cap)
+    case, p = r64["case"], r64["params"]
+    roof = sweep_roofline(r64, case, p.n_levels)
+    roof["traffic"] = load_traffic("k_sgs_c2_fp64")
+    res_ms, res_n = r64["prof"]["residual"]
+    line = {
+        "metric": "AW3+SGS cell-iters/s & time to 6-order drop; FP32-precond vs FP64",
+        "value": round(r64["value"], 1),
+        "unit": "cell-iters/s",
+        "n_gpus": 1,
+        "steps": r64["steps_done"],
+        "warmup": args.warmup,
+        "ms_per_step": round(r64["ms_per_step"], 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "steady RANS (Baldwin-Lomax) 256x128 C-grid, NACA 4-digit 10%% section, "
+                               "M=0.8, alpha=%.4f deg, Re=1e7; FAS V-cycle 3 levels; AW3+SGS robust "
+                               "mode" % case.alpha_deg,
+                   "fine_cells": case.ni * case.nj, "levels": p.n_levels, "step": "one FAS cycle"},
+        "time_to_6_orders_fp64": r64["drop"],
+        "kernel_ms_per_step_fp64": {k: round(v[0] / max(r64["steps_done"], 1), 4)
+                                    for k, v in r64["prof"].items()},
+        "residual_kernel": {"avg_launch_us": round(1e3 * res_ms / max(res_n, 1), 3),
+                            "launches": res_n},
+        "roofline": roof,
+        "paper_context": {"steady_rate": 0.85, "unsteady_rate": 0.77,
+                          "hardware": "Intel i7-3770 one core (uflo103, NACA 64A010 512x64)"},
+    }
+    if not args.no_fp32:
+        log("fp32 preconditioner run")
+        r32 = run_gpu(fas, torch, args.steps, args.warmup, True, args.drop_cap)
+        u64, u32 = r64["final_state"], r32["final_state"]
+        diff = float((np.abs(u32 - u64).max(axis=0) / np.abs(u64).max(axis=0)).max())
+        line["fp32_precond"] = {
+            "value": round(r32["value"], 1), "ms_per_step": round(r32["ms_per_step"], 4),
+            "speedup_vs_fp64": round(r32["value"] / r64["value"], 3),
+            "time_to_6_orders": r32["drop"],
+            "max_rel_state_diff_vs_fp64_after_drop_run": diff,
+            "kernel_ms_per_step": {k: round(v[0] / max(r32["steps_done"], 1), 4)
+                                   for k, v in r32["prof"].items()},
+        }
+    if not args.no_cpu:
+        log("cpu baseline (oracle)")
+        line["cpu_baseline"] = cpu_baseline()
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -143,6 +143,18 @@ fas_status fas_cycle(fas_state s, int32_t max_cycles, double drop_orders,
 fas_status fas_dual_time_step(fas_state s, double dt, double alpha_deg, int32_t max_inner,
                               double drop_orders, double *res_hist, int32_t *n_inner);
 
+/*
+ * Opt-in timing of kernel classes with HIP events recorded on the state's
+ * stream around each launch (adds a little launch overhead while on).
+ * fas_profile resets the counters and switches timing on (enable = 1) or
+ * off; fas_profile_read synchronises the stream and returns, per class,
+ * the summed kernel time in ms and the number of launches (arrays of
+ * FAS_PROF_NCLASS entries, either may be NULL).
+ */
+enum { FAS_PROF_SWEEP = 0, FAS_PROF_RESIDUAL = 1, FAS_PROF_BLOCKS = 2, FAS_PROF_NCLASS = 3 };
+fas_status fas_profile(fas_state s, int32_t enable);
+fas_status fas_profile_read(fas_state s, double *ms, int64_t *count);
+
 /* Message of the last failing call on this thread (never NULL). */
 const char *fas_last_error(void);
 

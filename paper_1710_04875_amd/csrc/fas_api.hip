@@ -86,6 +86,13 @@ struct fas_state_s {
     double dt = 0.0;
     double *d_norm = nullptr;   // device scalar
     std::vector<void *> allocs;
+    // optional per-kernel-class timing with HIP events on the state's stream
+    int prof = 0;
+    struct Rec { int cls; hipEvent_t a, b; };
+    std::vector<Rec> recs;
+    std::vector<hipEvent_t> pool;
+    double prof_ms[FAS_PROF_NCLASS] = {0};
+    int64_t prof_n[FAS_PROF_NCLASS] = {0};
 };
 
 // --------------------------------------------------------------------- grid
@@ -235,6 +242,11 @@ static void set_phys(fas_state s) {
 extern "C" void fas_state_destroy(fas_state s) {
     if (!s) return;
     if (s->st) (void)hipStreamSynchronize(s->st);
+    for (auto &r : s->recs) {
+        (void)hipEventDestroy(r.a);
+        (void)hipEventDestroy(r.b);
+    }
+    for (auto e : s->pool) (void)hipEventDestroy(e);
     for (auto p : s->allocs) (void)hipFree(p);
     delete s;
 }
@@ -327,6 +339,37 @@ extern "C" fas_status fas_get_level(fas_state s, int32_t level, double *u, doubl
 // ----------------------------------------------------------- building blocks
 namespace {
 
+hipEvent_t take_event(fas_state s) {
+    if (!s->pool.empty()) {
+        hipEvent_t e = s->pool.back();
+        s->pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    (void)hipEventCreate(&e);
+    return e;
+}
+
+// brackets a launch with events when profiling is on
+struct Prof {
+    fas_state s;
+    int cls;
+    hipEvent_t a = nullptr;
+    Prof(fas_state s_, int c) : s(s_), cls(c) {
+        if (s->prof) {
+            a = take_event(s);
+            (void)hipEventRecord(a, s->st);
+        }
+    }
+    ~Prof() {
+        if (a) {
+            hipEvent_t b = take_event(s);
+            (void)hipEventRecord(b, s->st);
+            s->recs.push_back({cls, a, b});
+        }
+    }
+};
+
 bool fine_rans(fas_state s, int l) { return l == 0 && s->p.model == FAS_RANS_BL; }
 
 double tau_of(fas_state s) {
@@ -387,6 +430,7 @@ void prepare_iteration(fas_state s, int l, double cfl) {
     LevelDev &d = s->lv[l];
     prep(s, l, fine_rans(s, l));
     launch_local_time_step(d.L, d.geo, d.u, d.dts, cfl, s->st);
+    Prof pr(s, FAS_PROF_BLOCKS);
     launch_blocks(d.L, d.geo, d.u, d.cq, d.mut, d.dts, s->ph, s->sc.aw, tau_of(s), fine_rans(s, l),
                   s->p.precond_fp32, d.blk, s->st);
 }
@@ -401,8 +445,11 @@ void smooth_once(fas_state s, int l) {
         ResArgs a = res_args(s, l, 1, 1);
         a.stage = k;
         a.beta = s->sc.beta[k];
-        launch_residual(d.L, d.geo, d.u, d.cq, d.vg, d.mut, d.un, d.unm1, d.src, s->ph, a, d.F,
-                        d.acc, d.dts, d.blk, d.g, s->st);
+        {
+            Prof pr(s, FAS_PROF_RESIDUAL);
+            launch_residual(d.L, d.geo, d.u, d.cq, d.vg, d.mut, d.un, d.unm1, d.src, s->ph, a, d.F,
+                            d.acc, d.dts, d.blk, d.g, s->st);
+        }
         SweepArgs sw;
         sw.update = 1;
         sw.alpha = s->sc.alpha[k];
@@ -411,6 +458,7 @@ void smooth_once(fas_state s, int l) {
         sw.u0 = d.u0;
         sw.dts = d.dts;
         sw.xout = nullptr;
+        Prof pr(s, FAS_PROF_SWEEP);
         launch_sgs(d.L, d.blk, d.g, d.y, sw, s->p.precond_fp32, s->st);
     }
 }
@@ -523,6 +571,41 @@ extern "C" fas_status fas_dual_time_step(fas_state s, double dt, double alpha_de
     s->p.alpha_deg = alpha_deg;
     set_phys(s);
     return fas_cycle(s, max_inner, drop_orders, res_hist, n_inner);
+}
+
+extern "C" fas_status fas_profile(fas_state s, int32_t enable) {
+    if (!s) return fail(FAS_EINVAL, "null state");
+    HIPCHK(hipStreamSynchronize(s->st));
+    for (auto &r : s->recs) {
+        s->pool.push_back(r.a);
+        s->pool.push_back(r.b);
+    }
+    s->recs.clear();
+    for (int c = 0; c < FAS_PROF_NCLASS; ++c) {
+        s->prof_ms[c] = 0.0;
+        s->prof_n[c] = 0;
+    }
+    s->prof = enable ? 1 : 0;
+    return FAS_OK;
+}
+
+extern "C" fas_status fas_profile_read(fas_state s, double *ms, int64_t *count) {
+    if (!s) return fail(FAS_EINVAL, "null state");
+    HIPCHK(hipStreamSynchronize(s->st));
+    for (auto &r : s->recs) {
+        float t = 0.0f;
+        HIPCHK(hipEventElapsedTime(&t, r.a, r.b));
+        s->prof_ms[r.cls] += t;
+        s->prof_n[r.cls] += 1;
+        s->pool.push_back(r.a);
+        s->pool.push_back(r.b);
+    }
+    s->recs.clear();
+    for (int c = 0; c < FAS_PROF_NCLASS; ++c) {
+        if (ms) ms[c] = s->prof_ms[c];
+        if (count) count[c] = s->prof_n[c];
+    }
+    return FAS_OK;
 }
 
 extern "C" const char *fas_last_error(void) { return g_err.c_str(); }

@@ -40,11 +40,16 @@ enum CqPlane { Q_P, Q_Q, Q_RXI, Q_RETA, Q_T, Q_NPLANES };
 // vertex-gradient planes, vertex (I, J) stored at the slot of cell (I, J)
 enum VgPlane { V_UX, V_UY, V_VX, V_VY, V_TX, V_TY, V_NPLANES };
 
-// block planes: inverse of D and M_s = D^-1 B_s for the four neighbour
-// slots (0 west, 1 east, 2 south or wake-cut partner, 3 north), row-major
-constexpr int BLK_DINV = 0;
-constexpr int BLK_M = 16;
-constexpr int BLK_NPLANES = 80;
+// preconditioner blocks: five 4x4 blocks per cell, D^-1 and M_s = D^-1 B_s
+// for the four neighbour slots (0 west, 1 east, 2 south or wake-cut
+// partner, 3 north).  Block b of cell slot s is a contiguous row-major
+// record of 16 values at (b * NS + s) * 16, so one row of a block is one
+// aligned 4-vector and a wave reading rows of consecutive cells reads one
+// contiguous run.
+constexpr int B_DINV = 0;
+constexpr int B_M0 = 1;          // + slot
+constexpr int BLK_NBLOCKS = 5;
+constexpr int BLK_NPLANES = 80;  // values per cell
 
 struct Phys {
     double mach, alpha_deg, re, pr, prt, mu_inf;

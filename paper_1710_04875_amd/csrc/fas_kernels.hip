@@ -45,6 +45,30 @@ __device__ inline double sutherland(double T, double mu_inf) {
     return ((mu_inf * (T * sqrt(T))) * (1.0 + SUTH)) / (T + SUTH);
 }
 
+__device__ inline size_t brec(int b, int NS, int s) { return ((size_t)b * NS + s) * 16; }
+
+template <typename T> struct V4;
+template <> struct V4<double> {
+    __device__ static void load(const double *p, double o[4]) {
+        double2 a = *reinterpret_cast<const double2 *>(p);
+        double2 b = *reinterpret_cast<const double2 *>(p + 2);
+        o[0] = a.x; o[1] = a.y; o[2] = b.x; o[3] = b.y;
+    }
+};
+template <> struct V4<float> {
+    __device__ static void load(const float *p, float o[4]) {
+        float4 a = *reinterpret_cast<const float4 *>(p);
+        o[0] = a.x; o[1] = a.y; o[2] = a.z; o[3] = a.w;
+    }
+};
+
+// workgroup barrier that waits for LDS traffic only (global loads issued
+// for later hyperplanes stay in flight across it)
+__device__ inline void lds_barrier() {
+    __builtin_amdgcn_s_waitcnt(0xC07F);   // lgkmcnt(0), vmcnt / expcnt untouched
+    __builtin_amdgcn_s_barrier();
+}
+
 __device__ inline void ld4(const double *a, int NS, int s, double v[4]) {
 #pragma unroll
     for (int k = 0; k < 4; ++k) v[k] = a[k * NS + s];
@@ -640,11 +664,12 @@ __global__ __launch_bounds__(TPB) void k_residual(Lay L, const double *geo, cons
         for (int k = 0; k < 4; ++k) r[k] = d * r[k];
     }
     BT rb[4] = {(BT)r[0], (BT)r[1], (BT)r[2], (BT)r[3]};
+    const BT *Di = blk + brec(B_DINV, NS, s);
 #pragma unroll
     for (int rr = 0; rr < 4; ++rr) {
         BT acc4 = (BT)0;
 #pragma unroll
-        for (int c = 0; c < 4; ++c) acc4 = fma(blk[(BLK_DINV + rr * 4 + c) * NS + s], rb[c], acc4);
+        for (int c = 0; c < 4; ++c) acc4 = fma(Di[rr * 4 + c], rb[c], acc4);
         g[rr * NS + s] = acc4;
     }
 }
@@ -788,8 +813,9 @@ __global__ __launch_bounds__(TPB) void k_blocks(Lay L, const double *geo, const 
             }
         }
     }
+    BT *out = blk + brec(B_DINV, NS, s);
 #pragma unroll
-    for (int k = 0; k < 16; ++k) blk[(BLK_DINV + k) * NS + s] = (BT)Di[k];
+    for (int k = 0; k < 16; ++k) out[k] = (BT)Di[k];
     // pass 2: M_slot = D^-1 B_slot
     const bool has[4] = {i > 0, i < L.ni - 1, j > 0 || cut_col(L, i), j < L.nj - 1};
 #pragma unroll
@@ -811,6 +837,7 @@ __global__ __launch_bounds__(TPB) void k_blocks(Lay L, const double *geo, const 
                 for (int k = 0; k < 16; ++k) B[k] = c * Am[k];
             }
         }
+        BT *mo = blk + brec(B_M0 + sl, NS, s);
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
 #pragma unroll
@@ -820,7 +847,7 @@ __global__ __launch_bounds__(TPB) void k_blocks(Lay L, const double *geo, const 
 #pragma unroll
                     for (int k = 0; k < 4; ++k) m = fma(Di[r * 4 + k], B[k * 4 + cc], m);
                 }
-                blk[(BLK_M + sl * 16 + r * 4 + cc) * NS + s] = (BT)m;
+                mo[r * 4 + cc] = (BT)m;
             }
         }
     }
@@ -837,12 +864,13 @@ __global__ __launch_bounds__(TPB) void k_blocks(Lay L, const double *geo, const 
 // dependency order is kept with one barrier per hyperplane.  The wake-cut
 // partner (same row 0, earlier or later hyperplane) is kept in LDS.
 template <typename T>
-__device__ inline void mv_sub(const T *blk, int plane0, int NS, int s, const T v[4], T out[4]) {
+__device__ inline void mv_sub(const T *blk, int b, int NS, int s, const T v[4], T out[4]) {
+    const T *M = blk + brec(b, NS, s);
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
         T a = out[r];
 #pragma unroll
-        for (int c = 0; c < 4; ++c) a = fma(-blk[(plane0 + r * 4 + c) * NS + s], v[c], a);
+        for (int c = 0; c < 4; ++c) a = fma(-M[r * 4 + c], v[c], a);
         out[r] = a;
     }
 }
@@ -865,18 +893,18 @@ __global__ __launch_bounds__(BS) void k_sgs(Lay L, const T *blk, const T *g, T *
             T v[4];
 #pragma unroll
             for (int k = 0; k < 4; ++k) v[k] = g[k * NS + s];
-            if (i > 0) mv_sub(blk, BLK_M + 0, NS, s, yw, v);
+            if (i > 0) mv_sub(blk, B_M0 + 0, NS, s, yw, v);
             if (j > 0) {
                 T ys[4];
 #pragma unroll
                 for (int k = 0; k < 4; ++k) ys[k] = nbuf[(h - 1) & 1][j - 1][k];
-                mv_sub(blk, BLK_M + 32, NS, s, ys, v);
+                mv_sub(blk, B_M0 + 2, NS, s, ys, v);
             } else if (L.topo == 1 && i >= ni - nw) {
                 T yp[4];
                 const int p = ni - 1 - i;
 #pragma unroll
                 for (int k = 0; k < 4; ++k) yp[k] = row0[p * 4 + k];
-                mv_sub(blk, BLK_M + 32, NS, s, yp, v);
+                mv_sub(blk, B_M0 + 2, NS, s, yp, v);
             }
 #pragma unroll
             for (int k = 0; k < 4; ++k) {
@@ -889,9 +917,10 @@ __global__ __launch_bounds__(BS) void k_sgs(Lay L, const T *blk, const T *g, T *
                 for (int k = 0; k < 4; ++k) row0[i * 4 + k] = v[k];
             }
         }
-        __syncthreads();
+        lds_barrier();
     }
-    // backward sweep (+ stage update)
+    // backward sweep (+ stage update); the full barrier completes the y stores
+    __syncthreads();
     T xe[4] = {0, 0, 0, 0};
     for (int h = H - 1; h >= 0; --h) {
         const int i = h - j;
@@ -900,19 +929,19 @@ __global__ __launch_bounds__(BS) void k_sgs(Lay L, const T *blk, const T *g, T *
             T v[4];
 #pragma unroll
             for (int k = 0; k < 4; ++k) v[k] = y[k * NS + s];
-            if (i < ni - 1) mv_sub(blk, BLK_M + 16, NS, s, xe, v);
+            if (i < ni - 1) mv_sub(blk, B_M0 + 1, NS, s, xe, v);
             if (j == 0 && L.topo == 1 && i < nw) {
                 T xp[4];
                 const int p = ni - 1 - i - (ni - nw);
 #pragma unroll
                 for (int k = 0; k < 4; ++k) xp[k] = row0[p * 4 + k];
-                mv_sub(blk, BLK_M + 32, NS, s, xp, v);
+                mv_sub(blk, B_M0 + 2, NS, s, xp, v);
             }
             if (j < nj - 1) {
                 T xn[4];
 #pragma unroll
                 for (int k = 0; k < 4; ++k) xn[k] = nbuf[(h + 1) & 1][j + 1][k];
-                mv_sub(blk, BLK_M + 48, NS, s, xn, v);
+                mv_sub(blk, B_M0 + 3, NS, s, xn, v);
             }
 #pragma unroll
             for (int k = 0; k < 4; ++k) {
@@ -940,7 +969,7 @@ __global__ __launch_bounds__(BS) void k_sgs(Lay L, const T *blk, const T *g, T *
                 }
             }
         }
-        __syncthreads();
+        lds_barrier();
     }
 }
 
@@ -951,12 +980,148 @@ __global__ void k_dinv(Lay L, const BT *blk, const double *r, BT *g) {
     if (!decode(L, s, i, j) || !interior(L, i, j)) return;
     const int NS = L.NS;
     BT rb[4] = {(BT)r[s], (BT)r[NS + s], (BT)r[2 * NS + s], (BT)r[3 * NS + s]};
+    const BT *Di = blk + brec(B_DINV, NS, s);
 #pragma unroll
     for (int rr = 0; rr < 4; ++rr) {
         BT a = (BT)0;
 #pragma unroll
-        for (int c = 0; c < 4; ++c) a = fma(blk[(BLK_DINV + rr * 4 + c) * NS + s], rb[c], a);
+        for (int c = 0; c < 4; ++c) a = fma(Di[rr * 4 + c], rb[c], a);
         g[rr * NS + s] = a;
+    }
+}
+
+// Same sweeps with four threads per cell, thread (j, r) owning component
+// r of row j: each thread needs one row of each 4x4 block per step, which
+// is prefetched D hyperplanes ahead into registers (the per-step data does
+// not depend on the sweep, only the neighbour values do).  The full
+// neighbour vectors are exchanged through LDS, one barrier per hyperplane.
+// Same operation order per component as k_sgs.
+template <typename T, int NT, int D>
+__global__ __launch_bounds__(NT) void k_sgs4(Lay L, const T *blk, const T *g, T *y, SweepArgs a) {
+    __shared__ T xb[2][NT];
+    extern __shared__ unsigned char smem[];
+    T *row0 = reinterpret_cast<T *>(smem);                 // n_wake x 4
+    T *pblk = row0 + (L.nw > 0 ? L.nw : 1) * 4;           // n_wake x 16: slot-2 blocks of (i, 0), i < n_wake
+    const int t = threadIdx.x, j = t >> 2, r = t & 3;
+    const int ni = L.ni, nj = L.nj, NS = L.NS, nw = L.nw;
+    const bool active = j < nj;
+    const bool cutg = L.topo == 1;
+    const int H = ni + nj - 1;
+    const int jc = j < nj ? j : nj - 1;
+    if (cutg) {
+        for (int q = t; q < nw * 16; q += NT) {
+            const int ii = q >> 4, e = q & 15;
+            pblk[q] = blk[brec(B_M0 + 2, NS, L.slot(ii, 0)) + e];
+        }
+    }
+    auto cslot = [&](int h) {
+        int i = h - j;
+        i = i < 0 ? 0 : (i >= ni ? ni - 1 : i);
+        return L.slot(i, jc);
+    };
+    // ---------------- forward
+    {
+        T pg[D], pw[D][4], ps[D][4];
+#pragma unroll
+        for (int k = 0; k < D; ++k) {
+            const int s = cslot(k < H ? k : H - 1);
+            pg[k] = g[r * NS + s];
+            V4<T>::load(blk + brec(B_M0 + 0, NS, s) + r * 4, pw[k]);
+            V4<T>::load(blk + brec(B_M0 + 2, NS, s) + r * 4, ps[k]);
+        }
+        __syncthreads();
+        for (int h0 = 0; h0 < H; h0 += D) {
+#pragma unroll
+            for (int k = 0; k < D; ++k) {
+                const int h = h0 + k;
+                if (h < H) {
+                    const int i = h - j;
+                    if (active && i >= 0 && i < ni) {
+                        const int s = L.slot(i, j);
+                        T v = pg[k];
+                        const T *prev = xb[(h - 1) & 1];
+                        if (i > 0) {
+#pragma unroll
+                            for (int c = 0; c < 4; ++c) v = fma(-pw[k][c], prev[4 * j + c], v);
+                        }
+                        if (j > 0) {
+#pragma unroll
+                            for (int c = 0; c < 4; ++c) v = fma(-ps[k][c], prev[4 * (j - 1) + c], v);
+                        } else if (cutg && i >= ni - nw) {
+                            const int p = ni - 1 - i;
+#pragma unroll
+                            for (int c = 0; c < 4; ++c) v = fma(-ps[k][c], row0[p * 4 + c], v);
+                        }
+                        xb[h & 1][t] = v;
+                        y[r * NS + s] = v;
+                        if (j == 0 && cutg && i < nw) row0[i * 4 + r] = v;
+                    }
+                    const int hn = h + D < H ? h + D : H - 1;
+                    const int sn = cslot(hn);
+                    pg[k] = g[r * NS + sn];
+                    V4<T>::load(blk + brec(B_M0 + 0, NS, sn) + r * 4, pw[k]);
+                    V4<T>::load(blk + brec(B_M0 + 2, NS, sn) + r * 4, ps[k]);
+                    lds_barrier();
+                }
+            }
+        }
+    }
+    // ---------------- backward (+ stage update); the full barrier completes the y stores
+    __syncthreads();
+    {
+        T py[D], pe[D][4], pn[D][4];
+        double pu[D];
+#pragma unroll
+        for (int k = 0; k < D; ++k) {
+            const int h = H - 1 - k;
+            const int s = cslot(h >= 0 ? h : 0);
+            py[k] = y[r * NS + s];
+            pu[k] = a.update ? a.u0[r * NS + s] : 0.0;
+            V4<T>::load(blk + brec(B_M0 + 1, NS, s) + r * 4, pe[k]);
+            V4<T>::load(blk + brec(B_M0 + 3, NS, s) + r * 4, pn[k]);
+        }
+        __syncthreads();
+        for (int h0 = 0; h0 < H; h0 += D) {
+#pragma unroll
+            for (int k = 0; k < D; ++k) {
+                const int h = H - 1 - (h0 + k);
+                if (h >= 0) {
+                    const int i = h - j;
+                    if (active && i >= 0 && i < ni) {
+                        const int s = L.slot(i, j);
+                        T v = py[k];
+                        const T *prev = xb[(h + 1) & 1];
+                        if (i < ni - 1) {
+#pragma unroll
+                            for (int c = 0; c < 4; ++c) v = fma(-pe[k][c], prev[4 * j + c], v);
+                        }
+                        if (j == 0 && cutg && i < nw) {
+                            const int p = ni - 1 - i - (ni - nw);
+#pragma unroll
+                            for (int c = 0; c < 4; ++c) v = fma(-pblk[i * 16 + r * 4 + c], row0[p * 4 + c], v);
+                        }
+                        if (j < nj - 1) {
+#pragma unroll
+                            for (int c = 0; c < 4; ++c) v = fma(-pn[k][c], prev[4 * (j + 1) + c], v);
+                        }
+                        xb[h & 1][t] = v;
+                        if (j == 0 && cutg && i >= ni - nw) row0[(i - (ni - nw)) * 4 + r] = v;
+                        if (a.xout) a.xout[r * NS + s] = (double)v;
+                        if (a.update) {
+                            if (a.aw) a.u[r * NS + s] = pu[k] - a.alpha * (double)v;
+                            else a.u[r * NS + s] = pu[k] - a.alpha * (a.dts[s] * (double)v);
+                        }
+                    }
+                    const int hn = h - D >= 0 ? h - D : 0;
+                    const int sn = cslot(hn);
+                    py[k] = y[r * NS + sn];
+                    pu[k] = a.update ? a.u0[r * NS + sn] : 0.0;
+                    V4<T>::load(blk + brec(B_M0 + 1, NS, sn) + r * 4, pe[k]);
+                    V4<T>::load(blk + brec(B_M0 + 3, NS, sn) + r * 4, pn[k]);
+                    lds_barrier();
+                }
+            }
+        }
     }
 }
 
@@ -1140,6 +1305,32 @@ template <typename T>
 static void sgs_dispatch(const Lay &L, const void *blk, const void *g, void *y, const SweepArgs &a,
                          hipStream_t st) {
     size_t shm = (size_t)(L.nw > 0 ? L.nw : 1) * 4 * sizeof(T);
+    size_t shm4 = (size_t)(L.nw > 0 ? L.nw : 1) * 20 * sizeof(T);
+    if (L.nj <= 16) {
+        hipLaunchKernelGGL((k_sgs4<T, 64, 8>), dim3(1), dim3(64), shm4, st, L, (const T *)blk,
+                           (const T *)g, (T *)y, a);
+        return;
+    }
+    if (L.nj <= 32) {
+        hipLaunchKernelGGL((k_sgs4<T, 128, 8>), dim3(1), dim3(128), shm4, st, L, (const T *)blk,
+                           (const T *)g, (T *)y, a);
+        return;
+    }
+    if (L.nj <= 64) {
+        hipLaunchKernelGGL((k_sgs4<T, 256, 8>), dim3(1), dim3(256), shm4, st, L, (const T *)blk,
+                           (const T *)g, (T *)y, a);
+        return;
+    }
+    if (L.nj <= 128) {
+        hipLaunchKernelGGL((k_sgs4<T, 512, 8>), dim3(1), dim3(512), shm4, st, L, (const T *)blk,
+                           (const T *)g, (T *)y, a);
+        return;
+    }
+    if (L.nj <= 256) {
+        hipLaunchKernelGGL((k_sgs4<T, 1024, 4>), dim3(1), dim3(1024), shm4, st, L, (const T *)blk,
+                           (const T *)g, (T *)y, a);
+        return;
+    }
     if (L.nj <= 64)
         hipLaunchKernelGGL((k_sgs<T, 64>), dim3(1), dim3(64), shm, st, L, (const T *)blk,
                            (const T *)g, (T *)y, a);

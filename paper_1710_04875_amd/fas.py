@@ -77,8 +77,9 @@ EXPORTS = [
     "fas_params_default", "fas_grid_create", "fas_grid_destroy", "fas_state_create",
     "fas_state_destroy", "fas_state_set_params", "fas_set_state", "fas_get_state",
     "fas_get_level", "fas_residual", "fas_smooth", "fas_sgs_apply", "fas_cycle",
-    "fas_dual_time_step", "fas_last_error",
+    "fas_dual_time_step", "fas_profile", "fas_profile_read", "fas_last_error",
 ]
+PROF_CLASSES = ("sweep", "residual", "blocks")
 
 
 def load(path: str = LIB_PATH):
@@ -106,6 +107,8 @@ def load(path: str = LIB_PATH):
         "fas_sgs_apply": (i32, [vp, i32, vp, vp]),
         "fas_cycle": (i32, [vp, i32, f64, dp, ip]),
         "fas_dual_time_step": (i32, [vp, f64, f64, i32, f64, dp, ip]),
+        "fas_profile": (i32, [vp, i32]),
+        "fas_profile_read": (i32, [vp, dp, ctypes.POINTER(ctypes.c_int64)]),
         "fas_last_error": (ctypes.c_char_p, []),
     }
     for name, (res, args) in sig.items():
@@ -226,6 +229,16 @@ class State:
                                    hist.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), ctypes.byref(n)),
                     allow=(FAS_NOT_CONVERGED, FAS_DIVERGED))
         return hist[:n.value + 1], st
+
+    def profile(self, enable=True):
+        _check(_lib.fas_profile(self.h, 1 if enable else 0))
+
+    def profile_read(self):
+        ms = np.zeros(len(PROF_CLASSES))
+        n = np.zeros(len(PROF_CLASSES), dtype=np.int64)
+        _check(_lib.fas_profile_read(self.h, ms.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                     n.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))))
+        return {c: (float(ms[k]), int(n[k])) for k, c in enumerate(PROF_CLASSES)}
 
     def dual_time_step(self, dt, alpha_deg, max_inner, drop_orders):
         hist = np.zeros(max_inner + 1)

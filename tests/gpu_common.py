@@ -13,6 +13,10 @@ def case_inputs(kind):
         x, y = fi.box_grid(64, 64)
         return dict(topo=fi.BOX, x=x, y=y, nw=0, u0=fi.box_initial_state(x, y), model=0,
                     alpha=0.0)
+    if kind == "box_tall":         # nj > 256: the one-thread-per-row sweep
+        x, y = fi.box_grid(16, 288, ratio=1.01)
+        return dict(topo=fi.BOX, x=x, y=y, nw=0, u0=fi.box_initial_state(x, y), model=0,
+                    alpha=0.0)
     if kind == "box_small":
         x, y = fi.box_grid(24, 20)
         return dict(topo=fi.BOX, x=x, y=y, nw=0, u0=fi.box_initial_state(x, y), model=0,

@@ -25,7 +25,8 @@ def test_residual_parity(kind):
     assert res_err(Fg, Fo) < 1e-12
 
 
-@pytest.mark.parametrize("kind", ["box_small", "cgrid_small_euler", "cgrid_small_rans"])
+@pytest.mark.parametrize("kind", ["box_small", "box_tall", "cgrid_small_euler", "cgrid_small_rans",
+                                  "cgrid_c2_rans"])
 def test_sgs_apply_parity(kind):
     inp = case_inputs(kind)
     g, st, S = make_pair(inp, cfl=1e4, cfl_ramp=1e4)
