@@ -47,6 +47,24 @@ __device__ inline double sutherland(double T, double mu_inf) {
 
 __device__ inline size_t brec(int b, int NS, int s) { return ((size_t)b * NS + s) * 16; }
 
+// Element (row r, column c) of block b of cell slot s.  FP32 blocks: one
+// 16-value record per cell (a block row is one 16-byte vector).  FP64
+// blocks: two half planes per block, columns 0-1 and 2-3, each holding the
+// four rows' column pairs of a cell contiguously (64 bytes), so that the
+// 16-byte loads of a wave reading one block row for consecutive cells form
+// one contiguous run.
+template <typename T> struct BL;
+template <> struct BL<float> {
+    __host__ __device__ static size_t at(int b, int NS, int s, int r, int c) {
+        return ((size_t)b * NS + s) * 16 + r * 4 + c;
+    }
+};
+template <> struct BL<double> {
+    __host__ __device__ static size_t at(int b, int NS, int s, int r, int c) {
+        return ((size_t)(2 * b + (c >> 1)) * NS + s) * 8 + r * 2 + (c & 1);
+    }
+};
+
 template <typename T> struct V4;
 template <> struct V4<double> {
     __device__ static void load(const double *p, double o[4]) {
@@ -664,12 +682,11 @@ __global__ __launch_bounds__(TPB) void k_residual(Lay L, const double *geo, cons
         for (int k = 0; k < 4; ++k) r[k] = d * r[k];
     }
     BT rb[4] = {(BT)r[0], (BT)r[1], (BT)r[2], (BT)r[3]};
-    const BT *Di = blk + brec(B_DINV, NS, s);
 #pragma unroll
     for (int rr = 0; rr < 4; ++rr) {
         BT acc4 = (BT)0;
 #pragma unroll
-        for (int c = 0; c < 4; ++c) acc4 = fma(Di[rr * 4 + c], rb[c], acc4);
+        for (int c = 0; c < 4; ++c) acc4 = fma(blk[BL<BT>::at(B_DINV, NS, s, rr, c)], rb[c], acc4);
         g[rr * NS + s] = acc4;
     }
 }
@@ -813,9 +830,8 @@ __global__ __launch_bounds__(TPB) void k_blocks(Lay L, const double *geo, const 
             }
         }
     }
-    BT *out = blk + brec(B_DINV, NS, s);
 #pragma unroll
-    for (int k = 0; k < 16; ++k) out[k] = (BT)Di[k];
+    for (int k = 0; k < 16; ++k) blk[BL<BT>::at(B_DINV, NS, s, k >> 2, k & 3)] = (BT)Di[k];
     // pass 2: M_slot = D^-1 B_slot
     const bool has[4] = {i > 0, i < L.ni - 1, j > 0 || cut_col(L, i), j < L.nj - 1};
 #pragma unroll
@@ -837,7 +853,6 @@ __global__ __launch_bounds__(TPB) void k_blocks(Lay L, const double *geo, const 
                 for (int k = 0; k < 16; ++k) B[k] = c * Am[k];
             }
         }
-        BT *mo = blk + brec(B_M0 + sl, NS, s);
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
 #pragma unroll
@@ -847,7 +862,7 @@ __global__ __launch_bounds__(TPB) void k_blocks(Lay L, const double *geo, const 
 #pragma unroll
                     for (int k = 0; k < 4; ++k) m = fma(Di[r * 4 + k], B[k * 4 + cc], m);
                 }
-                mo[r * 4 + cc] = (BT)m;
+                blk[BL<BT>::at(B_M0 + sl, NS, s, r, cc)] = (BT)m;
             }
         }
     }
@@ -865,12 +880,11 @@ __global__ __launch_bounds__(TPB) void k_blocks(Lay L, const double *geo, const 
 // partner (same row 0, earlier or later hyperplane) is kept in LDS.
 template <typename T>
 __device__ inline void mv_sub(const T *blk, int b, int NS, int s, const T v[4], T out[4]) {
-    const T *M = blk + brec(b, NS, s);
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
         T a = out[r];
 #pragma unroll
-        for (int c = 0; c < 4; ++c) a = fma(-M[r * 4 + c], v[c], a);
+        for (int c = 0; c < 4; ++c) a = fma(-blk[BL<T>::at(b, NS, s, r, c)], v[c], a);
         out[r] = a;
     }
 }
@@ -980,147 +994,225 @@ __global__ void k_dinv(Lay L, const BT *blk, const double *r, BT *g) {
     if (!decode(L, s, i, j) || !interior(L, i, j)) return;
     const int NS = L.NS;
     BT rb[4] = {(BT)r[s], (BT)r[NS + s], (BT)r[2 * NS + s], (BT)r[3 * NS + s]};
-    const BT *Di = blk + brec(B_DINV, NS, s);
 #pragma unroll
     for (int rr = 0; rr < 4; ++rr) {
         BT a = (BT)0;
 #pragma unroll
-        for (int c = 0; c < 4; ++c) a = fma(Di[rr * 4 + c], rb[c], a);
+        for (int c = 0; c < 4; ++c) a = fma(blk[BL<BT>::at(B_DINV, NS, s, rr, c)], rb[c], a);
         g[rr * NS + s] = a;
     }
 }
 
-// Same sweeps with four threads per cell, thread (j, r) owning component
-// r of row j: each thread needs one row of each 4x4 block per step, which
-// is prefetched D hyperplanes ahead into registers (the per-step data does
-// not depend on the sweep, only the neighbour values do).  The full
-// neighbour vectors are exchanged through LDS, one barrier per hyperplane.
-// Same operation order per component as k_sgs.
-template <typename T, int NT, int D>
+// Same sweeps with four threads per cell row: thread (g, r) owns component
+// r of the R consecutive rows j = R g .. R g + R - 1.  Each thread needs one
+// row of each 4x4 block per row and hyperplane; these are prefetched into
+// registers in two alternating batches of D hyperplanes (load batch B,
+// consume batch A, load A, consume B), so each batch is issued D..2D
+// hyperplanes before use and every wait only has to exclude the newest
+// batch.  A cell of row j on hyperplane h = i + j sits at slot
+// (h + 4) NJ + j + 2 of the skewed layout: moving one hyperplane is a
+// uniform stride, so every load is a scalar base plus a constant per-lane
+// offset (valid memory for every h in [0, ni + nj) even where the cell does
+// not exist).  Neighbour vectors of the previous hyperplane come from LDS:
+// every row writes its value every hyperplane (zero where the cell does
+// not exist) and zero guard rows sit below row 0 and above the last row, so
+// absent neighbours read zero vectors (their blocks are zero as well).
+// One LDS-only barrier per hyperplane.
+template <typename T>
+__device__ inline T dot4(const T (&m)[4], const T *x) {
+    T p0 = fma(m[1], x[1], m[0] * x[0]);
+    T p1 = fma(m[3], x[3], m[2] * x[2]);
+    return p0 + p1;
+}
+
+// row of a block for the lane's cell: base is the block's first plane at
+// the hyperplane, boff the lane's byte offset within a plane, pstride the
+// distance between the two FP64 half planes (unused for FP32 records)
+template <typename T> struct RowLd;
+template <> struct RowLd<float> {
+    __device__ static void load(const float *base, unsigned boff, size_t pstride, float (&o)[4]) {
+        (void)pstride;
+        V4<float>::load(reinterpret_cast<const float *>(reinterpret_cast<const char *>(base) + boff), o);
+    }
+};
+template <> struct RowLd<double> {
+    __device__ static void load(const double *base, unsigned boff, size_t pstride, double (&o)[4]) {
+        double2 a = *reinterpret_cast<const double2 *>(reinterpret_cast<const char *>(base) + boff);
+        double2 b = *reinterpret_cast<const double2 *>(reinterpret_cast<const char *>(base + pstride) + boff);
+        o[0] = a.x; o[1] = a.y; o[2] = b.x; o[3] = b.y;
+    }
+};
+template <typename T>
+__device__ inline void ldrow(const T *base, unsigned boff, size_t pstride, T (&o)[4]) {
+    RowLd<T>::load(base, boff, pstride, o);
+}
+
+template <typename T>
+__device__ inline T ld1(const T *base, unsigned boff) {
+    return *reinterpret_cast<const T *>(reinterpret_cast<const char *>(base) + boff);
+}
+
+template <typename T, int NT, int R, int D>
 __global__ __launch_bounds__(NT) void k_sgs4(Lay L, const T *blk, const T *g, T *y, SweepArgs a) {
-    __shared__ T xb[2][NT];
+    constexpr int NR = NT / 4 * R;            // rows handled by the workgroup
+    constexpr int XS = 4 * NR + 8;            // zero guard row at both ends
+    __shared__ T xb[2][XS];
     extern __shared__ unsigned char smem[];
     T *row0 = reinterpret_cast<T *>(smem);                 // n_wake x 4
     T *pblk = row0 + (L.nw > 0 ? L.nw : 1) * 4;           // n_wake x 16: slot-2 blocks of (i, 0), i < n_wake
-    const int t = threadIdx.x, j = t >> 2, r = t & 3;
-    const int ni = L.ni, nj = L.nj, NS = L.NS, nw = L.nw;
-    const bool active = j < nj;
+    const int t = threadIdx.x, grp = t >> 2, r = t & 3;
+    const int ni = L.ni, nj = L.nj, NS = L.NS, NJ = L.NJ, nw = L.nw;
     const bool cutg = L.topo == 1;
     const int H = ni + nj - 1;
-    const int jc = j < nj ? j : nj - 1;
+    for (int q = t; q < XS; q += NT) {
+        xb[0][q] = (T)0;
+        xb[1][q] = (T)0;
+    }
     if (cutg) {
         for (int q = t; q < nw * 16; q += NT) {
             const int ii = q >> 4, e = q & 15;
-            pblk[q] = blk[brec(B_M0 + 2, NS, L.slot(ii, 0)) + e];
+            pblk[q] = blk[BL<T>::at(B_M0 + 2, NS, L.slot(ii, 0), e >> 2, e & 3)];
         }
     }
-    auto cslot = [&](int h) {
-        int i = h - j;
-        i = i < 0 ? 0 : (i >= ni ? ni - 1 : i);
-        return L.slot(i, jc);
-    };
+    // constant per-lane byte offsets; hyperplane h adds (h + 4) * NJ slots
+    // rows beyond nj read the last row's data and write to the ghost row
+    // j = nj; lanes without a cell on a hyperplane write to a ghost or unused
+    // slot, so every global store is unconditional (exact wait counts)
+    unsigned ov[R], ob[R], ow[R];
+    int jq[R];
+#pragma unroll
+    for (int q = 0; q < R; ++q) {
+        jq[q] = grp * R + q;
+        const int jr = jq[q] < nj ? jq[q] : nj - 1;
+        const int jw = jq[q] < nj ? jq[q] : nj;
+        ov[q] = (unsigned)((r * NS + jr + NG) * sizeof(T));
+        ob[q] = (unsigned)((BL<T>::at(0, NS, jr + NG, r, 0)) * sizeof(T));
+        ow[q] = (unsigned)((r * NS + jw + NG) * sizeof(T));
+    }
+    // block b at hyperplane slot base hc * NJ: first plane element
+    const size_t bstride = (size_t)NS * 16;                // one block (both FP64 half planes)
+    const size_t hpl = sizeof(T) == 8 ? (size_t)NS * 8 : 0;  // FP64 second half plane
+    const int rec = sizeof(T) == 8 ? 8 : 16;               // values per cell in a plane
+    auto hcl = [&](int h) { return h < 0 ? 0 : (h >= H ? H - 1 : h); };
     // ---------------- forward
     {
-        T pg[D], pw[D][4], ps[D][4];
-#pragma unroll
-        for (int k = 0; k < D; ++k) {
-            const int s = cslot(k < H ? k : H - 1);
-            pg[k] = g[r * NS + s];
-            V4<T>::load(blk + brec(B_M0 + 0, NS, s) + r * 4, pw[k]);
-            V4<T>::load(blk + brec(B_M0 + 2, NS, s) + r * 4, ps[k]);
-        }
-        __syncthreads();
-        for (int h0 = 0; h0 < H; h0 += D) {
+        T gA[D][R], wA[D][R][4], sA[D][R][4], gB[D][R], wB[D][R][4], sB[D][R][4];
+        auto load = [&](T (&gg)[D][R], T (&ww)[D][R][4], T (&ss)[D][R][4], int hb) {
 #pragma unroll
             for (int k = 0; k < D; ++k) {
-                const int h = h0 + k;
-                if (h < H) {
-                    const int i = h - j;
-                    if (active && i >= 0 && i < ni) {
-                        const int s = L.slot(i, j);
-                        T v = pg[k];
-                        const T *prev = xb[(h - 1) & 1];
-                        if (i > 0) {
+                const int hc = hcl(hb + k) + 2 * NG;
+                const T *gb = g + (size_t)hc * NJ;
+                const T *wb = blk + (size_t)(B_M0 + 0) * bstride + (size_t)hc * NJ * rec;
+                const T *sb = blk + (size_t)(B_M0 + 2) * bstride + (size_t)hc * NJ * rec;
 #pragma unroll
-                            for (int c = 0; c < 4; ++c) v = fma(-pw[k][c], prev[4 * j + c], v);
-                        }
-                        if (j > 0) {
-#pragma unroll
-                            for (int c = 0; c < 4; ++c) v = fma(-ps[k][c], prev[4 * (j - 1) + c], v);
-                        } else if (cutg && i >= ni - nw) {
-                            const int p = ni - 1 - i;
-#pragma unroll
-                            for (int c = 0; c < 4; ++c) v = fma(-ps[k][c], row0[p * 4 + c], v);
-                        }
-                        xb[h & 1][t] = v;
-                        y[r * NS + s] = v;
-                        if (j == 0 && cutg && i < nw) row0[i * 4 + r] = v;
-                    }
-                    const int hn = h + D < H ? h + D : H - 1;
-                    const int sn = cslot(hn);
-                    pg[k] = g[r * NS + sn];
-                    V4<T>::load(blk + brec(B_M0 + 0, NS, sn) + r * 4, pw[k]);
-                    V4<T>::load(blk + brec(B_M0 + 2, NS, sn) + r * 4, ps[k]);
-                    lds_barrier();
+                for (int q = 0; q < R; ++q) {
+                    gg[k][q] = ld1(gb, ov[q]);
+                    ldrow(wb, ob[q], hpl, ww[k][q]);
+                    ldrow(sb, ob[q], hpl, ss[k][q]);
                 }
             }
+        };
+        auto step = [&](const T (&gv)[R], const T (&wv)[R][4], const T (&sv)[R][4], int h) {
+            const T *prev = xb[(h - 1) & 1];
+            T *cur = xb[h & 1];
+            T *yb = y + (size_t)(h + 2 * NG) * NJ;
+#pragma unroll
+            for (int q = 0; q < R; ++q) {
+                const int jj = jq[q];
+                const int i = h - jj;
+                const T *xs = prev + 4 * jj;                        // row jj - 1 (guard row for jj = 0)
+                if (jj == 0 && cutg && i >= ni - nw && i < ni) xs = row0 + (ni - 1 - i) * 4;
+                const T v = (gv[q] - dot4(wv[q], prev + 4 * jj + 4)) - dot4(sv[q], xs);
+                const bool valid = jj < nj && i >= 0 && i < ni;
+                cur[4 * jj + 4 + r] = valid ? v : (T)0;
+                *reinterpret_cast<T *>(reinterpret_cast<char *>(yb) + ow[q]) = v;
+                if (valid && jj == 0 && cutg && i < nw) row0[i * 4 + r] = v;
+            }
+            lds_barrier();
+        };
+        load(gA, wA, sA, 0);
+        __syncthreads();
+        for (int h0 = 0; h0 < H; h0 += 2 * D) {
+            load(gB, wB, sB, h0 + D);
+#pragma unroll
+            for (int k = 0; k < D; ++k)
+                if (h0 + k < H) step(gA[k], wA[k], sA[k], h0 + k);
+            load(gA, wA, sA, h0 + 2 * D);
+#pragma unroll
+            for (int k = 0; k < D; ++k)
+                if (h0 + D + k < H) step(gB[k], wB[k], sB[k], h0 + D + k);
         }
     }
     // ---------------- backward (+ stage update); the full barrier completes the y stores
     __syncthreads();
+    for (int q = t; q < XS; q += NT) {
+        xb[0][q] = (T)0;
+        xb[1][q] = (T)0;
+    }
+    __syncthreads();
     {
-        T py[D], pe[D][4], pn[D][4];
-        double pu[D];
-#pragma unroll
-        for (int k = 0; k < D; ++k) {
-            const int h = H - 1 - k;
-            const int s = cslot(h >= 0 ? h : 0);
-            py[k] = y[r * NS + s];
-            pu[k] = a.update ? a.u0[r * NS + s] : 0.0;
-            V4<T>::load(blk + brec(B_M0 + 1, NS, s) + r * 4, pe[k]);
-            V4<T>::load(blk + brec(B_M0 + 3, NS, s) + r * 4, pn[k]);
-        }
-        __syncthreads();
-        for (int h0 = 0; h0 < H; h0 += D) {
+        T yA[D][R], eA[D][R][4], nA[D][R][4], yB[D][R], eB[D][R][4], nB[D][R][4];
+        double uA[D][R], uB[D][R];
+        const double *u0 = a.update ? a.u0 : reinterpret_cast<const double *>(y);
+        auto load = [&](T (&yy)[D][R], T (&ee)[D][R][4], T (&nn)[D][R][4], double (&uu)[D][R], int hb) {
 #pragma unroll
             for (int k = 0; k < D; ++k) {
-                const int h = H - 1 - (h0 + k);
-                if (h >= 0) {
-                    const int i = h - j;
-                    if (active && i >= 0 && i < ni) {
-                        const int s = L.slot(i, j);
-                        T v = py[k];
-                        const T *prev = xb[(h + 1) & 1];
-                        if (i < ni - 1) {
+                const int hc = hcl(H - 1 - (hb + k)) + 2 * NG;
+                const T *yb = y + (size_t)hc * NJ;
+                const double *ub = u0 + (size_t)hc * NJ;
+                const T *eb = blk + (size_t)(B_M0 + 1) * bstride + (size_t)hc * NJ * rec;
+                const T *nb = blk + (size_t)(B_M0 + 3) * bstride + (size_t)hc * NJ * rec;
 #pragma unroll
-                            for (int c = 0; c < 4; ++c) v = fma(-pe[k][c], prev[4 * j + c], v);
-                        }
-                        if (j == 0 && cutg && i < nw) {
-                            const int p = ni - 1 - i - (ni - nw);
-#pragma unroll
-                            for (int c = 0; c < 4; ++c) v = fma(-pblk[i * 16 + r * 4 + c], row0[p * 4 + c], v);
-                        }
-                        if (j < nj - 1) {
-#pragma unroll
-                            for (int c = 0; c < 4; ++c) v = fma(-pn[k][c], prev[4 * (j + 1) + c], v);
-                        }
-                        xb[h & 1][t] = v;
-                        if (j == 0 && cutg && i >= ni - nw) row0[(i - (ni - nw)) * 4 + r] = v;
-                        if (a.xout) a.xout[r * NS + s] = (double)v;
-                        if (a.update) {
-                            if (a.aw) a.u[r * NS + s] = pu[k] - a.alpha * (double)v;
-                            else a.u[r * NS + s] = pu[k] - a.alpha * (a.dts[s] * (double)v);
-                        }
-                    }
-                    const int hn = h - D >= 0 ? h - D : 0;
-                    const int sn = cslot(hn);
-                    py[k] = y[r * NS + sn];
-                    pu[k] = a.update ? a.u0[r * NS + sn] : 0.0;
-                    V4<T>::load(blk + brec(B_M0 + 1, NS, sn) + r * 4, pe[k]);
-                    V4<T>::load(blk + brec(B_M0 + 3, NS, sn) + r * 4, pn[k]);
-                    lds_barrier();
+                for (int q = 0; q < R; ++q) {
+                    yy[k][q] = ld1(yb, ov[q]);
+                    uu[k][q] = a.update ? ld1(ub, ov[q] / sizeof(T) * sizeof(double)) : 0.0;
+                    ldrow(eb, ob[q], hpl, ee[k][q]);
+                    ldrow(nb, ob[q], hpl, nn[k][q]);
                 }
             }
+        };
+        auto step = [&](const T (&yv)[R], const T (&ev)[R][4], const T (&nv)[R][4], const double (&u0v)[R],
+                        int h) {
+            const T *prev = xb[(h + 1) & 1];
+            T *cur = xb[h & 1];
+            const size_t hs = (size_t)(h + 2 * NG) * NJ;
+#pragma unroll
+            for (int q = 0; q < R; ++q) {
+                const int jj = jq[q];
+                const int i = h - jj;
+                T v = (yv[q] - dot4(ev[q], prev + 4 * jj + 4)) - dot4(nv[q], prev + 4 * jj + 8);
+                if (jj == 0 && cutg && i >= 0 && i < nw) {
+                    T mp[4];
+#pragma unroll
+                    for (int c = 0; c < 4; ++c) mp[c] = pblk[i * 16 + r * 4 + c];
+                    v = v - dot4(mp, row0 + (ni - 1 - i - (ni - nw)) * 4);
+                }
+                const bool valid = jj < nj && i >= 0 && i < ni;
+                cur[4 * jj + 4 + r] = valid ? v : (T)0;
+                if (valid && jj == 0 && cutg && i >= ni - nw) row0[(i - (ni - nw)) * 4 + r] = v;
+                const unsigned ew = ow[q] / sizeof(T) * sizeof(double);
+                if (a.xout)
+                    *reinterpret_cast<double *>(reinterpret_cast<char *>(a.xout + hs) + ew) = (double)v;
+                if (a.update) {
+                    double un;
+                    if (a.aw) un = u0v[q] - a.alpha * (double)v;
+                    else un = u0v[q] - a.alpha * (a.dts[hs + (jj < nj ? jj : nj) + NG] * (double)v);
+                    *reinterpret_cast<double *>(reinterpret_cast<char *>(a.u + hs) + ew) = un;
+                }
+            }
+            lds_barrier();
+        };
+        load(yA, eA, nA, uA, 0);
+        __syncthreads();
+        for (int h0 = 0; h0 < H; h0 += 2 * D) {
+            load(yB, eB, nB, uB, h0 + D);
+#pragma unroll
+            for (int k = 0; k < D; ++k)
+                if (h0 + k < H) step(yA[k], eA[k], nA[k], uA[k], H - 1 - (h0 + k));
+            load(yA, eA, nA, uA, h0 + 2 * D);
+#pragma unroll
+            for (int k = 0; k < D; ++k)
+                if (h0 + D + k < H) step(yB[k], eB[k], nB[k], uB[k], H - 1 - (h0 + D + k));
         }
     }
 }
@@ -1306,28 +1398,30 @@ static void sgs_dispatch(const Lay &L, const void *blk, const void *g, void *y, 
                          hipStream_t st) {
     size_t shm = (size_t)(L.nw > 0 ? L.nw : 1) * 4 * sizeof(T);
     size_t shm4 = (size_t)(L.nw > 0 ? L.nw : 1) * 20 * sizeof(T);
+    // one row per four-thread group (NT = 4 nj threads), prefetch batches of
+    // D hyperplanes as deep as the register file allows
     if (L.nj <= 16) {
-        hipLaunchKernelGGL((k_sgs4<T, 64, 8>), dim3(1), dim3(64), shm4, st, L, (const T *)blk,
+        hipLaunchKernelGGL((k_sgs4<T, 64, 1, 10>), dim3(1), dim3(64), shm4, st, L, (const T *)blk,
                            (const T *)g, (T *)y, a);
         return;
     }
     if (L.nj <= 32) {
-        hipLaunchKernelGGL((k_sgs4<T, 128, 8>), dim3(1), dim3(128), shm4, st, L, (const T *)blk,
+        hipLaunchKernelGGL((k_sgs4<T, 128, 1, 10>), dim3(1), dim3(128), shm4, st, L, (const T *)blk,
                            (const T *)g, (T *)y, a);
         return;
     }
     if (L.nj <= 64) {
-        hipLaunchKernelGGL((k_sgs4<T, 256, 8>), dim3(1), dim3(256), shm4, st, L, (const T *)blk,
+        hipLaunchKernelGGL((k_sgs4<T, 256, 1, 10>), dim3(1), dim3(256), shm4, st, L, (const T *)blk,
                            (const T *)g, (T *)y, a);
         return;
     }
     if (L.nj <= 128) {
-        hipLaunchKernelGGL((k_sgs4<T, 512, 8>), dim3(1), dim3(512), shm4, st, L, (const T *)blk,
+        hipLaunchKernelGGL((k_sgs4<T, 512, 1, 5>), dim3(1), dim3(512), shm4, st, L, (const T *)blk,
                            (const T *)g, (T *)y, a);
         return;
     }
     if (L.nj <= 256) {
-        hipLaunchKernelGGL((k_sgs4<T, 1024, 4>), dim3(1), dim3(1024), shm4, st, L, (const T *)blk,
+        hipLaunchKernelGGL((k_sgs4<T, 1024, 1, 2>), dim3(1), dim3(1024), shm4, st, L, (const T *)blk,
                            (const T *)g, (T *)y, a);
         return;
     }
