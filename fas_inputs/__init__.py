@@ -150,6 +150,11 @@ def cgrid(ni: int = 256, nj: int = 128, n_wake: int = 32, t: float = 0.10,
     ds_stream[:n_wake + 1] = np.abs(np.gradient(x_in[:n_wake + 1]))
     ds_stream[ni - n_wake:] = np.abs(np.gradient(x_in[ni - n_wake:]))
     first = np.maximum(wall_spacing, ds_stream / max_aspect)
+    # far down a short wake the aspect-ratio floor can exceed what a
+    # stretched boundary-layer block of nbl cells holds; halve the block's
+    # mean spacing there (other columns are left as they are)
+    too_big = first * nbl >= bl_height
+    first = np.where(too_big, 0.5 * bl_height / max(nbl, 1), first)
     x = np.empty((nj + 1, ni + 1))
     y = np.empty((nj + 1, ni + 1))
     for I in range(ni + 1):

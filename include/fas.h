@@ -155,6 +155,54 @@ enum { FAS_PROF_SWEEP = 0, FAS_PROF_RESIDUAL = 1, FAS_PROF_BLOCKS = 2, FAS_PROF_
 fas_status fas_profile(fas_state s, int32_t enable);
 fas_status fas_profile_read(fas_state s, double *ms, int64_t *count);
 
+/*
+ * Batched steady solves: n independent flow cases, possibly on grids of
+ * different sizes and with different flow conditions, advanced together by
+ * the FAS cycle of Section 3 with the smoother of Section 4 (each case
+ * keeps its own exact SGS order).  Every kernel of a cycle is one launch
+ * over all cases; converged cases are masked by a device flag.
+ *
+ * fas_batch_create: the states must be on one device and share model,
+ * scheme, n_levels, cycle_gamma, nu1 and precond_fp32, and must be steady
+ * (no fas_dual_time_step taken).  The batch reads each state's flow
+ * parameters at creation and works in place on the states' device buffers:
+ * the states must outlive the batch and must not be used while a batch
+ * call runs.  stream: hipStream_t for the batch's work (NULL: the batch
+ * creates its own non-blocking stream).  autotune = 1 times every sweep
+ * configuration that covers the tallest grid of each level on the batch
+ * itself and keeps the fastest; 0 picks one by grid height.
+ * Errors: FAS_EINVAL, FAS_ENOMEM, FAS_EDEVICE.
+ */
+typedef struct fas_batch_s *fas_batch;
+fas_status fas_batch_create(int32_t n, const fas_state *states, void *stream, int32_t autotune,
+                            fas_batch *out);
+void fas_batch_destroy(fas_batch b);
+
+/*
+ * Up to max_cycles FAS cycles for every case, each case stopping on its own
+ * when its fine residual norm (as in fas_cycle) has dropped by drop_orders
+ * (<= 0: run max_cycles), is not finite, or the cap is reached.
+ * use_graph = 1 captures one batched cycle (cycle, norm, status update) in a
+ * HIP graph once and replays it; 0 launches the same kernels directly.
+ * Outputs (host, nullable): n_done[n] cycles run per case, status[n]
+ * (FAS_OK, FAS_NOT_CONVERGED, FAS_DIVERGED), res_hist[n][max_cycles + 1]
+ * norms before the first and after every cycle (entries after n_done are
+ * unspecified).  Returns the worst per-case status.
+ */
+fas_status fas_batch_solve(fas_batch b, int32_t max_cycles, double drop_orders, int32_t use_graph,
+                           int32_t *n_done, int32_t *status, double *res_hist);
+
+/* Sweep configuration chosen for a level (index, and rows one workgroup
+ * covers), and a manual override (cfg -1: pick by grid height; FAS_EINVAL
+ * if the configuration covers fewer rows than the level's tallest grid). */
+fas_status fas_batch_sweep_config(fas_batch b, int32_t level, int32_t *cfg, int32_t *rows);
+fas_status fas_batch_set_sweep_config(fas_batch b, int32_t level, int32_t cfg);
+
+/* Kernel-class timing of the batch's direct launches (as fas_profile;
+ * launches replayed from a graph are not timed). */
+fas_status fas_batch_profile(fas_batch b, int32_t enable);
+fas_status fas_batch_profile_read(fas_batch b, double *ms, int64_t *count);
+
 /* Message of the last failing call on this thread (never NULL). */
 const char *fas_last_error(void);
 

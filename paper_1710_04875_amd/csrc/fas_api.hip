@@ -71,28 +71,68 @@ struct fas_grid_s {
     std::vector<double *> geo, xn, yn;
 };
 
-struct fas_state_s {
-    fas_grid g;
-    fas_params p;
-    hipStream_t st;
-    int nlev;
-    Phys ph;
+namespace {
+
+// The cycle machinery over a batch of n cases that share the cycle
+// structure (model, scheme, levels, cycle type, preconditioner precision).
+// A flow state is a batch of one.
+struct Engine {
+    int n = 0, nlev = 0;
+    hipStream_t st = nullptr;
+    int model = FAS_EULER, fp32 = 0, gamma = 1, nu1 = 1;
     Scheme sc;
-    std::vector<LevelDev> lv;
-    std::vector<int> has_src;
-    int n_cycles = 0;
+    std::vector<BLev> lev;
+    int has_src[8] = {0, 0, 0, 0, 0, 0, 0, 0};
     int bdf = 0;
-    int have_un = 0;
     double dt = 0.0;
-    double *d_norm = nullptr;   // device scalar
-    std::vector<void *> allocs;
-    // optional per-kernel-class timing with HIP events on the state's stream
+    int *d_cyc = nullptr;       // [n]
+    double *d_norm = nullptr;   // [n]
+    // optional per-kernel-class timing with HIP events on the stream
     int prof = 0;
     struct Rec { int cls; hipEvent_t a, b; };
     std::vector<Rec> recs;
     std::vector<hipEvent_t> pool;
     double prof_ms[FAS_PROF_NCLASS] = {0};
     int64_t prof_n[FAS_PROF_NCLASS] = {0};
+};
+
+void engine_release_events(Engine &e) {
+    for (auto &r : e.recs) {
+        (void)hipEventDestroy(r.a);
+        (void)hipEventDestroy(r.b);
+    }
+    e.recs.clear();
+    for (auto ev : e.pool) (void)hipEventDestroy(ev);
+    e.pool.clear();
+}
+
+}  // namespace
+
+struct fas_state_s {
+    fas_grid g;
+    fas_params p;
+    int nlev;
+    Phys ph;
+    std::vector<LevelDev> lv;
+    Engine e;
+    int have_un = 0;
+    Phys *d_ph = nullptr;
+    std::vector<void *> allocs;
+};
+
+struct fas_batch_s {
+    std::vector<fas_state> states;
+    Engine e;
+    int own_stream = 0;
+    int *d_act = nullptr, *d_ndone = nullptr, *d_stat = nullptr;
+    double *d_h0 = nullptr, *d_hist = nullptr;
+    int hcap = 0;
+    int *h_act = nullptr;       // pinned
+    std::vector<void *> allocs;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    int graph_cap = -1;         // max_cycles / drop the graph was captured for
+    double graph_drop = 0.0;
 };
 
 // --------------------------------------------------------------------- grid
@@ -213,12 +253,11 @@ static fas_status check_params(const fas_params *p, int grid_levels) {
         return fail(FAS_EINVAL, "bad smoother parameters");
     if (!(p->mach > 0.0) || (p->model == FAS_RANS_BL && !(p->reynolds > 0.0)))
         return fail(FAS_EINVAL, "bad flow parameters");
+    if (p->precond_fp32 != 0 && p->precond_fp32 != 1) return fail(FAS_EINVAL, "bad precond_fp32");
     return FAS_OK;
 }
 
-static void set_phys(fas_state s) {
-    const fas_params &p = s->p;
-    Phys &ph = s->ph;
+static void fill_phys(const fas_params &p, Phys &ph) {
     ph.mach = p.mach;
     ph.alpha_deg = p.alpha_deg;
     ph.re = p.reynolds;
@@ -235,20 +274,54 @@ static void set_phys(fas_state s) {
     ph.eta = p.eta;
     ph.d_cut = p.d_cut;
     ph.kappa2c = p.kappa2c;
+    ph.cfl = p.cfl;
+    ph.cfl_ramp = p.cfl_ramp;
+    ph.ramp_growth = p.ramp_growth;
+    ph.n_ramp = p.n_ramp;
     ph.rans = p.model == FAS_RANS_BL;
-    s->sc = SCHEMES[p.scheme];
+}
+
+// host parameters -> device copy; waits for the state's earlier work, which
+// may still read the old values
+static fas_status set_phys(fas_state s) {
+    fill_phys(s->p, s->ph);
+    Engine &e = s->e;
+    e.model = s->p.model;
+    e.fp32 = s->p.precond_fp32;
+    e.gamma = s->p.cycle_gamma;
+    e.nu1 = s->p.nu1;
+    e.sc = SCHEMES[s->p.scheme];
+    HIPCHK(hipStreamSynchronize(e.st));
+    HIPCHK(hipMemcpyAsync(s->d_ph, &s->ph, sizeof(Phys), hipMemcpyHostToDevice, e.st));
+    HIPCHK(hipStreamSynchronize(e.st));
+    return FAS_OK;
 }
 
 extern "C" void fas_state_destroy(fas_state s) {
     if (!s) return;
-    if (s->st) (void)hipStreamSynchronize(s->st);
-    for (auto &r : s->recs) {
-        (void)hipEventDestroy(r.a);
-        (void)hipEventDestroy(r.b);
-    }
-    for (auto e : s->pool) (void)hipEventDestroy(e);
+    if (s->e.st) (void)hipStreamSynchronize(s->e.st);
+    engine_release_events(s->e);
     for (auto p : s->allocs) (void)hipFree(p);
     delete s;
+}
+
+static BLev make_blev(const std::vector<Lay> &lays, const LevelDev *dV, const Phys *dPH, const int *act,
+                      const int *cyc) {
+    BLev B;
+    B.k.V = dV;
+    B.k.PH = dPH;
+    B.k.act = act;
+    B.k.cyc = cyc;
+    B.n = (int)lays.size();
+    B.max_ns = B.max_ni = B.max_nj = B.max_nw = 0;
+    for (const Lay &L : lays) {
+        B.max_ns = std::max(B.max_ns, L.NS);
+        B.max_ni = std::max(B.max_ni, L.ni);
+        B.max_nj = std::max(B.max_nj, L.nj);
+        B.max_nw = std::max(B.max_nw, L.nw);
+    }
+    B.sweep_cfg = -1;
+    return B;
 }
 
 extern "C" fas_status fas_state_create(fas_grid g, const fas_params *p, const double *u0,
@@ -259,9 +332,11 @@ extern "C" fas_status fas_state_create(fas_grid g, const fas_params *p, const do
     fas_state s = new fas_state_s();
     s->g = g;
     s->p = *p;
-    s->st = (hipStream_t)stream;
     s->nlev = p->n_levels;
-    set_phys(s);
+    Engine &e = s->e;
+    e.st = (hipStream_t)stream;
+    e.n = 1;
+    e.nlev = s->nlev;
     auto cleanup = [&](fas_status st) {
         fas_state_destroy(s);
         return st;
@@ -280,8 +355,8 @@ extern "C" fas_status fas_state_create(fas_grid g, const fas_params *p, const do
         s->allocs.push_back(base);
         if (hipMalloc(&bb, nb) != hipSuccess) return cleanup(fail(FAS_ENOMEM, "state allocation failed"));
         s->allocs.push_back(bb);
-        if (hipMemsetAsync(base, 0, nd * sizeof(double), s->st) != hipSuccess ||
-            hipMemsetAsync(bb, 0, nb, s->st) != hipSuccess)
+        if (hipMemsetAsync(base, 0, nd * sizeof(double), e.st) != hipSuccess ||
+            hipMemsetAsync(bb, 0, nb, e.st) != hipSuccess)
             return cleanup(fail(FAS_EDEVICE, "state clear failed"));
         double *q = base;
         auto take = [&](size_t n) { double *r = q; q += n * NS; return r; };
@@ -294,10 +369,23 @@ extern "C" fas_status fas_state_create(fas_grid g, const fas_params *p, const do
         d.y = bb + (size_t)BLK_NPLANES * NS * 8 + (size_t)4 * NS * 8;
         s->lv.push_back(d);
     }
-    s->has_src.assign(s->nlev, 0);
-    if (hipMalloc(&s->d_norm, 8 * sizeof(double)) != hipSuccess) return cleanup(fail(FAS_ENOMEM, "allocation failed"));
-    s->allocs.push_back(s->d_norm);
-    launch_unpack(s->lv[0].L, u0, s->lv[0].u, 4, s->st);
+    // device descriptors: one LevelDev per level, the physics, the cycle
+    // counter and the norm
+    const size_t desc = (size_t)s->nlev * sizeof(LevelDev) + sizeof(Phys) + 64;
+    char *dd = nullptr;
+    if (hipMalloc(&dd, desc + 64) != hipSuccess) return cleanup(fail(FAS_ENOMEM, "allocation failed"));
+    s->allocs.push_back(dd);
+    LevelDev *dV = reinterpret_cast<LevelDev *>(dd);
+    s->d_ph = reinterpret_cast<Phys *>(dd + (size_t)s->nlev * sizeof(LevelDev));
+    e.d_norm = reinterpret_cast<double *>(dd + desc - 64);
+    e.d_cyc = reinterpret_cast<int *>(dd + desc);
+    if (hipMemcpyAsync(dV, s->lv.data(), (size_t)s->nlev * sizeof(LevelDev), hipMemcpyHostToDevice, e.st) != hipSuccess)
+        return cleanup(fail(FAS_EDEVICE, "descriptor upload failed"));
+    launch_fill_int(e.d_cyc, 1, 0, e.st);
+    for (int l = 0; l < s->nlev; ++l)
+        e.lev.push_back(make_blev({s->lv[l].L}, dV + l, s->d_ph, nullptr, e.d_cyc));
+    if (set_phys(s) != FAS_OK) return cleanup(FAS_EDEVICE);
+    launch_unpack(s->lv[0].L, u0, s->lv[0].u, 4, e.st);
     if (hipGetLastError() != hipSuccess) return cleanup(fail(FAS_EDEVICE, "kernel launch failed"));
     *out = s;
     return FAS_OK;
@@ -308,21 +396,20 @@ extern "C" fas_status fas_state_set_params(fas_state s, const fas_params *p) {
     STCHK(check_params(p, s->g->nlev));
     if (p->n_levels != s->nlev) return fail(FAS_EINVAL, "n_levels cannot change after creation");
     s->p = *p;
-    set_phys(s);
-    return FAS_OK;
+    return set_phys(s);
 }
 
 extern "C" fas_status fas_set_state(fas_state s, const double *u) {
     if (!s || !u) return fail(FAS_EINVAL, "null argument");
-    launch_unpack(s->lv[0].L, u, s->lv[0].u, 4, s->st);
+    launch_unpack(s->lv[0].L, u, s->lv[0].u, 4, s->e.st);
     HIPCHK(hipGetLastError());
     return FAS_OK;
 }
 
 extern "C" fas_status fas_get_state(fas_state s, double *u, double *mu_t) {
     if (!s) return fail(FAS_EINVAL, "null state");
-    if (u) launch_pack(s->lv[0].L, s->lv[0].u, u, 4, s->st);
-    if (mu_t) launch_pack(s->lv[0].L, s->lv[0].mut, mu_t, 1, s->st);
+    if (u) launch_pack(s->lv[0].L, s->lv[0].u, u, 4, s->e.st);
+    if (mu_t) launch_pack(s->lv[0].L, s->lv[0].mut, mu_t, 1, s->e.st);
     HIPCHK(hipGetLastError());
     return FAS_OK;
 }
@@ -330,8 +417,8 @@ extern "C" fas_status fas_get_state(fas_state s, double *u, double *mu_t) {
 extern "C" fas_status fas_get_level(fas_state s, int32_t level, double *u, double *source) {
     if (!s || level < 0 || level >= s->nlev) return fail(FAS_EINVAL, "bad level");
     const LevelDev &d = s->lv[level];
-    if (u) launch_pack(d.L, d.u, u, 4, s->st);
-    if (source) launch_pack(d.L, d.src, source, 4, s->st);
+    if (u) launch_pack(d.L, d.u, u, 4, s->e.st);
+    if (source) launch_pack(d.L, d.src, source, 4, s->e.st);
     HIPCHK(hipGetLastError());
     return FAS_OK;
 }
@@ -339,155 +426,176 @@ extern "C" fas_status fas_get_level(fas_state s, int32_t level, double *u, doubl
 // ----------------------------------------------------------- building blocks
 namespace {
 
-hipEvent_t take_event(fas_state s) {
-    if (!s->pool.empty()) {
-        hipEvent_t e = s->pool.back();
-        s->pool.pop_back();
-        return e;
+hipEvent_t take_event(Engine &e) {
+    if (!e.pool.empty()) {
+        hipEvent_t ev = e.pool.back();
+        e.pool.pop_back();
+        return ev;
     }
-    hipEvent_t e = nullptr;
-    (void)hipEventCreate(&e);
-    return e;
+    hipEvent_t ev = nullptr;
+    (void)hipEventCreate(&ev);
+    return ev;
 }
 
 // brackets a launch with events when profiling is on
 struct Prof {
-    fas_state s;
+    Engine &e;
     int cls;
     hipEvent_t a = nullptr;
-    Prof(fas_state s_, int c) : s(s_), cls(c) {
-        if (s->prof) {
-            a = take_event(s);
-            (void)hipEventRecord(a, s->st);
+    Prof(Engine &e_, int c) : e(e_), cls(c) {
+        if (e.prof) {
+            a = take_event(e);
+            (void)hipEventRecord(a, e.st);
         }
     }
     ~Prof() {
         if (a) {
-            hipEvent_t b = take_event(s);
-            (void)hipEventRecord(b, s->st);
-            s->recs.push_back({cls, a, b});
+            hipEvent_t b = take_event(e);
+            (void)hipEventRecord(b, e.st);
+            e.recs.push_back({cls, a, b});
         }
     }
 };
 
-bool fine_rans(fas_state s, int l) { return l == 0 && s->p.model == FAS_RANS_BL; }
+bool fine_rans(const Engine &e, int l) { return l == 0 && e.model == FAS_RANS_BL; }
 
-double tau_of(fas_state s) {
-    if (s->bdf == 2) return 3.0 / (2.0 * s->dt);
-    if (s->bdf == 1) return 1.0 / s->dt;
+double tau_of(const Engine &e) {
+    if (e.bdf == 2) return 3.0 / (2.0 * e.dt);
+    if (e.bdf == 1) return 1.0 / e.dt;
     return 0.0;
-}
-
-double cfl_now(fas_state s) {
-    const fas_params &p = s->p;
-    if (s->n_cycles < p.n_ramp) return std::fmin(p.cfl, p.cfl_ramp);
-    if (p.ramp_growth > 1.0)
-        return std::fmin(p.cfl, p.cfl_ramp * std::pow(p.ramp_growth, (double)(s->n_cycles - p.n_ramp + 1)));
-    return p.cfl;
 }
 
 // ghosts, cell quantities, vertex gradients (fine RANS) and, on request,
 // the Baldwin-Lomax eddy viscosity for the level's current solution
-void prep(fas_state s, int l, bool with_bl) {
-    LevelDev &d = s->lv[l];
-    const int noslip = s->p.model == FAS_RANS_BL;
-    launch_ghost_state(d.L, d.geo, d.u, s->ph, noslip, s->st);
-    launch_cell_quantities(d.L, d.geo, d.u, d.cq, s->p.model == FAS_RANS_BL, s->st);
-    if (fine_rans(s, l)) {
-        launch_vertex_gradients(d.L, d.geo, d.u, d.cq, d.vg, s->st);
+void prep(Engine &e, int l, bool with_bl) {
+    const BLev &B = e.lev[l];
+    const int rans = e.model == FAS_RANS_BL;
+    launch_ghost_state(B, rans, e.st);
+    launch_cell_quantities(B, rans, e.st);
+    if (fine_rans(e, l)) {
+        launch_vertex_gradients(B, e.st);
         if (with_bl) {
-            launch_baldwin_lomax(d.L, d.geo, d.u, d.cq, d.vg, d.mut, s->ph, s->st);
-            launch_mut_ghosts(d.L, d.mut, s->st);
+            launch_baldwin_lomax(B, e.st);
+            launch_mut_ghosts(B, e.st);
         }
     }
 }
 
-ResArgs res_args(fas_state s, int l, int mode, int forcing) {
+ResArgs res_args(const Engine &e, int l, int mode, int forcing) {
     ResArgs a;
     std::memset(&a, 0, sizeof(a));
     a.fine = l == 0;
-    a.viscous = fine_rans(s, l);
-    a.bdf = s->bdf;
-    a.dt = s->dt;
-    a.forcing = forcing && s->has_src[l];
+    a.viscous = fine_rans(e, l);
+    a.bdf = e.bdf;
+    a.dt = e.dt;
+    a.forcing = forcing && e.has_src[l];
     a.mode = mode;
-    a.aw = s->sc.aw;
-    a.fp32 = s->p.precond_fp32;
+    a.aw = e.sc.aw;
+    a.fp32 = e.fp32;
     return a;
 }
 
-// F_l(u_l) (- s_l) into lv[l].F, eddy viscosity evaluated at u_l
-void eval_F(fas_state s, int l, bool forcing) {
-    LevelDev &d = s->lv[l];
-    prep(s, l, fine_rans(s, l));
-    ResArgs a = res_args(s, l, 0, forcing);
-    launch_residual(d.L, d.geo, d.u, d.cq, d.vg, d.mut, d.un, d.unm1, d.src, s->ph, a, d.F, d.acc,
-                    d.dts, d.blk, d.g, s->st);
+// F_l(u_l) (- s_l) into the level's F, eddy viscosity evaluated at u_l
+void eval_F(Engine &e, int l, bool forcing) {
+    prep(e, l, fine_rans(e, l));
+    launch_residual(e.lev[l], res_args(e, l, 0, forcing), e.st);
 }
 
 // frozen quantities of one smoother iteration: dt*, eddy viscosity, blocks
-void prepare_iteration(fas_state s, int l, double cfl) {
-    LevelDev &d = s->lv[l];
-    prep(s, l, fine_rans(s, l));
-    launch_local_time_step(d.L, d.geo, d.u, d.dts, cfl, s->st);
-    Prof pr(s, FAS_PROF_BLOCKS);
-    launch_blocks(d.L, d.geo, d.u, d.cq, d.mut, d.dts, s->ph, s->sc.aw, tau_of(s), fine_rans(s, l),
-                  s->p.precond_fp32, d.blk, s->st);
+void prepare_iteration(Engine &e, int l) {
+    const BLev &B = e.lev[l];
+    prep(e, l, fine_rans(e, l));
+    launch_local_time_step(B, e.st);
+    Prof pr(e, FAS_PROF_BLOCKS);
+    launch_blocks(B, e.sc.aw, tau_of(e), fine_rans(e, l), e.fp32, e.st);
 }
 
 // one smoother iteration (Section 4 low-storage stages)
-void smooth_once(fas_state s, int l) {
-    LevelDev &d = s->lv[l];
-    launch_axpby_interior(d.L, 1.0, d.u, 0.0, nullptr, d.u0, 4, s->st);
-    prepare_iteration(s, l, cfl_now(s));
-    for (int k = 0; k < s->sc.s; ++k) {
-        if (k > 0) prep(s, l, false);
-        ResArgs a = res_args(s, l, 1, 1);
+void smooth_once(Engine &e, int l) {
+    const BLev &B = e.lev[l];
+    launch_axpby(B, 1.0, FLD_U, 0.0, FLD_NONE, FLD_U0, e.st);
+    prepare_iteration(e, l);
+    for (int k = 0; k < e.sc.s; ++k) {
+        if (k > 0) prep(e, l, false);
+        ResArgs a = res_args(e, l, 1, 1);
         a.stage = k;
-        a.beta = s->sc.beta[k];
+        a.beta = e.sc.beta[k];
         {
-            Prof pr(s, FAS_PROF_RESIDUAL);
-            launch_residual(d.L, d.geo, d.u, d.cq, d.vg, d.mut, d.un, d.unm1, d.src, s->ph, a, d.F,
-                            d.acc, d.dts, d.blk, d.g, s->st);
+            Prof pr(e, FAS_PROF_RESIDUAL);
+            launch_residual(B, a, e.st);
         }
         SweepArgs sw;
         sw.update = 1;
-        sw.alpha = s->sc.alpha[k];
-        sw.aw = s->sc.aw;
-        sw.u = d.u;
-        sw.u0 = d.u0;
-        sw.dts = d.dts;
-        sw.xout = nullptr;
-        Prof pr(s, FAS_PROF_SWEEP);
-        launch_sgs(d.L, d.blk, d.g, d.y, sw, s->p.precond_fp32, s->st);
+        sw.alpha = e.sc.alpha[k];
+        sw.aw = e.sc.aw;
+        sw.xout_acc = 0;
+        Prof pr(e, FAS_PROF_SWEEP);
+        launch_sgs(B, sw, e.fp32, e.st);
     }
 }
 
-void cycle(fas_state s, int l) {
-    const int nsm = l < s->nlev - 1 ? s->p.nu1 : 1;
-    for (int k = 0; k < nsm; ++k) smooth_once(s, l);
-    if (l == s->nlev - 1) return;
-    LevelDev &f = s->lv[l], &c = s->lv[l + 1];
-    eval_F(s, l, false);
+void cycle(Engine &e, int l) {
+    const int nsm = l < e.nlev - 1 ? e.nu1 : 1;
+    for (int k = 0; k < nsm; ++k) smooth_once(e, l);
+    if (l == e.nlev - 1) return;
+    const BLev &f = e.lev[l], &c = e.lev[l + 1];
+    eval_F(e, l, false);
     // r_l = s_l - F_l(u_l)
-    if (s->has_src[l]) launch_axpby_interior(f.L, -1.0, f.F, 1.0, f.src, f.F, 4, s->st);
-    else launch_axpby_interior(f.L, -1.0, f.F, 0.0, nullptr, f.F, 4, s->st);
-    launch_restrict(f.L, c.L, f.geo, c.geo, f.u, c.u, c.ut, s->st);
-    launch_restrict(f.L, c.L, f.geo, c.geo, f.F, c.acc, nullptr, s->st);
-    s->has_src[l + 1] = 0;
-    eval_F(s, l + 1, false);
-    launch_axpby_interior(c.L, 1.0, c.F, 1.0, c.acc, c.src, 4, s->st);
-    s->has_src[l + 1] = 1;
-    for (int k = 0; k < s->p.cycle_gamma; ++k) cycle(s, l + 1);
-    launch_prolong(f.L, c.L, c.u, c.ut, f.u, s->st);
+    if (e.has_src[l]) launch_axpby(f, -1.0, FLD_F, 1.0, FLD_SRC, FLD_F, e.st);
+    else launch_axpby(f, -1.0, FLD_F, 0.0, FLD_NONE, FLD_F, e.st);
+    launch_restrict(f, c, FLD_U, FLD_U, FLD_UT, e.st);
+    launch_restrict(f, c, FLD_F, FLD_ACC, FLD_NONE, e.st);
+    e.has_src[l + 1] = 0;
+    eval_F(e, l + 1, false);
+    launch_axpby(c, 1.0, FLD_F, 1.0, FLD_ACC, FLD_SRC, e.st);
+    e.has_src[l + 1] = 1;
+    for (int k = 0; k < e.gamma; ++k) cycle(e, l + 1);
+    launch_prolong(f, c, e.st);
+}
+
+// fine-level residual norm of every case into e.d_norm
+void eval_norm(Engine &e) {
+    eval_F(e, 0, false);
+    launch_norm(e.lev[0], e.d_norm, e.st);
 }
 
 fas_status norm(fas_state s, double *out) {
-    eval_F(s, 0, false);
-    LevelDev &d = s->lv[0];
-    launch_norm(d.L, d.F, d.red, s->d_norm, s->st);
-    HIPCHK(hipMemcpyAsync(out, s->d_norm, sizeof(double), hipMemcpyDeviceToHost, s->st));
-    HIPCHK(hipStreamSynchronize(s->st));
+    eval_norm(s->e);
+    HIPCHK(hipMemcpyAsync(out, s->e.d_norm, sizeof(double), hipMemcpyDeviceToHost, s->e.st));
+    HIPCHK(hipStreamSynchronize(s->e.st));
+    return FAS_OK;
+}
+
+fas_status profile_on(Engine &e, int enable) {
+    HIPCHK(hipStreamSynchronize(e.st));
+    for (auto &r : e.recs) {
+        e.pool.push_back(r.a);
+        e.pool.push_back(r.b);
+    }
+    e.recs.clear();
+    for (int c = 0; c < FAS_PROF_NCLASS; ++c) {
+        e.prof_ms[c] = 0.0;
+        e.prof_n[c] = 0;
+    }
+    e.prof = enable ? 1 : 0;
+    return FAS_OK;
+}
+
+fas_status profile_read(Engine &e, double *ms, int64_t *count) {
+    HIPCHK(hipStreamSynchronize(e.st));
+    for (auto &r : e.recs) {
+        float t = 0.0f;
+        HIPCHK(hipEventElapsedTime(&t, r.a, r.b));
+        e.prof_ms[r.cls] += t;
+        e.prof_n[r.cls] += 1;
+        e.pool.push_back(r.a);
+        e.pool.push_back(r.b);
+    }
+    e.recs.clear();
+    for (int c = 0; c < FAS_PROF_NCLASS; ++c) {
+        if (ms) ms[c] = e.prof_ms[c];
+        if (count) count[c] = e.prof_n[c];
+    }
     return FAS_OK;
 }
 
@@ -495,34 +603,31 @@ fas_status norm(fas_state s, double *out) {
 
 extern "C" fas_status fas_residual(fas_state s, int32_t level, double *F_out) {
     if (!s || !F_out || level < 0 || level >= s->nlev) return fail(FAS_EINVAL, "bad argument");
-    eval_F(s, level, true);
-    launch_pack(s->lv[level].L, s->lv[level].F, F_out, 4, s->st);
+    eval_F(s->e, level, true);
+    launch_pack(s->lv[level].L, s->lv[level].F, F_out, 4, s->e.st);
     HIPCHK(hipGetLastError());
     return FAS_OK;
 }
 
 extern "C" fas_status fas_smooth(fas_state s, int32_t level, int32_t n_iter) {
     if (!s || level < 0 || level >= s->nlev || n_iter < 0) return fail(FAS_EINVAL, "bad argument");
-    for (int k = 0; k < n_iter; ++k) smooth_once(s, level);
+    for (int k = 0; k < n_iter; ++k) smooth_once(s->e, level);
     HIPCHK(hipGetLastError());
     return FAS_OK;
 }
 
-namespace fas {
-void launch_dinv(const Lay &L, const void *blk, const double *r, void *g, int fp32, hipStream_t st);
-}
-
 extern "C" fas_status fas_sgs_apply(fas_state s, int32_t level, const double *r, double *x) {
     if (!s || !r || !x || level < 0 || level >= s->nlev) return fail(FAS_EINVAL, "bad argument");
-    LevelDev &d = s->lv[level];
-    prepare_iteration(s, level, cfl_now(s));
-    launch_unpack(d.L, r, d.F, 4, s->st);
-    launch_dinv(d.L, d.blk, d.F, d.g, s->p.precond_fp32, s->st);
+    Engine &e = s->e;
+    const LevelDev &d = s->lv[level];
+    prepare_iteration(e, level);
+    launch_unpack(d.L, r, d.F, 4, e.st);
+    launch_dinv(e.lev[level], e.fp32, e.st);
     SweepArgs sw;
     std::memset(&sw, 0, sizeof(sw));
-    sw.xout = d.acc;
-    launch_sgs(d.L, d.blk, d.g, d.y, sw, s->p.precond_fp32, s->st);
-    launch_pack(d.L, d.acc, x, 4, s->st);
+    sw.xout_acc = 1;
+    launch_sgs(e.lev[level], sw, e.fp32, e.st);
+    launch_pack(d.L, d.acc, x, 4, e.st);
     HIPCHK(hipGetLastError());
     return FAS_OK;
 }
@@ -530,6 +635,7 @@ extern "C" fas_status fas_sgs_apply(fas_state s, int32_t level, const double *r,
 extern "C" fas_status fas_cycle(fas_state s, int32_t max_cycles, double drop_orders, double *res_hist,
                                 int32_t *n_done) {
     if (!s || max_cycles < 0) return fail(FAS_EINVAL, "bad argument");
+    Engine &e = s->e;
     double h0 = 0.0, h = 0.0;
     STCHK(norm(s, &h0));
     if (res_hist) res_hist[0] = h0;
@@ -537,8 +643,8 @@ extern "C" fas_status fas_cycle(fas_state s, int32_t max_cycles, double drop_ord
     fas_status st = FAS_OK;
     if (!std::isfinite(h0)) st = FAS_DIVERGED;
     for (int k = 0; k < max_cycles && st == FAS_OK; ++k) {
-        cycle(s, 0);
-        s->n_cycles++;
+        cycle(e, 0);
+        launch_count_cycle(e.lev[0], e.d_cyc, e.st);
         ++done;
         STCHK(norm(s, &h));
         if (res_hist) res_hist[k + 1] = h;
@@ -557,55 +663,290 @@ extern "C" fas_status fas_cycle(fas_state s, int32_t max_cycles, double drop_ord
 extern "C" fas_status fas_dual_time_step(fas_state s, double dt, double alpha_deg, int32_t max_inner,
                                          double drop_orders, double *res_hist, int32_t *n_inner) {
     if (!s || !(dt > 0.0)) return fail(FAS_EINVAL, "bad argument");
+    Engine &e = s->e;
     if (s->have_un)
-        for (int l = 0; l < s->nlev; ++l)
-            launch_axpby_interior(s->lv[l].L, 1.0, s->lv[l].un, 0.0, nullptr, s->lv[l].unm1, 4, s->st);
-    launch_axpby_interior(s->lv[0].L, 1.0, s->lv[0].u, 0.0, nullptr, s->lv[0].un, 4, s->st);
-    for (int l = 1; l < s->nlev; ++l)
-        launch_restrict(s->lv[l - 1].L, s->lv[l].L, s->lv[l - 1].geo, s->lv[l].geo, s->lv[l - 1].un,
-                        s->lv[l].un, nullptr, s->st);
-    s->bdf = s->have_un ? 2 : 1;
+        for (int l = 0; l < s->nlev; ++l) launch_axpby(e.lev[l], 1.0, FLD_UN, 0.0, FLD_NONE, FLD_UNM1, e.st);
+    launch_axpby(e.lev[0], 1.0, FLD_U, 0.0, FLD_NONE, FLD_UN, e.st);
+    for (int l = 1; l < s->nlev; ++l) launch_restrict(e.lev[l - 1], e.lev[l], FLD_UN, FLD_UN, FLD_NONE, e.st);
+    e.bdf = s->have_un ? 2 : 1;
     s->have_un = 1;
-    s->dt = dt;
-    s->n_cycles = 0;
+    e.dt = dt;
+    launch_fill_int(e.d_cyc, 1, 0, e.st);
     s->p.alpha_deg = alpha_deg;
-    set_phys(s);
+    STCHK(set_phys(s));
     return fas_cycle(s, max_inner, drop_orders, res_hist, n_inner);
 }
 
 extern "C" fas_status fas_profile(fas_state s, int32_t enable) {
     if (!s) return fail(FAS_EINVAL, "null state");
-    HIPCHK(hipStreamSynchronize(s->st));
-    for (auto &r : s->recs) {
-        s->pool.push_back(r.a);
-        s->pool.push_back(r.b);
-    }
-    s->recs.clear();
-    for (int c = 0; c < FAS_PROF_NCLASS; ++c) {
-        s->prof_ms[c] = 0.0;
-        s->prof_n[c] = 0;
-    }
-    s->prof = enable ? 1 : 0;
-    return FAS_OK;
+    return profile_on(s->e, enable);
 }
 
 extern "C" fas_status fas_profile_read(fas_state s, double *ms, int64_t *count) {
     if (!s) return fail(FAS_EINVAL, "null state");
-    HIPCHK(hipStreamSynchronize(s->st));
-    for (auto &r : s->recs) {
-        float t = 0.0f;
-        HIPCHK(hipEventElapsedTime(&t, r.a, r.b));
-        s->prof_ms[r.cls] += t;
-        s->prof_n[r.cls] += 1;
-        s->pool.push_back(r.a);
-        s->pool.push_back(r.b);
-    }
-    s->recs.clear();
-    for (int c = 0; c < FAS_PROF_NCLASS; ++c) {
-        if (ms) ms[c] = s->prof_ms[c];
-        if (count) count[c] = s->prof_n[c];
-    }
+    return profile_read(s->e, ms, count);
+}
+
+// -------------------------------------------------------------------- batch
+extern "C" void fas_batch_destroy(fas_batch b) {
+    if (!b) return;
+    if (b->e.st) (void)hipStreamSynchronize(b->e.st);
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    engine_release_events(b->e);
+    for (auto p : b->allocs) (void)hipFree(p);
+    if (b->h_act) (void)hipHostFree(b->h_act);
+    if (b->own_stream && b->e.st) (void)hipStreamDestroy(b->e.st);
+    delete b;
+}
+
+static void drop_graph(fas_batch b) {
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    b->exec = nullptr;
+    b->graph = nullptr;
+    b->graph_cap = -1;
+}
+
+// time n sweeps of one level in configuration cfg (update off: only the
+// sweep's own scratch vector y is written)
+static fas_status time_sweep(Engine &e, int l, int cfg, int reps, float *ms) {
+    BLev B = e.lev[l];
+    B.sweep_cfg = cfg;
+    SweepArgs sw;
+    std::memset(&sw, 0, sizeof(sw));
+    hipEvent_t a = nullptr, c = nullptr;
+    HIPCHK(hipEventCreate(&a));
+    HIPCHK(hipEventCreate(&c));
+    launch_sgs(B, sw, e.fp32, e.st);     // warm-up
+    (void)hipEventRecord(a, e.st);
+    for (int k = 0; k < reps; ++k) launch_sgs(B, sw, e.fp32, e.st);
+    (void)hipEventRecord(c, e.st);
+    hipError_t er = hipEventSynchronize(c);
+    if (er == hipSuccess) er = hipEventElapsedTime(ms, a, c);
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(c);
+    if (er != hipSuccess) return fail(FAS_EDEVICE, std::string("sweep timing failed: ") + hipGetErrorString(er));
     return FAS_OK;
+}
+
+extern "C" fas_status fas_batch_create(int32_t n, const fas_state *states, void *stream, int32_t autotune,
+                                       fas_batch *out) {
+    if (!out || !states || n < 1) return fail(FAS_EINVAL, "bad argument");
+    *out = nullptr;
+    const fas_state s0 = states[0];
+    if (!s0) return fail(FAS_EINVAL, "null state");
+    for (int c = 0; c < n; ++c) {
+        const fas_state s = states[c];
+        if (!s) return fail(FAS_EINVAL, "null state");
+        if (s->g->device != s0->g->device) return fail(FAS_EINVAL, "states on different devices");
+        if (s->p.model != s0->p.model || s->p.scheme != s0->p.scheme || s->nlev != s0->nlev ||
+            s->p.cycle_gamma != s0->p.cycle_gamma || s->p.nu1 != s0->p.nu1 ||
+            s->p.precond_fp32 != s0->p.precond_fp32)
+            return fail(FAS_EINVAL, "batched states must share model, scheme, levels, cycle and precision");
+        if (s->e.bdf != 0) return fail(FAS_EINVAL, "batched states must be steady (no dual time step taken)");
+        for (int k = 0; k < c; ++k)
+            if (states[k] == s) return fail(FAS_EINVAL, "a state appears twice in the batch");
+    }
+    for (int c = 0; c < n; ++c) HIPCHK(hipStreamSynchronize(states[c]->e.st));
+    fas_batch b = new fas_batch_s();
+    b->states.assign(states, states + n);
+    Engine &e = b->e;
+    auto cleanup = [&](fas_status st) {
+        fas_batch_destroy(b);
+        return st;
+    };
+    if (stream) {
+        e.st = (hipStream_t)stream;
+    } else {
+        if (hipStreamCreateWithFlags(&e.st, hipStreamNonBlocking) != hipSuccess)
+            return cleanup(fail(FAS_EDEVICE, "stream creation failed"));
+        b->own_stream = 1;
+    }
+    e.n = n;
+    e.nlev = s0->nlev;
+    e.model = s0->p.model;
+    e.fp32 = s0->p.precond_fp32;
+    e.gamma = s0->p.cycle_gamma;
+    e.nu1 = s0->p.nu1;
+    e.sc = SCHEMES[s0->p.scheme];
+    // device arrays: per level n descriptors, n physics records, control
+    const size_t nl = (size_t)e.nlev * n;
+    const size_t bytes = nl * sizeof(LevelDev) + (size_t)n * sizeof(Phys) + (size_t)n * (4 * sizeof(int) + 2 * sizeof(double)) + 256;
+    char *dd = nullptr;
+    if (hipMalloc(&dd, bytes) != hipSuccess) return cleanup(fail(FAS_ENOMEM, "batch allocation failed"));
+    b->allocs.push_back(dd);
+    LevelDev *dV = reinterpret_cast<LevelDev *>(dd);
+    Phys *dPH = reinterpret_cast<Phys *>(dd + nl * sizeof(LevelDev));
+    char *q = dd + nl * sizeof(LevelDev) + (size_t)n * sizeof(Phys);
+    q = reinterpret_cast<char *>((reinterpret_cast<uintptr_t>(q) + 63) & ~uintptr_t(63));
+    e.d_norm = reinterpret_cast<double *>(q); q += n * sizeof(double);
+    b->d_h0 = reinterpret_cast<double *>(q); q += n * sizeof(double);
+    e.d_cyc = reinterpret_cast<int *>(q); q += n * sizeof(int);
+    b->d_act = reinterpret_cast<int *>(q); q += n * sizeof(int);
+    b->d_ndone = reinterpret_cast<int *>(q); q += n * sizeof(int);
+    b->d_stat = reinterpret_cast<int *>(q);
+    std::vector<LevelDev> hV(nl);
+    std::vector<Phys> hPH(n);
+    for (int l = 0; l < e.nlev; ++l)
+        for (int c = 0; c < n; ++c) hV[(size_t)l * n + c] = states[c]->lv[l];
+    for (int c = 0; c < n; ++c) hPH[c] = states[c]->ph;
+    if (hipMemcpy(dV, hV.data(), nl * sizeof(LevelDev), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(dPH, hPH.data(), n * sizeof(Phys), hipMemcpyHostToDevice) != hipSuccess)
+        return cleanup(fail(FAS_EDEVICE, "batch descriptor upload failed"));
+    if (hipHostMalloc(reinterpret_cast<void **>(&b->h_act), n * sizeof(int), hipHostMallocDefault) != hipSuccess)
+        return cleanup(fail(FAS_ENOMEM, "pinned allocation failed"));
+    launch_fill_int(b->d_act, n, 1, e.st);
+    for (int l = 0; l < e.nlev; ++l) {
+        std::vector<Lay> lays;
+        for (int c = 0; c < n; ++c) lays.push_back(states[c]->lv[l].L);
+        e.lev.push_back(make_blev(lays, dV + (size_t)l * n, dPH, b->d_act, e.d_cyc));
+    }
+    // autotuner: per level, the fastest sweep configuration that covers the
+    // tallest grid, timed on the batch itself
+    if (autotune) {
+        for (int l = 0; l < e.nlev; ++l) {
+            const int need = e.lev[l].max_nj;
+            int best = -1;
+            float best_ms = 0.0f;
+            for (int cfg = 0; cfg < sweep_cfg_count(); ++cfg) {
+                const int rows = sweep_cfg_rows(cfg);
+                if (rows < need || rows > 4 * std::max(need, 16)) continue;
+                float ms = 0.0f;
+                fas_status st = time_sweep(e, l, cfg, 3, &ms);
+                if (st != FAS_OK) return cleanup(st);
+                if (best < 0 || ms < best_ms) {
+                    best = cfg;
+                    best_ms = ms;
+                }
+            }
+            e.lev[l].sweep_cfg = best;
+        }
+    }
+    if (hipStreamSynchronize(e.st) != hipSuccess) return cleanup(fail(FAS_EDEVICE, "batch set-up failed"));
+    *out = b;
+    return FAS_OK;
+}
+
+extern "C" fas_status fas_batch_sweep_config(fas_batch b, int32_t level, int32_t *cfg, int32_t *rows) {
+    if (!b || level < 0 || level >= b->e.nlev) return fail(FAS_EINVAL, "bad argument");
+    int c = b->e.lev[level].sweep_cfg;
+    if (c < 0) c = sweep_cfg_default(b->e.lev[level].max_nj);
+    if (cfg) *cfg = c;
+    if (rows) *rows = sweep_cfg_rows(c);
+    return FAS_OK;
+}
+
+extern "C" fas_status fas_batch_set_sweep_config(fas_batch b, int32_t level, int32_t cfg) {
+    if (!b || level < 0 || level >= b->e.nlev) return fail(FAS_EINVAL, "bad argument");
+    if (cfg < -1 || cfg >= sweep_cfg_count()) return fail(FAS_EINVAL, "bad sweep configuration");
+    if (cfg >= 0 && sweep_cfg_rows(cfg) < b->e.lev[level].max_nj)
+        return fail(FAS_EINVAL, "sweep configuration covers fewer rows than the tallest grid");
+    b->e.lev[level].sweep_cfg = cfg;
+    drop_graph(b);
+    return FAS_OK;
+}
+
+// one batched cycle followed by the norm and the per-case status update
+static void batch_step(fas_batch b, const BatchCtl &ctl) {
+    Engine &e = b->e;
+    cycle(e, 0);
+    eval_norm(e);
+    launch_batch_status(ctl, e.n, e.st);
+}
+
+extern "C" fas_status fas_batch_solve(fas_batch b, int32_t max_cycles, double drop_orders, int32_t use_graph,
+                                      int32_t *n_done, int32_t *status, double *res_hist) {
+    if (!b || max_cycles < 0) return fail(FAS_EINVAL, "bad argument");
+    Engine &e = b->e;
+    const int n = e.n;
+    if (max_cycles + 1 > b->hcap) {
+        drop_graph(b);
+        HIPCHK(hipStreamSynchronize(e.st));
+        if (b->d_hist) {
+            (void)hipFree(b->d_hist);
+            for (auto &p : b->allocs)
+                if (p == b->d_hist) p = nullptr;
+        }
+        b->d_hist = nullptr;
+        HIPCHK(hipMalloc(&b->d_hist, (size_t)n * (max_cycles + 1) * sizeof(double)));
+        b->allocs.push_back(b->d_hist);
+        b->hcap = max_cycles + 1;
+    }
+    BatchCtl ctl;
+    ctl.nrm = e.d_norm;
+    ctl.h0 = b->d_h0;
+    ctl.hist = b->d_hist;
+    ctl.hcap = b->hcap;
+    ctl.act = b->d_act;
+    ctl.cyc = e.d_cyc;
+    ctl.ndone = b->d_ndone;
+    ctl.stat = b->d_stat;
+    ctl.drop_factor = drop_orders > 0.0 ? std::pow(10.0, -drop_orders) : 0.0;
+    ctl.max_cycles = max_cycles;
+    // every case starts active; its c* ramp continues from its own count
+    launch_fill_int(b->d_act, n, 1, e.st);
+    for (int c = 0; c < n; ++c)
+        HIPCHK(hipMemcpyAsync(e.d_cyc + c, b->states[c]->e.d_cyc, sizeof(int), hipMemcpyDeviceToDevice, e.st));
+    e.has_src[0] = 0;
+    eval_norm(e);
+    launch_batch_init(ctl, n, e.st);
+    HIPCHK(hipGetLastError());
+    if (use_graph && (b->graph_cap != max_cycles || b->graph_drop != drop_orders)) {
+        drop_graph(b);
+        const int prof = e.prof;
+        e.prof = 0;
+        HIPCHK(hipStreamBeginCapture(e.st, hipStreamCaptureModeThreadLocal));
+        batch_step(b, ctl);
+        hipError_t er = hipStreamEndCapture(e.st, &b->graph);
+        e.prof = prof;
+        if (er != hipSuccess) return fail(FAS_EDEVICE, std::string("graph capture failed: ") + hipGetErrorString(er));
+        HIPCHK(hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0));
+        b->graph_cap = max_cycles;
+        b->graph_drop = drop_orders;
+    }
+    const int check = 4;
+    for (int k = 0; k < max_cycles; ++k) {
+        if (use_graph) HIPCHK(hipGraphLaunch(b->exec, e.st));
+        else batch_step(b, ctl);
+        if ((k + 1) % check == 0 || k + 1 == max_cycles) {
+            HIPCHK(hipMemcpyAsync(b->h_act, b->d_act, n * sizeof(int), hipMemcpyDeviceToHost, e.st));
+            HIPCHK(hipStreamSynchronize(e.st));
+            int any = 0;
+            for (int c = 0; c < n; ++c) any |= b->h_act[c];
+            if (!any) break;
+        }
+    }
+    // hand the cycle counts back to the states
+    for (int c = 0; c < n; ++c)
+        HIPCHK(hipMemcpyAsync(b->states[c]->e.d_cyc, e.d_cyc + c, sizeof(int), hipMemcpyDeviceToDevice, e.st));
+    std::vector<int> nd(n), stv(n);
+    HIPCHK(hipMemcpyAsync(nd.data(), b->d_ndone, n * sizeof(int), hipMemcpyDeviceToHost, e.st));
+    HIPCHK(hipMemcpyAsync(stv.data(), b->d_stat, n * sizeof(int), hipMemcpyDeviceToHost, e.st));
+    if (res_hist)
+        HIPCHK(hipMemcpyAsync(res_hist, b->d_hist, (size_t)n * (max_cycles + 1) * sizeof(double),
+                              hipMemcpyDeviceToHost, e.st));
+    HIPCHK(hipStreamSynchronize(e.st));
+    int worst = FAS_OK;
+    for (int c = 0; c < n; ++c) {
+        if (n_done) n_done[c] = nd[c];
+        if (status) status[c] = stv[c];
+        if (stv[c] == FAS_DIVERGED) worst = FAS_DIVERGED;
+        else if (stv[c] == FAS_NOT_CONVERGED && worst == FAS_OK) worst = FAS_NOT_CONVERGED;
+    }
+    if (worst == FAS_DIVERGED) g_err = "residual norm of a batched case is not finite";
+    if (worst == FAS_NOT_CONVERGED) g_err = "cycle cap reached before the requested drop in a batched case";
+    return (fas_status)worst;
+}
+
+extern "C" fas_status fas_batch_profile(fas_batch b, int32_t enable) {
+    if (!b) return fail(FAS_EINVAL, "null batch");
+    return profile_on(b->e, enable);
+}
+
+extern "C" fas_status fas_batch_profile_read(fas_batch b, double *ms, int64_t *count) {
+    if (!b) return fail(FAS_EINVAL, "null batch");
+    return profile_read(b->e, ms, count);
 }
 
 extern "C" const char *fas_last_error(void) { return g_err.c_str(); }

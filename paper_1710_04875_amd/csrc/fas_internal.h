@@ -11,6 +11,11 @@
 //     (I+1, J) = +NJ,  (I, J+1) = +NJ+1,  (I+1, J-1) = -1,  (I-1, J+1) = +1.
 // Arrays are planes of NS = (NI + NJ - 1) * NJ values, one plane per
 // component.  Slots outside the padded rectangle are never read.
+//
+// Every kernel of the cycle works on a batch of independent cases: it
+// receives a device array of per-case level descriptors (LevelDev) and
+// per-case physics (Phys), takes its case from a block index, and skips
+// cases whose activity flag is 0.  A single flow state is a batch of one.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <cstdint>
@@ -42,10 +47,7 @@ enum VgPlane { V_UX, V_UY, V_VX, V_VY, V_TX, V_TY, V_NPLANES };
 
 // preconditioner blocks: five 4x4 blocks per cell, D^-1 and M_s = D^-1 B_s
 // for the four neighbour slots (0 west, 1 east, 2 south or wake-cut
-// partner, 3 north).  Block b of cell slot s is a contiguous row-major
-// record of 16 values at (b * NS + s) * 16, so one row of a block is one
-// aligned 4-vector and a wave reading rows of consecutive cells reads one
-// contiguous run.
+// partner, 3 north).
 constexpr int B_DINV = 0;
 constexpr int B_M0 = 1;          // + slot
 constexpr int BLK_NBLOCKS = 5;
@@ -55,6 +57,10 @@ struct Phys {
     double mach, alpha_deg, re, pr, prt, mu_inf;
     double uinf[4];
     double eta, d_cut, kappa2c;
+    // pseudo-time step c*: cfl_ramp for n_ramp cycles, then growth by
+    // ramp_growth per cycle up to cfl
+    double cfl, cfl_ramp, ramp_growth;
+    int n_ramp;
     int rans;
 };
 
@@ -75,28 +81,57 @@ struct LevelDev {
     void *blk;        // BLK_NPLANES * NS, double or float
     void *g;          // 4 * NS   D^-1 (dt* r) / forward sweep input
     void *y;          // 4 * NS   forward sweep output
-    double *red;      // reduction scratch
+    double *red;      // reduction scratch (RED_BLOCKS values)
+};
+
+// 4-component vector fields of a level, addressed by name in batched
+// launches (each case has its own pointers)
+enum Field { FLD_U, FLD_U0, FLD_ACC, FLD_F, FLD_SRC, FLD_UT, FLD_UN, FLD_UNM1, FLD_NONE };
+
+__host__ __device__ inline double *field(const LevelDev &d, int f) {
+    switch (f) {
+        case FLD_U: return d.u;
+        case FLD_U0: return d.u0;
+        case FLD_ACC: return d.acc;
+        case FLD_F: return d.F;
+        case FLD_SRC: return d.src;
+        case FLD_UT: return d.ut;
+        case FLD_UN: return d.un;
+        case FLD_UNM1: return d.unm1;
+        default: return nullptr;
+    }
+}
+
+// device view of one level of a batch (kernel argument)
+struct BK {
+    const LevelDev *V;    // [n]
+    const Phys *PH;       // [n]
+    const int *act;       // [n] 0 = skip the case; nullptr = all active
+    const int *cyc;       // [n] completed FAS cycles (c* ramp)
+};
+
+// host descriptor of one level of a batch
+struct BLev {
+    BK k;
+    int n;                // cases
+    int max_ns, max_ni, max_nj, max_nw;   // launch sizing over the cases
+    int sweep_cfg;        // sweep kernel configuration (-1: by max_nj)
 };
 
 // ---------------------------------------------------------------- launchers
-// geometry
+// geometry (one grid, at creation)
 void launch_geom_interior(const Lay &L, const double *xn, const double *yn, double *geo,
                           const double *vol_children, const Lay *Lf, const double *geo_f,
                           hipStream_t st);
 void launch_geom_ghost(const Lay &L, const double *xn, const double *yn, double *geo, hipStream_t st);
 
 // residual chain
-void launch_ghost_state(const Lay &L, const double *geo, double *u, const Phys &ph, int noslip,
-                        hipStream_t st);
-void launch_cell_quantities(const Lay &L, const double *geo, const double *u, double *cq, int rans,
-                            hipStream_t st);
-void launch_vertex_gradients(const Lay &L, const double *geo, const double *u, const double *cq,
-                             double *vg, hipStream_t st);
-void launch_baldwin_lomax(const Lay &L, const double *geo, const double *u, const double *cq,
-                          const double *vg, double *mut, const Phys &ph, hipStream_t st);
-void launch_mut_ghosts(const Lay &L, double *mut, hipStream_t st);
-void launch_local_time_step(const Lay &L, const double *geo, const double *u, double *dts,
-                            double cfl, hipStream_t st);
+void launch_ghost_state(const BLev &B, int noslip, hipStream_t st);
+void launch_cell_quantities(const BLev &B, int rans, hipStream_t st);
+void launch_vertex_gradients(const BLev &B, hipStream_t st);
+void launch_baldwin_lomax(const BLev &B, hipStream_t st);
+void launch_mut_ghosts(const BLev &B, hipStream_t st);
+void launch_local_time_step(const BLev &B, hipStream_t st);
 
 struct ResArgs {
     int fine;          // second-order JST (sensor, fourth difference)
@@ -110,37 +145,47 @@ struct ResArgs {
     int aw;            // 1: g = D^-1 (dt* r); 0: g = D^-1 r
     int fp32;          // blocks / g in float
 };
-void launch_residual(const Lay &L, const double *geo, const double *u, const double *cq,
-                     const double *vg, const double *mut, const double *un, const double *unm1,
-                     const double *src, const Phys &ph, const ResArgs &a, double *F, double *acc,
-                     const double *dts, const void *blk, void *g, hipStream_t st);
+void launch_residual(const BLev &B, const ResArgs &a, hipStream_t st);
 
 // preconditioner
-void launch_blocks(const Lay &L, const double *geo, const double *u, const double *cq,
-                   const double *mut, const double *dts, const Phys &ph, int aw, double tau,
-                   int viscous, int fp32, void *blk, hipStream_t st);
+void launch_blocks(const BLev &B, int aw, double tau, int viscous, int fp32, hipStream_t st);
 struct SweepArgs {
     int update;        // 1: write u = u0 - alpha x (AW) or u0 - alpha dt* x (pARK)
     double alpha;
     int aw;
-    double *u;         // padded solution to update
-    const double *u0;
-    const double *dts;
-    double *xout;      // optional: x written here (padded, 4 planes)
+    int xout_acc;      // 1: also write x (FP64) into the level's acc field
 };
-void launch_sgs(const Lay &L, const void *blk, const void *g, void *y, const SweepArgs &a,
-                int fp32, hipStream_t st);
+void launch_sgs(const BLev &B, const SweepArgs &a, int fp32, hipStream_t st);
+void launch_dinv(const BLev &B, int fp32, hipStream_t st);   // g = D^-1 F
+
+// sweep kernel configurations for the autotuner: cfg indexes a table of
+// (threads, rows per 4-thread group, prefetch depth); -1 picks by nj
+int sweep_cfg_count();
+int sweep_cfg_rows(int cfg);           // rows one workgroup covers
+int sweep_cfg_default(int max_nj);
 
 // transfers and utilities
-void launch_restrict(const Lay &Lf, const Lay &Lc, const double *geo_f, const double *geo_c,
-                     const double *vf, double *vc, double *vc_copy, hipStream_t st);
-void launch_prolong(const Lay &Lf, const Lay &Lc, const double *uc, const double *utc, double *uf,
-                    hipStream_t st);
-void launch_axpby_interior(const Lay &L, double a, const double *x, double b, const double *y,
-                           double *out, int ncomp, hipStream_t st);
+void launch_restrict(const BLev &Bf, const BLev &Bc, int fin, int fout, int fout2, hipStream_t st);
+void launch_prolong(const BLev &Bf, const BLev &Bc, hipStream_t st);
+void launch_axpby(const BLev &B, double a, int fx, double b, int fy, int fout, hipStream_t st);
 void launch_pack(const Lay &L, const double *padded, double *natural, int ncomp, hipStream_t st);
 void launch_unpack(const Lay &L, const double *natural, double *padded, int ncomp, hipStream_t st);
-void launch_norm(const Lay &L, const double *F, double *red, double *out, hipStream_t st);
-int norm_scratch_size(const Lay &L);
+void launch_norm(const BLev &B, double *out, hipStream_t st);   // out[n]
+void launch_count_cycle(const BLev &B, int *cyc, hipStream_t st);
+void launch_fill_int(int *p, int n, int v, hipStream_t st);
+int norm_scratch_size();
+
+// batch convergence control: per case c, after the norm of a cycle
+struct BatchCtl {
+    const double *nrm;    // [n] norm after the cycle
+    double *h0;           // [n] norm before the first cycle
+    double *hist;         // [n * hcap]
+    int hcap;
+    int *act, *cyc, *ndone, *stat;
+    double drop_factor;   // 10^-drop (0: run to max_cycles)
+    int max_cycles;
+};
+void launch_batch_init(const BatchCtl &c, int n, hipStream_t st);
+void launch_batch_status(const BatchCtl &c, int n, hipStream_t st);
 
 }  // namespace fas

@@ -92,6 +92,14 @@ __device__ inline void ld4(const double *a, int NS, int s, double v[4]) {
     for (int k = 0; k < 4; ++k) v[k] = a[k * NS + s];
 }
 
+// the level descriptor of case c of a batched launch; false if the case is
+// inactive (the whole block then returns before any barrier)
+__device__ inline bool take(const BK &b, int c, LevelDev &d) {
+    if (b.act != nullptr && b.act[c] == 0) return false;
+    d = b.V[c];
+    return true;
+}
+
 // ------------------------------------------------------------------ geometry
 // Section 2 (finite volumes on a structured mesh), Section 3 (agglomerated
 // coarse levels: coarse face = sum of child faces, coarse volume = sum of
@@ -305,7 +313,13 @@ __device__ void jrow_state(const Lay &L, const double *geo, const double *u, con
     farfield(ui, ph.uinf, nx, ny, out);
 }
 
-__global__ void k_ghost_state(Lay L, const double *geo, double *u, Phys ph, int noslip) {
+__global__ void k_ghost_state(BK b, int noslip) {
+    LevelDev d;
+    if (!take(b, blockIdx.y, d)) return;
+    const Lay L = d.L;
+    const double *geo = d.geo;
+    double *u = d.u;
+    const Phys ph = b.PH[blockIdx.y];
     int s = blockIdx.x * blockDim.x + threadIdx.x;
     int i, j;
     if (!decode(L, s, i, j) || interior(L, i, j)) return;
@@ -342,7 +356,11 @@ __device__ double jrow_mut(const Lay &L, const double *mut, int i, int j) {
     return mut[L.slot(i, L.nj - 1 - (j - L.nj))];
 }
 
-__global__ void k_mut_ghosts(Lay L, double *mut) {
+__global__ void k_mut_ghosts(BK b) {
+    LevelDev d;
+    if (!take(b, blockIdx.y, d)) return;
+    const Lay L = d.L;
+    double *mut = d.mut;
     int s = blockIdx.x * blockDim.x + threadIdx.x;
     int i, j;
     if (!decode(L, s, i, j) || interior(L, i, j)) return;
@@ -357,7 +375,12 @@ __global__ void k_mut_ghosts(Lay L, double *mut) {
 // Section 2: p, sensor quantity (entropy p/rho^gamma for RANS, pressure for
 // Euler), spectral radii r = |v.S| + a|S| and the multidimensional
 // correction of eq. "spectralcorrection"; temperature T = p / rho.
-__global__ void k_cell_quantities(Lay L, const double *geo, const double *u, double *cq, int rans) {
+__global__ void k_cell_quantities(BK b, int rans) {
+    LevelDev d;
+    if (!take(b, blockIdx.y, d)) return;
+    const Lay L = d.L;
+    const double *geo = d.geo, *u = d.u;
+    double *cq = d.cq;
     int s = blockIdx.x * blockDim.x + threadIdx.x;
     int i, j;
     if (!decode(L, s, i, j)) return;
@@ -382,8 +405,23 @@ __global__ void k_cell_quantities(Lay L, const double *geo, const double *u, dou
     cq[Q_T * NS + s] = p / r;
 }
 
+// c* of the current cycle: the start-up value for n_ramp cycles, then
+// geometric growth per cycle up to the target (Section 6 start-up)
+__device__ inline double cfl_of(const Phys &ph, int n) {
+    if (n < ph.n_ramp) return fmin(ph.cfl, ph.cfl_ramp);
+    if (ph.ramp_growth > 1.0)
+        return fmin(ph.cfl, ph.cfl_ramp * pow(ph.ramp_growth, (double)(n - ph.n_ramp + 1)));
+    return ph.cfl;
+}
+
 // Section 4.1: dt* = c* Omega / (r_xi + r_eta)
-__global__ void k_local_time_step(Lay L, const double *geo, const double *u, double *dts, double cfl) {
+__global__ void k_local_time_step(BK b) {
+    LevelDev d;
+    if (!take(b, blockIdx.y, d)) return;
+    const Lay L = d.L;
+    const double *geo = d.geo, *u = d.u;
+    double *dts = d.dts;
+    const double cfl = cfl_of(b.PH[blockIdx.y], b.cyc[blockIdx.y]);
     int s = blockIdx.x * blockDim.x + threadIdx.x;
     int i, j;
     if (!decode(L, s, i, j) || !interior(L, i, j)) return;
@@ -401,8 +439,12 @@ __global__ void k_local_time_step(Lay L, const double *geo, const double *u, dou
 
 // Section 2: velocity and temperature gradients at vertices, Green-Gauss
 // over the quadrilateral of the four surrounding cell centres.
-__global__ void k_vertex_gradients(Lay L, const double *geo, const double *u, const double *cq,
-                                   double *vg) {
+__global__ void k_vertex_gradients(BK b) {
+    LevelDev d;
+    if (!take(b, blockIdx.y, d)) return;
+    const Lay L = d.L;
+    const double *geo = d.geo, *u = d.u, *cq = d.cq;
+    double *vg = d.vg;
     int s = blockIdx.x * blockDim.x + threadIdx.x;
     int i, j;
     if (!decode(L, s, i, j)) return;
@@ -446,10 +488,15 @@ __global__ void k_vertex_gradients(Lay L, const double *geo, const double *u, co
 // maximum of F and the first inner/outer crossover go to the lowest j; the
 // search is limited to the inner half of the column.
 constexpr int BL_TPB = 256;
-__global__ __launch_bounds__(BL_TPB) void k_baldwin_lomax(Lay L, const double *geo, const double *u,
-                                                          const double *cq, const double *vg,
-                                                          double *mut, Phys ph) {
+__global__ __launch_bounds__(BL_TPB) void k_baldwin_lomax(BK b) {
     extern __shared__ double sh[];
+    LevelDev d;
+    if (!take(b, blockIdx.y, d)) return;
+    const Lay L = d.L;
+    if ((int)blockIdx.x >= L.ni) return;
+    const double *geo = d.geo, *u = d.u, *cq = d.cq, *vg = d.vg;
+    double *mut = d.mut;
+    const Phys ph = b.PH[blockIdx.y];
     const int nj = L.nj, NS = L.NS, NJ = L.NJ;
     double *Fs = sh, *ys = sh + nj, *sp = sh + 2 * nj, *mi = sh + 3 * nj, *mo = sh + 4 * nj;
     __shared__ double s_fmax, s_ymax, s_udif;
@@ -615,12 +662,16 @@ __device__ void face_flux(const Lay &L, const double *geo, const double *u, cons
 }
 
 template <typename BT>
-__global__ __launch_bounds__(TPB) void k_residual(Lay L, const double *geo, const double *u,
-                                                  const double *cq, const double *vg,
-                                                  const double *mut, const double *un,
-                                                  const double *unm1, const double *src, Phys ph,
-                                                  ResArgs a, double *F, double *acc,
-                                                  const double *dts, const BT *blk, BT *g) {
+__global__ __launch_bounds__(TPB) void k_residual(BK b, ResArgs a) {
+    LevelDev d;
+    if (!take(b, blockIdx.y, d)) return;
+    const Lay L = d.L;
+    const double *geo = d.geo, *u = d.u, *cq = d.cq, *vg = d.vg, *mut = d.mut;
+    const double *un = d.un, *unm1 = d.unm1, *src = d.src, *dts = d.dts;
+    double *F = d.F, *acc = d.acc;
+    const BT *blk = (const BT *)d.blk;
+    BT *g = (BT *)d.g;
+    const Phys ph = b.PH[blockIdx.y];
     int s = blockIdx.x * blockDim.x + threadIdx.x;
     int i, j;
     if (!decode(L, s, i, j) || !interior(L, i, j)) return;
@@ -677,9 +728,9 @@ __global__ __launch_bounds__(TPB) void k_residual(Lay L, const double *geo, cons
         r[k] = Fc[k] + av;
     }
     if (a.aw) {
-        double d = dts[s];
+        const double dt_s = dts[s];
 #pragma unroll
-        for (int k = 0; k < 4; ++k) r[k] = d * r[k];
+        for (int k = 0; k < 4; ++k) r[k] = dt_s * r[k];
     }
     BT rb[4] = {(BT)r[0], (BT)r[1], (BT)r[2], (BT)r[3]};
 #pragma unroll
@@ -771,10 +822,13 @@ __device__ void face_blocks(const Lay &L, const double *geo, const double *u, co
 }
 
 template <typename BT>
-__global__ __launch_bounds__(TPB) void k_blocks(Lay L, const double *geo, const double *u,
-                                                const double *cq, const double *mut,
-                                                const double *dts, Phys ph, int aw, double tau,
-                                                int viscous, BT *blk) {
+__global__ __launch_bounds__(TPB) void k_blocks(BK b, int aw, double tau, int viscous) {
+    LevelDev dv;
+    if (!take(b, blockIdx.y, dv)) return;
+    const Lay L = dv.L;
+    const double *geo = dv.geo, *u = dv.u, *cq = dv.cq, *mut = dv.mut, *dts = dv.dts;
+    BT *blk = (BT *)dv.blk;
+    const Phys ph = b.PH[blockIdx.y];
     int s = blockIdx.x * blockDim.x + threadIdx.x;
     int i, j;
     if (!decode(L, s, i, j) || !interior(L, i, j)) return;
@@ -890,9 +944,17 @@ __device__ inline void mv_sub(const T *blk, int b, int NS, int s, const T v[4], 
 }
 
 template <typename T, int BS>
-__global__ __launch_bounds__(BS) void k_sgs(Lay L, const T *blk, const T *g, T *y, SweepArgs a) {
+__global__ __launch_bounds__(BS) void k_sgs(BK bk, SweepArgs a) {
     __shared__ T nbuf[2][BS][4];
     extern __shared__ unsigned char smem[];
+    LevelDev d;
+    if (!take(bk, blockIdx.x, d)) return;
+    const Lay L = d.L;
+    const T *blk = (const T *)d.blk, *g = (const T *)d.g;
+    T *y = (T *)d.y;
+    double *xout = a.xout_acc ? d.acc : nullptr;
+    double *uu = d.u;
+    const double *u0 = d.u0, *dts = d.dts;
     T *row0 = reinterpret_cast<T *>(smem);          // n_wake x 4
     const int j = threadIdx.x;
     const int ni = L.ni, nj = L.nj, NS = L.NS, nw = L.nw;
@@ -966,20 +1028,20 @@ __global__ __launch_bounds__(BS) void k_sgs(Lay L, const T *blk, const T *g, T *
 #pragma unroll
                 for (int k = 0; k < 4; ++k) row0[(i - (ni - nw)) * 4 + k] = v[k];
             }
-            if (a.xout) {
+            if (xout) {
 #pragma unroll
-                for (int k = 0; k < 4; ++k) a.xout[k * NS + s] = (double)v[k];
+                for (int k = 0; k < 4; ++k) xout[k * NS + s] = (double)v[k];
             }
             if (a.update) {
                 if (a.aw) {
 #pragma unroll
                     for (int k = 0; k < 4; ++k)
-                        a.u[k * NS + s] = a.u0[k * NS + s] - a.alpha * (double)v[k];
+                        uu[k * NS + s] = u0[k * NS + s] - a.alpha * (double)v[k];
                 } else {
-                    const double d = a.dts[s];
+                    const double dt_s = dts[s];
 #pragma unroll
                     for (int k = 0; k < 4; ++k)
-                        a.u[k * NS + s] = a.u0[k * NS + s] - a.alpha * (d * (double)v[k]);
+                        uu[k * NS + s] = u0[k * NS + s] - a.alpha * (dt_s * (double)v[k]);
                 }
             }
         }
@@ -988,7 +1050,13 @@ __global__ __launch_bounds__(BS) void k_sgs(Lay L, const T *blk, const T *g, T *
 }
 
 template <typename BT>
-__global__ void k_dinv(Lay L, const BT *blk, const double *r, BT *g) {
+__global__ void k_dinv(BK b) {
+    LevelDev d;
+    if (!take(b, blockIdx.y, d)) return;
+    const Lay L = d.L;
+    const BT *blk = (const BT *)d.blk;
+    const double *r = d.F;
+    BT *g = (BT *)d.g;
     int s = blockIdx.x * blockDim.x + threadIdx.x;
     int i, j;
     if (!decode(L, s, i, j) || !interior(L, i, j)) return;
@@ -1053,17 +1121,28 @@ __device__ inline T ld1(const T *base, unsigned boff) {
 }
 
 template <typename T, int NT, int R, int D>
-__global__ __launch_bounds__(NT) void k_sgs4(Lay L, const T *blk, const T *g, T *y, SweepArgs a) {
+__global__ __launch_bounds__(NT) void k_sgs4(BK bk, SweepArgs a) {
     constexpr int NR = NT / 4 * R;            // rows handled by the workgroup
     constexpr int XS = 4 * NR + 8;            // zero guard row at both ends
     __shared__ T xb[2][XS];
     extern __shared__ unsigned char smem[];
+    LevelDev dv;
+    if (!take(bk, blockIdx.x, dv)) return;
+    const Lay L = dv.L;
+    const T *blk = (const T *)dv.blk, *g = (const T *)dv.g;
+    T *y = (T *)dv.y;
+    double *xout = a.xout_acc ? dv.acc : nullptr;
+    double *uu = dv.u;
+    const double *dts = dv.dts;
     T *row0 = reinterpret_cast<T *>(smem);                 // n_wake x 4
     T *pblk = row0 + (L.nw > 0 ? L.nw : 1) * 4;           // n_wake x 16: slot-2 blocks of (i, 0), i < n_wake
     const int t = threadIdx.x, grp = t >> 2, r = t & 3;
     const int ni = L.ni, nj = L.nj, NS = L.NS, NJ = L.NJ, nw = L.nw;
     const bool cutg = L.topo == 1;
     const int H = ni + nj - 1;
+    // a wave whose first row is beyond the case's rows (batches of uneven
+    // grids) issues no memory traffic; it only keeps the barrier count
+    const bool live = (t >> 6) * 16 * R < nj;
     for (int q = t; q < XS; q += NT) {
         xb[0][q] = (T)0;
         xb[1][q] = (T)0;
@@ -1098,6 +1177,7 @@ __global__ __launch_bounds__(NT) void k_sgs4(Lay L, const T *blk, const T *g, T 
     {
         T gA[D][R], wA[D][R][4], sA[D][R][4], gB[D][R], wB[D][R][4], sB[D][R][4];
         auto load = [&](T (&gg)[D][R], T (&ww)[D][R][4], T (&ss)[D][R][4], int hb) {
+            if (!live) return;
 #pragma unroll
             for (int k = 0; k < D; ++k) {
                 const int hc = hcl(hb + k) + 2 * NG;
@@ -1113,20 +1193,22 @@ __global__ __launch_bounds__(NT) void k_sgs4(Lay L, const T *blk, const T *g, T 
             }
         };
         auto step = [&](const T (&gv)[R], const T (&wv)[R][4], const T (&sv)[R][4], int h) {
-            const T *prev = xb[(h - 1) & 1];
-            T *cur = xb[h & 1];
-            T *yb = y + (size_t)(h + 2 * NG) * NJ;
+            if (live) {
+                const T *prev = xb[(h - 1) & 1];
+                T *cur = xb[h & 1];
+                T *yb = y + (size_t)(h + 2 * NG) * NJ;
 #pragma unroll
-            for (int q = 0; q < R; ++q) {
-                const int jj = jq[q];
-                const int i = h - jj;
-                const T *xs = prev + 4 * jj;                        // row jj - 1 (guard row for jj = 0)
-                if (jj == 0 && cutg && i >= ni - nw && i < ni) xs = row0 + (ni - 1 - i) * 4;
-                const T v = (gv[q] - dot4(wv[q], prev + 4 * jj + 4)) - dot4(sv[q], xs);
-                const bool valid = jj < nj && i >= 0 && i < ni;
-                cur[4 * jj + 4 + r] = valid ? v : (T)0;
-                *reinterpret_cast<T *>(reinterpret_cast<char *>(yb) + ow[q]) = v;
-                if (valid && jj == 0 && cutg && i < nw) row0[i * 4 + r] = v;
+                for (int q = 0; q < R; ++q) {
+                    const int jj = jq[q];
+                    const int i = h - jj;
+                    const T *xs = prev + 4 * jj;                        // row jj - 1 (guard row for jj = 0)
+                    if (jj == 0 && cutg && i >= ni - nw && i < ni) xs = row0 + (ni - 1 - i) * 4;
+                    const T v = (gv[q] - dot4(wv[q], prev + 4 * jj + 4)) - dot4(sv[q], xs);
+                    const bool valid = jj < nj && i >= 0 && i < ni;
+                    cur[4 * jj + 4 + r] = valid ? v : (T)0;
+                    *reinterpret_cast<T *>(reinterpret_cast<char *>(yb) + ow[q]) = v;
+                    if (valid && jj == 0 && cutg && i < nw) row0[i * 4 + r] = v;
+                }
             }
             lds_barrier();
         };
@@ -1153,8 +1235,9 @@ __global__ __launch_bounds__(NT) void k_sgs4(Lay L, const T *blk, const T *g, T 
     {
         T yA[D][R], eA[D][R][4], nA[D][R][4], yB[D][R], eB[D][R][4], nB[D][R][4];
         double uA[D][R], uB[D][R];
-        const double *u0 = a.update ? a.u0 : reinterpret_cast<const double *>(y);
-        auto load = [&](T (&yy)[D][R], T (&ee)[D][R][4], T (&nn)[D][R][4], double (&uu)[D][R], int hb) {
+        const double *u0 = a.update ? dv.u0 : reinterpret_cast<const double *>(y);
+        auto load = [&](T (&yy)[D][R], T (&ee)[D][R][4], T (&nn)[D][R][4], double (&u0r)[D][R], int hb) {
+            if (!live) return;
 #pragma unroll
             for (int k = 0; k < D; ++k) {
                 const int hc = hcl(H - 1 - (hb + k)) + 2 * NG;
@@ -1165,7 +1248,7 @@ __global__ __launch_bounds__(NT) void k_sgs4(Lay L, const T *blk, const T *g, T 
 #pragma unroll
                 for (int q = 0; q < R; ++q) {
                     yy[k][q] = ld1(yb, ov[q]);
-                    uu[k][q] = a.update ? ld1(ub, ov[q] / sizeof(T) * sizeof(double)) : 0.0;
+                    u0r[k][q] = a.update ? ld1(ub, ov[q] / sizeof(T) * sizeof(double)) : 0.0;
                     ldrow(eb, ob[q], hpl, ee[k][q]);
                     ldrow(nb, ob[q], hpl, nn[k][q]);
                 }
@@ -1173,31 +1256,33 @@ __global__ __launch_bounds__(NT) void k_sgs4(Lay L, const T *blk, const T *g, T 
         };
         auto step = [&](const T (&yv)[R], const T (&ev)[R][4], const T (&nv)[R][4], const double (&u0v)[R],
                         int h) {
-            const T *prev = xb[(h + 1) & 1];
-            T *cur = xb[h & 1];
-            const size_t hs = (size_t)(h + 2 * NG) * NJ;
+            if (live) {
+                const T *prev = xb[(h + 1) & 1];
+                T *cur = xb[h & 1];
+                const size_t hs = (size_t)(h + 2 * NG) * NJ;
 #pragma unroll
-            for (int q = 0; q < R; ++q) {
-                const int jj = jq[q];
-                const int i = h - jj;
-                T v = (yv[q] - dot4(ev[q], prev + 4 * jj + 4)) - dot4(nv[q], prev + 4 * jj + 8);
-                if (jj == 0 && cutg && i >= 0 && i < nw) {
-                    T mp[4];
+                for (int q = 0; q < R; ++q) {
+                    const int jj = jq[q];
+                    const int i = h - jj;
+                    T v = (yv[q] - dot4(ev[q], prev + 4 * jj + 4)) - dot4(nv[q], prev + 4 * jj + 8);
+                    if (jj == 0 && cutg && i >= 0 && i < nw) {
+                        T mp[4];
 #pragma unroll
-                    for (int c = 0; c < 4; ++c) mp[c] = pblk[i * 16 + r * 4 + c];
-                    v = v - dot4(mp, row0 + (ni - 1 - i - (ni - nw)) * 4);
-                }
-                const bool valid = jj < nj && i >= 0 && i < ni;
-                cur[4 * jj + 4 + r] = valid ? v : (T)0;
-                if (valid && jj == 0 && cutg && i >= ni - nw) row0[(i - (ni - nw)) * 4 + r] = v;
-                const unsigned ew = ow[q] / sizeof(T) * sizeof(double);
-                if (a.xout)
-                    *reinterpret_cast<double *>(reinterpret_cast<char *>(a.xout + hs) + ew) = (double)v;
-                if (a.update) {
-                    double un;
-                    if (a.aw) un = u0v[q] - a.alpha * (double)v;
-                    else un = u0v[q] - a.alpha * (a.dts[hs + (jj < nj ? jj : nj) + NG] * (double)v);
-                    *reinterpret_cast<double *>(reinterpret_cast<char *>(a.u + hs) + ew) = un;
+                        for (int c = 0; c < 4; ++c) mp[c] = pblk[i * 16 + r * 4 + c];
+                        v = v - dot4(mp, row0 + (ni - 1 - i - (ni - nw)) * 4);
+                    }
+                    const bool valid = jj < nj && i >= 0 && i < ni;
+                    cur[4 * jj + 4 + r] = valid ? v : (T)0;
+                    if (valid && jj == 0 && cutg && i >= ni - nw) row0[(i - (ni - nw)) * 4 + r] = v;
+                    const unsigned ew = ow[q] / sizeof(T) * sizeof(double);
+                    if (xout)
+                        *reinterpret_cast<double *>(reinterpret_cast<char *>(xout + hs) + ew) = (double)v;
+                    if (a.update) {
+                        double un;
+                        if (a.aw) un = u0v[q] - a.alpha * (double)v;
+                        else un = u0v[q] - a.alpha * (dts[hs + (jj < nj ? jj : nj) + NG] * (double)v);
+                        *reinterpret_cast<double *>(reinterpret_cast<char *>(uu + hs) + ew) = un;
+                    }
                 }
             }
             lds_barrier();
@@ -1219,8 +1304,12 @@ __global__ __launch_bounds__(NT) void k_sgs4(Lay L, const T *blk, const T *g, T 
 
 // ------------------------------------------------------------ transfers
 // Section 3: restriction = volume-weighted agglomeration of 2x2 cells.
-__global__ void k_restrict(Lay Lf, Lay Lc, const double *geof, const double *geoc, const double *vf,
-                           double *vc, double *vc2) {
+__global__ void k_restrict(BK bf, BK bc, int fin, int fout, int fout2) {
+    LevelDev df, dc;
+    if (!take(bf, blockIdx.y, df) || !take(bc, blockIdx.y, dc)) return;
+    const Lay Lf = df.L, Lc = dc.L;
+    const double *geof = df.geo, *geoc = dc.geo, *vf = field(df, fin);
+    double *vc = field(dc, fout), *vc2 = field(dc, fout2);
     int s = blockIdx.x * blockDim.x + threadIdx.x;
     int i, j;
     if (!decode(Lc, s, i, j) || !interior(Lc, i, j)) return;
@@ -1243,7 +1332,12 @@ __global__ void k_restrict(Lay Lf, Lay Lc, const double *geof, const double *geo
 // Section 3: bilinear prolongation of the coarse correction, weights
 // 9/16 (parent), 3/16, 3/16, 1/16 towards the fine cell's side; the wake-cut
 // partner across the cut, the parent's value where a neighbour is missing.
-__global__ void k_prolong(Lay Lf, Lay Lc, const double *uc, const double *utc, double *uf) {
+__global__ void k_prolong(BK bf, BK bc) {
+    LevelDev df, dc;
+    if (!take(bf, blockIdx.y, df) || !take(bc, blockIdx.y, dc)) return;
+    const Lay Lf = df.L, Lc = dc.L;
+    const double *uc = dc.u, *utc = dc.ut;
+    double *uf = df.u;
     int s = blockIdx.x * blockDim.x + threadIdx.x;
     int i, j;
     if (!decode(Lf, s, i, j) || !interior(Lf, i, j)) return;
@@ -1269,11 +1363,18 @@ __global__ void k_prolong(Lay Lf, Lay Lc, const double *uc, const double *utc, d
     }
 }
 
-__global__ void k_axpby(Lay L, double a, const double *x, double b, const double *y, double *out, int nc) {
+// out = a x (+ b y) on the interior cells, fields named per case
+__global__ void k_axpby(BK bk, double a, int fx, double b, int fy, int fout) {
+    LevelDev d;
+    if (!take(bk, blockIdx.y, d)) return;
+    const Lay L = d.L;
+    const double *x = field(d, fx), *y = field(d, fy);
+    double *out = field(d, fout);
     int s = blockIdx.x * blockDim.x + threadIdx.x;
     int i, j;
     if (!decode(L, s, i, j) || !interior(L, i, j)) return;
-    for (int k = 0; k < nc; ++k) {
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
         int o = k * L.NS + s;
         out[o] = (y == nullptr) ? a * x[o] : a * x[o] + b * y[o];
     }
@@ -1300,8 +1401,12 @@ __global__ void k_unpack(Lay L, const double *n, double *p, int nc) {
 // RMS of the density component of F over interior cells; fixed-order
 // two-pass reduction (deterministic).
 constexpr int RED_BLOCKS = 128;
-__global__ __launch_bounds__(TPB) void k_norm1(Lay L, const double *F, double *red) {
+__global__ __launch_bounds__(TPB) void k_norm1(BK bk) {
     __shared__ double sh[TPB];
+    LevelDev d;
+    if (!take(bk, blockIdx.y, d)) return;
+    const Lay L = d.L;
+    const double *F = d.F;
     double a = 0.0;
     for (int s = blockIdx.x * blockDim.x + threadIdx.x; s < L.NS; s += gridDim.x * blockDim.x) {
         int i, j;
@@ -1313,14 +1418,65 @@ __global__ __launch_bounds__(TPB) void k_norm1(Lay L, const double *F, double *r
         if (threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
         __syncthreads();
     }
-    if (threadIdx.x == 0) red[blockIdx.x] = sh[0];
+    if (threadIdx.x == 0) d.red[blockIdx.x] = sh[0];
 }
 
-__global__ void k_norm2(const double *red, int n, double count, double *out) {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+__global__ void k_norm2(BK bk, double *out) {
+    LevelDev d;
+    if (!take(bk, blockIdx.x, d)) return;
+    if (threadIdx.x != 0) return;
     double a = 0.0;
-    for (int k = 0; k < n; ++k) a += red[k];
-    *out = sqrt(a / count);
+    for (int k = 0; k < RED_BLOCKS; ++k) a += d.red[k];
+    out[blockIdx.x] = sqrt(a / ((double)d.L.ni * d.L.nj));
+}
+
+__global__ void k_count_cycle(BK bk, int *cyc, int n) {
+    int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= n) return;
+    if (bk.act != nullptr && bk.act[c] == 0) return;
+    cyc[c] = cyc[c] + 1;
+}
+
+__global__ void k_fill_int(int *p, int n, int v) {
+    int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c < n) p[c] = v;
+}
+
+// status codes (fas_status values)
+constexpr int ST_OK = 0, ST_DIVERGED = -4, ST_NOT_CONVERGED = -6;
+
+__global__ void k_batch_init(BatchCtl c, int n) {
+    int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n) return;
+    const double h = c.nrm[k];
+    c.h0[k] = h;
+    c.hist[(size_t)k * c.hcap] = h;
+    c.ndone[k] = 0;
+    const bool fin = isfinite(h);
+    c.stat[k] = fin ? (c.max_cycles > 0 ? ST_NOT_CONVERGED : ST_OK) : ST_DIVERGED;
+    c.act[k] = (fin && c.max_cycles > 0) ? 1 : 0;
+}
+
+// after the norm of a cycle: record it, count the cycle, stop the case when
+// the drop is reached, the norm is not finite or the cap is reached
+__global__ void k_batch_status(BatchCtl c, int n) {
+    int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n || c.act[k] == 0) return;
+    const double h = c.nrm[k];
+    const int m = c.ndone[k] + 1;
+    c.ndone[k] = m;
+    c.cyc[k] = c.cyc[k] + 1;
+    if (m < c.hcap) c.hist[(size_t)k * c.hcap + m] = h;
+    if (!isfinite(h)) {
+        c.stat[k] = ST_DIVERGED;
+        c.act[k] = 0;
+    } else if (c.drop_factor > 0.0 && h <= c.h0[k] * c.drop_factor) {
+        c.stat[k] = ST_OK;
+        c.act[k] = 0;
+    } else if (m >= c.max_cycles) {
+        c.stat[k] = c.drop_factor > 0.0 ? ST_NOT_CONVERGED : ST_OK;
+        c.act[k] = 0;
+    }
 }
 
 }  // namespace
@@ -1339,135 +1495,131 @@ void launch_geom_ghost(const Lay &L, const double *xn, const double *yn, double 
     hipLaunchKernelGGL(k_geom_ghost, dim3(nblocks(L.NS)), dim3(TPB), 0, st, L, xn, yn, geo);
 }
 
-void launch_ghost_state(const Lay &L, const double *geo, double *u, const Phys &ph, int noslip,
-                        hipStream_t st) {
-    hipLaunchKernelGGL(k_ghost_state, dim3(nblocks(L.NS)), dim3(TPB), 0, st, L, geo, u, ph, noslip);
+// one thread per padded slot of the largest case, one grid row per case
+static dim3 cells_grid(const BLev &B) { return dim3(nblocks(B.max_ns), B.n); }
+
+void launch_ghost_state(const BLev &B, int noslip, hipStream_t st) {
+    hipLaunchKernelGGL(k_ghost_state, cells_grid(B), dim3(TPB), 0, st, B.k, noslip);
 }
 
-void launch_cell_quantities(const Lay &L, const double *geo, const double *u, double *cq, int rans,
-                            hipStream_t st) {
-    hipLaunchKernelGGL(k_cell_quantities, dim3(nblocks(L.NS)), dim3(TPB), 0, st, L, geo, u, cq, rans);
+void launch_cell_quantities(const BLev &B, int rans, hipStream_t st) {
+    hipLaunchKernelGGL(k_cell_quantities, cells_grid(B), dim3(TPB), 0, st, B.k, rans);
 }
 
-void launch_vertex_gradients(const Lay &L, const double *geo, const double *u, const double *cq,
-                             double *vg, hipStream_t st) {
-    hipLaunchKernelGGL(k_vertex_gradients, dim3(nblocks(L.NS)), dim3(TPB), 0, st, L, geo, u, cq, vg);
+void launch_vertex_gradients(const BLev &B, hipStream_t st) {
+    hipLaunchKernelGGL(k_vertex_gradients, cells_grid(B), dim3(TPB), 0, st, B.k);
 }
 
-void launch_baldwin_lomax(const Lay &L, const double *geo, const double *u, const double *cq,
-                          const double *vg, double *mut, const Phys &ph, hipStream_t st) {
-    size_t shm = (size_t)5 * L.nj * sizeof(double);
-    hipLaunchKernelGGL(k_baldwin_lomax, dim3(L.ni), dim3(BL_TPB), shm, st, L, geo, u, cq, vg, mut, ph);
+void launch_baldwin_lomax(const BLev &B, hipStream_t st) {
+    size_t shm = (size_t)5 * B.max_nj * sizeof(double);
+    hipLaunchKernelGGL(k_baldwin_lomax, dim3(B.max_ni, B.n), dim3(BL_TPB), shm, st, B.k);
 }
 
-void launch_mut_ghosts(const Lay &L, double *mut, hipStream_t st) {
-    hipLaunchKernelGGL(k_mut_ghosts, dim3(nblocks(L.NS)), dim3(TPB), 0, st, L, mut);
+void launch_mut_ghosts(const BLev &B, hipStream_t st) {
+    hipLaunchKernelGGL(k_mut_ghosts, cells_grid(B), dim3(TPB), 0, st, B.k);
 }
 
-void launch_local_time_step(const Lay &L, const double *geo, const double *u, double *dts,
-                            double cfl, hipStream_t st) {
-    hipLaunchKernelGGL(k_local_time_step, dim3(nblocks(L.NS)), dim3(TPB), 0, st, L, geo, u, dts, cfl);
+void launch_local_time_step(const BLev &B, hipStream_t st) {
+    hipLaunchKernelGGL(k_local_time_step, cells_grid(B), dim3(TPB), 0, st, B.k);
 }
 
-void launch_residual(const Lay &L, const double *geo, const double *u, const double *cq,
-                     const double *vg, const double *mut, const double *un, const double *unm1,
-                     const double *src, const Phys &ph, const ResArgs &a, double *F, double *acc,
-                     const double *dts, const void *blk, void *g, hipStream_t st) {
+void launch_residual(const BLev &B, const ResArgs &a, hipStream_t st) {
     if (a.fp32)
-        hipLaunchKernelGGL(k_residual<float>, dim3(nblocks(L.NS)), dim3(TPB), 0, st, L, geo, u, cq,
-                           vg, mut, un, unm1, src, ph, a, F, acc, dts, (const float *)blk, (float *)g);
+        hipLaunchKernelGGL(k_residual<float>, cells_grid(B), dim3(TPB), 0, st, B.k, a);
     else
-        hipLaunchKernelGGL(k_residual<double>, dim3(nblocks(L.NS)), dim3(TPB), 0, st, L, geo, u, cq,
-                           vg, mut, un, unm1, src, ph, a, F, acc, dts, (const double *)blk,
-                           (double *)g);
+        hipLaunchKernelGGL(k_residual<double>, cells_grid(B), dim3(TPB), 0, st, B.k, a);
 }
 
-void launch_blocks(const Lay &L, const double *geo, const double *u, const double *cq,
-                   const double *mut, const double *dts, const Phys &ph, int aw, double tau,
-                   int viscous, int fp32, void *blk, hipStream_t st) {
+void launch_blocks(const BLev &B, int aw, double tau, int viscous, int fp32, hipStream_t st) {
     if (fp32)
-        hipLaunchKernelGGL(k_blocks<float>, dim3(nblocks(L.NS)), dim3(TPB), 0, st, L, geo, u, cq, mut,
-                           dts, ph, aw, tau, viscous, (float *)blk);
+        hipLaunchKernelGGL(k_blocks<float>, cells_grid(B), dim3(TPB), 0, st, B.k, aw, tau, viscous);
     else
-        hipLaunchKernelGGL(k_blocks<double>, dim3(nblocks(L.NS)), dim3(TPB), 0, st, L, geo, u, cq,
-                           mut, dts, ph, aw, tau, viscous, (double *)blk);
+        hipLaunchKernelGGL(k_blocks<double>, cells_grid(B), dim3(TPB), 0, st, B.k, aw, tau, viscous);
+}
+
+// Sweep configurations: four threads per row (k_sgs4 with NT threads, R
+// rows per four-thread group, prefetch batches of D hyperplanes, as deep as
+// the register file allows at that size), and the one-thread-per-row
+// kernel for grids taller than 256 rows.
+struct SweepCfg {
+    int kind;   // 4: k_sgs4, 1: k_sgs
+    int nt, r, d;
+};
+static const SweepCfg SWEEP_CFGS[] = {
+    {4, 64, 1, 10},  {4, 128, 1, 10}, {4, 256, 1, 10}, {4, 512, 1, 5}, {4, 1024, 1, 2},
+    {4, 64, 2, 5},   {4, 128, 2, 5},  {4, 256, 2, 5},  {4, 512, 2, 2},
+    {1, 64, 1, 0},   {1, 128, 1, 0},  {1, 256, 1, 0},  {1, 512, 1, 0},
+};
+constexpr int N_SWEEP_CFGS = (int)(sizeof(SWEEP_CFGS) / sizeof(SWEEP_CFGS[0]));
+
+int sweep_cfg_count() { return N_SWEEP_CFGS; }
+
+int sweep_cfg_rows(int cfg) {
+    const SweepCfg &c = SWEEP_CFGS[cfg];
+    return c.kind == 4 ? c.nt / 4 * c.r : c.nt;
+}
+
+int sweep_cfg_default(int max_nj) {
+    if (max_nj <= 16) return 0;
+    if (max_nj <= 32) return 1;
+    if (max_nj <= 64) return 2;
+    if (max_nj <= 128) return 3;
+    if (max_nj <= 256) return 4;
+    return 12;
 }
 
 template <typename T>
-static void sgs_dispatch(const Lay &L, const void *blk, const void *g, void *y, const SweepArgs &a,
-                         hipStream_t st) {
-    size_t shm = (size_t)(L.nw > 0 ? L.nw : 1) * 4 * sizeof(T);
-    size_t shm4 = (size_t)(L.nw > 0 ? L.nw : 1) * 20 * sizeof(T);
-    // one row per four-thread group (NT = 4 nj threads), prefetch batches of
-    // D hyperplanes as deep as the register file allows
-    if (L.nj <= 16) {
-        hipLaunchKernelGGL((k_sgs4<T, 64, 1, 10>), dim3(1), dim3(64), shm4, st, L, (const T *)blk,
-                           (const T *)g, (T *)y, a);
-        return;
+static void sgs_dispatch(const BLev &B, const SweepArgs &a, hipStream_t st) {
+    int cfg = B.sweep_cfg >= 0 ? B.sweep_cfg : sweep_cfg_default(B.max_nj);
+    if (sweep_cfg_rows(cfg) < B.max_nj) cfg = sweep_cfg_default(B.max_nj);
+    const int nwl = B.max_nw > 0 ? B.max_nw : 1;
+    const size_t shm = (size_t)nwl * 4 * sizeof(T);
+    const size_t shm4 = (size_t)nwl * 20 * sizeof(T);
+    const dim3 grid(B.n);
+#define FAS_SGS4(NT_, R_, D_) \
+    hipLaunchKernelGGL((k_sgs4<T, NT_, R_, D_>), grid, dim3(NT_), shm4, st, B.k, a)
+#define FAS_SGS1(NT_) hipLaunchKernelGGL((k_sgs<T, NT_>), grid, dim3(NT_), shm, st, B.k, a)
+    switch (cfg) {
+        case 0: FAS_SGS4(64, 1, 10); break;
+        case 1: FAS_SGS4(128, 1, 10); break;
+        case 2: FAS_SGS4(256, 1, 10); break;
+        case 3: FAS_SGS4(512, 1, 5); break;
+        case 4: FAS_SGS4(1024, 1, 2); break;
+        case 5: FAS_SGS4(64, 2, (sizeof(T) == 4 ? 3 : 5)); break;
+        case 6: FAS_SGS4(128, 2, (sizeof(T) == 4 ? 3 : 5)); break;
+        case 7: FAS_SGS4(256, 2, (sizeof(T) == 4 ? 3 : 5)); break;
+        case 8: FAS_SGS4(512, 2, 2); break;
+        case 9: FAS_SGS1(64); break;
+        case 10: FAS_SGS1(128); break;
+        case 11: FAS_SGS1(256); break;
+        default: FAS_SGS1(512); break;
     }
-    if (L.nj <= 32) {
-        hipLaunchKernelGGL((k_sgs4<T, 128, 1, 10>), dim3(1), dim3(128), shm4, st, L, (const T *)blk,
-                           (const T *)g, (T *)y, a);
-        return;
-    }
-    if (L.nj <= 64) {
-        hipLaunchKernelGGL((k_sgs4<T, 256, 1, 10>), dim3(1), dim3(256), shm4, st, L, (const T *)blk,
-                           (const T *)g, (T *)y, a);
-        return;
-    }
-    if (L.nj <= 128) {
-        hipLaunchKernelGGL((k_sgs4<T, 512, 1, 5>), dim3(1), dim3(512), shm4, st, L, (const T *)blk,
-                           (const T *)g, (T *)y, a);
-        return;
-    }
-    if (L.nj <= 256) {
-        hipLaunchKernelGGL((k_sgs4<T, 1024, 1, 2>), dim3(1), dim3(1024), shm4, st, L, (const T *)blk,
-                           (const T *)g, (T *)y, a);
-        return;
-    }
-    if (L.nj <= 64)
-        hipLaunchKernelGGL((k_sgs<T, 64>), dim3(1), dim3(64), shm, st, L, (const T *)blk,
-                           (const T *)g, (T *)y, a);
-    else if (L.nj <= 128)
-        hipLaunchKernelGGL((k_sgs<T, 128>), dim3(1), dim3(128), shm, st, L, (const T *)blk,
-                           (const T *)g, (T *)y, a);
-    else if (L.nj <= 256)
-        hipLaunchKernelGGL((k_sgs<T, 256>), dim3(1), dim3(256), shm, st, L, (const T *)blk,
-                           (const T *)g, (T *)y, a);
-    else
-        hipLaunchKernelGGL((k_sgs<T, 512>), dim3(1), dim3(512), shm, st, L, (const T *)blk,
-                           (const T *)g, (T *)y, a);
+#undef FAS_SGS4
+#undef FAS_SGS1
 }
 
-void launch_sgs(const Lay &L, const void *blk, const void *g, void *y, const SweepArgs &a, int fp32,
-                hipStream_t st) {
-    if (fp32) sgs_dispatch<float>(L, blk, g, y, a, st);
-    else sgs_dispatch<double>(L, blk, g, y, a, st);
+void launch_sgs(const BLev &B, const SweepArgs &a, int fp32, hipStream_t st) {
+    if (fp32) sgs_dispatch<float>(B, a, st);
+    else sgs_dispatch<double>(B, a, st);
 }
 
-void launch_dinv(const Lay &L, const void *blk, const double *r, void *g, int fp32, hipStream_t st) {
+void launch_dinv(const BLev &B, int fp32, hipStream_t st) {
     if (fp32)
-        hipLaunchKernelGGL(k_dinv<float>, dim3(nblocks(L.NS)), dim3(TPB), 0, st, L, (const float *)blk, r,
-                           (float *)g);
+        hipLaunchKernelGGL(k_dinv<float>, cells_grid(B), dim3(TPB), 0, st, B.k);
     else
-        hipLaunchKernelGGL(k_dinv<double>, dim3(nblocks(L.NS)), dim3(TPB), 0, st, L, (const double *)blk, r,
-                           (double *)g);
+        hipLaunchKernelGGL(k_dinv<double>, cells_grid(B), dim3(TPB), 0, st, B.k);
 }
 
-void launch_restrict(const Lay &Lf, const Lay &Lc, const double *geo_f, const double *geo_c,
-                     const double *vf, double *vc, double *vc_copy, hipStream_t st) {
-    hipLaunchKernelGGL(k_restrict, dim3(nblocks(Lc.NS)), dim3(TPB), 0, st, Lf, Lc, geo_f, geo_c, vf,
-                       vc, vc_copy);
+void launch_restrict(const BLev &Bf, const BLev &Bc, int fin, int fout, int fout2, hipStream_t st) {
+    hipLaunchKernelGGL(k_restrict, cells_grid(Bc), dim3(TPB), 0, st, Bf.k, Bc.k, fin, fout, fout2);
 }
 
-void launch_prolong(const Lay &Lf, const Lay &Lc, const double *uc, const double *utc, double *uf,
-                    hipStream_t st) {
-    hipLaunchKernelGGL(k_prolong, dim3(nblocks(Lf.NS)), dim3(TPB), 0, st, Lf, Lc, uc, utc, uf);
+void launch_prolong(const BLev &Bf, const BLev &Bc, hipStream_t st) {
+    hipLaunchKernelGGL(k_prolong, cells_grid(Bf), dim3(TPB), 0, st, Bf.k, Bc.k);
 }
 
-void launch_axpby_interior(const Lay &L, double a, const double *x, double b, const double *y,
-                           double *out, int ncomp, hipStream_t st) {
-    hipLaunchKernelGGL(k_axpby, dim3(nblocks(L.NS)), dim3(TPB), 0, st, L, a, x, b, y, out, ncomp);
+void launch_axpby(const BLev &B, double a, int fx, double b, int fy, int fout, hipStream_t st) {
+    hipLaunchKernelGGL(k_axpby, cells_grid(B), dim3(TPB), 0, st, B.k, a, fx, b, fy, fout);
 }
 
 void launch_pack(const Lay &L, const double *padded, double *natural, int ncomp, hipStream_t st) {
@@ -1478,14 +1630,27 @@ void launch_unpack(const Lay &L, const double *natural, double *padded, int ncom
     hipLaunchKernelGGL(k_unpack, dim3(nblocks(L.ni * L.nj)), dim3(TPB), 0, st, L, natural, padded, ncomp);
 }
 
-int norm_scratch_size(const Lay &L) {
-    (void)L;
-    return RED_BLOCKS;
+int norm_scratch_size() { return RED_BLOCKS; }
+
+void launch_norm(const BLev &B, double *out, hipStream_t st) {
+    hipLaunchKernelGGL(k_norm1, dim3(RED_BLOCKS, B.n), dim3(TPB), 0, st, B.k);
+    hipLaunchKernelGGL(k_norm2, dim3(B.n), dim3(64), 0, st, B.k, out);
 }
 
-void launch_norm(const Lay &L, const double *F, double *red, double *out, hipStream_t st) {
-    hipLaunchKernelGGL(k_norm1, dim3(RED_BLOCKS), dim3(TPB), 0, st, L, F, red);
-    hipLaunchKernelGGL(k_norm2, dim3(1), dim3(64), 0, st, red, RED_BLOCKS, (double)L.ni * L.nj, out);
+void launch_count_cycle(const BLev &B, int *cyc, hipStream_t st) {
+    hipLaunchKernelGGL(k_count_cycle, dim3(nblocks(B.n, 64)), dim3(64), 0, st, B.k, cyc, B.n);
+}
+
+void launch_fill_int(int *p, int n, int v, hipStream_t st) {
+    hipLaunchKernelGGL(k_fill_int, dim3(nblocks(n, 64)), dim3(64), 0, st, p, n, v);
+}
+
+void launch_batch_init(const BatchCtl &c, int n, hipStream_t st) {
+    hipLaunchKernelGGL(k_batch_init, dim3(nblocks(n, 64)), dim3(64), 0, st, c, n);
+}
+
+void launch_batch_status(const BatchCtl &c, int n, hipStream_t st) {
+    hipLaunchKernelGGL(k_batch_status, dim3(nblocks(n, 64)), dim3(64), 0, st, c, n);
 }
 
 }  // namespace fas

@@ -77,7 +77,9 @@ EXPORTS = [
     "fas_params_default", "fas_grid_create", "fas_grid_destroy", "fas_state_create",
     "fas_state_destroy", "fas_state_set_params", "fas_set_state", "fas_get_state",
     "fas_get_level", "fas_residual", "fas_smooth", "fas_sgs_apply", "fas_cycle",
-    "fas_dual_time_step", "fas_profile", "fas_profile_read", "fas_last_error",
+    "fas_dual_time_step", "fas_profile", "fas_profile_read", "fas_batch_create",
+    "fas_batch_destroy", "fas_batch_solve", "fas_batch_sweep_config", "fas_batch_set_sweep_config", "fas_batch_profile",
+    "fas_batch_profile_read", "fas_last_error",
 ]
 PROF_CLASSES = ("sweep", "residual", "blocks")
 
@@ -109,6 +111,13 @@ def load(path: str = LIB_PATH):
         "fas_dual_time_step": (i32, [vp, f64, f64, i32, f64, dp, ip]),
         "fas_profile": (i32, [vp, i32]),
         "fas_profile_read": (i32, [vp, dp, ctypes.POINTER(ctypes.c_int64)]),
+        "fas_batch_create": (i32, [i32, ctypes.POINTER(vp), vp, i32, ctypes.POINTER(vp)]),
+        "fas_batch_destroy": (None, [vp]),
+        "fas_batch_solve": (i32, [vp, i32, f64, i32, ip, ip, dp]),
+        "fas_batch_sweep_config": (i32, [vp, i32, ip, ip]),
+        "fas_batch_set_sweep_config": (i32, [vp, i32, i32]),
+        "fas_batch_profile": (i32, [vp, i32]),
+        "fas_batch_profile_read": (i32, [vp, dp, ctypes.POINTER(ctypes.c_int64)]),
         "fas_last_error": (ctypes.c_char_p, []),
     }
     for name, (res, args) in sig.items():
@@ -253,3 +262,54 @@ class State:
 def torch_dtype():
     import torch
     return torch.float64
+
+
+class Batch:
+    """Independent steady cases advanced together (one launch per kernel
+    over all cases, optionally replayed from a captured HIP graph).  The
+    batch works in place on the states' buffers; keep them alive."""
+
+    def __init__(self, states, autotune=True):
+        lib = load()
+        self.states = list(states)
+        arr = (ctypes.c_void_p * len(self.states))(*[st.h.value for st in self.states])
+        h = ctypes.c_void_p()
+        _check(lib.fas_batch_create(len(self.states), arr, _stream(), 1 if autotune else 0,
+                                    ctypes.byref(h)))
+        self.h = h
+
+    def __del__(self):
+        if getattr(self, "h", None) and _lib is not None:
+            _lib.fas_batch_destroy(self.h)
+            self.h = None
+
+    def solve(self, max_cycles, drop_orders=0.0, use_graph=True):
+        """Returns (per-case histories, per-case status, worst status)."""
+        n = len(self.states)
+        hist = np.zeros((n, max_cycles + 1))
+        nd = np.zeros(n, dtype=np.int32)
+        stv = np.zeros(n, dtype=np.int32)
+        ip = ctypes.POINTER(ctypes.c_int32)
+        st = _check(_lib.fas_batch_solve(self.h, max_cycles, drop_orders, 1 if use_graph else 0,
+                                         nd.ctypes.data_as(ip), stv.ctypes.data_as(ip),
+                                         hist.ctypes.data_as(ctypes.POINTER(ctypes.c_double))),
+                    allow=(FAS_NOT_CONVERGED, FAS_DIVERGED))
+        return [hist[c, :nd[c] + 1].copy() for c in range(n)], stv, st
+
+    def sweep_config(self, level):
+        c, r = ctypes.c_int32(0), ctypes.c_int32(0)
+        _check(_lib.fas_batch_sweep_config(self.h, level, ctypes.byref(c), ctypes.byref(r)))
+        return c.value, r.value
+
+    def set_sweep_config(self, level, cfg):
+        _check(_lib.fas_batch_set_sweep_config(self.h, level, cfg))
+
+    def profile(self, enable=True):
+        _check(_lib.fas_batch_profile(self.h, 1 if enable else 0))
+
+    def profile_read(self):
+        ms = np.zeros(len(PROF_CLASSES))
+        n = np.zeros(len(PROF_CLASSES), dtype=np.int64)
+        _check(_lib.fas_batch_profile_read(self.h, ms.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                           n.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))))
+        return {c: (float(ms[k]), int(n[k])) for k, c in enumerate(PROF_CLASSES)}

@@ -1,0 +1,166 @@
+"""Batched engine: uneven cases advanced together must give, case by case,
+exactly the result of the single-state path (same kernels, same order),
+with or without the captured graph and for every sweep configuration; one
+case is also checked against the oracle (needs a GPU)."""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+import fas_inputs as fi
+from gpu_common import TOL_STATE, state_err
+
+pytestmark = pytest.mark.gpu
+
+# sweep configurations from this index on use one thread per row
+ONE_THREAD_PER_ROW = 9
+
+# (ni, nj, n_wake, mach, alpha): uneven grids and flow conditions
+CASES = [(64, 32, 8, 0.8, 1.3), (96, 48, 12, 0.6, 0.4), (128, 16, 16, 0.75, 2.5)]
+
+
+def _params(mach, alpha, fp32=0, levels=3, model=1, **kw):
+    from paper_1710_04875_amd import fas
+    base = dict(model=model, scheme=fas.FAS_AW3, mach=mach, alpha_deg=alpha, n_levels=levels,
+                cycle_gamma=1, nu1=1, eta=0.5, d_cut=0.5, cfl=50.0, cfl_ramp=5.0, n_ramp=1,
+                ramp_growth=1.5, precond_fp32=fp32)
+    base.update(kw)
+    return fas.Params(**base)
+
+
+def _u0(ni, nj, mach, alpha, seed):
+    return fi.perturbed_state(fi.uniform_state(ni, nj, mach, alpha), 0.01, seed=seed)
+
+
+def _states(fp32=0, levels=3, cases=CASES, **kw):
+    from paper_1710_04875_amd import fas
+    out = []
+    for k, (ni, nj, nw, m, a) in enumerate(cases):
+        x, y = fi.cgrid(ni, nj, nw)
+        g = fas.Grid(fi.CGRID, x, y, nw, levels)
+        u0 = torch.from_numpy(_u0(ni, nj, m, a, 20 + k)).cuda()
+        out.append((g, fas.State(g, _params(m, a, fp32, levels, **kw), u0)))
+    return out
+
+
+def _run_single(fp32=0, cycles=6, drop=0.0, **kw):
+    res = []
+    for g, st in _states(fp32, **kw):
+        h, s = st.cycle(cycles, drop)
+        torch.cuda.synchronize()
+        res.append((st.get_state().cpu().numpy(), h, s))
+    return res
+
+
+def _run_batch(fp32=0, cycles=6, drop=0.0, use_graph=True, cfg=None, **kw):
+    from paper_1710_04875_amd import fas
+    pairs = _states(fp32, **kw)
+    b = fas.Batch([st for _, st in pairs], autotune=cfg is None)
+    if cfg is not None:
+        b.set_sweep_config(0, cfg)
+    hist, stat, worst = b.solve(cycles, drop, use_graph)
+    torch.cuda.synchronize()
+    us = [st.get_state().cpu().numpy() for _, st in pairs]
+    return us, hist, stat, b
+
+
+@pytest.mark.parametrize("use_graph", [True, False])
+def test_batch_equals_single_states(use_graph):
+    ref = _run_single()
+    us, hist, stat, _ = _run_batch(use_graph=use_graph)
+    for c in range(len(CASES)):
+        assert np.array_equal(us[c], ref[c][0]), c
+        assert np.array_equal(hist[c], ref[c][1]), c
+        assert stat[c] == 0
+
+
+def test_batch_fp32_preconditioner_equals_single_states():
+    ref = _run_single(fp32=1)
+    us, hist, stat, _ = _run_batch(fp32=1)
+    for c in range(len(CASES)):
+        assert np.array_equal(us[c], ref[c][0]), c
+        assert np.array_equal(hist[c], ref[c][1]), c
+
+
+def test_batch_stops_each_case_at_its_own_drop():
+    from paper_1710_04875_amd import fas
+    ref = _run_single(cycles=40, drop=3.0, cfl=20.0)
+    us, hist, stat, _ = _run_batch(cycles=40, drop=3.0, cfl=20.0)
+    for c in range(len(CASES)):
+        assert len(hist[c]) == len(ref[c][1]), c
+        assert np.array_equal(us[c], ref[c][0]), c
+        assert stat[c] == ref[c][2] == fas.FAS_OK
+    assert len({len(h) for h in hist}) > 1
+
+
+def test_diverging_case_stops_alone():
+    """At c* = 50 the 128 x 16 grid (4 rows on the coarsest level) diverges
+    after about 17 cycles, in the oracle as well; the other cases go on."""
+    from paper_1710_04875_amd import fas
+    ref = _run_single(cycles=30, drop=0.0)
+    us, hist, stat, _ = _run_batch(cycles=30, drop=0.0)
+    assert stat[2] == ref[2][2] == fas.FAS_DIVERGED
+    assert len(hist[2]) < 31
+    for c in (0, 1):
+        assert stat[c] == fas.FAS_OK and len(hist[c]) == 31
+        assert np.array_equal(us[c], ref[c][0]), c
+        assert np.array_equal(hist[c], ref[c][1]), c
+
+
+def test_every_sweep_configuration_gives_the_same_iterate():
+    from paper_1710_04875_amd import fas
+    ref = _run_single(cycles=2)
+    tried = 0
+    for cfg in range(13):
+        pairs = _states()
+        b = fas.Batch([st for _, st in pairs], autotune=False)
+        try:
+            b.set_sweep_config(0, cfg)
+        except fas.FasError:
+            continue        # covers fewer rows than the tallest grid
+        tried += 1
+        b.solve(2, 0.0, True)
+        torch.cuda.synchronize()
+        for c, (_, s) in enumerate(pairs):
+            u = s.get_state().cpu().numpy()
+            if cfg < ONE_THREAD_PER_ROW:
+                # the four-thread sweeps share their arithmetic: bitwise equal
+                assert np.array_equal(u, ref[c][0]), (cfg, c)
+            else:
+                # the one-thread-per-row sweep sums the block products in
+                # another order
+                assert state_err(u, ref[c][0]) < TOL_STATE, (cfg, c)
+    assert tried >= 8
+
+
+def test_autotuned_configuration_covers_the_tallest_grid():
+    _, _, _, b = _run_batch(cycles=1)
+    for level in range(3):
+        cfg, rows = b.sweep_config(level)
+        assert rows >= max(nj for _, nj, _, _, _ in CASES) >> level
+
+
+def test_batched_case_matches_oracle_after_one_cycle():
+    from oracle import fas as ofas
+    us, _, _, _ = _run_batch(cycles=1)
+    ni, nj, nw, m, a = CASES[1]
+    x, y = fi.cgrid(ni, nj, nw)
+    p = _params(m, a)
+    op = ofas.Params(model=1, scheme=0, mach=m, alpha_deg=a, n_levels=3, cycle_gamma=1, nu1=1,
+                     eta=0.5, d_cut=0.5, cfl=50.0, cfl_ramp=5.0, n_ramp=1, ramp_growth=1.5)
+    S = ofas.Solver(x, y, fi.CGRID, nw, op, _u0(ni, nj, m, a, 21))
+    S.cycle(0)
+    assert state_err(us[1], S.u()) < 10 * TOL_STATE
+    assert p.n_levels == 3
+
+
+def test_batch_rejects_mixed_structures():
+    from paper_1710_04875_amd import fas
+    pairs = _states(levels=3)
+    x, y = fi.cgrid(64, 32, 8)
+    g = fas.Grid(fi.CGRID, x, y, 8, 3)
+    other = fas.State(g, _params(0.8, 1.0, fp32=1), torch.from_numpy(_u0(64, 32, 0.8, 1.0, 5)).cuda())
+    with pytest.raises(fas.FasError):
+        fas.Batch([pairs[0][1], other])
+    with pytest.raises(fas.FasError):
+        fas.Batch([pairs[0][1], pairs[0][1]])
