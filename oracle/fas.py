@@ -12,7 +12,13 @@ coarsest).  One cycle on level l:
         cycle(l+1) gamma times           (gamma = 2: the paper's W-cycle)
         u_l += P (u_{l+1} - u~)          (bilinear prolongation)
 
-Readings: the smoother on a coarse level drives F_l(u) - s_l to zero (the
+Readings: on RANS levels the coarse operators keep the viscous flux (the
+paper only states that the convective part becomes first-order JST), with
+the eddy viscosity of the finer level restricted by volume-weighted
+agglomeration whenever the cycle descends, frozen on that level until the
+next descent (laminar, mu_t = 0, before the first one); without it the
+W-cycle diverges for RANS on boundary-layer grids.  The smoother on a
+coarse level drives F_l(u) - s_l to zero (the
 printed "s_l - F_l" has the opposite sign of a pseudo-time residual); R of
 the per-volume residual is its volume-weighted mean; the bilinear
 prolongation weights the parent and its three neighbours on the fine
@@ -66,6 +72,12 @@ def restrict(lev_f, lev_c, v):
     return s / lev_c.vol
 
 
+def restrict_scalar(lev_f, lev_c, m):
+    """Volume-weighted agglomeration of a (nj, ni) field."""
+    w = m * lev_f.vol
+    return (((w[0::2, 0::2] + w[0::2, 1::2]) + w[1::2, 0::2]) + w[1::2, 1::2]) / lev_c.vol
+
+
 def prolong(lev_f, lev_c, e):
     """Bilinear prolongation of a coarse correction e (4, njc, nic)."""
     nic, njc = lev_c.ni, lev_c.nj
@@ -116,6 +128,9 @@ class Solver:
         self.bdf = 0
         self.n_cycles = 0
         self.mut = np.zeros((self.levels[0].nj, self.levels[0].ni))
+        # padded eddy viscosity of the coarse levels (restricted)
+        self.mutc = [None] + [padded_eddy_viscosity(lev, np.zeros((lev.nj, lev.ni)))
+                              for lev in self.levels[1:]]
         self.alpha, self.beta, self.aw = SCHEMES[par.scheme]
 
     # ---------------------------------------------------------------- state
@@ -150,9 +165,11 @@ class Solver:
         return None
 
     def mutp(self, l):
-        if l == 0 and self.par.model == RANS:
+        if self.par.model != RANS:
+            return None
+        if l == 0:
             return padded_eddy_viscosity(self.levels[0], self.mut)
-        return None
+        return self.mutc[l]
 
     def split(self, l, u, mutp=None, with_forcing=True):
         Up = self.padded(l, u)
@@ -169,6 +186,8 @@ class Solver:
             Up = self.padded(0, u)
             mutp = padded_eddy_viscosity(self.levels[0],
                                          baldwin_lomax(self.levels[0], Up, self.par))
+        elif self.par.model == RANS:
+            mutp = self.mutc[l]
         Fc, Fv = self.split(l, u, mutp, with_forcing)
         return Fc + Fv
 
@@ -192,6 +211,8 @@ class Solver:
         if l == 0 and self.par.model == RANS:
             self.mut = baldwin_lomax(lev, Up, self.par)
             mutp = padded_eddy_viscosity(lev, self.mut)
+        elif self.par.model == RANS:
+            mutp = self.mutc[l]
         blocks = Blocks(lev, Up, dts, self.par, self.tau(), self.aw, mutp)
         return u0, dts, mutp, blocks
 
@@ -216,6 +237,13 @@ class Solver:
         if l == L - 1:
             return
         lev_f, lev_c = self.levels[l], self.levels[l + 1]
+        if self.par.model == RANS:
+            # eddy viscosity of this level at its current state, restricted
+            if l == 0:
+                m = baldwin_lomax(lev_f, self.padded(0, self.u(0)), self.par)
+            else:
+                m = self.mutc[l][NG:NG + lev_f.nj, NG:NG + lev_f.ni]
+            self.mutc[l + 1] = padded_eddy_viscosity(lev_c, restrict_scalar(lev_f, lev_c, m))
         F = self.residual(l, with_forcing=False)
         r = -F if self.s[l] is None else self.s[l] - F
         ut = restrict(lev_f, lev_c, self.u(l))

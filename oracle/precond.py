@@ -132,7 +132,7 @@ def face_viscous(lev, Up, mutp, par):
 class Blocks:
     """D and the four neighbour blocks of every cell, frozen at a state.
 
-    With ``mutp`` (fine level, RANS) a scalar estimate of the viscous
+    With ``mutp`` (RANS levels) a scalar estimate of the viscous
     Jacobian is added: v_f on the diagonal for every face and -v_f on the
     coupling (both then scaled like the convective blocks), v_f from
     ``face_viscous``.  The paper's

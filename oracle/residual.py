@@ -293,11 +293,14 @@ def padded_eddy_viscosity(lev, mut):
 def split_residual(lev, Up, par, fine: bool, mutp=None, time_src=None, forcing=None):
     """(F^c, F^v), per unit volume, for the padded state Up whose ghosts are
     already filled.  ``time_src`` is the BDF term, ``forcing`` the FAS
-    source s of the level (the smoother drives F(u) - s to zero)."""
+    source s of the level (the smoother drives F(u) - s to zero).  RANS
+    levels carry the viscous flux with the padded eddy viscosity ``mutp``
+    on every level (the fine level's Baldwin-Lomax field, restricted to
+    the coarse levels)."""
     ni, nj = lev.ni, lev.nj
     Cxi, Dxi, Ceta, Deta = convective_faces(lev, Up, par, second_order=fine)
     fc = (Cxi[:, :, 1:] - Cxi[:, :, :-1]) + (Ceta[:, 1:, :] - Ceta[:, :-1, :])
-    if fine and par.model == 1:
+    if par.model == 1 and mutp is not None:
         Gxi, Geta = viscous_faces(lev, Up, mutp, par)
         Vxi = -Dxi - Gxi
         Veta = -Deta - Geta

@@ -457,7 +457,10 @@ struct Prof {
     }
 };
 
+// the Baldwin-Lomax model runs on the fine level; every RANS level carries
+// the viscous flux (coarse levels with the restricted eddy viscosity)
 bool fine_rans(const Engine &e, int l) { return l == 0 && e.model == FAS_RANS_BL; }
+bool rans(const Engine &e) { return e.model == FAS_RANS_BL; }
 
 double tau_of(const Engine &e) {
     if (e.bdf == 2) return 3.0 / (2.0 * e.dt);
@@ -472,12 +475,10 @@ void prep(Engine &e, int l, bool with_bl) {
     const int rans = e.model == FAS_RANS_BL;
     launch_ghost_state(B, rans, e.st);
     launch_cell_quantities(B, rans, e.st);
-    if (fine_rans(e, l)) {
-        launch_vertex_gradients(B, e.st);
-        if (with_bl) {
-            launch_baldwin_lomax(B, e.st);
-            launch_mut_ghosts(B, e.st);
-        }
+    if (rans) launch_vertex_gradients(B, e.st);
+    if (fine_rans(e, l) && with_bl) {
+        launch_baldwin_lomax(B, e.st);
+        launch_mut_ghosts(B, e.st);
     }
 }
 
@@ -485,7 +486,7 @@ ResArgs res_args(const Engine &e, int l, int mode, int forcing) {
     ResArgs a;
     std::memset(&a, 0, sizeof(a));
     a.fine = l == 0;
-    a.viscous = fine_rans(e, l);
+    a.viscous = rans(e);
     a.bdf = e.bdf;
     a.dt = e.dt;
     a.forcing = forcing && e.has_src[l];
@@ -507,7 +508,7 @@ void prepare_iteration(Engine &e, int l) {
     prep(e, l, fine_rans(e, l));
     launch_local_time_step(B, e.st);
     Prof pr(e, FAS_PROF_BLOCKS);
-    launch_blocks(B, e.sc.aw, tau_of(e), fine_rans(e, l), e.fp32, e.st);
+    launch_blocks(B, e.sc.aw, tau_of(e), rans(e), e.fp32, e.st);
 }
 
 // one smoother iteration (Section 4 low-storage stages)
@@ -540,6 +541,12 @@ void cycle(Engine &e, int l) {
     if (l == e.nlev - 1) return;
     const BLev &f = e.lev[l], &c = e.lev[l + 1];
     eval_F(e, l, false);
+    if (rans(e)) {
+        // the eddy viscosity F_l was evaluated with, restricted and frozen
+        // on the coarser level until the next descent
+        launch_restrict_mut(f, c, e.st);
+        launch_mut_ghosts(c, e.st);
+    }
     // r_l = s_l - F_l(u_l)
     if (e.has_src[l]) launch_axpby(f, -1.0, FLD_F, 1.0, FLD_SRC, FLD_F, e.st);
     else launch_axpby(f, -1.0, FLD_F, 0.0, FLD_NONE, FLD_F, e.st);

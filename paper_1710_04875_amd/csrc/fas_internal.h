@@ -75,9 +75,9 @@ struct LevelDev {
     double *ut;       // 4 * NS   restricted solution u~ (coarse levels)
     double *un, *unm1;// 4 * NS   physical time levels
     double *dts;      // NS
-    double *mut;      // NS       eddy viscosity (fine level)
+    double *mut;      // NS       eddy viscosity (fine: Baldwin-Lomax; coarse: restricted)
     double *cq;       // Q_NPLANES * NS
-    double *vg;       // V_NPLANES * NS (fine RANS)
+    double *vg;       // V_NPLANES * NS (RANS)
     void *blk;        // BLK_NPLANES * NS, double or float
     void *g;          // 4 * NS   D^-1 (dt* r) / forward sweep input
     void *y;          // 4 * NS   forward sweep output
@@ -135,7 +135,7 @@ void launch_local_time_step(const BLev &B, hipStream_t st);
 
 struct ResArgs {
     int fine;          // second-order JST (sensor, fourth difference)
-    int viscous;       // add the viscous flux (fine RANS)
+    int viscous;       // add the viscous flux (RANS levels)
     int bdf;           // 0 steady, 1 implicit Euler, 2 BDF2
     double dt;         // physical time step
     int forcing;       // subtract src
@@ -166,6 +166,7 @@ int sweep_cfg_default(int max_nj);
 
 // transfers and utilities
 void launch_restrict(const BLev &Bf, const BLev &Bc, int fin, int fout, int fout2, hipStream_t st);
+void launch_restrict_mut(const BLev &Bf, const BLev &Bc, hipStream_t st);
 void launch_prolong(const BLev &Bf, const BLev &Bc, hipStream_t st);
 void launch_axpby(const BLev &B, double a, int fx, double b, int fy, int fout, hipStream_t st);
 void launch_pack(const Lay &L, const double *padded, double *natural, int ncomp, hipStream_t st);

@@ -1329,6 +1329,24 @@ __global__ void k_restrict(BK bf, BK bc, int fin, int fout, int fout2) {
     }
 }
 
+// eddy viscosity of the finer level agglomerated to the coarser one
+// (volume weighted), for the viscous flux of the coarse RANS operator
+__global__ void k_restrict_mut(BK bf, BK bc) {
+    LevelDev df, dc;
+    if (!take(bf, blockIdx.y, df) || !take(bc, blockIdx.y, dc)) return;
+    const Lay Lf = df.L, Lc = dc.L;
+    int s = blockIdx.x * blockDim.x + threadIdx.x;
+    int i, j;
+    if (!decode(Lc, s, i, j) || !interior(Lc, i, j)) return;
+    const int NSf = Lf.NS, NSc = Lc.NS;
+    int c00 = Lf.slot(2 * i, 2 * j), c10 = Lf.slot(2 * i + 1, 2 * j);
+    int c01 = Lf.slot(2 * i, 2 * j + 1), c11 = Lf.slot(2 * i + 1, 2 * j + 1);
+    const double *gf = df.geo + (size_t)G_VOL * NSf;
+    double w00 = df.mut[c00] * gf[c00], w10 = df.mut[c10] * gf[c10];
+    double w01 = df.mut[c01] * gf[c01], w11 = df.mut[c11] * gf[c11];
+    dc.mut[s] = (((w00 + w10) + w01) + w11) / dc.geo[(size_t)G_VOL * NSc + s];
+}
+
 // Section 3: bilinear prolongation of the coarse correction, weights
 // 9/16 (parent), 3/16, 3/16, 1/16 towards the fine cell's side; the wake-cut
 // partner across the cut, the parent's value where a neighbour is missing.
@@ -1612,6 +1630,10 @@ void launch_dinv(const BLev &B, int fp32, hipStream_t st) {
 
 void launch_restrict(const BLev &Bf, const BLev &Bc, int fin, int fout, int fout2, hipStream_t st) {
     hipLaunchKernelGGL(k_restrict, cells_grid(Bc), dim3(TPB), 0, st, Bf.k, Bc.k, fin, fout, fout2);
+}
+
+void launch_restrict_mut(const BLev &Bf, const BLev &Bc, hipStream_t st) {
+    hipLaunchKernelGGL(k_restrict_mut, cells_grid(Bc), dim3(TPB), 0, st, Bf.k, Bc.k);
 }
 
 void launch_prolong(const BLev &Bf, const BLev &Bc, hipStream_t st) {
