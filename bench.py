@@ -133,6 +133,114 @@ def load_traffic(kernel_key):
     return d.get("bytes_per_launch")
 
 
+def batch_params(fas, c, fp32):
+    return fas.Params(model=fas.FAS_RANS_BL, scheme=fas.FAS_AW3, mach=c.mach, alpha_deg=c.alpha_deg,
+                      reynolds=c.reynolds, n_levels=3, cycle_gamma=1, nu1=1, eta=0.5, d_cut=0.5,
+                      cfl=100.0, cfl_ramp=1.0, n_ramp=4, ramp_growth=1.5, kappa2c=0.125,
+                      precond_fp32=1 if fp32 else 0)
+
+
+def batch_section(fas, torch, cap, loop_cycles, full_loop):
+    """64 steady RANS cases on uneven C-grids (128..512 x 64..256, seed 4):
+    the batched engine (one launch per kernel over all cases, one captured
+    graph per cycle) to a 6-order drop per case with the FP32 and the FP64
+    preconditioner, and the FP64 per-case loop (the same kernels, one case
+    after another)."""
+    import numpy as np
+    import fas_inputs as fi
+    cases = fi.batch_cases(64, seed=4)
+    cells = np.array([c.ni * c.nj for c in cases], dtype=np.float64)
+    grids = []
+    for c in cases:
+        x, y = c.grid()
+        grids.append((fas.Grid(c.topology, x, y, c.n_wake, 3), torch.from_numpy(c.initial_state(x, y)).cuda()))
+    out = {"cases": len(cases), "fine_cells": int(cells.sum()), "cycle_cap": cap}
+    finals, cycles, status = {}, {}, {}
+    for fp32 in (True, False):
+        tag = "fp32_precond" if fp32 else "fp64"
+        log("batch %s: create + autotune" % tag)
+        sts = [fas.State(g, batch_params(fas, c, fp32), u0) for (g, u0), c in zip(grids, cases)]
+        b = fas.Batch(sts, autotune=True)
+        torch.cuda.synchronize()
+        log("batch %s: solve to 6 orders (graph)" % tag)
+        t0 = time.perf_counter()
+        hist, stat, _ = b.solve(cap, 6.0, True)
+        torch.cuda.synchronize()
+        t = time.perf_counter() - t0
+        nd = np.array([len(h) - 1 for h in hist])
+        conv = stat == 0
+        finals[tag] = [st.get_state().cpu().numpy() for st in sts]
+        cycles[tag] = nd
+        status[tag] = stat
+        r = {"seconds": round(t, 3), "converged": int(conv.sum()),
+             "diverged": int((stat == -4).sum()),
+             "cycles_total": int(nd.sum()), "cycles_max": int(nd.max()),
+             "cell_cycles_per_s": round(float((cells * nd).sum() / t), 1),
+             "median_rate": round(float(np.median([(h[-1] / h[0]) ** (1.0 / max(len(h) - 1, 1))
+                                                   for h in hist])), 4),
+             "sweep_cfg_rows": [b.sweep_config(l)[1] for l in range(3)]}
+        # kernel timing of the batched cycle: a few directly launched cycles
+        b.profile(True)
+        t0 = time.perf_counter()
+        b.solve(10, 0.0, False)
+        torch.cuda.synchronize()
+        t = time.perf_counter() - t0
+        prof = b.profile_read()
+        b.profile(False)
+        r["cycle_ms_all_active"] = round(1e3 * t / 10, 3)
+        r["kernel_ms_per_cycle"] = {k: round(v[0] / 10, 3) for k, v in prof.items()}
+        if not fp32:
+            ms, cnt = prof["sweep"]
+            per_cycle = 3.0 * float(cells.sum()) * (1 + 0.25 + 0.0625) * SWEEP_BYTES_PER_CELL
+            ach = per_cycle * 10 / (ms * 1e-3) / 1e9
+            out["roofline_batched_sweep"] = {
+                "bound": "hbm", "achieved": round(ach, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(ach / HBM_PEAK_GBS, 5), "kernel": "k_sgs4, one launch per stage and level over "
+                "all 64 cases", "avg_launch_us": round(1e3 * ms / max(cnt, 1), 3), "launches": cnt}
+        out[tag] = r
+        del b, sts
+    # converged solutions of the two precisions, cases that reached the drop in both
+    u64, u32 = finals["fp64"], finals["fp32_precond"]
+    both = [k for k in range(len(cases)) if status["fp64"][k] == 0 and status["fp32_precond"][k] == 0]
+    out["fp32_vs_fp64_max_rel_state_diff_converged"] = float(max(
+        (np.abs(u32[k] - u64[k]).max(axis=0) / np.abs(u64[k]).max(axis=0)).max() for k in both)) if both else None
+    out["fp32_vs_fp64_cases_compared"] = len(both)
+    # FP64 per-case loop: the iterates are bitwise those of the FP64 batch
+    # (same kernels, same order), so its time to the drop is the per-case
+    # cycle time times the batch's per-case cycle count
+    log("fp64 per-case loop (%s)" % ("full" if full_loop else "%d cycles per case" % loop_cycles))
+    t_loop = 0.0
+    per_case_ms = []
+    if full_loop:
+        t0 = time.perf_counter()
+        for (g, u0), c in zip(grids, cases):
+            st = fas.State(g, batch_params(fas, c, False), u0)
+            st.cycle(cap, 6.0)
+        torch.cuda.synchronize()
+        t_loop = time.perf_counter() - t0
+        out["fp64_per_case_loop"] = {"seconds": round(t_loop, 3), "measured": "full solve of every case"}
+    else:
+        for (g, u0), c in zip(grids, cases):
+            st = fas.State(g, batch_params(fas, c, False), u0)
+            st.cycle(2)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            st.cycle(loop_cycles)
+            torch.cuda.synchronize()
+            per_case_ms.append(1e3 * (time.perf_counter() - t0) / loop_cycles)
+        ms = np.array(per_case_ms)
+        t_loop = float((cycles["fp64"] * ms).sum() * 1e-3)
+        out["fp64_per_case_loop"] = {
+            "seconds": round(t_loop, 3),
+            "measured": "cycle time of every case over %d cycles after 2 warm-up cycles, times the "
+                        "case's cycle count to the drop (its iterates are bitwise those of the FP64 "
+                        "batch)" % loop_cycles,
+            "cell_cycles_per_s": round(float((cells * cycles["fp64"]).sum() / t_loop), 1)}
+    out["speedup_fp32_batch_vs_fp64_loop"] = round(t_loop / out["fp32_precond"]["seconds"], 2)
+    out["speedup_fp64_batch_vs_fp64_loop"] = round(t_loop / out["fp64"]["seconds"], 2)
+    return out
+
+
 def cpu_baseline(seconds_target=15.0):
     """The oracle (numpy + C sweep, single thread) on the first cycles of
     the same workload."""
@@ -169,6 +277,11 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--no-drop", action="store_true", help="skip the time-to-drop runs")
+    ap.add_argument("--no-batch", action="store_true", help="skip the 64-case batched section")
+    ap.add_argument("--batch-cap", type=int, default=1000)
+    ap.add_argument("--loop-cycles", type=int, default=20)
+    ap.add_argument("--full-loop", action="store_true",
+                    help="solve every case of the FP64 per-case loop to the drop (minutes)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only copy a 256 MiB buffer 5 times (HBM counter calibration)")
     args = ap.parse_args()
@@ -235,6 +348,9 @@ def main():
             "kernel_ms_per_step": {k: round(v[0] / max(r32["steps_done"], 1), 4)
                                    for k, v in r32["prof"].items()},
         }
+    if not args.no_batch:
+        line["batch_64_cases"] = batch_section(fas, torch, args.batch_cap, args.loop_cycles,
+                                               args.full_loop)
     if not args.no_cpu:
         log("cpu baseline (oracle)")
         line["cpu_baseline"] = cpu_baseline()

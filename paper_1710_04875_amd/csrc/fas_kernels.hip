@@ -92,11 +92,44 @@ __device__ inline void ld4(const double *a, int NS, int s, double v[4]) {
     for (int k = 0; k < 4; ++k) v[k] = a[k * NS + s];
 }
 
+// Pointers read from a descriptor in memory carry no address space, so the
+// compiler would access them with flat instructions, which also count on
+// the LDS wait counter (an LDS-only barrier would then drain every
+// prefetch in flight).  The descriptor is therefore read through a mirror
+// whose pointers are typed global, and every access derived from them
+// becomes a global load or store.
+#define FAS_GLOBAL __attribute__((address_space(1)))
+struct LevelDevG {
+    Lay L;
+    FAS_GLOBAL double *geo, *u, *u0, *acc, *F, *src, *ut, *un, *unm1, *dts, *mut, *cq, *vg;
+    FAS_GLOBAL char *blk, *g, *y;
+    FAS_GLOBAL double *red;
+};
+static_assert(sizeof(LevelDevG) == sizeof(LevelDev), "descriptor mirror layout");
+
 // the level descriptor of case c of a batched launch; false if the case is
 // inactive (the whole block then returns before any barrier)
 __device__ inline bool take(const BK &b, int c, LevelDev &d) {
     if (b.act != nullptr && b.act[c] == 0) return false;
-    d = b.V[c];
+    const LevelDevG &s = reinterpret_cast<const LevelDevG *>(b.V)[c];
+    d.L = s.L;
+    d.geo = (double *)s.geo;
+    d.u = (double *)s.u;
+    d.u0 = (double *)s.u0;
+    d.acc = (double *)s.acc;
+    d.F = (double *)s.F;
+    d.src = (double *)s.src;
+    d.ut = (double *)s.ut;
+    d.un = (double *)s.un;
+    d.unm1 = (double *)s.unm1;
+    d.dts = (double *)s.dts;
+    d.mut = (double *)s.mut;
+    d.cq = (double *)s.cq;
+    d.vg = (double *)s.vg;
+    d.blk = (void *)s.blk;
+    d.g = (void *)s.g;
+    d.y = (void *)s.y;
+    d.red = (double *)s.red;
     return true;
 }
 
@@ -1140,9 +1173,6 @@ __global__ __launch_bounds__(NT) void k_sgs4(BK bk, SweepArgs a) {
     const int ni = L.ni, nj = L.nj, NS = L.NS, NJ = L.NJ, nw = L.nw;
     const bool cutg = L.topo == 1;
     const int H = ni + nj - 1;
-    // a wave whose first row is beyond the case's rows (batches of uneven
-    // grids) issues no memory traffic; it only keeps the barrier count
-    const bool live = (t >> 6) * 16 * R < nj;
     for (int q = t; q < XS; q += NT) {
         xb[0][q] = (T)0;
         xb[1][q] = (T)0;
@@ -1177,7 +1207,6 @@ __global__ __launch_bounds__(NT) void k_sgs4(BK bk, SweepArgs a) {
     {
         T gA[D][R], wA[D][R][4], sA[D][R][4], gB[D][R], wB[D][R][4], sB[D][R][4];
         auto load = [&](T (&gg)[D][R], T (&ww)[D][R][4], T (&ss)[D][R][4], int hb) {
-            if (!live) return;
 #pragma unroll
             for (int k = 0; k < D; ++k) {
                 const int hc = hcl(hb + k) + 2 * NG;
@@ -1193,22 +1222,20 @@ __global__ __launch_bounds__(NT) void k_sgs4(BK bk, SweepArgs a) {
             }
         };
         auto step = [&](const T (&gv)[R], const T (&wv)[R][4], const T (&sv)[R][4], int h) {
-            if (live) {
-                const T *prev = xb[(h - 1) & 1];
-                T *cur = xb[h & 1];
-                T *yb = y + (size_t)(h + 2 * NG) * NJ;
+            const T *prev = xb[(h - 1) & 1];
+            T *cur = xb[h & 1];
+            T *yb = y + (size_t)(h + 2 * NG) * NJ;
 #pragma unroll
-                for (int q = 0; q < R; ++q) {
-                    const int jj = jq[q];
-                    const int i = h - jj;
-                    const T *xs = prev + 4 * jj;                        // row jj - 1 (guard row for jj = 0)
-                    if (jj == 0 && cutg && i >= ni - nw && i < ni) xs = row0 + (ni - 1 - i) * 4;
-                    const T v = (gv[q] - dot4(wv[q], prev + 4 * jj + 4)) - dot4(sv[q], xs);
-                    const bool valid = jj < nj && i >= 0 && i < ni;
-                    cur[4 * jj + 4 + r] = valid ? v : (T)0;
-                    *reinterpret_cast<T *>(reinterpret_cast<char *>(yb) + ow[q]) = v;
-                    if (valid && jj == 0 && cutg && i < nw) row0[i * 4 + r] = v;
-                }
+            for (int q = 0; q < R; ++q) {
+                const int jj = jq[q];
+                const int i = h - jj;
+                const T *xs = prev + 4 * jj;                        // row jj - 1 (guard row for jj = 0)
+                if (jj == 0 && cutg && i >= ni - nw && i < ni) xs = row0 + (ni - 1 - i) * 4;
+                const T v = (gv[q] - dot4(wv[q], prev + 4 * jj + 4)) - dot4(sv[q], xs);
+                const bool valid = jj < nj && i >= 0 && i < ni;
+                cur[4 * jj + 4 + r] = valid ? v : (T)0;
+                *reinterpret_cast<T *>(reinterpret_cast<char *>(yb) + ow[q]) = v;
+                if (valid && jj == 0 && cutg && i < nw) row0[i * 4 + r] = v;
             }
             lds_barrier();
         };
@@ -1237,7 +1264,6 @@ __global__ __launch_bounds__(NT) void k_sgs4(BK bk, SweepArgs a) {
         double uA[D][R], uB[D][R];
         const double *u0 = a.update ? dv.u0 : reinterpret_cast<const double *>(y);
         auto load = [&](T (&yy)[D][R], T (&ee)[D][R][4], T (&nn)[D][R][4], double (&u0r)[D][R], int hb) {
-            if (!live) return;
 #pragma unroll
             for (int k = 0; k < D; ++k) {
                 const int hc = hcl(H - 1 - (hb + k)) + 2 * NG;
@@ -1256,33 +1282,31 @@ __global__ __launch_bounds__(NT) void k_sgs4(BK bk, SweepArgs a) {
         };
         auto step = [&](const T (&yv)[R], const T (&ev)[R][4], const T (&nv)[R][4], const double (&u0v)[R],
                         int h) {
-            if (live) {
-                const T *prev = xb[(h + 1) & 1];
-                T *cur = xb[h & 1];
-                const size_t hs = (size_t)(h + 2 * NG) * NJ;
+            const T *prev = xb[(h + 1) & 1];
+            T *cur = xb[h & 1];
+            const size_t hs = (size_t)(h + 2 * NG) * NJ;
 #pragma unroll
-                for (int q = 0; q < R; ++q) {
-                    const int jj = jq[q];
-                    const int i = h - jj;
-                    T v = (yv[q] - dot4(ev[q], prev + 4 * jj + 4)) - dot4(nv[q], prev + 4 * jj + 8);
-                    if (jj == 0 && cutg && i >= 0 && i < nw) {
-                        T mp[4];
+            for (int q = 0; q < R; ++q) {
+                const int jj = jq[q];
+                const int i = h - jj;
+                T v = (yv[q] - dot4(ev[q], prev + 4 * jj + 4)) - dot4(nv[q], prev + 4 * jj + 8);
+                if (jj == 0 && cutg && i >= 0 && i < nw) {
+                    T mp[4];
 #pragma unroll
-                        for (int c = 0; c < 4; ++c) mp[c] = pblk[i * 16 + r * 4 + c];
-                        v = v - dot4(mp, row0 + (ni - 1 - i - (ni - nw)) * 4);
-                    }
-                    const bool valid = jj < nj && i >= 0 && i < ni;
-                    cur[4 * jj + 4 + r] = valid ? v : (T)0;
-                    if (valid && jj == 0 && cutg && i >= ni - nw) row0[(i - (ni - nw)) * 4 + r] = v;
-                    const unsigned ew = ow[q] / sizeof(T) * sizeof(double);
-                    if (xout)
-                        *reinterpret_cast<double *>(reinterpret_cast<char *>(xout + hs) + ew) = (double)v;
-                    if (a.update) {
-                        double un;
-                        if (a.aw) un = u0v[q] - a.alpha * (double)v;
-                        else un = u0v[q] - a.alpha * (dts[hs + (jj < nj ? jj : nj) + NG] * (double)v);
-                        *reinterpret_cast<double *>(reinterpret_cast<char *>(uu + hs) + ew) = un;
-                    }
+                    for (int c = 0; c < 4; ++c) mp[c] = pblk[i * 16 + r * 4 + c];
+                    v = v - dot4(mp, row0 + (ni - 1 - i - (ni - nw)) * 4);
+                }
+                const bool valid = jj < nj && i >= 0 && i < ni;
+                cur[4 * jj + 4 + r] = valid ? v : (T)0;
+                if (valid && jj == 0 && cutg && i >= ni - nw) row0[(i - (ni - nw)) * 4 + r] = v;
+                const unsigned ew = ow[q] / sizeof(T) * sizeof(double);
+                if (xout)
+                    *reinterpret_cast<double *>(reinterpret_cast<char *>(xout + hs) + ew) = (double)v;
+                if (a.update) {
+                    double un;
+                    if (a.aw) un = u0v[q] - a.alpha * (double)v;
+                    else un = u0v[q] - a.alpha * (dts[hs + (jj < nj ? jj : nj) + NG] * (double)v);
+                    *reinterpret_cast<double *>(reinterpret_cast<char *>(uu + hs) + ew) = un;
                 }
             }
             lds_barrier();
