@@ -203,6 +203,43 @@ fas_status fas_batch_set_sweep_config(fas_batch b, int32_t level, int32_t cfg);
 fas_status fas_batch_profile(fas_batch b, int32_t enable);
 fas_status fas_batch_profile_read(fas_batch b, double *ms, int64_t *count);
 
+/*
+ * Discrete adjoint of the steady fine-level residual F(u) (Section 2
+ * discretisation; eq. "nonlin-eq-steady").  Derivatives are exact
+ * derivatives of the discrete F with the eddy viscosity frozen at the
+ * current state (frozen-turbulence adjoint); they do not include the
+ * Baldwin-Lomax model's own dependence on u.  All arrays are device
+ * [4][nj][ni] on the fine level.
+ *
+ * fas_forces: lift and drag coefficients of the wall pressure force of
+ * the current solution (the residual's wall flux p_w S summed over the
+ * solid-wall faces, q_inf = rho_inf |v_inf|^2 / 2, chord 1; host values),
+ * and, if dcl_du is not NULL, dC_L/du.
+ * fas_vjp: out = (dF/du)^T lam.
+ * fas_param_partials: dF/dalpha (per degree) and dF/dM at fixed u (either
+ * may be NULL), and dcl_dparam (host [2], may be NULL): the explicit
+ * partials of C_L with respect to alpha (per degree) and M at fixed u.
+ * fas_sgs_apply_transpose: x = P^-T r for the SGS preconditioner built at
+ * the current state (transpose of fas_sgs_apply).
+ * fas_adjoint_solve: (dF/du)^T lam = rhs by the transposed smoother (the
+ * stages of the state's scheme with the transposed increments), starting
+ * from lam (in/out), until the RMS of the adjoint residual has dropped by
+ * drop_orders or max_iter iterations ran; res_hist (host, may be NULL,
+ * max_iter + 1 entries).  Returns FAS_OK, FAS_NOT_CONVERGED or
+ * FAS_DIVERGED.
+ * fas_lift_gradient: at a converged state, dC_L/dalpha (per degree) and
+ * dC_L/dM into grad (host [2]) by the adjoint, dC_L/dq = dC_L/dq|_u +
+ * lam^T dF/dq with (dF/du)^T lam = -dC_L/du; cl (host, may be NULL).
+ */
+fas_status fas_forces(fas_state s, double *cl, double *cd, double *dcl_du);
+fas_status fas_vjp(fas_state s, const double *lam, double *out);
+fas_status fas_param_partials(fas_state s, double *dF_dalpha, double *dF_dmach, double *dcl_dparam);
+fas_status fas_sgs_apply_transpose(fas_state s, const double *r, double *x);
+fas_status fas_adjoint_solve(fas_state s, const double *rhs, double *lam, int32_t max_iter,
+                             double drop_orders, double *res_hist, int32_t *n_iter);
+fas_status fas_lift_gradient(fas_state s, int32_t max_iter, double drop_orders, double *cl,
+                             double *grad, double *res_hist, int32_t *n_iter);
+
 /* Message of the last failing call on this thread (never NULL). */
 const char *fas_last_error(void);
 

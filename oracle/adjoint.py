@@ -1,0 +1,121 @@
+"""Discrete adjoint of the steady fine-level residual (test infrastructure).
+
+Everything here is differentiated by the complex step: F(u + i h e)
+carries h dF/du e in its imaginary part to rounding accuracy, so the dense
+Jacobian and the parameter derivatives below are exact derivatives of the
+oracle's own discrete residual, not finite-difference approximations.
+
+Readings (the paper states no adjoint):
+* the functional is the lift (and drag) coefficient of the pressure force
+  on the solid wall, with the wall pressure the residual itself uses (the
+  mean of the wall cell and its ghost), force = -sum p_w S over the wall
+  faces (S points into the fluid), q_inf = rho_inf |v_inf|^2 / 2, chord 1;
+* the eddy viscosity is frozen at the state (frozen-turbulence adjoint):
+  the Baldwin-Lomax field is evaluated once at the real state and is not
+  differentiated;
+* the adjoint equation is (dF/du)^T lambda = -dJ/du and the gradient of J
+  with respect to a flow parameter q is dJ/dq = dJ/dq|_u + lambda^T dF/dq.
+
+Vector layout: component-major flattening of (4, nj, ni) arrays.
+"""
+from __future__ import annotations
+
+import dataclasses
+
+import numpy as np
+
+from . import gas
+from .bc import fill_ghosts
+from .geometry import NG
+from .residual import baldwin_lomax, padded_eddy_viscosity, split_residual
+
+H_CS = 1.0e-30
+
+
+def _padded(S, u, uinf):
+    lev = S.levels[0]
+    Up = np.zeros((4, lev.nj + 2 * NG, lev.ni + 2 * NG), dtype=np.result_type(u, uinf))
+    Up[:, NG:NG + lev.nj, NG:NG + lev.ni] = u
+    fill_ghosts(Up, lev, uinf, noslip=S.par.model == 1)
+    return Up
+
+
+def frozen_mut(S, u):
+    """Padded eddy viscosity at the (real) state u, or None for Euler."""
+    if S.par.model != 1:
+        return None
+    lev = S.levels[0]
+    return padded_eddy_viscosity(lev, baldwin_lomax(lev, _padded(S, u, S.uinf), S.par))
+
+
+def fine_residual(S, u, mutp, mach=None, alpha_deg=None):
+    """Steady fine-level F(u) (no forcing, no time term) with the frozen eddy
+    viscosity mutp; u, mach and alpha may be complex."""
+    mach = S.par.mach if mach is None else mach
+    alpha_deg = S.par.alpha_deg if alpha_deg is None else alpha_deg
+    par = dataclasses.replace(S.par, mach=mach, alpha_deg=alpha_deg)
+    uinf = gas.freestream(mach, alpha_deg)
+    Up = _padded(S, u, uinf)
+    Fc, Fv = split_residual(S.levels[0], Up, par, True, mutp, None, None)
+    return Fc + Fv
+
+
+def forces(S, u, mach=None, alpha_deg=None):
+    """(C_L, C_D) of the wall pressure force of state u."""
+    mach = S.par.mach if mach is None else mach
+    alpha_deg = S.par.alpha_deg if alpha_deg is None else alpha_deg
+    lev = S.levels[0]
+    Up = _padded(S, u, gas.freestream(mach, alpha_deg))
+    p = gas.pressure(Up)
+    cols = slice(NG, NG + lev.ni)
+    pw = 0.5 * (p[NG - 1, cols] + p[NG, cols])
+    wall = ~lev.cut_mask()
+    fx = -np.sum((pw * lev.Seta[0][0])[wall])
+    fy = -np.sum((pw * lev.Seta[1][0])[wall])
+    a = alpha_deg * (np.pi / 180.0)
+    q = 0.5 * (mach * mach * gas.GAMMA)
+    cl = (fy * np.cos(a) - fx * np.sin(a)) / q
+    cd = (fx * np.cos(a) + fy * np.sin(a)) / q
+    return cl, cd
+
+
+def dense_jacobian(S, u, mutp):
+    """dF/du (4N x 4N) at u, column by column."""
+    n = u.size
+    J = np.empty((n, n))
+    flat = u.reshape(-1)
+    for k in range(n):
+        uc = flat.astype(complex)
+        uc[k] += 1j * H_CS
+        J[:, k] = fine_residual(S, uc.reshape(u.shape), mutp).imag.reshape(-1) / H_CS
+    return J
+
+
+def residual_param_partials(S, u, mutp):
+    """(dF/dalpha_deg, dF/dmach) at fixed u, as (4, nj, ni) arrays."""
+    da = fine_residual(S, u, mutp, alpha_deg=S.par.alpha_deg + 1j * H_CS).imag / H_CS
+    dm = fine_residual(S, u, mutp, mach=S.par.mach + 1j * H_CS).imag / H_CS
+    return da, dm
+
+
+def lift_partials(S, u):
+    """(dC_L/du as (4, nj, ni), dC_L/dalpha_deg, dC_L/dmach) at fixed u."""
+    flat = u.reshape(-1)
+    g = np.empty(flat.size)
+    for k in range(flat.size):
+        uc = flat.astype(complex)
+        uc[k] += 1j * H_CS
+        g[k] = forces(S, uc.reshape(u.shape))[0].imag / H_CS
+    da = forces(S, u, alpha_deg=S.par.alpha_deg + 1j * H_CS)[0].imag / H_CS
+    dm = forces(S, u, mach=S.par.mach + 1j * H_CS)[0].imag / H_CS
+    return g.reshape(u.shape), da, dm
+
+
+def lift_gradient(S, u):
+    """dC_L/d(alpha_deg, mach) at a converged state u by the dense adjoint."""
+    mutp = frozen_mut(S, u)
+    J = dense_jacobian(S, u, mutp)
+    g, cla, clm = lift_partials(S, u)
+    lam = np.linalg.solve(J.T, -g.reshape(-1))
+    da, dm = residual_param_partials(S, u, mutp)
+    return (cla + lam @ da.reshape(-1), clm + lam @ dm.reshape(-1)), lam.reshape(u.shape)

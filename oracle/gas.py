@@ -26,7 +26,7 @@ def freestream(mach: float, alpha_deg: float):
     |v| = M sqrt(gamma); this scaling reproduces the paper's physical time
     step 0.486822 (Section 6.4) for M = 0.75, k = 0.202, 36 steps."""
     V = mach * np.sqrt(GAMMA)
-    a = np.deg2rad(alpha_deg)
+    a = alpha_deg * (np.pi / 180.0)
     vx = V * np.cos(a)
     vy = V * np.sin(a)
     E = 1.0 / (GAMMA - 1.0) + 0.5 * (vx * vx + vy * vy)

@@ -24,9 +24,10 @@ Paper passages followed:
   Reading: Sutherland's law for mu, Pr_t = 0.9.
 * Section 2, Baldwin-Lomax algebraic eddy viscosity, standard constants of
   the cited model (A+ = 26, C_cp = 1.6, C_kleb = 0.3, C_wk = 0.25,
-  kappa = 0.4, K = 0.0168), fine level only.
+  kappa = 0.4, K = 0.0168), evaluated on the fine level.
 * Section 3: coarse levels use a first-order JST flux (no fourth
-  difference, no sensor): eps2 = kappa2c * r (reading, kappa2c = 0.25).
+  difference, no sensor): eps2 = kappa2c * r (reading, kappa2c = 0.125);
+  they keep the viscous flux with the restricted eddy viscosity (reading).
 * Section 4.1, eq. "split-rhs": f^c holds the convective fluxes, the
   physical time derivative and the multigrid source; f^v the artificial
   dissipation and the viscous terms.
@@ -45,6 +46,23 @@ SUTH = 110.4 / 288.15
 BL_APLUS, BL_CCP, BL_CKLEB, BL_CWK, BL_KAPPA, BL_K = 26.0, 1.6, 0.3, 0.25, 0.4, 0.0168
 
 
+def _abs(x):
+    """|x|; for complex arguments (complex-step differentiation) the value
+    times the sign of its real part, which carries the derivative."""
+    if np.iscomplexobj(x):
+        return np.where(x.real < 0.0, -x, x)
+    return np.abs(x)
+
+
+def _cbrt(x):
+    """Real cube root; for complex arguments its first-order extension
+    cbrt(a) + i b / (3 cbrt(a)^2) (complex-step differentiation)."""
+    if np.iscomplexobj(x):
+        c = np.cbrt(x.real)
+        return c + 1j * (x.imag / (3.0 * c * c))
+    return np.cbrt(x)
+
+
 def sutherland(T, mu_inf):
     return ((mu_inf * (T * np.sqrt(T))) * (1.0 + SUTH)) / (T + SUTH)
 
@@ -59,12 +77,12 @@ def cell_scalars(lev, Up, rans: bool):
     a = np.sqrt(GAMMA * p / rho)
     q = p / rho ** GAMMA if rans else p
     sb = lev.sbar
-    rxi = np.abs(vx * sb[0] + vy * sb[1]) + a * np.sqrt(sb[0] * sb[0] + sb[1] * sb[1])
-    reta = np.abs(vx * sb[2] + vy * sb[3]) + a * np.sqrt(sb[2] * sb[2] + sb[3] * sb[3])
+    rxi = _abs(vx * sb[0] + vy * sb[1]) + a * np.sqrt(sb[0] * sb[0] + sb[1] * sb[1])
+    reta = _abs(vx * sb[2] + vy * sb[3]) + a * np.sqrt(sb[2] * sb[2] + sb[3] * sb[3])
     t = reta / rxi
-    rtxi = rxi * (1.0 + np.cbrt(t * t))
+    rtxi = rxi * (1.0 + _cbrt(t * t))
     t = rxi / reta
-    rteta = reta * (1.0 + np.cbrt(t * t))
+    rteta = reta * (1.0 + _cbrt(t * t))
     return p, q, rxi, reta, rtxi, rteta
 
 
@@ -80,7 +98,7 @@ def local_time_step(lev, Up, cfl: float):
 def _sensor(q_m, q_0, q_p):
     num = (q_p - 2.0 * q_0) + q_m
     den = ((q_p + 2.0 * q_0) + q_m) + 0.001
-    return np.abs(num / den)
+    return _abs(num / den)
 
 
 def _face_dissipation(wLL, wL, wR, wRR, sL, sR, rL, rR, second_order: bool, kappa2c: float):

@@ -12,7 +12,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libfas.so")
-SOURCES = ["fas_kernels.hip", "fas_api.hip"]
+SOURCES = ["fas_kernels.hip", "fas_adjoint.hip", "fas_api.hip"]
 FLAGS = [
     "-O3", "--offload-arch=gfx950", "-std=c++17", "-fPIC",
     # identical rounding to the oracle wherever a formula is shared: no

@@ -1,0 +1,849 @@
+// HIP kernels (gfx950) of the discrete adjoint of the steady fine-level
+// residual: vector-Jacobian products, parameter derivatives, the wall
+// force and its gradient, and the transposed SGS preconditioner.
+//
+// Derivatives are exact derivatives of the discrete residual (Section 2:
+// JST flux, viscous flux, boundary conditions), taken by forward-mode dual
+// numbers on a cell's local stencil, with the eddy viscosity frozen at the
+// state.  Layout: fas_internal.h.
+#include "fas_internal.h"
+
+#include <cmath>
+
+namespace fas {
+
+namespace {
+
+constexpr int TPB = 256;
+constexpr double SUTH = 110.4 / 288.15;
+inline int nblocks(int n, int t = TPB) { return (n + t - 1) / t; }
+
+// ------------------------------------------------------------- dual numbers
+// value and four derivative lanes
+struct D4 {
+    double v, d[4];
+};
+
+__device__ inline D4 dc(double v) { return D4{v, {0.0, 0.0, 0.0, 0.0}}; }
+__device__ inline D4 operator+(const D4 &a, const D4 &b) {
+    return D4{a.v + b.v, {a.d[0] + b.d[0], a.d[1] + b.d[1], a.d[2] + b.d[2], a.d[3] + b.d[3]}};
+}
+__device__ inline D4 operator-(const D4 &a, const D4 &b) {
+    return D4{a.v - b.v, {a.d[0] - b.d[0], a.d[1] - b.d[1], a.d[2] - b.d[2], a.d[3] - b.d[3]}};
+}
+__device__ inline D4 operator-(const D4 &a) { return D4{-a.v, {-a.d[0], -a.d[1], -a.d[2], -a.d[3]}}; }
+__device__ inline D4 operator*(const D4 &a, const D4 &b) {
+    D4 r;
+    r.v = a.v * b.v;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) r.d[k] = a.d[k] * b.v + a.v * b.d[k];
+    return r;
+}
+__device__ inline D4 operator/(const D4 &a, const D4 &b) {
+    D4 r;
+    r.v = a.v / b.v;
+    const double ib = 1.0 / b.v;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) r.d[k] = (a.d[k] - r.v * b.d[k]) * ib;
+    return r;
+}
+__device__ inline D4 operator*(double s, const D4 &a) {
+    return D4{s * a.v, {s * a.d[0], s * a.d[1], s * a.d[2], s * a.d[3]}};
+}
+__device__ inline D4 operator*(const D4 &a, double s) { return s * a; }
+__device__ inline D4 operator+(const D4 &a, double s) { return D4{a.v + s, {a.d[0], a.d[1], a.d[2], a.d[3]}}; }
+__device__ inline D4 operator+(double s, const D4 &a) { return a + s; }
+__device__ inline D4 operator-(const D4 &a, double s) { return D4{a.v - s, {a.d[0], a.d[1], a.d[2], a.d[3]}}; }
+__device__ inline D4 operator-(double s, const D4 &a) { return dc(s) - a; }
+__device__ inline D4 operator/(const D4 &a, double s) { return a * (1.0 / s); }
+__device__ inline D4 chain(const D4 &a, double f, double df) {
+    return D4{f, {df * a.d[0], df * a.d[1], df * a.d[2], df * a.d[3]}};
+}
+__device__ inline D4 dsqrt(const D4 &a) {
+    const double r = sqrt(a.v);
+    return chain(a, r, 0.5 / r);
+}
+__device__ inline D4 dcbrt(const D4 &a) {
+    const double r = cbrt(a.v);
+    return chain(a, r, 1.0 / (3.0 * r * r));
+}
+__device__ inline D4 dpow(const D4 &a, double e) {
+    const double r = pow(a.v, e);
+    return chain(a, r, e * pow(a.v, e - 1.0));
+}
+__device__ inline D4 dabs(const D4 &a) { return a.v < 0.0 ? -a : a; }
+__device__ inline D4 dmax(const D4 &a, const D4 &b) { return (b.v > a.v) ? b : a; }
+__device__ inline D4 dmin(const D4 &a, const D4 &b) { return (b.v < a.v) ? b : a; }
+
+// --------------------------------------------------------------- geometry
+__device__ inline bool decode(const Lay &L, int s, int &i, int &j) {
+    if (s >= L.NS) return false;
+    int H = s / L.NJ;
+    int J = s - H * L.NJ;
+    int I = H - J;
+    if (I < 0 || I >= L.NI) return false;
+    i = I - NG;
+    j = J - NG;
+    return true;
+}
+__device__ inline bool interior(const Lay &L, int i, int j) {
+    return i >= 0 && i < L.ni && j >= 0 && j < L.nj;
+}
+__device__ inline bool cut_col(const Lay &L, int i) {
+    return L.topo == 1 && (i < L.nw || i >= L.ni - L.nw);
+}
+
+// --------------------------------------------- local residual, dual numbers
+// Everything a cell's residual needs is rebuilt from the interior states of
+// its stencil: ghost states through the boundary conditions, pressure,
+// sensor and spectral radii, vertex gradients.  Interior cell (si, sj)
+// carries the derivative seed (lane k = d/du_k of that cell); the far-field
+// state may carry parameter lanes instead.
+struct Ctx {
+    Lay L;
+    const double *geo, *u, *mut;
+    D4 uinf[4];
+    D4 mu_inf;
+    double pr, prt, kappa2c;
+    int rans, noslip, fine, viscous;
+    int si, sj;
+};
+
+__device__ inline void cell_u(const Ctx &c, int i, int j, D4 o[4]) {
+    const int s = c.L.slot(i, j), NS = c.L.NS;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) o[k] = dc(c.u[k * NS + s]);
+    if (i == c.si && j == c.sj) {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) o[k].d[k] = 1.0;
+    }
+}
+
+__device__ inline D4 dpres(const D4 U[4]) {
+    return (GAM - 1.0) * (U[3] - 0.5 * (U[1] * U[1] + U[2] * U[2]) / U[0]);
+}
+
+__device__ inline void unit(double sx, double sy, double &nx, double &ny) {
+    double ln = sqrt(sx * sx + sy * sy);
+    nx = sx / ln;
+    ny = sy / ln;
+}
+
+// Riemann-invariant far-field state (Section 2)
+__device__ void farfield(const D4 ui[4], const D4 uf[4], double nx, double ny, D4 out[4]) {
+    const double g1 = GAM - 1.0;
+    D4 rho = ui[0];
+    D4 vx = ui[1] / rho, vy = ui[2] / rho;
+    D4 p = dpres(ui);
+    D4 a = dsqrt(GAM * p / rho);
+    D4 rinf = uf[0];
+    D4 vxf = uf[1] / rinf, vyf = uf[2] / rinf;
+    D4 pf = dpres(uf);
+    D4 af = dsqrt(GAM * pf / rinf);
+    D4 vn = vx * nx + vy * ny;
+    D4 vnf = vxf * nx + vyf * ny;
+    D4 rp = vn + 2.0 * a / g1;
+    D4 rm = vnf - 2.0 * af / g1;
+    D4 vnb = 0.5 * (rp + rm);
+    D4 ab = 0.25 * g1 * (rp - rm);
+    const bool outf = vnb.v > 0.0;
+    D4 sent = outf ? p / dpow(rho, GAM) : pf / dpow(rinf, GAM);
+    D4 tx = outf ? vx - vn * nx : vxf - vnf * nx;
+    D4 ty = outf ? vy - vn * ny : vyf - vnf * ny;
+    D4 base = ab * ab / (GAM * sent);
+    D4 rhob = base * base * dsqrt(base);
+    D4 pb = rhob * ab * ab / GAM;
+    D4 ub = tx + vnb * nx, vb = ty + vnb * ny;
+    out[0] = rhob;
+    out[1] = rhob * ub;
+    out[2] = rhob * vb;
+    out[3] = pb / g1 + 0.5 * rhob * (ub * ub + vb * vb);
+}
+
+// state of (i, j): i interior, j in [-2, nj + 2)
+__device__ void jrow(const Ctx &c, int i, int j, D4 o[4]) {
+    const Lay &L = c.L;
+    const int NS = L.NS;
+    if (j >= 0 && j < L.nj) {
+        cell_u(c, i, j, o);
+        return;
+    }
+    if (j < 0) {
+        const int k = -1 - j;
+        if (cut_col(L, i)) {
+            cell_u(c, L.ni - 1 - i, k, o);
+            return;
+        }
+        D4 ui[4];
+        cell_u(c, i, k, ui);
+        if (c.noslip) {
+            o[0] = ui[0];
+            o[1] = -ui[1];
+            o[2] = -ui[2];
+            o[3] = ui[3];
+        } else {
+            const int f = L.slot(i, 0);
+            double nx, ny;
+            unit(c.geo[G_SETA_X * NS + f], c.geo[G_SETA_Y * NS + f], nx, ny);
+            D4 mn = ui[1] * nx + ui[2] * ny;
+            o[0] = ui[0];
+            o[1] = ui[1] - 2.0 * mn * nx;
+            o[2] = ui[2] - 2.0 * mn * ny;
+            o[3] = ui[3];
+        }
+        return;
+    }
+    const int k = j - L.nj;
+    D4 ui[4];
+    cell_u(c, i, L.nj - 1 - k, ui);
+    const int f = L.slot(i, L.nj);
+    double nx, ny;
+    unit(c.geo[G_SETA_X * NS + f], c.geo[G_SETA_Y * NS + f], nx, ny);
+    farfield(ui, c.uinf, nx, ny, o);
+}
+
+// state of any padded cell (i, j), i and j in [-2, n + 2)
+__device__ void state(const Ctx &c, int i, int j, D4 o[4]) {
+    const Lay &L = c.L;
+    if (i >= 0 && i < L.ni) {
+        jrow(c, i, j, o);
+        return;
+    }
+    const int NS = L.NS;
+    const int jc = min(max(j, 0), L.nj - 1);
+    D4 src[4];
+    double nx, ny;
+    if (i < 0) {
+        jrow(c, -1 - i, j, src);
+        const int f = L.slot(0, jc);
+        unit(-c.geo[G_SXI_X * NS + f], -c.geo[G_SXI_Y * NS + f], nx, ny);
+    } else {
+        jrow(c, L.ni - 1 - (i - L.ni), j, src);
+        const int f = L.slot(L.ni, jc);
+        unit(c.geo[G_SXI_X * NS + f], c.geo[G_SXI_Y * NS + f], nx, ny);
+    }
+    farfield(src, c.uinf, nx, ny, o);
+}
+
+// interior cell whose state a padded cell's state is built from
+__device__ void source_of(const Lay &L, int i, int j, int &si, int &sj) {
+    if (i < 0) i = -1 - i;
+    else if (i >= L.ni) i = L.ni - 1 - (i - L.ni);
+    if (j >= 0 && j < L.nj) {
+        si = i;
+        sj = j;
+    } else if (j < 0) {
+        const int k = -1 - j;
+        si = cut_col(L, i) ? L.ni - 1 - i : i;
+        sj = k;
+    } else {
+        si = i;
+        sj = L.nj - 1 - (j - L.nj);
+    }
+}
+
+struct CQ {
+    D4 U[4], p, q, rxi, reta, T;
+};
+
+// Section 2: pressure, sensor quantity, corrected spectral radii, p / rho
+__device__ void cell_q(const Ctx &c, int i, int j, CQ &o) {
+    state(c, i, j, o.U);
+    const int s = c.L.slot(i, j), NS = c.L.NS;
+    const D4 &r = o.U[0];
+    D4 vx = o.U[1] / r, vy = o.U[2] / r;
+    o.p = dpres(o.U);
+    D4 a = dsqrt(GAM * o.p / r);
+    o.q = c.rans ? o.p / dpow(r, GAM) : o.p;
+    const double sb0 = c.geo[G_SB0 * NS + s], sb1 = c.geo[G_SB1 * NS + s];
+    const double sb2 = c.geo[G_SB2 * NS + s], sb3 = c.geo[G_SB3 * NS + s];
+    D4 rxi = dabs(vx * sb0 + vy * sb1) + a * sqrt(sb0 * sb0 + sb1 * sb1);
+    D4 reta = dabs(vx * sb2 + vy * sb3) + a * sqrt(sb2 * sb2 + sb3 * sb3);
+    D4 t = reta / rxi;
+    o.rxi = rxi * (1.0 + dcbrt(t * t));
+    t = rxi / reta;
+    o.reta = reta * (1.0 + dcbrt(t * t));
+    o.T = o.p / r;
+}
+
+// Green-Gauss gradients of (u, v, T) at vertex (I, J) over the four cell
+// centres SW, SE, NE, NW
+__device__ void vertex_grad(const Ctx &c, int I, int J, D4 g[6]) {
+    const int NS = c.L.NS;
+    const int ci[4] = {I - 1, I, I, I - 1}, cj[4] = {J - 1, J - 1, J, J};
+    double X[4], Y[4];
+    D4 U[4], V[4], T[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const int s = c.L.slot(ci[k], cj[k]);
+        X[k] = c.geo[G_XC * NS + s];
+        Y[k] = c.geo[G_YC * NS + s];
+        D4 st[4];
+        state(c, ci[k], cj[k], st);
+        U[k] = st[1] / st[0];
+        V[k] = st[2] / st[0];
+        T[k] = dpres(st) / st[0];
+    }
+    const double A = 0.5 * ((X[2] - X[0]) * (Y[3] - Y[1]) - (Y[2] - Y[0]) * (X[3] - X[1]));
+    const D4 *phi[3] = {U, V, T};
+#pragma unroll
+    for (int f = 0; f < 3; ++f) {
+        D4 gx = dc(0.0), gy = dc(0.0);
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const int a = e, b = (e + 1) & 3;
+            D4 m = 0.5 * (phi[f][a] + phi[f][b]);
+            D4 tx = m * (Y[b] - Y[a]);
+            D4 ty = m * (X[a] - X[b]);
+            if (e == 0) {
+                gx = tx;
+                gy = ty;
+            } else {
+                gx = gx + tx;
+                gy = gy + ty;
+            }
+        }
+        g[2 * f] = gx / A;
+        g[2 * f + 1] = gy / A;
+    }
+}
+
+__device__ inline D4 dsutherland(const D4 &T, const D4 &mu_inf) {
+    return ((mu_inf * (T * dsqrt(T))) * (1.0 + SUTH)) / (T + SUTH);
+}
+
+// JST face flux (central C, dissipation / viscous V) between L and R with
+// outer neighbours LL and RR (Section 2), as in the primal residual
+__device__ void face(const Ctx &c, int iL, int jL, int iR, int jR, int iLL, int jLL, int iRR, int jRR,
+                     bool xi_face, double sx, double sy, bool wall, int vAi, int vAj, int vBi, int vBj,
+                     D4 C[4], D4 V[4]) {
+    CQ L, R;
+    cell_q(c, iL, jL, L);
+    cell_q(c, iR, jR, R);
+    if (wall) {
+        D4 pw = 0.5 * (L.p + R.p);
+        C[0] = dc(0.0);
+        C[1] = pw * sx;
+        C[2] = pw * sy;
+        C[3] = dc(0.0);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) V[k] = dc(0.0);
+    } else {
+        D4 qsL = L.U[1] * sx + L.U[2] * sy, vsL = qsL / L.U[0];
+        D4 qsR = R.U[1] * sx + R.U[2] * sy, vsR = qsR / R.U[0];
+        D4 FL[4] = {qsL, L.U[1] * vsL + L.p * sx, L.U[2] * vsL + L.p * sy, (L.U[3] + L.p) * vsL};
+        D4 FR[4] = {qsR, R.U[1] * vsR + R.p * sx, R.U[2] * vsR + R.p * sy, (R.U[3] + R.p) * vsR};
+#pragma unroll
+        for (int k = 0; k < 4; ++k) C[k] = 0.5 * (FL[k] + FR[k]);
+        D4 rf = xi_face ? dmax(L.rxi, R.rxi) : dmax(L.reta, R.reta);
+        D4 wL[4] = {L.U[0], L.U[1], L.U[2], L.U[3] + L.p};
+        D4 wR[4] = {R.U[0], R.U[1], R.U[2], R.U[3] + R.p};
+        D4 d[4];
+        if (c.fine) {
+            CQ LL, RR;
+            cell_q(c, iLL, jLL, LL);
+            cell_q(c, iRR, jRR, RR);
+            D4 sLs = dabs(((R.q - 2.0 * L.q) + LL.q) / (((R.q + 2.0 * L.q) + LL.q) + 0.001));
+            D4 sRs = dabs(((RR.q - 2.0 * R.q) + L.q) / (((RR.q + 2.0 * R.q) + L.q) + 0.001));
+            D4 sf = dmin(dc(0.25), dmax(sLs, sRs));
+            D4 e2 = sf * rf;
+            D4 e4 = dmax(dc(0.0), rf / 32.0 - 2.0 * e2);
+            D4 wLL[4] = {LL.U[0], LL.U[1], LL.U[2], LL.U[3] + LL.p};
+            D4 wRR[4] = {RR.U[0], RR.U[1], RR.U[2], RR.U[3] + RR.p};
+#pragma unroll
+            for (int k = 0; k < 4; ++k)
+                d[k] = e2 * (wR[k] - wL[k]) - e4 * (((wRR[k] - 3.0 * wR[k]) + 3.0 * wL[k]) - wLL[k]);
+        } else {
+            D4 e2 = c.kappa2c * rf;
+#pragma unroll
+            for (int k = 0; k < 4; ++k) d[k] = e2 * (wR[k] - wL[k]);
+        }
+#pragma unroll
+        for (int k = 0; k < 4; ++k) V[k] = -d[k];
+    }
+    if (c.viscous) {
+        D4 gA[6], gB[6];
+        vertex_grad(c, vAi, vAj, gA);
+        vertex_grad(c, vBi, vBj, gB);
+        D4 fux = 0.5 * (gA[0] + gB[0]), fuy = 0.5 * (gA[1] + gB[1]);
+        D4 fwx = 0.5 * (gA[2] + gB[2]), fwy = 0.5 * (gA[3] + gB[3]);
+        D4 fTx = 0.5 * (gA[4] + gB[4]), fTy = 0.5 * (gA[5] + gB[5]);
+        D4 fvx = 0.5 * (L.U[1] / L.U[0] + R.U[1] / R.U[0]);
+        D4 fvy = 0.5 * (L.U[2] / L.U[0] + R.U[2] / R.U[0]);
+        D4 fT = 0.5 * (L.T + R.T);
+        D4 mu = dsutherland(fT, c.mu_inf);
+        const int sL = c.L.slot(iL, jL), sR = c.L.slot(iR, jR);
+        const double mt = 0.5 * (c.mut[sL] + c.mut[sR]);
+        D4 mue = mu + mt;
+        D4 kc = (mu / c.pr + mt / c.prt) * (GAM / (GAM - 1.0));
+        D4 div = fux + fwy;
+        D4 txx = mue * (2.0 * fux - (2.0 / 3.0) * div);
+        D4 tyy = mue * (2.0 * fwy - (2.0 / 3.0) * div);
+        D4 txy = mue * (fuy + fwx);
+        D4 qx = kc * fTx, qy = kc * fTy;
+        D4 G1 = txx * sx + txy * sy;
+        D4 G2 = txy * sx + tyy * sy;
+        D4 G3 = ((fvx * txx + fvy * txy) + qx) * sx + ((fvx * txy + fvy * tyy) + qy) * sy;
+        V[1] = V[1] - G1;
+        V[2] = V[2] - G2;
+        V[3] = V[3] - G3;
+    }
+}
+
+// F of interior cell (i, j) per unit volume (steady, no forcing)
+__device__ void cell_residual(const Ctx &c, int i, int j, D4 F[4]) {
+    const Lay &L = c.L;
+    const int NS = L.NS, s = L.slot(i, j), NJ = L.NJ;
+    const double *g = c.geo;
+    D4 wC[4], wV[4], eC[4], eV[4], sC[4], sV[4], nC[4], nV[4];
+    face(c, i - 1, j, i, j, i - 2, j, i + 1, j, true, g[G_SXI_X * NS + s], g[G_SXI_Y * NS + s], false,
+         i, j, i, j + 1, wC, wV);
+    face(c, i, j, i + 1, j, i - 1, j, i + 2, j, true, g[G_SXI_X * NS + s + NJ], g[G_SXI_Y * NS + s + NJ],
+         false, i + 1, j, i + 1, j + 1, eC, eV);
+    const bool wall = (j == 0) && !cut_col(L, i);
+    face(c, i, j - 1, i, j, i, j - 2, i, j + 1, false, g[G_SETA_X * NS + s], g[G_SETA_Y * NS + s], wall,
+         i, j, i + 1, j, sC, sV);
+    face(c, i, j, i, j + 1, i, j - 1, i, j + 2, false, g[G_SETA_X * NS + s + NJ + 1],
+         g[G_SETA_Y * NS + s + NJ + 1], false, i, j + 1, i + 1, j + 1, nC, nV);
+    const double vol = g[G_VOL * NS + s];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        D4 fc = (eC[k] - wC[k]) + (nC[k] - sC[k]);
+        D4 fv = (eV[k] - wV[k]) + (nV[k] - sV[k]);
+        F[k] = fc / vol + fv / vol;
+    }
+}
+
+__device__ void make_ctx(Ctx &c, const Lay &L, const double *geo, const double *u, const double *mut,
+                         const Phys &ph) {
+    c.L = L;
+    c.geo = geo;
+    c.u = u;
+    c.mut = mut;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) c.uinf[k] = dc(ph.uinf[k]);
+    c.mu_inf = dc(ph.mu_inf);
+    c.pr = ph.pr;
+    c.prt = ph.prt;
+    c.kappa2c = ph.kappa2c;
+    c.rans = ph.rans;
+    c.noslip = ph.rans;
+    c.fine = 1;
+    c.viscous = ph.rans;
+    c.si = c.sj = -1000000;
+}
+
+// ------------------------------------------------------------------ kernels
+// out += (dF/du)^T lam: every cell scatters (dF_c/du_s)^T lam_c to each
+// interior cell s its residual depends on (13 stencil positions mapped
+// through the boundary conditions).  out must be zeroed first.
+__global__ __launch_bounds__(TPB) void k_vjp(Lay L, const double *geo, const double *u, const double *mut,
+                                             Phys ph, const double *lam, double *out) {
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    int i, j;
+    if (!decode(L, s, i, j) || !interior(L, i, j)) return;
+    const int NS = L.NS;
+    double lc[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) lc[k] = lam[k * NS + s];
+    Ctx c;
+    make_ctx(c, L, geo, u, mut, ph);
+    const int di[13] = {0, -1, 1, -2, 2, 0, 0, 0, 0, -1, 1, -1, 1};
+    const int dj[13] = {0, 0, 0, 0, 0, -1, 1, -2, 2, -1, -1, 1, 1};
+    int srci[13], srcj[13], n = 0;
+    for (int p = 0; p < 13; ++p) {
+        int a, b;
+        source_of(L, i + di[p], j + dj[p], a, b);
+        bool dup = false;
+        for (int q = 0; q < n; ++q) dup = dup || (srci[q] == a && srcj[q] == b);
+        if (!dup) {
+            srci[n] = a;
+            srcj[n] = b;
+            ++n;
+        }
+    }
+    for (int q = 0; q < n; ++q) {
+        c.si = srci[q];
+        c.sj = srcj[q];
+        D4 F[4];
+        cell_residual(c, i, j, F);
+        const int t = L.slot(c.si, c.sj);
+#pragma unroll
+        for (int m = 0; m < 4; ++m) {
+            const double v = ((lc[0] * F[0].d[m] + lc[1] * F[1].d[m]) + lc[2] * F[2].d[m]) + lc[3] * F[3].d[m];
+            atomicAdd(out + m * NS + t, v);
+        }
+    }
+}
+
+// dF/dalpha (degrees) and dF/dM at fixed state: lane 0 alpha, lane 1 Mach
+// (through the far-field state and mu_inf = M sqrt(gamma) / Re)
+__global__ __launch_bounds__(TPB) void k_param_partials(Lay L, const double *geo, const double *u,
+                                                        const double *mut, Phys ph, double reynolds,
+                                                        double *dFa, double *dFm) {
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    int i, j;
+    if (!decode(L, s, i, j) || !interior(L, i, j)) return;
+    const int NS = L.NS;
+    Ctx c;
+    make_ctx(c, L, geo, u, mut, ph);
+    const double V = ph.mach * sqrt(GAM);
+    const double a = ph.alpha_deg * (M_PI / 180.0);
+    const double da = M_PI / 180.0;
+    D4 vx = dc(ph.uinf[1]), vy = dc(ph.uinf[2]);
+    vx.d[0] = -V * sin(a) * da;
+    vx.d[1] = sqrt(GAM) * cos(a);
+    vy.d[0] = V * cos(a) * da;
+    vy.d[1] = sqrt(GAM) * sin(a);
+    c.uinf[1] = vx;
+    c.uinf[2] = vy;
+    D4 E = 0.5 * (vx * vx + vy * vy);
+    c.uinf[3] = D4{ph.uinf[3], {E.d[0], E.d[1], 0.0, 0.0}};
+    if (ph.rans) c.mu_inf.d[1] = sqrt(GAM) / reynolds;
+    D4 F[4];
+    cell_residual(c, i, j, F);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        dFa[k * NS + s] = F[k].d[0];
+        dFm[k * NS + s] = F[k].d[1];
+    }
+}
+
+// Wall pressure force (the residual's own wall flux p_w S, p_w the mean of
+// the wall cell and its ghost): one workgroup, deterministic tree sum.
+// out[0..5] = C_L, C_D, dC_L/dalpha_deg, dC_L/dM (at fixed state), F_x, F_y;
+// dcl (padded, zeroed) receives dC_L/du on the wall cells.
+__global__ __launch_bounds__(TPB) void k_forces(Lay L, const double *geo, const double *u, Phys ph,
+                                                double *out, double *dcl) {
+    __shared__ double sx_[TPB], sy_[TPB];
+    const int NS = L.NS;
+    Ctx c;
+    make_ctx(c, L, geo, u, nullptr, ph);
+    const double a = ph.alpha_deg * (M_PI / 180.0);
+    const double q = 0.5 * (ph.mach * ph.mach * GAM);
+    double fx = 0.0, fy = 0.0;
+    for (int i = threadIdx.x; i < L.ni; i += TPB) {
+        if (cut_col(L, i)) continue;
+        c.si = i;
+        c.sj = 0;
+        D4 Ug[4], Ui[4];
+        state(c, i, -1, Ug);
+        state(c, i, 0, Ui);
+        D4 pw = 0.5 * (dpres(Ug) + dpres(Ui));
+        const int f = L.slot(i, 0);
+        const double Sx = geo[G_SETA_X * NS + f], Sy = geo[G_SETA_Y * NS + f];
+        fx -= pw.v * Sx;
+        fy -= pw.v * Sy;
+        if (dcl) {
+#pragma unroll
+            for (int m = 0; m < 4; ++m) {
+                const double dfx = -pw.d[m] * Sx, dfy = -pw.d[m] * Sy;
+                dcl[m * NS + f] = (dfy * cos(a) - dfx * sin(a)) / q;
+            }
+        }
+    }
+    sx_[threadIdx.x] = fx;
+    sy_[threadIdx.x] = fy;
+    __syncthreads();
+    for (int w = TPB / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) {
+            sx_[threadIdx.x] += sx_[threadIdx.x + w];
+            sy_[threadIdx.x] += sy_[threadIdx.x + w];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        const double Fx = sx_[0], Fy = sy_[0];
+        const double cl = (Fy * cos(a) - Fx * sin(a)) / q;
+        const double cd = (Fx * cos(a) + Fy * sin(a)) / q;
+        out[0] = cl;
+        out[1] = cd;
+        out[2] = (-Fy * sin(a) - Fx * cos(a)) * (M_PI / 180.0) / q;
+        out[3] = -2.0 * cl / ph.mach;
+        out[4] = Fx;
+        out[5] = Fy;
+    }
+}
+
+// Transposed SGS preconditioner x = P^-T r, P = (D+L) D^-1 (D+U), with the
+// stored D^-1 and M_s = D^-1 B_s: with zeta = D^T z and xi = D^T x,
+//     ascending:  zeta_c = r_c  - sum_{nb earlier} M_{nb->c}^T zeta_nb
+//     descending: xi_c   = zeta_c - sum_{nb later} M_{nb->c}^T xi_nb,
+//                 x_c    = D_c^-T xi_c,
+// where M_{nb->c} is neighbour nb's block toward c.  One thread per row,
+// hyperplane wavefront as in the primal sweep.
+template <typename T>
+__device__ inline void mtv_sub(const T *blk, int b, int NS, int s, const T v[4], T out[4]) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        T a = out[r];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) a = fma(-blk[BL<T>::at(b, NS, s, k, r)], v[k], a);
+        out[r] = a;
+    }
+}
+
+template <typename T, int BS>
+__global__ __launch_bounds__(BS) void k_sgs_t(Lay L, const T *blk, const double *r, T *zeta, double *x) {
+    __shared__ T nbuf[2][BS][4];
+    extern __shared__ unsigned char smem[];
+    T *row0 = reinterpret_cast<T *>(smem);          // n_wake x 4
+    const int j = threadIdx.x;
+    const int ni = L.ni, nj = L.nj, NS = L.NS, nw = L.nw, NJ = L.NJ;
+    const bool active = j < nj;
+    const int H = ni + nj - 1;
+    T zw[4] = {0, 0, 0, 0};
+    for (int h = 0; h < H; ++h) {
+        const int i = h - j;
+        if (active && i >= 0 && i < ni) {
+            const int s = L.slot(i, j);
+            T v[4];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) v[k] = (T)r[k * NS + s];
+            if (i > 0) mtv_sub(blk, B_M0 + 1, NS, s - NJ, zw, v);          // west cell's east block
+            if (j > 0) {
+                T zs[4];
+#pragma unroll
+                for (int k = 0; k < 4; ++k) zs[k] = nbuf[(h - 1) & 1][j - 1][k];
+                mtv_sub(blk, B_M0 + 3, NS, s - NJ - 1, zs, v);             // south cell's north block
+            } else if (L.topo == 1 && i >= ni - nw) {
+                const int p = ni - 1 - i;                                   // earlier partner
+                T zp[4];
+#pragma unroll
+                for (int k = 0; k < 4; ++k) zp[k] = row0[p * 4 + k];
+                mtv_sub(blk, B_M0 + 2, NS, L.slot(p, 0), zp, v);
+            }
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                nbuf[h & 1][j][k] = v[k];
+                zeta[k * NS + s] = v[k];
+                zw[k] = v[k];
+            }
+            if (j == 0 && L.topo == 1 && i < nw) {
+#pragma unroll
+                for (int k = 0; k < 4; ++k) row0[i * 4 + k] = v[k];
+            }
+        }
+        __syncthreads();
+    }
+    T xe[4] = {0, 0, 0, 0};
+    for (int h = H - 1; h >= 0; --h) {
+        const int i = h - j;
+        if (active && i >= 0 && i < ni) {
+            const int s = L.slot(i, j);
+            T v[4];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) v[k] = zeta[k * NS + s];
+            if (i < ni - 1) mtv_sub(blk, B_M0 + 0, NS, s + NJ, xe, v);     // east cell's west block
+            if (j < nj - 1) {
+                T xn[4];
+#pragma unroll
+                for (int k = 0; k < 4; ++k) xn[k] = nbuf[(h + 1) & 1][j + 1][k];
+                mtv_sub(blk, B_M0 + 2, NS, s + NJ + 1, xn, v);             // north cell's south block
+            }
+            if (j == 0 && L.topo == 1 && i < nw) {
+                const int q = ni - 1 - i;                                   // later partner
+                T xq[4];
+#pragma unroll
+                for (int k = 0; k < 4; ++k) xq[k] = row0[(q - (ni - nw)) * 4 + k];
+                mtv_sub(blk, B_M0 + 2, NS, L.slot(q, 0), xq, v);
+            }
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                nbuf[h & 1][j][k] = v[k];
+                xe[k] = v[k];
+            }
+            if (j == 0 && L.topo == 1 && i >= ni - nw) {
+#pragma unroll
+                for (int k = 0; k < 4; ++k) row0[(i - (ni - nw)) * 4 + k] = v[k];
+            }
+            // x = D^-T xi
+#pragma unroll
+            for (int rr = 0; rr < 4; ++rr) {
+                T acc = (T)0;
+#pragma unroll
+                for (int k = 0; k < 4; ++k) acc = fma(blk[BL<T>::at(B_DINV, NS, s, k, rr)], v[k], acc);
+                x[rr * NS + s] = (double)acc;
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// sum of squares of all four components over the interior, and dot
+// products; fixed-order two-pass reductions
+constexpr int RB = 128;
+__global__ __launch_bounds__(TPB) void k_dot1(Lay L, const double *a, const double *b, double *red) {
+    __shared__ double sh[TPB];
+    double acc = 0.0;
+    for (int s = blockIdx.x * blockDim.x + threadIdx.x; s < L.NS; s += gridDim.x * blockDim.x) {
+        int i, j;
+        if (decode(L, s, i, j) && interior(L, i, j)) {
+#pragma unroll
+            for (int k = 0; k < 4; ++k) acc += a[k * L.NS + s] * b[k * L.NS + s];
+        }
+    }
+    sh[threadIdx.x] = acc;
+    __syncthreads();
+    for (int w = TPB / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) red[blockIdx.x] = sh[0];
+}
+
+__global__ void k_dot2(const double *red, double *out) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    double a = 0.0;
+    for (int k = 0; k < RB; ++k) a += red[k];
+    *out = a;
+}
+
+// out = a x + b y on the interior (four components), plain pointers
+__global__ void k_axpby_p(Lay L, double a, const double *x, double b, const double *y, double *out) {
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    int i, j;
+    if (!decode(L, s, i, j) || !interior(L, i, j)) return;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const int o = k * L.NS + s;
+        out[o] = (y == nullptr) ? a * x[o] : a * x[o] + b * y[o];
+    }
+}
+
+// out = x + a * dts * z (x may be null: out = a * dts * z)
+__global__ void k_adj_update(Lay L, const double *x, double a, const double *dts, const double *z,
+                             double *out) {
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    int i, j;
+    if (!decode(L, s, i, j) || !interior(L, i, j)) return;
+    const double d = dts[s];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const int o = k * L.NS + s;
+        out[o] = (x == nullptr) ? a * (d * z[o]) : x[o] + a * (d * z[o]);
+    }
+}
+
+// out[i] = <w, v_i> for the n vectors v_i = basis + i * V (interior,
+// four components); fixed-order two-pass reduction
+__global__ __launch_bounds__(TPB) void k_mdot1(Lay L, const double *w, const double *basis, size_t V,
+                                               double *red) {
+    __shared__ double sh[TPB];
+    const double *v = basis + (size_t)blockIdx.y * V;
+    double acc = 0.0;
+    for (int s = blockIdx.x * blockDim.x + threadIdx.x; s < L.NS; s += gridDim.x * blockDim.x) {
+        int i, j;
+        if (decode(L, s, i, j) && interior(L, i, j)) {
+#pragma unroll
+            for (int k = 0; k < 4; ++k) acc += w[k * L.NS + s] * v[k * L.NS + s];
+        }
+    }
+    sh[threadIdx.x] = acc;
+    __syncthreads();
+    for (int q = TPB / 2; q > 0; q >>= 1) {
+        if ((int)threadIdx.x < q) sh[threadIdx.x] += sh[threadIdx.x + q];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) red[(size_t)blockIdx.y * RB + blockIdx.x] = sh[0];
+}
+
+__global__ void k_mdot2(const double *red, int n, double *out) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double a = 0.0;
+    for (int k = 0; k < RB; ++k) a += red[(size_t)i * RB + k];
+    out[i] = a;
+}
+
+// w -= sum_i h_i v_i
+__global__ void k_maxpy(Lay L, double *w, const double *basis, size_t V, const double *h, int n) {
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    int i, j;
+    if (!decode(L, s, i, j) || !interior(L, i, j)) return;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const size_t o = (size_t)k * L.NS + s;
+        double a = w[o];
+        for (int q = 0; q < n; ++q) a -= h[q] * basis[(size_t)q * V + o];
+        w[o] = a;
+    }
+}
+
+__global__ void k_zero(double *p, size_t n) {
+    const size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < n) p[t] = 0.0;
+}
+
+}  // namespace
+
+// =================================================================== launchers
+void launch_vjp(const Lay &L, const double *geo, const double *u, const double *mut, const Phys &ph,
+                const double *lam, double *out, hipStream_t st) {
+    hipLaunchKernelGGL(k_vjp, dim3(nblocks(L.NS)), dim3(TPB), 0, st, L, geo, u, mut, ph, lam, out);
+}
+
+void launch_param_partials(const Lay &L, const double *geo, const double *u, const double *mut,
+                           const Phys &ph, double reynolds, double *dFa, double *dFm, hipStream_t st) {
+    hipLaunchKernelGGL(k_param_partials, dim3(nblocks(L.NS)), dim3(TPB), 0, st, L, geo, u, mut, ph,
+                       reynolds, dFa, dFm);
+}
+
+void launch_forces(const Lay &L, const double *geo, const double *u, const Phys &ph, double *out,
+                   double *dcl, hipStream_t st) {
+    hipLaunchKernelGGL(k_forces, dim3(1), dim3(TPB), 0, st, L, geo, u, ph, out, dcl);
+}
+
+template <typename T>
+static void sgs_t_dispatch(const Lay &L, const void *blk, const double *r, void *zeta, double *x,
+                           hipStream_t st) {
+    const size_t shm = (size_t)(L.nw > 0 ? L.nw : 1) * 4 * sizeof(T);
+    if (L.nj <= 64)
+        hipLaunchKernelGGL((k_sgs_t<T, 64>), dim3(1), dim3(64), shm, st, L, (const T *)blk, r, (T *)zeta, x);
+    else if (L.nj <= 128)
+        hipLaunchKernelGGL((k_sgs_t<T, 128>), dim3(1), dim3(128), shm, st, L, (const T *)blk, r, (T *)zeta, x);
+    else if (L.nj <= 256)
+        hipLaunchKernelGGL((k_sgs_t<T, 256>), dim3(1), dim3(256), shm, st, L, (const T *)blk, r, (T *)zeta, x);
+    else
+        hipLaunchKernelGGL((k_sgs_t<T, 512>), dim3(1), dim3(512), shm, st, L, (const T *)blk, r, (T *)zeta, x);
+}
+
+void launch_sgs_transpose(const Lay &L, const void *blk, const double *r, void *zeta, double *x, int fp32,
+                          hipStream_t st) {
+    if (fp32) sgs_t_dispatch<float>(L, blk, r, zeta, x, st);
+    else sgs_t_dispatch<double>(L, blk, r, zeta, x, st);
+}
+
+int dot_scratch_size() { return RB; }
+
+void launch_dot(const Lay &L, const double *a, const double *b, double *red, double *out, hipStream_t st) {
+    hipLaunchKernelGGL(k_dot1, dim3(RB), dim3(TPB), 0, st, L, a, b, red);
+    hipLaunchKernelGGL(k_dot2, dim3(1), dim3(64), 0, st, red, out);
+}
+
+void launch_axpby_ptr(const Lay &L, double a, const double *x, double b, const double *y, double *out,
+                      hipStream_t st) {
+    hipLaunchKernelGGL(k_axpby_p, dim3(nblocks(L.NS)), dim3(TPB), 0, st, L, a, x, b, y, out);
+}
+
+void launch_adj_update(const Lay &L, const double *x, double a, const double *dts, const double *z,
+                       double *out, hipStream_t st) {
+    hipLaunchKernelGGL(k_adj_update, dim3(nblocks(L.NS)), dim3(TPB), 0, st, L, x, a, dts, z, out);
+}
+
+void launch_mdot(const Lay &L, const double *w, const double *basis, size_t V, int n, double *red,
+                 double *out, hipStream_t st) {
+    hipLaunchKernelGGL(k_mdot1, dim3(RB, n), dim3(TPB), 0, st, L, w, basis, V, red);
+    hipLaunchKernelGGL(k_mdot2, dim3(nblocks(n, 64)), dim3(64), 0, st, red, n, out);
+}
+
+void launch_maxpy(const Lay &L, double *w, const double *basis, size_t V, const double *h, int n,
+                  hipStream_t st) {
+    hipLaunchKernelGGL(k_maxpy, dim3(nblocks(L.NS)), dim3(TPB), 0, st, L, w, basis, V, h, n);
+}
+
+void launch_zero(double *p, size_t n, hipStream_t st) {
+    hipLaunchKernelGGL(k_zero, dim3((unsigned)((n + TPB - 1) / TPB)), dim3(TPB), 0, st, p, n);
+}
+
+}  // namespace fas

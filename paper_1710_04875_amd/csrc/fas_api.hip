@@ -118,6 +118,10 @@ struct fas_state_s {
     int have_un = 0;
     Phys *d_ph = nullptr;
     std::vector<void *> allocs;
+    // adjoint work arrays (padded fine level), allocated on first use
+    double *a_lam = nullptr, *a_g = nullptr, *a_r = nullptr, *a_z = nullptr, *a_jt = nullptr,
+           *a_lam0 = nullptr, *a_zeta = nullptr, *a_dFa = nullptr, *a_dFm = nullptr, *a_dcl = nullptr,
+           *a_red = nullptr, *a_out = nullptr, *a_basis = nullptr;
 };
 
 struct fas_batch_s {
@@ -692,6 +696,273 @@ extern "C" fas_status fas_profile(fas_state s, int32_t enable) {
 extern "C" fas_status fas_profile_read(fas_state s, double *ms, int64_t *count) {
     if (!s) return fail(FAS_EINVAL, "null state");
     return profile_read(s->e, ms, count);
+}
+
+// ------------------------------------------------------------------ adjoint
+namespace {
+
+fas_status ensure_adjoint(fas_state s) {
+    if (s->a_lam) return FAS_OK;
+    const size_t V = (size_t)4 * s->lv[0].L.NS;
+    const size_t n = 10 * V + dot_scratch_size() + 16;
+    double *b = nullptr;
+    HIPCHK(hipMalloc(&b, n * sizeof(double)));
+    s->allocs.push_back(b);
+    launch_zero(b, n, s->e.st);
+    double **f[10] = {&s->a_lam, &s->a_g, &s->a_r, &s->a_z, &s->a_jt, &s->a_lam0, &s->a_zeta,
+                      &s->a_dFa, &s->a_dFm, &s->a_dcl};
+    for (int k = 0; k < 10; ++k) *f[k] = b + k * V;
+    s->a_red = b + 10 * V;
+    s->a_out = s->a_red + dot_scratch_size();
+    HIPCHK(hipGetLastError());
+    return FAS_OK;
+}
+
+// sqrt(<a, b>) / (4 N) style scalar: <a, b> over the fine interior (host value)
+fas_status fine_dot(fas_state s, const double *a, const double *b, double *out) {
+    const LevelDev &d = s->lv[0];
+    launch_dot(d.L, a, b, s->a_red, s->a_out + 8, s->e.st);
+    HIPCHK(hipMemcpyAsync(out, s->a_out + 8, sizeof(double), hipMemcpyDeviceToHost, s->e.st));
+    HIPCHK(hipStreamSynchronize(s->e.st));
+    return FAS_OK;
+}
+
+// a_r = a_g - (dF/du)^T a_lam at the prepared state
+void adj_residual(fas_state s, const double *lam) {
+    const LevelDev &d = s->lv[0];
+    const size_t V = (size_t)4 * d.L.NS;
+    launch_zero(s->a_jt, V, s->e.st);
+    launch_vjp(d.L, d.geo, d.u, d.mut, s->ph, lam, s->a_jt, s->e.st);
+    launch_axpby_ptr(d.L, 1.0, s->a_g, -1.0, s->a_jt, s->a_r, s->e.st);
+}
+
+// Krylov space of the adjoint GMRES (restart length)
+constexpr int ADJ_KRYLOV = 200;
+
+// Preconditioner of the adjoint system: the transpose of the primal
+// increment operator, D_t P^-T (AW: increment P^-1 D_t r) or P^-T D_t
+// (pARK: increment D_t P^-1 r).  out = M v; uses a_jt as scratch.
+void adj_precond(fas_state s, const double *v, double *out) {
+    Engine &e = s->e;
+    const LevelDev &d = s->lv[0];
+    if (e.sc.aw) {
+        launch_sgs_transpose(d.L, d.blk, v, s->a_zeta, s->a_z, e.fp32, e.st);
+        launch_adj_update(d.L, nullptr, 1.0, d.dts, s->a_z, out, e.st);
+    } else {
+        launch_adj_update(d.L, nullptr, 1.0, d.dts, v, s->a_jt, e.st);
+        launch_sgs_transpose(d.L, d.blk, s->a_jt, s->a_zeta, out, e.fp32, e.st);
+    }
+}
+
+// (dF/du)^T lam = g on the padded work arrays (a_g, a_lam) by GMRES(200)
+// with restarts, right-preconditioned by the transposed smoother.  The
+// exact Jacobian of the switched JST scheme is not dissipative in general
+// (some eigenvalues of the preconditioned operator have negative real
+// parts), so a fixed-point iteration with the smoother alone need not
+// converge; GMRES only needs a nonsingular system.  hist[k] is the RMS of
+// the residual estimate after k iterations.
+fas_status adj_solve(fas_state s, int max_iter, double drop, double *hist, int *n_iter) {
+    Engine &e = s->e;
+    const LevelDev &d = s->lv[0];
+    const size_t V = (size_t)4 * d.L.NS;
+    const double N4 = 4.0 * d.L.ni * d.L.nj;
+    constexpr int M = ADJ_KRYLOV;
+    if (!s->a_basis) {
+        // basis vectors, then the Gram-Schmidt scratch: coefficients and
+        // reduction partials
+        const size_t nb = (size_t)(M + 1) * V + (size_t)(M + 1) * (dot_scratch_size() + 2);
+        HIPCHK(hipMalloc(&s->a_basis, nb * sizeof(double)));
+        s->allocs.push_back(s->a_basis);
+        launch_zero(s->a_basis, nb, e.st);
+    }
+    double *d_h = s->a_basis + (size_t)(M + 1) * V;      // M + 1 coefficients
+    double *d_red = d_h + (M + 1);                         // (M + 1) * RB partials
+    std::vector<double> hh(M + 1), h2(M + 1);
+    auto vb = [&](int k) { return s->a_basis + (size_t)k * V; };
+    prepare_iteration(e, 0);
+    adj_residual(s, s->a_lam);
+    double beta = 0.0;
+    STCHK(fine_dot(s, s->a_r, s->a_r, &beta));
+    beta = std::sqrt(beta);
+    const double h0 = beta / std::sqrt(N4);
+    if (hist) hist[0] = h0;
+    const double target = drop > 0.0 ? beta * std::pow(10.0, -drop) : -1.0;
+    int it = 0;
+    double res = beta;
+    std::vector<double> H((size_t)(M + 1) * M), cs(M), sn(M), gg(M + 1), y(M);
+    while (it < max_iter && std::isfinite(res) && res > target && res > 0.0) {
+        launch_axpby_ptr(d.L, 1.0 / res, s->a_r, 0.0, nullptr, vb(0), e.st);
+        std::fill(gg.begin(), gg.end(), 0.0);
+        gg[0] = res;
+        int k = 0;
+        for (; k < M && it < max_iter; ++k) {
+            // w = J^T M v_k
+            adj_precond(s, vb(k), s->a_r);
+            launch_zero(vb(k + 1), V, e.st);
+            launch_vjp(d.L, d.geo, d.u, d.mut, s->ph, s->a_r, vb(k + 1), e.st);
+            // classical Gram-Schmidt, twice (all k + 1 products in one launch)
+            for (int pass = 0; pass < 2; ++pass) {
+                launch_mdot(d.L, vb(k + 1), vb(0), V, k + 1, d_red, d_h, e.st);
+                HIPCHK(hipMemcpyAsync(pass ? h2.data() : hh.data(), d_h, (k + 1) * sizeof(double),
+                                      hipMemcpyDeviceToHost, e.st));
+                launch_maxpy(d.L, vb(k + 1), vb(0), V, d_h, k + 1, e.st);
+            }
+            HIPCHK(hipStreamSynchronize(e.st));
+            for (int i = 0; i <= k; ++i) H[(size_t)i * M + k] = hh[i] + h2[i];
+            double hn = 0.0;
+            STCHK(fine_dot(s, vb(k + 1), vb(k + 1), &hn));
+            hn = std::sqrt(hn);
+            H[(size_t)(k + 1) * M + k] = hn;
+            if (hn > 0.0) launch_axpby_ptr(d.L, 1.0 / hn, vb(k + 1), 0.0, nullptr, vb(k + 1), e.st);
+            for (int i = 0; i < k; ++i) {
+                const double a = H[(size_t)i * M + k], b = H[(size_t)(i + 1) * M + k];
+                H[(size_t)i * M + k] = cs[i] * a + sn[i] * b;
+                H[(size_t)(i + 1) * M + k] = -sn[i] * a + cs[i] * b;
+            }
+            const double a = H[(size_t)k * M + k], b = H[(size_t)(k + 1) * M + k];
+            const double r = std::hypot(a, b);
+            cs[k] = r > 0.0 ? a / r : 1.0;
+            sn[k] = r > 0.0 ? b / r : 0.0;
+            H[(size_t)k * M + k] = r;
+            H[(size_t)(k + 1) * M + k] = 0.0;
+            gg[k + 1] = -sn[k] * gg[k];
+            gg[k] = cs[k] * gg[k];
+            ++it;
+            res = std::fabs(gg[k + 1]);
+            if (hist) hist[it] = res / std::sqrt(N4);
+            if (!(res > target) || hn == 0.0) {
+                ++k;
+                break;
+            }
+        }
+        // y = H^-1 g, lam += M (V y)
+        for (int i = k - 1; i >= 0; --i) {
+            double t = gg[i];
+            for (int j = i + 1; j < k; ++j) t -= H[(size_t)i * M + j] * y[j];
+            y[i] = t / H[(size_t)i * M + i];
+        }
+        launch_zero(s->a_r, V, e.st);
+        for (int i = 0; i < k; ++i) launch_axpby_ptr(d.L, 1.0, s->a_r, y[i], vb(i), s->a_r, e.st);
+        adj_precond(s, s->a_r, s->a_z);
+        launch_axpby_ptr(d.L, 1.0, s->a_lam, 1.0, s->a_z, s->a_lam, e.st);
+        // true residual for the restart
+        adj_residual(s, s->a_lam);
+        STCHK(fine_dot(s, s->a_r, s->a_r, &res));
+        res = std::sqrt(res);
+        if (hist) hist[it] = res / std::sqrt(N4);
+    }
+    if (n_iter) *n_iter = it;
+    HIPCHK(hipGetLastError());
+    if (!std::isfinite(res)) return fail(FAS_DIVERGED, "adjoint residual is not finite");
+    if (drop > 0.0 && res > target) return fail(FAS_NOT_CONVERGED, "adjoint iteration cap reached");
+    return FAS_OK;
+}
+
+}  // namespace
+
+extern "C" fas_status fas_forces(fas_state s, double *cl, double *cd, double *dcl_du) {
+    if (!s) return fail(FAS_EINVAL, "null state");
+    STCHK(ensure_adjoint(s));
+    const LevelDev &d = s->lv[0];
+    if (dcl_du) launch_zero(s->a_dcl, (size_t)4 * d.L.NS, s->e.st);
+    launch_forces(d.L, d.geo, d.u, s->ph, s->a_out, dcl_du ? s->a_dcl : nullptr, s->e.st);
+    double h[6];
+    HIPCHK(hipMemcpyAsync(h, s->a_out, sizeof(h), hipMemcpyDeviceToHost, s->e.st));
+    if (dcl_du) launch_pack(d.L, s->a_dcl, dcl_du, 4, s->e.st);
+    HIPCHK(hipStreamSynchronize(s->e.st));
+    if (cl) *cl = h[0];
+    if (cd) *cd = h[1];
+    return FAS_OK;
+}
+
+extern "C" fas_status fas_vjp(fas_state s, const double *lam, double *out) {
+    if (!s || !lam || !out) return fail(FAS_EINVAL, "null argument");
+    STCHK(ensure_adjoint(s));
+    const LevelDev &d = s->lv[0];
+    prep(s->e, 0, fine_rans(s->e, 0));
+    launch_unpack(d.L, lam, s->a_lam, 4, s->e.st);
+    launch_zero(s->a_jt, (size_t)4 * d.L.NS, s->e.st);
+    launch_vjp(d.L, d.geo, d.u, d.mut, s->ph, s->a_lam, s->a_jt, s->e.st);
+    launch_pack(d.L, s->a_jt, out, 4, s->e.st);
+    HIPCHK(hipGetLastError());
+    return FAS_OK;
+}
+
+extern "C" fas_status fas_param_partials(fas_state s, double *dF_dalpha, double *dF_dmach, double *dcl_dparam) {
+    if (!s) return fail(FAS_EINVAL, "null state");
+    STCHK(ensure_adjoint(s));
+    const LevelDev &d = s->lv[0];
+    prep(s->e, 0, fine_rans(s->e, 0));
+    launch_param_partials(d.L, d.geo, d.u, d.mut, s->ph, s->p.reynolds, s->a_dFa, s->a_dFm, s->e.st);
+    if (dF_dalpha) launch_pack(d.L, s->a_dFa, dF_dalpha, 4, s->e.st);
+    if (dF_dmach) launch_pack(d.L, s->a_dFm, dF_dmach, 4, s->e.st);
+    if (dcl_dparam) {
+        launch_forces(d.L, d.geo, d.u, s->ph, s->a_out, nullptr, s->e.st);
+        double h[6];
+        HIPCHK(hipMemcpyAsync(h, s->a_out, sizeof(h), hipMemcpyDeviceToHost, s->e.st));
+        HIPCHK(hipStreamSynchronize(s->e.st));
+        dcl_dparam[0] = h[2];
+        dcl_dparam[1] = h[3];
+    }
+    HIPCHK(hipGetLastError());
+    return FAS_OK;
+}
+
+extern "C" fas_status fas_sgs_apply_transpose(fas_state s, const double *r, double *x) {
+    if (!s || !r || !x) return fail(FAS_EINVAL, "null argument");
+    STCHK(ensure_adjoint(s));
+    const LevelDev &d = s->lv[0];
+    prepare_iteration(s->e, 0);
+    launch_unpack(d.L, r, s->a_r, 4, s->e.st);
+    launch_sgs_transpose(d.L, d.blk, s->a_r, s->a_zeta, s->a_z, s->e.fp32, s->e.st);
+    launch_pack(d.L, s->a_z, x, 4, s->e.st);
+    HIPCHK(hipGetLastError());
+    return FAS_OK;
+}
+
+extern "C" fas_status fas_adjoint_solve(fas_state s, const double *rhs, double *lam, int32_t max_iter,
+                                        double drop_orders, double *res_hist, int32_t *n_iter) {
+    if (!s || !rhs || !lam || max_iter < 0) return fail(FAS_EINVAL, "bad argument");
+    STCHK(ensure_adjoint(s));
+    const LevelDev &d = s->lv[0];
+    launch_unpack(d.L, rhs, s->a_g, 4, s->e.st);
+    launch_unpack(d.L, lam, s->a_lam, 4, s->e.st);
+    int n = 0;
+    fas_status st = adj_solve(s, max_iter, drop_orders, res_hist, &n);
+    if (n_iter) *n_iter = n;
+    launch_pack(d.L, s->a_lam, lam, 4, s->e.st);
+    HIPCHK(hipStreamSynchronize(s->e.st));
+    return st;
+}
+
+extern "C" fas_status fas_lift_gradient(fas_state s, int32_t max_iter, double drop_orders, double *cl,
+                                        double *grad, double *res_hist, int32_t *n_iter) {
+    if (!s || !grad || max_iter < 0) return fail(FAS_EINVAL, "bad argument");
+    STCHK(ensure_adjoint(s));
+    Engine &e = s->e;
+    const LevelDev &d = s->lv[0];
+    const size_t V = (size_t)4 * d.L.NS;
+    // dC_L/du and the explicit partials at the current state
+    launch_zero(s->a_dcl, V, e.st);
+    launch_forces(d.L, d.geo, d.u, s->ph, s->a_out, s->a_dcl, e.st);
+    double h[6];
+    HIPCHK(hipMemcpyAsync(h, s->a_out, sizeof(h), hipMemcpyDeviceToHost, e.st));
+    HIPCHK(hipStreamSynchronize(e.st));
+    // (dF/du)^T lam = -dC_L/du
+    launch_axpby_ptr(d.L, -1.0, s->a_dcl, 0.0, nullptr, s->a_g, e.st);
+    launch_zero(s->a_lam, V, e.st);
+    int n = 0;
+    fas_status st = adj_solve(s, max_iter, drop_orders, res_hist, &n);
+    if (n_iter) *n_iter = n;
+    if (st != FAS_OK && st != FAS_NOT_CONVERGED) return st;
+    launch_param_partials(d.L, d.geo, d.u, d.mut, s->ph, s->p.reynolds, s->a_dFa, s->a_dFm, e.st);
+    double la = 0.0, lm = 0.0;
+    STCHK(fine_dot(s, s->a_lam, s->a_dFa, &la));
+    STCHK(fine_dot(s, s->a_lam, s->a_dFm, &lm));
+    if (cl) *cl = h[0];
+    grad[0] = h[2] + la;
+    grad[1] = h[3] + lm;
+    return st;
 }
 
 // -------------------------------------------------------------------- batch

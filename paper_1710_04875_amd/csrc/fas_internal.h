@@ -53,6 +53,24 @@ constexpr int B_M0 = 1;          // + slot
 constexpr int BLK_NBLOCKS = 5;
 constexpr int BLK_NPLANES = 80;  // values per cell
 
+// Element (row r, column c) of block b of cell slot s.  FP32 blocks: one
+// 16-value record per cell (a block row is one 16-byte vector).  FP64
+// blocks: two half planes per block, columns 0-1 and 2-3, each holding the
+// four rows' column pairs of a cell contiguously (64 bytes), so that the
+// 16-byte loads of a wave reading one block row for consecutive cells form
+// one contiguous run.
+template <typename T> struct BL;
+template <> struct BL<float> {
+    __host__ __device__ static size_t at(int b, int NS, int s, int r, int c) {
+        return ((size_t)b * NS + s) * 16 + r * 4 + c;
+    }
+};
+template <> struct BL<double> {
+    __host__ __device__ static size_t at(int b, int NS, int s, int r, int c) {
+        return ((size_t)(2 * b + (c >> 1)) * NS + s) * 8 + r * 2 + (c & 1);
+    }
+};
+
 struct Phys {
     double mach, alpha_deg, re, pr, prt, mu_inf;
     double uinf[4];
@@ -175,6 +193,28 @@ void launch_norm(const BLev &B, double *out, hipStream_t st);   // out[n]
 void launch_count_cycle(const BLev &B, int *cyc, hipStream_t st);
 void launch_fill_int(int *p, int n, int v, hipStream_t st);
 int norm_scratch_size();
+
+// discrete adjoint of the steady fine-level residual (frozen eddy viscosity)
+void launch_vjp(const Lay &L, const double *geo, const double *u, const double *mut, const Phys &ph,
+                const double *lam, double *out, hipStream_t st);      // out += (dF/du)^T lam
+void launch_param_partials(const Lay &L, const double *geo, const double *u, const double *mut,
+                           const Phys &ph, double reynolds, double *dFa, double *dFm, hipStream_t st);
+void launch_forces(const Lay &L, const double *geo, const double *u, const Phys &ph, double *out,
+                   double *dcl, hipStream_t st);                       // out[6], dcl padded (zeroed)
+void launch_sgs_transpose(const Lay &L, const void *blk, const double *r, void *zeta, double *x, int fp32,
+                          hipStream_t st);
+int dot_scratch_size();
+void launch_dot(const Lay &L, const double *a, const double *b, double *red, double *out, hipStream_t st);
+void launch_axpby_ptr(const Lay &L, double a, const double *x, double b, const double *y, double *out,
+                      hipStream_t st);
+void launch_adj_update(const Lay &L, const double *x, double a, const double *dts, const double *z,
+                       double *out, hipStream_t st);
+void launch_zero(double *p, size_t n, hipStream_t st);
+// out[i] = <w, basis_i>, i < n (red: n * dot_scratch_size() values); w -= sum h_i basis_i
+void launch_mdot(const Lay &L, const double *w, const double *basis, size_t V, int n, double *red,
+                 double *out, hipStream_t st);
+void launch_maxpy(const Lay &L, double *w, const double *basis, size_t V, const double *h, int n,
+                  hipStream_t st);
 
 // batch convergence control: per case c, after the norm of a cycle
 struct BatchCtl {

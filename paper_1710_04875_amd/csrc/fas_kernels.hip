@@ -47,23 +47,6 @@ __device__ inline double sutherland(double T, double mu_inf) {
 
 __device__ inline size_t brec(int b, int NS, int s) { return ((size_t)b * NS + s) * 16; }
 
-// Element (row r, column c) of block b of cell slot s.  FP32 blocks: one
-// 16-value record per cell (a block row is one 16-byte vector).  FP64
-// blocks: two half planes per block, columns 0-1 and 2-3, each holding the
-// four rows' column pairs of a cell contiguously (64 bytes), so that the
-// 16-byte loads of a wave reading one block row for consecutive cells form
-// one contiguous run.
-template <typename T> struct BL;
-template <> struct BL<float> {
-    __host__ __device__ static size_t at(int b, int NS, int s, int r, int c) {
-        return ((size_t)b * NS + s) * 16 + r * 4 + c;
-    }
-};
-template <> struct BL<double> {
-    __host__ __device__ static size_t at(int b, int NS, int s, int r, int c) {
-        return ((size_t)(2 * b + (c >> 1)) * NS + s) * 8 + r * 2 + (c & 1);
-    }
-};
 
 template <typename T> struct V4;
 template <> struct V4<double> {

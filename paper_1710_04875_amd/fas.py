@@ -79,7 +79,8 @@ EXPORTS = [
     "fas_get_level", "fas_residual", "fas_smooth", "fas_sgs_apply", "fas_cycle",
     "fas_dual_time_step", "fas_profile", "fas_profile_read", "fas_batch_create",
     "fas_batch_destroy", "fas_batch_solve", "fas_batch_sweep_config", "fas_batch_set_sweep_config", "fas_batch_profile",
-    "fas_batch_profile_read", "fas_last_error",
+    "fas_batch_profile_read", "fas_forces", "fas_vjp", "fas_param_partials",
+    "fas_sgs_apply_transpose", "fas_adjoint_solve", "fas_lift_gradient", "fas_last_error",
 ]
 PROF_CLASSES = ("sweep", "residual", "blocks")
 
@@ -118,6 +119,12 @@ def load(path: str = LIB_PATH):
         "fas_batch_set_sweep_config": (i32, [vp, i32, i32]),
         "fas_batch_profile": (i32, [vp, i32]),
         "fas_batch_profile_read": (i32, [vp, dp, ctypes.POINTER(ctypes.c_int64)]),
+        "fas_forces": (i32, [vp, dp, dp, vp]),
+        "fas_vjp": (i32, [vp, vp, vp]),
+        "fas_param_partials": (i32, [vp, vp, vp, dp]),
+        "fas_sgs_apply_transpose": (i32, [vp, vp, vp]),
+        "fas_adjoint_solve": (i32, [vp, vp, vp, i32, f64, dp, ip]),
+        "fas_lift_gradient": (i32, [vp, i32, f64, dp, dp, dp, ip]),
         "fas_last_error": (ctypes.c_char_p, []),
     }
     for name, (res, args) in sig.items():
@@ -249,6 +256,63 @@ class State:
                                      n.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))))
         return {c: (float(ms[k]), int(n[k])) for k, c in enumerate(PROF_CLASSES)}
 
+    # ------------------------------------------------------------ adjoint
+    def forces(self, with_grad=False):
+        """(C_L, C_D[, dC_L/du]) of the wall pressure force."""
+        import torch
+        cl, cd = ctypes.c_double(0.0), ctypes.c_double(0.0)
+        g = torch.empty(self.shape(), dtype=torch.float64, device=self.device) if with_grad else None
+        _check(_lib.fas_forces(self.h, ctypes.byref(cl), ctypes.byref(cd), _dptr(g) if with_grad else None))
+        return (cl.value, cd.value, g) if with_grad else (cl.value, cd.value)
+
+    def vjp(self, lam):
+        """(dF/du)^T lam at the current state (frozen eddy viscosity)."""
+        import torch
+        lam = lam.to(torch.float64).contiguous()
+        out = torch.empty_like(lam)
+        _check(_lib.fas_vjp(self.h, _dptr(lam), _dptr(out)))
+        return out
+
+    def param_partials(self):
+        """(dF/dalpha_deg, dF/dM, [dC_L/dalpha_deg, dC_L/dM] at fixed u)."""
+        import torch
+        da = torch.empty(self.shape(), dtype=torch.float64, device=self.device)
+        dm = torch.empty_like(da)
+        c = np.zeros(2)
+        _check(_lib.fas_param_partials(self.h, _dptr(da), _dptr(dm),
+                                       c.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
+        return da, dm, c
+
+    def sgs_apply_transpose(self, r):
+        import torch
+        r = r.to(torch.float64).contiguous()
+        x = torch.empty_like(r)
+        _check(_lib.fas_sgs_apply_transpose(self.h, _dptr(r), _dptr(x)))
+        return x
+
+    def adjoint_solve(self, rhs, max_iter, drop_orders, lam0=None):
+        import torch
+        rhs = rhs.to(torch.float64).contiguous()
+        lam = torch.zeros_like(rhs) if lam0 is None else lam0.to(torch.float64).clone().contiguous()
+        hist = np.zeros(max_iter + 1)
+        n = ctypes.c_int32(0)
+        st = _check(_lib.fas_adjoint_solve(self.h, _dptr(rhs), _dptr(lam), max_iter, drop_orders,
+                                           hist.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                           ctypes.byref(n)), allow=(FAS_NOT_CONVERGED,))
+        return lam, hist[:n.value + 1], st
+
+    def lift_gradient(self, max_iter=2000, drop_orders=10.0):
+        """(C_L, [dC_L/dalpha_deg, dC_L/dM], adjoint history, status)."""
+        cl = ctypes.c_double(0.0)
+        g = np.zeros(2)
+        hist = np.zeros(max_iter + 1)
+        n = ctypes.c_int32(0)
+        st = _check(_lib.fas_lift_gradient(self.h, max_iter, drop_orders, ctypes.byref(cl),
+                                           g.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                           hist.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                           ctypes.byref(n)), allow=(FAS_NOT_CONVERGED,))
+        return cl.value, g, hist[:n.value + 1], st
+
     def dual_time_step(self, dt, alpha_deg, max_inner, drop_orders):
         hist = np.zeros(max_inner + 1)
         n = ctypes.c_int32(0)
@@ -313,3 +377,36 @@ class Batch:
         _check(_lib.fas_batch_profile_read(self.h, ms.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
                                            n.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))))
         return {c: (float(ms[k]), int(n[k])) for k, c in enumerate(PROF_CLASSES)}
+
+
+def _steady_lift_fn():
+    import torch
+
+    class SteadyLift(torch.autograd.Function):
+        """C_L(M, alpha_deg) of the converged steady solution on a State:
+        the forward pass sets the flow parameters and runs FAS cycles to the
+        drop, the backward pass solves the adjoint for dC_L/d(M, alpha)."""
+
+        @staticmethod
+        def forward(ctx, mach, alpha_deg, state, max_cycles, drop_orders, adj_iter, adj_drop):
+            p = state.params
+            p.mach = float(mach)
+            p.alpha_deg = float(alpha_deg)
+            state.set_params(p)
+            state.cycle(max_cycles, drop_orders)
+            cl, _ = state.forces()
+            ctx.state = state
+            ctx.adj = (adj_iter, adj_drop)
+            return torch.tensor(cl, dtype=torch.float64)
+
+        @staticmethod
+        def backward(ctx, g):
+            _, grad, _, _ = ctx.state.lift_gradient(*ctx.adj)
+            return (g * grad[1], g * grad[0], None, None, None, None, None)
+
+    return SteadyLift
+
+
+def steady_lift(mach, alpha_deg, state, max_cycles=400, drop_orders=10.0, adj_iter=2000, adj_drop=10.0):
+    """Differentiable C_L(M, alpha) (torch scalars) of a converged State."""
+    return _steady_lift_fn().apply(mach, alpha_deg, state, max_cycles, drop_orders, adj_iter, adj_drop)

@@ -1,0 +1,197 @@
+"""Discrete adjoint on the GPU against the oracle's complex-step dense
+Jacobian, dense SGS transpose and dense adjoint gradient, and the lift
+gradient against central finite differences of converged solutions
+(needs a GPU)."""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+import fas_inputs as fi
+from oracle import adjoint as oadj
+from oracle import fas as ofas
+
+pytestmark = pytest.mark.gpu
+
+TOL_ADJ = 1e-10
+
+
+def _case(kind):
+    if kind == "box_euler":
+        # the bump state has exactly uniform pressure: every pressure-sensor
+        # numerator would sit on the kink of |.|, so the pressure is perturbed
+        x, y = fi.box_grid(24, 20)
+        u = fi.perturbed_state(fi.box_initial_state(x, y), 0.01, seed=12)
+        return dict(topo=fi.BOX, x=x, y=y, nw=0, u=u, model=0, mach=0.8, alpha=0.0)
+    model = 0 if kind.endswith("euler") else 1
+    x, y = fi.cgrid(32, 16, 4)
+    u = fi.perturbed_state(fi.uniform_state(32, 16, 0.7, 1.3), 0.01, seed=11)
+    return dict(topo=fi.CGRID, x=x, y=y, nw=4, u=u, model=model, mach=0.7, alpha=1.3)
+
+
+def _pair(c, levels=1, **kw):
+    from paper_1710_04875_amd import fas
+    par = dict(model=c["model"], mach=c["mach"], alpha_deg=c["alpha"], n_levels=levels, **kw)
+    g = fas.Grid(c["topo"], c["x"], c["y"], c["nw"], levels)
+    st = fas.State(g, fas.Params(**par), torch.from_numpy(c["u"]).cuda())
+    S = ofas.Solver(c["x"], c["y"], c["topo"], c["nw"],
+                    ofas.Params(**{k: v for k, v in par.items() if k in ofas.Params.__dataclass_fields__}),
+                    c["u"])
+    return g, st, S
+
+
+def _np(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+def _rel(a, b):
+    return float(np.abs(a - b).max() / np.abs(b).max())
+
+
+KINDS = ["box_euler", "cgrid_euler", "cgrid_rans"]
+
+
+@pytest.mark.parametrize("kind", KINDS)
+def test_vjp_matches_oracle_dense_transpose(kind):
+    c = _case(kind)
+    g, st, S = _pair(c)
+    mutp = oadj.frozen_mut(S, c["u"])
+    J = oadj.dense_jacobian(S, c["u"], mutp)
+    lam = np.random.default_rng(5).standard_normal(c["u"].shape)
+    ref = (J.T @ lam.reshape(-1)).reshape(lam.shape)
+    out = _np(st.vjp(torch.from_numpy(lam).cuda()))
+    assert _rel(out, ref) < TOL_ADJ
+
+
+@pytest.mark.parametrize("kind", KINDS)
+def test_parameter_partials_match_oracle(kind):
+    c = _case(kind)
+    g, st, S = _pair(c)
+    mutp = oadj.frozen_mut(S, c["u"])
+    da, dm = oadj.residual_param_partials(S, c["u"], mutp)
+    ga, gm, gcl = st.param_partials()
+    assert _rel(_np(ga), da) < TOL_ADJ
+    assert _rel(_np(gm), dm) < TOL_ADJ
+    _, cla, clm = oadj.lift_partials(S, c["u"])
+    assert abs(gcl[0] - cla) <= 1e-12 * abs(cla) + 1e-15
+    assert abs(gcl[1] - clm) <= 1e-12 * abs(clm) + 1e-15
+
+
+@pytest.mark.parametrize("kind", ["box_euler", "cgrid_rans"])
+def test_forces_and_lift_gradient_in_u_match_oracle(kind):
+    c = _case(kind)
+    g, st, S = _pair(c)
+    cl, cd, dcl = st.forces(with_grad=True)
+    ocl, ocd = oadj.forces(S, c["u"])
+    assert abs(cl - ocl) <= 1e-12 * max(abs(ocl), 1e-3)
+    assert abs(cd - ocd) <= 1e-12 * max(abs(ocd), 1e-3)
+    og, _, _ = oadj.lift_partials(S, c["u"])
+    assert _rel(_np(dcl), og) < 1e-12
+
+
+@pytest.mark.parametrize("kind", ["box_euler", "cgrid_euler", "cgrid_rans"])
+def test_transposed_sgs_matches_dense(kind):
+    c = _case(kind)
+    g, st, S = _pair(c, cfl=50.0, cfl_ramp=50.0)
+    _, dts, _, B = S.prepare(0)
+    r = np.random.default_rng(3).standard_normal(c["u"].shape)
+    DL, DD, DU = B.dense()
+    P = DL @ np.linalg.solve(DD, DU)
+    rc = np.moveaxis(r, 0, -1).reshape(-1)
+    xd = np.moveaxis(np.linalg.solve(P.T, rc).reshape(r.shape[1], r.shape[2], 4), -1, 0)
+    x = _np(st.sgs_apply_transpose(torch.from_numpy(r).cuda()))
+    assert _rel(x, xd) < 1e-12
+
+
+GRID_FD = (32, 16, 4)
+
+
+def _converged_state(alpha, mach=0.5, model=0):
+    """32 x 16 C-grid, 3-level V-cycles to a 12-order drop."""
+    from paper_1710_04875_amd import fas
+    ni, nj, nw = GRID_FD
+    x, y = fi.cgrid(ni, nj, nw)
+    par = fas.Params(model=model, mach=mach, alpha_deg=alpha, n_levels=3, cycle_gamma=1, nu1=1,
+                     cfl=20.0, cfl_ramp=5.0, n_ramp=1, ramp_growth=1.5)
+    g = fas.Grid(fi.CGRID, x, y, nw, 3)
+    st = fas.State(g, par, torch.from_numpy(fi.uniform_state(ni, nj, mach, alpha)).cuda())
+    h, status = st.cycle(4000, 12.0)
+    assert status == 0, (len(h), h[-1] / h[0])
+    return g, st
+
+
+def _oracle_at(st, model, alpha, mach):
+    u = _np(st.get_state())
+    ni, nj, nw = GRID_FD
+    x, y = fi.cgrid(ni, nj, nw)
+    return ofas.Solver(x, y, fi.CGRID, nw, ofas.Params(model=model, mach=mach, alpha_deg=alpha), u), u
+
+
+@pytest.mark.parametrize("model", [0, 1])
+def test_adjoint_solve_matches_dense_solve(model):
+    """GMRES on the adjoint system at a converged state (the exact Jacobian
+    of the switched scheme at an arbitrary state need not be dissipative)."""
+    g, st = _converged_state(1.5, 0.5, model)
+    S, u = _oracle_at(st, model, 1.5, 0.5)
+    J = oadj.dense_jacobian(S, u, oadj.frozen_mut(S, u))
+    rhs = np.random.default_rng(7).standard_normal(u.shape)
+    lam_d = np.linalg.solve(J.T, rhs.reshape(-1)).reshape(rhs.shape)
+    lam, hist, status = st.adjoint_solve(torch.from_numpy(rhs).cuda(), 3000, 10.0)
+    assert status == 0, (len(hist), hist[-1] / hist[0])
+    assert _rel(_np(lam), lam_d) < 1e-7
+
+
+def _cl(alpha, mach):
+    return _converged_state(alpha, mach)[1].forces()[0]
+
+
+def _richardson(f, x, h):
+    """Central difference extrapolated from steps h and h/2 (O(h^4))."""
+    d1 = (f(x + h) - f(x - h)) / (2 * h)
+    d2 = (f(x + h / 2) - f(x - h / 2)) / h
+    return (4.0 * d2 - d1) / 3.0
+
+
+def test_lift_gradient_matches_central_differences():
+    """dC_L/dalpha and dC_L/dM of converged Euler solutions (frozen
+    turbulence does not enter) against central differences.  The discrete
+    C_L(M) switches a JST limiter (max / min) within about 1e-5 of M = 0.5:
+    central differences with h >= 3e-5 straddle the switch (they settle at
+    0.109870 against 0.109866 on the smooth piece), so the Mach step is
+    3e-6, the 12-order convergence keeping C_L to about 1e-13."""
+    alpha, mach = 1.5, 0.5
+    g, st = _converged_state(alpha, mach)
+    cl, grad, hist, status = st.lift_gradient(3000, 11.0)
+    assert status == 0
+    fd_a = _richardson(lambda a: _cl(a, mach), alpha, 2e-3)
+    hm = 3e-6
+    fd_m = (_cl(alpha, mach + hm) - _cl(alpha, mach - hm)) / (2 * hm)
+    assert abs(grad[0] - fd_a) <= 1e-5 * abs(fd_a), (grad[0], fd_a)
+    assert abs(grad[1] - fd_m) <= 1e-5 * abs(fd_m), (grad[1], fd_m)
+    assert cl > 0.0 and grad[0] > 0.0        # lift grows with the angle of attack
+
+
+@pytest.mark.parametrize("model", [0, 1])
+def test_lift_gradient_matches_oracle_dense_adjoint(model):
+    alpha, mach = 1.5, 0.5
+    g, st = _converged_state(alpha, mach, model)
+    cl, grad, hist, status = st.lift_gradient(3000, 11.0)
+    assert status == 0
+    S, u = _oracle_at(st, model, alpha, mach)
+    (ga, gm), _ = oadj.lift_gradient(S, u)
+    assert abs(grad[0] - ga) <= 1e-8 * abs(ga)
+    assert abs(grad[1] - gm) <= 1e-8 * abs(gm)
+
+
+def test_steady_lift_autograd():
+    from paper_1710_04875_amd import fas
+    alpha, mach = 1.5, 0.5
+    g, st = _converged_state(alpha, mach)
+    m = torch.tensor(mach, dtype=torch.float64, requires_grad=True)
+    a = torch.tensor(alpha, dtype=torch.float64, requires_grad=True)
+    cl = fas.steady_lift(m, a, st, max_cycles=50, drop_orders=11.0, adj_iter=3000, adj_drop=11.0)
+    cl.backward()
+    _, grad, _, _ = st.lift_gradient(3000, 11.0)
+    assert abs(a.grad.item() - grad[0]) <= 1e-10 * abs(grad[0])
+    assert abs(m.grad.item() - grad[1]) <= 1e-10 * abs(grad[1])

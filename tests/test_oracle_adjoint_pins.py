@@ -1,0 +1,90 @@
+"""Pins of the oracle's discrete adjoint against facts that do not come from
+the adjoint code itself: central differences of the residual, the closure
+of the airfoil surface, and the direct (forward) sensitivity (CPU only)."""
+import numpy as np
+import pytest
+
+import fas_inputs as fi
+from oracle import adjoint as adj
+from oracle import fas
+
+
+def _state(model, ni=32, nj=16, nw=4, mach=0.7, alpha=1.3, seed=11):
+    x, y = fi.cgrid(ni, nj, nw)
+    u = fi.perturbed_state(fi.uniform_state(ni, nj, mach, alpha), 0.01, seed=seed)
+    S = fas.Solver(x, y, fi.CGRID, nw, fas.Params(model=model, mach=mach, alpha_deg=alpha), u)
+    return S, u
+
+
+@pytest.mark.parametrize("model", [0, 1])
+def test_complex_step_product_matches_central_differences(model):
+    S, u = _state(model)
+    mutp = adj.frozen_mut(S, u)
+    v = np.random.default_rng(0).standard_normal(u.shape)
+    jv = adj.fine_residual(S, u + 1j * adj.H_CS * v, mutp).imag / adj.H_CS
+    h = 1e-6
+    fd = (adj.fine_residual(S, u + h * v, mutp) - adj.fine_residual(S, u - h * v, mutp)) / (2 * h)
+    assert np.abs(jv - fd).max() <= 1e-8 * np.abs(jv).max()
+    # the real part of the complex evaluation is the residual itself (up to
+    # the rounding of complex division)
+    F = adj.fine_residual(S, u + 1j * adj.H_CS * v, mutp).real
+    F0 = S.residual(0)
+    assert np.abs(F - F0).max() <= 1e-14 * np.abs(F0).max()
+
+
+def test_dense_jacobian_columns_are_directional_derivatives():
+    S, u = _state(1, ni=16, nj=8, nw=2)
+    mutp = adj.frozen_mut(S, u)
+    J = adj.dense_jacobian(S, u, mutp)
+    v = np.random.default_rng(1).standard_normal(u.shape)
+    jv = adj.fine_residual(S, u + 1j * adj.H_CS * v, mutp).imag / adj.H_CS
+    assert np.abs(J @ v.reshape(-1) - jv.reshape(-1)).max() <= 1e-12 * np.abs(jv).max()
+
+
+@pytest.mark.parametrize("model", [0, 1])
+def test_parameter_derivatives_match_central_differences(model):
+    S, u = _state(model)
+    mutp = adj.frozen_mut(S, u)
+    da, dm = adj.residual_param_partials(S, u, mutp)
+    h = 1e-5
+    fa = (adj.fine_residual(S, u, mutp, alpha_deg=1.3 + h)
+          - adj.fine_residual(S, u, mutp, alpha_deg=1.3 - h)) / (2 * h)
+    fm = (adj.fine_residual(S, u, mutp, mach=0.7 + h) - adj.fine_residual(S, u, mutp, mach=0.7 - h)) / (2 * h)
+    assert np.abs(da - fa).max() <= 1e-6 * np.abs(da).max()
+    assert np.abs(dm - fm).max() <= 1e-6 * np.abs(dm).max()
+
+
+def test_uniform_pressure_exerts_no_force_on_the_closed_airfoil():
+    x, y = fi.cgrid(64, 32, 8)
+    for alpha in (0.0, 2.0):
+        u = fi.uniform_state(64, 32, 0.7, alpha)
+        S = fas.Solver(x, y, fi.CGRID, 8, fas.Params(model=0, mach=0.7, alpha_deg=alpha), u)
+        cl, cd = adj.forces(S, u)
+        assert abs(cl) < 1e-12 and abs(cd) < 1e-12
+
+
+def test_lift_partials_match_central_differences():
+    S, u = _state(0)
+    g, cla, clm = adj.lift_partials(S, u)
+    v = np.random.default_rng(2).standard_normal(u.shape)
+    h = 1e-6
+    fd = (adj.forces(S, u + h * v)[0] - adj.forces(S, u - h * v)[0]) / (2 * h)
+    assert abs(np.sum(g * v) - fd) <= 1e-7 * abs(fd)
+    fa = (adj.forces(S, u, alpha_deg=1.3 + 1e-5)[0] - adj.forces(S, u, alpha_deg=1.3 - 1e-5)[0]) / 2e-5
+    assert abs(cla - fa) <= 1e-7 * abs(fa)
+
+
+@pytest.mark.parametrize("model", [0, 1])
+def test_adjoint_gradient_equals_direct_sensitivity(model):
+    """dC_L/dq = dC_L/dq|_u + g . du/dq with J du/dq = -dF/dq (direct)
+    equals the adjoint form dC_L/dq|_u + lam . dF/dq, J^T lam = -g."""
+    S, u = _state(model, ni=16, nj=8, nw=2)
+    mutp = adj.frozen_mut(S, u)
+    J = adj.dense_jacobian(S, u, mutp)
+    g, cla, clm = adj.lift_partials(S, u)
+    da, dm = adj.residual_param_partials(S, u, mutp)
+    (ga, gm), lam = adj.lift_gradient(S, u)
+    dua = np.linalg.solve(J, -da.reshape(-1))
+    dum = np.linalg.solve(J, -dm.reshape(-1))
+    assert abs(ga - (cla + g.reshape(-1) @ dua)) <= 1e-8 * abs(ga)
+    assert abs(gm - (clm + g.reshape(-1) @ dum)) <= 1e-8 * abs(gm)
