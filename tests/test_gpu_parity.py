@@ -88,3 +88,21 @@ def test_dual_time_step_parity():
         S.begin_time_step(dt, alpha)
         S.run_cycles(2)
         assert state_err(_np(st.get_state()), S.u(0)) < TOL_STATE, step
+
+
+@pytest.mark.parametrize("kind", ["box_small", "cgrid_small_rans"])
+@pytest.mark.parametrize("scheme", [2, 3, 4, 5])
+def test_five_stage_smoothers(kind, scheme):
+    """AW5J, AW51, AW52 and pARK51 (the five-stage rows of the coefficient
+    table) run on the same kernels: one iteration and one V-cycle."""
+    inp = case_inputs(kind)
+    cfl = 1.0 if scheme == 5 else 50.0
+    g, st, S = make_pair(inp, scheme=scheme, cfl=cfl, cfl_ramp=cfl)
+    st.smooth(0, 1)
+    S.smooth(0)
+    assert state_err(_np(st.get_state()), S.u(0)) < TOL_STATE
+    levels = 2 if kind == "box_small" else 3
+    g, st, S = make_pair(inp, scheme=scheme, n_levels=levels, cfl=cfl, cfl_ramp=cfl)
+    st.cycle(1)
+    S.run_cycles(1)
+    assert state_err(_np(st.get_state()), S.u(0)) < TOL_STATE
