@@ -144,6 +144,24 @@ fas_status fas_dual_time_step(fas_state s, double dt, double alpha_deg, int32_t 
                               double drop_orders, double *res_hist, int32_t *n_inner);
 
 /*
+ * Rigid-body pitching on a moving mesh (arbitrary Lagrangian-Eulerian
+ * finite volumes; the paper's pitching airfoils, Section 6; the grid-motion
+ * terms are a reading, Section 2 does not print them).  The body is turned
+ * nose-up by dalpha_deg about (pivot_x, pivot_y), i.e. the whole mesh of
+ * every level rotates by -dalpha_deg, turning at -rate_deg (degrees per
+ * unit time); the free stream keeps the angle of the parameters.  Face
+ * fluxes gain -(w . S) (u_L + u_R) / 2 with w the grid velocity at the face
+ * midpoint, spectral radii, far-field Riemann states and the split
+ * Jacobians use velocities relative to the mesh, walls move with it (a
+ * moving wall does the pressure work p_w (w . S)); volumes are unchanged.
+ * Call before fas_dual_time_step for the state at t_{n+1} (with alpha_deg
+ * of that call kept at the free-stream angle).  The first call allocates
+ * per-state geometry.  The adjoint entry points and batches reject moving
+ * meshes.  Errors: FAS_EINVAL, FAS_ENOMEM, FAS_EDEVICE.
+ */
+fas_status fas_set_motion(fas_state s, double dalpha_deg, double rate_deg, double pivot_x, double pivot_y);
+
+/*
  * Opt-in timing of kernel classes with HIP events recorded on the state's
  * stream around each launch (adds a little launch overhead while on).
  * fas_profile resets the counters and switches timing on (enable = 1) or

@@ -66,6 +66,52 @@ def wall_ghost(Ui, nx, ny, noslip: bool):
     return np.stack([rho, mx - 2.0 * mn * nx, my - 2.0 * mn * ny, Ui[3]])
 
 
+def _relative(U, wx, wy):
+    """The state seen from a boundary moving at w: velocity v - w, same
+    density and pressure."""
+    rho = U[0]
+    p = gas.pressure(U)
+    mx = U[1] - rho * wx
+    my = U[2] - rho * wy
+    return np.stack([rho, mx, my, p / (GAMMA - 1.0) + 0.5 * (mx * mx + my * my) / rho])
+
+
+def _absolute(U, wx, wy):
+    """Inverse of _relative."""
+    rho = U[0]
+    p = gas.pressure(U)
+    mx = U[1] + rho * wx
+    my = U[2] + rho * wy
+    return np.stack([rho, mx, my, p / (GAMMA - 1.0) + 0.5 * (mx * mx + my * my) / rho])
+
+
+def moving_wall_ghost(Ui, nx, ny, wx, wy, noslip: bool):
+    """Wall moving at w: no-slip v_g = 2 w - v, slip: the velocity relative
+    to the wall mirrored; density and pressure mirrored."""
+    rho = Ui[0]
+    p = gas.pressure(Ui)
+    if noslip:
+        mx = 2.0 * rho * wx - Ui[1]
+        my = 2.0 * rho * wy - Ui[2]
+    else:
+        rx = Ui[1] - rho * wx
+        ry = Ui[2] - rho * wy
+        rn = rx * nx + ry * ny
+        mx = (rx - 2.0 * rn * nx) + rho * wx
+        my = (ry - 2.0 * rn * ny) + rho * wy
+    return np.stack([rho, mx, my, p / (GAMMA - 1.0) + 0.5 * (mx * mx + my * my) / rho])
+
+
+def _farfield_moving(Ui, uinf, nx, ny, w):
+    """Riemann far field for a boundary moving at w (None: fixed)."""
+    if w is None:
+        return riemann_farfield(Ui, uinf, nx, ny)
+    wx, wy = w
+    ur = _relative(Ui, wx, wy)
+    fr = _relative(np.broadcast_to(uinf, Ui.shape), wx, wy)
+    return _absolute(riemann_farfield(ur, fr, nx, ny), wx, wy)
+
+
 def _unit(sx, sy):
     ln = np.sqrt(sx * sx + sy * sy)
     return sx / ln, sy / ln
@@ -82,25 +128,32 @@ def fill_ghosts(Up, lev, Uinf, noslip: bool):
     # bottom (j < 0)
     nbx, nby = _unit(lev.Seta[0][0], lev.Seta[1][0])          # +j, into the domain
     ntx, nty = _unit(lev.Seta[0][nj], lev.Seta[1][nj])        # +j, out of the domain
+    moving = lev.weta is not None
     for k in range(P):
         jg = P - 1 - k
         Ui = Up[:, P + k, P:P + ni]
-        g = wall_ghost(Ui, nbx, nby, noslip)
+        if moving:
+            g = moving_wall_ghost(Ui, nbx, nby, lev.weta[0][0], lev.weta[1][0], noslip)
+        else:
+            g = wall_ghost(Ui, nbx, nby, noslip)
         if lev.topology == CGRID:
             partner = Up[:, P + k, P + (ni - 1 - ii)]
             g = np.where(cut[None, :], partner, g)
         Up[:, jg, P:P + ni] = g
         Ui = Up[:, P + nj - 1 - k, P:P + ni]
-        Up[:, P + nj + k, P:P + ni] = riemann_farfield(Ui, uinf, ntx, nty)
+        wt = (lev.weta[0][nj], lev.weta[1][nj]) if moving else None
+        Up[:, P + nj + k, P:P + ni] = _farfield_moving(Ui, uinf, ntx, nty, wt)
     # sides, every padded row
     jc = np.clip(np.arange(nj + 2 * P) - P, 0, nj - 1)
     nwx, nwy = _unit(-lev.Sxi[0][jc, 0], -lev.Sxi[1][jc, 0])  # outward at i = 0
     nex, ney = _unit(lev.Sxi[0][jc, ni], lev.Sxi[1][jc, ni])  # outward at i = ni
+    ww = (lev.wxi[0][jc, 0], lev.wxi[1][jc, 0]) if moving else None
+    we = (lev.wxi[0][jc, ni], lev.wxi[1][jc, ni]) if moving else None
     for k in range(P):
         Ui = Up[:, :, P + k]
-        Up[:, :, P - 1 - k] = riemann_farfield(Ui, uinf, nwx, nwy)
+        Up[:, :, P - 1 - k] = _farfield_moving(Ui, uinf, nwx, nwy, ww)
         Ui = Up[:, :, P + ni - 1 - k]
-        Up[:, :, P + ni + k] = riemann_farfield(Ui, uinf, nex, ney)
+        Up[:, :, P + ni + k] = _farfield_moving(Ui, uinf, nex, ney, we)
     return Up
 
 

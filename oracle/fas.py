@@ -273,6 +273,20 @@ class Solver:
                 break
         return np.array(hist)
 
+    # ------------------------------------------------------ moving mesh
+    def set_motion(self, dalpha_deg: float, rate_deg: float, pivot=(0.25, 0.0)):
+        """Rigid-body pitching: the body is turned nose-up by dalpha about
+        the pivot, i.e. the whole mesh rotates by -dalpha, turning at
+        -rate (degrees per unit time); the free stream keeps its angle.
+        Reading: moving-mesh (ALE) finite volumes, Section 2 does not state
+        the grid-motion terms."""
+        from .geometry import rotated
+        if not hasattr(self, "levels_ref"):
+            self.levels_ref = self.levels
+        theta = -dalpha_deg * (np.pi / 180.0)
+        omega = -rate_deg * (np.pi / 180.0)
+        self.levels = [rotated(lev, theta, omega, pivot[0], pivot[1]) for lev in self.levels_ref]
+
     # ---------------------------------------------------------- dual time
     def begin_time_step(self, dt: float, alpha_deg: float = None):
         """Shift the time levels and switch to the physical-time equation:

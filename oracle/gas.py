@@ -107,10 +107,15 @@ def cutoff_abs(lam, a, d: float):
     return np.where(al <= ad, 0.5 * (ad + al * al / ad), al)
 
 
-def split_jacobians(U, nx, ny, d: float):
-    """(A+, A-) = ((A + |A|_c)/2, (A - |A|_c)/2) at state U, unit normal n."""
+def split_jacobians(U, nx, ny, d: float, shift=None):
+    """(A+, A-) = ((A + |A|_c)/2, (A - |A|_c)/2) at state U, unit normal n.
+    On a moving face the normal flux is F.n - w_n u, so A and its
+    eigenvalues are shifted by the face's normal grid speed ``shift``."""
     A = flux_jacobian(U, nx, ny)
     lam, R, L, a = eigensystem(U, nx, ny)
+    if shift is not None:
+        A = A - shift[..., None, None] * np.eye(4)
+        lam = lam - shift[..., None]
     al = cutoff_abs(lam, a, d)
     absA = np.einsum("...ik,...k,...kj->...ij", R, al, L)
     return 0.5 * (A + absA), 0.5 * (A - absA)

@@ -121,6 +121,8 @@ class Level:
                 sb[:, jp, ie] = sb[:, src[0], src[1]]
                 vp[jp, ie] = vp[src]
         self.xc, self.yc, self.sbar, self.volp = xc, yc, sb, vp
+        # grid velocities of a moving (rigidly rotating) mesh; None: fixed
+        self.wxi = self.weta = self.wc = None
         # wall (or cut) distance: cell centre to the midpoint of face (i, J=0)
         self.wall_dist = np.sqrt(
             (xc[P:P + nj, P:P + ni] - self.meta[0][0][None, :]) ** 2
@@ -143,6 +145,44 @@ class Level:
         vc = ((v[0::2, 0::2] + v[0::2, 1::2]) + v[1::2, 0::2]) + v[1::2, 1::2]
         return Level(self.x[::2, ::2], self.y[::2, ::2], self.topology,
                      self.n_wake // 2, vol=vc)
+
+
+def rotated(lev: Level, theta: float, omega: float, px: float, py: float) -> Level:
+    """The level rigidly rotated by theta (radians, counter-clockwise)
+    about (px, py) and spinning at omega (radians per unit time): face
+    vectors, mean face vectors, centres and face midpoints rotate, volumes
+    and wall distances do not.  Grid velocities omega x (r - pivot) are
+    attached at the face midpoints (wxi, weta) and at the padded cell
+    centres (wc) for the moving-mesh (ALE) terms."""
+    import copy
+    import math
+    c, s = math.cos(theta), math.sin(theta)
+
+    def vec(vx, vy):
+        return c * vx - s * vy, s * vx + c * vy
+
+    def pt(x, y):
+        dx, dy = x - px, y - py
+        return px + (c * dx - s * dy), py + (s * dx + c * dy)
+
+    r = copy.copy(lev)
+    r.x, r.y = pt(lev.x, lev.y)
+    r.Sxi = np.stack(vec(lev.Sxi[0], lev.Sxi[1]))
+    r.Seta = np.stack(vec(lev.Seta[0], lev.Seta[1]))
+    sb0, sb1 = vec(lev.sbar[0], lev.sbar[1])
+    sb2, sb3 = vec(lev.sbar[2], lev.sbar[3])
+    r.sbar = np.stack([sb0, sb1, sb2, sb3])
+    r.xc, r.yc = pt(lev.xc, lev.yc)
+    r.mxi = pt(lev.mxi[0], lev.mxi[1])
+    r.meta = pt(lev.meta[0], lev.meta[1])
+
+    def gv(x, y):
+        return -omega * (y - py), omega * (x - px)
+
+    r.wxi = gv(*r.mxi)
+    r.weta = gv(*r.meta)
+    r.wc = gv(r.xc, r.yc)
+    return r
 
 
 def build_levels(x, y, topology: int, n_wake: int, n_levels: int):

@@ -76,15 +76,18 @@ def face_split(lev, Up, d: float):
     P = NG
     ni, nj = lev.ni, lev.nj
     out = []
-    for (S, UL, UR) in (
-        (lev.Sxi, Up[:, P:P + nj, P - 1:P + ni], Up[:, P:P + nj, P:P + ni + 1]),
-        (lev.Seta, Up[:, P - 1:P + nj, P:P + ni], Up[:, P:P + nj + 1, P:P + ni]),
+    for (S, UL, UR, W) in (
+        (lev.Sxi, Up[:, P:P + nj, P - 1:P + ni], Up[:, P:P + nj, P:P + ni + 1], lev.wxi),
+        (lev.Seta, Up[:, P - 1:P + nj, P:P + ni], Up[:, P:P + nj + 1, P:P + ni], lev.weta),
     ):
         ln = np.sqrt(S[0] * S[0] + S[1] * S[1])
         nx = S[0] / ln
         ny = S[1] / ln
         Uf = 0.5 * (UL + UR)
-        Ap, Am = gas.split_jacobians(Uf, nx, ny, d)
+        shift = None
+        if W is not None:          # moving mesh: normal grid speed of the face
+            shift = (W[0] * S[0] + W[1] * S[1]) / ln
+        Ap, Am = gas.split_jacobians(Uf, nx, ny, d, shift)
         out.append((ln[..., None, None] * Ap, ln[..., None, None] * Am))
     return out
 

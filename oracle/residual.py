@@ -77,8 +77,13 @@ def cell_scalars(lev, Up, rans: bool):
     a = np.sqrt(GAMMA * p / rho)
     q = p / rho ** GAMMA if rans else p
     sb = lev.sbar
-    rxi = _abs(vx * sb[0] + vy * sb[1]) + a * np.sqrt(sb[0] * sb[0] + sb[1] * sb[1])
-    reta = _abs(vx * sb[2] + vy * sb[3]) + a * np.sqrt(sb[2] * sb[2] + sb[3] * sb[3])
+    vnx = vx * sb[0] + vy * sb[1]
+    vne = vx * sb[2] + vy * sb[3]
+    if lev.wc is not None:         # moving mesh: velocity relative to the cell
+        vnx = vnx - (lev.wc[0] * sb[0] + lev.wc[1] * sb[1])
+        vne = vne - (lev.wc[0] * sb[2] + lev.wc[1] * sb[3])
+    rxi = _abs(vnx) + a * np.sqrt(sb[0] * sb[0] + sb[1] * sb[1])
+    reta = _abs(vne) + a * np.sqrt(sb[2] * sb[2] + sb[3] * sb[3])
     t = reta / rxi
     rtxi = rxi * (1.0 + _cbrt(t * t))
     t = rxi / reta
@@ -128,6 +133,9 @@ def convective_faces(lev, Up, par, second_order: bool):
     UL, UR = Up[:, rows, sl(1)], Up[:, rows, sl(2)]
     pL, pR = p[rows, sl(1)], p[rows, sl(2)]
     Cxi = 0.5 * (gas.normal_flux(UL, pL, sx, sy) + gas.normal_flux(UR, pR, sx, sy))
+    if lev.wxi is not None:        # moving face: - (w . S) times the mean state
+        qxi = lev.wxi[0] * sx + lev.wxi[1] * sy
+        Cxi = Cxi - qxi * (0.5 * (UL + UR))
     sxi = None
     if second_order:
         s = np.zeros_like(q)
@@ -145,6 +153,10 @@ def convective_faces(lev, Up, par, second_order: bool):
     UL, UR = Up[:, sj(1), cols], Up[:, sj(2), cols]
     pL, pR = p[sj(1), cols], p[sj(2), cols]
     Ceta = 0.5 * (gas.normal_flux(UL, pL, sx, sy) + gas.normal_flux(UR, pR, sx, sy))
+    qeta = None
+    if lev.weta is not None:
+        qeta = lev.weta[0] * sx + lev.weta[1] * sy
+        Ceta = Ceta - qeta * (0.5 * (UL + UR))
     seta = None
     if second_order:
         s = np.zeros_like(q)
@@ -163,7 +175,8 @@ def convective_faces(lev, Up, par, second_order: bool):
     Ceta[0, 0, wallcols] = 0.0
     Ceta[1, 0, wallcols] = (pw * sx[0])[wallcols]
     Ceta[2, 0, wallcols] = (pw * sy[0])[wallcols]
-    Ceta[3, 0, wallcols] = 0.0
+    # a moving wall does the pressure work p_w (w . S)
+    Ceta[3, 0, wallcols] = 0.0 if qeta is None else (pw * qeta[0])[wallcols]
     Deta[:, 0, wallcols] = 0.0
     return Cxi, Dxi, Ceta, Deta
 

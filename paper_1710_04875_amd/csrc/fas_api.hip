@@ -117,6 +117,11 @@ struct fas_state_s {
     Engine e;
     int have_un = 0;
     Phys *d_ph = nullptr;
+    LevelDev *d_lv = nullptr;             // device copy of lv
+    // rigidly rotating mesh: per-level rotated geometry and the motion
+    std::vector<double *> ale_geo;
+    int ale = 0;
+    double ale_omega = 0.0, ale_px = 0.0, ale_py = 0.0;
     std::vector<void *> allocs;
     // adjoint work arrays (padded fine level), allocated on first use
     double *a_lam = nullptr, *a_g = nullptr, *a_r = nullptr, *a_z = nullptr, *a_jt = nullptr,
@@ -283,12 +288,18 @@ static void fill_phys(const fas_params &p, Phys &ph) {
     ph.ramp_growth = p.ramp_growth;
     ph.n_ramp = p.n_ramp;
     ph.rans = p.model == FAS_RANS_BL;
+    ph.ale = 0;
+    ph.omega = ph.px = ph.py = 0.0;
 }
 
 // host parameters -> device copy; waits for the state's earlier work, which
 // may still read the old values
 static fas_status set_phys(fas_state s) {
     fill_phys(s->p, s->ph);
+    s->ph.ale = s->ale;
+    s->ph.omega = s->ale_omega;
+    s->ph.px = s->ale_px;
+    s->ph.py = s->ale_py;
     Engine &e = s->e;
     e.model = s->p.model;
     e.fp32 = s->p.precond_fp32;
@@ -380,6 +391,7 @@ extern "C" fas_status fas_state_create(fas_grid g, const fas_params *p, const do
     if (hipMalloc(&dd, desc + 64) != hipSuccess) return cleanup(fail(FAS_ENOMEM, "allocation failed"));
     s->allocs.push_back(dd);
     LevelDev *dV = reinterpret_cast<LevelDev *>(dd);
+    s->d_lv = dV;
     s->d_ph = reinterpret_cast<Phys *>(dd + (size_t)s->nlev * sizeof(LevelDev));
     e.d_norm = reinterpret_cast<double *>(dd + desc - 64);
     e.d_cyc = reinterpret_cast<int *>(dd + desc);
@@ -400,6 +412,39 @@ extern "C" fas_status fas_state_set_params(fas_state s, const fas_params *p) {
     STCHK(check_params(p, s->g->nlev));
     if (p->n_levels != s->nlev) return fail(FAS_EINVAL, "n_levels cannot change after creation");
     s->p = *p;
+    return set_phys(s);
+}
+
+extern "C" fas_status fas_set_motion(fas_state s, double dalpha_deg, double rate_deg, double pivot_x,
+                                      double pivot_y) {
+    if (!s) return fail(FAS_EINVAL, "null state");
+    if (!std::isfinite(dalpha_deg) || !std::isfinite(rate_deg) || !std::isfinite(pivot_x) ||
+        !std::isfinite(pivot_y))
+        return fail(FAS_EINVAL, "bad motion");
+    Engine &e = s->e;
+    HIPCHK(hipStreamSynchronize(e.st));
+    if (s->ale_geo.empty()) {
+        for (int l = 0; l < s->nlev; ++l) {
+            double *g = nullptr;
+            HIPCHK(hipMalloc(&g, (size_t)G_NPLANES * s->lv[l].L.NS * sizeof(double)));
+            s->allocs.push_back(g);
+            s->ale_geo.push_back(g);
+        }
+    }
+    const double theta = -dalpha_deg * (M_PI / 180.0);
+    const double omega = -rate_deg * (M_PI / 180.0);
+    const double c = std::cos(theta), sn = std::sin(theta);
+    for (int l = 0; l < s->nlev; ++l) {
+        launch_rotate_geometry(s->lv[l].L, s->g->geo[l], s->g->xn[l], s->g->yn[l], s->ale_geo[l], c, sn,
+                               pivot_x, pivot_y, omega, e.st);
+        s->lv[l].geo = s->ale_geo[l];
+    }
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipMemcpyAsync(s->d_lv, s->lv.data(), (size_t)s->nlev * sizeof(LevelDev), hipMemcpyHostToDevice, e.st));
+    s->ale = 1;
+    s->ale_omega = omega;
+    s->ale_px = pivot_x;
+    s->ale_py = pivot_y;
     return set_phys(s);
 }
 
@@ -877,6 +922,7 @@ extern "C" fas_status fas_forces(fas_state s, double *cl, double *cd, double *dc
 
 extern "C" fas_status fas_vjp(fas_state s, const double *lam, double *out) {
     if (!s || !lam || !out) return fail(FAS_EINVAL, "null argument");
+    if (s->ale) return fail(FAS_EINVAL, "the adjoint is for fixed meshes");
     STCHK(ensure_adjoint(s));
     const LevelDev &d = s->lv[0];
     prep(s->e, 0, fine_rans(s->e, 0));
@@ -890,6 +936,7 @@ extern "C" fas_status fas_vjp(fas_state s, const double *lam, double *out) {
 
 extern "C" fas_status fas_param_partials(fas_state s, double *dF_dalpha, double *dF_dmach, double *dcl_dparam) {
     if (!s) return fail(FAS_EINVAL, "null state");
+    if (s->ale) return fail(FAS_EINVAL, "the adjoint is for fixed meshes");
     STCHK(ensure_adjoint(s));
     const LevelDev &d = s->lv[0];
     prep(s->e, 0, fine_rans(s->e, 0));
@@ -923,6 +970,7 @@ extern "C" fas_status fas_sgs_apply_transpose(fas_state s, const double *r, doub
 extern "C" fas_status fas_adjoint_solve(fas_state s, const double *rhs, double *lam, int32_t max_iter,
                                         double drop_orders, double *res_hist, int32_t *n_iter) {
     if (!s || !rhs || !lam || max_iter < 0) return fail(FAS_EINVAL, "bad argument");
+    if (s->ale) return fail(FAS_EINVAL, "the adjoint is for fixed meshes");
     STCHK(ensure_adjoint(s));
     const LevelDev &d = s->lv[0];
     launch_unpack(d.L, rhs, s->a_g, 4, s->e.st);
@@ -938,6 +986,7 @@ extern "C" fas_status fas_adjoint_solve(fas_state s, const double *rhs, double *
 extern "C" fas_status fas_lift_gradient(fas_state s, int32_t max_iter, double drop_orders, double *cl,
                                         double *grad, double *res_hist, int32_t *n_iter) {
     if (!s || !grad || max_iter < 0) return fail(FAS_EINVAL, "bad argument");
+    if (s->ale) return fail(FAS_EINVAL, "the adjoint is for fixed meshes");
     STCHK(ensure_adjoint(s));
     Engine &e = s->e;
     const LevelDev &d = s->lv[0];
@@ -1022,7 +1071,8 @@ extern "C" fas_status fas_batch_create(int32_t n, const fas_state *states, void 
             s->p.cycle_gamma != s0->p.cycle_gamma || s->p.nu1 != s0->p.nu1 ||
             s->p.precond_fp32 != s0->p.precond_fp32)
             return fail(FAS_EINVAL, "batched states must share model, scheme, levels, cycle and precision");
-        if (s->e.bdf != 0) return fail(FAS_EINVAL, "batched states must be steady (no dual time step taken)");
+        if (s->e.bdf != 0 || s->ale)
+            return fail(FAS_EINVAL, "batched states must be steady on fixed meshes (no dual time step, no motion)");
         for (int k = 0; k < c; ++k)
             if (states[k] == s) return fail(FAS_EINVAL, "a state appears twice in the batch");
     }

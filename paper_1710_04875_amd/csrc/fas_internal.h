@@ -37,6 +37,8 @@ enum GeoPlane {
     G_SB0, G_SB1, G_SB2, G_SB3,  // mean i- and j- face vectors
     G_VOL, G_XC, G_YC,    // volume, centre
     G_WD,                 // distance to the j = 0 face (fine level, interior)
+    G_WIX, G_WIY,         // moving mesh: grid velocity at the midpoint of i-face (I, j)
+    G_WJX, G_WJY,         // moving mesh: grid velocity at the midpoint of j-face (i, J)
     G_NPLANES
 };
 
@@ -80,6 +82,10 @@ struct Phys {
     double cfl, cfl_ramp, ramp_growth;
     int n_ramp;
     int rans;
+    // rigidly rotating mesh (ALE): rate omega about (px, py); grid
+    // velocities omega x (r - pivot) are in the G_W* planes
+    int ale;
+    double omega, px, py;
 };
 
 struct LevelDev {
@@ -142,6 +148,12 @@ void launch_geom_interior(const Lay &L, const double *xn, const double *yn, doub
                           const double *vol_children, const Lay *Lf, const double *geo_f,
                           hipStream_t st);
 void launch_geom_ghost(const Lay &L, const double *xn, const double *yn, double *geo, hipStream_t st);
+
+// rigid rotation of a level's geometry by (c, s) = (cos, sin) of the
+// angle about (px, py), grid velocities for the rate omega
+void launch_rotate_geometry(const Lay &L, const double *geo_ref, const double *xn, const double *yn,
+                            double *geo, double c, double s, double px, double py, double omega,
+                            hipStream_t st);
 
 // residual chain
 void launch_ghost_state(const BLev &B, int noslip, hipStream_t st);

@@ -167,6 +167,54 @@ __global__ void k_geom_interior(Lay L, const double *xn, const double *yn, doubl
     geo[G_WD * NS + s] = sqrt(cx * cx + cy * cy);
 }
 
+// Rigid rotation of a level (moving mesh): vectors and points rotate by
+// (c, s) about (px, py), volumes and wall distances are unchanged; grid
+// velocities omega x (r - pivot) at the rotated face midpoints.
+__global__ void k_rotate_geometry(Lay L, const double *geo0, const double *xn, const double *yn, double *geo,
+                                  double c, double s, double px, double py, double omega) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    int i, j;
+    if (!decode(L, t, i, j)) return;
+    const int NS = L.NS, W = L.ni + 1;
+    auto vec = [&](int px_, int py_) {
+        const double vx = geo0[px_ * NS + t], vy = geo0[py_ * NS + t];
+        geo[px_ * NS + t] = c * vx - s * vy;
+        geo[py_ * NS + t] = s * vx + c * vy;
+    };
+    vec(G_SXI_X, G_SXI_Y);
+    vec(G_SETA_X, G_SETA_Y);
+    vec(G_SB0, G_SB1);
+    vec(G_SB2, G_SB3);
+    {
+        const double dx = geo0[G_XC * NS + t] - px, dy = geo0[G_YC * NS + t] - py;
+        geo[G_XC * NS + t] = px + (c * dx - s * dy);
+        geo[G_YC * NS + t] = py + (s * dx + c * dy);
+    }
+    geo[G_VOL * NS + t] = geo0[G_VOL * NS + t];
+    geo[G_WD * NS + t] = geo0[G_WD * NS + t];
+    double wix = 0.0, wiy = 0.0, wjx = 0.0, wjy = 0.0;
+    if (i >= 0 && i <= L.ni && j >= 0 && j < L.nj) {          // i-face (i, j)
+        const double mx = 0.5 * (xn[j * W + i] + xn[(j + 1) * W + i]);
+        const double my = 0.5 * (yn[j * W + i] + yn[(j + 1) * W + i]);
+        const double dx = mx - px, dy = my - py;
+        const double rx = px + (c * dx - s * dy), ry = py + (s * dx + c * dy);
+        wix = -omega * (ry - py);
+        wiy = omega * (rx - px);
+    }
+    if (i >= 0 && i < L.ni && j >= 0 && j <= L.nj) {          // j-face (i, j)
+        const double mx = 0.5 * (xn[j * W + i] + xn[j * W + i + 1]);
+        const double my = 0.5 * (yn[j * W + i] + yn[j * W + i + 1]);
+        const double dx = mx - px, dy = my - py;
+        const double rx = px + (c * dx - s * dy), ry = py + (s * dx + c * dy);
+        wjx = -omega * (ry - py);
+        wjy = omega * (rx - px);
+    }
+    geo[G_WIX * NS + t] = wix;
+    geo[G_WIY * NS + t] = wiy;
+    geo[G_WJX * NS + t] = wjx;
+    geo[G_WJY * NS + t] = wjy;
+}
+
 __device__ inline void reflect(double &cx, double &cy, double mx, double my, double sx, double sy) {
     double ln = sqrt(sx * sx + sy * sy);
     double nx = sx / ln, ny = sy / ln;
@@ -287,6 +335,51 @@ __device__ inline void unit(double sx, double sy, double &nx, double &ny) {
     ny = sy / ln;
 }
 
+// a state seen from a boundary moving at (wx, wy) (sign +1: relative,
+// -1: back to absolute): velocity shifted, density and pressure kept
+__device__ void shift_frame(const double in[4], double wx, double wy, double sign, double out[4]) {
+    const double rho = in[0];
+    const double p = pres(in[0], in[1], in[2], in[3]);
+    const double mx = in[1] - sign * (rho * wx), my = in[2] - sign * (rho * wy);
+    out[0] = rho;
+    out[1] = mx;
+    out[2] = my;
+    out[3] = p / (GAM - 1.0) + 0.5 * (mx * mx + my * my) / rho;
+}
+
+// far field of a boundary face moving at w (Riemann invariants of the
+// velocity relative to the face)
+__device__ void farfield_moving(const double ui[4], const double uinf[4], double nx, double ny, double wx,
+                                double wy, double out[4]) {
+    double ur[4], fr[4], br[4];
+    shift_frame(ui, wx, wy, 1.0, ur);
+    shift_frame(uinf, wx, wy, 1.0, fr);
+    farfield(ur, fr, nx, ny, br);
+    shift_frame(br, wx, wy, -1.0, out);
+}
+
+// ghost of a wall moving at w: no-slip v_g = 2 w - v, slip the relative
+// velocity mirrored; density and pressure mirrored
+__device__ void moving_wall(const double ui[4], double nx, double ny, double wx, double wy, int noslip,
+                            double out[4]) {
+    const double rho = ui[0];
+    const double p = pres(ui[0], ui[1], ui[2], ui[3]);
+    double mx, my;
+    if (noslip) {
+        mx = 2.0 * rho * wx - ui[1];
+        my = 2.0 * rho * wy - ui[2];
+    } else {
+        const double rx = ui[1] - rho * wx, ry = ui[2] - rho * wy;
+        const double rn = rx * nx + ry * ny;
+        mx = (rx - 2.0 * rn * nx) + rho * wx;
+        my = (ry - 2.0 * rn * ny) + rho * wy;
+    }
+    out[0] = rho;
+    out[1] = mx;
+    out[2] = my;
+    out[3] = p / (GAM - 1.0) + 0.5 * (mx * mx + my * my) / rho;
+}
+
 // state of cell (i, j), i interior, j in [-2, nj+2)
 __device__ void jrow_state(const Lay &L, const double *geo, const double *u, const Phys &ph,
                            int noslip, int i, int j, double out[4]) {
@@ -303,7 +396,12 @@ __device__ void jrow_state(const Lay &L, const double *geo, const double *u, con
         }
         double ui[4];
         ld4(u, NS, L.slot(i, k), ui);
-        if (noslip) {
+        if (ph.ale) {
+            int f = L.slot(i, 0);
+            double nx, ny;
+            unit(geo[G_SETA_X * NS + f], geo[G_SETA_Y * NS + f], nx, ny);
+            moving_wall(ui, nx, ny, geo[G_WJX * NS + f], geo[G_WJY * NS + f], noslip, out);
+        } else if (noslip) {
             out[0] = ui[0];
             out[1] = -ui[1];
             out[2] = -ui[2];
@@ -326,7 +424,8 @@ __device__ void jrow_state(const Lay &L, const double *geo, const double *u, con
     int f = L.slot(i, L.nj);
     double nx, ny;
     unit(geo[G_SETA_X * NS + f], geo[G_SETA_Y * NS + f], nx, ny);
-    farfield(ui, ph.uinf, nx, ny, out);
+    if (ph.ale) farfield_moving(ui, ph.uinf, nx, ny, geo[G_WJX * NS + f], geo[G_WJY * NS + f], out);
+    else farfield(ui, ph.uinf, nx, ny, out);
 }
 
 __global__ void k_ghost_state(BK b, int noslip) {
@@ -346,16 +445,18 @@ __global__ void k_ghost_state(BK b, int noslip) {
     } else {
         int jc = min(max(j, 0), L.nj - 1);
         double src[4], nx, ny;
+        int f;
         if (i < 0) {
             jrow_state(L, geo, u, ph, noslip, -1 - i, j, src);
-            int f = L.slot(0, jc);
+            f = L.slot(0, jc);
             unit(-geo[G_SXI_X * NS + f], -geo[G_SXI_Y * NS + f], nx, ny);
         } else {
             jrow_state(L, geo, u, ph, noslip, L.ni - 1 - (i - L.ni), j, src);
-            int f = L.slot(L.ni, jc);
+            f = L.slot(L.ni, jc);
             unit(geo[G_SXI_X * NS + f], geo[G_SXI_Y * NS + f], nx, ny);
         }
-        farfield(src, ph.uinf, nx, ny, out);
+        if (ph.ale) farfield_moving(src, ph.uinf, nx, ny, geo[G_WIX * NS + f], geo[G_WIY * NS + f], out);
+        else farfield(src, ph.uinf, nx, ny, out);
     }
 #pragma unroll
     for (int k = 0; k < 4; ++k) u[k * NS + s] = out[k];
@@ -391,12 +492,27 @@ __global__ void k_mut_ghosts(BK b) {
 // Section 2: p, sensor quantity (entropy p/rho^gamma for RANS, pressure for
 // Euler), spectral radii r = |v.S| + a|S| and the multidimensional
 // correction of eq. "spectralcorrection"; temperature T = p / rho.
+// normal velocities through the mean i- and j-faces, relative to a moving
+// mesh (grid velocity omega x (r - pivot) at the cell centre)
+__device__ inline void rel_normal(const Phys &ph, const double *geo, int NS, int s, double vx, double vy,
+                                  double sb0, double sb1, double sb2, double sb3, double &vnx, double &vne) {
+    vnx = vx * sb0 + vy * sb1;
+    vne = vx * sb2 + vy * sb3;
+    if (ph.ale) {
+        const double wx = -ph.omega * (geo[G_YC * NS + s] - ph.py);
+        const double wy = ph.omega * (geo[G_XC * NS + s] - ph.px);
+        vnx = vnx - (wx * sb0 + wy * sb1);
+        vne = vne - (wx * sb2 + wy * sb3);
+    }
+}
+
 __global__ void k_cell_quantities(BK b, int rans) {
     LevelDev d;
     if (!take(b, blockIdx.y, d)) return;
     const Lay L = d.L;
     const double *geo = d.geo, *u = d.u;
     double *cq = d.cq;
+    const Phys ph = b.PH[blockIdx.y];
     int s = blockIdx.x * blockDim.x + threadIdx.x;
     int i, j;
     if (!decode(L, s, i, j)) return;
@@ -408,8 +524,10 @@ __global__ void k_cell_quantities(BK b, int rans) {
     double q = rans ? p / pow(r, GAM) : p;
     double sb0 = geo[G_SB0 * NS + s], sb1 = geo[G_SB1 * NS + s];
     double sb2 = geo[G_SB2 * NS + s], sb3 = geo[G_SB3 * NS + s];
-    double rxi = fabs(vx * sb0 + vy * sb1) + a * sqrt(sb0 * sb0 + sb1 * sb1);
-    double reta = fabs(vx * sb2 + vy * sb3) + a * sqrt(sb2 * sb2 + sb3 * sb3);
+    double vnx, vne;
+    rel_normal(ph, geo, NS, s, vx, vy, sb0, sb1, sb2, sb3, vnx, vne);
+    double rxi = fabs(vnx) + a * sqrt(sb0 * sb0 + sb1 * sb1);
+    double reta = fabs(vne) + a * sqrt(sb2 * sb2 + sb3 * sb3);
     double t = reta / rxi;
     double rtxi = rxi * (1.0 + cbrt(t * t));
     t = rxi / reta;
@@ -448,8 +566,10 @@ __global__ void k_local_time_step(BK b) {
     double a = sqrt(GAM * p / r);
     double sb0 = geo[G_SB0 * NS + s], sb1 = geo[G_SB1 * NS + s];
     double sb2 = geo[G_SB2 * NS + s], sb3 = geo[G_SB3 * NS + s];
-    double rxi = fabs(vx * sb0 + vy * sb1) + a * sqrt(sb0 * sb0 + sb1 * sb1);
-    double reta = fabs(vx * sb2 + vy * sb3) + a * sqrt(sb2 * sb2 + sb3 * sb3);
+    double vnx, vne;
+    rel_normal(b.PH[blockIdx.y], geo, NS, s, vx, vy, sb0, sb1, sb2, sb3, vnx, vne);
+    double rxi = fabs(vnx) + a * sqrt(sb0 * sb0 + sb1 * sb1);
+    double reta = fabs(vne) + a * sqrt(sb2 * sb2 + sb3 * sb3);
     dts[s] = cfl * geo[G_VOL * NS + s] / (rxi + reta);
 }
 
@@ -597,18 +717,20 @@ struct FaceOut {
 __device__ void face_flux(const Lay &L, const double *geo, const double *u, const double *cq,
                           const double *vg, const double *mut, const Phys &ph, const ResArgs &a,
                           int sL, int sR, int off, double sx, double sy, int gL, int gR, bool wall,
-                          FaceOut &o) {
+                          int sf, int wplane, FaceOut &o) {
     const int NS = L.NS;
     double UL[4], UR[4];
     ld4(u, NS, sL, UL);
     ld4(u, NS, sR, UR);
     double pL = cq[Q_P * NS + sL], pR = cq[Q_P * NS + sR];
+    // moving mesh: grid flux w . S of the face (grid velocity at its midpoint)
+    const double q = ph.ale ? geo[wplane * NS + sf] * sx + geo[(wplane + 1) * NS + sf] * sy : 0.0;
     if (wall) {
         double pw = 0.5 * (pL + pR);
         o.C[0] = 0.0;
         o.C[1] = pw * sx;
         o.C[2] = pw * sy;
-        o.C[3] = 0.0;
+        o.C[3] = ph.ale ? pw * q : 0.0;     // pressure work of a moving wall
 #pragma unroll
         for (int k = 0; k < 4; ++k) o.V[k] = 0.0;
     } else {
@@ -618,6 +740,10 @@ __device__ void face_flux(const Lay &L, const double *geo, const double *u, cons
         double FR[4] = {qsR, UR[1] * vsR + pR * sx, UR[2] * vsR + pR * sy, (UR[3] + pR) * vsR};
 #pragma unroll
         for (int k = 0; k < 4; ++k) o.C[k] = 0.5 * (FL[k] + FR[k]);
+        if (ph.ale) {
+#pragma unroll
+            for (int k = 0; k < 4; ++k) o.C[k] = o.C[k] - q * (0.5 * (UL[k] + UR[k]));
+        }
         const int rp = (off == L.NJ ? Q_RXI : Q_RETA) * NS;
         double rf = fmax(cq[rp + sL], cq[rp + sR]);
         double wL[4] = {UL[0], UL[1], UL[2], UL[3] + pL};
@@ -694,15 +820,15 @@ __global__ __launch_bounds__(TPB) void k_residual(BK b, ResArgs a) {
     const int NS = L.NS, NJ = L.NJ;
     FaceOut w, e, so, n;
     face_flux(L, geo, u, cq, vg, mut, ph, a, s - NJ, s, NJ, geo[G_SXI_X * NS + s],
-              geo[G_SXI_Y * NS + s], s, s + NJ + 1, false, w);
+              geo[G_SXI_Y * NS + s], s, s + NJ + 1, false, s, G_WIX, w);
     face_flux(L, geo, u, cq, vg, mut, ph, a, s, s + NJ, NJ, geo[G_SXI_X * NS + s + NJ],
-              geo[G_SXI_Y * NS + s + NJ], s + NJ, s + 2 * NJ + 1, false, e);
+              geo[G_SXI_Y * NS + s + NJ], s + NJ, s + 2 * NJ + 1, false, s + NJ, G_WIX, e);
     bool wall = (j == 0) && !cut_col(L, i);
     face_flux(L, geo, u, cq, vg, mut, ph, a, s - NJ - 1, s, NJ + 1, geo[G_SETA_X * NS + s],
-              geo[G_SETA_Y * NS + s], s, s + NJ, wall, so);
+              geo[G_SETA_Y * NS + s], s, s + NJ, wall, s, G_WJX, so);
     face_flux(L, geo, u, cq, vg, mut, ph, a, s, s + NJ + 1, NJ + 1,
               geo[G_SETA_X * NS + s + NJ + 1], geo[G_SETA_Y * NS + s + NJ + 1], s + NJ + 1,
-              s + 2 * NJ + 1, false, n);
+              s + 2 * NJ + 1, false, s + NJ + 1, G_WJX, n);
     const double vol = geo[G_VOL * NS + s];
     double Fc[4], Fv[4];
 #pragma unroll
@@ -764,7 +890,7 @@ __global__ __launch_bounds__(TPB) void k_residual(BK b, ResArgs a) {
 // |A|_c = |l1| I + (|l3| - |l1|) r3 l3^T + (|l4| - |l1|) r4 l4^T (same
 // matrix, the two acoustic projections written out).
 __device__ void split_face(const double UL[4], const double UR[4], double sx, double sy, double d,
-                           double Ap[16], double Am[16]) {
+                           double qf, int ale, double Ap[16], double Am[16]) {
     double ln = sqrt(sx * sx + sy * sy);
     double nx = sx / ln, ny = sy / ln;
     double U0 = 0.5 * (UL[0] + UR[0]), U1 = 0.5 * (UL[1] + UR[1]);
@@ -782,6 +908,15 @@ __device__ void split_face(const double UL[4], const double UR[4], double sx, do
                     phi * ny - vv * V, vv * nx - g1 * uu * ny, V - (GAM - 2.0) * vv * ny, g1 * ny,
                     V * (phi - H), H * nx - g1 * uu * V, H * ny - g1 * vv * V, GAM * V};
     double lam[3] = {V, V + a, V - a};
+    if (ale) {
+        // moving face: F.n - w_n u, Jacobian and eigenvalues shifted by w_n
+        const double sh = qf / ln;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) A[k * 5] = A[k * 5] - sh;
+        lam[0] = lam[0] - sh;
+        lam[1] = lam[1] - sh;
+        lam[2] = lam[2] - sh;
+    }
     double al[3];
     double ad = a * d;
 #pragma unroll
@@ -826,7 +961,12 @@ __device__ void face_blocks(const Lay &L, const double *geo, const double *u, co
     ld4(u, NS, sL, UL);
     ld4(u, NS, sR, UR);
     double sx = geo[plane_x * NS + sf], sy = geo[plane_y * NS + sf];
-    split_face(UL, UR, sx, sy, ph.d_cut, Ap, Am);
+    double qf = 0.0;
+    if (ph.ale) {
+        const int wp = plane_x == G_SXI_X ? G_WIX : G_WJX;
+        qf = geo[wp * NS + sf] * sx + geo[(wp + 1) * NS + sf] * sy;
+    }
+    split_face(UL, UR, sx, sy, ph.d_cut, qf, ph.ale, Ap, Am);
     if (viscous) {
         double v = visc_face(L, geo, u, cq, mut, ph, sL, sR, sx, sy);
 #pragma unroll
@@ -1518,6 +1658,13 @@ void launch_geom_interior(const Lay &L, const double *xn, const double *yn, doub
 
 void launch_geom_ghost(const Lay &L, const double *xn, const double *yn, double *geo, hipStream_t st) {
     hipLaunchKernelGGL(k_geom_ghost, dim3(nblocks(L.NS)), dim3(TPB), 0, st, L, xn, yn, geo);
+}
+
+void launch_rotate_geometry(const Lay &L, const double *geo_ref, const double *xn, const double *yn,
+                            double *geo, double c, double s, double px, double py, double omega,
+                            hipStream_t st) {
+    hipLaunchKernelGGL(k_rotate_geometry, dim3(nblocks(L.NS)), dim3(TPB), 0, st, L, geo_ref, xn, yn, geo, c, s,
+                       px, py, omega);
 }
 
 // one thread per padded slot of the largest case, one grid row per case

@@ -80,7 +80,8 @@ EXPORTS = [
     "fas_dual_time_step", "fas_profile", "fas_profile_read", "fas_batch_create",
     "fas_batch_destroy", "fas_batch_solve", "fas_batch_sweep_config", "fas_batch_set_sweep_config", "fas_batch_profile",
     "fas_batch_profile_read", "fas_forces", "fas_vjp", "fas_param_partials",
-    "fas_sgs_apply_transpose", "fas_adjoint_solve", "fas_lift_gradient", "fas_last_error",
+    "fas_sgs_apply_transpose", "fas_adjoint_solve", "fas_lift_gradient", "fas_set_motion",
+    "fas_last_error",
 ]
 PROF_CLASSES = ("sweep", "residual", "blocks")
 
@@ -125,6 +126,7 @@ def load(path: str = LIB_PATH):
         "fas_sgs_apply_transpose": (i32, [vp, vp, vp]),
         "fas_adjoint_solve": (i32, [vp, vp, vp, i32, f64, dp, ip]),
         "fas_lift_gradient": (i32, [vp, i32, f64, dp, dp, dp, ip]),
+        "fas_set_motion": (i32, [vp, f64, f64, f64, f64]),
         "fas_last_error": (ctypes.c_char_p, []),
     }
     for name, (res, args) in sig.items():
@@ -255,6 +257,11 @@ class State:
         _check(_lib.fas_profile_read(self.h, ms.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
                                      n.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))))
         return {c: (float(ms[k]), int(n[k])) for k, c in enumerate(PROF_CLASSES)}
+
+    def set_motion(self, dalpha_deg, rate_deg, pivot=(0.25, 0.0)):
+        """Rigid-body pitching on a moving mesh: the body turned nose-up by
+        dalpha_deg about the pivot, turning at rate_deg per unit time."""
+        _check(_lib.fas_set_motion(self.h, dalpha_deg, rate_deg, pivot[0], pivot[1]))
 
     # ------------------------------------------------------------ adjoint
     def forces(self, with_grad=False):
