@@ -1711,16 +1711,18 @@ void launch_blocks(const BLev &B, int aw, double tau, int viscous, int fp32, hip
 
 // Sweep configurations: four threads per row (k_sgs4 with NT threads, R
 // rows per four-thread group, prefetch batches of D hyperplanes, as deep as
-// the register file allows at that size), and the one-thread-per-row
-// kernel for grids taller than 256 rows.
+// the register file allows at that size and precision: FP32 rows take
+// half the registers), and the one-thread-per-row kernel for grids taller
+// than 256 rows.
 struct SweepCfg {
-    int kind;   // 4: k_sgs4, 1: k_sgs
-    int nt, r, d;
+    int kind;        // 4: k_sgs4, 1: k_sgs
+    int nt, r;
+    int d64, d32;    // prefetch depth for FP64 / FP32 blocks
 };
 static const SweepCfg SWEEP_CFGS[] = {
-    {4, 64, 1, 10},  {4, 128, 1, 10}, {4, 256, 1, 10}, {4, 512, 1, 5}, {4, 1024, 1, 2},
-    {4, 64, 2, 5},   {4, 128, 2, 5},  {4, 256, 2, 5},  {4, 512, 2, 2},
-    {1, 64, 1, 0},   {1, 128, 1, 0},  {1, 256, 1, 0},  {1, 512, 1, 0},
+    {4, 64, 1, 10, 10},  {4, 128, 1, 10, 10}, {4, 256, 1, 10, 10}, {4, 512, 1, 5, 8}, {4, 1024, 1, 2, 4},
+    {4, 64, 2, 5, 3},    {4, 128, 2, 5, 3},   {4, 256, 2, 5, 3},   {4, 512, 2, 2, 4}, {4, 256, 4, 2, 2},
+    {1, 64, 1, 0, 0},    {1, 128, 1, 0, 0},   {1, 256, 1, 0, 0},   {1, 512, 1, 0, 0},
 };
 constexpr int N_SWEEP_CFGS = (int)(sizeof(SWEEP_CFGS) / sizeof(SWEEP_CFGS[0]));
 
@@ -1737,7 +1739,7 @@ int sweep_cfg_default(int max_nj) {
     if (max_nj <= 64) return 2;
     if (max_nj <= 128) return 3;
     if (max_nj <= 256) return 4;
-    return 12;
+    return 13;
 }
 
 template <typename T>
@@ -1748,22 +1750,24 @@ static void sgs_dispatch(const BLev &B, const SweepArgs &a, hipStream_t st) {
     const size_t shm = (size_t)nwl * 4 * sizeof(T);
     const size_t shm4 = (size_t)nwl * 20 * sizeof(T);
     const dim3 grid(B.n);
-#define FAS_SGS4(NT_, R_, D_) \
-    hipLaunchKernelGGL((k_sgs4<T, NT_, R_, D_>), grid, dim3(NT_), shm4, st, B.k, a)
+    constexpr bool F32 = sizeof(T) == 4;
+#define FAS_SGS4(NT_, R_, D64_, D32_) \
+    hipLaunchKernelGGL((k_sgs4<T, NT_, R_, (F32 ? D32_ : D64_)>), grid, dim3(NT_), shm4, st, B.k, a)
 #define FAS_SGS1(NT_) hipLaunchKernelGGL((k_sgs<T, NT_>), grid, dim3(NT_), shm, st, B.k, a)
     switch (cfg) {
-        case 0: FAS_SGS4(64, 1, 10); break;
-        case 1: FAS_SGS4(128, 1, 10); break;
-        case 2: FAS_SGS4(256, 1, 10); break;
-        case 3: FAS_SGS4(512, 1, 5); break;
-        case 4: FAS_SGS4(1024, 1, 2); break;
-        case 5: FAS_SGS4(64, 2, (sizeof(T) == 4 ? 3 : 5)); break;
-        case 6: FAS_SGS4(128, 2, (sizeof(T) == 4 ? 3 : 5)); break;
-        case 7: FAS_SGS4(256, 2, (sizeof(T) == 4 ? 3 : 5)); break;
-        case 8: FAS_SGS4(512, 2, 2); break;
-        case 9: FAS_SGS1(64); break;
-        case 10: FAS_SGS1(128); break;
-        case 11: FAS_SGS1(256); break;
+        case 0: FAS_SGS4(64, 1, 10, 10); break;
+        case 1: FAS_SGS4(128, 1, 10, 10); break;
+        case 2: FAS_SGS4(256, 1, 10, 10); break;
+        case 3: FAS_SGS4(512, 1, 5, 8); break;
+        case 4: FAS_SGS4(1024, 1, 2, 4); break;
+        case 5: FAS_SGS4(64, 2, 5, 3); break;
+        case 6: FAS_SGS4(128, 2, 5, 3); break;
+        case 7: FAS_SGS4(256, 2, 5, 3); break;
+        case 8: FAS_SGS4(512, 2, 2, 4); break;
+        case 9: FAS_SGS4(256, 4, 2, 2); break;
+        case 10: FAS_SGS1(64); break;
+        case 11: FAS_SGS1(128); break;
+        case 12: FAS_SGS1(256); break;
         default: FAS_SGS1(512); break;
     }
 #undef FAS_SGS4
