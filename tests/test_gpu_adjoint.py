@@ -195,3 +195,41 @@ def test_steady_lift_autograd():
     _, grad, _, _ = st.lift_gradient(3000, 11.0)
     assert abs(a.grad.item() - grad[0]) <= 1e-10 * abs(grad[0])
     assert abs(m.grad.item() - grad[1]) <= 1e-10 * abs(grad[1])
+
+
+def test_symmetric_airfoil_at_zero_incidence_has_no_lift():
+    """Mirror-symmetric C-grid, alpha = 0, converged Euler solution: C_L = 0."""
+    g, st = _converged_state(0.0, 0.5)
+    cl, cd = st.forces()
+    assert abs(cl) < 1e-10
+
+
+def test_converged_state_is_a_fixed_point():
+    """A cycle and a smoother iteration leave a converged state unchanged,
+    up to the 12-order convergence of the state (changes ~1e-11)."""
+    g, st = _converged_state(1.5, 0.5)
+    u = _np(st.get_state())
+    st.cycle(1)
+    st.smooth(0, 1)
+    assert state_err_local(_np(st.get_state()), u) < 1e-10
+
+
+@pytest.mark.parametrize("variant", [dict(cycle_gamma=2, n_levels=2), dict(d_cut=0.75),
+                                     dict(cfl=50.0, cfl_ramp=5.0), dict(precond_fp32=1), dict(eta=0.75)])
+def test_converged_solution_does_not_depend_on_the_smoother(variant):
+    """The fixed point F(u) = 0 is a property of the discretisation alone."""
+    from paper_1710_04875_amd import fas
+    _, ref = _converged_state(1.5, 0.5)
+    ni, nj, nw = GRID_FD
+    par = dict(model=0, mach=0.5, alpha_deg=1.5, n_levels=3, cycle_gamma=1, nu1=1, cfl=20.0, cfl_ramp=5.0,
+               n_ramp=1, ramp_growth=1.5)
+    par.update(variant)
+    g = fas.Grid(fi.CGRID, *fi.cgrid(ni, nj, nw), nw, par["n_levels"])
+    st = fas.State(g, fas.Params(**par), torch.from_numpy(fi.uniform_state(ni, nj, 0.5, 1.5)).cuda())
+    h, status = st.cycle(6000, 12.0)
+    assert status == 0, (len(h), h[-1] / h[0])
+    assert state_err_local(_np(st.get_state()), _np(ref.get_state())) < 1e-8
+
+
+def state_err_local(a, b):
+    return float((np.abs(a - b).max(axis=0) / np.abs(b).max(axis=0)).max())

@@ -525,3 +525,21 @@ def test_motion_at_rest_reproduces_the_fixed_mesh():
         # the moving-wall ghost rebuilds its energy from the pressure: a
         # rounding difference, amplified in the wall cell's heat flux
         assert np.abs(Fa - Fb).max() <= 1e-11 * np.abs(Fa).max()
+
+
+def test_bdf_terms_are_exact_for_quadratic_and_linear_histories():
+    """BDF2 (3u - 4u^n + u^{n-1}) / (2 dt) differentiates a quadratic in time
+    exactly at t_{n+1}; the implicit-Euler start (u - u^n) / dt a linear one."""
+    x, y = fi.box_grid(8, 6)
+    u0 = fi.box_initial_state(x, y)
+    S = _solver(x, y, fi.BOX, 0, model=0, u=u0)
+    dt = 0.37
+    rng = np.random.default_rng(4)
+    a, b, c = (rng.standard_normal(u0.shape) for _ in range(3))
+    S.begin_time_step(dt)                          # first step: implicit Euler
+    S.un[0] = a - b * dt                           # linear history a + b t at t = -dt
+    assert np.abs(S.time_src(0, a) - b).max() < 1e-12 * np.abs(b).max()
+    S.begin_time_step(dt)                          # later steps: BDF2
+    q = lambda t: a + b * t + c * t * t            # derivative at t = 0 is b
+    S.un[0], S.unm1[0] = q(-dt), q(-2 * dt)
+    assert np.abs(S.time_src(0, q(0.0)) - b).max() < 1e-11 * np.abs(b).max()
