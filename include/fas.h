@@ -79,8 +79,10 @@ void fas_params_default(fas_params *p);
  * the wall / wake cut outward, cells (i,0) and (ni-1-i,0) are neighbours
  * across the cut for i < n_wake or i >= ni - n_wake.  FAS_BOX: slip wall at
  * j = 0, far field elsewhere.  ni, nj (and n_wake) must be divisible by
- * 2^(n_levels-1); nj <= 512 (one sweep row per thread).  The grid is
- * bound to the current HIP device.  Errors: FAS_EINVAL, FAS_ENOMEM.
+ * 2^(n_levels-1); nj <= 512 (one sweep row per thread); the fine level's
+ * preconditioner blocks (640 bytes per padded cell) must stay below 2 GiB,
+ * about (ni + nj) * nj < 3.3e6.  The grid is bound to the current HIP
+ * device.  Errors: FAS_EINVAL, FAS_ENOMEM.
  */
 fas_status fas_grid_create(int32_t topology, int32_t ni, int32_t nj, int32_t n_wake,
                            const double *x_nodes, const double *y_nodes,

@@ -183,6 +183,11 @@ extern "C" fas_status fas_grid_create(int32_t topology, int32_t ni, int32_t nj, 
             return fail(FAS_EINVAL, "n_wake must be in [1, ni/2) and divisible by 2^(n_levels-1)");
         if ((ni / f) < 4 || (nj / f) < 2) return fail(FAS_EINVAL, "coarsest level too small");
     }
+    // the sweep addresses each per-level array with 32-bit byte offsets
+    // below 2^31 (the FP64 block array is the largest: 640 bytes per slot)
+    if ((size_t)BLK_NPLANES * make_lay(ni, nj, topology == FAS_CGRID ? n_wake : 0, topology).NS * 8 >=
+        ((size_t)1 << 31))
+        return fail(FAS_EINVAL, "grid too large (the preconditioner blocks of the fine level exceed 2 GiB)");
     fas_grid g = new fas_grid_s();
     g->topo = topology;
     g->ni = ni;

@@ -1235,13 +1235,20 @@ __global__ void k_dinv(BK b) {
 // hyperplanes before use and every wait only has to exclude the newest
 // batch.  A cell of row j on hyperplane h = i + j sits at slot
 // (h + 4) NJ + j + 2 of the skewed layout: moving one hyperplane is a
-// uniform stride, so every load is a scalar base plus a constant per-lane
-// offset (valid memory for every h in [0, ni + nj) even where the cell does
-// not exist).  Neighbour vectors of the previous hyperplane come from LDS:
-// every row writes its value every hyperplane (zero where the cell does
-// not exist) and zero guard rows sit below row 0 and above the last row, so
-// absent neighbours read zero vectors (their blocks are zero as well).
-// One LDS-only barrier per hyperplane.
+// uniform stride, so every access is a uniform base plus a constant
+// per-lane offset.  Neighbour vectors of the previous hyperplane come from
+// LDS: every row writes its value every hyperplane (zero where the cell
+// does not exist) and zero guard rows sit below row 0 and above the last
+// row, so absent neighbours read zero vectors.  One LDS-only barrier per
+// hyperplane.
+//
+// Global memory is accessed through raw buffer resources whose record
+// count is the exact extent of the array or plane.  A lane without a cell
+// on a hyperplane (before the first column, past the last, or above the
+// last row) uses an offset beyond every record count: its loads return
+// zeros and its stores are dropped, without touching memory.  Every load
+// and store thus stays one unconditional instruction (exact wait counts
+// for the prefetch), while absent cells cost no memory traffic.
 template <typename T>
 __device__ inline T dot4(const T (&m)[4], const T *x) {
     T p0 = fma(m[1], x[1], m[0] * x[0]);
@@ -1249,32 +1256,51 @@ __device__ inline T dot4(const T (&m)[4], const T *x) {
     return p0 + p1;
 }
 
-// row of a block for the lane's cell: base is the block's first plane at
-// the hyperplane, boff the lane's byte offset within a plane, pstride the
-// distance between the two FP64 half planes (unused for FP32 records)
-template <typename T> struct RowLd;
-template <> struct RowLd<float> {
-    __device__ static void load(const float *base, unsigned boff, size_t pstride, float (&o)[4]) {
-        (void)pstride;
-        V4<float>::load(reinterpret_cast<const float *>(reinterpret_cast<const char *>(base) + boff), o);
-    }
-};
-template <> struct RowLd<double> {
-    __device__ static void load(const double *base, unsigned boff, size_t pstride, double (&o)[4]) {
-        double2 a = *reinterpret_cast<const double2 *>(reinterpret_cast<const char *>(base) + boff);
-        double2 b = *reinterpret_cast<const double2 *>(reinterpret_cast<const char *>(base + pstride) + boff);
-        o[0] = a.x; o[1] = a.y; o[2] = b.x; o[3] = b.y;
-    }
-};
-template <typename T>
-__device__ inline void ldrow(const T *base, unsigned boff, size_t pstride, T (&o)[4]) {
-    RowLd<T>::load(base, boff, pstride, o);
+typedef __amdgpu_buffer_rsrc_t Res;
+typedef unsigned int U32x2 __attribute__((ext_vector_type(2)));
+typedef unsigned int U32x4 __attribute__((ext_vector_type(4)));
+constexpr unsigned OOB = 0x80000000u;      // above every record count (extents < 2 GiB)
+constexpr int RES_WORD3 = 0x00020000;      // raw (untyped) access, 32-bit data format
+
+__device__ inline Res mkres(const void *p, size_t bytes) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(p), (short)0, (int)bytes, RES_WORD3);
 }
 
-template <typename T>
-__device__ inline T ld1(const T *base, unsigned boff) {
-    return *reinterpret_cast<const T *>(reinterpret_cast<const char *>(base) + boff);
+__device__ inline double bld_d(Res r, unsigned off) {
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
 }
+__device__ inline void bst_d(Res r, unsigned off, double x) {
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(U32x2, x), r, off, 0, 0);
+}
+
+// one value, and one block row of the lane's cell (FP64: 16 bytes from each
+// of the two half planes; FP32: the 16-byte row).  The uniform byte offset
+// of a block plane goes into the scalar offset: a lane inside the array
+// stays inside it, and an out-of-range lane stays out of range (plane
+// offsets are below 2^31, so the sum does not wrap).
+template <typename T> struct BufIO;
+template <> struct BufIO<double> {
+    __device__ static double ld(Res r, unsigned off) { return bld_d(r, off); }
+    __device__ static void st(Res r, unsigned off, double x) { bst_d(r, off, x); }
+    __device__ static void row(Res rb, unsigned off, int p0, int p1, double (&o)[4]) {
+        const U32x4 a = __builtin_amdgcn_raw_buffer_load_b128(rb, off, p0, 0);
+        const U32x4 b = __builtin_amdgcn_raw_buffer_load_b128(rb, off, p1, 0);
+        const double2 da = __builtin_bit_cast(double2, a), db = __builtin_bit_cast(double2, b);
+        o[0] = da.x; o[1] = da.y; o[2] = db.x; o[3] = db.y;
+    }
+};
+template <> struct BufIO<float> {
+    __device__ static float ld(Res r, unsigned off) {
+        return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0));
+    }
+    __device__ static void st(Res r, unsigned off, float x) {
+        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, x), r, off, 0, 0);
+    }
+    __device__ static void row(Res rb, unsigned off, int p0, int, float (&o)[4]) {
+        const float4 a = __builtin_bit_cast(float4, __builtin_amdgcn_raw_buffer_load_b128(rb, off, p0, 0));
+        o[0] = a.x; o[1] = a.y; o[2] = a.z; o[3] = a.w;
+    }
+};
 
 template <typename T, int NT, int R, int D>
 __global__ __launch_bounds__(NT) void k_sgs4(BK bk, SweepArgs a) {
@@ -1285,11 +1311,7 @@ __global__ __launch_bounds__(NT) void k_sgs4(BK bk, SweepArgs a) {
     LevelDev dv;
     if (!take(bk, blockIdx.x, dv)) return;
     const Lay L = dv.L;
-    const T *blk = (const T *)dv.blk, *g = (const T *)dv.g;
-    T *y = (T *)dv.y;
-    double *xout = a.xout_acc ? dv.acc : nullptr;
-    double *uu = dv.u;
-    const double *dts = dv.dts;
+    const T *blk = (const T *)dv.blk;
     T *row0 = reinterpret_cast<T *>(smem);                 // n_wake x 4
     T *pblk = row0 + (L.nw > 0 ? L.nw : 1) * 4;           // n_wake x 16: slot-2 blocks of (i, 0), i < n_wake
     const int t = threadIdx.x, grp = t >> 2, r = t & 3;
@@ -1306,48 +1328,56 @@ __global__ __launch_bounds__(NT) void k_sgs4(BK bk, SweepArgs a) {
             pblk[q] = blk[BL<T>::at(B_M0 + 2, NS, L.slot(ii, 0), e >> 2, e & 3)];
         }
     }
-    // constant per-lane byte offsets; hyperplane h adds (h + 4) * NJ slots
-    // rows beyond nj read the last row's data and write to the ghost row
-    // j = nj; lanes without a cell on a hyperplane write to a ghost or unused
-    // slot, so every global store is unconditional (exact wait counts)
-    unsigned ov[R], ob[R], ow[R];
+    // resources: the block array (block b, FP64 half plane hf, at a uniform
+    // byte offset) and the four-component vectors
+    const size_t bstride = (size_t)NS * 16;                // one block (both FP64 half planes)
+    const size_t hpl = sizeof(T) == 8 ? (size_t)NS * 8 : 0;  // FP64 second half plane
+    const int rec = sizeof(T) == 8 ? 8 : 16;               // values per cell in a plane
+    const Res rb = mkres(blk, (size_t)BLK_NBLOCKS * bstride * sizeof(T));
+    auto poff = [&](int b, int hf) { return (int)(((size_t)b * bstride + hf * hpl) * sizeof(T)); };
+    const size_t vbytes = (size_t)4 * NS * sizeof(T), dbytes = (size_t)4 * NS * sizeof(double);
+    // per-lane byte offsets at slot base 0 (a hyperplane adds (h + 4) NJ slots)
+    unsigned ov[R], ob[R], od[R];
     int jq[R];
 #pragma unroll
     for (int q = 0; q < R; ++q) {
         jq[q] = grp * R + q;
-        const int jr = jq[q] < nj ? jq[q] : nj - 1;
-        const int jw = jq[q] < nj ? jq[q] : nj;
+        const int jr = jq[q] < nj ? jq[q] : 0;
         ov[q] = (unsigned)((r * NS + jr + NG) * sizeof(T));
         ob[q] = (unsigned)((BL<T>::at(0, NS, jr + NG, r, 0)) * sizeof(T));
-        ow[q] = (unsigned)((r * NS + jw + NG) * sizeof(T));
+        od[q] = (unsigned)((r * NS + jr + NG) * sizeof(double));
     }
-    // block b at hyperplane slot base hc * NJ: first plane element
-    const size_t bstride = (size_t)NS * 16;                // one block (both FP64 half planes)
-    const size_t hpl = sizeof(T) == 8 ? (size_t)NS * 8 : 0;  // FP64 second half plane
-    const int rec = sizeof(T) == 8 ? 8 : 16;               // values per cell in a plane
-    auto hcl = [&](int h) { return h < 0 ? 0 : (h >= H ? H - 1 : h); };
+    // the lane's cell of row q on hyperplane h exists
+    auto cell = [&](int h, int q) {
+        const int i = h - jq[q];
+        return jq[q] < nj && i >= 0 && i < ni;
+    };
     // ---------------- forward
     {
+        const Res rg = mkres(dv.g, vbytes), ry = mkres(dv.y, vbytes);
+        const int pw0 = poff(B_M0 + 0, 0), pw1 = poff(B_M0 + 0, 1);
+        const int ps0 = poff(B_M0 + 2, 0), ps1 = poff(B_M0 + 2, 1);
         T gA[D][R], wA[D][R][4], sA[D][R][4], gB[D][R], wB[D][R][4], sB[D][R][4];
         auto load = [&](T (&gg)[D][R], T (&ww)[D][R][4], T (&ss)[D][R][4], int hb) {
 #pragma unroll
             for (int k = 0; k < D; ++k) {
-                const int hc = hcl(hb + k) + 2 * NG;
-                const T *gb = g + (size_t)hc * NJ;
-                const T *wb = blk + (size_t)(B_M0 + 0) * bstride + (size_t)hc * NJ * rec;
-                const T *sb = blk + (size_t)(B_M0 + 2) * bstride + (size_t)hc * NJ * rec;
+                const int h = hb + k;
+                const unsigned hv = (unsigned)((h + 2 * NG) * NJ);
 #pragma unroll
                 for (int q = 0; q < R; ++q) {
-                    gg[k][q] = ld1(gb, ov[q]);
-                    ldrow(wb, ob[q], hpl, ww[k][q]);
-                    ldrow(sb, ob[q], hpl, ss[k][q]);
+                    const bool ok = cell(h, q);
+                    const unsigned og = ok ? hv * (unsigned)sizeof(T) + ov[q] : OOB;
+                    const unsigned obk = ok ? hv * (unsigned)(rec * sizeof(T)) + ob[q] : OOB;
+                    gg[k][q] = BufIO<T>::ld(rg, og);
+                    BufIO<T>::row(rb, obk, pw0, pw1, ww[k][q]);
+                    BufIO<T>::row(rb, obk, ps0, ps1, ss[k][q]);
                 }
             }
         };
         auto step = [&](const T (&gv)[R], const T (&wv)[R][4], const T (&sv)[R][4], int h) {
             const T *prev = xb[(h - 1) & 1];
             T *cur = xb[h & 1];
-            T *yb = y + (size_t)(h + 2 * NG) * NJ;
+            const unsigned hv = (unsigned)((h + 2 * NG) * NJ);
 #pragma unroll
             for (int q = 0; q < R; ++q) {
                 const int jj = jq[q];
@@ -1355,9 +1385,9 @@ __global__ __launch_bounds__(NT) void k_sgs4(BK bk, SweepArgs a) {
                 const T *xs = prev + 4 * jj;                        // row jj - 1 (guard row for jj = 0)
                 if (jj == 0 && cutg && i >= ni - nw && i < ni) xs = row0 + (ni - 1 - i) * 4;
                 const T v = (gv[q] - dot4(wv[q], prev + 4 * jj + 4)) - dot4(sv[q], xs);
-                const bool valid = jj < nj && i >= 0 && i < ni;
+                const bool valid = cell(h, q);
                 cur[4 * jj + 4 + r] = valid ? v : (T)0;
-                *reinterpret_cast<T *>(reinterpret_cast<char *>(yb) + ow[q]) = v;
+                BufIO<T>::st(ry, valid ? hv * (unsigned)sizeof(T) + ov[q] : OOB, v);
                 if (valid && jj == 0 && cutg && i < nw) row0[i * 4 + r] = v;
             }
             lds_barrier();
@@ -1383,23 +1413,27 @@ __global__ __launch_bounds__(NT) void k_sgs4(BK bk, SweepArgs a) {
     }
     __syncthreads();
     {
+        const Res ry = mkres(dv.y, vbytes);
+        const int pe0 = poff(B_M0 + 1, 0), pe1 = poff(B_M0 + 1, 1);
+        const int pn0 = poff(B_M0 + 3, 0), pn1 = poff(B_M0 + 3, 1);
+        const Res ru0 = mkres(a.update ? dv.u0 : dv.u, dbytes), ruu = mkres(dv.u, dbytes);
+        const Res rx = mkres(dv.acc, dbytes);
+        const Res rdt = mkres(dv.dts, (size_t)NS * sizeof(double));
         T yA[D][R], eA[D][R][4], nA[D][R][4], yB[D][R], eB[D][R][4], nB[D][R][4];
         double uA[D][R], uB[D][R];
-        const double *u0 = a.update ? dv.u0 : reinterpret_cast<const double *>(y);
         auto load = [&](T (&yy)[D][R], T (&ee)[D][R][4], T (&nn)[D][R][4], double (&u0r)[D][R], int hb) {
 #pragma unroll
             for (int k = 0; k < D; ++k) {
-                const int hc = hcl(H - 1 - (hb + k)) + 2 * NG;
-                const T *yb = y + (size_t)hc * NJ;
-                const double *ub = u0 + (size_t)hc * NJ;
-                const T *eb = blk + (size_t)(B_M0 + 1) * bstride + (size_t)hc * NJ * rec;
-                const T *nb = blk + (size_t)(B_M0 + 3) * bstride + (size_t)hc * NJ * rec;
+                const int h = H - 1 - (hb + k);
+                const unsigned hv = (unsigned)((h + 2 * NG) * NJ);
 #pragma unroll
                 for (int q = 0; q < R; ++q) {
-                    yy[k][q] = ld1(yb, ov[q]);
-                    u0r[k][q] = a.update ? ld1(ub, ov[q] / sizeof(T) * sizeof(double)) : 0.0;
-                    ldrow(eb, ob[q], hpl, ee[k][q]);
-                    ldrow(nb, ob[q], hpl, nn[k][q]);
+                    const bool ok = cell(h, q);
+                    const unsigned obk = ok ? hv * (unsigned)(rec * sizeof(T)) + ob[q] : OOB;
+                    yy[k][q] = BufIO<T>::ld(ry, ok ? hv * (unsigned)sizeof(T) + ov[q] : OOB);
+                    u0r[k][q] = bld_d(ru0, ok && a.update ? hv * 8u + od[q] : OOB);
+                    BufIO<T>::row(rb, obk, pe0, pe1, ee[k][q]);
+                    BufIO<T>::row(rb, obk, pn0, pn1, nn[k][q]);
                 }
             }
         };
@@ -1407,7 +1441,7 @@ __global__ __launch_bounds__(NT) void k_sgs4(BK bk, SweepArgs a) {
                         int h) {
             const T *prev = xb[(h + 1) & 1];
             T *cur = xb[h & 1];
-            const size_t hs = (size_t)(h + 2 * NG) * NJ;
+            const unsigned hv = (unsigned)((h + 2 * NG) * NJ);
 #pragma unroll
             for (int q = 0; q < R; ++q) {
                 const int jj = jq[q];
@@ -1419,17 +1453,20 @@ __global__ __launch_bounds__(NT) void k_sgs4(BK bk, SweepArgs a) {
                     for (int c = 0; c < 4; ++c) mp[c] = pblk[i * 16 + r * 4 + c];
                     v = v - dot4(mp, row0 + (ni - 1 - i - (ni - nw)) * 4);
                 }
-                const bool valid = jj < nj && i >= 0 && i < ni;
+                const bool valid = cell(h, q);
                 cur[4 * jj + 4 + r] = valid ? v : (T)0;
                 if (valid && jj == 0 && cutg && i >= ni - nw) row0[(i - (ni - nw)) * 4 + r] = v;
-                const unsigned ew = ow[q] / sizeof(T) * sizeof(double);
-                if (xout)
-                    *reinterpret_cast<double *>(reinterpret_cast<char *>(xout + hs) + ew) = (double)v;
+                const unsigned oe = valid ? hv * 8u + od[q] : OOB;
+                if (a.xout_acc) bst_d(rx, oe, (double)v);
                 if (a.update) {
                     double un;
-                    if (a.aw) un = u0v[q] - a.alpha * (double)v;
-                    else un = u0v[q] - a.alpha * (dts[hs + (jj < nj ? jj : nj) + NG] * (double)v);
-                    *reinterpret_cast<double *>(reinterpret_cast<char *>(uu + hs) + ew) = un;
+                    if (a.aw) {
+                        un = u0v[q] - a.alpha * (double)v;
+                    } else {
+                        const double dt_s = bld_d(rdt, valid ? (hv + (unsigned)(jj + NG)) * 8u : OOB);
+                        un = u0v[q] - a.alpha * (dt_s * (double)v);
+                    }
+                    bst_d(ruu, oe, un);
                 }
             }
             lds_barrier();
@@ -1719,9 +1756,9 @@ struct SweepCfg {
     int nt, r;
     int d64, d32;    // prefetch depth for FP64 / FP32 blocks
 };
-static const SweepCfg SWEEP_CFGS[] = {
-    {4, 64, 1, 10, 10},  {4, 128, 1, 10, 10}, {4, 256, 1, 10, 10}, {4, 512, 1, 5, 8}, {4, 1024, 1, 2, 4},
-    {4, 64, 2, 5, 3},    {4, 128, 2, 5, 3},   {4, 256, 2, 5, 3},   {4, 512, 2, 2, 4}, {4, 256, 4, 2, 2},
+static constexpr SweepCfg SWEEP_CFGS[] = {
+    {4, 64, 1, 10, 10},  {4, 128, 1, 10, 10}, {4, 256, 1, 10, 10}, {4, 512, 1, 4, 8}, {4, 1024, 1, 2, 3},
+    {4, 64, 2, 5, 3},    {4, 128, 2, 5, 3},   {4, 256, 2, 5, 3},   {4, 512, 2, 2, 3}, {4, 256, 4, 2, 2},
     {1, 64, 1, 0, 0},    {1, 128, 1, 0, 0},   {1, 256, 1, 0, 0},   {1, 512, 1, 0, 0},
 };
 constexpr int N_SWEEP_CFGS = (int)(sizeof(SWEEP_CFGS) / sizeof(SWEEP_CFGS[0]));
@@ -1751,24 +1788,29 @@ static void sgs_dispatch(const BLev &B, const SweepArgs &a, hipStream_t st) {
     const size_t shm4 = (size_t)nwl * 20 * sizeof(T);
     const dim3 grid(B.n);
     constexpr bool F32 = sizeof(T) == 4;
-#define FAS_SGS4(NT_, R_, D64_, D32_) \
-    hipLaunchKernelGGL((k_sgs4<T, NT_, R_, (F32 ? D32_ : D64_)>), grid, dim3(NT_), shm4, st, B.k, a)
-#define FAS_SGS1(NT_) hipLaunchKernelGGL((k_sgs<T, NT_>), grid, dim3(NT_), shm, st, B.k, a)
+#define FAS_SGS4(C_)                                                                                  \
+    hipLaunchKernelGGL((k_sgs4<T, SWEEP_CFGS[C_].nt, SWEEP_CFGS[C_].r,                                \
+                                (F32 ? SWEEP_CFGS[C_].d32 : SWEEP_CFGS[C_].d64)>),                    \
+                       grid, dim3(SWEEP_CFGS[C_].nt), shm4, st, B.k, a)
+#define FAS_SGS1(C_) \
+    hipLaunchKernelGGL((k_sgs<T, SWEEP_CFGS[C_].nt>), grid, dim3(SWEEP_CFGS[C_].nt), shm, st, B.k, a)
+    static_assert(N_SWEEP_CFGS == 14 && SWEEP_CFGS[9].kind == 4 && SWEEP_CFGS[10].kind == 1,
+                  "the switch below follows the configuration table");
     switch (cfg) {
-        case 0: FAS_SGS4(64, 1, 10, 10); break;
-        case 1: FAS_SGS4(128, 1, 10, 10); break;
-        case 2: FAS_SGS4(256, 1, 10, 10); break;
-        case 3: FAS_SGS4(512, 1, 5, 8); break;
-        case 4: FAS_SGS4(1024, 1, 2, 4); break;
-        case 5: FAS_SGS4(64, 2, 5, 3); break;
-        case 6: FAS_SGS4(128, 2, 5, 3); break;
-        case 7: FAS_SGS4(256, 2, 5, 3); break;
-        case 8: FAS_SGS4(512, 2, 2, 4); break;
-        case 9: FAS_SGS4(256, 4, 2, 2); break;
-        case 10: FAS_SGS1(64); break;
-        case 11: FAS_SGS1(128); break;
-        case 12: FAS_SGS1(256); break;
-        default: FAS_SGS1(512); break;
+        case 0: FAS_SGS4(0); break;
+        case 1: FAS_SGS4(1); break;
+        case 2: FAS_SGS4(2); break;
+        case 3: FAS_SGS4(3); break;
+        case 4: FAS_SGS4(4); break;
+        case 5: FAS_SGS4(5); break;
+        case 6: FAS_SGS4(6); break;
+        case 7: FAS_SGS4(7); break;
+        case 8: FAS_SGS4(8); break;
+        case 9: FAS_SGS4(9); break;
+        case 10: FAS_SGS1(10); break;
+        case 11: FAS_SGS1(11); break;
+        case 12: FAS_SGS1(12); break;
+        default: FAS_SGS1(13); break;
     }
 #undef FAS_SGS4
 #undef FAS_SGS1
