@@ -106,6 +106,13 @@ fas_status fas_get_state(fas_state s, double *u, double *mu_t);
 /* Solution and FAS source term of any level ([4][nj_l][ni_l]; source may be NULL). */
 fas_status fas_get_level(fas_state s, int32_t level, double *u, double *source);
 
+/* Diagnostic of the banded sweeps (row bands hand their boundary rows on
+ * through a per-level device array whose slots hold a sentinel between
+ * launches): *n_pending = number of 32-bit words of a level's array that
+ * do not hold the sentinel; 0 whenever no sweep is running.  Synchronises
+ * the state's stream.  Errors: FAS_EINVAL, FAS_EDEVICE. */
+fas_status fas_handoff_pending(fas_state s, int32_t level, int64_t *n_pending);
+
 /*
  * F_l(u_l) - s_l per unit volume on a level (eqs. "nonlin-eq",
  * "nonlin-eq-steady" and "coarse-nonlin-eq"; s = 0 on level 0), with the
@@ -212,11 +219,24 @@ void fas_batch_destroy(fas_batch b);
 fas_status fas_batch_solve(fas_batch b, int32_t max_cycles, double drop_orders, int32_t use_graph,
                            int32_t *n_done, int32_t *status, double *res_hist);
 
-/* Sweep configuration chosen for a level (index, and rows one workgroup
- * covers), and a manual override (cfg -1: pick by grid height; FAS_EINVAL
- * if the configuration covers fewer rows than the level's tallest grid). */
+/* Sweep configuration chosen for a level (index, and rows one launch covers
+ * per case), and a manual override (cfg -1: pick by grid height; FAS_EINVAL
+ * if the configuration covers fewer rows than the level's tallest grid).
+ * Configurations 0 .. fas_sweep_config_count() - 1: one workgroup per case
+ * (four threads per row, or one thread per row), or row bands of one
+ * workgroup each, several per case, handing the band-boundary rows on
+ * through device memory (the forward and backward sweeps of Section 4.4 keep
+ * their exact order).  A banded configuration whose workgroups cannot all
+ * be resident at once runs as the height-based default instead. */
 fas_status fas_batch_sweep_config(fas_batch b, int32_t level, int32_t *cfg, int32_t *rows);
 fas_status fas_batch_set_sweep_config(fas_batch b, int32_t level, int32_t cfg);
+int32_t fas_sweep_config_count(void);
+/* Configuration cfg: kind (0: four threads per row, one workgroup per
+ * case; 1: one thread per row; 2: row bands), threads per workgroup, rows
+ * per workgroup, prefetch depth (hyperplanes per batch) for FP64 and FP32
+ * blocks.  Errors: FAS_EINVAL. */
+fas_status fas_sweep_config_info(int32_t cfg, int32_t *kind, int32_t *threads, int32_t *rows_per_workgroup,
+                                 int32_t *depth_fp64, int32_t *depth_fp32);
 
 /* Kernel-class timing of the batch's direct launches (as fas_profile;
  * launches replayed from a graph are not timed). */

@@ -368,7 +368,7 @@ extern "C" fas_status fas_state_create(fas_grid g, const fas_params *p, const do
         d.geo = g->geo[l];
         const size_t NS = d.L.NS;
         const size_t nd = (size_t)(4 * 8 + 2 + Q_NPLANES + V_NPLANES) * NS + 256;
-        const size_t nb = (size_t)BLK_NPLANES * NS * 8 + (size_t)8 * NS * 8;
+        const size_t nb = (size_t)BLK_NPLANES * NS * 8 + (size_t)8 * NS * 8 + bnd_count(d.L) * 8;
         double *base = nullptr;
         char *bb = nullptr;
         if (hipMalloc(&base, nd * sizeof(double)) != hipSuccess) return cleanup(fail(FAS_ENOMEM, "state allocation failed"));
@@ -387,6 +387,8 @@ extern "C" fas_status fas_state_create(fas_grid g, const fas_params *p, const do
         d.blk = bb;
         d.g = bb + (size_t)BLK_NPLANES * NS * 8;
         d.y = bb + (size_t)BLK_NPLANES * NS * 8 + (size_t)4 * NS * 8;
+        d.bnd = bb + (size_t)BLK_NPLANES * NS * 8 + (size_t)8 * NS * 8;
+        launch_fill_int(reinterpret_cast<int *>(d.bnd), (int)(2 * bnd_count(d.L)), (int)BND_SENTINEL32, e.st);
         s->lv.push_back(d);
     }
     // device descriptors: one LevelDev per level, the physics, the cycle
@@ -474,6 +476,18 @@ extern "C" fas_status fas_get_level(fas_state s, int32_t level, double *u, doubl
     if (u) launch_pack(d.L, d.u, u, 4, s->e.st);
     if (source) launch_pack(d.L, d.src, source, 4, s->e.st);
     HIPCHK(hipGetLastError());
+    return FAS_OK;
+}
+
+extern "C" fas_status fas_handoff_pending(fas_state s, int32_t level, int64_t *n_pending) {
+    if (!s || !n_pending || level < 0 || level >= s->nlev) return fail(FAS_EINVAL, "bad argument");
+    const LevelDev &d = s->lv[level];
+    std::vector<uint32_t> h(2 * bnd_count(d.L));
+    HIPCHK(hipStreamSynchronize(s->e.st));
+    HIPCHK(hipMemcpy(h.data(), d.bnd, h.size() * sizeof(uint32_t), hipMemcpyDeviceToHost));
+    int64_t n = 0;
+    for (uint32_t w : h) n += w != BND_SENTINEL32;
+    *n_pending = n;
     return FAS_OK;
 }
 
@@ -1136,15 +1150,21 @@ extern "C" fas_status fas_batch_create(int32_t n, const fas_state *states, void 
         e.lev.push_back(make_blev(lays, dV + (size_t)l * n, dPH, b->d_act, e.d_cyc));
     }
     // autotuner: per level, the fastest sweep configuration that covers the
-    // tallest grid, timed on the batch itself
+    // tallest grid (banded ones with 2 to 16 bands), timed on the batch itself
     if (autotune) {
         for (int l = 0; l < e.nlev; ++l) {
             const int need = e.lev[l].max_nj;
             int best = -1;
             float best_ms = 0.0f;
             for (int cfg = 0; cfg < sweep_cfg_count(); ++cfg) {
-                const int rows = sweep_cfg_rows(cfg);
-                if (rows < need || rows > 4 * std::max(need, 16)) continue;
+                const int rows = sweep_cfg_rows(cfg, need);
+                if (rows < need) continue;
+                if (sweep_cfg_banded(cfg)) {
+                    const int nb = sweep_cfg_bands(cfg, need);
+                    if (nb < 2 || nb > 16) continue;
+                } else if (rows > 4 * std::max(need, 16)) {
+                    continue;
+                }
                 float ms = 0.0f;
                 fas_status st = time_sweep(e, l, cfg, 3, &ms);
                 if (st != FAS_OK) return cleanup(st);
@@ -1164,16 +1184,34 @@ extern "C" fas_status fas_batch_create(int32_t n, const fas_state *states, void 
 extern "C" fas_status fas_batch_sweep_config(fas_batch b, int32_t level, int32_t *cfg, int32_t *rows) {
     if (!b || level < 0 || level >= b->e.nlev) return fail(FAS_EINVAL, "bad argument");
     int c = b->e.lev[level].sweep_cfg;
-    if (c < 0) c = sweep_cfg_default(b->e.lev[level].max_nj);
+    if (c < 0) c = sweep_cfg_default(b->e.lev[level].max_nj, b->e.fp32);
     if (cfg) *cfg = c;
-    if (rows) *rows = sweep_cfg_rows(c);
+    if (rows) *rows = sweep_cfg_rows(c, b->e.lev[level].max_nj);
+    return FAS_OK;
+}
+
+extern "C" int32_t fas_sweep_config_count(void) { return sweep_cfg_count(); }
+
+extern "C" fas_status fas_sweep_config_info(int32_t cfg, int32_t *kind, int32_t *threads,
+                                            int32_t *rows_per_workgroup, int32_t *depth_fp64,
+                                            int32_t *depth_fp32) {
+    if (cfg < 0 || cfg >= sweep_cfg_count() || !kind || !threads || !rows_per_workgroup || !depth_fp64 ||
+        !depth_fp32)
+        return fail(FAS_EINVAL, "bad argument");
+    int k, t, r, a, b;
+    sweep_cfg_info(cfg, &k, &t, &r, &a, &b);
+    *kind = k;
+    *threads = t;
+    *rows_per_workgroup = r;
+    *depth_fp64 = a;
+    *depth_fp32 = b;
     return FAS_OK;
 }
 
 extern "C" fas_status fas_batch_set_sweep_config(fas_batch b, int32_t level, int32_t cfg) {
     if (!b || level < 0 || level >= b->e.nlev) return fail(FAS_EINVAL, "bad argument");
     if (cfg < -1 || cfg >= sweep_cfg_count()) return fail(FAS_EINVAL, "bad sweep configuration");
-    if (cfg >= 0 && sweep_cfg_rows(cfg) < b->e.lev[level].max_nj)
+    if (cfg >= 0 && sweep_cfg_rows(cfg, b->e.lev[level].max_nj) < b->e.lev[level].max_nj)
         return fail(FAS_EINVAL, "sweep configuration covers fewer rows than the tallest grid");
     b->e.lev[level].sweep_cfg = cfg;
     drop_graph(b);

@@ -105,8 +105,22 @@ struct LevelDev {
     void *blk;        // BLK_NPLANES * NS, double or float
     void *g;          // 4 * NS   D^-1 (dt* r) / forward sweep input
     void *y;          // 4 * NS   forward sweep output
+    void *bnd;        // bnd_count(L) hand-off between row bands of one sweep (a sentinel
+                      //          marks every slot not yet written in a launch)
     double *red;      // reduction scratch (RED_BLOCKS values)
 };
+
+// hand-off array of the banded sweeps: component r of row j on hyperplane
+// h at ((r HB + h + BND_HOFF) NJ + j), for h in [-BND_HOFF, ni + nj +
+// BND_HOFF), so that prefetches and padded steps stay inside their plane
+constexpr int BND_HOFF = 32;
+__host__ __device__ inline int bnd_hb(const Lay &L) { return L.ni + L.nj + 2 * BND_HOFF; }
+__host__ __device__ inline size_t bnd_count(const Lay &L) { return (size_t)4 * bnd_hb(L) * L.NJ; }
+
+// bit pattern of an unwritten hand-off slot: a signalling NaN in FP64 and,
+// in each 32-bit half, a NaN payload no FP32 arithmetic produces
+constexpr unsigned BND_SENTINEL32 = 0x7FF5A5A5u;
+constexpr unsigned long long BND_SENTINEL64 = 0x7FF5A5A57FF5A5A5ull;
 
 // 4-component vector fields of a level, addressed by name in batched
 // launches (each case has its own pointers)
@@ -184,6 +198,7 @@ struct SweepArgs {
     double alpha;
     int aw;
     int xout_acc;      // 1: also write x (FP64) into the level's acc field
+    int bands;         // row bands per case of a banded launch (set by the launcher)
 };
 void launch_sgs(const BLev &B, const SweepArgs &a, int fp32, hipStream_t st);
 void launch_dinv(const BLev &B, int fp32, hipStream_t st);   // g = D^-1 F
@@ -191,8 +206,12 @@ void launch_dinv(const BLev &B, int fp32, hipStream_t st);   // g = D^-1 F
 // sweep kernel configurations for the autotuner: cfg indexes a table of
 // (threads, rows per 4-thread group, prefetch depth); -1 picks by nj
 int sweep_cfg_count();
-int sweep_cfg_rows(int cfg);           // rows one workgroup covers
-int sweep_cfg_default(int max_nj);
+int sweep_cfg_bands(int cfg, int max_nj);  // workgroups per case (1 unless banded)
+int sweep_cfg_rows(int cfg, int max_nj);   // rows one launch covers per case
+bool sweep_cfg_banded(int cfg);
+void sweep_cfg_info(int cfg, int *kind, int *threads, int *rows, int *d64, int *d32);
+int sweep_cfg_default(int max_nj, int fp32);
+int sweep_cfg_plain(int max_nj);
 
 // transfers and utilities
 void launch_restrict(const BLev &Bf, const BLev &Bc, int fin, int fout, int fout2, hipStream_t st);

@@ -85,7 +85,7 @@ __device__ inline void ld4(const double *a, int NS, int s, double v[4]) {
 struct LevelDevG {
     Lay L;
     FAS_GLOBAL double *geo, *u, *u0, *acc, *F, *src, *ut, *un, *unm1, *dts, *mut, *cq, *vg;
-    FAS_GLOBAL char *blk, *g, *y;
+    FAS_GLOBAL char *blk, *g, *y, *bnd;
     FAS_GLOBAL double *red;
 };
 static_assert(sizeof(LevelDevG) == sizeof(LevelDev), "descriptor mirror layout");
@@ -112,6 +112,7 @@ __device__ inline bool take(const BK &b, int c, LevelDev &d) {
     d.blk = (void *)s.blk;
     d.g = (void *)s.g;
     d.y = (void *)s.y;
+    d.bnd = (void *)s.bnd;
     d.red = (double *)s.red;
     return true;
 }
@@ -1302,21 +1303,90 @@ template <> struct BufIO<float> {
     }
 };
 
-template <typename T, int NT, int R, int D>
+// Row bands (BANDED): the rows of a grid are split into bands of NR rows,
+// one workgroup each, so that one grid's sweep runs on several CUs.  Band b
+// needs, on hyperplane h, the value of the last row of band b - 1 on
+// hyperplane h - 1 (forward) or of the first row of band b + 1 on h + 1
+// (backward).  The producing row writes its value of every hyperplane to
+// its slot of the hand-off array; the consuming row prefetches it with the
+// blocks, waits (bounded) while it still reads the sentinel, puts it into
+// its LDS guard row and restores the sentinel.  Every slot written in a
+// launch is consumed in it, so between launches the array holds only
+// sentinels whatever the band layout.  Hand-off accesses are device-scope
+// coherent (bands of one grid may run on different XCDs).  A band waits
+// only for its neighbours, which the launcher keeps co-resident; a wait
+// that does not end within the spin budget leaves the sentinel (a NaN) in
+// the result, so the residual reports divergence instead of a hang: each
+// consuming lane has a budget of polls for the whole launch (a correct
+// launch needs a few thousand at most), after which it no longer waits.
+constexpr int SC1 = 16;                   // cache policy: device-scope coherent
+constexpr unsigned BND_SPIN_BUDGET = 1u << 20;
+
+template <typename T> struct Sent;
+template <> struct Sent<double> {
+    __device__ static bool is(double x) { return __builtin_bit_cast(unsigned long long, x) == BND_SENTINEL64; }
+    __device__ static double value() { return __builtin_bit_cast(double, BND_SENTINEL64); }
+    __device__ static double ld(Res r, unsigned off) {
+        return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, SC1));
+    }
+    __device__ static void st(Res r, unsigned off, double x) {
+        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(U32x2, x), r, off, 0, SC1);
+    }
+};
+template <> struct Sent<float> {
+    __device__ static bool is(float x) { return __builtin_bit_cast(unsigned, x) == BND_SENTINEL32; }
+    __device__ static float value() { return __builtin_bit_cast(float, BND_SENTINEL32); }
+    __device__ static float ld(Res r, unsigned off) {
+        return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, SC1));
+    }
+    __device__ static void st(Res r, unsigned off, float x) {
+        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, x), r, off, 0, SC1);
+    }
+};
+
+// the hand-off value prefetched for this hyperplane, once it is written
+template <typename T>
+__device__ inline T bnd_wait(T v, bool consumer, Res r, unsigned off, unsigned &budget) {
+    if (consumer) {
+        while (Sent<T>::is(v) && budget > 0) {
+            __builtin_amdgcn_s_sleep(1);
+            v = Sent<T>::ld(r, off);
+            --budget;
+        }
+    }
+    return v;
+}
+
+// End of a hyperplane step.  A workgroup of one wave needs no barrier: LDS
+// instructions of a wave execute in order, so the next step's reads see
+// this step's writes once the compiler keeps them in program order.
+template <int NT>
+__device__ inline void step_sync() {
+    if constexpr (NT == 64) __builtin_amdgcn_wave_barrier();
+    else lds_barrier();
+}
+
+template <typename T, int NT, int R, int D, bool BANDED>
 __global__ __launch_bounds__(NT) void k_sgs4(BK bk, SweepArgs a) {
     constexpr int NR = NT / 4 * R;            // rows handled by the workgroup
-    constexpr int XS = 4 * NR + 8;            // zero guard row at both ends
+    constexpr int XS = 4 * NR + 8;            // guard row at both ends
     __shared__ T xb[2][XS];
     extern __shared__ unsigned char smem[];
     LevelDev dv;
-    if (!take(bk, blockIdx.x, dv)) return;
+    const int nbands = BANDED ? a.bands : 1;
+    const int band = BANDED ? (int)blockIdx.x % nbands : 0;
+    if (!take(bk, BANDED ? (int)blockIdx.x / nbands : (int)blockIdx.x, dv)) return;
     const Lay L = dv.L;
+    const int ni = L.ni, nj = L.nj, NS = L.NS, NJ = L.NJ, nw = L.nw;
+    const int j0 = band * NR;                 // first row of the band
+    if (BANDED && j0 >= nj) return;           // band above this case's grid
+    const bool below = BANDED && band > 0;                // a band below feeds the forward sweep
+    const bool above = BANDED && j0 + NR < nj;            // a band above feeds the backward sweep
     const T *blk = (const T *)dv.blk;
     T *row0 = reinterpret_cast<T *>(smem);                 // n_wake x 4
     T *pblk = row0 + (L.nw > 0 ? L.nw : 1) * 4;           // n_wake x 16: slot-2 blocks of (i, 0), i < n_wake
     const int t = threadIdx.x, grp = t >> 2, r = t & 3;
-    const int ni = L.ni, nj = L.nj, NS = L.NS, NJ = L.NJ, nw = L.nw;
-    const bool cutg = L.topo == 1;
+    const bool cutg = L.topo == 1 && j0 == 0;
     const int H = ni + nj - 1;
     for (int q = t; q < XS; q += NT) {
         xb[0][q] = (T)0;
@@ -1336,12 +1406,13 @@ __global__ __launch_bounds__(NT) void k_sgs4(BK bk, SweepArgs a) {
     const Res rb = mkres(blk, (size_t)BLK_NBLOCKS * bstride * sizeof(T));
     auto poff = [&](int b, int hf) { return (int)(((size_t)b * bstride + hf * hpl) * sizeof(T)); };
     const size_t vbytes = (size_t)4 * NS * sizeof(T), dbytes = (size_t)4 * NS * sizeof(double);
+    const Res rh = mkres(BANDED ? dv.bnd : dv.y, BANDED ? bnd_count(L) * sizeof(T) : 0);
     // per-lane byte offsets at slot base 0 (a hyperplane adds (h + 4) NJ slots)
     unsigned ov[R], ob[R], od[R];
     int jq[R];
 #pragma unroll
     for (int q = 0; q < R; ++q) {
-        jq[q] = grp * R + q;
+        jq[q] = j0 + grp * R + q;
         const int jr = jq[q] < nj ? jq[q] : 0;
         ov[q] = (unsigned)((r * NS + jr + NG) * sizeof(T));
         ob[q] = (unsigned)((BL<T>::at(0, NS, jr + NG, r, 0)) * sizeof(T));
@@ -1352,11 +1423,31 @@ __global__ __launch_bounds__(NT) void k_sgs4(BK bk, SweepArgs a) {
         const int i = h - jq[q];
         return jq[q] < nj && i >= 0 && i < ni;
     };
+    // hand-off lanes: the first row of the band (forward consumer, backward
+    // producer) and its last row (forward producer, backward consumer).  A
+    // hand-off offset is the uniform part of hyperplane h plus a per-lane
+    // part that is out of range on lanes without that role.
+    const bool first = grp == 0, last = grp == NT / 4 - 1;
+    const int HB = bnd_hb(L);
+    auto hrow = [&](bool on, int j) { return on ? (unsigned)((r * HB * NJ + j) * sizeof(T)) : OOB; };
+    auto hplane = [&](int h) { return (unsigned)((h + BND_HOFF) * NJ * sizeof(T)); };
+    unsigned budget = BND_SPIN_BUDGET;
+    // hand-off values wait in a ring of 2D registers, slot = step mod 2D,
+    // each loaded P steps before it is needed (short, so that neighbouring
+    // bands run only a few steps apart)
+    // (banded launches run every step of the last batch: steps past the
+    // last hyperplane touch memory only through out-of-range offsets, and
+    // unconditional steps keep the compiler's wait counts exact)
+    constexpr int NRING = BANDED ? 2 * D : 1;
+    constexpr int P = 2 * D - 1 < 8 ? 2 * D - 1 : 8;
+    T ring[NRING];
     // ---------------- forward
     {
         const Res rg = mkres(dv.g, vbytes), ry = mkres(dv.y, vbytes);
         const int pw0 = poff(B_M0 + 0, 0), pw1 = poff(B_M0 + 0, 1);
         const int ps0 = poff(B_M0 + 2, 0), ps1 = poff(B_M0 + 2, 1);
+        const bool cons = below && first, prod = above && last;
+        const unsigned hl = hrow(cons, j0 - 1), hs = cons ? hl : hrow(prod, j0 + NR - 1);
         T gA[D][R], wA[D][R][4], sA[D][R][4], gB[D][R], wB[D][R][4], sB[D][R][4];
         auto load = [&](T (&gg)[D][R], T (&ww)[D][R][4], T (&ss)[D][R][4], int hb) {
 #pragma unroll
@@ -1374,35 +1465,51 @@ __global__ __launch_bounds__(NT) void k_sgs4(BK bk, SweepArgs a) {
                 }
             }
         };
-        auto step = [&](const T (&gv)[R], const T (&wv)[R][4], const T (&sv)[R][4], int h) {
+        auto step = [&](const T (&gv)[R], const T (&wv)[R][4], const T (&sv)[R][4], int sl, int h) {
             const T *prev = xb[(h - 1) & 1];
             T *cur = xb[h & 1];
             const unsigned hv = (unsigned)((h + 2 * NG) * NJ);
+            if constexpr (BANDED) {
+                // the row below the band on this hyperplane, for the next one
+                const T bv = bnd_wait(ring[sl], cons, rh, hplane(h) + hl, budget);
+                if (cons) cur[r] = bv;
+                ring[(sl + P) % NRING] = Sent<T>::ld(rh, hplane(h + P) + hl);
+            }
 #pragma unroll
             for (int q = 0; q < R; ++q) {
-                const int jj = jq[q];
-                const int i = h - jj;
-                const T *xs = prev + 4 * jj;                        // row jj - 1 (guard row for jj = 0)
-                if (jj == 0 && cutg && i >= ni - nw && i < ni) xs = row0 + (ni - 1 - i) * 4;
+                const int jj = jq[q] - j0;                          // row within the band
+                const int i = h - jq[q];
+                const T *xs = prev + 4 * jj;                        // row below (guard row for jj = 0)
+                if (jq[q] == 0 && cutg && i >= ni - nw && i < ni) xs = row0 + (ni - 1 - i) * 4;
                 const T v = (gv[q] - dot4(wv[q], prev + 4 * jj + 4)) - dot4(sv[q], xs);
                 const bool valid = cell(h, q);
-                cur[4 * jj + 4 + r] = valid ? v : (T)0;
+                const T vz = valid ? v : (T)0;
+                cur[4 * jj + 4 + r] = vz;
                 BufIO<T>::st(ry, valid ? hv * (unsigned)sizeof(T) + ov[q] : OOB, v);
-                if (valid && jj == 0 && cutg && i < nw) row0[i * 4 + r] = v;
+                if (valid && jq[q] == 0 && cutg && i < nw) row0[i * 4 + r] = v;
+                // one store: the last row's value (producer lanes) and the
+                // sentinel back into the slot just consumed (consumer lanes)
+                if constexpr (BANDED)
+                    if (q == R - 1)
+                        Sent<T>::st(rh, hplane(h) + hs, cons ? Sent<T>::value() : vz);
             }
-            lds_barrier();
+            step_sync<NT>();
         };
+        if constexpr (BANDED) {
+#pragma unroll
+            for (int k = 0; k < P; ++k) ring[k] = Sent<T>::ld(rh, hplane(k) + hl);
+        }
         load(gA, wA, sA, 0);
         __syncthreads();
         for (int h0 = 0; h0 < H; h0 += 2 * D) {
             load(gB, wB, sB, h0 + D);
 #pragma unroll
             for (int k = 0; k < D; ++k)
-                if (h0 + k < H) step(gA[k], wA[k], sA[k], h0 + k);
+                if (BANDED || h0 + k < H) step(gA[k], wA[k], sA[k], k, h0 + k);
             load(gA, wA, sA, h0 + 2 * D);
 #pragma unroll
             for (int k = 0; k < D; ++k)
-                if (h0 + D + k < H) step(gB[k], wB[k], sB[k], h0 + D + k);
+                if (BANDED || h0 + D + k < H) step(gB[k], wB[k], sB[k], D + k, h0 + D + k);
         }
     }
     // ---------------- backward (+ stage update); the full barrier completes the y stores
@@ -1419,6 +1526,8 @@ __global__ __launch_bounds__(NT) void k_sgs4(BK bk, SweepArgs a) {
         const Res ru0 = mkres(a.update ? dv.u0 : dv.u, dbytes), ruu = mkres(dv.u, dbytes);
         const Res rx = mkres(dv.acc, dbytes);
         const Res rdt = mkres(dv.dts, (size_t)NS * sizeof(double));
+        const bool cons = above && last, prod = below && first;
+        const unsigned hl = hrow(cons, j0 + NR), hs = cons ? hl : hrow(prod, j0);
         T yA[D][R], eA[D][R][4], nA[D][R][4], yB[D][R], eB[D][R][4], nB[D][R][4];
         double uA[D][R], uB[D][R];
         auto load = [&](T (&yy)[D][R], T (&ee)[D][R][4], T (&nn)[D][R][4], double (&u0r)[D][R], int hb) {
@@ -1438,24 +1547,34 @@ __global__ __launch_bounds__(NT) void k_sgs4(BK bk, SweepArgs a) {
             }
         };
         auto step = [&](const T (&yv)[R], const T (&ev)[R][4], const T (&nv)[R][4], const double (&u0v)[R],
-                        int h) {
+                        int sl, int h) {
             const T *prev = xb[(h + 1) & 1];
             T *cur = xb[h & 1];
             const unsigned hv = (unsigned)((h + 2 * NG) * NJ);
+            if constexpr (BANDED) {
+                // the row above the band on this hyperplane, for the next one
+                const T bv = bnd_wait(ring[sl], cons, rh, hplane(h) + hl, budget);
+                if (cons) cur[4 * NR + 4 + r] = bv;
+                ring[(sl + P) % NRING] = Sent<T>::ld(rh, hplane(h - P) + hl);
+            }
 #pragma unroll
             for (int q = 0; q < R; ++q) {
-                const int jj = jq[q];
-                const int i = h - jj;
+                const int jj = jq[q] - j0;
+                const int i = h - jq[q];
                 T v = (yv[q] - dot4(ev[q], prev + 4 * jj + 4)) - dot4(nv[q], prev + 4 * jj + 8);
-                if (jj == 0 && cutg && i >= 0 && i < nw) {
+                if (jq[q] == 0 && cutg && i >= 0 && i < nw) {
                     T mp[4];
 #pragma unroll
                     for (int c = 0; c < 4; ++c) mp[c] = pblk[i * 16 + r * 4 + c];
                     v = v - dot4(mp, row0 + (ni - 1 - i - (ni - nw)) * 4);
                 }
                 const bool valid = cell(h, q);
-                cur[4 * jj + 4 + r] = valid ? v : (T)0;
-                if (valid && jj == 0 && cutg && i >= ni - nw) row0[(i - (ni - nw)) * 4 + r] = v;
+                const T vz = valid ? v : (T)0;
+                cur[4 * jj + 4 + r] = vz;
+                if (valid && jq[q] == 0 && cutg && i >= ni - nw) row0[(i - (ni - nw)) * 4 + r] = v;
+                if constexpr (BANDED)
+                    if (q == 0)
+                        Sent<T>::st(rh, hplane(h) + hs, cons ? Sent<T>::value() : vz);
                 const unsigned oe = valid ? hv * 8u + od[q] : OOB;
                 if (a.xout_acc) bst_d(rx, oe, (double)v);
                 if (a.update) {
@@ -1463,25 +1582,29 @@ __global__ __launch_bounds__(NT) void k_sgs4(BK bk, SweepArgs a) {
                     if (a.aw) {
                         un = u0v[q] - a.alpha * (double)v;
                     } else {
-                        const double dt_s = bld_d(rdt, valid ? (hv + (unsigned)(jj + NG)) * 8u : OOB);
+                        const double dt_s = bld_d(rdt, valid ? (hv + (unsigned)(jq[q] + NG)) * 8u : OOB);
                         un = u0v[q] - a.alpha * (dt_s * (double)v);
                     }
                     bst_d(ruu, oe, un);
                 }
             }
-            lds_barrier();
+            step_sync<NT>();
         };
+        if constexpr (BANDED) {
+#pragma unroll
+            for (int k = 0; k < P; ++k) ring[k] = Sent<T>::ld(rh, hplane(H - 1 - k) + hl);
+        }
         load(yA, eA, nA, uA, 0);
         __syncthreads();
         for (int h0 = 0; h0 < H; h0 += 2 * D) {
             load(yB, eB, nB, uB, h0 + D);
 #pragma unroll
             for (int k = 0; k < D; ++k)
-                if (h0 + k < H) step(yA[k], eA[k], nA[k], uA[k], H - 1 - (h0 + k));
+                if (BANDED || h0 + k < H) step(yA[k], eA[k], nA[k], uA[k], k, H - 1 - (h0 + k));
             load(yA, eA, nA, uA, h0 + 2 * D);
 #pragma unroll
             for (int k = 0; k < D; ++k)
-                if (h0 + D + k < H) step(yB[k], eB[k], nB[k], uB[k], H - 1 - (h0 + D + k));
+                if (BANDED || h0 + D + k < H) step(yB[k], eB[k], nB[k], uB[k], D + k, H - 1 - (h0 + D + k));
         }
     }
 }
@@ -1749,10 +1872,11 @@ void launch_blocks(const BLev &B, int aw, double tau, int viscous, int fp32, hip
 // Sweep configurations: four threads per row (k_sgs4 with NT threads, R
 // rows per four-thread group, prefetch batches of D hyperplanes, as deep as
 // the register file allows at that size and precision: FP32 rows take
-// half the registers), and the one-thread-per-row kernel for grids taller
-// than 256 rows.
+// half the registers), the one-thread-per-row kernel for grids taller than
+// 256 rows, and the banded form of k_sgs4 (kind 5: bands of NT / 4 * R
+// rows, one workgroup per band, as many bands as the tallest grid needs).
 struct SweepCfg {
-    int kind;        // 4: k_sgs4, 1: k_sgs
+    int kind;        // 4: k_sgs4, 1: k_sgs, 5: banded k_sgs4
     int nt, r;
     int d64, d32;    // prefetch depth for FP64 / FP32 blocks
 };
@@ -1760,41 +1884,100 @@ static constexpr SweepCfg SWEEP_CFGS[] = {
     {4, 64, 1, 10, 10},  {4, 128, 1, 10, 10}, {4, 256, 1, 10, 10}, {4, 512, 1, 4, 8}, {4, 1024, 1, 2, 3},
     {4, 64, 2, 5, 3},    {4, 128, 2, 5, 3},   {4, 256, 2, 5, 3},   {4, 512, 2, 2, 3}, {4, 256, 4, 2, 2},
     {1, 64, 1, 0, 0},    {1, 128, 1, 0, 0},   {1, 256, 1, 0, 0},   {1, 512, 1, 0, 0},
+    {5, 64, 1, 10, 10},  {5, 128, 1, 10, 10}, {5, 256, 1, 10, 10}, {5, 128, 2, 5, 3},
+    {4, 128, 1, 5, 5},   {4, 256, 1, 5, 5},   {5, 64, 1, 5, 5},    {5, 128, 1, 5, 5}, {5, 256, 1, 5, 5},
 };
 constexpr int N_SWEEP_CFGS = (int)(sizeof(SWEEP_CFGS) / sizeof(SWEEP_CFGS[0]));
 
 int sweep_cfg_count() { return N_SWEEP_CFGS; }
 
-int sweep_cfg_rows(int cfg) {
+static int cfg_group_rows(int cfg) {
     const SweepCfg &c = SWEEP_CFGS[cfg];
-    return c.kind == 4 ? c.nt / 4 * c.r : c.nt;
+    return c.kind == 1 ? c.nt : c.nt / 4 * c.r;
 }
 
-int sweep_cfg_default(int max_nj) {
+int sweep_cfg_bands(int cfg, int max_nj) {
+    const int nr = cfg_group_rows(cfg);
+    return SWEEP_CFGS[cfg].kind == 5 ? (max_nj + nr - 1) / nr : 1;
+}
+
+int sweep_cfg_rows(int cfg, int max_nj) { return cfg_group_rows(cfg) * sweep_cfg_bands(cfg, max_nj); }
+
+bool sweep_cfg_banded(int cfg) { return SWEEP_CFGS[cfg].kind == 5; }
+
+void sweep_cfg_info(int cfg, int *kind, int *threads, int *rows, int *d64, int *d32) {
+    const SweepCfg &c = SWEEP_CFGS[cfg];
+    *kind = c.kind == 4 ? 0 : c.kind == 1 ? 1 : 2;
+    *threads = c.nt;
+    *rows = cfg_group_rows(cfg);
+    *d64 = c.d64;
+    *d32 = c.d32;
+}
+
+// one workgroup per case, by height (also the fall-back of a banded launch
+// whose workgroups cannot all be resident)
+int sweep_cfg_plain(int max_nj) {
     if (max_nj <= 16) return 0;
-    if (max_nj <= 32) return 1;
-    if (max_nj <= 64) return 2;
+    if (max_nj <= 32) return 18;
+    if (max_nj <= 64) return 19;
     if (max_nj <= 128) return 3;
     if (max_nj <= 256) return 4;
     return 13;
 }
 
+// Default by height and precision, from timings of the three levels of a
+// 256 x 128 grid: one 128-thread workgroup up to 32 rows; above, bands of
+// 32 rows (two waves each), except FP32 blocks at 64 rows, where one
+// 256-thread workgroup is faster.
+int sweep_cfg_default(int max_nj, int fp32) {
+    if (max_nj <= 32 || (fp32 && max_nj <= 64)) return sweep_cfg_plain(max_nj);
+    return 21;
+}
+
+// Banded launches wait on neighbouring workgroups: they are used only when
+// the whole grid can be resident at once.
+template <typename K>
+static int resident_blocks(K kernel, int nt, size_t shm) {
+    int dev = 0, ncu = 0, per = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, reinterpret_cast<const void *>(kernel), nt, shm) !=
+            hipSuccess)
+        return 0;
+    return per * ncu;
+}
+
 template <typename T>
-static void sgs_dispatch(const BLev &B, const SweepArgs &a, hipStream_t st) {
-    int cfg = B.sweep_cfg >= 0 ? B.sweep_cfg : sweep_cfg_default(B.max_nj);
-    if (sweep_cfg_rows(cfg) < B.max_nj) cfg = sweep_cfg_default(B.max_nj);
+static void sgs_dispatch(const BLev &B, const SweepArgs &a0, hipStream_t st) {
+    constexpr int FP32 = sizeof(T) == 4 ? 1 : 0;
+    int cfg = B.sweep_cfg >= 0 ? B.sweep_cfg : sweep_cfg_default(B.max_nj, FP32);
+    if (sweep_cfg_rows(cfg, B.max_nj) < B.max_nj) cfg = sweep_cfg_default(B.max_nj, FP32);
     const int nwl = B.max_nw > 0 ? B.max_nw : 1;
     const size_t shm = (size_t)nwl * 4 * sizeof(T);
     const size_t shm4 = (size_t)nwl * 20 * sizeof(T);
-    const dim3 grid(B.n);
     constexpr bool F32 = sizeof(T) == 4;
-#define FAS_SGS4(C_)                                                                                  \
-    hipLaunchKernelGGL((k_sgs4<T, SWEEP_CFGS[C_].nt, SWEEP_CFGS[C_].r,                                \
-                                (F32 ? SWEEP_CFGS[C_].d32 : SWEEP_CFGS[C_].d64)>),                    \
-                       grid, dim3(SWEEP_CFGS[C_].nt), shm4, st, B.k, a)
+    SweepArgs a = a0;
+    a.bands = sweep_cfg_bands(cfg, B.max_nj);
+#define FAS_K4(C_, BANDED_)                                                                           \
+    k_sgs4<T, SWEEP_CFGS[C_].nt, SWEEP_CFGS[C_].r, (F32 ? SWEEP_CFGS[C_].d32 : SWEEP_CFGS[C_].d64), \
+           BANDED_>
+#define FAS_SGS4(C_) hipLaunchKernelGGL((FAS_K4(C_, false)), dim3(B.n), dim3(SWEEP_CFGS[C_].nt), shm4, st, B.k, a)
+#define FAS_SGS5(C_)                                                                                   \
+    do {                                                                                               \
+        if (B.n * a.bands <= resident_blocks(FAS_K4(C_, true), SWEEP_CFGS[C_].nt, shm4)) {             \
+            hipLaunchKernelGGL((FAS_K4(C_, true)), dim3(B.n * a.bands), dim3(SWEEP_CFGS[C_].nt), shm4, \
+                               st, B.k, a);                                                            \
+        } else {                                                                                       \
+            BLev B1 = B;                                                                               \
+            B1.sweep_cfg = sweep_cfg_plain(B.max_nj);                                                  \
+            sgs_dispatch<T>(B1, a0, st);                                                               \
+        }                                                                                              \
+    } while (0)
 #define FAS_SGS1(C_) \
-    hipLaunchKernelGGL((k_sgs<T, SWEEP_CFGS[C_].nt>), grid, dim3(SWEEP_CFGS[C_].nt), shm, st, B.k, a)
-    static_assert(N_SWEEP_CFGS == 14 && SWEEP_CFGS[9].kind == 4 && SWEEP_CFGS[10].kind == 1,
+    hipLaunchKernelGGL((k_sgs<T, SWEEP_CFGS[C_].nt>), dim3(B.n), dim3(SWEEP_CFGS[C_].nt), shm, st, B.k, a)
+    static_assert(N_SWEEP_CFGS == 23 && SWEEP_CFGS[9].kind == 4 && SWEEP_CFGS[10].kind == 1 &&
+                      SWEEP_CFGS[13].kind == 1 && SWEEP_CFGS[14].kind == 5 && SWEEP_CFGS[17].kind == 5 &&
+                      SWEEP_CFGS[18].kind == 4 && SWEEP_CFGS[19].kind == 4 && SWEEP_CFGS[20].kind == 5,
                   "the switch below follows the configuration table");
     switch (cfg) {
         case 0: FAS_SGS4(0); break;
@@ -1810,9 +1993,20 @@ static void sgs_dispatch(const BLev &B, const SweepArgs &a, hipStream_t st) {
         case 10: FAS_SGS1(10); break;
         case 11: FAS_SGS1(11); break;
         case 12: FAS_SGS1(12); break;
-        default: FAS_SGS1(13); break;
+        case 13: FAS_SGS1(13); break;
+        case 14: FAS_SGS5(14); break;
+        case 15: FAS_SGS5(15); break;
+        case 16: FAS_SGS5(16); break;
+        case 17: FAS_SGS5(17); break;
+        case 18: FAS_SGS4(18); break;
+        case 19: FAS_SGS4(19); break;
+        case 20: FAS_SGS5(20); break;
+        case 21: FAS_SGS5(21); break;
+        default: FAS_SGS5(22); break;
     }
+#undef FAS_K4
 #undef FAS_SGS4
+#undef FAS_SGS5
 #undef FAS_SGS1
 }
 

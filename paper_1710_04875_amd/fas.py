@@ -76,9 +76,10 @@ class Params:
 EXPORTS = [
     "fas_params_default", "fas_grid_create", "fas_grid_destroy", "fas_state_create",
     "fas_state_destroy", "fas_state_set_params", "fas_set_state", "fas_get_state",
-    "fas_get_level", "fas_residual", "fas_smooth", "fas_sgs_apply", "fas_cycle",
+    "fas_get_level", "fas_handoff_pending", "fas_residual", "fas_smooth", "fas_sgs_apply", "fas_cycle",
     "fas_dual_time_step", "fas_profile", "fas_profile_read", "fas_batch_create",
-    "fas_batch_destroy", "fas_batch_solve", "fas_batch_sweep_config", "fas_batch_set_sweep_config", "fas_batch_profile",
+    "fas_batch_destroy", "fas_batch_solve", "fas_batch_sweep_config", "fas_batch_set_sweep_config",
+    "fas_sweep_config_count", "fas_sweep_config_info", "fas_batch_profile",
     "fas_batch_profile_read", "fas_forces", "fas_vjp", "fas_param_partials",
     "fas_sgs_apply_transpose", "fas_adjoint_solve", "fas_lift_gradient", "fas_set_motion",
     "fas_last_error",
@@ -106,6 +107,7 @@ def load(path: str = LIB_PATH):
         "fas_set_state": (i32, [vp, vp]),
         "fas_get_state": (i32, [vp, vp, vp]),
         "fas_get_level": (i32, [vp, i32, vp, vp]),
+        "fas_handoff_pending": (i32, [vp, i32, ctypes.POINTER(ctypes.c_int64)]),
         "fas_residual": (i32, [vp, i32, vp]),
         "fas_smooth": (i32, [vp, i32, i32]),
         "fas_sgs_apply": (i32, [vp, i32, vp, vp]),
@@ -118,6 +120,8 @@ def load(path: str = LIB_PATH):
         "fas_batch_solve": (i32, [vp, i32, f64, i32, ip, ip, dp]),
         "fas_batch_sweep_config": (i32, [vp, i32, ip, ip]),
         "fas_batch_set_sweep_config": (i32, [vp, i32, i32]),
+        "fas_sweep_config_count": (i32, []),
+        "fas_sweep_config_info": (i32, [i32, ip, ip, ip, ip, ip]),
         "fas_batch_profile": (i32, [vp, i32]),
         "fas_batch_profile_read": (i32, [vp, dp, ctypes.POINTER(ctypes.c_int64)]),
         "fas_forces": (i32, [vp, dp, dp, vp]),
@@ -223,6 +227,13 @@ class State:
         s = torch.empty(self.shape(level), dtype=torch.float64, device=self.device)
         _check(_lib.fas_get_level(self.h, level, _dptr(u), _dptr(s)))
         return u, s
+
+    def handoff_pending(self, level=0):
+        """Words of a level's band hand-off array not holding the sentinel
+        (0 whenever no sweep is running)."""
+        n = ctypes.c_int64(0)
+        _check(_lib.fas_handoff_pending(self.h, level, ctypes.byref(n)))
+        return int(n.value)
 
     def residual(self, level=0):
         import torch
@@ -333,6 +344,23 @@ class State:
 def torch_dtype():
     import torch
     return torch.float64
+
+
+SWEEP_FOUR_THREADS, SWEEP_ONE_THREAD, SWEEP_BANDED = 0, 1, 2
+
+
+def sweep_config_count():
+    """Number of sweep configurations (indices for Batch.set_sweep_config)."""
+    return int(load().fas_sweep_config_count())
+
+
+def sweep_config_info(cfg):
+    """(kind, threads, rows per workgroup, FP64 depth, FP32 depth) of a sweep
+    configuration; kind is SWEEP_FOUR_THREADS, SWEEP_ONE_THREAD or
+    SWEEP_BANDED."""
+    v = [ctypes.c_int32(0) for _ in range(5)]
+    _check(load().fas_sweep_config_info(cfg, *[ctypes.byref(x) for x in v]))
+    return tuple(int(x.value) for x in v)
 
 
 class Batch:

@@ -12,8 +12,10 @@ from gpu_common import TOL_STATE, state_err
 
 pytestmark = pytest.mark.gpu
 
-# sweep configurations from this index on use one thread per row
-ONE_THREAD_PER_ROW = 10
+
+def _cfgs(kind):
+    from paper_1710_04875_amd import fas
+    return [c for c in range(fas.sweep_config_count()) if fas.sweep_config_info(c)[0] == kind]
 
 # (ni, nj, n_wake, mach, alpha): uneven grids and flow conditions
 CASES = [(64, 32, 8, 0.8, 1.3), (96, 48, 12, 0.6, 0.4), (128, 16, 16, 0.75, 2.5)]
@@ -111,7 +113,8 @@ def test_every_sweep_configuration_gives_the_same_iterate():
     from paper_1710_04875_amd import fas
     ref = _run_single(cycles=2)
     tried = 0
-    for cfg in range(14):
+    one_thread = _cfgs(fas.SWEEP_ONE_THREAD)
+    for cfg in range(fas.sweep_config_count()):
         pairs = _states()
         b = fas.Batch([st for _, st in pairs], autotune=False)
         try:
@@ -123,14 +126,40 @@ def test_every_sweep_configuration_gives_the_same_iterate():
         torch.cuda.synchronize()
         for c, (_, s) in enumerate(pairs):
             u = s.get_state().cpu().numpy()
-            if cfg < ONE_THREAD_PER_ROW:
-                # the four-thread sweeps share their arithmetic: bitwise equal
+            if cfg not in one_thread:
+                # the four-thread sweeps, banded or not, share their
+                # arithmetic: bitwise equal
                 assert np.array_equal(u, ref[c][0]), (cfg, c)
             else:
                 # the one-thread-per-row sweep sums the block products in
                 # another order
                 assert state_err(u, ref[c][0]) < TOL_STATE, (cfg, c)
-    assert tried >= 9
+    assert tried >= 13
+
+
+@pytest.mark.parametrize("fp32,scheme,cfl", [(0, 0, 50.0), (1, 0, 50.0), (0, 1, 1.0)])
+def test_row_bands_equal_one_workgroup_per_case(fp32, scheme, cfl):
+    """Banded sweeps on every level (2-3 bands of 16 rows on the 48-row fine
+    grid, one band on the coarsest levels, bands above the shorter grids
+    idle) against the single-state path, bitwise, for the FP64 and FP32
+    preconditioners and for an AW and a preconditioned-ARK scheme (its
+    stage update reads dt*); the hand-off array must hold only sentinels
+    again after every launch."""
+    from paper_1710_04875_amd import fas
+    ref = _run_single(fp32=fp32, cycles=3, scheme=scheme, cfl=cfl, cfl_ramp=min(cfl, 5.0))
+    assert all(np.isfinite(u).all() for u, _, _ in ref)
+    for cfg in _cfgs(fas.SWEEP_BANDED):
+        pairs = _states(fp32=fp32, scheme=scheme, cfl=cfl, cfl_ramp=min(cfl, 5.0))
+        b = fas.Batch([st for _, st in pairs], autotune=False)
+        for level in range(3):
+            b.set_sweep_config(level, cfg)
+        hist, stat, _ = b.solve(3, 0.0, True)
+        torch.cuda.synchronize()
+        for c, (_, s) in enumerate(pairs):
+            assert np.array_equal(s.get_state().cpu().numpy(), ref[c][0]), (cfg, c)
+            assert np.array_equal(hist[c], ref[c][1]), (cfg, c)
+            for level in range(3):
+                assert s.handoff_pending(level) == 0, (cfg, c, level)
 
 
 def test_autotuned_configuration_covers_the_tallest_grid():
