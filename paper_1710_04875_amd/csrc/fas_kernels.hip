@@ -1439,7 +1439,7 @@ __global__ __launch_bounds__(NT) void k_sgs4(BK bk, SweepArgs a) {
     // last hyperplane touch memory only through out-of-range offsets, and
     // unconditional steps keep the compiler's wait counts exact)
     constexpr int NRING = BANDED ? 2 * D : 1;
-    constexpr int P = 2 * D - 1 < 8 ? 2 * D - 1 : 8;
+    constexpr int P = 2 * D - 1 < 3 ? 2 * D - 1 : 3;
     T ring[NRING];
     // ---------------- forward
     {
@@ -1886,6 +1886,8 @@ static constexpr SweepCfg SWEEP_CFGS[] = {
     {1, 64, 1, 0, 0},    {1, 128, 1, 0, 0},   {1, 256, 1, 0, 0},   {1, 512, 1, 0, 0},
     {5, 64, 1, 10, 10},  {5, 128, 1, 10, 10}, {5, 256, 1, 10, 10}, {5, 128, 2, 5, 3},
     {4, 128, 1, 5, 5},   {4, 256, 1, 5, 5},   {5, 64, 1, 5, 5},    {5, 128, 1, 5, 5}, {5, 256, 1, 5, 5},
+    {5, 128, 1, 3, 3},   {5, 128, 1, 4, 4},   {4, 128, 1, 3, 3},   {5, 128, 1, 2, 2},
+    {5, 128, 1, 1, 1},   {5, 64, 1, 2, 2},    {5, 64, 1, 3, 3},    {4, 128, 1, 2, 2},
 };
 constexpr int N_SWEEP_CFGS = (int)(sizeof(SWEEP_CFGS) / sizeof(SWEEP_CFGS[0]));
 
@@ -1918,20 +1920,22 @@ void sweep_cfg_info(int cfg, int *kind, int *threads, int *rows, int *d64, int *
 // whose workgroups cannot all be resident)
 int sweep_cfg_plain(int max_nj) {
     if (max_nj <= 16) return 0;
-    if (max_nj <= 32) return 18;
+    if (max_nj <= 32) return 25;
     if (max_nj <= 64) return 19;
     if (max_nj <= 128) return 3;
     if (max_nj <= 256) return 4;
     return 13;
 }
 
-// Default by height and precision, from timings of the three levels of a
-// 256 x 128 grid: one 128-thread workgroup up to 32 rows; above, bands of
-// 32 rows (two waves each), except FP32 blocks at 64 rows, where one
-// 256-thread workgroup is faster.
+// Default by height and precision, from timings of every configuration on
+// the three levels of a 256 x 128 grid: one 128-thread workgroup with
+// prefetch depth 3 up to 32 rows; above, bands of 32 rows (two waves each)
+// with depth 2 for FP64 blocks and depth 4 for FP32 blocks (a FP32 block
+// row is one 16-byte load instead of two, so the same depth keeps fewer
+// loads in flight).
 int sweep_cfg_default(int max_nj, int fp32) {
-    if (max_nj <= 32 || (fp32 && max_nj <= 64)) return sweep_cfg_plain(max_nj);
-    return 21;
+    if (max_nj <= 32) return sweep_cfg_plain(max_nj);
+    return fp32 ? 24 : 26;
 }
 
 // Banded launches wait on neighbouring workgroups: they are used only when
@@ -1975,9 +1979,10 @@ static void sgs_dispatch(const BLev &B, const SweepArgs &a0, hipStream_t st) {
     } while (0)
 #define FAS_SGS1(C_) \
     hipLaunchKernelGGL((k_sgs<T, SWEEP_CFGS[C_].nt>), dim3(B.n), dim3(SWEEP_CFGS[C_].nt), shm, st, B.k, a)
-    static_assert(N_SWEEP_CFGS == 23 && SWEEP_CFGS[9].kind == 4 && SWEEP_CFGS[10].kind == 1 &&
+    static_assert(N_SWEEP_CFGS == 31 && SWEEP_CFGS[30].kind == 4 && SWEEP_CFGS[27].kind == 5 && SWEEP_CFGS[9].kind == 4 && SWEEP_CFGS[10].kind == 1 &&
                       SWEEP_CFGS[13].kind == 1 && SWEEP_CFGS[14].kind == 5 && SWEEP_CFGS[17].kind == 5 &&
-                      SWEEP_CFGS[18].kind == 4 && SWEEP_CFGS[19].kind == 4 && SWEEP_CFGS[20].kind == 5,
+                      SWEEP_CFGS[18].kind == 4 && SWEEP_CFGS[19].kind == 4 && SWEEP_CFGS[20].kind == 5 &&
+                      SWEEP_CFGS[22].kind == 5 && SWEEP_CFGS[24].kind == 5 && SWEEP_CFGS[25].kind == 4,
                   "the switch below follows the configuration table");
     switch (cfg) {
         case 0: FAS_SGS4(0); break;
@@ -2002,7 +2007,15 @@ static void sgs_dispatch(const BLev &B, const SweepArgs &a0, hipStream_t st) {
         case 19: FAS_SGS4(19); break;
         case 20: FAS_SGS5(20); break;
         case 21: FAS_SGS5(21); break;
-        default: FAS_SGS5(22); break;
+        case 22: FAS_SGS5(22); break;
+        case 23: FAS_SGS5(23); break;
+        case 24: FAS_SGS5(24); break;
+        case 25: FAS_SGS4(25); break;
+        case 26: FAS_SGS5(26); break;
+        case 27: FAS_SGS5(27); break;
+        case 28: FAS_SGS5(28); break;
+        case 29: FAS_SGS5(29); break;
+        default: FAS_SGS4(30); break;
     }
 #undef FAS_K4
 #undef FAS_SGS4
