@@ -16,7 +16,13 @@ Readings (the paper states no adjoint):
 * the adjoint equation is (dF/du)^T lambda = -dJ/du and the gradient of J
   with respect to a flow parameter q is dJ/dq = dJ/dq|_u + lambda^T dF/dq.
 
-Vector layout: component-major flattening of (4, nj, ni) arrays.
+* grid-node sensitivities differentiate the fine level's metrics (face
+  vectors, mean face vectors, volumes, centres, ghost reflections) with
+  respect to the node coordinates; the eddy viscosity stays frozen, so the
+  wall distance of the turbulence model is not differentiated.
+
+Vector layout: component-major flattening of (4, nj, ni) arrays; node
+arrays are (nj + 1, ni + 1), i fastest.
 """
 from __future__ import annotations
 
@@ -26,7 +32,7 @@ import numpy as np
 
 from . import gas
 from .bc import fill_ghosts
-from .geometry import NG
+from .geometry import NG, Level
 from .residual import baldwin_lomax, padded_eddy_viscosity, split_residual
 
 H_CS = 1.0e-30
@@ -60,12 +66,39 @@ def fine_residual(S, u, mutp, mach=None, alpha_deg=None):
     return Fc + Fv
 
 
-def forces(S, u, mach=None, alpha_deg=None):
-    """(C_L, C_D) of the wall pressure force of state u."""
+def _fine_level(S, x, y):
+    L0 = S.levels[0]
+    return Level(x, y, L0.topology, L0.n_wake)
+
+
+def residual_at_nodes(S, u, mutp, x, y):
+    """Steady fine-level F(u) on the grid with nodes (x, y) (which may be
+    complex), frozen eddy viscosity mutp."""
+    lev = _fine_level(S, x, y)
+    Up = np.zeros((4, lev.nj + 2 * NG, lev.ni + 2 * NG), dtype=np.result_type(u, lev.x, S.uinf))
+    Up[:, NG:NG + lev.nj, NG:NG + lev.ni] = u
+    fill_ghosts(Up, lev, S.uinf, noslip=S.par.model == 1)
+    Fc, Fv = split_residual(lev, Up, S.par, True, mutp, None, None)
+    return Fc + Fv
+
+
+def residual_node_jvp(S, u, mutp, vx, vy):
+    """(dF/dx) vx + (dF/dy) vy at fixed u: the derivative of the residual
+    along the node displacement (vx, vy), by the complex step."""
+    L0 = S.levels[0]
+    return residual_at_nodes(S, u, mutp, L0.x + 1j * H_CS * vx, L0.y + 1j * H_CS * vy).imag / H_CS
+
+
+def forces(S, u, mach=None, alpha_deg=None, nodes=None):
+    """(C_L, C_D) of the wall pressure force of state u (on the grid with
+    nodes = (x, y) if given, which may be complex)."""
     mach = S.par.mach if mach is None else mach
     alpha_deg = S.par.alpha_deg if alpha_deg is None else alpha_deg
-    lev = S.levels[0]
-    Up = _padded(S, u, gas.freestream(mach, alpha_deg))
+    lev = S.levels[0] if nodes is None else _fine_level(S, *nodes)
+    uinf = gas.freestream(mach, alpha_deg)
+    Up = np.zeros((4, lev.nj + 2 * NG, lev.ni + 2 * NG), dtype=np.result_type(u, lev.x, uinf))
+    Up[:, NG:NG + lev.nj, NG:NG + lev.ni] = u
+    fill_ghosts(Up, lev, uinf, noslip=S.par.model == 1)
     p = gas.pressure(Up)
     cols = slice(NG, NG + lev.ni)
     pw = 0.5 * (p[NG - 1, cols] + p[NG, cols])
@@ -77,6 +110,22 @@ def forces(S, u, mach=None, alpha_deg=None):
     cl = (fy * np.cos(a) - fx * np.sin(a)) / q
     cd = (fx * np.cos(a) + fy * np.sin(a)) / q
     return cl, cd
+
+
+def lift_node_jvp(S, u, vx, vy):
+    """dC_L/dx . vx + dC_L/dy . vy at fixed u (complex step)."""
+    L0 = S.levels[0]
+    return forces(S, u, nodes=(L0.x + 1j * H_CS * vx, L0.y + 1j * H_CS * vy))[0].imag / H_CS
+
+
+def lift_node_derivative(S, u, vx, vy, lam=None):
+    """Total derivative of C_L of the converged state u along the node
+    displacement (vx, vy): dC_L/dX v + lam . (dF/dX v), with lam the dense
+    adjoint solution of (dF/du)^T lam = -dC_L/du (computed if not given)."""
+    mutp = frozen_mut(S, u)
+    if lam is None:
+        _, lam = lift_gradient(S, u)
+    return lift_node_jvp(S, u, vx, vy) + np.sum(lam * residual_node_jvp(S, u, mutp, vx, vy))
 
 
 def dense_jacobian(S, u, mutp):

@@ -39,8 +39,11 @@ class Level:
     """Geometry of one multigrid level (interior ni x nj cells)."""
 
     def __init__(self, x, y, topology: int, n_wake: int, vol=None):
-        self.x = np.asarray(x, dtype=np.float64)
-        self.y = np.asarray(y, dtype=np.float64)
+        # node coordinates may be complex (complex-step derivatives with
+        # respect to the grid); every metric is then complex as well
+        dt = np.result_type(np.asarray(x), np.asarray(y), np.float64)
+        self.x = np.asarray(x, dtype=dt)
+        self.y = np.asarray(y, dtype=dt)
         self.nj = self.x.shape[0] - 1
         self.ni = self.x.shape[1] - 1
         self.topology = topology
@@ -59,7 +62,7 @@ class Level:
             d2x = x[1:, :-1] - x[:-1, 1:]
             d2y = y[1:, :-1] - y[:-1, 1:]
             vol = 0.5 * (d1x * d2y - d1y * d2x)
-        if np.any(vol <= 0.0):
+        if np.any(np.real(vol) <= 0.0):
             raise ValueError("non-positive cell volume (grid must be right-handed)")
         self.vol = vol
         # face midpoints
@@ -68,10 +71,10 @@ class Level:
         # padded cell data: centre and mean face vectors
         P = NG
         shape = (nj + 2 * P, ni + 2 * P)
-        xc = np.zeros(shape)
-        yc = np.zeros(shape)
-        sb = np.zeros((4,) + shape)     # sbar_xi x,y ; sbar_eta x,y
-        vp = np.zeros(shape)            # volume, ghosts copy their source
+        xc = np.zeros(shape, dtype=dt)
+        yc = np.zeros(shape, dtype=dt)
+        sb = np.zeros((4,) + shape, dtype=dt)     # sbar_xi x,y ; sbar_eta x,y
+        vp = np.zeros(shape, dtype=dt)            # volume, ghosts copy their source
         xc[P:P + nj, P:P + ni] = 0.25 * (((x[:-1, :-1] + x[:-1, 1:]) + x[1:, 1:]) + x[1:, :-1])
         yc[P:P + nj, P:P + ni] = 0.25 * (((y[:-1, :-1] + y[:-1, 1:]) + y[1:, 1:]) + y[1:, :-1])
         sb[0, P:P + nj, P:P + ni] = 0.5 * (self.Sxi[0][:, :-1] + self.Sxi[0][:, 1:])

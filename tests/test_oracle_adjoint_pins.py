@@ -88,3 +88,78 @@ def test_adjoint_gradient_equals_direct_sensitivity(model):
     dum = np.linalg.solve(J, -dm.reshape(-1))
     assert abs(ga - (cla + g.reshape(-1) @ dua)) <= 1e-8 * abs(ga)
     assert abs(gm - (clm + g.reshape(-1) @ dum)) <= 1e-8 * abs(gm)
+
+
+def _spacing(x, y):
+    """Smallest edge length at every node (scales test displacements, so
+    that the displaced grids stay valid at wall spacings of 1e-6)."""
+    sp = np.full(x.shape, np.inf)
+    di = np.hypot(np.diff(x, axis=1), np.diff(y, axis=1))
+    dj = np.hypot(np.diff(x, axis=0), np.diff(y, axis=0))
+    sp[:, :-1] = np.minimum(sp[:, :-1], di)
+    sp[:, 1:] = np.minimum(sp[:, 1:], di)
+    sp[:-1, :] = np.minimum(sp[:-1, :], dj)
+    sp[1:, :] = np.minimum(sp[1:, :], dj)
+    return sp
+
+
+@pytest.mark.parametrize("model", [0, 1])
+def test_node_derivative_of_residual_matches_central_differences(model):
+    S, u = _state(model)
+    mutp = adj.frozen_mut(S, u)
+    x, y = S.levels[0].x, S.levels[0].y
+    sp = _spacing(x, y)
+    rng = np.random.default_rng(4)
+    vx, vy = rng.standard_normal(x.shape) * sp, rng.standard_normal(x.shape) * sp
+    jv = adj.residual_node_jvp(S, u, mutp, vx, vy)
+    h = 1e-5
+    fd = (adj.residual_at_nodes(S, u, mutp, x + h * vx, y + h * vy)
+          - adj.residual_at_nodes(S, u, mutp, x - h * vx, y - h * vy)) / (2 * h)
+    assert np.abs(jv - fd).max() <= 2e-6 * np.abs(jv).max()
+    # on the unperturbed nodes the residual is the solver's own
+    F0 = adj.residual_at_nodes(S, u, mutp, x, y)
+    assert np.array_equal(F0, adj.fine_residual(S, u, mutp))
+
+
+@pytest.mark.parametrize("model", [0, 1])
+def test_translating_the_grid_changes_neither_residual_nor_lift(model):
+    """F and C_L depend on node differences only (the turbulence model's
+    wall distance is frozen): a rigid translation has zero derivative."""
+    S, u = _state(model)
+    mutp = adj.frozen_mut(S, u)
+    x = S.levels[0].x
+    one, zero = np.ones(x.shape), np.zeros(x.shape)
+    scale = np.abs(adj.residual_node_jvp(S, u, mutp, *(np.random.default_rng(5).standard_normal((2,) + x.shape)))).max()
+    for v in ((one, zero), (zero, one)):
+        assert np.abs(adj.residual_node_jvp(S, u, mutp, *v)).max() <= 1e-13 * scale
+        assert abs(adj.lift_node_jvp(S, u, *v)) <= 1e-13
+
+
+def test_node_derivative_of_lift_matches_central_differences():
+    S, u = _state(0)
+    x, y = S.levels[0].x, S.levels[0].y
+    sp = _spacing(x, y)
+    rng = np.random.default_rng(6)
+    vx, vy = rng.standard_normal(x.shape) * sp, rng.standard_normal(x.shape) * sp
+    h = 1e-5
+    fd = (adj.forces(S, u, nodes=(x + h * vx, y + h * vy))[0]
+          - adj.forces(S, u, nodes=(x - h * vx, y - h * vy))[0]) / (2 * h)
+    # the derivative along this displacement is ~1e-6 while C_L ~ 0.1: the
+    # central difference carries ~1e-16 * 0.1 / h of cancellation error
+    assert abs(adj.lift_node_jvp(S, u, vx, vy) - fd) <= 1e-4 * abs(fd)
+
+
+@pytest.mark.parametrize("model", [0, 1])
+def test_adjoint_node_derivative_equals_direct_sensitivity(model):
+    """dC_L/dX v = dC_L/dX|_u v + g . du with J du = -(dF/dX) v (direct)
+    equals the adjoint form used for the node gradient."""
+    S, u = _state(model, ni=16, nj=8, nw=2)
+    mutp = adj.frozen_mut(S, u)
+    x = S.levels[0].x
+    rng = np.random.default_rng(7)
+    vx, vy = rng.standard_normal((2,) + x.shape) * _spacing(x, S.levels[0].y)
+    J = adj.dense_jacobian(S, u, mutp)
+    g, _, _ = adj.lift_partials(S, u)
+    du = np.linalg.solve(J, -adj.residual_node_jvp(S, u, mutp, vx, vy).reshape(-1))
+    direct = adj.lift_node_jvp(S, u, vx, vy) + g.reshape(-1) @ du
+    assert abs(adj.lift_node_derivative(S, u, vx, vy) - direct) <= 1e-8 * abs(direct)
