@@ -88,6 +88,12 @@ fas_status fas_grid_create(int32_t topology, int32_t ni, int32_t nj, int32_t n_w
                            const double *x_nodes, const double *y_nodes,
                            int32_t n_levels, fas_grid *out);
 void fas_grid_destroy(fas_grid g);
+/* Move the grid's nodes (host arrays as for fas_grid_create): every level's
+ * metrics are recomputed; states on the grid use them from their next call
+ * (a moving state's rotated copy from its next rotation).  Synchronises the
+ * device.  Errors: FAS_EINVAL (null, other device, non-positive volume),
+ * FAS_EDEVICE. */
+fas_status fas_grid_set_nodes(fas_grid g, const double *x_nodes, const double *y_nodes);
 
 /*
  * State of one flow case on grid g, initialised with the fine-level
@@ -279,6 +285,25 @@ fas_status fas_adjoint_solve(fas_state s, const double *rhs, double *lam, int32_
                              double drop_orders, double *res_hist, int32_t *n_iter);
 fas_status fas_lift_gradient(fas_state s, int32_t max_iter, double drop_orders, double *cl,
                              double *grad, double *res_hist, int32_t *n_iter);
+
+/*
+ * Grid-node sensitivities of the steady fine-level residual and the lift.
+ * The residual depends on the nodes through the metrics of Section 2 (face
+ * vectors, mean face vectors, volumes, cell centres, and the ghost cells'
+ * centres reflected across the boundary faces); the eddy viscosity is
+ * frozen, so the turbulence model's wall distance is not differentiated.
+ * Node arrays: device [(nj+1)][(ni+1)], i fastest, every node an
+ * independent coordinate (the coinciding wake-cut nodes included).
+ * fas_vjp_nodes: dx = (dF/dx)^T lam, dy = (dF/dy)^T lam (overwritten), lam
+ * device [4][nj][ni].
+ * fas_lift_gradient_nodes: fas_lift_gradient, plus dC_L/dx and dC_L/dy of
+ * every node: dC_L/dX = dC_L/dX|_u + lam^T dF/dX with the same adjoint
+ * solution.  Errors as fas_lift_gradient; moving meshes: FAS_EINVAL.
+ */
+fas_status fas_vjp_nodes(fas_state s, const double *lam, double *dx, double *dy);
+fas_status fas_lift_gradient_nodes(fas_state s, int32_t max_iter, double drop_orders, double *cl,
+                                   double *grad, double *dcl_dx, double *dcl_dy, double *res_hist,
+                                   int32_t *n_iter);
 
 /* Message of the last failing call on this thread (never NULL). */
 const char *fas_last_error(void);

@@ -112,6 +112,24 @@ def forces(S, u, mach=None, alpha_deg=None, nodes=None):
     return cl, cd
 
 
+def residual_node_vjp(S, u, mutp, lam):
+    """((dF/dx)^T lam, (dF/dy)^T lam) on the node arrays, one complex-step
+    residual per node coordinate (small grids only)."""
+    L0 = S.levels[0]
+    out = []
+    for axis in (0, 1):
+        g = np.empty(L0.x.shape)
+        for J in range(L0.x.shape[0]):
+            for I in range(L0.x.shape[1]):
+                e = np.zeros(L0.x.shape)
+                e[J, I] = 1.0
+                z = np.zeros(L0.x.shape)
+                jv = residual_node_jvp(S, u, mutp, e if axis == 0 else z, z if axis == 0 else e)
+                g[J, I] = np.sum(lam * jv)
+        out.append(g)
+    return out[0], out[1]
+
+
 def lift_node_jvp(S, u, vx, vy):
     """dC_L/dx . vx + dC_L/dy . vy at fixed u (complex step)."""
     L0 = S.levels[0]

@@ -7,6 +7,7 @@
 // numbers on a cell's local stencil, with the eddy viscosity frozen at the
 // state.  Layout: fas_internal.h.
 #include "fas_internal.h"
+#include "fas_geom.h"
 
 #include <cmath>
 
@@ -107,7 +108,30 @@ struct Ctx {
     double pr, prt, kappa2c;
     int rans, noslip, fine, viscous;
     int si, sj;
+    int gp[4], gs[4];     // geometry seeds: plane and slot of derivative lane k (-1: none)
 };
+
+using ::fas::gsqrt;
+__device__ inline D4 gsqrt(const D4 &a) { return dsqrt(a); }
+
+// a metric value: plain, or as a dual number seeded on the geometry lanes
+template <class G> struct GeoRead;
+template <> struct GeoRead<double> {
+    __device__ static double at(const Ctx &c, int p, int s) { return c.geo[p * c.L.NS + s]; }
+};
+template <> struct GeoRead<D4> {
+    __device__ static D4 at(const Ctx &c, int p, int s) {
+        D4 v = dc(c.geo[p * c.L.NS + s]);
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+            if (c.gp[k] == p && c.gs[k] == s) v.d[k] = 1.0;
+        return v;
+    }
+};
+template <class G>
+__device__ inline G gget(const Ctx &c, int p, int s) {
+    return GeoRead<G>::at(c, p, s);
+}
 
 __device__ inline void cell_u(const Ctx &c, int i, int j, D4 o[4]) {
     const int s = c.L.slot(i, j), NS = c.L.NS;
@@ -123,14 +147,16 @@ __device__ inline D4 dpres(const D4 U[4]) {
     return (GAM - 1.0) * (U[3] - 0.5 * (U[1] * U[1] + U[2] * U[2]) / U[0]);
 }
 
-__device__ inline void unit(double sx, double sy, double &nx, double &ny) {
-    double ln = sqrt(sx * sx + sy * sy);
+template <class G>
+__device__ inline void unit(G sx, G sy, G &nx, G &ny) {
+    G ln = gsqrt(sx * sx + sy * sy);
     nx = sx / ln;
     ny = sy / ln;
 }
 
 // Riemann-invariant far-field state (Section 2)
-__device__ void farfield(const D4 ui[4], const D4 uf[4], double nx, double ny, D4 out[4]) {
+template <class G>
+__device__ void farfield(const D4 ui[4], const D4 uf[4], G nx, G ny, D4 out[4]) {
     const double g1 = GAM - 1.0;
     D4 rho = ui[0];
     D4 vx = ui[1] / rho, vy = ui[2] / rho;
@@ -161,6 +187,7 @@ __device__ void farfield(const D4 ui[4], const D4 uf[4], double nx, double ny, D
 }
 
 // state of (i, j): i interior, j in [-2, nj + 2)
+template <class G>
 __device__ void jrow(const Ctx &c, int i, int j, D4 o[4]) {
     const Lay &L = c.L;
     const int NS = L.NS;
@@ -183,8 +210,8 @@ __device__ void jrow(const Ctx &c, int i, int j, D4 o[4]) {
             o[3] = ui[3];
         } else {
             const int f = L.slot(i, 0);
-            double nx, ny;
-            unit(c.geo[G_SETA_X * NS + f], c.geo[G_SETA_Y * NS + f], nx, ny);
+            G nx, ny;
+            unit<G>(gget<G>(c, G_SETA_X, f), gget<G>(c, G_SETA_Y, f), nx, ny);
             D4 mn = ui[1] * nx + ui[2] * ny;
             o[0] = ui[0];
             o[1] = ui[1] - 2.0 * mn * nx;
@@ -197,32 +224,32 @@ __device__ void jrow(const Ctx &c, int i, int j, D4 o[4]) {
     D4 ui[4];
     cell_u(c, i, L.nj - 1 - k, ui);
     const int f = L.slot(i, L.nj);
-    double nx, ny;
-    unit(c.geo[G_SETA_X * NS + f], c.geo[G_SETA_Y * NS + f], nx, ny);
-    farfield(ui, c.uinf, nx, ny, o);
+    G nx, ny;
+    unit<G>(gget<G>(c, G_SETA_X, f), gget<G>(c, G_SETA_Y, f), nx, ny);
+    farfield<G>(ui, c.uinf, nx, ny, o);
 }
 
 // state of any padded cell (i, j), i and j in [-2, n + 2)
+template <class G>
 __device__ void state(const Ctx &c, int i, int j, D4 o[4]) {
     const Lay &L = c.L;
     if (i >= 0 && i < L.ni) {
-        jrow(c, i, j, o);
+        jrow<G>(c, i, j, o);
         return;
     }
-    const int NS = L.NS;
     const int jc = min(max(j, 0), L.nj - 1);
     D4 src[4];
-    double nx, ny;
+    G nx, ny;
     if (i < 0) {
-        jrow(c, -1 - i, j, src);
+        jrow<G>(c, -1 - i, j, src);
         const int f = L.slot(0, jc);
-        unit(-c.geo[G_SXI_X * NS + f], -c.geo[G_SXI_Y * NS + f], nx, ny);
+        unit<G>(-gget<G>(c, G_SXI_X, f), -gget<G>(c, G_SXI_Y, f), nx, ny);
     } else {
-        jrow(c, L.ni - 1 - (i - L.ni), j, src);
+        jrow<G>(c, L.ni - 1 - (i - L.ni), j, src);
         const int f = L.slot(L.ni, jc);
-        unit(c.geo[G_SXI_X * NS + f], c.geo[G_SXI_Y * NS + f], nx, ny);
+        unit<G>(gget<G>(c, G_SXI_X, f), gget<G>(c, G_SXI_Y, f), nx, ny);
     }
-    farfield(src, c.uinf, nx, ny, o);
+    farfield<G>(src, c.uinf, nx, ny, o);
 }
 
 // interior cell whose state a padded cell's state is built from
@@ -247,18 +274,19 @@ struct CQ {
 };
 
 // Section 2: pressure, sensor quantity, corrected spectral radii, p / rho
+template <class G>
 __device__ void cell_q(const Ctx &c, int i, int j, CQ &o) {
-    state(c, i, j, o.U);
-    const int s = c.L.slot(i, j), NS = c.L.NS;
+    state<G>(c, i, j, o.U);
+    const int s = c.L.slot(i, j);
     const D4 &r = o.U[0];
     D4 vx = o.U[1] / r, vy = o.U[2] / r;
     o.p = dpres(o.U);
     D4 a = dsqrt(GAM * o.p / r);
     o.q = c.rans ? o.p / dpow(r, GAM) : o.p;
-    const double sb0 = c.geo[G_SB0 * NS + s], sb1 = c.geo[G_SB1 * NS + s];
-    const double sb2 = c.geo[G_SB2 * NS + s], sb3 = c.geo[G_SB3 * NS + s];
-    D4 rxi = dabs(vx * sb0 + vy * sb1) + a * sqrt(sb0 * sb0 + sb1 * sb1);
-    D4 reta = dabs(vx * sb2 + vy * sb3) + a * sqrt(sb2 * sb2 + sb3 * sb3);
+    const G sb0 = gget<G>(c, G_SB0, s), sb1 = gget<G>(c, G_SB1, s);
+    const G sb2 = gget<G>(c, G_SB2, s), sb3 = gget<G>(c, G_SB3, s);
+    D4 rxi = dabs(vx * sb0 + vy * sb1) + a * gsqrt(sb0 * sb0 + sb1 * sb1);
+    D4 reta = dabs(vx * sb2 + vy * sb3) + a * gsqrt(sb2 * sb2 + sb3 * sb3);
     D4 t = reta / rxi;
     o.rxi = rxi * (1.0 + dcbrt(t * t));
     t = rxi / reta;
@@ -268,23 +296,23 @@ __device__ void cell_q(const Ctx &c, int i, int j, CQ &o) {
 
 // Green-Gauss gradients of (u, v, T) at vertex (I, J) over the four cell
 // centres SW, SE, NE, NW
+template <class G>
 __device__ void vertex_grad(const Ctx &c, int I, int J, D4 g[6]) {
-    const int NS = c.L.NS;
     const int ci[4] = {I - 1, I, I, I - 1}, cj[4] = {J - 1, J - 1, J, J};
-    double X[4], Y[4];
+    G X[4], Y[4];
     D4 U[4], V[4], T[4];
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
         const int s = c.L.slot(ci[k], cj[k]);
-        X[k] = c.geo[G_XC * NS + s];
-        Y[k] = c.geo[G_YC * NS + s];
+        X[k] = gget<G>(c, G_XC, s);
+        Y[k] = gget<G>(c, G_YC, s);
         D4 st[4];
-        state(c, ci[k], cj[k], st);
+        state<G>(c, ci[k], cj[k], st);
         U[k] = st[1] / st[0];
         V[k] = st[2] / st[0];
         T[k] = dpres(st) / st[0];
     }
-    const double A = 0.5 * ((X[2] - X[0]) * (Y[3] - Y[1]) - (Y[2] - Y[0]) * (X[3] - X[1]));
+    const G A = 0.5 * ((X[2] - X[0]) * (Y[3] - Y[1]) - (Y[2] - Y[0]) * (X[3] - X[1]));
     const D4 *phi[3] = {U, V, T};
 #pragma unroll
     for (int f = 0; f < 3; ++f) {
@@ -314,12 +342,13 @@ __device__ inline D4 dsutherland(const D4 &T, const D4 &mu_inf) {
 
 // JST face flux (central C, dissipation / viscous V) between L and R with
 // outer neighbours LL and RR (Section 2), as in the primal residual
+template <class G>
 __device__ void face(const Ctx &c, int iL, int jL, int iR, int jR, int iLL, int jLL, int iRR, int jRR,
-                     bool xi_face, double sx, double sy, bool wall, int vAi, int vAj, int vBi, int vBj,
+                     bool xi_face, G sx, G sy, bool wall, int vAi, int vAj, int vBi, int vBj,
                      D4 C[4], D4 V[4]) {
     CQ L, R;
-    cell_q(c, iL, jL, L);
-    cell_q(c, iR, jR, R);
+    cell_q<G>(c, iL, jL, L);
+    cell_q<G>(c, iR, jR, R);
     if (wall) {
         D4 pw = 0.5 * (L.p + R.p);
         C[0] = dc(0.0);
@@ -341,8 +370,8 @@ __device__ void face(const Ctx &c, int iL, int jL, int iR, int jR, int iLL, int 
         D4 d[4];
         if (c.fine) {
             CQ LL, RR;
-            cell_q(c, iLL, jLL, LL);
-            cell_q(c, iRR, jRR, RR);
+            cell_q<G>(c, iLL, jLL, LL);
+            cell_q<G>(c, iRR, jRR, RR);
             D4 sLs = dabs(((R.q - 2.0 * L.q) + LL.q) / (((R.q + 2.0 * L.q) + LL.q) + 0.001));
             D4 sRs = dabs(((RR.q - 2.0 * R.q) + L.q) / (((RR.q + 2.0 * R.q) + L.q) + 0.001));
             D4 sf = dmin(dc(0.25), dmax(sLs, sRs));
@@ -363,8 +392,8 @@ __device__ void face(const Ctx &c, int iL, int jL, int iR, int jR, int iLL, int 
     }
     if (c.viscous) {
         D4 gA[6], gB[6];
-        vertex_grad(c, vAi, vAj, gA);
-        vertex_grad(c, vBi, vBj, gB);
+        vertex_grad<G>(c, vAi, vAj, gA);
+        vertex_grad<G>(c, vBi, vBj, gB);
         D4 fux = 0.5 * (gA[0] + gB[0]), fuy = 0.5 * (gA[1] + gB[1]);
         D4 fwx = 0.5 * (gA[2] + gB[2]), fwy = 0.5 * (gA[3] + gB[3]);
         D4 fTx = 0.5 * (gA[4] + gB[4]), fTy = 0.5 * (gA[5] + gB[5]);
@@ -391,21 +420,21 @@ __device__ void face(const Ctx &c, int iL, int jL, int iR, int jR, int iLL, int 
 }
 
 // F of interior cell (i, j) per unit volume (steady, no forcing)
+template <class G>
 __device__ void cell_residual(const Ctx &c, int i, int j, D4 F[4]) {
     const Lay &L = c.L;
-    const int NS = L.NS, s = L.slot(i, j), NJ = L.NJ;
-    const double *g = c.geo;
+    const int s = L.slot(i, j), NJ = L.NJ;
     D4 wC[4], wV[4], eC[4], eV[4], sC[4], sV[4], nC[4], nV[4];
-    face(c, i - 1, j, i, j, i - 2, j, i + 1, j, true, g[G_SXI_X * NS + s], g[G_SXI_Y * NS + s], false,
-         i, j, i, j + 1, wC, wV);
-    face(c, i, j, i + 1, j, i - 1, j, i + 2, j, true, g[G_SXI_X * NS + s + NJ], g[G_SXI_Y * NS + s + NJ],
-         false, i + 1, j, i + 1, j + 1, eC, eV);
+    face<G>(c, i - 1, j, i, j, i - 2, j, i + 1, j, true, gget<G>(c, G_SXI_X, s), gget<G>(c, G_SXI_Y, s), false,
+            i, j, i, j + 1, wC, wV);
+    face<G>(c, i, j, i + 1, j, i - 1, j, i + 2, j, true, gget<G>(c, G_SXI_X, s + NJ),
+            gget<G>(c, G_SXI_Y, s + NJ), false, i + 1, j, i + 1, j + 1, eC, eV);
     const bool wall = (j == 0) && !cut_col(L, i);
-    face(c, i, j - 1, i, j, i, j - 2, i, j + 1, false, g[G_SETA_X * NS + s], g[G_SETA_Y * NS + s], wall,
-         i, j, i + 1, j, sC, sV);
-    face(c, i, j, i, j + 1, i, j - 1, i, j + 2, false, g[G_SETA_X * NS + s + NJ + 1],
-         g[G_SETA_Y * NS + s + NJ + 1], false, i, j + 1, i + 1, j + 1, nC, nV);
-    const double vol = g[G_VOL * NS + s];
+    face<G>(c, i, j - 1, i, j, i, j - 2, i, j + 1, false, gget<G>(c, G_SETA_X, s), gget<G>(c, G_SETA_Y, s),
+            wall, i, j, i + 1, j, sC, sV);
+    face<G>(c, i, j, i, j + 1, i, j - 1, i, j + 2, false, gget<G>(c, G_SETA_X, s + NJ + 1),
+            gget<G>(c, G_SETA_Y, s + NJ + 1), false, i, j + 1, i + 1, j + 1, nC, nV);
+    const G vol = gget<G>(c, G_VOL, s);
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
         D4 fc = (eC[k] - wC[k]) + (nC[k] - sC[k]);
@@ -431,6 +460,8 @@ __device__ void make_ctx(Ctx &c, const Lay &L, const double *geo, const double *
     c.fine = 1;
     c.viscous = ph.rans;
     c.si = c.sj = -1000000;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) c.gp[k] = c.gs[k] = -1;
 }
 
 // ------------------------------------------------------------------ kernels
@@ -466,12 +497,215 @@ __global__ __launch_bounds__(TPB) void k_vjp(Lay L, const double *geo, const dou
         c.si = srci[q];
         c.sj = srcj[q];
         D4 F[4];
-        cell_residual(c, i, j, F);
+        cell_residual<double>(c, i, j, F);
         const int t = L.slot(c.si, c.sj);
 #pragma unroll
         for (int m = 0; m < 4; ++m) {
             const double v = ((lc[0] * F[0].d[m] + lc[1] * F[1].d[m]) + lc[2] * F[2].d[m]) + lc[3] * F[3].d[m];
             atomicAdd(out + m * NS + t, v);
+        }
+    }
+}
+
+// Grid-node sensitivities (chain rule through the metrics).  The residual
+// depends on the nodes only through the metric planes SXI, SETA, SB0-3, VOL,
+// XC, YC (the eddy viscosity, and with it the wall distance, is frozen).
+// gbar(p, slot) += sum_c lam_c . dF_c / dG(p, slot): every interior cell
+// seeds the metric entries its residual reads, four per evaluation.
+constexpr int N_GEO_ADJ = G_YC + 1;       // planes G_SXI_X .. G_YC
+constexpr int MAX_GSEEDS = 96;
+
+__global__ __launch_bounds__(TPB) void k_vjp_geo(Lay L, const double *geo, const double *u, const double *mut,
+                                                 Phys ph, const double *lam, double *gbar) {
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    int i, j;
+    if (!decode(L, s, i, j) || !interior(L, i, j)) return;
+    const int NS = L.NS;
+    double lc[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) lc[k] = lam[k * NS + s];
+    if (lc[0] == 0.0 && lc[1] == 0.0 && lc[2] == 0.0 && lc[3] == 0.0) return;
+    Ctx c;
+    make_ctx(c, L, geo, u, mut, ph);
+    int ep[MAX_GSEEDS], es[MAX_GSEEDS], n = 0;
+    auto add = [&](int p, int ii, int jj) {
+        const int t = L.slot(ii, jj);
+        for (int q = 0; q < n; ++q)
+            if (ep[q] == p && es[q] == t) return;
+        if (n < MAX_GSEEDS) {
+            ep[n] = p;
+            es[n] = t;
+            ++n;
+        }
+    };
+    // the cell's faces and volume
+    add(G_SXI_X, i, j); add(G_SXI_Y, i, j); add(G_SXI_X, i + 1, j); add(G_SXI_Y, i + 1, j);
+    add(G_SETA_X, i, j); add(G_SETA_Y, i, j); add(G_SETA_X, i, j + 1); add(G_SETA_Y, i, j + 1);
+    add(G_VOL, i, j);
+    // mean face vectors of the two cells of each face (spectral radii)
+    const int nb[5][2] = {{0, 0}, {-1, 0}, {1, 0}, {0, -1}, {0, 1}};
+    for (int q = 0; q < 5; ++q)
+        for (int p = G_SB0; p <= G_SB3; ++p) add(p, i + nb[q][0], j + nb[q][1]);
+    // centres of the cells around the face vertices (viscous gradients)
+    if (c.viscous)
+        for (int dj = -1; dj <= 1; ++dj)
+            for (int di = -1; di <= 1; ++di) {
+                add(G_XC, i + di, j + dj);
+                add(G_YC, i + di, j + dj);
+            }
+    // boundary normals of the ghost states in the stencil
+    for (int dj = -2; dj <= 2; ++dj)
+        for (int di = -2; di <= 2; ++di) {
+            const int a = i + di, b = j + dj;
+            if (interior(L, a, b)) continue;
+            const int jc = min(max(b, 0), L.nj - 1);
+            if (a < 0) { add(G_SXI_X, 0, jc); add(G_SXI_Y, 0, jc); }
+            if (a >= L.ni) { add(G_SXI_X, L.ni, jc); add(G_SXI_Y, L.ni, jc); }
+            const int ia = a < 0 ? -1 - a : (a >= L.ni ? L.ni - 1 - (a - L.ni) : a);
+            if (b < 0 && !cut_col(L, ia) && !c.noslip) { add(G_SETA_X, ia, 0); add(G_SETA_Y, ia, 0); }
+            if (b >= L.nj) { add(G_SETA_X, ia, L.nj); add(G_SETA_Y, ia, L.nj); }
+        }
+    for (int g = 0; g < n; g += 4) {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            c.gp[k] = g + k < n ? ep[g + k] : -1;
+            c.gs[k] = g + k < n ? es[g + k] : -1;
+        }
+        D4 F[4];
+        cell_residual<D4>(c, i, j, F);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            if (g + k >= n) break;
+            const double v = ((lc[0] * F[0].d[k] + lc[1] * F[1].d[k]) + lc[2] * F[2].d[k]) + lc[3] * F[3].d[k];
+            atomicAdd(gbar + (size_t)ep[g + k] * NS + es[g + k], v);
+        }
+    }
+}
+
+// gbar += dC_L/dS of the wall faces (the force is -sum p_w S; p_w does not
+// depend on the metrics for no-slip or slip walls): one thread per column
+__global__ void k_forces_geo(Lay L, const double *geo, const double *u, Phys ph, double *gbar) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= L.ni || cut_col(L, i)) return;
+    const int NS = L.NS;
+    Ctx c;
+    make_ctx(c, L, geo, u, nullptr, ph);
+    D4 Ug[4], Ui[4];
+    state<double>(c, i, -1, Ug);
+    state<double>(c, i, 0, Ui);
+    const double pw = (0.5 * (dpres(Ug) + dpres(Ui))).v;
+    const double a = ph.alpha_deg * (M_PI / 180.0);
+    const double q = 0.5 * (ph.mach * ph.mach * GAM);
+    const int f = L.slot(i, 0);
+    gbar[(size_t)G_SETA_X * NS + f] += pw * sin(a) / q;
+    gbar[(size_t)G_SETA_Y * NS + f] += -pw * cos(a) / q;
+}
+
+// (dG/dX)^T gbar: every padded slot differentiates its metrics (faces
+// stored there, the cell's volume, centre and mean face vectors, or the
+// reflected centre and copied metrics of a ghost cell) with respect to the
+// nodes they depend on, four coordinates per evaluation, and scatters into
+// the node gradients dx, dy ((nj + 1) x (ni + 1), i fastest).
+__global__ __launch_bounds__(TPB) void k_geo_nodes(Lay L, const double *xn, const double *yn,
+                                                   const double *gbar, double *dx, double *dy) {
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    int i, j;
+    if (!decode(L, s, i, j)) return;
+    const int NS = L.NS, W = L.ni + 1;
+    double gb[N_GEO_ADJ];
+    bool any = false;
+#pragma unroll
+    for (int p = 0; p < N_GEO_ADJ; ++p) {
+        gb[p] = gbar[(size_t)p * NS + s];
+        any = any || gb[p] != 0.0;
+    }
+    if (!any) return;
+    const bool iface = i >= 0 && i <= L.ni && j >= 0 && j < L.nj;
+    const bool jface = i >= 0 && i < L.ni && j >= 0 && j <= L.nj;
+    // dependency nodes
+    int nd[16][2], nn = 0;
+    {
+        auto Xd = [&](int I, int J) { return xn[J * W + I]; };
+        auto Yd = [&](int I, int J) { return yn[J * W + I]; };
+        if (iface) { nd[nn][0] = i; nd[nn][1] = j; nd[nn + 1][0] = i; nd[nn + 1][1] = j + 1; nn += 2; }
+        if (jface) { nd[nn][0] = i; nd[nn][1] = j; nd[nn + 1][0] = i + 1; nd[nn + 1][1] = j; nn += 2; }
+        if (interior(L, i, j)) {
+            nd[nn][0] = i; nd[nn][1] = j; nd[nn + 1][0] = i + 1; nd[nn + 1][1] = j;
+            nd[nn + 2][0] = i; nd[nn + 2][1] = j + 1; nd[nn + 3][0] = i + 1; nd[nn + 3][1] = j + 1;
+            nn += 4;
+        } else {
+            double cx, cy;
+            int si, sj;
+            g_centre<double>(L, Xd, Yd, i, j, cx, cy, si, sj, nd + nn, &nn);
+        }
+    }
+    // unique (node, axis) coordinates
+    int cI[32], cJ[32], cA[32], nc = 0;
+    for (int q = 0; q < nn; ++q) {
+        bool dup = false;
+        for (int r = 0; r < q; ++r) dup = dup || (nd[r][0] == nd[q][0] && nd[r][1] == nd[q][1]);
+        if (dup) continue;
+        for (int ax = 0; ax < 2; ++ax) {
+            cI[nc] = nd[q][0];
+            cJ[nc] = nd[q][1];
+            cA[nc] = ax;
+            ++nc;
+        }
+    }
+    for (int g = 0; g < nc; g += 4) {
+        auto X = [&](int I, int J) {
+            D4 v = dc(xn[J * W + I]);
+#pragma unroll
+            for (int k = 0; k < 4; ++k)
+                if (g + k < nc && cA[g + k] == 0 && cI[g + k] == I && cJ[g + k] == J) v.d[k] = 1.0;
+            return v;
+        };
+        auto Y = [&](int I, int J) {
+            D4 v = dc(yn[J * W + I]);
+#pragma unroll
+            for (int k = 0; k < 4; ++k)
+                if (g + k < nc && cA[g + k] == 1 && cI[g + k] == I && cJ[g + k] == J) v.d[k] = 1.0;
+            return v;
+        };
+        double acc[4] = {0.0, 0.0, 0.0, 0.0};
+        auto take = [&](double w, const D4 &v) {
+            if (w == 0.0) return;
+#pragma unroll
+            for (int k = 0; k < 4; ++k) acc[k] += w * v.d[k];
+        };
+        if (iface) {
+            D4 sx, sy;
+            g_iface<D4>(X, Y, i, j, sx, sy);
+            take(gb[G_SXI_X], sx);
+            take(gb[G_SXI_Y], sy);
+        }
+        if (jface) {
+            D4 sx, sy;
+            g_jface<D4>(X, Y, i, j, sx, sy);
+            take(gb[G_SETA_X], sx);
+            take(gb[G_SETA_Y], sy);
+        }
+        D4 vol, xc, yc, sb[4];
+        if (interior(L, i, j)) {
+            g_cell<D4>(X, Y, i, j, vol, xc, yc, sb);
+        } else {
+            int si, sj;
+            g_centre<D4>(L, X, Y, i, j, xc, yc, si, sj);
+            D4 xs, ys;
+            g_cell<D4>(X, Y, si, sj, vol, xs, ys, sb);
+        }
+        take(gb[G_VOL], vol);
+        take(gb[G_XC], xc);
+        take(gb[G_YC], yc);
+        take(gb[G_SB0], sb[0]);
+        take(gb[G_SB1], sb[1]);
+        take(gb[G_SB2], sb[2]);
+        take(gb[G_SB3], sb[3]);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            if (g + k >= nc) break;
+            double *dst = cA[g + k] == 0 ? dx : dy;
+            atomicAdd(dst + cJ[g + k] * W + cI[g + k], acc[k]);
         }
     }
 }
@@ -501,7 +735,7 @@ __global__ __launch_bounds__(TPB) void k_param_partials(Lay L, const double *geo
     c.uinf[3] = D4{ph.uinf[3], {E.d[0], E.d[1], 0.0, 0.0}};
     if (ph.rans) c.mu_inf.d[1] = sqrt(GAM) / reynolds;
     D4 F[4];
-    cell_residual(c, i, j, F);
+    cell_residual<double>(c, i, j, F);
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
         dFa[k * NS + s] = F[k].d[0];
@@ -527,8 +761,8 @@ __global__ __launch_bounds__(TPB) void k_forces(Lay L, const double *geo, const 
         c.si = i;
         c.sj = 0;
         D4 Ug[4], Ui[4];
-        state(c, i, -1, Ug);
-        state(c, i, 0, Ui);
+        state<double>(c, i, -1, Ug);
+        state<double>(c, i, 0, Ui);
         D4 pw = 0.5 * (dpres(Ug) + dpres(Ui));
         const int f = L.slot(i, 0);
         const double Sx = geo[G_SETA_X * NS + f], Sy = geo[G_SETA_Y * NS + f];
@@ -787,6 +1021,21 @@ void launch_param_partials(const Lay &L, const double *geo, const double *u, con
                            const Phys &ph, double reynolds, double *dFa, double *dFm, hipStream_t st) {
     hipLaunchKernelGGL(k_param_partials, dim3(nblocks(L.NS)), dim3(TPB), 0, st, L, geo, u, mut, ph,
                        reynolds, dFa, dFm);
+}
+
+void launch_vjp_geo(const Lay &L, const double *geo, const double *u, const double *mut, const Phys &ph,
+                    const double *lam, double *gbar, hipStream_t st) {
+    hipLaunchKernelGGL(k_vjp_geo, dim3(nblocks(L.NS)), dim3(TPB), 0, st, L, geo, u, mut, ph, lam, gbar);
+}
+
+void launch_forces_geo(const Lay &L, const double *geo, const double *u, const Phys &ph, double *gbar,
+                       hipStream_t st) {
+    hipLaunchKernelGGL(k_forces_geo, dim3(nblocks(L.ni)), dim3(TPB), 0, st, L, geo, u, ph, gbar);
+}
+
+void launch_geo_nodes(const Lay &L, const double *xn, const double *yn, const double *gbar, double *dx,
+                      double *dy, hipStream_t st) {
+    hipLaunchKernelGGL(k_geo_nodes, dim3(nblocks(L.NS)), dim3(TPB), 0, st, L, xn, yn, gbar, dx, dy);
 }
 
 void launch_forces(const Lay &L, const double *geo, const double *u, const Phys &ph, double *out,

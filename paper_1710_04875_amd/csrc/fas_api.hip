@@ -124,6 +124,7 @@ struct fas_state_s {
     double ale_omega = 0.0, ale_px = 0.0, ale_py = 0.0;
     std::vector<void *> allocs;
     // adjoint work arrays (padded fine level), allocated on first use
+    double *a_gbar = nullptr;   // metric-plane adjoint of the node sensitivities (lazy)
     double *a_lam = nullptr, *a_g = nullptr, *a_r = nullptr, *a_z = nullptr, *a_jt = nullptr,
            *a_lam0 = nullptr, *a_zeta = nullptr, *a_dFa = nullptr, *a_dFm = nullptr, *a_dcl = nullptr,
            *a_red = nullptr, *a_out = nullptr, *a_basis = nullptr;
@@ -168,6 +169,42 @@ extern "C" void fas_params_default(fas_params *p) {
     p->precond_fp32 = 0;
 }
 
+// upload the nodes of every level (every 2^l-th node of the fine grid) and
+// compute the metrics (coarse volumes agglomerated from the finer level);
+// every fine volume must be positive
+static fas_status grid_upload(fas_grid g, const double *x_nodes, const double *y_nodes) {
+    const int W = g->ni + 1;
+    for (int l = 0; l < g->nlev; ++l) {
+        const int s = 1 << l;
+        const Lay &L = g->lay[l];
+        const int nil = L.ni, njl = L.nj;
+        std::vector<double> hx((size_t)(nil + 1) * (njl + 1)), hy(hx.size());
+        for (int J = 0; J <= njl; ++J)
+            for (int I = 0; I <= nil; ++I) {
+                hx[(size_t)J * (nil + 1) + I] = x_nodes[(size_t)(J * s) * W + I * s];
+                hy[(size_t)J * (nil + 1) + I] = y_nodes[(size_t)(J * s) * W + I * s];
+            }
+        if (hipMemcpy(g->xn[l], hx.data(), hx.size() * sizeof(double), hipMemcpyHostToDevice) != hipSuccess ||
+            hipMemcpy(g->yn[l], hy.data(), hy.size() * sizeof(double), hipMemcpyHostToDevice) != hipSuccess ||
+            hipMemset(g->geo[l], 0, (size_t)G_NPLANES * L.NS * sizeof(double)) != hipSuccess)
+            return fail(FAS_EDEVICE, "grid upload failed");
+        if (l == 0) launch_geom_interior(L, g->xn[l], g->yn[l], g->geo[l], nullptr, nullptr, nullptr, 0);
+        else launch_geom_interior(L, g->xn[l], g->yn[l], g->geo[l], nullptr, &g->lay[l - 1], g->geo[l - 1], 0);
+        launch_geom_ghost(L, g->xn[l], g->yn[l], g->geo[l], 0);
+    }
+    if (hipDeviceSynchronize() != hipSuccess) return fail(FAS_EDEVICE, "geometry kernels failed");
+    const Lay &L = g->lay[0];
+    std::vector<double> vol(L.NS);
+    if (hipMemcpy(vol.data(), g->geo[0] + (size_t)G_VOL * L.NS, L.NS * sizeof(double), hipMemcpyDeviceToHost) !=
+        hipSuccess)
+        return fail(FAS_EDEVICE, "volume check failed");
+    for (int j = 0; j < L.nj; ++j)
+        for (int i = 0; i < L.ni; ++i)
+            if (!(vol[L.slot(i, j)] > 0.0))
+                return fail(FAS_EINVAL, "non-positive cell volume (grid must be right-handed)");
+    return FAS_OK;
+}
+
 extern "C" fas_status fas_grid_create(int32_t topology, int32_t ni, int32_t nj, int32_t n_wake,
                                       const double *x_nodes, const double *y_nodes,
                                       int32_t n_levels, fas_grid *out) {
@@ -199,21 +236,15 @@ extern "C" fas_status fas_grid_create(int32_t topology, int32_t ni, int32_t nj, 
         fas_grid_destroy(g);
         return s;
     };
-    const int W = ni + 1;
     for (int l = 0; l < n_levels; ++l) {
         int s = 1 << l;
         int nil = ni / s, njl = nj / s;
         Lay L = make_lay(nil, njl, g->nw / s, topology);
         g->lay.push_back(L);
-        std::vector<double> hx((size_t)(nil + 1) * (njl + 1)), hy(hx.size());
-        for (int J = 0; J <= njl; ++J)
-            for (int I = 0; I <= nil; ++I) {
-                hx[(size_t)J * (nil + 1) + I] = x_nodes[(size_t)(J * s) * W + I * s];
-                hy[(size_t)J * (nil + 1) + I] = y_nodes[(size_t)(J * s) * W + I * s];
-            }
+        const size_t nn = (size_t)(nil + 1) * (njl + 1);
         double *dx = nullptr, *dy = nullptr, *geo = nullptr;
-        if (hipMalloc(&dx, hx.size() * sizeof(double)) != hipSuccess ||
-            hipMalloc(&dy, hy.size() * sizeof(double)) != hipSuccess ||
+        if (hipMalloc(&dx, nn * sizeof(double)) != hipSuccess ||
+            hipMalloc(&dy, nn * sizeof(double)) != hipSuccess ||
             hipMalloc(&geo, (size_t)G_NPLANES * L.NS * sizeof(double)) != hipSuccess) {
             if (dx) g->xn.push_back(dx);
             if (dy) g->yn.push_back(dy);
@@ -223,29 +254,20 @@ extern "C" fas_status fas_grid_create(int32_t topology, int32_t ni, int32_t nj, 
         g->xn.push_back(dx);
         g->yn.push_back(dy);
         g->geo.push_back(geo);
-        if (hipMemcpy(dx, hx.data(), hx.size() * sizeof(double), hipMemcpyHostToDevice) != hipSuccess ||
-            hipMemcpy(dy, hy.data(), hy.size() * sizeof(double), hipMemcpyHostToDevice) != hipSuccess ||
-            hipMemset(geo, 0, (size_t)G_NPLANES * L.NS * sizeof(double)) != hipSuccess)
-            return cleanup(fail(FAS_EDEVICE, "grid upload failed"));
-        if (l == 0) launch_geom_interior(L, dx, dy, geo, nullptr, nullptr, nullptr, 0);
-        else launch_geom_interior(L, dx, dy, geo, nullptr, &g->lay[l - 1], g->geo[l - 1], 0);
-        launch_geom_ghost(L, dx, dy, geo, 0);
     }
-    if (hipDeviceSynchronize() != hipSuccess) return cleanup(fail(FAS_EDEVICE, "geometry kernels failed"));
-    // every volume must be positive (right-handed grid)
     {
-        const Lay &L = g->lay[0];
-        std::vector<double> vol(L.NS);
-        if (hipMemcpy(vol.data(), g->geo[0] + (size_t)G_VOL * L.NS, L.NS * sizeof(double),
-                      hipMemcpyDeviceToHost) != hipSuccess)
-            return cleanup(fail(FAS_EDEVICE, "volume check failed"));
-        for (int j = 0; j < nj; ++j)
-            for (int i = 0; i < ni; ++i)
-                if (!(vol[L.slot(i, j)] > 0.0))
-                    return cleanup(fail(FAS_EINVAL, "non-positive cell volume (grid must be right-handed)"));
+        fas_status st = grid_upload(g, x_nodes, y_nodes);
+        if (st != FAS_OK) return cleanup(st);
     }
     *out = g;
     return FAS_OK;
+}
+
+extern "C" fas_status fas_grid_set_nodes(fas_grid g, const double *x_nodes, const double *y_nodes) {
+    if (!g || !x_nodes || !y_nodes) return fail(FAS_EINVAL, "null argument");
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev != g->device) return fail(FAS_EINVAL, "grid on another device");
+    return grid_upload(g, x_nodes, y_nodes);
 }
 
 extern "C" void fas_grid_destroy(fas_grid g) {
@@ -953,6 +975,35 @@ extern "C" fas_status fas_vjp(fas_state s, const double *lam, double *out) {
     return FAS_OK;
 }
 
+// dx, dy = (dG/dX)^T ((dF/dG)^T lam (+ dC_L/dG)) at the prepared fine level
+static fas_status node_gradient(fas_state s, const double *lam, bool with_lift, double *dx, double *dy) {
+    const LevelDev &d = s->lv[0];
+    const size_t ng = (size_t)(G_YC + 1) * d.L.NS;
+    if (!s->a_gbar) {
+        HIPCHK(hipMalloc(&s->a_gbar, ng * sizeof(double)));
+        s->allocs.push_back(s->a_gbar);
+    }
+    const size_t nn = (size_t)(d.L.ni + 1) * (d.L.nj + 1);
+    launch_zero(s->a_gbar, ng, s->e.st);
+    launch_vjp_geo(d.L, d.geo, d.u, d.mut, s->ph, lam, s->a_gbar, s->e.st);
+    if (with_lift) launch_forces_geo(d.L, d.geo, d.u, s->ph, s->a_gbar, s->e.st);
+    launch_zero(dx, nn, s->e.st);
+    launch_zero(dy, nn, s->e.st);
+    launch_geo_nodes(d.L, s->g->xn[0], s->g->yn[0], s->a_gbar, dx, dy, s->e.st);
+    HIPCHK(hipGetLastError());
+    return FAS_OK;
+}
+
+extern "C" fas_status fas_vjp_nodes(fas_state s, const double *lam, double *dx, double *dy) {
+    if (!s || !lam || !dx || !dy) return fail(FAS_EINVAL, "null argument");
+    if (s->ale) return fail(FAS_EINVAL, "the adjoint is for fixed meshes");
+    STCHK(ensure_adjoint(s));
+    const LevelDev &d = s->lv[0];
+    prep(s->e, 0, fine_rans(s->e, 0));
+    launch_unpack(d.L, lam, s->a_jt, 4, s->e.st);
+    return node_gradient(s, s->a_jt, false, dx, dy);
+}
+
 extern "C" fas_status fas_param_partials(fas_state s, double *dF_dalpha, double *dF_dmach, double *dcl_dparam) {
     if (!s) return fail(FAS_EINVAL, "null state");
     if (s->ale) return fail(FAS_EINVAL, "the adjoint is for fixed meshes");
@@ -1030,6 +1081,18 @@ extern "C" fas_status fas_lift_gradient(fas_state s, int32_t max_iter, double dr
     if (cl) *cl = h[0];
     grad[0] = h[2] + la;
     grad[1] = h[3] + lm;
+    return st;
+}
+
+extern "C" fas_status fas_lift_gradient_nodes(fas_state s, int32_t max_iter, double drop_orders, double *cl,
+                                              double *grad, double *dcl_dx, double *dcl_dy, double *res_hist,
+                                              int32_t *n_iter) {
+    if (!s || !grad || !dcl_dx || !dcl_dy || max_iter < 0) return fail(FAS_EINVAL, "bad argument");
+    const fas_status st = fas_lift_gradient(s, max_iter, drop_orders, cl, grad, res_hist, n_iter);
+    if (st != FAS_OK && st != FAS_NOT_CONVERGED) return st;
+    prep(s->e, 0, fine_rans(s->e, 0));
+    STCHK(node_gradient(s, s->a_lam, true, dcl_dx, dcl_dy));
+    HIPCHK(hipStreamSynchronize(s->e.st));
     return st;
 }
 

@@ -230,6 +230,15 @@ void launch_vjp(const Lay &L, const double *geo, const double *u, const double *
                 const double *lam, double *out, hipStream_t st);      // out += (dF/du)^T lam
 void launch_param_partials(const Lay &L, const double *geo, const double *u, const double *mut,
                            const Phys &ph, double reynolds, double *dFa, double *dFm, hipStream_t st);
+// grid-node sensitivities: gbar (metric planes G_SXI_X .. G_YC, zeroed)
+// += (dF/dG)^T lam; gbar += dC_L/dG of the wall faces; dx, dy (zeroed node
+// arrays) += (dG/dX)^T gbar
+void launch_vjp_geo(const Lay &L, const double *geo, const double *u, const double *mut, const Phys &ph,
+                    const double *lam, double *gbar, hipStream_t st);
+void launch_forces_geo(const Lay &L, const double *geo, const double *u, const Phys &ph, double *gbar,
+                       hipStream_t st);
+void launch_geo_nodes(const Lay &L, const double *xn, const double *yn, const double *gbar, double *dx,
+                      double *dy, hipStream_t st);
 void launch_forces(const Lay &L, const double *geo, const double *u, const Phys &ph, double *out,
                    double *dcl, hipStream_t st);                       // out[6], dcl padded (zeroed)
 void launch_sgs_transpose(const Lay &L, const void *blk, const double *r, void *zeta, double *x, int fp32,

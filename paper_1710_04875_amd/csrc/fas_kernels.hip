@@ -4,6 +4,7 @@
 // approximation scheme for the RANS equations".  Each kernel names the
 // section / equation it implements.  Layout: fas_internal.h.
 #include "fas_internal.h"
+#include "fas_geom.h"
 
 #include <cmath>
 
@@ -130,41 +131,34 @@ __global__ void k_geom_interior(Lay L, const double *xn, const double *yn, doubl
     auto X = [&](int I, int J) { return xn[J * W + I]; };
     auto Y = [&](int I, int J) { return yn[J * W + I]; };
     if (i >= 0 && i <= L.ni && j >= 0 && j < L.nj) {
-        double dx = X(i, j + 1) - X(i, j);
-        double dy = Y(i, j + 1) - Y(i, j);
-        geo[G_SXI_X * NS + s] = dy;
-        geo[G_SXI_Y * NS + s] = -dx;
+        double sx, sy;
+        g_iface<double>(X, Y, i, j, sx, sy);
+        geo[G_SXI_X * NS + s] = sx;
+        geo[G_SXI_Y * NS + s] = sy;
     }
     if (i >= 0 && i < L.ni && j >= 0 && j <= L.nj) {
-        double dx = X(i + 1, j) - X(i, j);
-        double dy = Y(i + 1, j) - Y(i, j);
-        geo[G_SETA_X * NS + s] = -dy;
-        geo[G_SETA_Y * NS + s] = dx;
+        double sx, sy;
+        g_jface<double>(X, Y, i, j, sx, sy);
+        geo[G_SETA_X * NS + s] = sx;
+        geo[G_SETA_Y * NS + s] = sy;
     }
     if (!interior(L, i, j)) return;
-    double vol;
-    if (volf == nullptr) {
-        double d1x = X(i + 1, j + 1) - X(i, j), d1y = Y(i + 1, j + 1) - Y(i, j);
-        double d2x = X(i, j + 1) - X(i + 1, j), d2y = Y(i, j + 1) - Y(i + 1, j);
-        vol = 0.5 * (d1x * d2y - d1y * d2x);
-    } else {
+    double vol, xc, yc, sb[4];
+    g_cell(X, Y, i, j, vol, xc, yc, sb);
+    if (volf != nullptr) {
         double v00 = volf[Lf.slot(2 * i, 2 * j)], v10 = volf[Lf.slot(2 * i + 1, 2 * j)];
         double v01 = volf[Lf.slot(2 * i, 2 * j + 1)], v11 = volf[Lf.slot(2 * i + 1, 2 * j + 1)];
         vol = ((v00 + v10) + v01) + v11;
     }
     geo[G_VOL * NS + s] = vol;
-    geo[G_XC * NS + s] = 0.25 * (((X(i, j) + X(i + 1, j)) + X(i + 1, j + 1)) + X(i, j + 1));
-    geo[G_YC * NS + s] = 0.25 * (((Y(i, j) + Y(i + 1, j)) + Y(i + 1, j + 1)) + Y(i, j + 1));
-    double wx = Y(i, j + 1) - Y(i, j), wy = -(X(i, j + 1) - X(i, j));
-    double ex = Y(i + 1, j + 1) - Y(i + 1, j), ey = -(X(i + 1, j + 1) - X(i + 1, j));
-    double sx = -(Y(i + 1, j) - Y(i, j)), sy = X(i + 1, j) - X(i, j);
-    double nx = -(Y(i + 1, j + 1) - Y(i, j + 1)), ny = X(i + 1, j + 1) - X(i, j + 1);
-    geo[G_SB0 * NS + s] = 0.5 * (wx + ex);
-    geo[G_SB1 * NS + s] = 0.5 * (wy + ey);
-    geo[G_SB2 * NS + s] = 0.5 * (sx + nx);
-    geo[G_SB3 * NS + s] = 0.5 * (sy + ny);
+    geo[G_XC * NS + s] = xc;
+    geo[G_YC * NS + s] = yc;
+    geo[G_SB0 * NS + s] = sb[0];
+    geo[G_SB1 * NS + s] = sb[1];
+    geo[G_SB2 * NS + s] = sb[2];
+    geo[G_SB3 * NS + s] = sb[3];
     double mx = 0.5 * (X(i, 0) + X(i + 1, 0)), my = 0.5 * (Y(i, 0) + Y(i + 1, 0));
-    double cx = geo[G_XC * NS + s] - mx, cy = geo[G_YC * NS + s] - my;
+    double cx = xc - mx, cy = yc - my;
     geo[G_WD * NS + s] = sqrt(cx * cx + cy * cy);
 }
 
@@ -216,77 +210,19 @@ __global__ void k_rotate_geometry(Lay L, const double *geo0, const double *xn, c
     geo[G_WJY * NS + t] = wjy;
 }
 
-__device__ inline void reflect(double &cx, double &cy, double mx, double my, double sx, double sy) {
-    double ln = sqrt(sx * sx + sy * sy);
-    double nx = sx / ln, ny = sy / ln;
-    double dist = (cx - mx) * nx + (cy - my) * ny;
-    cx = cx - 2.0 * dist * nx;
-    cy = cy - 2.0 * dist * ny;
-}
-
-// centre of the cell (i, j) for interior i and j in [-2, nj+2), plus the
-// slot of the interior cell whose metrics it copies
-__device__ void jrow_geom(const Lay &L, const double *xn, const double *yn, const double *geo,
-                          int i, int j, double &cx, double &cy, int &msrc) {
-    const int NS = L.NS, W = L.ni + 1;
-    if (j >= 0 && j < L.nj) {
-        int s = L.slot(i, j);
-        cx = geo[G_XC * NS + s];
-        cy = geo[G_YC * NS + s];
-        msrc = s;
-        return;
-    }
-    if (j < 0) {
-        int k = -1 - j;
-        if (cut_col(L, i)) {
-            int s = L.slot(L.ni - 1 - i, k);
-            cx = geo[G_XC * NS + s];
-            cy = geo[G_YC * NS + s];
-            msrc = s;
-            return;
-        }
-        int s = L.slot(i, k);
-        cx = geo[G_XC * NS + s];
-        cy = geo[G_YC * NS + s];
-        msrc = s;
-        double mx = 0.5 * (xn[i] + xn[i + 1]), my = 0.5 * (yn[i] + yn[i + 1]);
-        int f = L.slot(i, 0);
-        reflect(cx, cy, mx, my, geo[G_SETA_X * NS + f], geo[G_SETA_Y * NS + f]);
-        return;
-    }
-    int k = j - L.nj;
-    int s = L.slot(i, L.nj - 1 - k);
-    cx = geo[G_XC * NS + s];
-    cy = geo[G_YC * NS + s];
-    msrc = s;
-    double mx = 0.5 * (xn[L.nj * W + i] + xn[L.nj * W + i + 1]);
-    double my = 0.5 * (yn[L.nj * W + i] + yn[L.nj * W + i + 1]);
-    int f = L.slot(i, L.nj);
-    reflect(cx, cy, mx, my, geo[G_SETA_X * NS + f], geo[G_SETA_Y * NS + f]);
-}
-
+// ghost cells: centre reflected across the boundary face (the partner's
+// across the wake cut), volume and mean face vectors of the mirrored cell
 __global__ void k_geom_ghost(Lay L, const double *xn, const double *yn, double *geo) {
     int s = blockIdx.x * blockDim.x + threadIdx.x;
     int i, j;
     if (!decode(L, s, i, j) || interior(L, i, j)) return;
     const int NS = L.NS, W = L.ni + 1;
+    auto X = [&](int I, int J) { return xn[J * W + I]; };
+    auto Y = [&](int I, int J) { return yn[J * W + I]; };
     double cx, cy;
-    int msrc;
-    if (i >= 0 && i < L.ni) {
-        jrow_geom(L, xn, yn, geo, i, j, cx, cy, msrc);
-    } else {
-        int jc = min(max(j, 0), L.nj - 1);
-        int isrc, I;
-        double sgn;
-        if (i < 0) { isrc = -1 - i; I = 0; sgn = 1.0; }
-        else { isrc = L.ni - 1 - (i - L.ni); I = L.ni; sgn = 1.0; }
-        (void)sgn;
-        jrow_geom(L, xn, yn, geo, isrc, j, cx, cy, msrc);
-        double mx = 0.5 * (xn[jc * W + I] + xn[(jc + 1) * W + I]);
-        double my = 0.5 * (yn[jc * W + I] + yn[(jc + 1) * W + I]);
-        int f = L.slot(I, jc);
-        reflect(cx, cy, mx, my, geo[G_SXI_X * NS + f], geo[G_SXI_Y * NS + f]);
-    }
+    int si, sj;
+    g_centre<double>(L, X, Y, i, j, cx, cy, si, sj);
+    const int msrc = L.slot(si, sj);
     geo[G_XC * NS + s] = cx;
     geo[G_YC * NS + s] = cy;
     geo[G_SB0 * NS + s] = geo[G_SB0 * NS + msrc];

@@ -74,14 +74,15 @@ class Params:
 
 
 EXPORTS = [
-    "fas_params_default", "fas_grid_create", "fas_grid_destroy", "fas_state_create",
+    "fas_params_default", "fas_grid_create", "fas_grid_destroy", "fas_grid_set_nodes", "fas_state_create",
     "fas_state_destroy", "fas_state_set_params", "fas_set_state", "fas_get_state",
     "fas_get_level", "fas_handoff_pending", "fas_residual", "fas_smooth", "fas_sgs_apply", "fas_cycle",
     "fas_dual_time_step", "fas_profile", "fas_profile_read", "fas_batch_create",
     "fas_batch_destroy", "fas_batch_solve", "fas_batch_sweep_config", "fas_batch_set_sweep_config",
     "fas_sweep_config_count", "fas_sweep_config_info", "fas_batch_profile",
     "fas_batch_profile_read", "fas_forces", "fas_vjp", "fas_param_partials",
-    "fas_sgs_apply_transpose", "fas_adjoint_solve", "fas_lift_gradient", "fas_set_motion",
+    "fas_sgs_apply_transpose", "fas_adjoint_solve", "fas_lift_gradient", "fas_vjp_nodes",
+    "fas_lift_gradient_nodes", "fas_set_motion",
     "fas_last_error",
 ]
 PROF_CLASSES = ("sweep", "residual", "blocks")
@@ -100,6 +101,7 @@ def load(path: str = LIB_PATH):
     sig = {
         "fas_params_default": (None, [ctypes.POINTER(_Params)]),
         "fas_grid_create": (i32, [i32, i32, i32, i32, dp, dp, i32, ctypes.POINTER(vp)]),
+        "fas_grid_set_nodes": (i32, [vp, dp, dp]),
         "fas_grid_destroy": (None, [vp]),
         "fas_state_create": (i32, [vp, ctypes.POINTER(_Params), vp, vp, ctypes.POINTER(vp)]),
         "fas_state_destroy": (None, [vp]),
@@ -130,6 +132,8 @@ def load(path: str = LIB_PATH):
         "fas_sgs_apply_transpose": (i32, [vp, vp, vp]),
         "fas_adjoint_solve": (i32, [vp, vp, vp, i32, f64, dp, ip]),
         "fas_lift_gradient": (i32, [vp, i32, f64, dp, dp, dp, ip]),
+        "fas_vjp_nodes": (i32, [vp, vp, vp, vp]),
+        "fas_lift_gradient_nodes": (i32, [vp, i32, f64, dp, dp, vp, vp, dp, ip]),
         "fas_set_motion": (i32, [vp, f64, f64, f64, f64]),
         "fas_last_error": (ctypes.c_char_p, []),
     }
@@ -173,6 +177,18 @@ class Grid:
                                    y.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
                                    n_levels, ctypes.byref(h)))
         self.h = h
+        self.x, self.y = x.copy(), y.copy()
+
+    def set_nodes(self, x, y):
+        """Move the nodes (same shape): every level's metrics are recomputed;
+        states on this grid use them from their next call."""
+        x = np.ascontiguousarray(x, dtype=np.float64)
+        y = np.ascontiguousarray(y, dtype=np.float64)
+        if x.shape != (self.nj + 1, self.ni + 1) or y.shape != x.shape:
+            raise ValueError("node arrays must be (nj + 1, ni + 1)")
+        _check(_lib.fas_grid_set_nodes(self.h, x.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                       y.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
+        self.x, self.y = x.copy(), y.copy()
 
     def __del__(self):
         if getattr(self, "h", None) and _lib is not None:
@@ -331,6 +347,33 @@ class State:
                                            ctypes.byref(n)), allow=(FAS_NOT_CONVERGED,))
         return cl.value, g, hist[:n.value + 1], st
 
+    def vjp_nodes(self, lam):
+        """((dF/dx)^T lam, (dF/dy)^T lam) on the node arrays (nj + 1, ni + 1)
+        at the current state (frozen eddy viscosity)."""
+        import torch
+        lam = lam.to(torch.float64).contiguous()
+        dx = torch.empty((self.grid.nj + 1, self.grid.ni + 1), dtype=torch.float64, device=self.device)
+        dy = torch.empty_like(dx)
+        _check(_lib.fas_vjp_nodes(self.h, _dptr(lam), _dptr(dx), _dptr(dy)))
+        return dx, dy
+
+    def lift_gradient_nodes(self, max_iter=2000, drop_orders=10.0):
+        """(C_L, [dC_L/dalpha_deg, dC_L/dM], dC_L/dx, dC_L/dy (node arrays),
+        adjoint history, status) at a converged state."""
+        import torch
+        cl = ctypes.c_double(0.0)
+        g = np.zeros(2)
+        dx = torch.empty((self.grid.nj + 1, self.grid.ni + 1), dtype=torch.float64, device=self.device)
+        dy = torch.empty_like(dx)
+        hist = np.zeros(max_iter + 1)
+        n = ctypes.c_int32(0)
+        st = _check(_lib.fas_lift_gradient_nodes(self.h, max_iter, drop_orders, ctypes.byref(cl),
+                                                 g.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                                 _dptr(dx), _dptr(dy),
+                                                 hist.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                                 ctypes.byref(n)), allow=(FAS_NOT_CONVERGED,))
+        return cl.value, g, dx, dy, hist[:n.value + 1], st
+
     def dual_time_step(self, dt, alpha_deg, max_inner, drop_orders):
         hist = np.zeros(max_inner + 1)
         n = ctypes.c_int32(0)
@@ -418,30 +461,54 @@ def _steady_lift_fn():
     import torch
 
     class SteadyLift(torch.autograd.Function):
-        """C_L(M, alpha_deg) of the converged steady solution on a State:
-        the forward pass sets the flow parameters and runs FAS cycles to the
-        drop, the backward pass solves the adjoint for dC_L/d(M, alpha)."""
+        """C_L(M, alpha_deg[, x_nodes, y_nodes]) of the converged steady
+        solution on a State: the forward pass sets the flow parameters (and
+        moves the grid's nodes if given) and runs FAS cycles to the drop,
+        the backward pass solves the adjoint for dC_L/d(M, alpha) and, if
+        the nodes are inputs, dC_L/d(x, y) of every node."""
 
         @staticmethod
-        def forward(ctx, mach, alpha_deg, state, max_cycles, drop_orders, adj_iter, adj_drop):
+        def forward(ctx, mach, alpha_deg, x_nodes, y_nodes, state, max_cycles, drop_orders, adj_iter, adj_drop):
             p = state.params
             p.mach = float(mach)
             p.alpha_deg = float(alpha_deg)
             state.set_params(p)
+            ctx.nodes = x_nodes is not None or y_nodes is not None
+            if ctx.nodes:
+                g = state.grid
+                x = x_nodes.detach().cpu().numpy() if x_nodes is not None else g.x
+                y = y_nodes.detach().cpu().numpy() if y_nodes is not None else g.y
+                g.set_nodes(x, y)
             state.cycle(max_cycles, drop_orders)
             cl, _ = state.forces()
             ctx.state = state
             ctx.adj = (adj_iter, adj_drop)
+            ctx.node_meta = [(t.device, t.dtype) if t is not None else None for t in (x_nodes, y_nodes)]
             return torch.tensor(cl, dtype=torch.float64)
 
         @staticmethod
         def backward(ctx, g):
-            _, grad, _, _ = ctx.state.lift_gradient(*ctx.adj)
-            return (g * grad[1], g * grad[0], None, None, None, None, None)
+            gx = gy = None
+            if ctx.nodes:
+                _, grad, dx, dy, _, _ = ctx.state.lift_gradient_nodes(*ctx.adj)
+                mx, my = ctx.node_meta
+                if mx is not None:
+                    gx = g.to(dx.device) * dx
+                    gx = gx.to(device=mx[0], dtype=mx[1])
+                if my is not None:
+                    gy = g.to(dy.device) * dy
+                    gy = gy.to(device=my[0], dtype=my[1])
+            else:
+                _, grad, _, _ = ctx.state.lift_gradient(*ctx.adj)
+            return (g * grad[1], g * grad[0], gx, gy, None, None, None, None, None)
 
     return SteadyLift
 
 
-def steady_lift(mach, alpha_deg, state, max_cycles=400, drop_orders=10.0, adj_iter=2000, adj_drop=10.0):
-    """Differentiable C_L(M, alpha) (torch scalars) of a converged State."""
-    return _steady_lift_fn().apply(mach, alpha_deg, state, max_cycles, drop_orders, adj_iter, adj_drop)
+def steady_lift(mach, alpha_deg, state, max_cycles=400, drop_orders=10.0, adj_iter=2000, adj_drop=10.0,
+                x_nodes=None, y_nodes=None):
+    """Differentiable C_L(M, alpha) (torch scalars) of a converged State; with
+    x_nodes / y_nodes ((nj + 1, ni + 1) tensors) also differentiable in the
+    grid-node coordinates (the forward pass moves the State's grid there)."""
+    return _steady_lift_fn().apply(mach, alpha_deg, x_nodes, y_nodes, state, max_cycles, drop_orders, adj_iter,
+                                   adj_drop)

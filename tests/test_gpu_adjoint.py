@@ -233,3 +233,135 @@ def test_converged_solution_does_not_depend_on_the_smoother(variant):
 
 def state_err_local(a, b):
     return float((np.abs(a - b).max(axis=0) / np.abs(b).max(axis=0)).max())
+
+
+# ------------------------------------------------------- grid-node gradients
+def _spacing(x, y):
+    """Smallest edge length at every node (scales test displacements)."""
+    sp = np.full(x.shape, np.inf)
+    di = np.hypot(np.diff(x, axis=1), np.diff(y, axis=1))
+    dj = np.hypot(np.diff(x, axis=0), np.diff(y, axis=0))
+    sp[:, :-1] = np.minimum(sp[:, :-1], di)
+    sp[:, 1:] = np.minimum(sp[:, 1:], di)
+    sp[:-1, :] = np.minimum(sp[:-1, :], dj)
+    sp[1:, :] = np.minimum(sp[1:, :], dj)
+    return sp
+
+
+@pytest.mark.parametrize("kind", KINDS)
+def test_node_vjp_matches_oracle_per_node(kind):
+    """(dF/dx)^T lam and (dF/dy)^T lam on every node against the oracle's
+    complex step through its metrics (slip walls, far field, wake cut,
+    viscous centres)."""
+    c = _case(kind)
+    g, st, S = _pair(c)
+    mutp = oadj.frozen_mut(S, c["u"])
+    lam = np.random.default_rng(8).standard_normal(c["u"].shape)
+    dx, dy = st.vjp_nodes(torch.from_numpy(lam).cuda())
+    ox, oy = oadj.residual_node_vjp(S, c["u"], mutp, lam)
+    scale = max(np.abs(ox).max(), np.abs(oy).max())
+    assert np.abs(_np(dx) - ox).max() <= 1e-10 * scale
+    assert np.abs(_np(dy) - oy).max() <= 1e-10 * scale
+
+
+@pytest.mark.parametrize("kind", KINDS)
+def test_node_vjp_is_translation_invariant(kind):
+    """F depends on node differences only: the node gradient sums to zero
+    in each coordinate."""
+    c = _case(kind)
+    g, st, S = _pair(c)
+    lam = np.random.default_rng(9).standard_normal(c["u"].shape)
+    dx, dy = (_np(t) for t in st.vjp_nodes(torch.from_numpy(lam).cuda()))
+    assert abs(dx.sum()) <= 1e-12 * np.abs(dx).sum()
+    assert abs(dy.sum()) <= 1e-12 * np.abs(dy).sum()
+
+
+@pytest.mark.parametrize("model", [0, 1])
+def test_lift_node_gradient_matches_oracle_dense_adjoint(model):
+    alpha, mach = 1.5, 0.5
+    g, st = _converged_state(alpha, mach, model)
+    cl, grad, dx, dy, hist, status = st.lift_gradient_nodes(3000, 11.0)
+    assert status == 0
+    S, u = _oracle_at(st, model, alpha, mach)
+    _, lam = oadj.lift_gradient(S, u)
+    x, y = S.levels[0].x, S.levels[0].y
+    sp = _spacing(x, y)
+    rng = np.random.default_rng(10)
+    gx, gy = _np(dx), _np(dy)
+    for _ in range(3):
+        vx, vy = rng.standard_normal(x.shape) * sp, rng.standard_normal(x.shape) * sp
+        ref = oadj.lift_node_derivative(S, u, vx, vy, lam=lam)
+        got = float(np.sum(gx * vx) + np.sum(gy * vy))
+        terms = float(np.sum(np.abs(gx * vx)) + np.sum(np.abs(gy * vy)))
+        assert abs(got - ref) <= 1e-8 * terms, (got, ref, terms)
+
+
+def test_lift_node_gradient_matches_central_differences():
+    """dC_L/dX along a displacement of the airfoil surface (a smooth bump of
+    the upper surface, the field nodes following with decaying amplitude)
+    against central differences of converged solutions on moved grids."""
+    from paper_1710_04875_amd import fas
+    alpha, mach = 1.5, 0.5
+    g, st = _converged_state(alpha, mach)
+    cl0, grad, dx, dy, hist, status = st.lift_gradient_nodes(3000, 11.0)
+    assert status == 0
+    x0, y0 = g.x.copy(), g.y.copy()
+    ni, nj, nw = GRID_FD
+    # bump on the airfoil nodes i in [nw, ni - nw], decaying with the
+    # distance from the column's wall node (the thin wall cells, 1e-6 chord,
+    # move almost rigidly and stay valid)
+    I = np.arange(ni + 1)
+    s = np.clip((I - nw) / (ni - 2 * nw), 0.0, 1.0)
+    bump = np.sin(np.pi * s) ** 2 * ((I >= nw) & (I <= ni - nw))
+    dist = np.hypot(x0 - x0[0:1, :], y0 - y0[0:1, :])
+    vy = 1e-2 * np.exp(-dist / 0.3) * bump[None, :]
+    vx = np.zeros_like(vy)
+    pred = float(np.sum(_np(dx) * vx) + np.sum(_np(dy) * vy))
+
+    def cl_at(h):
+        g.set_nodes(x0 + h * vx, y0 + h * vy)
+        _, s2 = _converged_state_on(g, alpha, mach)
+        return s2.forces()[0]
+
+    h = 1e-3
+    fd = (cl_at(h) - cl_at(-h)) / (2 * h)
+    g.set_nodes(x0, y0)
+    assert abs(pred - fd) <= 1e-5 * abs(fd), (pred, fd)
+
+
+def _converged_state_on(g, alpha, mach, model=0):
+    from paper_1710_04875_amd import fas
+    ni, nj, nw = GRID_FD
+    par = fas.Params(model=model, mach=mach, alpha_deg=alpha, n_levels=3, cycle_gamma=1, nu1=1,
+                     cfl=20.0, cfl_ramp=5.0, n_ramp=1, ramp_growth=1.5)
+    st = fas.State(g, par, torch.from_numpy(fi.uniform_state(ni, nj, mach, alpha)).cuda())
+    h, status = st.cycle(4000, 12.0)
+    assert status == 0, (len(h), h[-1] / h[0])
+    return g, st
+
+
+def test_steady_lift_autograd_in_the_nodes():
+    """The autograd path returns the adjoint node gradient.  Entries of
+    nodes next to the 1e-6-chord wall cells are sums of large cancelling
+    terms (they amplify the 11-order adjoint tolerance), so the comparison
+    is along a smooth displacement, against the gradient at the same state."""
+    from paper_1710_04875_amd import fas
+    alpha, mach = 1.5, 0.5
+    g, st = _converged_state(alpha, mach)
+    yn = torch.tensor(g.y, dtype=torch.float64, requires_grad=True)
+    m = torch.tensor(mach, dtype=torch.float64, requires_grad=True)
+    cl = fas.steady_lift(m, torch.tensor(alpha, dtype=torch.float64), st, max_cycles=50, drop_orders=11.0,
+                         adj_iter=3000, adj_drop=11.0, y_nodes=yn)
+    cl.backward()
+    _, grad, dx, dy, _, status = st.lift_gradient_nodes(3000, 11.0)
+    assert status == 0
+    ni, nj, nw = GRID_FD
+    dist = np.hypot(g.x - g.x[0:1, :], g.y - g.y[0:1, :])
+    I = np.arange(ni + 1)
+    bump = np.sin(np.pi * np.clip((I - nw) / (ni - 2 * nw), 0.0, 1.0)) ** 2
+    v = np.exp(-dist / 0.3) * bump[None, :]
+    got = float(np.sum(yn.grad.numpy() * v))
+    ref = float(np.sum(_np(dy) * v))
+    assert np.isfinite(yn.grad.numpy()).all()
+    assert abs(got - ref) <= 1e-8 * abs(ref)
+    assert abs(m.grad.item() - grad[1]) <= 1e-8 * abs(grad[1])
