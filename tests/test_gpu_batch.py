@@ -193,3 +193,16 @@ def test_batch_rejects_mixed_structures():
         fas.Batch([pairs[0][1], other])
     with pytest.raises(fas.FasError):
         fas.Batch([pairs[0][1], pairs[0][1]])
+
+
+def test_convergence_studies_run_on_small_grids():
+    """The study tool (mesh independence, flow angle, second BDF2 step) on
+    small grids: the benchmark mode converges on every grid and angle."""
+    from paper_1710_04875_amd import studies
+    mi = studies.mesh_independence(cycles=30, drop=9.0, meshes=[(64, 32), (96, 48)])
+    for m in ("64x32", "96x48"):
+        assert 0.0 < mi["bench_cstar_100"][m]["rate"] < 1.0
+    fa = studies.flow_angle(cycles=20, mesh=(64, 32))
+    for a in ("0.0", "1.0", "2.0", "4.0"):
+        assert 0.0 < fa["steady_bench_d_0.5"][a]["rate"] < 1.0
+        assert np.isfinite(fa["unsteady_second_step_bench"][a]["rate"])
