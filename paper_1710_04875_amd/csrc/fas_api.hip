@@ -563,8 +563,7 @@ double tau_of(const Engine &e) {
 void prep(Engine &e, int l, bool with_bl) {
     const BLev &B = e.lev[l];
     const int rans = e.model == FAS_RANS_BL;
-    launch_ghost_state(B, rans, e.st);
-    launch_cell_quantities(B, rans, e.st);
+    launch_ghost_cq(B, rans, rans, e.st);
     if (rans) launch_vertex_gradients(B, e.st);
     if (fine_rans(e, l) && with_bl) {
         launch_baldwin_lomax(B, e.st);

@@ -170,8 +170,7 @@ void launch_rotate_geometry(const Lay &L, const double *geo_ref, const double *x
                             hipStream_t st);
 
 // residual chain
-void launch_ghost_state(const BLev &B, int noslip, hipStream_t st);
-void launch_cell_quantities(const BLev &B, int rans, hipStream_t st);
+void launch_ghost_cq(const BLev &B, int noslip, int rans, hipStream_t st);   // both in one pass
 void launch_vertex_gradients(const BLev &B, hipStream_t st);
 void launch_baldwin_lomax(const BLev &B, hipStream_t st);
 void launch_mut_ghosts(const BLev &B, hipStream_t st);

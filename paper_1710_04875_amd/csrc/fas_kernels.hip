@@ -365,38 +365,29 @@ __device__ void jrow_state(const Lay &L, const double *geo, const double *u, con
     else farfield(ui, ph.uinf, nx, ny, out);
 }
 
-__global__ void k_ghost_state(BK b, int noslip) {
-    LevelDev d;
-    if (!take(b, blockIdx.y, d)) return;
-    const Lay L = d.L;
-    const double *geo = d.geo;
-    double *u = d.u;
-    const Phys ph = b.PH[blockIdx.y];
-    int s = blockIdx.x * blockDim.x + threadIdx.x;
-    int i, j;
-    if (!decode(L, s, i, j) || interior(L, i, j)) return;
+// state of ghost cell (i, j) from the interior states (ghost states never
+// read other ghosts, so all of them can be filled at once)
+__device__ inline void ghost_state(const Lay &L, const double *geo, const double *u, const Phys &ph, int noslip,
+                                   int i, int j, double out[4]) {
     const int NS = L.NS;
-    double out[4];
     if (i >= 0 && i < L.ni) {
         jrow_state(L, geo, u, ph, noslip, i, j, out);
-    } else {
-        int jc = min(max(j, 0), L.nj - 1);
-        double src[4], nx, ny;
-        int f;
-        if (i < 0) {
-            jrow_state(L, geo, u, ph, noslip, -1 - i, j, src);
-            f = L.slot(0, jc);
-            unit(-geo[G_SXI_X * NS + f], -geo[G_SXI_Y * NS + f], nx, ny);
-        } else {
-            jrow_state(L, geo, u, ph, noslip, L.ni - 1 - (i - L.ni), j, src);
-            f = L.slot(L.ni, jc);
-            unit(geo[G_SXI_X * NS + f], geo[G_SXI_Y * NS + f], nx, ny);
-        }
-        if (ph.ale) farfield_moving(src, ph.uinf, nx, ny, geo[G_WIX * NS + f], geo[G_WIY * NS + f], out);
-        else farfield(src, ph.uinf, nx, ny, out);
+        return;
     }
-#pragma unroll
-    for (int k = 0; k < 4; ++k) u[k * NS + s] = out[k];
+    int jc = min(max(j, 0), L.nj - 1);
+    double src[4], nx, ny;
+    int f;
+    if (i < 0) {
+        jrow_state(L, geo, u, ph, noslip, -1 - i, j, src);
+        f = L.slot(0, jc);
+        unit(-geo[G_SXI_X * NS + f], -geo[G_SXI_Y * NS + f], nx, ny);
+    } else {
+        jrow_state(L, geo, u, ph, noslip, L.ni - 1 - (i - L.ni), j, src);
+        f = L.slot(L.ni, jc);
+        unit(geo[G_SXI_X * NS + f], geo[G_SXI_Y * NS + f], nx, ny);
+    }
+    if (ph.ale) farfield_moving(src, ph.uinf, nx, ny, geo[G_WIX * NS + f], geo[G_WIY * NS + f], out);
+    else farfield(src, ph.uinf, nx, ny, out);
 }
 
 // eddy viscosity ghosts: zero at walls, copy at far field, partner at the cut
@@ -443,18 +434,9 @@ __device__ inline void rel_normal(const Phys &ph, const double *geo, int NS, int
     }
 }
 
-__global__ void k_cell_quantities(BK b, int rans) {
-    LevelDev d;
-    if (!take(b, blockIdx.y, d)) return;
-    const Lay L = d.L;
-    const double *geo = d.geo, *u = d.u;
-    double *cq = d.cq;
-    const Phys ph = b.PH[blockIdx.y];
-    int s = blockIdx.x * blockDim.x + threadIdx.x;
-    int i, j;
-    if (!decode(L, s, i, j)) return;
-    const int NS = L.NS;
-    double r = u[s], mx = u[NS + s], my = u[2 * NS + s], E = u[3 * NS + s];
+__device__ inline void cell_quantities(const Phys &ph, const double *geo, int NS, int s, int rans, const double U[4],
+                                       double *cq) {
+    double r = U[0], mx = U[1], my = U[2], E = U[3];
     double vx = mx / r, vy = my / r;
     double p = pres(r, mx, my, E);
     double a = sqrt(GAM * p / r);
@@ -474,6 +456,29 @@ __global__ void k_cell_quantities(BK b, int rans) {
     cq[Q_RXI * NS + s] = rtxi;
     cq[Q_RETA * NS + s] = rteta;
     cq[Q_T * NS + s] = p / r;
+}
+
+// ghost states and cell quantities in one pass: a ghost cell's quantities
+// need only its own (just computed) state
+__global__ void k_ghost_cq(BK b, int noslip, int rans) {
+    LevelDev d;
+    if (!take(b, blockIdx.y, d)) return;
+    const Lay L = d.L;
+    const Phys ph = b.PH[blockIdx.y];
+    int s = blockIdx.x * blockDim.x + threadIdx.x;
+    int i, j;
+    if (!decode(L, s, i, j)) return;
+    const int NS = L.NS;
+    double U[4];
+    if (interior(L, i, j)) {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) U[k] = d.u[k * NS + s];
+    } else {
+        ghost_state(L, d.geo, d.u, ph, noslip, i, j, U);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) d.u[k * NS + s] = U[k];
+    }
+    cell_quantities(ph, d.geo, NS, s, rans, U, d.cq);
 }
 
 // c* of the current cycle: the start-up value for n_ramp cycles, then
@@ -1766,12 +1771,8 @@ void launch_rotate_geometry(const Lay &L, const double *geo_ref, const double *x
 // one thread per padded slot of the largest case, one grid row per case
 static dim3 cells_grid(const BLev &B) { return dim3(nblocks(B.max_ns), B.n); }
 
-void launch_ghost_state(const BLev &B, int noslip, hipStream_t st) {
-    hipLaunchKernelGGL(k_ghost_state, cells_grid(B), dim3(TPB), 0, st, B.k, noslip);
-}
-
-void launch_cell_quantities(const BLev &B, int rans, hipStream_t st) {
-    hipLaunchKernelGGL(k_cell_quantities, cells_grid(B), dim3(TPB), 0, st, B.k, rans);
+void launch_ghost_cq(const BLev &B, int noslip, int rans, hipStream_t st) {
+    hipLaunchKernelGGL(k_ghost_cq, cells_grid(B), dim3(TPB), 0, st, B.k, noslip, rans);
 }
 
 void launch_vertex_gradients(const BLev &B, hipStream_t st) {
