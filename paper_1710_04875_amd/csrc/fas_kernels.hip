@@ -1198,6 +1198,30 @@ __device__ inline T dot4(const T (&m)[4], const T *x) {
     return p0 + p1;
 }
 
+template <typename T>
+__device__ inline T dot4r(const T (&m)[4], const T (&x)[4]) {
+    T p0 = fma(m[1], x[1], m[0] * x[0]);
+    T p1 = fma(m[3], x[3], m[2] * x[2]);
+    return p0 + p1;
+}
+
+// a row's 4-vector from LDS (16-byte aligned): two 16-byte reads for FP64,
+// one for FP32, so the neighbour rows of a step arrive in one round trip
+template <typename T> struct LdsRow;
+template <> struct LdsRow<double> {
+    __device__ static void get(const double *p, double (&o)[4]) {
+        const double2 a = *reinterpret_cast<const double2 *>(p);
+        const double2 b = *reinterpret_cast<const double2 *>(p + 2);
+        o[0] = a.x; o[1] = a.y; o[2] = b.x; o[3] = b.y;
+    }
+};
+template <> struct LdsRow<float> {
+    __device__ static void get(const float *p, float (&o)[4]) {
+        const float4 a = *reinterpret_cast<const float4 *>(p);
+        o[0] = a.x; o[1] = a.y; o[2] = a.z; o[3] = a.w;
+    }
+};
+
 typedef __amdgpu_buffer_rsrc_t Res;
 typedef unsigned int U32x2 __attribute__((ext_vector_type(2)));
 typedef unsigned int U32x4 __attribute__((ext_vector_type(4)));
@@ -1311,8 +1335,8 @@ template <typename T, int NT, int R, int D, bool BANDED>
 __global__ __launch_bounds__(NT) void k_sgs4(BK bk, SweepArgs a) {
     constexpr int NR = NT / 4 * R;            // rows handled by the workgroup
     constexpr int XS = 4 * NR + 8;            // guard row at both ends
-    __shared__ T xb[2][XS];
-    extern __shared__ unsigned char smem[];
+    __shared__ __attribute__((aligned(16))) T xb[2][XS];
+    extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
     LevelDev dv;
     const int nbands = BANDED ? a.bands : 1;
     const int band = BANDED ? (int)blockIdx.x % nbands : 0;
@@ -1421,13 +1445,20 @@ __global__ __launch_bounds__(NT) void k_sgs4(BK bk, SweepArgs a) {
                 const int jj = jq[q] - j0;                          // row within the band
                 const int i = h - jq[q];
                 const T *xs = prev + 4 * jj;                        // row below (guard row for jj = 0)
-                if (jq[q] == 0 && cutg && i >= ni - nw && i < ni) xs = row0 + (ni - 1 - i) * 4;
-                const T v = (gv[q] - dot4(wv[q], prev + 4 * jj + 4)) - dot4(sv[q], xs);
+                if (cutg) {                                         // band 0: wake-cut partner of row 0
+                    if (jq[q] == 0 && i >= ni - nw && i < ni) xs = row0 + (ni - 1 - i) * 4;
+                }
+                T xw[4], xsv[4];
+                LdsRow<T>::get(prev + 4 * jj + 4, xw);
+                LdsRow<T>::get(xs, xsv);
+                const T v = (gv[q] - dot4r(wv[q], xw)) - dot4r(sv[q], xsv);
                 const bool valid = cell(h, q);
                 const T vz = valid ? v : (T)0;
                 cur[4 * jj + 4 + r] = vz;
                 BufIO<T>::st(ry, valid ? hv * (unsigned)sizeof(T) + ov[q] : OOB, v);
-                if (valid && jq[q] == 0 && cutg && i < nw) row0[i * 4 + r] = v;
+                if (cutg) {
+                    if (valid && jq[q] == 0 && i < nw) row0[i * 4 + r] = v;
+                }
                 // one store: the last row's value (producer lanes) and the
                 // sentinel back into the slot just consumed (consumer lanes)
                 if constexpr (BANDED)
@@ -1502,17 +1533,24 @@ __global__ __launch_bounds__(NT) void k_sgs4(BK bk, SweepArgs a) {
             for (int q = 0; q < R; ++q) {
                 const int jj = jq[q] - j0;
                 const int i = h - jq[q];
-                T v = (yv[q] - dot4(ev[q], prev + 4 * jj + 4)) - dot4(nv[q], prev + 4 * jj + 8);
-                if (jq[q] == 0 && cutg && i >= 0 && i < nw) {
-                    T mp[4];
+                T xe[4], xn[4];
+                LdsRow<T>::get(prev + 4 * jj + 4, xe);
+                LdsRow<T>::get(prev + 4 * jj + 8, xn);
+                T v = (yv[q] - dot4r(ev[q], xe)) - dot4r(nv[q], xn);
+                if (cutg) {                                         // band 0: wake-cut partner of row 0
+                    if (jq[q] == 0 && i >= 0 && i < nw) {
+                        T mp[4];
 #pragma unroll
-                    for (int c = 0; c < 4; ++c) mp[c] = pblk[i * 16 + r * 4 + c];
-                    v = v - dot4(mp, row0 + (ni - 1 - i - (ni - nw)) * 4);
+                        for (int c = 0; c < 4; ++c) mp[c] = pblk[i * 16 + r * 4 + c];
+                        v = v - dot4(mp, row0 + (ni - 1 - i - (ni - nw)) * 4);
+                    }
                 }
                 const bool valid = cell(h, q);
                 const T vz = valid ? v : (T)0;
                 cur[4 * jj + 4 + r] = vz;
-                if (valid && jq[q] == 0 && cutg && i >= ni - nw) row0[(i - (ni - nw)) * 4 + r] = v;
+                if (cutg) {
+                    if (valid && jq[q] == 0 && i >= ni - nw) row0[(i - (ni - nw)) * 4 + r] = v;
+                }
                 if constexpr (BANDED)
                     if (q == 0)
                         Sent<T>::st(rh, hplane(h) + hs, cons ? Sent<T>::value() : vz);
