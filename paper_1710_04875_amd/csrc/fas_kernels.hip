@@ -7,6 +7,7 @@
 #include "fas_geom.h"
 
 #include <cmath>
+#include <type_traits>
 
 namespace fas {
 
@@ -1309,10 +1310,13 @@ template <> struct Sent<float> {
     }
 };
 
-// the hand-off value prefetched for this hyperplane, once it is written
+// the hand-off value prefetched for this hyperplane, once it is written.
+// Lanes without the consumer role read zeros (out-of-range offset), so one
+// ballot detects the rare step whose consumer still reads the sentinel and
+// the spin stays off the common path.
 template <typename T>
-__device__ inline T bnd_wait(T v, bool consumer, Res r, unsigned off, unsigned &budget) {
-    if (consumer) {
+__device__ inline T bnd_wait(T v, Res r, unsigned off, unsigned &budget) {
+    if (__builtin_amdgcn_ballot_w64(Sent<T>::is(v)) != 0) {
         while (Sent<T>::is(v) && budget > 0) {
             __builtin_amdgcn_s_sleep(1);
             v = Sent<T>::ld(r, off);
@@ -1336,6 +1340,7 @@ __global__ __launch_bounds__(NT) void k_sgs4(BK bk, SweepArgs a) {
     constexpr int NR = NT / 4 * R;            // rows handled by the workgroup
     constexpr int XS = 4 * NR + 8;            // guard row at both ends
     __shared__ __attribute__((aligned(16))) T xb[2][XS];
+    __shared__ T sink[BANDED ? NT : 1];       // guard-row writes of lanes without the consumer role
     extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
     LevelDev dv;
     const int nbands = BANDED ? a.bands : 1;
@@ -1374,20 +1379,22 @@ __global__ __launch_bounds__(NT) void k_sgs4(BK bk, SweepArgs a) {
     const Res rh = mkres(BANDED ? dv.bnd : dv.y, BANDED ? bnd_count(L) * sizeof(T) : 0);
     // per-lane byte offsets at slot base 0 (a hyperplane adds (h + 4) NJ slots)
     unsigned ov[R], ob[R], od[R];
-    int jq[R];
+    int jq[R], jx[R];
 #pragma unroll
     for (int q = 0; q < R; ++q) {
         jq[q] = j0 + grp * R + q;
+        jx[q] = jq[q] < nj ? jq[q] : jq[q] + (1 << 30);     // rows above the grid never have a cell
         const int jr = jq[q] < nj ? jq[q] : 0;
         ov[q] = (unsigned)((r * NS + jr + NG) * sizeof(T));
         ob[q] = (unsigned)((BL<T>::at(0, NS, jr + NG, r, 0)) * sizeof(T));
         od[q] = (unsigned)((r * NS + jr + NG) * sizeof(double));
     }
     // the lane's cell of row q on hyperplane h exists
-    auto cell = [&](int h, int q) {
-        const int i = h - jq[q];
-        return jq[q] < nj && i >= 0 && i < ni;
-    };
+    auto cell = [&](int h, int q) { return (unsigned)(h - jx[q]) < (unsigned)ni; };
+    // Absent cells (before the first column, past the last, above the last
+    // row, padded steps) load zero g (y) and blocks, so their value is +0
+    // exactly while the neighbour values are finite: it is written to LDS
+    // and handed on as it is, without a select.
     // hand-off lanes: the first row of the band (forward consumer, backward
     // producer) and its last row (forward producer, backward consumer).  A
     // hand-off offset is the uniform part of hyperplane h plus a per-lane
@@ -1430,40 +1437,41 @@ __global__ __launch_bounds__(NT) void k_sgs4(BK bk, SweepArgs a) {
                 }
             }
         };
-        auto step = [&](const T (&gv)[R], const T (&wv)[R][4], const T (&sv)[R][4], int sl, int h) {
-            const T *prev = xb[(h - 1) & 1];
-            T *cur = xb[h & 1];
+        // consumer lanes put the hand-off value into the guard row of the
+        // next hyperplane's buffer, the other lanes into their sink slot
+        T *const gd[2] = {cons ? &xb[0][r] : &sink[t], cons ? &xb[1][r] : &sink[t]};
+        // step sl of a batch (h0 + sl = h, h0 even): buffers alternate with sl
+        auto step = [&](auto wake, const T (&gv)[R], const T (&wv)[R][4], const T (&sv)[R][4], int sl, int h) {
+            constexpr bool WAKE = decltype(wake)::value;
+            const T *prev = xb[(sl + 1) & 1];
+            T *cur = xb[sl & 1];
             const unsigned hv = (unsigned)((h + 2 * NG) * NJ);
             if constexpr (BANDED) {
                 // the row below the band on this hyperplane, for the next one
-                const T bv = bnd_wait(ring[sl], cons, rh, hplane(h) + hl, budget);
-                if (cons) cur[r] = bv;
+                *gd[sl & 1] = bnd_wait(ring[sl], rh, hplane(h) + hl, budget);
                 ring[(sl + P) % NRING] = Sent<T>::ld(rh, hplane(h + P) + hl);
             }
 #pragma unroll
             for (int q = 0; q < R; ++q) {
                 const int jj = jq[q] - j0;                          // row within the band
-                const int i = h - jq[q];
                 const T *xs = prev + 4 * jj;                        // row below (guard row for jj = 0)
-                if (cutg) {                                         // band 0: wake-cut partner of row 0
-                    if (jq[q] == 0 && i >= ni - nw && i < ni) xs = row0 + (ni - 1 - i) * 4;
+                if (WAKE && h >= ni - nw && h < ni) {               // row 0 at i = h: wake-cut partner
+                    if (jq[q] == 0) xs = row0 + (ni - 1 - h) * 4;
                 }
                 T xw[4], xsv[4];
                 LdsRow<T>::get(prev + 4 * jj + 4, xw);
                 LdsRow<T>::get(xs, xsv);
                 const T v = (gv[q] - dot4r(wv[q], xw)) - dot4r(sv[q], xsv);
-                const bool valid = cell(h, q);
-                const T vz = valid ? v : (T)0;
-                cur[4 * jj + 4 + r] = vz;
-                BufIO<T>::st(ry, valid ? hv * (unsigned)sizeof(T) + ov[q] : OOB, v);
-                if (cutg) {
-                    if (valid && jq[q] == 0 && i < nw) row0[i * 4 + r] = v;
+                cur[4 * jj + 4 + r] = v;
+                BufIO<T>::st(ry, cell(h, q) ? hv * (unsigned)sizeof(T) + ov[q] : OOB, v);
+                if (WAKE && h < nw) {
+                    if (jq[q] == 0) row0[h * 4 + r] = v;
                 }
                 // one store: the last row's value (producer lanes) and the
                 // sentinel back into the slot just consumed (consumer lanes)
                 if constexpr (BANDED)
                     if (q == R - 1)
-                        Sent<T>::st(rh, hplane(h) + hs, cons ? Sent<T>::value() : vz);
+                        Sent<T>::st(rh, hplane(h) + hs, cons ? Sent<T>::value() : v);
             }
             step_sync<NT>();
         };
@@ -1471,17 +1479,25 @@ __global__ __launch_bounds__(NT) void k_sgs4(BK bk, SweepArgs a) {
 #pragma unroll
             for (int k = 0; k < P; ++k) ring[k] = Sent<T>::ld(rh, hplane(k) + hl);
         }
-        load(gA, wA, sA, 0);
-        __syncthreads();
-        for (int h0 = 0; h0 < H; h0 += 2 * D) {
+        // a batch of 2D hyperplanes; the wake-cut code is compiled only into
+        // the variant that band 0 of a C-grid runs near the cut columns
+        auto batch = [&](auto wake, int h0) {
             load(gB, wB, sB, h0 + D);
 #pragma unroll
             for (int k = 0; k < D; ++k)
-                if (BANDED || h0 + k < H) step(gA[k], wA[k], sA[k], k, h0 + k);
+                if (BANDED || h0 + k < H) step(wake, gA[k], wA[k], sA[k], k, h0 + k);
             load(gA, wA, sA, h0 + 2 * D);
 #pragma unroll
             for (int k = 0; k < D; ++k)
-                if (BANDED || h0 + D + k < H) step(gB[k], wB[k], sB[k], D + k, h0 + D + k);
+                if (BANDED || h0 + D + k < H) step(wake, gB[k], wB[k], sB[k], D + k, h0 + D + k);
+        };
+        load(gA, wA, sA, 0);
+        __syncthreads();
+        for (int h0 = 0; h0 < H; h0 += 2 * D) {
+            // row 0 of the batch's hyperplanes outside [0, nw) and [ni - nw, ni)
+            const bool plain = !cutg || h0 >= ni || (h0 >= nw && h0 + 2 * D <= ni - nw);
+            if (plain) batch(std::false_type(), h0);
+            else batch(std::true_type(), h0);
         }
     }
     // ---------------- backward (+ stage update); the full barrier completes the y stores
@@ -1501,8 +1517,10 @@ __global__ __launch_bounds__(NT) void k_sgs4(BK bk, SweepArgs a) {
         const bool cons = above && last, prod = below && first;
         const unsigned hl = hrow(cons, j0 + NR), hs = cons ? hl : hrow(prod, j0);
         T yA[D][R], eA[D][R][4], nA[D][R][4], yB[D][R], eB[D][R][4], nB[D][R][4];
-        double uA[D][R], uB[D][R];
-        auto load = [&](T (&yy)[D][R], T (&ee)[D][R][4], T (&nn)[D][R][4], double (&u0r)[D][R], int hb) {
+        double uA[D][R], uB[D][R], tA[D][R], tB[D][R];
+        const bool want_dt = a.update && !a.aw;
+        auto load = [&](T (&yy)[D][R], T (&ee)[D][R][4], T (&nn)[D][R][4], double (&u0r)[D][R], double (&dtr)[D][R],
+                        int hb) {
 #pragma unroll
             for (int k = 0; k < D; ++k) {
                 const int h = H - 1 - (hb + k);
@@ -1513,57 +1531,54 @@ __global__ __launch_bounds__(NT) void k_sgs4(BK bk, SweepArgs a) {
                     const unsigned obk = ok ? hv * (unsigned)(rec * sizeof(T)) + ob[q] : OOB;
                     yy[k][q] = BufIO<T>::ld(ry, ok ? hv * (unsigned)sizeof(T) + ov[q] : OOB);
                     u0r[k][q] = bld_d(ru0, ok && a.update ? hv * 8u + od[q] : OOB);
+                    dtr[k][q] = bld_d(rdt, ok && want_dt ? (hv + (unsigned)(jq[q] + NG)) * 8u : OOB);
                     BufIO<T>::row(rb, obk, pe0, pe1, ee[k][q]);
                     BufIO<T>::row(rb, obk, pn0, pn1, nn[k][q]);
                 }
             }
         };
-        auto step = [&](const T (&yv)[R], const T (&ev)[R][4], const T (&nv)[R][4], const double (&u0v)[R],
-                        int sl, int h) {
-            const T *prev = xb[(h + 1) & 1];
-            T *cur = xb[h & 1];
+        T *const gd[2] = {cons ? &xb[0][4 * NR + 4 + r] : &sink[t], cons ? &xb[1][4 * NR + 4 + r] : &sink[t]};
+        // step sl of a batch: buffers alternate with the step
+        auto step = [&](auto wake, const T (&yv)[R], const T (&ev)[R][4], const T (&nv)[R][4],
+                        const double (&u0v)[R], const double (&dtv)[R], int sl, int h) {
+            constexpr bool WAKE = decltype(wake)::value;
+            const T *prev = xb[(sl + 1) & 1];
+            T *cur = xb[sl & 1];
             const unsigned hv = (unsigned)((h + 2 * NG) * NJ);
             if constexpr (BANDED) {
                 // the row above the band on this hyperplane, for the next one
-                const T bv = bnd_wait(ring[sl], cons, rh, hplane(h) + hl, budget);
-                if (cons) cur[4 * NR + 4 + r] = bv;
+                *gd[sl & 1] = bnd_wait(ring[sl], rh, hplane(h) + hl, budget);
                 ring[(sl + P) % NRING] = Sent<T>::ld(rh, hplane(h - P) + hl);
             }
 #pragma unroll
             for (int q = 0; q < R; ++q) {
                 const int jj = jq[q] - j0;
-                const int i = h - jq[q];
                 T xe[4], xn[4];
                 LdsRow<T>::get(prev + 4 * jj + 4, xe);
                 LdsRow<T>::get(prev + 4 * jj + 8, xn);
                 T v = (yv[q] - dot4r(ev[q], xe)) - dot4r(nv[q], xn);
-                if (cutg) {                                         // band 0: wake-cut partner of row 0
-                    if (jq[q] == 0 && i >= 0 && i < nw) {
+                if (WAKE && h >= 0 && h < nw) {                    // row 0 at i = h: wake-cut partner
+                    if (jq[q] == 0) {
                         T mp[4];
 #pragma unroll
-                        for (int c = 0; c < 4; ++c) mp[c] = pblk[i * 16 + r * 4 + c];
-                        v = v - dot4(mp, row0 + (ni - 1 - i - (ni - nw)) * 4);
+                        for (int c = 0; c < 4; ++c) mp[c] = pblk[h * 16 + r * 4 + c];
+                        v = v - dot4(mp, row0 + (nw - 1 - h) * 4);
                     }
                 }
                 const bool valid = cell(h, q);
-                const T vz = valid ? v : (T)0;
-                cur[4 * jj + 4 + r] = vz;
-                if (cutg) {
-                    if (valid && jq[q] == 0 && i >= ni - nw) row0[(i - (ni - nw)) * 4 + r] = v;
+                cur[4 * jj + 4 + r] = v;
+                if (WAKE && h >= ni - nw && h < ni) {
+                    if (jq[q] == 0) row0[(h - (ni - nw)) * 4 + r] = v;
                 }
                 if constexpr (BANDED)
                     if (q == 0)
-                        Sent<T>::st(rh, hplane(h) + hs, cons ? Sent<T>::value() : vz);
+                        Sent<T>::st(rh, hplane(h) + hs, cons ? Sent<T>::value() : v);
                 const unsigned oe = valid ? hv * 8u + od[q] : OOB;
                 if (a.xout_acc) bst_d(rx, oe, (double)v);
                 if (a.update) {
                     double un;
-                    if (a.aw) {
-                        un = u0v[q] - a.alpha * (double)v;
-                    } else {
-                        const double dt_s = bld_d(rdt, valid ? (hv + (unsigned)(jq[q] + NG)) * 8u : OOB);
-                        un = u0v[q] - a.alpha * (dt_s * (double)v);
-                    }
+                    if (a.aw) un = u0v[q] - a.alpha * (double)v;
+                    else un = u0v[q] - a.alpha * (dtv[q] * (double)v);
                     bst_d(ruu, oe, un);
                 }
             }
@@ -1573,17 +1588,25 @@ __global__ __launch_bounds__(NT) void k_sgs4(BK bk, SweepArgs a) {
 #pragma unroll
             for (int k = 0; k < P; ++k) ring[k] = Sent<T>::ld(rh, hplane(H - 1 - k) + hl);
         }
-        load(yA, eA, nA, uA, 0);
+        auto batch = [&](auto wake, int h0) {
+            load(yB, eB, nB, uB, tB, h0 + D);
+#pragma unroll
+            for (int k = 0; k < D; ++k)
+                if (BANDED || h0 + k < H) step(wake, yA[k], eA[k], nA[k], uA[k], tA[k], k, H - 1 - (h0 + k));
+            load(yA, eA, nA, uA, tA, h0 + 2 * D);
+#pragma unroll
+            for (int k = 0; k < D; ++k)
+                if (BANDED || h0 + D + k < H)
+                    step(wake, yB[k], eB[k], nB[k], uB[k], tB[k], D + k, H - 1 - (h0 + D + k));
+        };
+        load(yA, eA, nA, uA, tA, 0);
         __syncthreads();
         for (int h0 = 0; h0 < H; h0 += 2 * D) {
-            load(yB, eB, nB, uB, h0 + D);
-#pragma unroll
-            for (int k = 0; k < D; ++k)
-                if (BANDED || h0 + k < H) step(yA[k], eA[k], nA[k], uA[k], k, H - 1 - (h0 + k));
-            load(yA, eA, nA, uA, h0 + 2 * D);
-#pragma unroll
-            for (int k = 0; k < D; ++k)
-                if (BANDED || h0 + D + k < H) step(yB[k], eB[k], nB[k], uB[k], D + k, H - 1 - (h0 + D + k));
+            // the batch's hyperplanes H - 1 - h0 down to H - 2D - h0
+            const int hhi = H - 1 - h0, hlo = H - 2 * D - h0;
+            const bool plain = !cutg || hlo >= ni || hhi < 0 || (hlo >= nw && hhi < ni - nw);
+            if (plain) batch(std::false_type(), h0);
+            else batch(std::true_type(), h0);
         }
     }
 }
