@@ -1886,6 +1886,7 @@ static constexpr SweepCfg SWEEP_CFGS[] = {
     {4, 128, 1, 5, 5},   {4, 256, 1, 5, 5},   {5, 64, 1, 5, 5},    {5, 128, 1, 5, 5}, {5, 256, 1, 5, 5},
     {5, 128, 1, 3, 3},   {5, 128, 1, 4, 4},   {4, 128, 1, 3, 3},   {5, 128, 1, 2, 2},
     {5, 128, 1, 1, 1},   {5, 64, 1, 2, 2},    {5, 64, 1, 3, 3},    {4, 128, 1, 2, 2},
+    {5, 64, 1, 4, 4},
 };
 constexpr int N_SWEEP_CFGS = (int)(sizeof(SWEEP_CFGS) / sizeof(SWEEP_CFGS[0]));
 
@@ -1927,15 +1928,14 @@ int sweep_cfg_plain(int max_nj) {
 
 // Default by height and precision, from timings of every configuration on
 // the three levels of a 256 x 128 grid: one 128-thread workgroup with
-// prefetch depth 3 up to 32 rows; above, bands of 32 rows (two waves each)
-// with depth 2 for FP64 blocks and depth 4 for FP32 blocks (a FP32 block
-// row is one 16-byte load instead of two, so the same depth keeps fewer
-// loads in flight).
+// prefetch depth 3 up to 32 rows; above, bands of 16 rows (one wave each,
+// no workgroup barrier) with depth 4 for FP64 blocks and depth 5 for FP32
+// blocks (a FP32 block row is one 16-byte load instead of two, so the same
+// depth keeps fewer loads in flight).
 int sweep_cfg_default(int max_nj, int fp32) {
     if (max_nj <= 32) return sweep_cfg_plain(max_nj);
-    return fp32 ? 24 : 26;
+    return fp32 ? 20 : 31;
 }
-
 // Banded launches wait on neighbouring workgroups: they are used only when
 // the whole grid can be resident at once.
 template <typename K>
@@ -1977,7 +1977,7 @@ static void sgs_dispatch(const BLev &B, const SweepArgs &a0, hipStream_t st) {
     } while (0)
 #define FAS_SGS1(C_) \
     hipLaunchKernelGGL((k_sgs<T, SWEEP_CFGS[C_].nt>), dim3(B.n), dim3(SWEEP_CFGS[C_].nt), shm, st, B.k, a)
-    static_assert(N_SWEEP_CFGS == 31 && SWEEP_CFGS[30].kind == 4 && SWEEP_CFGS[27].kind == 5 && SWEEP_CFGS[9].kind == 4 && SWEEP_CFGS[10].kind == 1 &&
+    static_assert(N_SWEEP_CFGS == 32 && SWEEP_CFGS[31].kind == 5 && SWEEP_CFGS[30].kind == 4 && SWEEP_CFGS[27].kind == 5 && SWEEP_CFGS[9].kind == 4 && SWEEP_CFGS[10].kind == 1 &&
                       SWEEP_CFGS[13].kind == 1 && SWEEP_CFGS[14].kind == 5 && SWEEP_CFGS[17].kind == 5 &&
                       SWEEP_CFGS[18].kind == 4 && SWEEP_CFGS[19].kind == 4 && SWEEP_CFGS[20].kind == 5 &&
                       SWEEP_CFGS[22].kind == 5 && SWEEP_CFGS[24].kind == 5 && SWEEP_CFGS[25].kind == 4,
@@ -2013,6 +2013,7 @@ static void sgs_dispatch(const BLev &B, const SweepArgs &a0, hipStream_t st) {
         case 27: FAS_SGS5(27); break;
         case 28: FAS_SGS5(28); break;
         case 29: FAS_SGS5(29); break;
+        case 31: FAS_SGS5(31); break;
         default: FAS_SGS4(30); break;
     }
 #undef FAS_K4
