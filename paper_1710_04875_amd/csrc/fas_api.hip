@@ -128,6 +128,14 @@ struct fas_state_s {
     double *a_lam = nullptr, *a_g = nullptr, *a_r = nullptr, *a_z = nullptr, *a_jt = nullptr,
            *a_lam0 = nullptr, *a_zeta = nullptr, *a_dFa = nullptr, *a_dFm = nullptr, *a_dcl = nullptr,
            *a_red = nullptr, *a_out = nullptr, *a_basis = nullptr;
+    // graph-replayed cycles: activity flag (read by every kernel of the
+    // state), cycles done, status, initial norm, history; a private stream
+    // to capture on (the state's own stream may be the legacy default)
+    int *d_act = nullptr, *d_ndone = nullptr, *d_stat = nullptr;
+    double *d_h0 = nullptr, *d_hist = nullptr;
+    int hcap = 0;
+    int *h_act = nullptr;       // pinned
+    hipStream_t cap_st = nullptr;
 };
 
 struct fas_batch_s {
@@ -341,8 +349,10 @@ static fas_status set_phys(fas_state s) {
 
 extern "C" void fas_state_destroy(fas_state s) {
     if (!s) return;
-    if (s->e.st) (void)hipStreamSynchronize(s->e.st);
+    (void)hipStreamSynchronize(s->e.st);
     engine_release_events(s->e);
+    if (s->cap_st) (void)hipStreamDestroy(s->cap_st);
+    if (s->h_act) (void)hipHostFree(s->h_act);
     for (auto p : s->allocs) (void)hipFree(p);
     delete s;
 }
@@ -427,8 +437,18 @@ extern "C" fas_status fas_state_create(fas_grid g, const fas_params *p, const do
     if (hipMemcpyAsync(dV, s->lv.data(), (size_t)s->nlev * sizeof(LevelDev), hipMemcpyHostToDevice, e.st) != hipSuccess)
         return cleanup(fail(FAS_EDEVICE, "descriptor upload failed"));
     launch_fill_int(e.d_cyc, 1, 0, e.st);
+    char *gc = nullptr;
+    if (hipMalloc(&gc, 64) != hipSuccess) return cleanup(fail(FAS_ENOMEM, "allocation failed"));
+    s->allocs.push_back(gc);
+    s->d_h0 = reinterpret_cast<double *>(gc);
+    s->d_act = reinterpret_cast<int *>(gc + 16);
+    s->d_ndone = reinterpret_cast<int *>(gc + 20);
+    s->d_stat = reinterpret_cast<int *>(gc + 24);
+    launch_fill_int(s->d_act, 1, 1, e.st);
+    if (hipHostMalloc(reinterpret_cast<void **>(&s->h_act), sizeof(int), hipHostMallocDefault) != hipSuccess)
+        return cleanup(fail(FAS_ENOMEM, "pinned allocation failed"));
     for (int l = 0; l < s->nlev; ++l)
-        e.lev.push_back(make_blev({s->lv[l].L}, dV + l, s->d_ph, nullptr, e.d_cyc));
+        e.lev.push_back(make_blev({s->lv[l].L}, dV + l, s->d_ph, s->d_act, e.d_cyc));
     if (set_phys(s) != FAS_OK) return cleanup(FAS_EDEVICE);
     launch_unpack(s->lv[0].L, u0, s->lv[0].u, 4, e.st);
     if (hipGetLastError() != hipSuccess) return cleanup(fail(FAS_EDEVICE, "kernel launch failed"));
@@ -728,10 +748,101 @@ extern "C" fas_status fas_sgs_apply(fas_state s, int32_t level, const double *r,
     return FAS_OK;
 }
 
+// fas_cycle by graph replay: the cycle, its norm and the stopping test are
+// captured once per call (so every host-side setting in force is the one
+// replayed) on the state's private stream and replayed on its own stream;
+// the activity flag turns the replays after the stop into no-ops, so the
+// iterates, history and count are those of the direct launches.  The host
+// reads the flag every few cycles.
+static fas_status cycle_graph(fas_state s, int32_t max_cycles, double drop_orders, double *res_hist,
+                              int32_t *n_done) {
+    Engine &e = s->e;
+    if (max_cycles + 1 > s->hcap) {
+        HIPCHK(hipStreamSynchronize(e.st));
+        if (s->d_hist) {
+            (void)hipFree(s->d_hist);
+            for (auto &p : s->allocs)
+                if (p == s->d_hist) p = nullptr;
+        }
+        s->d_hist = nullptr;
+        HIPCHK(hipMalloc(&s->d_hist, (size_t)(max_cycles + 1) * sizeof(double)));
+        s->allocs.push_back(s->d_hist);
+        s->hcap = max_cycles + 1;
+    }
+    if (!s->cap_st) HIPCHK(hipStreamCreateWithFlags(&s->cap_st, hipStreamNonBlocking));
+    BatchCtl ctl;
+    ctl.nrm = e.d_norm;
+    ctl.h0 = s->d_h0;
+    ctl.hist = s->d_hist;
+    ctl.hcap = s->hcap;
+    ctl.act = s->d_act;
+    ctl.cyc = e.d_cyc;
+    ctl.ndone = s->d_ndone;
+    ctl.stat = s->d_stat;
+    ctl.drop_factor = drop_orders > 0.0 ? std::pow(10.0, -drop_orders) : 0.0;
+    ctl.max_cycles = max_cycles;
+    launch_fill_int(s->d_act, 1, 1, e.st);
+    eval_norm(e);
+    launch_batch_init(ctl, 1, e.st);
+    HIPCHK(hipGetLastError());
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    const hipStream_t own = e.st;
+    e.st = s->cap_st;
+    hipError_t er = hipStreamBeginCapture(e.st, hipStreamCaptureModeThreadLocal);
+    if (er == hipSuccess) {
+        cycle(e, 0);
+        eval_norm(e);
+        launch_batch_status(ctl, 1, e.st);
+        er = hipStreamEndCapture(e.st, &graph);
+    }
+    e.st = own;
+    if (er == hipSuccess) er = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    if (er != hipSuccess) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return fail(FAS_EDEVICE, std::string("graph capture failed: ") + hipGetErrorString(er));
+    }
+    const int check = 4;
+    fas_status st = FAS_OK;
+    for (int k = 0; k < max_cycles; ++k) {
+        if (hipGraphLaunch(exec, e.st) != hipSuccess) {
+            st = fail(FAS_EDEVICE, "graph launch failed");
+            break;
+        }
+        if ((k + 1) % check == 0 || k + 1 == max_cycles) {
+            if (hipMemcpyAsync(s->h_act, s->d_act, sizeof(int), hipMemcpyDeviceToHost, e.st) != hipSuccess ||
+                hipStreamSynchronize(e.st) != hipSuccess) {
+                st = fail(FAS_EDEVICE, "graph replay failed");
+                break;
+            }
+            if (!*s->h_act) break;
+        }
+    }
+    (void)hipStreamSynchronize(e.st);
+    (void)hipGraphExecDestroy(exec);
+    (void)hipGraphDestroy(graph);
+    if (st != FAS_OK) return st;
+    int nd = 0, stv = 0;
+    HIPCHK(hipMemcpyAsync(&nd, s->d_ndone, sizeof(int), hipMemcpyDeviceToHost, e.st));
+    HIPCHK(hipMemcpyAsync(&stv, s->d_stat, sizeof(int), hipMemcpyDeviceToHost, e.st));
+    if (res_hist)
+        HIPCHK(hipMemcpyAsync(res_hist, s->d_hist, (size_t)(max_cycles + 1) * sizeof(double), hipMemcpyDeviceToHost,
+                              e.st));
+    launch_fill_int(s->d_act, 1, 1, e.st);
+    HIPCHK(hipStreamSynchronize(e.st));
+    HIPCHK(hipGetLastError());
+    if (n_done) *n_done = nd;
+    if (stv == FAS_DIVERGED) g_err = "residual norm is not finite";
+    if (stv == FAS_NOT_CONVERGED) g_err = "cycle cap reached before the requested residual drop";
+    return (fas_status)stv;
+}
+
 extern "C" fas_status fas_cycle(fas_state s, int32_t max_cycles, double drop_orders, double *res_hist,
                                 int32_t *n_done) {
     if (!s || max_cycles < 0) return fail(FAS_EINVAL, "bad argument");
     Engine &e = s->e;
+    // enough cycles to repay a capture, and no per-launch profiling events
+    if (max_cycles >= 4 && !e.prof) return cycle_graph(s, max_cycles, drop_orders, res_hist, n_done);
     double h0 = 0.0, h = 0.0;
     STCHK(norm(s, &h0));
     if (res_hist) res_hist[0] = h0;

@@ -162,6 +162,33 @@ def test_row_bands_equal_one_workgroup_per_case(fp32, scheme, cfl):
                 assert s.handoff_pending(level) == 0, (cfg, c, level)
 
 
+@pytest.mark.parametrize("drop", [0.0, 1.5, 30.0])
+def test_graph_replayed_cycles_equal_direct_launches(drop):
+    """A state's cycles of four or more are replayed from a captured graph
+    (cycle, norm and stopping test), with profiling on they are launched
+    directly: the same iterate, history, count and status, also when the
+    drop stops the run between two host checks of the activity flag and
+    when the cap stops it first."""
+    out = []
+    for direct in (False, True):
+        (g, st), = _states(cases=CASES[:1])
+        if direct:
+            st.profile(True)
+        h, s = st.cycle(11, drop)
+        torch.cuda.synchronize()
+        out.append((st.get_state().cpu().numpy(), h, s))
+        # a later call starts from the count and state this one left
+        h2, s2 = st.cycle(5, 0.0)
+        torch.cuda.synchronize()
+        out.append((st.get_state().cpu().numpy(), h2, s2))
+    for k in (0, 1):
+        assert np.array_equal(out[k][0], out[k + 2][0]), k
+        assert np.array_equal(out[k][1], out[k + 2][1]), k
+        assert out[k][2] == out[k + 2][2], k
+    if drop == 30.0:
+        assert len(out[0][1]) == 12
+
+
 def test_autotuned_configuration_covers_the_tallest_grid():
     _, _, _, b = _run_batch(cycles=1)
     for level in range(3):
