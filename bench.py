@@ -7,7 +7,9 @@ attack drawn from U[0, 2] deg (seed 3), Baldwin-Lomax RANS, FAS V-cycle on
 3 levels, AW3 smoother with the SGS preconditioner (d = 0.5, eta = 0.5,
 c* = 100 after a start-up ramp from c* = 1; the c* = 1e4 robust mode stalls
 at two orders on this grid).  A step is one FAS cycle including the residual-norm
-evaluation.  value = fine cells x cycles / s (one fine-level AW3 iteration
+evaluation and stopping test (the library replays a captured graph per
+cycle); the kernel breakdown and the sweep's launch duration come from as
+many cycles again, launched directly with HIP events around each launch.  value = fine cells x cycles / s (one fine-level AW3 iteration
 per V-cycle: "cell-iters/s"), FP64 residual, FP64 preconditioner.  Also
 reported: the same with the FP32 preconditioner, the time to a 6-order
 residual drop for both, the roofline of the dominant kernel, and the CPU
@@ -61,17 +63,25 @@ def run_gpu(fas, torch, steps, warmup, fp32, drop_cap):
     u0 = torch.from_numpy(case.initial_state(x, y)).cuda()
     g = fas.Grid(case.topology, x, y, case.n_wake, p.n_levels)
     out = {}
-    # throughput: warmup cycles, then K timed cycles with kernel timing on
+    # throughput: warmup cycles, then K timed cycles (replayed from the
+    # library's captured cycle graph)
     st = fas.State(g, p, u0)
     st.cycle(warmup)
-    st.profile(True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     hist, status = st.cycle(steps)
     torch.cuda.synchronize()
     t = time.perf_counter() - t0
+    # kernel timing: K more cycles launched directly with HIP events around
+    # every launch of the timed kernel classes, on the library's stream (the
+    # events cost about a tenth of the cycle time, so the throughput region
+    # runs without them)
+    st.profile(True)
+    hp, _ = st.cycle(steps)
+    torch.cuda.synchronize()
     prof = st.profile_read()
     st.profile(False)
+    out["prof_cycles"] = len(hp) - 1
     n = len(hist) - 1
     N = case.ni * case.nj
     out["ms_per_step"] = 1e3 * t / max(n, 1)
@@ -116,13 +126,34 @@ def sweep_roofline(res, case, levels):
     cells = level_cells(case.ni, case.nj, levels)
     # per cycle one AW3 iteration on every level: 3 sweep launches per level
     per_cycle = 3.0 * sum(cells) * SWEEP_BYTES_PER_CELL
-    cycles = res["steps_done"]
+    cycles = res["prof_cycles"]
     achieved = per_cycle * cycles / (ms * 1e-3) / 1e9 if ms > 0 else 0.0
     return {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": None,
             "kernel": "k_sgs4 (forward + backward hyperplane block-SGS sweep, one launch per stage)",
             "avg_launch_us": round(1e3 * ms / max(cnt, 1), 3), "launches": cnt,
+            "launch_timing": "HIP events around each sweep launch on the library stream, over %d cycles "
+                             "launched directly after the timed ones" % cycles,
             "algorithmic_bytes_per_cell": SWEEP_BYTES_PER_CELL}
+
+
+def sweep_source_hash():
+    """Hash of the sources that define the sweep kernel and the
+    configuration it is launched in: the internal header, and the SGS-sweep
+    and sweep-configuration sections of fas_kernels.hip."""
+    csrc = os.path.join(ROOT, "paper_1710_04875_amd", "csrc")
+    with open(os.path.join(csrc, "fas_kernels.hip")) as f:
+        k = f.read()
+    a = k.index("// ------------------------------------------------------------- SGS sweeps")
+    b = k.index("// ------------------------------------------------------------ transfers")
+    c = k.index("// Sweep configurations:")
+    d = k.index("#undef FAS_SGS1", c)
+    h = hashlib.sha256()
+    with open(os.path.join(csrc, "fas_internal.h"), "rb") as f:
+        h.update(f.read())
+    h.update(k[a:b].encode())
+    h.update(k[c:d].encode())
+    return h.hexdigest()[:16]
 
 
 def load_traffic(kernel_key):
@@ -133,11 +164,59 @@ def load_traffic(kernel_key):
         return None
     with open(path) as f:
         d = json.load(f)
-    src = os.path.join(ROOT, "paper_1710_04875_amd", "csrc", "fas_kernels.hip")
-    h = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
-    if d.get("kernels_sha") != h:
+    if d.get("kernels_sha") != sweep_source_hash():
         return None
     return d.get("bytes_per_launch")
+
+
+def traffic_summary(fetch_dir, write_dir, calf_dir, calw_dir):
+    """Calibrated HBM bytes per sweep launch from four rocprofv3 counter
+    runs of this file: FETCH_SIZE and WRITE_SIZE over the sweep kernels of the
+    throughput workload, and the same counters over --calibrate-copy (a
+    256 MiB device copy, which reads and writes 262144 KiB per dispatch).
+    Writes profiles/traffic_k_sgs_c2_fp64.json and prints the per-level
+    table."""
+    import csv
+    import numpy as np
+
+    def rows(d):
+        with open(os.path.join(d, "run_counter_collection.csv")) as f:
+            return list(csv.DictReader(f))
+
+    def per_kernel(d):
+        g = {}
+        for r in rows(d):
+            g.setdefault((r["Kernel_Name"], int(r["Grid_Size"])), []).append(float(r["Counter_Value"]))
+        return {k: float(np.mean(v)) for k, v in g.items()}
+
+    copy_kib = 262144.0
+    calf = max(v for (n, _), v in per_kernel(calf_dir).items() if "copyBuffer" in n)
+    calw = max(v for (n, _), v in per_kernel(calw_dir).items() if "copyBuffer" in n)
+    ff, fw = copy_kib / calf, copy_kib / calw
+    fetch, write = per_kernel(fetch_dir), per_kernel(write_dir)
+    cells = level_cells(256, 128, 3)
+    keys = sorted(fetch, key=lambda k: -fetch[k])
+    assert len(keys) == 3, keys
+    lines, per = [], []
+    for k, c in zip(keys, cells):
+        b = (fetch[k] * ff + write[k] * fw) * 1024.0
+        per.append(b)
+        lines.append("| %d cells | `%s` (grid %d) | %.1f | %.1f | %.4g | %.4g | %.2f |" % (
+            c, k[0].replace("void ", "").replace("fas::(anonymous namespace)::", "").split("(")[0], k[1],
+            fetch[k], write[k], b, c * SWEEP_BYTES_PER_CELL, b / (c * SWEEP_BYTES_PER_CELL)))
+    out = {"kernel": "k_sgs4 (FP64)", "workload": "256x128 RANS C-grid V-cycle",
+           "kernels_sha": sweep_source_hash(), "bytes_per_launch": round(float(np.mean(per)), 1),
+           "fetch_factor": ff, "write_factor": fw,
+           "source": "profiles/k_sgs4_c2_rans_256x128_hbm_traffic.md"}
+    with open(os.path.join(ROOT, "profiles", "traffic_k_sgs_c2_fp64.json"), "w") as f:
+        json.dump(out, f, indent=1)
+        f.write("\n")
+    print("calibration: FETCH %.1f KiB (x%.4f), WRITE %.1f KiB (x%.4f) per 262144 KiB copy" % (calf, ff, calw, fw))
+    print("| level | kernel | FETCH_SIZE KiB/dispatch | WRITE_SIZE KiB/dispatch | calibrated bytes/launch | "
+          "algorithmic bytes/launch | ratio |")
+    print("|---|---|---|---|---|---|---|")
+    print("\n".join(lines))
+    print("mean over the levels: %.4g bytes per launch" % out["bytes_per_launch"])
 
 
 def batch_params(fas, c, fp32):
@@ -337,7 +416,12 @@ def main():
     ap.add_argument("--inner-cap", type=int, default=300)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only copy a 256 MiB buffer 5 times (HBM counter calibration)")
+    ap.add_argument("--traffic-summary", nargs=4, metavar=("FETCH_DIR", "WRITE_DIR", "CALF_DIR", "CALW_DIR"),
+                    help="summarise four rocprofv3 --pmc output folders into the sweep's traffic record")
     args = ap.parse_args()
+    if args.traffic_summary:
+        traffic_summary(*args.traffic_summary)
+        return
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
               "(--gpus %d requested)" % args.gpus, file=sys.stderr)
@@ -380,7 +464,7 @@ def main():
                                "eta=0.5 c*=100" % case.alpha_deg,
                    "fine_cells": case.ni * case.nj, "levels": p.n_levels, "step": "one FAS cycle"},
         "time_to_6_orders_fp64": r64["drop"],
-        "kernel_ms_per_step_fp64": {k: round(v[0] / max(r64["steps_done"], 1), 4)
+        "kernel_ms_per_step_fp64": {k: round(v[0] / max(r64["prof_cycles"], 1), 4)
                                     for k, v in r64["prof"].items()},
         "residual_kernel": {"avg_launch_us": round(1e3 * res_ms / max(res_n, 1), 3),
                             "launches": res_n},
@@ -405,7 +489,7 @@ def main():
             "max_rel_state_diff_vs_fp64_converged": diff_deep,
             "converged_orders": ({"fp64": r64["deep"]["orders"], "fp32": r32["deep"]["orders"]}
                                  if diff_deep is not None else None),
-            "kernel_ms_per_step": {k: round(v[0] / max(r32["steps_done"], 1), 4)
+            "kernel_ms_per_step": {k: round(v[0] / max(r32["prof_cycles"], 1), 4)
                                    for k, v in r32["prof"].items()},
         }
     if not args.no_batch:
