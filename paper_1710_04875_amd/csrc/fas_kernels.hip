@@ -1830,14 +1830,17 @@ void launch_rotate_geometry(const Lay &L, const double *geo_ref, const double *x
 }
 
 // one thread per padded slot of the largest case, one grid row per case
-static dim3 cells_grid(const BLev &B) { return dim3(nblocks(B.max_ns), B.n); }
+// per-cell kernels: one wave per workgroup, so that even the fine level of
+// one grid (about 50k slots) spreads over every CU
+constexpr int CELL_TPB = 64;
+static dim3 cells_grid(const BLev &B) { return dim3(nblocks(B.max_ns, CELL_TPB), B.n); }
 
 void launch_ghost_cq(const BLev &B, int noslip, int rans, hipStream_t st) {
-    hipLaunchKernelGGL(k_ghost_cq, cells_grid(B), dim3(TPB), 0, st, B.k, noslip, rans);
+    hipLaunchKernelGGL(k_ghost_cq, cells_grid(B), dim3(CELL_TPB), 0, st, B.k, noslip, rans);
 }
 
 void launch_vertex_gradients(const BLev &B, hipStream_t st) {
-    hipLaunchKernelGGL(k_vertex_gradients, cells_grid(B), dim3(TPB), 0, st, B.k);
+    hipLaunchKernelGGL(k_vertex_gradients, cells_grid(B), dim3(CELL_TPB), 0, st, B.k);
 }
 
 void launch_baldwin_lomax(const BLev &B, hipStream_t st) {
@@ -1846,25 +1849,25 @@ void launch_baldwin_lomax(const BLev &B, hipStream_t st) {
 }
 
 void launch_mut_ghosts(const BLev &B, hipStream_t st) {
-    hipLaunchKernelGGL(k_mut_ghosts, cells_grid(B), dim3(TPB), 0, st, B.k);
+    hipLaunchKernelGGL(k_mut_ghosts, cells_grid(B), dim3(CELL_TPB), 0, st, B.k);
 }
 
 void launch_local_time_step(const BLev &B, hipStream_t st) {
-    hipLaunchKernelGGL(k_local_time_step, cells_grid(B), dim3(TPB), 0, st, B.k);
+    hipLaunchKernelGGL(k_local_time_step, cells_grid(B), dim3(CELL_TPB), 0, st, B.k);
 }
 
 void launch_residual(const BLev &B, const ResArgs &a, hipStream_t st) {
     if (a.fp32)
-        hipLaunchKernelGGL(k_residual<float>, cells_grid(B), dim3(TPB), 0, st, B.k, a);
+        hipLaunchKernelGGL(k_residual<float>, cells_grid(B), dim3(CELL_TPB), 0, st, B.k, a);
     else
-        hipLaunchKernelGGL(k_residual<double>, cells_grid(B), dim3(TPB), 0, st, B.k, a);
+        hipLaunchKernelGGL(k_residual<double>, cells_grid(B), dim3(CELL_TPB), 0, st, B.k, a);
 }
 
 void launch_blocks(const BLev &B, int aw, double tau, int viscous, int fp32, hipStream_t st) {
     if (fp32)
-        hipLaunchKernelGGL(k_blocks<float>, cells_grid(B), dim3(TPB), 0, st, B.k, aw, tau, viscous);
+        hipLaunchKernelGGL(k_blocks<float>, cells_grid(B), dim3(CELL_TPB), 0, st, B.k, aw, tau, viscous);
     else
-        hipLaunchKernelGGL(k_blocks<double>, cells_grid(B), dim3(TPB), 0, st, B.k, aw, tau, viscous);
+        hipLaunchKernelGGL(k_blocks<double>, cells_grid(B), dim3(CELL_TPB), 0, st, B.k, aw, tau, viscous);
 }
 
 // Sweep configurations: four threads per row (k_sgs4 with NT threads, R
@@ -2029,25 +2032,25 @@ void launch_sgs(const BLev &B, const SweepArgs &a, int fp32, hipStream_t st) {
 
 void launch_dinv(const BLev &B, int fp32, hipStream_t st) {
     if (fp32)
-        hipLaunchKernelGGL(k_dinv<float>, cells_grid(B), dim3(TPB), 0, st, B.k);
+        hipLaunchKernelGGL(k_dinv<float>, cells_grid(B), dim3(CELL_TPB), 0, st, B.k);
     else
-        hipLaunchKernelGGL(k_dinv<double>, cells_grid(B), dim3(TPB), 0, st, B.k);
+        hipLaunchKernelGGL(k_dinv<double>, cells_grid(B), dim3(CELL_TPB), 0, st, B.k);
 }
 
 void launch_restrict(const BLev &Bf, const BLev &Bc, int fin, int fout, int fout2, hipStream_t st) {
-    hipLaunchKernelGGL(k_restrict, cells_grid(Bc), dim3(TPB), 0, st, Bf.k, Bc.k, fin, fout, fout2);
+    hipLaunchKernelGGL(k_restrict, cells_grid(Bc), dim3(CELL_TPB), 0, st, Bf.k, Bc.k, fin, fout, fout2);
 }
 
 void launch_restrict_mut(const BLev &Bf, const BLev &Bc, hipStream_t st) {
-    hipLaunchKernelGGL(k_restrict_mut, cells_grid(Bc), dim3(TPB), 0, st, Bf.k, Bc.k);
+    hipLaunchKernelGGL(k_restrict_mut, cells_grid(Bc), dim3(CELL_TPB), 0, st, Bf.k, Bc.k);
 }
 
 void launch_prolong(const BLev &Bf, const BLev &Bc, hipStream_t st) {
-    hipLaunchKernelGGL(k_prolong, cells_grid(Bf), dim3(TPB), 0, st, Bf.k, Bc.k);
+    hipLaunchKernelGGL(k_prolong, cells_grid(Bf), dim3(CELL_TPB), 0, st, Bf.k, Bc.k);
 }
 
 void launch_axpby(const BLev &B, double a, int fx, double b, int fy, int fout, hipStream_t st) {
-    hipLaunchKernelGGL(k_axpby, cells_grid(B), dim3(TPB), 0, st, B.k, a, fx, b, fy, fout);
+    hipLaunchKernelGGL(k_axpby, cells_grid(B), dim3(CELL_TPB), 0, st, B.k, a, fx, b, fy, fout);
 }
 
 void launch_pack(const Lay &L, const double *padded, double *natural, int ncomp, hipStream_t st) {
