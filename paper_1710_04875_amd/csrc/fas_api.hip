@@ -612,19 +612,21 @@ void eval_F(Engine &e, int l, bool forcing) {
 }
 
 // frozen quantities of one smoother iteration: dt*, eddy viscosity, blocks
-void prepare_iteration(Engine &e, int l) {
+// (prepped: the level's ghosts, cell quantities, vertex gradients and fine
+// eddy viscosity already belong to its current solution)
+void prepare_iteration(Engine &e, int l, bool prepped = false) {
     const BLev &B = e.lev[l];
-    prep(e, l, fine_rans(e, l));
+    if (!prepped) prep(e, l, fine_rans(e, l));
     launch_local_time_step(B, e.st);
     Prof pr(e, FAS_PROF_BLOCKS);
     launch_blocks(B, e.sc.aw, tau_of(e), rans(e), e.fp32, e.st);
 }
 
 // one smoother iteration (Section 4 low-storage stages)
-void smooth_once(Engine &e, int l) {
+void smooth_once(Engine &e, int l, bool prepped = false) {
     const BLev &B = e.lev[l];
     launch_axpby(B, 1.0, FLD_U, 0.0, FLD_NONE, FLD_U0, e.st);
-    prepare_iteration(e, l);
+    prepare_iteration(e, l, prepped);
     for (int k = 0; k < e.sc.s; ++k) {
         if (k > 0) prep(e, l, false);
         ResArgs a = res_args(e, l, 1, 1);
@@ -644,9 +646,15 @@ void smooth_once(Engine &e, int l) {
     }
 }
 
-void cycle(Engine &e, int l) {
+// FAS cycle from level l.  prepped: a residual evaluation of level l's
+// current solution (with the eddy viscosity the smoother uses) came last, so
+// the first smoother iteration reuses its ghosts, cell quantities, vertex
+// gradients and eddy viscosity instead of recomputing the same values
+// (the coarse levels' forcing evaluation below, and the fine-level norm
+// that precedes every cycle).
+void cycle(Engine &e, int l, bool prepped = false) {
     const int nsm = l < e.nlev - 1 ? e.nu1 : 1;
-    for (int k = 0; k < nsm; ++k) smooth_once(e, l);
+    for (int k = 0; k < nsm; ++k) smooth_once(e, l, prepped && k == 0);
     if (l == e.nlev - 1) return;
     const BLev &f = e.lev[l], &c = e.lev[l + 1];
     eval_F(e, l, false);
@@ -665,7 +673,7 @@ void cycle(Engine &e, int l) {
     eval_F(e, l + 1, false);
     launch_axpby(c, 1.0, FLD_F, 1.0, FLD_ACC, FLD_SRC, e.st);
     e.has_src[l + 1] = 1;
-    for (int k = 0; k < e.gamma; ++k) cycle(e, l + 1);
+    for (int k = 0; k < e.gamma; ++k) cycle(e, l + 1, k == 0);
     launch_prolong(f, c, e.st);
 }
 
@@ -791,7 +799,7 @@ static fas_status cycle_graph(fas_state s, int32_t max_cycles, double drop_order
     e.st = s->cap_st;
     hipError_t er = hipStreamBeginCapture(e.st, hipStreamCaptureModeThreadLocal);
     if (er == hipSuccess) {
-        cycle(e, 0);
+        cycle(e, 0, true);       // the norm before the capture, then each replay's own
         eval_norm(e);
         launch_batch_status(ctl, 1, e.st);
         er = hipStreamEndCapture(e.st, &graph);
@@ -850,7 +858,7 @@ extern "C" fas_status fas_cycle(fas_state s, int32_t max_cycles, double drop_ord
     fas_status st = FAS_OK;
     if (!std::isfinite(h0)) st = FAS_DIVERGED;
     for (int k = 0; k < max_cycles && st == FAS_OK; ++k) {
-        cycle(e, 0);
+        cycle(e, 0, true);       // right after a norm evaluation
         launch_count_cycle(e.lev[0], e.d_cyc, e.st);
         ++done;
         STCHK(norm(s, &h));
@@ -1394,7 +1402,7 @@ extern "C" fas_status fas_batch_set_sweep_config(fas_batch b, int32_t level, int
 // one batched cycle followed by the norm and the per-case status update
 static void batch_step(fas_batch b, const BatchCtl &ctl) {
     Engine &e = b->e;
-    cycle(e, 0);
+    cycle(e, 0, true);           // the norm before the loop, then each step's own
     eval_norm(e);
     launch_batch_status(ctl, e.n, e.st);
 }
