@@ -617,7 +617,6 @@ void eval_F(Engine &e, int l, bool forcing) {
 void prepare_iteration(Engine &e, int l, bool prepped = false) {
     const BLev &B = e.lev[l];
     if (!prepped) prep(e, l, fine_rans(e, l));
-    launch_local_time_step(B, e.st);
     Prof pr(e, FAS_PROF_BLOCKS);
     launch_blocks(B, e.sc.aw, tau_of(e), rans(e), e.fp32, e.st);
 }
@@ -664,14 +663,17 @@ void cycle(Engine &e, int l, bool prepped = false) {
         launch_restrict_mut(f, c, e.st);
         launch_mut_ghosts(c, e.st);
     }
-    // r_l = s_l - F_l(u_l)
-    if (e.has_src[l]) launch_axpby(f, -1.0, FLD_F, 1.0, FLD_SRC, FLD_F, e.st);
-    else launch_axpby(f, -1.0, FLD_F, 0.0, FLD_NONE, FLD_F, e.st);
-    launch_restrict(f, c, FLD_U, FLD_U, FLD_UT, e.st);
-    launch_restrict(f, c, FLD_F, FLD_ACC, FLD_NONE, e.st);
+    // u_{l+1} = I u_l (also kept as ut); acc_{l+1} = I r_l with the defect
+    // r_l = s_l - F_l(u_l) formed per fine cell inside the restriction
+    const RJob jobs[2] = {{FLD_U, 1.0, FLD_NONE, 0.0, FLD_U, FLD_UT},
+                          {FLD_F, -1.0, e.has_src[l] ? FLD_SRC : FLD_NONE, 1.0, FLD_ACC, FLD_NONE}};
+    launch_restrict_jobs(f, c, jobs, 2, e.st);
+    // s_{l+1} = F_{l+1}(u_{l+1}) + acc_{l+1}, written by the residual itself
     e.has_src[l + 1] = 0;
-    eval_F(e, l + 1, false);
-    launch_axpby(c, 1.0, FLD_F, 1.0, FLD_ACC, FLD_SRC, e.st);
+    prep(e, l + 1, fine_rans(e, l + 1));
+    ResArgs ra = res_args(e, l + 1, 0, 0);
+    ra.src_acc = 1;
+    launch_residual(c, ra, e.st);
     e.has_src[l + 1] = 1;
     for (int k = 0; k < e.gamma; ++k) cycle(e, l + 1, k == 0);
     launch_prolong(f, c, e.st);

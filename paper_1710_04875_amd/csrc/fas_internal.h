@@ -174,7 +174,6 @@ void launch_ghost_cq(const BLev &B, int noslip, int rans, hipStream_t st);   // 
 void launch_vertex_gradients(const BLev &B, hipStream_t st);
 void launch_baldwin_lomax(const BLev &B, hipStream_t st);
 void launch_mut_ghosts(const BLev &B, hipStream_t st);
-void launch_local_time_step(const BLev &B, hipStream_t st);
 
 struct ResArgs {
     int fine;          // second-order JST (sensor, fourth difference)
@@ -187,10 +186,11 @@ struct ResArgs {
     double beta;       // beta_{i+1} of the blended f^v (stage > 0)
     int aw;            // 1: g = D^-1 (dt* r); 0: g = D^-1 r
     int fp32;          // blocks / g in float
+    int src_acc;       // mode 0: also write src = F + acc (a coarse level's FAS forcing)
 };
 void launch_residual(const BLev &B, const ResArgs &a, hipStream_t st);
 
-// preconditioner
+// preconditioner (the kernel also writes the level's dt*, Section 4.1)
 void launch_blocks(const BLev &B, int aw, double tau, int viscous, int fp32, hipStream_t st);
 struct SweepArgs {
     int update;        // 1: write u = u0 - alpha x (AW) or u0 - alpha dt* x (pARK)
@@ -214,6 +214,15 @@ int sweep_cfg_plain(int max_nj);
 
 // transfers and utilities
 void launch_restrict(const BLev &Bf, const BLev &Bc, int fin, int fout, int fout2, hipStream_t st);
+// restriction of up to two fine-level combinations a x (+ b y) in one launch
+struct RJob {
+    int fx;
+    double a;
+    int fy;            // FLD_NONE: a x alone
+    double b;
+    int fout, fout2;   // coarse outputs (fout2 may be FLD_NONE)
+};
+void launch_restrict_jobs(const BLev &Bf, const BLev &Bc, const RJob *jobs, int njobs, hipStream_t st);
 void launch_restrict_mut(const BLev &Bf, const BLev &Bc, hipStream_t st);
 void launch_prolong(const BLev &Bf, const BLev &Bc, hipStream_t st);
 void launch_axpby(const BLev &B, double a, int fx, double b, int fy, int fout, hipStream_t st);

@@ -491,18 +491,8 @@ __device__ inline double cfl_of(const Phys &ph, int n) {
     return ph.cfl;
 }
 
-// Section 4.1: dt* = c* Omega / (r_xi + r_eta)
-__global__ void k_local_time_step(BK b) {
-    LevelDev d;
-    if (!take(b, blockIdx.y, d)) return;
-    const Lay L = d.L;
-    const double *geo = d.geo, *u = d.u;
-    double *dts = d.dts;
-    const double cfl = cfl_of(b.PH[blockIdx.y], b.cyc[blockIdx.y]);
-    int s = blockIdx.x * blockDim.x + threadIdx.x;
-    int i, j;
-    if (!decode(L, s, i, j) || !interior(L, i, j)) return;
-    const int NS = L.NS;
+// Section 4.1: dt* = c* Omega / (r_xi + r_eta) of interior cell s
+__device__ inline double local_dt(const Phys &ph, double cfl, const double *geo, const double *u, int NS, int s) {
     double r = u[s], mx = u[NS + s], my = u[2 * NS + s], E = u[3 * NS + s];
     double vx = mx / r, vy = my / r;
     double p = pres(r, mx, my, E);
@@ -510,10 +500,10 @@ __global__ void k_local_time_step(BK b) {
     double sb0 = geo[G_SB0 * NS + s], sb1 = geo[G_SB1 * NS + s];
     double sb2 = geo[G_SB2 * NS + s], sb3 = geo[G_SB3 * NS + s];
     double vnx, vne;
-    rel_normal(b.PH[blockIdx.y], geo, NS, s, vx, vy, sb0, sb1, sb2, sb3, vnx, vne);
+    rel_normal(ph, geo, NS, s, vx, vy, sb0, sb1, sb2, sb3, vnx, vne);
     double rxi = fabs(vnx) + a * sqrt(sb0 * sb0 + sb1 * sb1);
     double reta = fabs(vne) + a * sqrt(sb2 * sb2 + sb3 * sb3);
-    dts[s] = cfl * geo[G_VOL * NS + s] / (rxi + reta);
+    return cfl * geo[G_VOL * NS + s] / (rxi + reta);
 }
 
 // Section 2: velocity and temperature gradients at vertices, Green-Gauss
@@ -801,7 +791,11 @@ __global__ __launch_bounds__(TPB) void k_residual(BK b, ResArgs a) {
     }
     if (a.mode == 0) {
 #pragma unroll
-        for (int k = 0; k < 4; ++k) F[k * NS + s] = Fc[k] + Fv[k];
+        for (int k = 0; k < 4; ++k) {
+            const double f = Fc[k] + Fv[k];
+            F[k * NS + s] = f;
+            if (a.src_acc) d.src[k * NS + s] = f + acc[k * NS + s];
+        }
         return;
     }
     double r[4];
@@ -925,16 +919,19 @@ __global__ __launch_bounds__(TPB) void k_blocks(BK b, int aw, double tau, int vi
     LevelDev dv;
     if (!take(b, blockIdx.y, dv)) return;
     const Lay L = dv.L;
-    const double *geo = dv.geo, *u = dv.u, *cq = dv.cq, *mut = dv.mut, *dts = dv.dts;
+    const double *geo = dv.geo, *u = dv.u, *cq = dv.cq, *mut = dv.mut;
     BT *blk = (BT *)dv.blk;
     const Phys ph = b.PH[blockIdx.y];
     int s = blockIdx.x * blockDim.x + threadIdx.x;
     int i, j;
     if (!decode(L, s, i, j) || !interior(L, i, j)) return;
     const int NS = L.NS, NJ = L.NJ;
+    // the iteration's frozen dt* (read by the stages' residuals and sweeps)
+    const double dt_s = local_dt(ph, cfl_of(ph, b.cyc[blockIdx.y]), geo, u, NS, s);
+    dv.dts[s] = dt_s;
     double c, diag;
     if (aw) {
-        double e = ph.eta * dts[s];
+        double e = ph.eta * dt_s;
         c = e / geo[G_VOL * NS + s];
         diag = 1.0 + tau * e;
     } else {
@@ -1613,12 +1610,13 @@ __global__ __launch_bounds__(NT) void k_sgs4(BK bk, SweepArgs a) {
 
 // ------------------------------------------------------------ transfers
 // Section 3: restriction = volume-weighted agglomeration of 2x2 cells.
-__global__ void k_restrict(BK bf, BK bc, int fin, int fout, int fout2) {
+// Each job restricts the fine-level combination a x (+ b y), formed per
+// fine cell as the elementwise update of the same name would form it.
+__global__ void k_restrict(BK bf, BK bc, RJob j0, RJob j1, int njobs) {
     LevelDev df, dc;
     if (!take(bf, blockIdx.y, df) || !take(bc, blockIdx.y, dc)) return;
     const Lay Lf = df.L, Lc = dc.L;
-    const double *geof = df.geo, *geoc = dc.geo, *vf = field(df, fin);
-    double *vc = field(dc, fout), *vc2 = field(dc, fout2);
+    const double *geof = df.geo, *geoc = dc.geo;
     int s = blockIdx.x * blockDim.x + threadIdx.x;
     int i, j;
     if (!decode(Lc, s, i, j) || !interior(Lc, i, j)) return;
@@ -1628,13 +1626,19 @@ __global__ void k_restrict(BK bf, BK bc, int fin, int fout, int fout2) {
     double v00 = geof[G_VOL * NSf + c00], v10 = geof[G_VOL * NSf + c10];
     double v01 = geof[G_VOL * NSf + c01], v11 = geof[G_VOL * NSf + c11];
     double vol = geoc[G_VOL * NSc + s];
+    for (int q = 0; q < njobs; ++q) {
+        const RJob jb = q == 0 ? j0 : j1;
+        const double *x = field(df, jb.fx), *y = field(df, jb.fy);
+        double *vc = field(dc, jb.fout), *vc2 = field(dc, jb.fout2);
+        auto val = [&](int o) { return y ? jb.a * x[o] + jb.b * y[o] : jb.a * x[o]; };
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
-        double w00 = vf[k * NSf + c00] * v00, w10 = vf[k * NSf + c10] * v10;
-        double w01 = vf[k * NSf + c01] * v01, w11 = vf[k * NSf + c11] * v11;
-        double r = (((w00 + w10) + w01) + w11) / vol;
-        vc[k * NSc + s] = r;
-        if (vc2) vc2[k * NSc + s] = r;
+        for (int k = 0; k < 4; ++k) {
+            double w00 = val(k * NSf + c00) * v00, w10 = val(k * NSf + c10) * v10;
+            double w01 = val(k * NSf + c01) * v01, w11 = val(k * NSf + c11) * v11;
+            double r = (((w00 + w10) + w01) + w11) / vol;
+            vc[k * NSc + s] = r;
+            if (vc2) vc2[k * NSc + s] = r;
+        }
     }
 }
 
@@ -1852,10 +1856,6 @@ void launch_mut_ghosts(const BLev &B, hipStream_t st) {
     hipLaunchKernelGGL(k_mut_ghosts, cells_grid(B), dim3(CELL_TPB), 0, st, B.k);
 }
 
-void launch_local_time_step(const BLev &B, hipStream_t st) {
-    hipLaunchKernelGGL(k_local_time_step, cells_grid(B), dim3(CELL_TPB), 0, st, B.k);
-}
-
 void launch_residual(const BLev &B, const ResArgs &a, hipStream_t st) {
     if (a.fp32)
         hipLaunchKernelGGL(k_residual<float>, cells_grid(B), dim3(CELL_TPB), 0, st, B.k, a);
@@ -2038,7 +2038,13 @@ void launch_dinv(const BLev &B, int fp32, hipStream_t st) {
 }
 
 void launch_restrict(const BLev &Bf, const BLev &Bc, int fin, int fout, int fout2, hipStream_t st) {
-    hipLaunchKernelGGL(k_restrict, cells_grid(Bc), dim3(CELL_TPB), 0, st, Bf.k, Bc.k, fin, fout, fout2);
+    const RJob j = {fin, 1.0, FLD_NONE, 0.0, fout, fout2};
+    launch_restrict_jobs(Bf, Bc, &j, 1, st);
+}
+
+void launch_restrict_jobs(const BLev &Bf, const BLev &Bc, const RJob *jobs, int njobs, hipStream_t st) {
+    hipLaunchKernelGGL(k_restrict, cells_grid(Bc), dim3(CELL_TPB), 0, st, Bf.k, Bc.k, jobs[0],
+                       njobs > 1 ? jobs[1] : jobs[0], njobs > 1 ? 2 : 1);
 }
 
 void launch_restrict_mut(const BLev &Bf, const BLev &Bc, hipStream_t st) {
