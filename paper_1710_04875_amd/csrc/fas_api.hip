@@ -614,18 +614,17 @@ void eval_F(Engine &e, int l, bool forcing) {
 // frozen quantities of one smoother iteration: dt*, eddy viscosity, blocks
 // (prepped: the level's ghosts, cell quantities, vertex gradients and fine
 // eddy viscosity already belong to its current solution)
-void prepare_iteration(Engine &e, int l, bool prepped = false) {
+void prepare_iteration(Engine &e, int l, bool prepped = false, bool copy_u0 = false) {
     const BLev &B = e.lev[l];
     if (!prepped) prep(e, l, fine_rans(e, l));
     Prof pr(e, FAS_PROF_BLOCKS);
-    launch_blocks(B, e.sc.aw, tau_of(e), rans(e), e.fp32, e.st);
+    launch_blocks(B, e.sc.aw, tau_of(e), rans(e), e.fp32, e.st, copy_u0 ? 1 : 0);
 }
 
 // one smoother iteration (Section 4 low-storage stages)
 void smooth_once(Engine &e, int l, bool prepped = false) {
     const BLev &B = e.lev[l];
-    launch_axpby(B, 1.0, FLD_U, 0.0, FLD_NONE, FLD_U0, e.st);
-    prepare_iteration(e, l, prepped);
+    prepare_iteration(e, l, prepped, true);      // u0 = u: the iteration's starting state
     for (int k = 0; k < e.sc.s; ++k) {
         if (k > 0) prep(e, l, false);
         ResArgs a = res_args(e, l, 1, 1);
@@ -657,17 +656,14 @@ void cycle(Engine &e, int l, bool prepped = false) {
     if (l == e.nlev - 1) return;
     const BLev &f = e.lev[l], &c = e.lev[l + 1];
     eval_F(e, l, false);
-    if (rans(e)) {
-        // the eddy viscosity F_l was evaluated with, restricted and frozen
-        // on the coarser level until the next descent
-        launch_restrict_mut(f, c, e.st);
-        launch_mut_ghosts(c, e.st);
-    }
     // u_{l+1} = I u_l (also kept as ut); acc_{l+1} = I r_l with the defect
-    // r_l = s_l - F_l(u_l) formed per fine cell inside the restriction
+    // r_l = s_l - F_l(u_l) formed per fine cell inside the restriction; on
+    // RANS levels also the eddy viscosity F_l was evaluated with, frozen on
+    // the coarser level until the next descent
     const RJob jobs[2] = {{FLD_U, 1.0, FLD_NONE, 0.0, FLD_U, FLD_UT},
                           {FLD_F, -1.0, e.has_src[l] ? FLD_SRC : FLD_NONE, 1.0, FLD_ACC, FLD_NONE}};
-    launch_restrict_jobs(f, c, jobs, 2, e.st);
+    launch_restrict_jobs(f, c, jobs, 2, rans(e) ? 1 : 0, e.st);
+    if (rans(e)) launch_mut_ghosts(c, e.st);
     // s_{l+1} = F_{l+1}(u_{l+1}) + acc_{l+1}, written by the residual itself
     e.has_src[l + 1] = 0;
     prep(e, l + 1, fine_rans(e, l + 1));

@@ -190,8 +190,9 @@ struct ResArgs {
 };
 void launch_residual(const BLev &B, const ResArgs &a, hipStream_t st);
 
-// preconditioner (the kernel also writes the level's dt*, Section 4.1)
-void launch_blocks(const BLev &B, int aw, double tau, int viscous, int fp32, hipStream_t st);
+// preconditioner (the kernel also writes the level's dt*, Section 4.1, and
+// on request copies u to u0, the smoother iteration's starting state)
+void launch_blocks(const BLev &B, int aw, double tau, int viscous, int fp32, hipStream_t st, int copy_u0 = 0);
 struct SweepArgs {
     int update;        // 1: write u = u0 - alpha x (AW) or u0 - alpha dt* x (pARK)
     double alpha;
@@ -222,8 +223,8 @@ struct RJob {
     double b;
     int fout, fout2;   // coarse outputs (fout2 may be FLD_NONE)
 };
-void launch_restrict_jobs(const BLev &Bf, const BLev &Bc, const RJob *jobs, int njobs, hipStream_t st);
-void launch_restrict_mut(const BLev &Bf, const BLev &Bc, hipStream_t st);
+// (mut: also the volume-weighted eddy viscosity)
+void launch_restrict_jobs(const BLev &Bf, const BLev &Bc, const RJob *jobs, int njobs, int mut, hipStream_t st);
 void launch_prolong(const BLev &Bf, const BLev &Bc, hipStream_t st);
 void launch_axpby(const BLev &B, double a, int fx, double b, int fy, int fout, hipStream_t st);
 void launch_pack(const Lay &L, const double *padded, double *natural, int ncomp, hipStream_t st);

@@ -915,7 +915,7 @@ __device__ void face_blocks(const Lay &L, const double *geo, const double *u, co
 }
 
 template <typename BT>
-__global__ __launch_bounds__(TPB) void k_blocks(BK b, int aw, double tau, int viscous) {
+__global__ __launch_bounds__(TPB) void k_blocks(BK b, int aw, double tau, int viscous, int copy_u0) {
     LevelDev dv;
     if (!take(b, blockIdx.y, dv)) return;
     const Lay L = dv.L;
@@ -929,6 +929,10 @@ __global__ __launch_bounds__(TPB) void k_blocks(BK b, int aw, double tau, int vi
     // the iteration's frozen dt* (read by the stages' residuals and sweeps)
     const double dt_s = local_dt(ph, cfl_of(ph, b.cyc[blockIdx.y]), geo, u, NS, s);
     dv.dts[s] = dt_s;
+    if (copy_u0) {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) dv.u0[k * NS + s] = u[k * NS + s];
+    }
     double c, diag;
     if (aw) {
         double e = ph.eta * dt_s;
@@ -1612,7 +1616,7 @@ __global__ __launch_bounds__(NT) void k_sgs4(BK bk, SweepArgs a) {
 // Section 3: restriction = volume-weighted agglomeration of 2x2 cells.
 // Each job restricts the fine-level combination a x (+ b y), formed per
 // fine cell as the elementwise update of the same name would form it.
-__global__ void k_restrict(BK bf, BK bc, RJob j0, RJob j1, int njobs) {
+__global__ void k_restrict(BK bf, BK bc, RJob j0, RJob j1, int njobs, int mut) {
     LevelDev df, dc;
     if (!take(bf, blockIdx.y, df) || !take(bc, blockIdx.y, dc)) return;
     const Lay Lf = df.L, Lc = dc.L;
@@ -1640,24 +1644,11 @@ __global__ void k_restrict(BK bf, BK bc, RJob j0, RJob j1, int njobs) {
             if (vc2) vc2[k * NSc + s] = r;
         }
     }
-}
-
-// eddy viscosity of the finer level agglomerated to the coarser one
-// (volume weighted), for the viscous flux of the coarse RANS operator
-__global__ void k_restrict_mut(BK bf, BK bc) {
-    LevelDev df, dc;
-    if (!take(bf, blockIdx.y, df) || !take(bc, blockIdx.y, dc)) return;
-    const Lay Lf = df.L, Lc = dc.L;
-    int s = blockIdx.x * blockDim.x + threadIdx.x;
-    int i, j;
-    if (!decode(Lc, s, i, j) || !interior(Lc, i, j)) return;
-    const int NSf = Lf.NS, NSc = Lc.NS;
-    int c00 = Lf.slot(2 * i, 2 * j), c10 = Lf.slot(2 * i + 1, 2 * j);
-    int c01 = Lf.slot(2 * i, 2 * j + 1), c11 = Lf.slot(2 * i + 1, 2 * j + 1);
-    const double *gf = df.geo + (size_t)G_VOL * NSf;
-    double w00 = df.mut[c00] * gf[c00], w10 = df.mut[c10] * gf[c10];
-    double w01 = df.mut[c01] * gf[c01], w11 = df.mut[c11] * gf[c11];
-    dc.mut[s] = (((w00 + w10) + w01) + w11) / dc.geo[(size_t)G_VOL * NSc + s];
+    if (mut) {
+        double w00 = df.mut[c00] * v00, w10 = df.mut[c10] * v10;
+        double w01 = df.mut[c01] * v01, w11 = df.mut[c11] * v11;
+        dc.mut[s] = (((w00 + w10) + w01) + w11) / vol;
+    }
 }
 
 // Section 3: bilinear prolongation of the coarse correction, weights
@@ -1863,11 +1854,12 @@ void launch_residual(const BLev &B, const ResArgs &a, hipStream_t st) {
         hipLaunchKernelGGL(k_residual<double>, cells_grid(B), dim3(CELL_TPB), 0, st, B.k, a);
 }
 
-void launch_blocks(const BLev &B, int aw, double tau, int viscous, int fp32, hipStream_t st) {
+void launch_blocks(const BLev &B, int aw, double tau, int viscous, int fp32, hipStream_t st, int copy_u0) {
     if (fp32)
-        hipLaunchKernelGGL(k_blocks<float>, cells_grid(B), dim3(CELL_TPB), 0, st, B.k, aw, tau, viscous);
+        hipLaunchKernelGGL(k_blocks<float>, cells_grid(B), dim3(CELL_TPB), 0, st, B.k, aw, tau, viscous, copy_u0);
     else
-        hipLaunchKernelGGL(k_blocks<double>, cells_grid(B), dim3(CELL_TPB), 0, st, B.k, aw, tau, viscous);
+        hipLaunchKernelGGL(k_blocks<double>, cells_grid(B), dim3(CELL_TPB), 0, st, B.k, aw, tau, viscous,
+                           copy_u0);
 }
 
 // Sweep configurations: four threads per row (k_sgs4 with NT threads, R
@@ -2039,16 +2031,12 @@ void launch_dinv(const BLev &B, int fp32, hipStream_t st) {
 
 void launch_restrict(const BLev &Bf, const BLev &Bc, int fin, int fout, int fout2, hipStream_t st) {
     const RJob j = {fin, 1.0, FLD_NONE, 0.0, fout, fout2};
-    launch_restrict_jobs(Bf, Bc, &j, 1, st);
+    launch_restrict_jobs(Bf, Bc, &j, 1, 0, st);
 }
 
-void launch_restrict_jobs(const BLev &Bf, const BLev &Bc, const RJob *jobs, int njobs, hipStream_t st) {
+void launch_restrict_jobs(const BLev &Bf, const BLev &Bc, const RJob *jobs, int njobs, int mut, hipStream_t st) {
     hipLaunchKernelGGL(k_restrict, cells_grid(Bc), dim3(CELL_TPB), 0, st, Bf.k, Bc.k, jobs[0],
-                       njobs > 1 ? jobs[1] : jobs[0], njobs > 1 ? 2 : 1);
-}
-
-void launch_restrict_mut(const BLev &Bf, const BLev &Bc, hipStream_t st) {
-    hipLaunchKernelGGL(k_restrict_mut, cells_grid(Bc), dim3(CELL_TPB), 0, st, Bf.k, Bc.k);
+                       njobs > 1 ? jobs[1] : jobs[0], njobs > 1 ? 2 : 1, mut);
 }
 
 void launch_prolong(const BLev &Bf, const BLev &Bc, hipStream_t st) {
