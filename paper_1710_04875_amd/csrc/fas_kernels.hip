@@ -942,20 +942,33 @@ __global__ __launch_bounds__(TPB) void k_blocks(BK b, int aw, double tau, int vi
         c = 1.0 / geo[G_VOL * NS + s];
         diag = tau;
     }
-    double Ap[16], Am[16], acc[16];
-    // pass 1: D = c (((Xp_e - Xm_w) + Ep_n) - Em_s) + diag I
+    // pass 1: D = c (((Xp_e - Xm_w) + Ep_n) - Em_s) + diag I; each face's
+    // other block is kept for its off-diagonal slot (pass 2)
+    double Ap[16], Am[16], acc[16], Bw[16], Be[16], Bs[16], Bn[16];
     face_blocks(L, geo, u, cq, mut, ph, viscous, s, s + NJ, G_SXI_X, G_SXI_Y, s + NJ, Ap, Am);
 #pragma unroll
-    for (int k = 0; k < 16; ++k) acc[k] = Ap[k];
+    for (int k = 0; k < 16; ++k) {
+        acc[k] = Ap[k];
+        Be[k] = Am[k];
+    }
     face_blocks(L, geo, u, cq, mut, ph, viscous, s - NJ, s, G_SXI_X, G_SXI_Y, s, Ap, Am);
 #pragma unroll
-    for (int k = 0; k < 16; ++k) acc[k] = acc[k] - Am[k];
+    for (int k = 0; k < 16; ++k) {
+        acc[k] = acc[k] - Am[k];
+        Bw[k] = Ap[k];
+    }
     face_blocks(L, geo, u, cq, mut, ph, viscous, s, s + NJ + 1, G_SETA_X, G_SETA_Y, s + NJ + 1, Ap, Am);
 #pragma unroll
-    for (int k = 0; k < 16; ++k) acc[k] = acc[k] + Ap[k];
+    for (int k = 0; k < 16; ++k) {
+        acc[k] = acc[k] + Ap[k];
+        Bn[k] = Am[k];
+    }
     face_blocks(L, geo, u, cq, mut, ph, viscous, s - NJ - 1, s, G_SETA_X, G_SETA_Y, s, Ap, Am);
 #pragma unroll
-    for (int k = 0; k < 16; ++k) acc[k] = acc[k] - Am[k];
+    for (int k = 0; k < 16; ++k) {
+        acc[k] = acc[k] - Am[k];
+        Bs[k] = Ap[k];
+    }
     double D[16], Di[16];
 #pragma unroll
     for (int k = 0; k < 16; ++k) {
@@ -992,19 +1005,12 @@ __global__ __launch_bounds__(TPB) void k_blocks(BK b, int aw, double tau, int vi
     for (int sl = 0; sl < 4; ++sl) {
         double B[16];
         if (has[sl]) {
-            if (sl == 0) {
-                face_blocks(L, geo, u, cq, mut, ph, viscous, s - NJ, s, G_SXI_X, G_SXI_Y, s, Ap, Am);
-                for (int k = 0; k < 16; ++k) B[k] = -(c * Ap[k]);
-            } else if (sl == 1) {
-                face_blocks(L, geo, u, cq, mut, ph, viscous, s, s + NJ, G_SXI_X, G_SXI_Y, s + NJ, Ap, Am);
-                for (int k = 0; k < 16; ++k) B[k] = c * Am[k];
-            } else if (sl == 2) {
-                face_blocks(L, geo, u, cq, mut, ph, viscous, s - NJ - 1, s, G_SETA_X, G_SETA_Y, s, Ap, Am);
-                for (int k = 0; k < 16; ++k) B[k] = -(c * Ap[k]);
-            } else {
-                face_blocks(L, geo, u, cq, mut, ph, viscous, s, s + NJ + 1, G_SETA_X, G_SETA_Y,
-                            s + NJ + 1, Ap, Am);
-                for (int k = 0; k < 16; ++k) B[k] = c * Am[k];
+#pragma unroll
+            for (int k = 0; k < 16; ++k) {
+                if (sl == 0) B[k] = -(c * Bw[k]);
+                else if (sl == 1) B[k] = c * Be[k];
+                else if (sl == 2) B[k] = -(c * Bs[k]);
+                else B[k] = c * Bn[k];
             }
         }
 #pragma unroll
