@@ -305,6 +305,40 @@ fas_status fas_lift_gradient_nodes(fas_state s, int32_t max_iter, double drop_or
                                    double *grad, double *dcl_dx, double *dcl_dy, double *res_hist,
                                    int32_t *n_iter);
 
+/*
+ * Discrete Fourier analysis of the smoothers (Section "Discrete Fourier
+ * Analysis"): amplification and smoothing factors of one AW or
+ * preconditioned ARK iteration for the Euler equations linearised about a
+ * constant state, JST scheme (the constant state's pressure sensor is zero:
+ * fourth differences only, eps4 = (|v_k| + a)/32) and the SGS preconditioner
+ * with the cutoff splitting, on a periodic Cartesian mesh; every pair of
+ * phase angles gives one 4x4 complex iteration matrix.
+ * cases: host array of n_cases descriptors.  Mesh: nx cells of width 1/nx
+ * in x, dy = ar dx; nx and ny (phase angles in y, normally nx ar) even and
+ * >= 2; phase angles 2 pi k / n, k = -n/2 + 1 .. n/2.  Steps: dt* = cstar
+ * dx / (|v_1| + a) and, with unsteady = 1, the BDF2 terms 3/(2 dt) with
+ * dt = c dx / (|v_1| + a).  The amplification factor is the largest
+ * spectral radius over all pairs, the smoothing factor over the pairs with
+ * max(|Theta_x|, |Theta_y|) >= pi/2.
+ * amp, smooth: device [n_cases]; radius: device, nullable, the spectral
+ * radius of every pair, case after case, Theta_x slowest (sum of nx ny
+ * values).  Enqueued on stream; returns once the results are written.
+ * Errors: FAS_EINVAL (sizes or parameters), FAS_EDEVICE.
+ */
+typedef struct {
+    double u[4];            /* linearisation state (rho, rho v1, rho v2, rho E), rho, p > 0 */
+    int32_t scheme;         /* FAS_AW3 ... FAS_PARK51 */
+    int32_t nx, ny;
+    int32_t unsteady;       /* 1: dual time stepping (BDF2 terms), 0: steady */
+    double cstar;           /* pseudo CFL c* (> 0) */
+    double d;               /* eigenvalue cutoff (>= 0) */
+    double eta;             /* W parameter (additive W schemes) */
+    double ar;              /* aspect ratio dy / dx (> 0) */
+    double c;               /* physical CFL (> 0 when unsteady) */
+} fas_dfa_case;
+fas_status fas_dfa(const fas_dfa_case *cases, int32_t n_cases, double *amp, double *smooth, double *radius,
+                   void *stream);
+
 /* Message of the last failing call on this thread (never NULL). */
 const char *fas_last_error(void);
 

@@ -3,6 +3,7 @@
 // time stepping, all enqueued on the caller's HIP stream.
 #include "fas.h"
 #include "fas_internal.h"
+#include "fas_dfa.h"
 
 #include <cmath>
 #include <cstdio>
@@ -1500,3 +1501,54 @@ extern "C" fas_status fas_batch_profile_read(fas_batch b, double *ms, int64_t *c
 }
 
 extern "C" const char *fas_last_error(void) { return g_err.c_str(); }
+
+// ------------------------------------------------- discrete Fourier analysis
+extern "C" fas_status fas_dfa(const fas_dfa_case *cases, int32_t n_cases, double *amp, double *smooth,
+                              double *radius, void *stream) {
+    if (!cases || n_cases <= 0 || !amp || !smooth) return fail(FAS_EINVAL, "bad argument");
+    std::vector<DfaCase> h(n_cases);
+    long long total = 0;
+    for (int k = 0; k < n_cases; ++k) {
+        const fas_dfa_case &c = cases[k];
+        const double rho = c.u[0];
+        const double p = (1.4 - 1.0) * (c.u[3] - 0.5 * (c.u[1] * c.u[1] + c.u[2] * c.u[2]) / rho);
+        if (c.scheme < 0 || c.scheme > FAS_PARK51 || c.nx < 2 || c.ny < 2 || (c.nx & 1) || (c.ny & 1) ||
+            !(rho > 0.0) || !(p > 0.0) || !(c.cstar > 0.0) || !(c.d >= 0.0) || !(c.ar > 0.0) ||
+            !(c.eta > 0.0) || (c.unsteady && !(c.c > 0.0)) || !std::isfinite(c.cstar) || !std::isfinite(c.c))
+            return fail(FAS_EINVAL, "bad Fourier analysis case");
+        const Scheme &sc = SCHEMES[c.scheme];
+        DfaCase &d = h[k];
+        std::memset(&d, 0, sizeof(d));
+        for (int q = 0; q < 4; ++q) d.u[q] = c.u[q];
+        for (int q = 0; q < sc.s; ++q) {
+            d.alpha[q] = sc.alpha[q];
+            d.beta[q] = sc.beta[q];
+        }
+        d.s = sc.s;
+        d.wform = sc.aw;
+        d.nx = c.nx;
+        d.ny = c.ny;
+        d.unsteady = c.unsteady ? 1 : 0;
+        d.cstar = c.cstar;
+        d.d = c.d;
+        d.eta = c.eta;
+        d.ar = c.ar;
+        d.c = c.c;
+        d.start = total;
+        total += (long long)c.nx * c.ny;
+    }
+    if (total > (1ll << 31)) return fail(FAS_EINVAL, "too many phase angles");
+    hipStream_t st = (hipStream_t)stream;
+    DfaCase *dc = nullptr;
+    HIPCHK(hipMalloc(&dc, h.size() * sizeof(DfaCase)));
+    fas_status out = FAS_OK;
+    if (hipMemcpyAsync(dc, h.data(), h.size() * sizeof(DfaCase), hipMemcpyHostToDevice, st) != hipSuccess) {
+        out = fail(FAS_EDEVICE, "descriptor upload failed");
+    } else {
+        launch_dfa(dc, n_cases, total, radius, amp, smooth, st);
+        if (hipGetLastError() != hipSuccess || hipStreamSynchronize(st) != hipSuccess)
+            out = fail(FAS_EDEVICE, "Fourier analysis kernel failed");
+    }
+    (void)hipFree(dc);
+    return out;
+}

@@ -5,6 +5,7 @@
 // section / equation it implements.  Layout: fas_internal.h.
 #include "fas_internal.h"
 #include "fas_geom.h"
+#include "fas_dfa.h"
 
 #include <cmath>
 #include <type_traits>
@@ -1807,6 +1808,303 @@ __global__ void k_batch_status(BatchCtl c, int n) {
     }
 }
 
+
+// ------------------------------------------------- discrete Fourier analysis
+// Section "Discrete Fourier Analysis": one thread per (case, pair of phase
+// angles) builds the 4x4 complex Fourier symbols of the linearised JST
+// operator (H_c, H_v) and of the SGS factors (L, D, U, flux splitting with
+// the cutoff of eq. "cutoff" in the ARK form, eqs. "d-l-u-matrices-J",
+// "d-unsteady-J", or the W form, eqs. "d-l-u-matrices-W", "d-unsteady-W"),
+// forms P = (D + L) D^-1 (D + U), applies the low-storage stages of Section 4
+// to the mode (U_0 = I, V_0 = P^-1 H_v, U_i = I - alpha_i dt* (P^-1 H_c
+// U_{i-1} + V_{i-1}), V_i = beta_{i+1} P^-1 H_v U_i + (1 - beta_{i+1})
+// V_{i-1}; G = U_s), and returns the spectral radius of G.  Per case the
+// largest radius over all pairs is the amplification factor, over the pairs
+// with max(|Theta_x|, |Theta_y|) >= pi/2 the smoothing factor.  Mesh and
+// steps: nx cells of width 1/nx, dy = AR dx, dt* = c* dx / (|v_1| + a),
+// dt = c dx / (|v_1| + a); eps2 = 0 and eps4 = (|v_k| + a) / 32 for the
+// constant state.
+struct cx {
+    double r, i;
+};
+__device__ inline cx cxm(double r, double i) { return cx{r, i}; }
+__device__ inline cx operator+(cx a, cx b) { return cx{a.r + b.r, a.i + b.i}; }
+__device__ inline cx operator-(cx a, cx b) { return cx{a.r - b.r, a.i - b.i}; }
+__device__ inline cx operator*(cx a, cx b) { return cx{a.r * b.r - a.i * b.i, a.r * b.i + a.i * b.r}; }
+__device__ inline cx operator*(double s, cx a) { return cx{s * a.r, s * a.i}; }
+__device__ inline cx conjx(cx a) { return cx{a.r, -a.i}; }
+__device__ inline double absx(cx a) { return hypot(a.r, a.i); }
+__device__ inline cx divx(cx a, cx b) {
+    // Smith's division
+    if (fabs(b.r) >= fabs(b.i)) {
+        const double q = b.i / b.r, den = b.r + b.i * q;
+        return cx{(a.r + a.i * q) / den, (a.i - a.r * q) / den};
+    }
+    const double q = b.r / b.i, den = b.i + b.r * q;
+    return cx{(a.r * q + a.i) / den, (a.i * q - a.r) / den};
+}
+__device__ inline cx sqrtx(cx a) {
+    const double m = absx(a);
+    if (m == 0.0) return cx{0.0, 0.0};
+    const double re = sqrt(0.5 * (m + fabs(a.r)));
+    if (a.r >= 0.0) return cx{re, a.i / (2.0 * re)};
+    return cx{fabs(a.i) / (2.0 * re), a.i >= 0.0 ? re : -re};
+}
+
+// C = A B (4x4, row-major)
+__device__ inline void cmul4(const cx *A, const cx *B, cx *C) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            cx acc = A[r * 4] * B[c];
+#pragma unroll
+            for (int k = 1; k < 4; ++k) acc = acc + A[r * 4 + k] * B[k * 4 + c];
+            C[r * 4 + c] = acc;
+        }
+}
+
+// X := A^-1 X for m right-hand columns (X row-major 4 x m), Gaussian
+// elimination with partial pivoting; A is destroyed
+template <int m>
+__device__ inline void csolve4(cx *A, cx *X) {
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        int pr = k;
+        double pm = absx(A[k * 4 + k]);
+#pragma unroll
+        for (int r = k + 1; r < 4; ++r) {
+            const double v = absx(A[r * 4 + k]);
+            if (v > pm) { pm = v; pr = r; }
+        }
+        if (pr != k) {
+#pragma unroll
+            for (int c = 0; c < 4; ++c) { cx t = A[k * 4 + c]; A[k * 4 + c] = A[pr * 4 + c]; A[pr * 4 + c] = t; }
+#pragma unroll
+            for (int c = 0; c < m; ++c) { cx t = X[k * m + c]; X[k * m + c] = X[pr * m + c]; X[pr * m + c] = t; }
+        }
+#pragma unroll
+        for (int r = k + 1; r < 4; ++r) {
+            const cx f = divx(A[r * 4 + k], A[k * 4 + k]);
+#pragma unroll
+            for (int c = k; c < 4; ++c) A[r * 4 + c] = A[r * 4 + c] - f * A[k * 4 + c];
+#pragma unroll
+            for (int c = 0; c < m; ++c) X[r * m + c] = X[r * m + c] - f * X[k * m + c];
+        }
+    }
+#pragma unroll
+    for (int k = 3; k >= 0; --k) {
+#pragma unroll
+        for (int c = 0; c < m; ++c) {
+            cx acc = X[k * m + c];
+#pragma unroll
+            for (int j = k + 1; j < 4; ++j) acc = acc - A[k * 4 + j] * X[j * m + c];
+            X[k * m + c] = divx(acc, A[k * 4 + k]);
+        }
+    }
+}
+
+// largest eigenvalue modulus of a 4x4 complex matrix (destroyed):
+// Householder reduction to Hessenberg form, then shifted QR steps (Givens
+// rotations, Wilkinson shift from the trailing 2x2 block, exceptional
+// shifts on stagnation) with deflation of negligible subdiagonals
+__device__ double spectral_radius4(cx *H) {
+    for (int k = 0; k < 2; ++k) {
+        double xn = 0.0;
+        for (int r = k + 1; r < 4; ++r) xn += H[r * 4 + k].r * H[r * 4 + k].r + H[r * 4 + k].i * H[r * 4 + k].i;
+        xn = sqrt(xn);
+        if (xn == 0.0) continue;
+        const cx x0 = H[(k + 1) * 4 + k];
+        const double a0 = absx(x0);
+        const cx ph = a0 > 0.0 ? cx{x0.r / a0, x0.i / a0} : cx{1.0, 0.0};
+        cx v[4] = {cx{0, 0}, cx{0, 0}, cx{0, 0}, cx{0, 0}};
+        for (int r = k + 1; r < 4; ++r) v[r] = H[r * 4 + k];
+        v[k + 1] = x0 + xn * ph;
+        double vn2 = 0.0;
+        for (int r = k + 1; r < 4; ++r) vn2 += v[r].r * v[r].r + v[r].i * v[r].i;
+        if (vn2 == 0.0) continue;
+        const double w = 2.0 / vn2;
+        for (int c = 0; c < 4; ++c) {           // H := (I - w v v^H) H
+            cx sacc = cx{0, 0};
+            for (int r = k + 1; r < 4; ++r) sacc = sacc + conjx(v[r]) * H[r * 4 + c];
+            for (int r = k + 1; r < 4; ++r) H[r * 4 + c] = H[r * 4 + c] - w * (v[r] * sacc);
+        }
+        for (int r = 0; r < 4; ++r) {           // H := H (I - w v v^H)
+            cx sacc = cx{0, 0};
+            for (int c = k + 1; c < 4; ++c) sacc = sacc + H[r * 4 + c] * v[c];
+            for (int c = k + 1; c < 4; ++c) H[r * 4 + c] = H[r * 4 + c] - w * (sacc * conjx(v[c]));
+        }
+    }
+    double rmax = 0.0;
+    int hi = 3, it = 0;
+    while (hi >= 0) {
+        if (hi == 0) {
+            rmax = fmax(rmax, absx(H[0]));
+            break;
+        }
+        int l = hi;
+        while (l > 0) {
+            const double sub = absx(H[l * 4 + l - 1]);
+            const double dd = absx(H[l * 4 + l]) + absx(H[(l - 1) * 4 + l - 1]);
+            if (sub <= 1e-17 * dd || sub < 1e-300) break;
+            --l;
+        }
+        if (l == hi) {
+            rmax = fmax(rmax, absx(H[hi * 4 + hi]));
+            --hi;
+            it = 0;
+            continue;
+        }
+        if (it >= 200) {                        // give up refining: take the block's diagonal
+            for (int k = l; k <= hi; ++k) rmax = fmax(rmax, absx(H[k * 4 + k]));
+            hi = l - 1;
+            it = 0;
+            continue;
+        }
+        const cx a = H[(hi - 1) * 4 + hi - 1], b = H[(hi - 1) * 4 + hi], c = H[hi * 4 + hi - 1],
+                 d = H[hi * 4 + hi];
+        cx mu;
+        if (it > 0 && it % 11 == 0) {
+            mu = d + cx{absx(c), 0.0};
+        } else {
+            const cx half = 0.5 * (a - d);
+            const cx disc = sqrtx(half * half + b * c);
+            const cx m1 = d + half + disc, m2 = d + half - disc;   // (a + d)/2 +- disc
+            mu = absx(m1 - d) <= absx(m2 - d) ? m1 : m2;
+        }
+        for (int k = l; k <= hi; ++k) H[k * 4 + k] = H[k * 4 + k] - mu;
+        double cs[3];
+        cx sn[3];
+        for (int k = l; k < hi; ++k) {
+            const cx x = H[k * 4 + k], y = H[(k + 1) * 4 + k];
+            const double ax = absx(x), ay = absx(y), rr = hypot(ax, ay);
+            double cc;
+            cx ss;
+            if (rr == 0.0) { cc = 1.0; ss = cx{0, 0}; }
+            else if (ax == 0.0) { cc = 0.0; ss = cx{y.r / ay, -y.i / ay}; }
+            else { cc = ax / rr; ss = (1.0 / rr) * (cx{x.r / ax, x.i / ax} * conjx(y)); }
+            cs[k - l] = cc;
+            sn[k - l] = ss;
+            for (int j = k; j <= hi; ++j) {
+                const cx hk = H[k * 4 + j], hk1 = H[(k + 1) * 4 + j];
+                H[k * 4 + j] = cc * hk + ss * hk1;
+                H[(k + 1) * 4 + j] = cc * hk1 - conjx(ss) * hk;
+            }
+        }
+        for (int k = l; k < hi; ++k) {
+            const double cc = cs[k - l];
+            const cx ss = sn[k - l];
+            const int rmx = k + 2 <= hi ? k + 2 : hi;
+            for (int i = l; i <= rmx; ++i) {
+                const cx hk = H[i * 4 + k], hk1 = H[i * 4 + k + 1];
+                H[i * 4 + k] = cc * hk + conjx(ss) * hk1;
+                H[i * 4 + k + 1] = cc * hk1 - ss * hk;
+            }
+        }
+        for (int k = l; k <= hi; ++k) H[k * 4 + k] = H[k * 4 + k] + mu;
+        ++it;
+    }
+    return rmax;
+}
+
+__global__ __launch_bounds__(64) void k_dfa_clear(unsigned long long *amp, unsigned long long *smooth, int n) {
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c < n) {
+        amp[c] = 0ull;
+        smooth[c] = 0ull;
+    }
+}
+
+__global__ __launch_bounds__(64) void k_dfa(const DfaCase *cases, int n_cases, long long total, double *rad,
+                                            unsigned long long *amp, unsigned long long *smooth) {
+    const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= total) return;
+    int ci = 0;
+    while (ci + 1 < n_cases && cases[ci + 1].start <= t) ++ci;
+    const DfaCase P = cases[ci];
+    const long long m = t - P.start;
+    const int kx = (int)(m / P.ny), ky = (int)(m - (long long)kx * P.ny);
+    const double tx = 2.0 * M_PI * (double)(kx - P.nx / 2 + 1) / (double)P.nx;
+    const double ty = 2.0 * M_PI * (double)(ky - P.ny / 2 + 1) / (double)P.ny;
+    // state, steps
+    const double rho = P.u[0], v1 = P.u[1] / rho, v2 = P.u[2] / rho;
+    const double a = sqrt(GAM * pres(P.u[0], P.u[1], P.u[2], P.u[3]) / rho);
+    const double dx = 1.0 / (double)P.nx, dy = P.ar * dx, vol = dx * dy;
+    const double base = dx / (fabs(v1) + a);
+    const double dts = P.cstar * base, dt = P.c * base;
+    // split Jacobians of the unit normals (1, 0) and (0, 1)
+    double Ap[16], Am[16], Bp[16], Bm[16];
+    split_face(P.u, P.u, 1.0, 0.0, P.d, 0.0, 0, Ap, Am);
+    split_face(P.u, P.u, 0.0, 1.0, P.d, 0.0, 0, Bp, Bm);
+    const cx ex = cx{cos(tx), sin(tx)}, ey = cx{cos(ty), sin(ty)};
+    const cx exi = conjx(ex), eyi = conjx(ey);
+    const cx dex = ex - exi, dey = ey - eyi;             // E - E^-1
+    const double fx = (6.0 - 8.0 * cos(tx)) + 2.0 * cos(2.0 * tx);   // fourth difference symbols
+    const double fy = (6.0 - 8.0 * cos(ty)) + 2.0 * cos(2.0 * ty);
+    const double e4x = (fabs(v1) + a) / 32.0, e4y = (fabs(v2) + a) / 32.0;
+    const double hv = (e4x * fx * dy + e4y * fy * dx) / vol;
+    const double f = P.wform ? P.eta * dts : 1.0;
+    const double diag = P.wform ? 1.0 + (P.unsteady ? 1.5 * P.eta * dts / dt : 0.0) : (P.unsteady ? 1.5 / dt : 0.0);
+    cx DL[16], X[16], RHS[32];
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            const int k = r * 4 + c;
+            const double Ak = Ap[k] + Am[k], Bk = Bp[k] + Bm[k];
+            const double dk = (f / vol) * (dy * (Ap[k] - Am[k]) + dx * (Bp[k] - Bm[k])) + (r == c ? diag : 0.0);
+            const cx lk = (-(f / vol)) * (dy * Ap[k] * exi + dx * Bp[k] * eyi);
+            const cx uk = (f / vol) * (dy * Am[k] * ex + dx * Bm[k] * ey);
+            DL[k] = cx{dk, 0.0} + lk;                    // D + L
+            X[k] = cx{dk, 0.0} + uk;                     // D + U, becomes D^-1 (D + U)
+            // H_c and H_v, side by side as 8 right-hand columns
+            cx hc = (1.0 / (2.0 * vol)) * (Ak * dy * dex + Bk * dx * dey);
+            if (P.unsteady && r == c) hc = hc + cx{1.5 / dt, 0.0};
+            double Mk = (r == c) ? 1.0 : 0.0;
+            if (r == 3 && c == 0) Mk = -(GAM - 1.0) * (v1 * v1 + v2 * v2) / 2.0;
+            if (r == 3 && c == 3) Mk = GAM;
+            RHS[r * 8 + c] = hc;
+            RHS[r * 8 + 4 + c] = cx{Mk * hv, 0.0};
+        }
+    {
+        cx Dm[16];
+#pragma unroll
+        for (int k = 0; k < 16; ++k) Dm[k] = cx{(f / vol) * (dy * (Ap[k] - Am[k]) + dx * (Bp[k] - Bm[k])) +
+                                                   ((k % 5 == 0) ? diag : 0.0), 0.0};
+        csolve4<4>(Dm, X);
+    }
+    cx Pm[16];
+    cmul4(DL, X, Pm);
+    csolve4<8>(Pm, RHS);                                 // [P^-1 H_c | P^-1 H_v]
+    cx Hc[16], Hv[16], Ui[16], V[16], T[16];
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            Hc[r * 4 + c] = RHS[r * 8 + c];
+            Hv[r * 4 + c] = RHS[r * 8 + 4 + c];
+            Ui[r * 4 + c] = cx{r == c ? 1.0 : 0.0, 0.0};
+            V[r * 4 + c] = RHS[r * 8 + 4 + c];
+        }
+    for (int st = 0; st < P.s; ++st) {
+        cmul4(Hc, Ui, T);
+        const double al = P.alpha[st] * dts;
+#pragma unroll
+        for (int k = 0; k < 16; ++k) Ui[k] = cx{(k % 5 == 0) ? 1.0 : 0.0, 0.0} - al * (T[k] + V[k]);
+        if (st + 1 < P.s) {
+            cmul4(Hv, Ui, T);
+            const double b = P.beta[st + 1];
+#pragma unroll
+            for (int k = 0; k < 16; ++k) V[k] = b * T[k] + (1.0 - b) * V[k];
+        }
+    }
+    const double r = spectral_radius4(Ui);
+    if (rad) rad[t] = r;
+    const unsigned long long bits = __builtin_bit_cast(unsigned long long, r);
+    atomicMax(&amp[ci], bits);
+    if (fmax(fabs(tx), fabs(ty)) >= 0.5 * M_PI - 1e-12) atomicMax(&smooth[ci], bits);
+}
+
 }  // namespace
 
 // =================================================================== launchers
@@ -2082,6 +2380,18 @@ void launch_batch_init(const BatchCtl &c, int n, hipStream_t st) {
 
 void launch_batch_status(const BatchCtl &c, int n, hipStream_t st) {
     hipLaunchKernelGGL(k_batch_status, dim3(nblocks(n, 64)), dim3(64), 0, st, c, n);
+}
+
+// Non-negative doubles order like their bit patterns as unsigned integers,
+// so the per-case maxima are reduced with an integer atomic maximum.
+void launch_dfa(const DfaCase *d_cases, int n_cases, long long total, double *rad, double *amp, double *smooth,
+                hipStream_t st) {
+    unsigned long long *ua = reinterpret_cast<unsigned long long *>(amp);
+    unsigned long long *us = reinterpret_cast<unsigned long long *>(smooth);
+    hipLaunchKernelGGL(k_dfa_clear, dim3(nblocks(n_cases, 64)), dim3(64), 0, st, ua, us, n_cases);
+    if (total > 0)
+        hipLaunchKernelGGL(k_dfa, dim3((unsigned)((total + 63) / 64)), dim3(64), 0, st, d_cases, n_cases, total, rad,
+                           ua, us);
 }
 
 }  // namespace fas

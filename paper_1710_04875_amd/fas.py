@@ -82,7 +82,7 @@ EXPORTS = [
     "fas_sweep_config_count", "fas_sweep_config_info", "fas_batch_profile",
     "fas_batch_profile_read", "fas_forces", "fas_vjp", "fas_param_partials",
     "fas_sgs_apply_transpose", "fas_adjoint_solve", "fas_lift_gradient", "fas_vjp_nodes",
-    "fas_lift_gradient_nodes", "fas_set_motion",
+    "fas_lift_gradient_nodes", "fas_set_motion", "fas_dfa",
     "fas_last_error",
 ]
 PROF_CLASSES = ("sweep", "residual", "blocks")
@@ -135,6 +135,7 @@ def load(path: str = LIB_PATH):
         "fas_vjp_nodes": (i32, [vp, vp, vp, vp]),
         "fas_lift_gradient_nodes": (i32, [vp, i32, f64, dp, dp, vp, vp, dp, ip]),
         "fas_set_motion": (i32, [vp, f64, f64, f64, f64]),
+        "fas_dfa": (i32, [ctypes.POINTER(_DfaCase), i32, vp, vp, vp, vp]),
         "fas_last_error": (ctypes.c_char_p, []),
     }
     for name, (res, args) in sig.items():
@@ -390,6 +391,58 @@ def torch_dtype():
 
 
 SWEEP_FOUR_THREADS, SWEEP_ONE_THREAD, SWEEP_BANDED = 0, 1, 2
+
+
+class _DfaCase(ctypes.Structure):
+    _fields_ = [("u", ctypes.c_double * 4), ("scheme", ctypes.c_int32), ("nx", ctypes.c_int32),
+                ("ny", ctypes.c_int32), ("unsteady", ctypes.c_int32), ("cstar", ctypes.c_double),
+                ("d", ctypes.c_double), ("eta", ctypes.c_double), ("ar", ctypes.c_double),
+                ("c", ctypes.c_double)]
+
+
+@dataclass
+class DfaCase:
+    """Mirror of fas_dfa_case: one Fourier analysis of a smoother (the
+    linearisation state at Mach 0.8, alpha 0 by default; ny defaults to
+    nx * ar)."""
+    u: tuple = (1.0, 1.0, 0.0, 3.290)
+    scheme: int = FAS_AW3
+    cstar: float = 3.0
+    d: float = 0.5
+    eta: float = 0.8
+    ar: float = 1.0
+    c: float = 200.0
+    nx: int = 8
+    ny: int = 0
+    unsteady: int = 1
+
+    def c_struct(self) -> _DfaCase:
+        x = _DfaCase()
+        for k in range(4):
+            x.u[k] = float(self.u[k])
+        x.scheme, x.nx = int(self.scheme), int(self.nx)
+        x.ny = int(self.ny) if self.ny else int(round(self.nx * self.ar))
+        x.unsteady = int(self.unsteady)
+        x.cstar, x.d, x.eta, x.ar, x.c = float(self.cstar), float(self.d), float(self.eta), float(self.ar), float(self.c)
+        return x
+
+
+def dfa(cases, with_radius=False):
+    """Amplification and smoothing factors (float64 tensors on the current
+    device, one per case) and, on request, the spectral radius of every pair
+    of phase angles (cases concatenated, Theta_x slowest)."""
+    import torch
+    lib = load()
+    arr = (_DfaCase * len(cases))(*[c.c_struct() for c in cases])
+    dev = torch.device("cuda", torch.cuda.current_device())
+    amp = torch.empty(len(cases), dtype=torch.float64, device=dev)
+    smooth = torch.empty_like(amp)
+    total = sum(int(a.nx) * int(a.ny) for a in arr)
+    rad = torch.empty(total, dtype=torch.float64, device=dev) if with_radius else None
+    _check(lib.fas_dfa(arr, len(cases), ctypes.c_void_p(amp.data_ptr()), ctypes.c_void_p(smooth.data_ptr()),
+                       ctypes.c_void_p(rad.data_ptr() if rad is not None else 0),
+                       ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)))
+    return (amp, smooth, rad) if with_radius else (amp, smooth)
 
 
 def sweep_config_count():
