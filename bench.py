@@ -219,6 +219,67 @@ def traffic_summary(fetch_dir, write_dir, calf_dir, calw_dir):
     print("mean over the levels: %.4g bytes per launch" % out["bytes_per_launch"])
 
 
+# FP64 operations per pair of phase angles of the Fourier analysis that do
+# not depend on the data (a complex multiply-add is 8, a division 11): the
+# solve D^-1 (D + U) (786), the product P = (D + L) X (512), the solve with
+# eight right-hand columns (1346), per stage a product and update (608,
+# s stages and s - 1 blends), the Hessenberg reduction (400); the shifted QR
+# iterations come on top, so this is a lower bound
+def dfa_flops_per_pair(stages):
+    return 786 + 512 + 1346 + 608 * (2 * stages - 1) + 400
+
+
+def dfa_section(fas, torch):
+    """Discrete Fourier analysis over the paper's table grid: schemes ARK3J,
+    AW3, AW51, AW52, AW5J x cutoffs d = 0, 0.1, 0.25, 0.5, 1 x aspect ratios
+    1, 100, 10000 (8 x 8 AR phase angles) x c* = 3, 30, 1e3, 1e6, Mach 0.8,
+    alpha 0, c = 200: one fas_dfa call, timed with HIP events on the
+    library's stream; the printed amplification factors at aspect ratio 1 as
+    a check; the oracle on a bounded sample as the CPU baseline."""
+    import numpy as np
+    from oracle import dfa as odfa
+    stages = {fas.FAS_PARK3J: 3, fas.FAS_AW3: 3, fas.FAS_AW51: 5, fas.FAS_AW52: 5, fas.FAS_AW5J: 5}
+    cases = [fas.DfaCase(scheme=sc, cstar=cs, d=d, ar=ar) for sc in stages for d in (0.0, 0.1, 0.25, 0.5, 1.0)
+             for ar in (1.0, 100.0, 10000.0) for cs in (3.0, 30.0, 1e3, 1e6)]
+    pairs = [c.nx * int(round(c.nx * c.ar)) for c in cases]
+    fas.dfa(cases[:2])
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    amp, smooth = fas.dfa(cases)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    flops = float(sum(p * dfa_flops_per_pair(stages[c.scheme]) for p, c in zip(pairs, cases)))
+    ach = flops / (ms * 1e-3) / 1e12
+    # the printed amplification factors (aspect ratio 1, alpha 0)
+    printed = [(fas.FAS_PARK3J, 1, 0.0, 0.8, 0.9974), (fas.FAS_PARK3J, 14, 0.5, 0.8, 0.9722),
+               (fas.FAS_AW3, 3, 0.5, 0.8, 0.9841), (fas.FAS_AW3, 7, 1.0, 0.8, 0.9765),
+               (fas.FAS_AW51, 4, 0.5, 0.5, 0.9776), (fas.FAS_AW5J, 3, 0.1, 0.5, 0.9815)]
+    pa, _ = fas.dfa([fas.DfaCase(scheme=sc, cstar=cs, d=d, eta=eta) for sc, cs, d, eta, _ in printed])
+    dev = float(np.max(np.abs(pa.cpu().numpy() - np.array([r[-1] for r in printed]))))
+    # CPU baseline: the oracle on the aspect-ratio-100 cases of the first scheme
+    sample = [c for c in cases if c.ar == 100.0][:20]
+    t0 = time.perf_counter()
+    npairs = 0
+    for c in sample:
+        o = odfa.DfaCase(u=c.u, scheme=c.scheme, cstar=c.cstar, d=c.d, eta=c.eta, ar=c.ar, c=c.c)
+        npairs += odfa.factors(o)[2].size
+        if time.perf_counter() - t0 > 15.0:
+            break
+    tc = time.perf_counter() - t0
+    return {"cases": len(cases), "pairs": int(sum(pairs)), "ms": round(ms, 3),
+            "pairs_per_s": round(sum(pairs) / (ms * 1e-3), 1),
+            "max_dev_printed_amplification": dev,
+            "roofline": {"bound": "alu", "achieved": round(ach, 3), "peak": 78.6, "unit": "TFLOP/s",
+                         "frac": round(ach / 78.6, 5), "traffic": None,
+                         "kernel": "k_dfa (one thread per pair of phase angles)",
+                         "flops": "lower bound: %d FP64 operations per pair for 3 stages, %d for 5" % (
+                             dfa_flops_per_pair(3), dfa_flops_per_pair(5))},
+            "cpu_baseline": {"value": round(npairs / tc, 1), "unit": "pairs/s", "cores": 1, "kind": "oracle",
+                             "sample": "%d pairs of the aspect-ratio-100 cases (numpy, vectorised)" % npairs}}
+
+
 def batch_params(fas, c, fp32):
     return fas.Params(model=fas.FAS_RANS_BL, scheme=fas.FAS_AW3, mach=c.mach, alpha_deg=c.alpha_deg,
                       reynolds=c.reynolds, n_levels=3, cycle_gamma=1, nu1=1, eta=0.5, d_cut=0.5,
@@ -416,6 +477,8 @@ def main():
     ap.add_argument("--inner-cap", type=int, default=300)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only copy a 256 MiB buffer 5 times (HBM counter calibration)")
+    ap.add_argument("--no-dfa", action="store_true", help="skip the Fourier analysis section")
+    ap.add_argument("--dfa-only", action="store_true", help="run only the Fourier analysis section")
     ap.add_argument("--traffic-summary", nargs=4, metavar=("FETCH_DIR", "WRITE_DIR", "CALF_DIR", "CALW_DIR"),
                     help="summarise four rocprofv3 --pmc output folders into the sweep's traffic record")
     args = ap.parse_args()
@@ -439,6 +502,9 @@ def main():
     from paper_1710_04875_amd import fas
     fas.load()
     assert torch.cuda.is_available(), "bench.py needs a GPU"
+    if args.dfa_only:
+        print(json.dumps({"dfa": dfa_section(fas, torch)}), flush=True)
+        return
     run_gpu.no_drop = args.no_drop
     log("fp64 preconditioner run")
     r64 = run_gpu(fas, torch, args.steps, args.warmup, False, args.drop_cap)
@@ -497,6 +563,9 @@ def main():
                                                args.full_loop)
     if not args.no_unsteady:
         line["unsteady_pitching"] = unsteady_section(fas, torch, args.inner_cap)
+    if not args.no_dfa:
+        log("discrete Fourier analysis")
+        line["dfa"] = dfa_section(fas, torch)
     if not args.no_cpu:
         log("cpu baseline (oracle)")
         line["cpu_baseline"] = cpu_baseline()
