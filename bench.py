@@ -226,30 +226,41 @@ def traffic_summary(fetch_dir, write_dir, calf_dir, calw_dir):
 # s stages and s - 1 blends), the Hessenberg reduction (400); the shifted QR
 # iterations come on top, so this is a lower bound
 def dfa_flops_per_pair(stages):
-    return 786 + 512 + 1346 + 608 * (2 * stages - 1) + 400
+    """FP64 operations per pair that do not depend on the data: D, D + L and
+    D + U (484), D^-1 (D + U) with the real D (262), (D + L) D^-1 (D + U)
+    (480), the right-hand sides H_c and H_v (180), the 8-column complex
+    solve (1132), the Householder reduction to Hessenberg form (720) and per
+    product of the stage recursion 580 (2 s - 1 of them).  The split
+    Jacobians, the trigonometric functions and the QR sweeps are left out,
+    so the count is a lower bound."""
+    return 484 + 262 + 480 + 180 + 1132 + 720 + 580 * (2 * stages - 1)
 
 
 def dfa_section(fas, torch):
     """Discrete Fourier analysis over the paper's table grid: schemes ARK3J,
     AW3, AW51, AW52, AW5J x cutoffs d = 0, 0.1, 0.25, 0.5, 1 x aspect ratios
     1, 100, 10000 (8 x 8 AR phase angles) x c* = 3, 30, 1e3, 1e6, Mach 0.8,
-    alpha 0, c = 200: one fas_dfa call, timed with HIP events on the
-    library's stream; the printed amplification factors at aspect ratio 1 as
-    a check; the oracle on a bounded sample as the CPU baseline."""
+    alpha 0, c = 200: one fas_dfa call over all of it, timed with HIP events
+    on the library's stream (median of three after a warm-up call); the
+    printed amplification factors at aspect ratio 1 as a check; the oracle on
+    a bounded sample as the CPU baseline."""
     import numpy as np
     from oracle import dfa as odfa
     stages = {fas.FAS_PARK3J: 3, fas.FAS_AW3: 3, fas.FAS_AW51: 5, fas.FAS_AW52: 5, fas.FAS_AW5J: 5}
     cases = [fas.DfaCase(scheme=sc, cstar=cs, d=d, ar=ar) for sc in stages for d in (0.0, 0.1, 0.25, 0.5, 1.0)
              for ar in (1.0, 100.0, 10000.0) for cs in (3.0, 30.0, 1e3, 1e6)]
     pairs = [c.nx * int(round(c.nx * c.ar)) for c in cases]
-    fas.dfa(cases[:2])
+    fas.dfa(cases)
     torch.cuda.synchronize()
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record()
-    amp, smooth = fas.dfa(cases)
-    e1.record()
-    torch.cuda.synchronize()
-    ms = e0.elapsed_time(e1)
+    runs = []
+    for _ in range(3):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        amp, smooth = fas.dfa(cases)
+        e1.record()
+        torch.cuda.synchronize()
+        runs.append(e0.elapsed_time(e1))
+    ms = sorted(runs)[1]
     flops = float(sum(p * dfa_flops_per_pair(stages[c.scheme]) for p, c in zip(pairs, cases)))
     ach = flops / (ms * 1e-3) / 1e12
     # the printed amplification factors (aspect ratio 1, alpha 0)

@@ -1827,24 +1827,19 @@ __global__ void k_batch_status(BatchCtl c, int n) {
 struct cx {
     double r, i;
 };
-__device__ inline cx cxm(double r, double i) { return cx{r, i}; }
 __device__ inline cx operator+(cx a, cx b) { return cx{a.r + b.r, a.i + b.i}; }
 __device__ inline cx operator-(cx a, cx b) { return cx{a.r - b.r, a.i - b.i}; }
 __device__ inline cx operator*(cx a, cx b) { return cx{a.r * b.r - a.i * b.i, a.r * b.i + a.i * b.r}; }
 __device__ inline cx operator*(double s, cx a) { return cx{s * a.r, s * a.i}; }
 __device__ inline cx conjx(cx a) { return cx{a.r, -a.i}; }
-__device__ inline double absx(cx a) { return hypot(a.r, a.i); }
-__device__ inline cx divx(cx a, cx b) {
-    // Smith's division
-    if (fabs(b.r) >= fabs(b.i)) {
-        const double q = b.i / b.r, den = b.r + b.i * q;
-        return cx{(a.r + a.i * q) / den, (a.i - a.r * q) / den};
-    }
-    const double q = b.r / b.i, den = b.i + b.r * q;
-    return cx{(a.r * q + a.i) / den, (a.i * q - a.r) / den};
+__device__ inline double norm2x(cx a) { return a.r * a.r + a.i * a.i; }
+__device__ inline double cabs1(cx a) { return fabs(a.r) + fabs(a.i); }   // |Re| + |Im|, for comparisons
+__device__ inline cx recipx(cx a) {
+    const double q = 1.0 / norm2x(a);
+    return cx{a.r * q, -a.i * q};
 }
 __device__ inline cx sqrtx(cx a) {
-    const double m = absx(a);
+    const double m = sqrt(norm2x(a));
     if (m == 0.0) return cx{0.0, 0.0};
     const double re = sqrt(0.5 * (m + fabs(a.r)));
     if (a.r >= 0.0) return cx{re, a.i / (2.0 * re)};
@@ -1865,29 +1860,30 @@ __device__ inline void cmul4(const cx *A, const cx *B, cx *C) {
 }
 
 // X := A^-1 X for m right-hand columns (X row-major 4 x m), Gaussian
-// elimination with partial pivoting; A is destroyed
+// elimination with partial pivoting; A is destroyed.  One reciprocal per
+// pivot serves the elimination factors and the back substitution.
 template <int m>
 __device__ inline void csolve4(cx *A, cx *X) {
+    cx ip[4];
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
-        int pr = k;
-        double pm = absx(A[k * 4 + k]);
+        // partial pivoting: the larger of rows k and r moves to row k, for
+        // each r below (static indices, so everything stays in registers)
 #pragma unroll
         for (int r = k + 1; r < 4; ++r) {
-            const double v = absx(A[r * 4 + k]);
-            if (v > pm) { pm = v; pr = r; }
-        }
-        if (pr != k) {
+            if (cabs1(A[r * 4 + k]) > cabs1(A[k * 4 + k])) {
 #pragma unroll
-            for (int c = 0; c < 4; ++c) { cx t = A[k * 4 + c]; A[k * 4 + c] = A[pr * 4 + c]; A[pr * 4 + c] = t; }
+                for (int c = 0; c < 4; ++c) { cx t = A[k * 4 + c]; A[k * 4 + c] = A[r * 4 + c]; A[r * 4 + c] = t; }
 #pragma unroll
-            for (int c = 0; c < m; ++c) { cx t = X[k * m + c]; X[k * m + c] = X[pr * m + c]; X[pr * m + c] = t; }
+                for (int c = 0; c < m; ++c) { cx t = X[k * m + c]; X[k * m + c] = X[r * m + c]; X[r * m + c] = t; }
+            }
         }
+        ip[k] = recipx(A[k * 4 + k]);
 #pragma unroll
         for (int r = k + 1; r < 4; ++r) {
-            const cx f = divx(A[r * 4 + k], A[k * 4 + k]);
+            const cx f = A[r * 4 + k] * ip[k];
 #pragma unroll
-            for (int c = k; c < 4; ++c) A[r * 4 + c] = A[r * 4 + c] - f * A[k * 4 + c];
+            for (int c = k + 1; c < 4; ++c) A[r * 4 + c] = A[r * 4 + c] - f * A[k * 4 + c];
 #pragma unroll
             for (int c = 0; c < m; ++c) X[r * m + c] = X[r * m + c] - f * X[k * m + c];
         }
@@ -1899,114 +1895,179 @@ __device__ inline void csolve4(cx *A, cx *X) {
             cx acc = X[k * m + c];
 #pragma unroll
             for (int j = k + 1; j < 4; ++j) acc = acc - A[k * 4 + j] * X[j * m + c];
-            X[k * m + c] = divx(acc, A[k * 4 + k]);
+            X[k * m + c] = acc * ip[k];
         }
     }
 }
 
-// largest eigenvalue modulus of a 4x4 complex matrix (destroyed):
-// Householder reduction to Hessenberg form, then shifted QR steps (Givens
-// rotations, Wilkinson shift from the trailing 2x2 block, exceptional
-// shifts on stagnation) with deflation of negligible subdiagonals
-__device__ double spectral_radius4(cx *H) {
+// X := A^-1 X for a real 4x4 A and 4 complex right-hand columns (X
+// row-major), Gaussian elimination with partial pivoting; A is destroyed
+__device__ inline void rsolve4(double *A, cx *X) {
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+#pragma unroll
+        for (int r = k + 1; r < 4; ++r) {
+            if (fabs(A[r * 4 + k]) > fabs(A[k * 4 + k])) {
+#pragma unroll
+                for (int c = 0; c < 4; ++c) { double t = A[k * 4 + c]; A[k * 4 + c] = A[r * 4 + c]; A[r * 4 + c] = t; }
+#pragma unroll
+                for (int c = 0; c < 4; ++c) { cx t = X[k * 4 + c]; X[k * 4 + c] = X[r * 4 + c]; X[r * 4 + c] = t; }
+            }
+        }
+        const double ip = 1.0 / A[k * 4 + k];
+#pragma unroll
+        for (int r = k + 1; r < 4; ++r) {
+            const double f = A[r * 4 + k] * ip;
+#pragma unroll
+            for (int c = k; c < 4; ++c) A[r * 4 + c] = A[r * 4 + c] - f * A[k * 4 + c];
+#pragma unroll
+            for (int c = 0; c < 4; ++c) X[r * 4 + c] = X[r * 4 + c] - f * X[k * 4 + c];
+        }
+    }
+#pragma unroll
+    for (int k = 3; k >= 0; --k) {
+        const double ip = 1.0 / A[k * 4 + k];
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            cx acc = X[k * 4 + c];
+#pragma unroll
+            for (int j = k + 1; j < 4; ++j) acc = acc - A[k * 4 + j] * X[j * 4 + c];
+            X[k * 4 + c] = ip * acc;
+        }
+    }
+}
+
+// flux Jacobian dF.n/dU of the state U for the unit normal (nx, ny),
+// row-major (Section 2, Euler fluxes)
+__device__ inline void flux_jacobian4(const double U[4], double nx, double ny, double A[16]) {
+    const double uu = U[1] / U[0], vv = U[2] / U[0];
+    const double p = pres(U[0], U[1], U[2], U[3]);
+    const double H = (U[3] + p) / U[0], g1 = GAM - 1.0;
+    const double phi = 0.5 * g1 * (uu * uu + vv * vv), V = uu * nx + vv * ny;
+    A[0] = 0.0; A[1] = nx; A[2] = ny; A[3] = 0.0;
+    A[4] = phi * nx - uu * V; A[5] = V - (GAM - 2.0) * uu * nx; A[6] = uu * ny - g1 * vv * nx; A[7] = g1 * nx;
+    A[8] = phi * ny - vv * V; A[9] = vv * nx - g1 * uu * ny; A[10] = V - (GAM - 2.0) * vv * ny; A[11] = g1 * ny;
+    A[12] = V * (phi - H); A[13] = H * nx - g1 * uu * V; A[14] = H * ny - g1 * vv * V; A[15] = GAM * V;
+}
+
+// largest eigenvalue modulus of a 4x4 complex matrix (destroyed): the
+// matrix is scaled to unit size, reduced to Hessenberg form by Householder
+// reflections, then shifted QR sweeps over the whole matrix (Givens
+// rotations) run until every subdiagonal entry is negligible against its
+// diagonal neighbours (unit roundoff, |Re| + |Im| moduli).  Negligible
+// subdiagonals are set to zero, so converged blocks decouple (their
+// rotations are the identity); the Wilkinson shift comes from the lowest
+// unconverged 2x2 block, with an exceptional shift on stagnation.  Every
+// index is static, so the matrix stays in registers.
+__device__ double spectral_radius4(cx (&H)[16]) {
+    // scale to unit size: every modulus below is a plain square root
+    double s = 0.0;
+#pragma unroll
+    for (int k = 0; k < 16; ++k) s = fmax(s, cabs1(H[k]));
+    if (s == 0.0) return 0.0;
+    const double is = 1.0 / s;
+#pragma unroll
+    for (int k = 0; k < 16; ++k) H[k] = is * H[k];
+#pragma unroll
     for (int k = 0; k < 2; ++k) {
         double xn = 0.0;
-        for (int r = k + 1; r < 4; ++r) xn += H[r * 4 + k].r * H[r * 4 + k].r + H[r * 4 + k].i * H[r * 4 + k].i;
+#pragma unroll
+        for (int r = k + 1; r < 4; ++r) xn += norm2x(H[r * 4 + k]);
         xn = sqrt(xn);
-        if (xn == 0.0) continue;
         const cx x0 = H[(k + 1) * 4 + k];
-        const double a0 = absx(x0);
-        const cx ph = a0 > 0.0 ? cx{x0.r / a0, x0.i / a0} : cx{1.0, 0.0};
+        const double a0 = sqrt(norm2x(x0));
+        const cx ph = a0 > 0.0 ? (1.0 / a0) * x0 : cx{1.0, 0.0};
         cx v[4] = {cx{0, 0}, cx{0, 0}, cx{0, 0}, cx{0, 0}};
+#pragma unroll
         for (int r = k + 1; r < 4; ++r) v[r] = H[r * 4 + k];
         v[k + 1] = x0 + xn * ph;
         double vn2 = 0.0;
-        for (int r = k + 1; r < 4; ++r) vn2 += v[r].r * v[r].r + v[r].i * v[r].i;
-        if (vn2 == 0.0) continue;
-        const double w = 2.0 / vn2;
-        for (int c = 0; c < 4; ++c) {           // H := (I - w v v^H) H
+#pragma unroll
+        for (int r = k + 1; r < 4; ++r) vn2 += norm2x(v[r]);
+        const double w = vn2 > 0.0 ? 2.0 / vn2 : 0.0;
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
             cx sacc = cx{0, 0};
+#pragma unroll
             for (int r = k + 1; r < 4; ++r) sacc = sacc + conjx(v[r]) * H[r * 4 + c];
+#pragma unroll
             for (int r = k + 1; r < 4; ++r) H[r * 4 + c] = H[r * 4 + c] - w * (v[r] * sacc);
         }
-        for (int r = 0; r < 4; ++r) {           // H := H (I - w v v^H)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
             cx sacc = cx{0, 0};
+#pragma unroll
             for (int c = k + 1; c < 4; ++c) sacc = sacc + H[r * 4 + c] * v[c];
+#pragma unroll
             for (int c = k + 1; c < 4; ++c) H[r * 4 + c] = H[r * 4 + c] - w * (sacc * conjx(v[c]));
         }
     }
-    double rmax = 0.0;
-    int hi = 3, it = 0;
-    while (hi >= 0) {
-        if (hi == 0) {
-            rmax = fmax(rmax, absx(H[0]));
-            break;
+    H[8] = H[12] = H[13] = cx{0, 0};
+    for (int it = 0; it < 120; ++it) {
+        bool z[4] = {true, false, false, false};
+#pragma unroll
+        for (int k = 1; k < 4; ++k) {
+            const double sub = cabs1(H[k * 4 + k - 1]);
+            z[k] = sub <= 0x1p-52 * (cabs1(H[k * 4 + k]) + cabs1(H[(k - 1) * 4 + k - 1])) || sub < 1e-300;
+            if (z[k]) H[k * 4 + k - 1] = cx{0, 0};
         }
-        int l = hi;
-        while (l > 0) {
-            const double sub = absx(H[l * 4 + l - 1]);
-            const double dd = absx(H[l * 4 + l]) + absx(H[(l - 1) * 4 + l - 1]);
-            if (sub <= 1e-17 * dd || sub < 1e-300) break;
-            --l;
-        }
-        if (l == hi) {
-            rmax = fmax(rmax, absx(H[hi * 4 + hi]));
-            --hi;
-            it = 0;
-            continue;
-        }
-        if (it >= 200) {                        // give up refining: take the block's diagonal
-            for (int k = l; k <= hi; ++k) rmax = fmax(rmax, absx(H[k * 4 + k]));
-            hi = l - 1;
-            it = 0;
-            continue;
-        }
-        const cx a = H[(hi - 1) * 4 + hi - 1], b = H[(hi - 1) * 4 + hi], c = H[hi * 4 + hi - 1],
-                 d = H[hi * 4 + hi];
+        if (z[1] && z[2] && z[3]) break;
+        const int hi = !z[3] ? 3 : (!z[2] ? 2 : 1);
+        cx a = H[0], b = H[1], c = H[4], d = H[5];
+        if (hi == 2) { a = H[5]; b = H[6]; c = H[9]; d = H[10]; }
+        if (hi == 3) { a = H[10]; b = H[11]; c = H[14]; d = H[15]; }
         cx mu;
         if (it > 0 && it % 11 == 0) {
-            mu = d + cx{absx(c), 0.0};
+            mu = d + cx{cabs1(c), 0.0};
         } else {
             const cx half = 0.5 * (a - d);
             const cx disc = sqrtx(half * half + b * c);
-            const cx m1 = d + half + disc, m2 = d + half - disc;   // (a + d)/2 +- disc
-            mu = absx(m1 - d) <= absx(m2 - d) ? m1 : m2;
+            const cx m1 = d + half + disc, m2 = d + half - disc;
+            mu = norm2x(m1 - d) <= norm2x(m2 - d) ? m1 : m2;
         }
-        for (int k = l; k <= hi; ++k) H[k * 4 + k] = H[k * 4 + k] - mu;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) H[k * 5] = H[k * 5] - mu;
         double cs[3];
         cx sn[3];
-        for (int k = l; k < hi; ++k) {
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
             const cx x = H[k * 4 + k], y = H[(k + 1) * 4 + k];
-            const double ax = absx(x), ay = absx(y), rr = hypot(ax, ay);
-            double cc;
-            cx ss;
-            if (rr == 0.0) { cc = 1.0; ss = cx{0, 0}; }
-            else if (ax == 0.0) { cc = 0.0; ss = cx{y.r / ay, -y.i / ay}; }
-            else { cc = ax / rr; ss = (1.0 / rr) * (cx{x.r / ax, x.i / ax} * conjx(y)); }
-            cs[k - l] = cc;
-            sn[k - l] = ss;
-            for (int j = k; j <= hi; ++j) {
+            const double nx = norm2x(x), ny = norm2x(y);
+            double cc = 1.0;
+            cx ss = cx{0, 0};
+            if (ny > 0.0) {
+                // c = |x| / r, s = x conj(y) / (|x| r) with r^2 = |x|^2 + |y|^2
+                if (nx == 0.0) { const double iy = rsqrt(ny); cc = 0.0; ss = cx{y.r * iy, -y.i * iy}; }
+                else { const double q = rsqrt(nx * (nx + ny)); cc = nx * q; ss = q * (x * conjx(y)); }
+            }
+            cs[k] = cc;
+            sn[k] = ss;
+#pragma unroll
+            for (int j = k; j < 4; ++j) {
                 const cx hk = H[k * 4 + j], hk1 = H[(k + 1) * 4 + j];
                 H[k * 4 + j] = cc * hk + ss * hk1;
                 H[(k + 1) * 4 + j] = cc * hk1 - conjx(ss) * hk;
             }
         }
-        for (int k = l; k < hi; ++k) {
-            const double cc = cs[k - l];
-            const cx ss = sn[k - l];
-            const int rmx = k + 2 <= hi ? k + 2 : hi;
-            for (int i = l; i <= rmx; ++i) {
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            const double cc = cs[k];
+            const cx ss = sn[k];
+#pragma unroll
+            for (int i = 0; i < (k + 2 < 4 ? k + 2 : 3) + 1; ++i) {
                 const cx hk = H[i * 4 + k], hk1 = H[i * 4 + k + 1];
                 H[i * 4 + k] = cc * hk + conjx(ss) * hk1;
                 H[i * 4 + k + 1] = cc * hk1 - ss * hk;
             }
         }
-        for (int k = l; k <= hi; ++k) H[k * 4 + k] = H[k * 4 + k] + mu;
-        ++it;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) H[k * 5] = H[k * 5] + mu;
     }
-    return rmax;
+    double r2 = 0.0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) r2 = fmax(r2, norm2x(H[k * 5]));
+    return s * sqrt(r2);
 }
-
 __global__ __launch_bounds__(64) void k_dfa_clear(unsigned long long *amp, unsigned long long *smooth, int n) {
     const int c = blockIdx.x * blockDim.x + threadIdx.x;
     if (c < n) {
@@ -2015,11 +2076,25 @@ __global__ __launch_bounds__(64) void k_dfa_clear(unsigned long long *amp, unsig
     }
 }
 
-__global__ __launch_bounds__(64) void k_dfa(const DfaCase *cases, int n_cases, long long total, double *rad,
+// two waves per SIMD: the register cap costs a few spills and hides more of
+// the FP64 dependency latency than it loses
+__global__ __launch_bounds__(64, 2) void k_dfa(const DfaCase *cases, int n_cases, long long total, double *rad,
                                             unsigned long long *amp, unsigned long long *smooth) {
-    const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= total) return;
-    int ci = 0;
+    // one wave per block; every lane stays active for the reduction at the
+    // end: lanes past the last pair redo the last pair and contribute nothing
+    const long long tg = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const bool valid = tg < total;
+    const long long t = valid ? tg : total - 1;
+    // case of the block's first pair by binary search over the case starts
+    // (uniform across the block), then the cases that start inside it
+    const long long t0 = (long long)blockIdx.x * blockDim.x;
+    int lo = 0, hi = n_cases - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (cases[mid].start <= t0) lo = mid;
+        else hi = mid - 1;
+    }
+    int ci = lo;
     while (ci + 1 < n_cases && cases[ci + 1].start <= t) ++ci;
     const DfaCase P = cases[ci];
     const long long m = t - P.start;
@@ -2032,10 +2107,6 @@ __global__ __launch_bounds__(64) void k_dfa(const DfaCase *cases, int n_cases, l
     const double dx = 1.0 / (double)P.nx, dy = P.ar * dx, vol = dx * dy;
     const double base = dx / (fabs(v1) + a);
     const double dts = P.cstar * base, dt = P.c * base;
-    // split Jacobians of the unit normals (1, 0) and (0, 1)
-    double Ap[16], Am[16], Bp[16], Bm[16];
-    split_face(P.u, P.u, 1.0, 0.0, P.d, 0.0, 0, Ap, Am);
-    split_face(P.u, P.u, 0.0, 1.0, P.d, 0.0, 0, Bp, Bm);
     const cx ex = cx{cos(tx), sin(tx)}, ey = cx{cos(ty), sin(ty)};
     const cx exi = conjx(ex), eyi = conjx(ey);
     const cx dex = ex - exi, dey = ey - eyi;             // E - E^-1
@@ -2045,64 +2116,108 @@ __global__ __launch_bounds__(64) void k_dfa(const DfaCase *cases, int n_cases, l
     const double hv = (e4x * fx * dy + e4y * fy * dx) / vol;
     const double f = P.wform ? P.eta * dts : 1.0;
     const double diag = P.wform ? 1.0 + (P.unsteady ? 1.5 * P.eta * dts / dt : 0.0) : (P.unsteady ? 1.5 / dt : 0.0);
-    cx DL[16], X[16], RHS[32];
+    // D + L, and X = D + U, then X := D^-1 (D + U) with the real D (split
+    // Jacobians of the unit normals (1, 0) and (0, 1), dead afterwards)
+    cx DL[16], X[16];
+    {
+        double Ap[16], Am[16], Bp[16], Bm[16], D[16];
+        split_face(P.u, P.u, 1.0, 0.0, P.d, 0.0, 0, Ap, Am);
+        split_face(P.u, P.u, 0.0, 1.0, P.d, 0.0, 0, Bp, Bm);
 #pragma unroll
-    for (int r = 0; r < 4; ++r)
-#pragma unroll
-        for (int c = 0; c < 4; ++c) {
-            const int k = r * 4 + c;
-            const double Ak = Ap[k] + Am[k], Bk = Bp[k] + Bm[k];
-            const double dk = (f / vol) * (dy * (Ap[k] - Am[k]) + dx * (Bp[k] - Bm[k])) + (r == c ? diag : 0.0);
+        for (int k = 0; k < 16; ++k) {
+            D[k] = (f / vol) * (dy * (Ap[k] - Am[k]) + dx * (Bp[k] - Bm[k])) + (k % 5 == 0 ? diag : 0.0);
             const cx lk = (-(f / vol)) * (dy * Ap[k] * exi + dx * Bp[k] * eyi);
             const cx uk = (f / vol) * (dy * Am[k] * ex + dx * Bm[k] * ey);
-            DL[k] = cx{dk, 0.0} + lk;                    // D + L
-            X[k] = cx{dk, 0.0} + uk;                     // D + U, becomes D^-1 (D + U)
-            // H_c and H_v, side by side as 8 right-hand columns
-            cx hc = (1.0 / (2.0 * vol)) * (Ak * dy * dex + Bk * dx * dey);
-            if (P.unsteady && r == c) hc = hc + cx{1.5 / dt, 0.0};
-            double Mk = (r == c) ? 1.0 : 0.0;
-            if (r == 3 && c == 0) Mk = -(GAM - 1.0) * (v1 * v1 + v2 * v2) / 2.0;
-            if (r == 3 && c == 3) Mk = GAM;
-            RHS[r * 8 + c] = hc;
-            RHS[r * 8 + 4 + c] = cx{Mk * hv, 0.0};
+            DL[k] = cx{D[k], 0.0} + lk;
+            X[k] = cx{D[k], 0.0} + uk;
         }
-    {
-        cx Dm[16];
-#pragma unroll
-        for (int k = 0; k < 16; ++k) Dm[k] = cx{(f / vol) * (dy * (Ap[k] - Am[k]) + dx * (Bp[k] - Bm[k])) +
-                                                   ((k % 5 == 0) ? diag : 0.0), 0.0};
-        csolve4<4>(Dm, X);
+        rsolve4(D, X);
     }
     cx Pm[16];
-    cmul4(DL, X, Pm);
-    csolve4<8>(Pm, RHS);                                 // [P^-1 H_c | P^-1 H_v]
-    cx Hc[16], Hv[16], Ui[16], V[16], T[16];
+    cmul4(DL, X, Pm);                                    // P = (D + L) D^-1 (D + U)
+    // H_c and H_v side by side as 8 right-hand columns, from the flux
+    // Jacobians of the constant state; then [P^-1 H_c | P^-1 H_v]
+    cx RHS[32];
+    {
+        double A[16], B[16];
+        flux_jacobian4(P.u, 1.0, 0.0, A);
+        flux_jacobian4(P.u, 0.0, 1.0, B);
+        const double mv = -(GAM - 1.0) * (v1 * v1 + v2 * v2) / 2.0;
 #pragma unroll
-    for (int r = 0; r < 4; ++r)
+        for (int r = 0; r < 4; ++r)
 #pragma unroll
-        for (int c = 0; c < 4; ++c) {
-            Hc[r * 4 + c] = RHS[r * 8 + c];
-            Hv[r * 4 + c] = RHS[r * 8 + 4 + c];
-            Ui[r * 4 + c] = cx{r == c ? 1.0 : 0.0, 0.0};
-            V[r * 4 + c] = RHS[r * 8 + 4 + c];
-        }
-    for (int st = 0; st < P.s; ++st) {
-        cmul4(Hc, Ui, T);
-        const double al = P.alpha[st] * dts;
-#pragma unroll
-        for (int k = 0; k < 16; ++k) Ui[k] = cx{(k % 5 == 0) ? 1.0 : 0.0, 0.0} - al * (T[k] + V[k]);
-        if (st + 1 < P.s) {
-            cmul4(Hv, Ui, T);
-            const double b = P.beta[st + 1];
-#pragma unroll
-            for (int k = 0; k < 16; ++k) V[k] = b * T[k] + (1.0 - b) * V[k];
-        }
+            for (int c = 0; c < 4; ++c) {
+                const int k = r * 4 + c;
+                cx hc = (1.0 / (2.0 * vol)) * (A[k] * dy * dex + B[k] * dx * dey);
+                if (P.unsteady && r == c) hc = hc + cx{1.5 / dt, 0.0};
+                const double Mk = (r == 3 && c == 0) ? mv : (r == 3 && c == 3) ? GAM : (r == c ? 1.0 : 0.0);
+                RHS[r * 8 + c] = hc;
+                RHS[r * 8 + 4 + c] = cx{Mk * hv, 0.0};
+            }
     }
-    const double r = spectral_radius4(Ui);
-    if (rad) rad[t] = r;
-    const unsigned long long bits = __builtin_bit_cast(unsigned long long, r);
-    atomicMax(&amp[ci], bits);
-    if (fmax(fabs(tx), fabs(ty)) >= 0.5 * M_PI - 1e-12) atomicMax(&smooth[ci], bits);
+    csolve4<8>(Pm, RHS);
+    // the stage recursion acts on each column of G on its own (column c
+    // starts from the unit vector e_c), so only one column's U and V are live
+    cx G[16];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+        cx u[4], v[4], w[4];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            u[r] = cx{r == c ? 1.0 : 0.0, 0.0};
+            v[r] = RHS[r * 8 + 4 + c];
+        }
+        for (int st = 0; st < P.s; ++st) {
+            const double al = cases[ci].alpha[st] * dts;     // from memory: no indexed register copy
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                cx acc = RHS[r * 8] * u[0];
+#pragma unroll
+                for (int k = 1; k < 4; ++k) acc = acc + RHS[r * 8 + k] * u[k];
+                w[r] = acc;
+            }
+#pragma unroll
+            for (int r = 0; r < 4; ++r) u[r] = cx{r == c ? 1.0 : 0.0, 0.0} - al * (w[r] + v[r]);
+            if (st + 1 < P.s) {
+                const double b = cases[ci].beta[st + 1];
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    cx acc = RHS[r * 8 + 4] * u[0];
+#pragma unroll
+                    for (int k = 1; k < 4; ++k) acc = acc + RHS[r * 8 + 4 + k] * u[k];
+                    w[r] = acc;
+                }
+#pragma unroll
+                for (int r = 0; r < 4; ++r) v[r] = b * w[r] + (1.0 - b) * v[r];
+            }
+        }
+#pragma unroll
+        for (int r = 0; r < 4; ++r) G[r * 4 + c] = u[r];
+    }
+    const double r = spectral_radius4(G);
+    if (rad && valid) rad[t] = r;
+    const bool hf = fmax(fabs(tx), fabs(ty)) >= 0.5 * M_PI - 1e-12;
+    unsigned long long ba = valid ? __builtin_bit_cast(unsigned long long, r) : 0ull;
+    unsigned long long bs = hf ? ba : 0ull;
+    // per-case maxima (bit patterns of non-negative doubles order like the
+    // values): a wave whose lanes all belong to one case reduces over its
+    // lanes first and issues one atomic per maximum
+    const int c0 = __builtin_amdgcn_readfirstlane(ci);
+    if (__all(ci == c0)) {
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) {
+            const unsigned long long xa = __shfl_xor(ba, o), xs = __shfl_xor(bs, o);
+            ba = xa > ba ? xa : ba;
+            bs = xs > bs ? xs : bs;
+        }
+        if (threadIdx.x == 0) {
+            atomicMax(&amp[c0], ba);
+            if (bs) atomicMax(&smooth[c0], bs);
+        }
+    } else {
+        if (valid) atomicMax(&amp[ci], ba);
+        if (bs) atomicMax(&smooth[ci], bs);
+    }
 }
 
 }  // namespace
