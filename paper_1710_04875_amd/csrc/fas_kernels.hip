@@ -32,6 +32,49 @@ __device__ inline bool decode(const Lay &L, int s, int &i, int &j) {
     return true;
 }
 
+// Cell number t of the ri x rj rectangle of cells (i, j), -o <= i < ri - o,
+// -o <= j < rj - o, in hyperplane order (h = i + j ascending, j ascending
+// inside a hyperplane): consecutive t are consecutive slots of a hyperplane,
+// so a wave's accesses stay coalesced while every lane holds a cell.  With
+// m = min(ri, rj) and M = max(ri, rj), hyperplanes 0 .. m-2 of the rectangle
+// hold 1 .. m-1 cells, m-1 .. M-1 hold m each and M .. ri+rj-2 hold m-1 .. 1;
+// the hyperplane of t comes from inverting those prefix sums (a square root
+// for the two triangles, then an exact integer check).
+__device__ inline int cells_before(int h, int ri, int rj) {
+    const int m = min(ri, rj), M = max(ri, rj);
+    if (h <= m - 1) return h * (h + 1) / 2;
+    const int A = (m - 1) * m / 2;
+    if (h <= M) return A + (h - (m - 1)) * m;
+    const int k = h - M;
+    return A + (M - m + 1) * m + k * (m - 1) - k * (k - 1) / 2;
+}
+__device__ inline int tri_root(int t) {
+    // largest h with h (h + 1) / 2 <= t
+    int h = (int)((sqrt(8.0 * (double)t + 1.0) - 1.0) * 0.5);
+    while ((h + 1) * (h + 2) / 2 <= t) ++h;
+    while (h * (h + 1) / 2 > t) --h;
+    return h;
+}
+__device__ inline bool rect_cell(const Lay &L, int t, int ri, int rj, int o, int &s, int &i, int &j) {
+    const int n = ri * rj;
+    if (t >= n) return false;
+    const int m = min(ri, rj), M = max(ri, rj);
+    const int A = (m - 1) * m / 2, B = A + (M - m + 1) * m;
+    int h;
+    if (t < A) h = tri_root(t);
+    else if (t < B) h = (m - 1) + (t - A) / m;
+    else h = (ri + rj - 2) - tri_root(n - 1 - t);   // the last triangle, counted from the end
+    const int jr = max(0, h - ri + 1) + (t - cells_before(h, ri, rj));
+    i = h - jr - o;
+    j = jr - o;
+    s = L.slot(i, j);
+    return true;
+}
+// interior cells: 0 <= i < ni, 0 <= j < nj
+__device__ inline bool interior_cell(const Lay &L, int t, int &s, int &i, int &j) {
+    return rect_cell(L, t, L.ni, L.nj, 0, s, i, j);
+}
+
 __device__ inline bool interior(const Lay &L, int i, int j) {
     return i >= 0 && i < L.ni && j >= 0 && j < L.nj;
 }
@@ -467,9 +510,8 @@ __global__ void k_ghost_cq(BK b, int noslip, int rans) {
     if (!take(b, blockIdx.y, d)) return;
     const Lay L = d.L;
     const Phys ph = b.PH[blockIdx.y];
-    int s = blockIdx.x * blockDim.x + threadIdx.x;
-    int i, j;
-    if (!decode(L, s, i, j)) return;
+    int s, i, j;   // every padded cell, -NG <= i < ni + NG, -NG <= j < nj + NG
+    if (!rect_cell(L, blockIdx.x * blockDim.x + threadIdx.x, L.NI, L.NJ, NG, s, i, j)) return;
     const int NS = L.NS;
     double U[4];
     if (interior(L, i, j)) {
@@ -515,10 +557,8 @@ __global__ void k_vertex_gradients(BK b) {
     const Lay L = d.L;
     const double *geo = d.geo, *u = d.u, *cq = d.cq;
     double *vg = d.vg;
-    int s = blockIdx.x * blockDim.x + threadIdx.x;
-    int i, j;
-    if (!decode(L, s, i, j)) return;
-    if (i < 0 || i > L.ni || j < 0 || j > L.nj) return;
+    int s, i, j;   // every vertex, 0 <= i <= ni, 0 <= j <= nj
+    if (!rect_cell(L, blockIdx.x * blockDim.x + threadIdx.x, L.ni + 1, L.nj + 1, 0, s, i, j)) return;
     const int NS = L.NS, NJ = L.NJ;
     const int c[4] = {s - (2 * NJ + 1), s - (NJ + 1), s, s - NJ};   // SW, SE, NE, NW
     double X[4], Y[4], U[4], V[4], T[4];
@@ -748,9 +788,8 @@ __global__ __launch_bounds__(TPB) void k_residual(BK b, ResArgs a) {
     const BT *blk = (const BT *)d.blk;
     BT *g = (BT *)d.g;
     const Phys ph = b.PH[blockIdx.y];
-    int s = blockIdx.x * blockDim.x + threadIdx.x;
-    int i, j;
-    if (!decode(L, s, i, j) || !interior(L, i, j)) return;
+    int s, i, j;
+    if (!interior_cell(L, blockIdx.x * blockDim.x + threadIdx.x, s, i, j)) return;
     const int NS = L.NS, NJ = L.NJ;
     FaceOut w, e, so, n;
     face_flux(L, geo, u, cq, vg, mut, ph, a, s - NJ, s, NJ, geo[G_SXI_X * NS + s],
@@ -923,9 +962,8 @@ __global__ __launch_bounds__(TPB) void k_blocks(BK b, int aw, double tau, int vi
     const double *geo = dv.geo, *u = dv.u, *cq = dv.cq, *mut = dv.mut;
     BT *blk = (BT *)dv.blk;
     const Phys ph = b.PH[blockIdx.y];
-    int s = blockIdx.x * blockDim.x + threadIdx.x;
-    int i, j;
-    if (!decode(L, s, i, j) || !interior(L, i, j)) return;
+    int s, i, j;
+    if (!interior_cell(L, blockIdx.x * blockDim.x + threadIdx.x, s, i, j)) return;
     const int NS = L.NS, NJ = L.NJ;
     // the iteration's frozen dt* (read by the stages' residuals and sweeps)
     const double dt_s = local_dt(ph, cfl_of(ph, b.cyc[blockIdx.y]), geo, u, NS, s);
@@ -2248,13 +2286,20 @@ void launch_rotate_geometry(const Lay &L, const double *geo_ref, const double *x
 // one grid (about 50k slots) spreads over every CU
 constexpr int CELL_TPB = 64;
 static dim3 cells_grid(const BLev &B) { return dim3(nblocks(B.max_ns, CELL_TPB), B.n); }
+// one thread per cell of a rectangle (rect_cell numbering): interior cells,
+// vertices, every padded cell
+static dim3 interior_grid(const BLev &B) { return dim3(nblocks(B.max_ni * B.max_nj, CELL_TPB), B.n); }
+static dim3 vertex_grid(const BLev &B) { return dim3(nblocks((B.max_ni + 1) * (B.max_nj + 1), CELL_TPB), B.n); }
+static dim3 padded_grid(const BLev &B) {
+    return dim3(nblocks((B.max_ni + 2 * NG) * (B.max_nj + 2 * NG), CELL_TPB), B.n);
+}
 
 void launch_ghost_cq(const BLev &B, int noslip, int rans, hipStream_t st) {
-    hipLaunchKernelGGL(k_ghost_cq, cells_grid(B), dim3(CELL_TPB), 0, st, B.k, noslip, rans);
+    hipLaunchKernelGGL(k_ghost_cq, padded_grid(B), dim3(CELL_TPB), 0, st, B.k, noslip, rans);
 }
 
 void launch_vertex_gradients(const BLev &B, hipStream_t st) {
-    hipLaunchKernelGGL(k_vertex_gradients, cells_grid(B), dim3(CELL_TPB), 0, st, B.k);
+    hipLaunchKernelGGL(k_vertex_gradients, vertex_grid(B), dim3(CELL_TPB), 0, st, B.k);
 }
 
 void launch_baldwin_lomax(const BLev &B, hipStream_t st) {
@@ -2268,16 +2313,16 @@ void launch_mut_ghosts(const BLev &B, hipStream_t st) {
 
 void launch_residual(const BLev &B, const ResArgs &a, hipStream_t st) {
     if (a.fp32)
-        hipLaunchKernelGGL(k_residual<float>, cells_grid(B), dim3(CELL_TPB), 0, st, B.k, a);
+        hipLaunchKernelGGL(k_residual<float>, interior_grid(B), dim3(CELL_TPB), 0, st, B.k, a);
     else
-        hipLaunchKernelGGL(k_residual<double>, cells_grid(B), dim3(CELL_TPB), 0, st, B.k, a);
+        hipLaunchKernelGGL(k_residual<double>, interior_grid(B), dim3(CELL_TPB), 0, st, B.k, a);
 }
 
 void launch_blocks(const BLev &B, int aw, double tau, int viscous, int fp32, hipStream_t st, int copy_u0) {
     if (fp32)
-        hipLaunchKernelGGL(k_blocks<float>, cells_grid(B), dim3(CELL_TPB), 0, st, B.k, aw, tau, viscous, copy_u0);
+        hipLaunchKernelGGL(k_blocks<float>, interior_grid(B), dim3(CELL_TPB), 0, st, B.k, aw, tau, viscous, copy_u0);
     else
-        hipLaunchKernelGGL(k_blocks<double>, cells_grid(B), dim3(CELL_TPB), 0, st, B.k, aw, tau, viscous,
+        hipLaunchKernelGGL(k_blocks<double>, interior_grid(B), dim3(CELL_TPB), 0, st, B.k, aw, tau, viscous,
                            copy_u0);
 }
 
