@@ -1,0 +1,91 @@
+"""Host check of the hyperplane-ordered cell numbering that the cell-parallel
+kernels launch over (rect_cell in fas_kernels.hip).
+
+The device functions and the layout struct are taken verbatim from the
+sources, compiled for the host with g++, and run over every rectangle the
+kernels use: interior cells, vertices and every padded cell, for all grids
+up to 48 x 48 plus a few large and thin ones.  For each, the numbering must
+hit every cell of the rectangle exactly once, give strictly increasing slots
+(hyperplane order, j ascending inside a hyperplane), agree with decode(),
+and reject numbers past the last cell."""
+import os
+import re
+import shutil
+import subprocess
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+CSRC = os.path.join(ROOT, "paper_1710_04875_amd", "csrc")
+
+MAIN = r"""
+int main() {
+    long bad = 0, checked = 0;
+    auto run = [&](const Lay &L, int ri, int rj, int o) {
+        std::vector<int> seen((size_t)ri * rj, 0);
+        int last = -1;
+        for (int t = 0; t < ri * rj + 70; ++t) {
+            int s, i, j;
+            const bool ok = rect_cell(L, t, ri, rj, o, s, i, j);
+            if (t >= ri * rj) { if (ok) ++bad; continue; }
+            int di, dj;
+            if (!ok || i < -o || i >= ri - o || j < -o || j >= rj - o || s < 0 || s >= L.NS || s <= last ||
+                !decode(L, s, di, dj) || di != i || dj != j) { ++bad; continue; }
+            last = s;
+            seen[(size_t)(i + o) * rj + (j + o)]++;
+        }
+        for (int v : seen) if (v != 1) ++bad;
+        ++checked;
+    };
+    auto lay = [](int ni, int nj) {
+        Lay L{};
+        L.ni = ni; L.nj = nj; L.NI = ni + 2 * NG; L.NJ = nj + 2 * NG;
+        L.NS = (L.NI + L.NJ - 1) * L.NJ;
+        return L;
+    };
+    auto all = [&](int ni, int nj) {
+        const Lay L = lay(ni, nj);
+        run(L, ni, nj, 0);                 // interior cells
+        run(L, ni + 1, nj + 1, 0);         // vertices
+        run(L, L.NI, L.NJ, NG);            // every padded cell
+        int s, i, j;                       // interior_cell is the interior rectangle
+        for (int t = 0; t < ni * nj; t += 7) {
+            int s2, i2, j2;
+            if (!interior_cell(L, t, s, i, j) || !rect_cell(L, t, ni, nj, 0, s2, i2, j2) || s != s2) ++bad;
+        }
+    };
+    for (int ni = 1; ni <= 48; ++ni)
+        for (int nj = 1; nj <= 48; ++nj) all(ni, nj);
+    const int big[][2] = {{512, 256}, {256, 512}, {1024, 64}, {16, 4096}, {4096, 8}};
+    for (const auto &p : big) all(p[0], p[1]);
+    std::printf("rectangles %ld bad %ld\n", checked, bad);
+    return bad != 0;
+}
+"""
+
+
+def _source():
+    with open(os.path.join(CSRC, "fas_internal.h")) as f:
+        internal = f.read()
+    with open(os.path.join(CSRC, "fas_kernels.hip")) as f:
+        kernels = f.read()
+    ng = re.search(r"constexpr int NG = (\d+);", internal).group(1)
+    lay = re.search(r"struct Lay \{.*?\n\};", internal, re.S).group(0)
+    a = kernels.index("__device__ inline bool decode(")
+    b = kernels.index("__device__ inline bool interior(const Lay &L, int i, int j) {")
+    funcs = kernels[a:b]
+    host = lambda t: t.replace("__host__ ", "").replace("__device__ ", "")
+    head = ("#include <algorithm>\n#include <cmath>\n#include <cstdio>\n#include <vector>\n"
+            "using std::max; using std::min;\nconstexpr int NG = %s;\n" % ng)
+    return head + host(lay) + "\n" + host(funcs) + MAIN
+
+
+@pytest.mark.skipif(shutil.which("g++") is None, reason="needs g++")
+def test_rect_cell_numbering_is_a_hyperplane_ordered_bijection(tmp_path):
+    src = tmp_path / "cells.cpp"
+    exe = tmp_path / "cells"
+    src.write_text(_source())
+    subprocess.run(["g++", "-O2", "-std=c++17", "-o", str(exe), str(src)], check=True)
+    out = subprocess.run([str(exe)], capture_output=True, text=True)
+    assert out.returncode == 0, out.stdout + out.stderr
+    assert out.stdout.strip().endswith("bad 0")
