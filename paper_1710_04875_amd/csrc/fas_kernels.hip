@@ -777,40 +777,16 @@ __device__ void face_flux(const Lay &L, const double *geo, const double *u, cons
     }
 }
 
+// The cell's part of the residual once its face sums are known (Section 2
+// and eq. "split-rhs"): BDF time derivative, FAS forcing, then either F, or
+// the smoother stage's blended f^v accumulator and g = D^-1 (dt*) r.
 template <typename BT>
-__global__ __launch_bounds__(TPB) void k_residual(BK b, ResArgs a) {
-    LevelDev d;
-    if (!take(b, blockIdx.y, d)) return;
-    const Lay L = d.L;
-    const double *geo = d.geo, *u = d.u, *cq = d.cq, *vg = d.vg, *mut = d.mut;
-    const double *un = d.un, *unm1 = d.unm1, *src = d.src, *dts = d.dts;
+__device__ inline void residual_cell(const LevelDev &d, const ResArgs &a, int NS, int s, double Fc[4],
+                                     double Fv[4]) {
+    const double *u = d.u, *un = d.un, *unm1 = d.unm1, *src = d.src, *dts = d.dts;
     double *F = d.F, *acc = d.acc;
     const BT *blk = (const BT *)d.blk;
     BT *g = (BT *)d.g;
-    const Phys ph = b.PH[blockIdx.y];
-    int s, i, j;
-    if (!interior_cell(L, blockIdx.x * blockDim.x + threadIdx.x, s, i, j)) return;
-    const int NS = L.NS, NJ = L.NJ;
-    FaceOut w, e, so, n;
-    face_flux(L, geo, u, cq, vg, mut, ph, a, s - NJ, s, NJ, geo[G_SXI_X * NS + s],
-              geo[G_SXI_Y * NS + s], s, s + NJ + 1, false, s, G_WIX, w);
-    face_flux(L, geo, u, cq, vg, mut, ph, a, s, s + NJ, NJ, geo[G_SXI_X * NS + s + NJ],
-              geo[G_SXI_Y * NS + s + NJ], s + NJ, s + 2 * NJ + 1, false, s + NJ, G_WIX, e);
-    bool wall = (j == 0) && !cut_col(L, i);
-    face_flux(L, geo, u, cq, vg, mut, ph, a, s - NJ - 1, s, NJ + 1, geo[G_SETA_X * NS + s],
-              geo[G_SETA_Y * NS + s], s, s + NJ, wall, s, G_WJX, so);
-    face_flux(L, geo, u, cq, vg, mut, ph, a, s, s + NJ + 1, NJ + 1,
-              geo[G_SETA_X * NS + s + NJ + 1], geo[G_SETA_Y * NS + s + NJ + 1], s + NJ + 1,
-              s + 2 * NJ + 1, false, s + NJ + 1, G_WJX, n);
-    const double vol = geo[G_VOL * NS + s];
-    double Fc[4], Fv[4];
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-        double fc = (e.C[k] - w.C[k]) + (n.C[k] - so.C[k]);
-        double fv = (e.V[k] - w.V[k]) + (n.V[k] - so.V[k]);
-        Fc[k] = fc / vol;
-        Fv[k] = fv / vol;
-    }
     if (a.bdf) {
         double uu[4], u1[4];
         ld4(u, NS, s, uu);
@@ -859,6 +835,85 @@ __global__ __launch_bounds__(TPB) void k_residual(BK b, ResArgs a) {
         for (int c = 0; c < 4; ++c) acc4 = fma(blk[BL<BT>::at(B_DINV, NS, s, rr, c)], rb[c], acc4);
         g[rr * NS + s] = acc4;
     }
+}
+
+template <typename BT>
+__global__ __launch_bounds__(TPB) void k_residual(BK b, ResArgs a) {
+    LevelDev d;
+    if (!take(b, blockIdx.y, d)) return;
+    const Lay L = d.L;
+    const double *geo = d.geo, *u = d.u, *cq = d.cq, *vg = d.vg, *mut = d.mut;
+    const Phys ph = b.PH[blockIdx.y];
+    int s, i, j;
+    if (!interior_cell(L, blockIdx.x * blockDim.x + threadIdx.x, s, i, j)) return;
+    const int NS = L.NS, NJ = L.NJ;
+    FaceOut w, e, so, n;
+    face_flux(L, geo, u, cq, vg, mut, ph, a, s - NJ, s, NJ, geo[G_SXI_X * NS + s],
+              geo[G_SXI_Y * NS + s], s, s + NJ + 1, false, s, G_WIX, w);
+    face_flux(L, geo, u, cq, vg, mut, ph, a, s, s + NJ, NJ, geo[G_SXI_X * NS + s + NJ],
+              geo[G_SXI_Y * NS + s + NJ], s + NJ, s + 2 * NJ + 1, false, s + NJ, G_WIX, e);
+    bool wall = (j == 0) && !cut_col(L, i);
+    face_flux(L, geo, u, cq, vg, mut, ph, a, s - NJ - 1, s, NJ + 1, geo[G_SETA_X * NS + s],
+              geo[G_SETA_Y * NS + s], s, s + NJ, wall, s, G_WJX, so);
+    face_flux(L, geo, u, cq, vg, mut, ph, a, s, s + NJ + 1, NJ + 1,
+              geo[G_SETA_X * NS + s + NJ + 1], geo[G_SETA_Y * NS + s + NJ + 1], s + NJ + 1,
+              s + 2 * NJ + 1, false, s + NJ + 1, G_WJX, n);
+    const double vol = geo[G_VOL * NS + s];
+    double Fc[4], Fv[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        double fc = (e.C[k] - w.C[k]) + (n.C[k] - so.C[k]);
+        double fv = (e.V[k] - w.V[k]) + (n.V[k] - so.V[k]);
+        Fc[k] = fc / vol;
+        Fv[k] = fv / vol;
+    }
+    residual_cell<BT>(d, a, NS, s, Fc, Fv);
+}
+
+// Small launches: four lanes per cell, one face each (w, e, s, n), so the
+// flux chain each lane runs is a quarter as long.  The face sums are formed
+// by lane shuffles in the order of k_residual, (e - w) + (n - s), so the
+// result is bitwise the same; lanes past the last cell redo cell 0 and store
+// nothing, so every lane takes part in the shuffles.
+template <typename BT>
+__global__ __launch_bounds__(TPB) void k_residual_q(BK b, ResArgs a) {
+    LevelDev d;
+    if (!take(b, blockIdx.y, d)) return;
+    const Lay L = d.L;
+    const Phys ph = b.PH[blockIdx.y];
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    const int q = t & 3;
+    int s, i, j;
+    const bool valid = interior_cell(L, t >> 2, s, i, j);
+    if (!valid) interior_cell(L, 0, s, i, j);
+    const int NS = L.NS, NJ = L.NJ;
+    // q = 0 west, 1 east (i-faces), 2 south, 3 north (j-faces); sf is the
+    // face's slot (face vector, grid velocity) and also its first vertex
+    const int sf = q == 0 ? s : q == 1 ? s + NJ : q == 2 ? s : s + NJ + 1;
+    const int sL = q == 0 ? s - NJ : q == 2 ? s - NJ - 1 : s;
+    const int sR = q == 0 ? s : q == 1 ? s + NJ : q == 2 ? s : s + NJ + 1;
+    const int gR = q == 0 ? s + NJ + 1 : q == 2 ? s + NJ : s + 2 * NJ + 1;
+    const int off = q < 2 ? NJ : NJ + 1;
+    const int px = q < 2 ? G_SXI_X : G_SETA_X, py = q < 2 ? G_SXI_Y : G_SETA_Y;
+    const bool wall = q == 2 && j == 0 && !cut_col(L, i);
+    FaceOut o;
+    face_flux(L, d.geo, d.u, d.cq, d.vg, d.mut, ph, a, sL, sR, off, d.geo[px * NS + sf], d.geo[py * NS + sf], sf,
+              gR, wall, sf, q < 2 ? G_WIX : G_WJX, o);
+    const double vol = d.geo[G_VOL * NS + s];
+    double Fc[4], Fv[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        // odd lanes: e - w and n - s (the partner is the even lane below)
+        const double dc = o.C[k] - __shfl_xor(o.C[k], 1);
+        const double dv = o.V[k] - __shfl_xor(o.V[k], 1);
+        // lane 1: (e - w) + (n - s)
+        const double fc = dc + __shfl_xor(dc, 2);
+        const double fv = dv + __shfl_xor(dv, 2);
+        Fc[k] = fc / vol;
+        Fv[k] = fv / vol;
+    }
+    if (!valid || q != 1) return;
+    residual_cell<BT>(d, a, NS, s, Fc, Fv);
 }
 
 // -------------------------------------------------- preconditioner blocks
@@ -2311,7 +2366,20 @@ void launch_mut_ghosts(const BLev &B, hipStream_t st) {
     hipLaunchKernelGGL(k_mut_ghosts, cells_grid(B), dim3(CELL_TPB), 0, st, B.k);
 }
 
+// Launches of at most this many cells (over all cases) take the four-lane
+// residual: they leave most of the chip idle, so the flux chain's latency
+// sets their time.
+constexpr long long RES_QUAD_MAX_CELLS = 65536;
+
 void launch_residual(const BLev &B, const ResArgs &a, hipStream_t st) {
+    if ((long long)B.max_ni * B.max_nj * B.n <= RES_QUAD_MAX_CELLS) {
+        const dim3 grid(nblocks(4 * B.max_ni * B.max_nj, CELL_TPB), B.n);
+        if (a.fp32)
+            hipLaunchKernelGGL(k_residual_q<float>, grid, dim3(CELL_TPB), 0, st, B.k, a);
+        else
+            hipLaunchKernelGGL(k_residual_q<double>, grid, dim3(CELL_TPB), 0, st, B.k, a);
+        return;
+    }
     if (a.fp32)
         hipLaunchKernelGGL(k_residual<float>, interior_grid(B), dim3(CELL_TPB), 0, st, B.k, a);
     else
