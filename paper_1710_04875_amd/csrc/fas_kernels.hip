@@ -1122,6 +1122,114 @@ __global__ __launch_bounds__(TPB) void k_blocks(BK b, int aw, double tau, int vi
     }
 }
 
+// Small launches: four lanes per cell, one face each, in k_blocks's face
+// order (q = 0 east, 1 west, 2 north, 3 south).  Every lane gathers the four
+// faces' diagonal contributions by shuffles and forms D = c (((X_e - X_w) +
+// X_n) - X_s) + diag I and its inverse exactly as k_blocks does; lane q then
+// writes row q of D^-1 and its own face's off-diagonal block D^-1 B.  The
+// arithmetic is k_blocks's, so the blocks are bitwise the same; lanes past
+// the last cell redo cell 0 and store nothing.
+template <typename BT>
+__global__ __launch_bounds__(TPB) void k_blocks_q(BK b, int aw, double tau, int viscous, int copy_u0) {
+    LevelDev dv;
+    if (!take(b, blockIdx.y, dv)) return;
+    const Lay L = dv.L;
+    const double *geo = dv.geo, *u = dv.u, *cq = dv.cq, *mut = dv.mut;
+    BT *blk = (BT *)dv.blk;
+    const Phys ph = b.PH[blockIdx.y];
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    const int q = t & 3;
+    int s, i, j;
+    const bool valid = interior_cell(L, t >> 2, s, i, j);
+    if (!valid) interior_cell(L, 0, s, i, j);
+    const int NS = L.NS, NJ = L.NJ;
+    const double dt_s = local_dt(ph, cfl_of(ph, b.cyc[blockIdx.y]), geo, u, NS, s);
+    if (valid && q == 0) {
+        dv.dts[s] = dt_s;
+        if (copy_u0) {
+#pragma unroll
+            for (int k = 0; k < 4; ++k) dv.u0[k * NS + s] = u[k * NS + s];
+        }
+    }
+    double c, diag;
+    if (aw) {
+        double e = ph.eta * dt_s;
+        c = e / geo[G_VOL * NS + s];
+        diag = 1.0 + tau * e;
+    } else {
+        c = 1.0 / geo[G_VOL * NS + s];
+        diag = tau;
+    }
+    const int sL = q == 0 ? s : q == 1 ? s - NJ : q == 2 ? s : s - NJ - 1;
+    const int sR = q == 0 ? s + NJ : q == 1 ? s : q == 2 ? s + NJ + 1 : s;
+    const int sf = q == 0 ? s + NJ : q == 1 ? s : q == 2 ? s + NJ + 1 : s;
+    double Ap[16], Am[16];
+    face_blocks(L, geo, u, cq, mut, ph, viscous, sL, sR, q < 2 ? G_SXI_X : G_SETA_X, q < 2 ? G_SXI_Y : G_SETA_Y, sf,
+                Ap, Am);
+    // this face's part of D (X) and its off-diagonal block (Bf)
+    const bool plus = (q & 1) == 0;   // east and north add A+, west and south subtract A-
+    double X[16], Bf[16];
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+        X[k] = plus ? Ap[k] : Am[k];
+        Bf[k] = plus ? Am[k] : Ap[k];
+    }
+    double D[16], Di[16];
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+        const double xe = __shfl(X[k], 0, 4), xw = __shfl(X[k], 1, 4);
+        const double xn = __shfl(X[k], 2, 4), xs = __shfl(X[k], 3, 4);
+        const double acc = ((xe - xw) + xn) - xs;
+        D[k] = c * acc;
+        Di[k] = (k % 5 == 0) ? 1.0 : 0.0;
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k) D[k * 5] = D[k * 5] + diag;
+    // Gauss-Jordan inverse without pivoting
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        double piv = 1.0 / D[k * 5];
+#pragma unroll
+        for (int cc = 0; cc < 4; ++cc) {
+            D[k * 4 + cc] *= piv;
+            Di[k * 4 + cc] *= piv;
+        }
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            if (r == k) continue;
+            double f = D[r * 4 + k];
+#pragma unroll
+            for (int cc = 0; cc < 4; ++cc) {
+                D[r * 4 + cc] = fma(-f, D[k * 4 + cc], D[r * 4 + cc]);
+                Di[r * 4 + cc] = fma(-f, Di[k * 4 + cc], Di[r * 4 + cc]);
+            }
+        }
+    }
+    if (!valid) return;
+#pragma unroll
+    for (int k = 0; k < 16; ++k)
+        if ((k >> 2) == q) blk[BL<BT>::at(B_DINV, NS, s, k >> 2, k & 3)] = (BT)Di[k];
+    // M_slot = D^-1 B_slot for this lane's face: slot 1 east, 0 west, 3 north,
+    // 2 south; the west and south blocks enter with a minus sign
+    const int sl = q == 0 ? 1 : q == 1 ? 0 : q == 2 ? 3 : 2;
+    const bool has = sl == 0 ? i > 0 : sl == 1 ? i < L.ni - 1 : sl == 2 ? (j > 0 || cut_col(L, i)) : j < L.nj - 1;
+    double B[16];
+#pragma unroll
+    for (int k = 0; k < 16; ++k) B[k] = plus ? c * Bf[k] : -(c * Bf[k]);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+#pragma unroll
+        for (int cc = 0; cc < 4; ++cc) {
+            double m = 0.0;
+            if (has) {
+#pragma unroll
+                for (int k = 0; k < 4; ++k) m = fma(Di[r * 4 + k], B[k * 4 + cc], m);
+            }
+            blk[BL<BT>::at(B_M0 + sl, NS, s, r, cc)] = (BT)m;
+        }
+    }
+}
+
 // ------------------------------------------------------------- SGS sweeps
 // Eq. "sgs-precon": x = P^-1 r, P = (D+L) D^-1 (D+U), by a forward and a
 // backward block Gauss-Seidel sweep.  With g = D^-1 r and M = D^-1 B:
@@ -2387,6 +2495,14 @@ void launch_residual(const BLev &B, const ResArgs &a, hipStream_t st) {
 }
 
 void launch_blocks(const BLev &B, int aw, double tau, int viscous, int fp32, hipStream_t st, int copy_u0) {
+    if ((long long)B.max_ni * B.max_nj * B.n <= RES_QUAD_MAX_CELLS) {   // the residual's small-launch rule
+        const dim3 grid(nblocks(4 * B.max_ni * B.max_nj, CELL_TPB), B.n);
+        if (fp32)
+            hipLaunchKernelGGL(k_blocks_q<float>, grid, dim3(CELL_TPB), 0, st, B.k, aw, tau, viscous, copy_u0);
+        else
+            hipLaunchKernelGGL(k_blocks_q<double>, grid, dim3(CELL_TPB), 0, st, B.k, aw, tau, viscous, copy_u0);
+        return;
+    }
     if (fp32)
         hipLaunchKernelGGL(k_blocks<float>, interior_grid(B), dim3(CELL_TPB), 0, st, B.k, aw, tau, viscous, copy_u0);
     else
