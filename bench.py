@@ -443,6 +443,61 @@ def unsteady_section(fas, torch, inner_cap):
             "steps": steps}
 
 
+def adjoint_section(fas, torch, primal_cap, adj_cap):
+    """Discrete adjoint of the lift on the 1024 x 256 C-grid (n_w = 128),
+    RANS, M = 0.8, alpha ~ U[0, 2] deg (seed 5), FP64 residual with the FP32
+    preconditioner: the primal FAS cycles to an 8-order drop (or the cap),
+    then one gradient of C_L with respect to M, alpha and every node (x, y)
+    (the adjoint solve, GMRES right-preconditioned by the transposed
+    smoother, to 8 orders or the iteration cap, then the node products), and
+    the transposed residual product (fas_vjp) timed on its own over 20 calls
+    on a seeded adjoint vector."""
+    import numpy as np
+    import fas_inputs as fi
+    case = fi.steady_cgrid_case(1024, 256, 128, seed=5)
+    x, y = case.grid()
+    par = fas.Params(model=fas.FAS_RANS_BL, scheme=fas.FAS_AW3, mach=case.mach, alpha_deg=case.alpha_deg,
+                     reynolds=case.reynolds, n_levels=3, cycle_gamma=1, nu1=1, eta=0.5, d_cut=0.5, cfl=100.0,
+                     cfl_ramp=1.0, n_ramp=4, ramp_growth=1.5, kappa2c=0.125, precond_fp32=1)
+    g = fas.Grid(case.topology, x, y, case.n_wake, 3)
+    st = fas.State(g, par, torch.from_numpy(case.initial_state(x, y)).cuda())
+    torch.cuda.synchronize()
+    log("adjoint: primal to 8 orders (1024x256)")
+    t0 = time.perf_counter()
+    hp, sp = st.cycle(primal_cap, 8.0)
+    torch.cuda.synchronize()
+    tp = time.perf_counter() - t0
+    log("adjoint: lift gradient (M, alpha, every node)")
+    t0 = time.perf_counter()
+    cl, gp, dx, dy, ha, sa = st.lift_gradient_nodes(adj_cap, 8.0)
+    torch.cuda.synchronize()
+    tg = time.perf_counter() - t0
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(6)
+    lam = torch.randn(st.shape(), dtype=torch.float64, device="cuda", generator=gen)
+    st.vjp(lam)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(20):
+        st.vjp(lam)
+    torch.cuda.synchronize()
+    tv = (time.perf_counter() - t0) / 20
+    cells = case.ni * case.nj
+    return {"workload": "steady RANS 1024x256 C-grid (n_w 128), M=0.8, alpha=%.4f deg, FP32 preconditioner; "
+                        "dC_L/d(M, alpha, every node x and y)" % case.alpha_deg,
+            "primal": {"seconds": round(tp, 3), "cycles": len(hp) - 1, "status": int(sp),
+                       "orders": round(float(np.log10(hp[0] / np.nanmin(hp))), 2)},
+            # the gradient's values mean nothing until the adjoint solve has
+            # converged, so only its cost and progress are reported
+            "gradient": {"seconds": round(tg, 3), "adjoint_iterations": len(ha) - 1, "status": int(sa),
+                         "converged": bool(sa == 0),
+                         "orders": round(float(np.log10(ha[0] / np.nanmin(ha))), 2) if len(ha) > 1 else None,
+                         "ms_per_adjoint_iteration": round(1e3 * tg / max(len(ha) - 1, 1), 3),
+                         "cl": round(cl, 6), "node_gradient_entries": int(dx.numel() + dy.numel())},
+            "vjp": {"ms_per_call": round(1e3 * tv, 4), "cells": cells,
+                    "cell_products_per_s": round(cells / tv, 1)}}
+
+
 def cpu_baseline(seconds_target=15.0):
     """The oracle (numpy + C sweep, single thread) on the first cycles of
     the same workload."""
@@ -489,6 +544,10 @@ def main():
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only copy a 256 MiB buffer 5 times (HBM counter calibration)")
     ap.add_argument("--no-dfa", action="store_true", help="skip the Fourier analysis section")
+    ap.add_argument("--no-adjoint", action="store_true", help="skip the 1024x256 adjoint section")
+    ap.add_argument("--adjoint-only", action="store_true", help="run only the 1024x256 adjoint section")
+    ap.add_argument("--primal-cap", type=int, default=1000)
+    ap.add_argument("--adjoint-cap", type=int, default=200)
     ap.add_argument("--dfa-only", action="store_true", help="run only the Fourier analysis section")
     ap.add_argument("--traffic-summary", nargs=4, metavar=("FETCH_DIR", "WRITE_DIR", "CALF_DIR", "CALW_DIR"),
                     help="summarise four rocprofv3 --pmc output folders into the sweep's traffic record")
@@ -515,6 +574,10 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     if args.dfa_only:
         print(json.dumps({"dfa": dfa_section(fas, torch)}), flush=True)
+        return
+    if args.adjoint_only:
+        print(json.dumps({"adjoint_1024x256": adjoint_section(fas, torch, args.primal_cap, args.adjoint_cap)}),
+              flush=True)
         return
     run_gpu.no_drop = args.no_drop
     log("fp64 preconditioner run")
@@ -577,6 +640,8 @@ def main():
     if not args.no_dfa:
         log("discrete Fourier analysis")
         line["dfa"] = dfa_section(fas, torch)
+    if not args.no_adjoint:
+        line["adjoint_1024x256"] = adjoint_section(fas, torch, args.primal_cap, args.adjoint_cap)
     if not args.no_cpu:
         log("cpu baseline (oracle)")
         line["cpu_baseline"] = cpu_baseline()
