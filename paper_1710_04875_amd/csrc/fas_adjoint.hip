@@ -8,6 +8,7 @@
 // state.  Layout: fas_internal.h.
 #include "fas_internal.h"
 #include "fas_geom.h"
+#include "fas_cells.h"
 
 #include <cmath>
 
@@ -470,9 +471,8 @@ __device__ void make_ctx(Ctx &c, const Lay &L, const double *geo, const double *
 // through the boundary conditions).  out must be zeroed first.
 __global__ __launch_bounds__(TPB) void k_vjp(Lay L, const double *geo, const double *u, const double *mut,
                                              Phys ph, const double *lam, double *out) {
-    const int s = blockIdx.x * blockDim.x + threadIdx.x;
-    int i, j;
-    if (!decode(L, s, i, j) || !interior(L, i, j)) return;
+    int s, i, j;
+    if (!interior_cell(L, blockIdx.x * blockDim.x + threadIdx.x, s, i, j)) return;
     const int NS = L.NS;
     double lc[4];
 #pragma unroll
@@ -517,9 +517,8 @@ constexpr int MAX_GSEEDS = 96;
 
 __global__ __launch_bounds__(TPB) void k_vjp_geo(Lay L, const double *geo, const double *u, const double *mut,
                                                  Phys ph, const double *lam, double *gbar) {
-    const int s = blockIdx.x * blockDim.x + threadIdx.x;
-    int i, j;
-    if (!decode(L, s, i, j) || !interior(L, i, j)) return;
+    int s, i, j;
+    if (!interior_cell(L, blockIdx.x * blockDim.x + threadIdx.x, s, i, j)) return;
     const int NS = L.NS;
     double lc[4];
 #pragma unroll
@@ -715,9 +714,8 @@ __global__ __launch_bounds__(TPB) void k_geo_nodes(Lay L, const double *xn, cons
 __global__ __launch_bounds__(TPB) void k_param_partials(Lay L, const double *geo, const double *u,
                                                         const double *mut, Phys ph, double reynolds,
                                                         double *dFa, double *dFm) {
-    const int s = blockIdx.x * blockDim.x + threadIdx.x;
-    int i, j;
-    if (!decode(L, s, i, j) || !interior(L, i, j)) return;
+    int s, i, j;
+    if (!interior_cell(L, blockIdx.x * blockDim.x + threadIdx.x, s, i, j)) return;
     const int NS = L.NS;
     Ctx c;
     make_ctx(c, L, geo, u, mut, ph);
@@ -1014,18 +1012,18 @@ __global__ void k_zero(double *p, size_t n) {
 // =================================================================== launchers
 void launch_vjp(const Lay &L, const double *geo, const double *u, const double *mut, const Phys &ph,
                 const double *lam, double *out, hipStream_t st) {
-    hipLaunchKernelGGL(k_vjp, dim3(nblocks(L.NS)), dim3(TPB), 0, st, L, geo, u, mut, ph, lam, out);
+    hipLaunchKernelGGL(k_vjp, dim3(nblocks(L.ni * L.nj)), dim3(TPB), 0, st, L, geo, u, mut, ph, lam, out);
 }
 
 void launch_param_partials(const Lay &L, const double *geo, const double *u, const double *mut,
                            const Phys &ph, double reynolds, double *dFa, double *dFm, hipStream_t st) {
-    hipLaunchKernelGGL(k_param_partials, dim3(nblocks(L.NS)), dim3(TPB), 0, st, L, geo, u, mut, ph,
+    hipLaunchKernelGGL(k_param_partials, dim3(nblocks(L.ni * L.nj)), dim3(TPB), 0, st, L, geo, u, mut, ph,
                        reynolds, dFa, dFm);
 }
 
 void launch_vjp_geo(const Lay &L, const double *geo, const double *u, const double *mut, const Phys &ph,
                     const double *lam, double *gbar, hipStream_t st) {
-    hipLaunchKernelGGL(k_vjp_geo, dim3(nblocks(L.NS)), dim3(TPB), 0, st, L, geo, u, mut, ph, lam, gbar);
+    hipLaunchKernelGGL(k_vjp_geo, dim3(nblocks(L.ni * L.nj)), dim3(TPB), 0, st, L, geo, u, mut, ph, lam, gbar);
 }
 
 void launch_forces_geo(const Lay &L, const double *geo, const double *u, const Phys &ph, double *gbar,

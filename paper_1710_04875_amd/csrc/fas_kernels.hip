@@ -5,6 +5,7 @@
 // section / equation it implements.  Layout: fas_internal.h.
 #include "fas_internal.h"
 #include "fas_geom.h"
+#include "fas_cells.h"
 #include "fas_dfa.h"
 
 #include <cmath>
@@ -30,49 +31,6 @@ __device__ inline bool decode(const Lay &L, int s, int &i, int &j) {
     i = I - NG;
     j = J - NG;
     return true;
-}
-
-// Cell number t of the ri x rj rectangle of cells (i, j), -o <= i < ri - o,
-// -o <= j < rj - o, in hyperplane order (h = i + j ascending, j ascending
-// inside a hyperplane): consecutive t are consecutive slots of a hyperplane,
-// so a wave's accesses stay coalesced while every lane holds a cell.  With
-// m = min(ri, rj) and M = max(ri, rj), hyperplanes 0 .. m-2 of the rectangle
-// hold 1 .. m-1 cells, m-1 .. M-1 hold m each and M .. ri+rj-2 hold m-1 .. 1;
-// the hyperplane of t comes from inverting those prefix sums (a square root
-// for the two triangles, then an exact integer check).
-__device__ inline int cells_before(int h, int ri, int rj) {
-    const int m = min(ri, rj), M = max(ri, rj);
-    if (h <= m - 1) return h * (h + 1) / 2;
-    const int A = (m - 1) * m / 2;
-    if (h <= M) return A + (h - (m - 1)) * m;
-    const int k = h - M;
-    return A + (M - m + 1) * m + k * (m - 1) - k * (k - 1) / 2;
-}
-__device__ inline int tri_root(int t) {
-    // largest h with h (h + 1) / 2 <= t
-    int h = (int)((sqrt(8.0 * (double)t + 1.0) - 1.0) * 0.5);
-    while ((h + 1) * (h + 2) / 2 <= t) ++h;
-    while (h * (h + 1) / 2 > t) --h;
-    return h;
-}
-__device__ inline bool rect_cell(const Lay &L, int t, int ri, int rj, int o, int &s, int &i, int &j) {
-    const int n = ri * rj;
-    if (t >= n) return false;
-    const int m = min(ri, rj), M = max(ri, rj);
-    const int A = (m - 1) * m / 2, B = A + (M - m + 1) * m;
-    int h;
-    if (t < A) h = tri_root(t);
-    else if (t < B) h = (m - 1) + (t - A) / m;
-    else h = (ri + rj - 2) - tri_root(n - 1 - t);   // the last triangle, counted from the end
-    const int jr = max(0, h - ri + 1) + (t - cells_before(h, ri, rj));
-    i = h - jr - o;
-    j = jr - o;
-    s = L.slot(i, j);
-    return true;
-}
-// interior cells: 0 <= i < ni, 0 <= j < nj
-__device__ inline bool interior_cell(const Lay &L, int t, int &s, int &i, int &j) {
-    return rect_cell(L, t, L.ni, L.nj, 0, s, i, j);
 }
 
 __device__ inline bool interior(const Lay &L, int i, int j) {

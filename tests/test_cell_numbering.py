@@ -1,5 +1,5 @@
 """Host check of the hyperplane-ordered cell numbering that the cell-parallel
-kernels launch over (rect_cell in fas_kernels.hip).
+kernels launch over (rect_cell in fas_cells.h).
 
 The device functions and the layout struct are taken verbatim from the
 sources, compiled for the host with g++, and run over every rectangle the
@@ -71,9 +71,13 @@ def _source():
         kernels = f.read()
     ng = re.search(r"constexpr int NG = (\d+);", internal).group(1)
     lay = re.search(r"struct Lay \{.*?\n\};", internal, re.S).group(0)
+    with open(os.path.join(CSRC, "fas_cells.h")) as f:
+        cells = f.read()
     a = kernels.index("__device__ inline bool decode(")
     b = kernels.index("__device__ inline bool interior(const Lay &L, int i, int j) {")
-    funcs = kernels[a:b]
+    c = cells.index("__device__ inline int cells_before(")
+    d = cells.rindex("}  // namespace fas")
+    funcs = kernels[a:b] + cells[c:d]
     host = lambda t: t.replace("__host__ ", "").replace("__device__ ", "")
     head = ("#include <algorithm>\n#include <cmath>\n#include <cstdio>\n#include <vector>\n"
             "using std::max; using std::min;\nconstexpr int NG = %s;\n" % ng)
