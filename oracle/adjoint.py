@@ -186,3 +186,44 @@ def lift_gradient(S, u):
     lam = np.linalg.solve(J.T, -g.reshape(-1))
     da, dm = residual_param_partials(S, u, mutp)
     return (cla + lam @ da.reshape(-1), clm + lam @ dm.reshape(-1)), lam.reshape(u.shape)
+
+
+def smoother_map(S, u, frozen):
+    """One fine-level smoother iteration (Section 4: the low-storage stages
+    with the split f^c / f^v of Section 4.1) from the state u, which may be
+    complex, with dt*, the SGS blocks and the eddy viscosity held at the
+    values ``frozen`` = S.prepare(0) computed at the real starting state."""
+    from .smoother import additive_iteration
+    _, dts, mutp, blocks = frozen
+    lev = S.levels[0]
+
+    def split(v):
+        Up = _padded(S, v, S.uinf)
+        return split_residual(lev, Up, S.par, True, mutp, None, None)
+
+    def apply(r):   # P^-1 is linear with real blocks
+        if np.iscomplexobj(r):
+            return blocks.apply(np.ascontiguousarray(r.real)) + 1j * blocks.apply(np.ascontiguousarray(r.imag))
+        return blocks.apply(r)
+
+    if S.aw:
+        inc = lambda r: apply(dts * r)
+    else:
+        inc = lambda r: dts * apply(r)
+    return additive_iteration(u, split, inc, S.alpha, S.beta)
+
+
+def smoother_jacobian(S, u):
+    """dS/du (4N x 4N, component-major flattening) of the smoother map at
+    the steady state u with its frozen quantities, column by column by the
+    complex step."""
+    S.set_u(0, u)
+    frozen = S.prepare(0)
+    n = u.size
+    J = np.empty((n, n))
+    flat = u.reshape(-1)
+    for k in range(n):
+        uc = flat.astype(complex)
+        uc[k] += 1j * H_CS
+        J[:, k] = smoother_map(S, uc.reshape(u.shape), frozen).imag.reshape(-1) / H_CS
+    return J

@@ -63,6 +63,12 @@ class Params:
     reynolds: float = 1.0e7
     prandtl: float = 0.75
     prandtl_t: float = 0.9
+    # 0: the printed convective blocks (eqs. "d-l-u-matrices-W" / "-J");
+    # 1: plus the thin-layer viscous scalar on RANS levels (extension)
+    viscous_blocks: int = 0
+    # pseudo time step reading: 0: c* Omega / (r_xi + r_eta);
+    # 1: c* Omega / max(r_xi, r_eta)
+    dt_form: int = 1
 
 
 def restrict(lev_f, lev_c, v):
@@ -206,14 +212,15 @@ class Solver:
         lev = self.levels[l]
         u0 = self.u(l)
         Up = self.padded(l, u0)
-        dts = local_time_step(lev, Up, self.cfl_now() if cfl is None else cfl)
+        dts = local_time_step(lev, Up, self.cfl_now() if cfl is None else cfl, self.par.dt_form)
         mutp = None
         if l == 0 and self.par.model == RANS:
             self.mut = baldwin_lomax(lev, Up, self.par)
             mutp = padded_eddy_viscosity(lev, self.mut)
         elif self.par.model == RANS:
             mutp = self.mutc[l]
-        blocks = Blocks(lev, Up, dts, self.par, self.tau(), self.aw, mutp)
+        blocks = Blocks(lev, Up, dts, self.par, self.tau(), self.aw,
+                        mutp if self.par.viscous_blocks else None)
         return u0, dts, mutp, blocks
 
     def increment(self, blocks, dts):

@@ -135,14 +135,15 @@ def face_viscous(lev, Up, mutp, par):
 class Blocks:
     """D and the four neighbour blocks of every cell, frozen at a state.
 
-    With ``mutp`` (RANS levels) a scalar estimate of the viscous
-    Jacobian is added: v_f on the diagonal for every face and -v_f on the
-    coupling (both then scaled like the convective blocks), v_f from
-    ``face_viscous``.  The paper's
-    blocks hold the convective splitting only; on high-Reynolds-number
-    grids with 1e-6 wall spacing the unmatched laminar stiffness makes the
-    W smoother unstable at large c*, so the fine-level RANS blocks carry
-    this thin-layer term (an extension, not part of the printed formulas).
+    Without ``mutp`` the blocks are the printed ones: the convective
+    flux-vector splitting alone.  With ``mutp`` (RANS levels, the
+    ``viscous_blocks`` option) a scalar estimate of the viscous Jacobian is
+    added: v_f on the diagonal for every face and -v_f on the coupling (both
+    then scaled like the convective blocks), v_f from ``face_viscous``.
+    This thin-layer term is an extension, not part of the printed formulas:
+    on high-Reynolds-number grids with 1e-6 wall spacing it damps the
+    laminar sublayer's stiffness, which the convective splitting leaves
+    unmatched.
     """
 
     def __init__(self, lev, Up, dts, par, tau: float = 0.0, aw: bool = True, mutp=None):

@@ -54,6 +54,22 @@ def _abs(x):
     return np.abs(x)
 
 
+def _max(a, b):
+    """max(a, b); for complex arguments (complex-step differentiation) the
+    branch whose real part is larger, the first argument on ties (the
+    derivative of the taken branch)."""
+    if np.iscomplexobj(a) or np.iscomplexobj(b):
+        return np.where(np.real(b) > np.real(a), b, a)
+    return np.maximum(a, b)
+
+
+def _min(a, b):
+    """min(a, b) with the tie rule of _max."""
+    if np.iscomplexobj(a) or np.iscomplexobj(b):
+        return np.where(np.real(b) < np.real(a), b, a)
+    return np.minimum(a, b)
+
+
 def _cbrt(x):
     """Real cube root; for complex arguments its first-order extension
     cbrt(a) + i b / (3 cbrt(a)^2) (complex-step differentiation)."""
@@ -91,12 +107,19 @@ def cell_scalars(lev, Up, rans: bool):
     return p, q, rxi, reta, rtxi, rteta
 
 
-def local_time_step(lev, Up, cfl: float):
-    """Pseudo time step Delta t* = c* Omega / (r_xi + r_eta) per cell
-    (reading of "c* times the local mesh width", Section 4.1)."""
+def local_time_step(lev, Up, cfl: float, dt_form: int = 1):
+    """Pseudo time step per cell, a reading of "c* times the local mesh
+    width" (Section 4.1): the directional CFL steps Omega / r_xi and
+    Omega / r_eta (r carries the face length, so Omega / r is a width over
+    a wave speed); dt_form 1 takes the smaller of the two, c* Omega /
+    max(r_xi, r_eta), which on a Cartesian cell at zero incidence is the
+    step c* dx / (|v_1| + a) of the Fourier analysis; dt_form 0 takes
+    c* Omega / (r_xi + r_eta)."""
     p, q, rxi, reta, _, _ = cell_scalars(lev, Up, False)
     P = NG
-    r = rxi[P:-P, P:-P] + reta[P:-P, P:-P]
+    rx = rxi[P:-P, P:-P]
+    re = reta[P:-P, P:-P]
+    r = np.maximum(rx, re) if dt_form else rx + re
     return cfl * lev.vol / r
 
 
@@ -107,11 +130,11 @@ def _sensor(q_m, q_0, q_p):
 
 
 def _face_dissipation(wLL, wL, wR, wRR, sL, sR, rL, rR, second_order: bool, kappa2c: float):
-    rf = np.maximum(rL, rR)
+    rf = _max(rL, rR)
     if second_order:
-        sf = np.minimum(0.25, np.maximum(sL, sR))
+        sf = _min(0.25, _max(sL, sR))
         e2 = sf * rf
-        e4 = np.maximum(0.0, rf / 32.0 - 2.0 * e2)
+        e4 = _max(0.0, rf / 32.0 - 2.0 * e2)
         return e2 * (wR - wL) - e4 * (((wRR - 3.0 * wR) + 3.0 * wL) - wLL)
     e2 = kappa2c * rf
     return e2 * (wR - wL)

@@ -163,3 +163,21 @@ def test_adjoint_node_derivative_equals_direct_sensitivity(model):
     du = np.linalg.solve(J, -adj.residual_node_jvp(S, u, mutp, vx, vy).reshape(-1))
     direct = adj.lift_node_jvp(S, u, vx, vy) + g.reshape(-1) @ du
     assert abs(adj.lift_node_derivative(S, u, vx, vy) - direct) <= 1e-8 * abs(direct)
+
+
+@pytest.mark.parametrize("model,scheme", [(1, 0), (0, 1)])
+def test_smoother_jacobian_matches_central_differences(model, scheme):
+    """The complex-step Jacobian of one smoother iteration at frozen dt*,
+    blocks and eddy viscosity against central differences of the same map
+    (a perturbed C-grid state, away from the kinks of the switches)."""
+    x, y = fi.cgrid(16, 8, 2)
+    u = fi.perturbed_state(fi.uniform_state(16, 8, 0.7, 1.3), 0.01, seed=11)
+    cfl = 1.0 if scheme == 1 else 50.0
+    S = fas.Solver(x, y, fi.CGRID, 2, fas.Params(model=model, mach=0.7, alpha_deg=1.3, scheme=scheme,
+                                                 cfl=cfl, cfl_ramp=cfl), u)
+    J = adj.smoother_jacobian(S, u)
+    frozen = S.prepare(0)
+    v = np.random.default_rng(3).standard_normal(u.shape)
+    h = 1e-7
+    fd = (adj.smoother_map(S, u + h * v, frozen) - adj.smoother_map(S, u - h * v, frozen)) / (2 * h)
+    assert np.abs(J @ v.reshape(-1) - fd.reshape(-1)).max() < 1e-7 * np.abs(fd).max()
