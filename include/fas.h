@@ -36,7 +36,8 @@ typedef enum {
     FAS_EINVAL = -1,          /* bad argument, shape or parameter */
     FAS_ENOMEM = -2,          /* device allocation failed */
     FAS_EDEVICE = -3,         /* HIP runtime error */
-    FAS_DIVERGED = -4,        /* non-finite residual norm */
+    FAS_DIVERGED = -4,        /* non-finite or grown residual norm (state rolled back) */
+    FAS_STALLED = -5,         /* too little residual drop over the stall window */
     FAS_NOT_CONVERGED = -6    /* cycle cap reached before the requested drop */
 } fas_status;
 
@@ -46,7 +47,7 @@ enum {                                         /* smoother (Table "RK smoothers"
     FAS_AW3 = 0, FAS_PARK3J = 1, FAS_AW5J = 2, FAS_AW51 = 3, FAS_AW52 = 4, FAS_PARK51 = 5
 };
 
-#define FAS_PARAMS_VERSION 1
+#define FAS_PARAMS_VERSION 2
 
 typedef struct {
     int32_t version;        /* FAS_PARAMS_VERSION */
@@ -64,12 +65,39 @@ typedef struct {
     int32_t cycle_gamma;    /* 1: V-cycle, 2: W-cycle (Section 3) */
     int32_t nu1;            /* pre-smoothing iterations per level */
     int32_t precond_fp32;   /* 1: SGS blocks and sweeps in FP32 */
+    /* 0: the preconditioner blocks hold the convective flux-vector
+     * splitting alone, as printed (eqs. "d-l-u-matrices-W",
+     * "d-l-u-matrices-J"); 1: on RANS levels every face also adds the
+     * thin-layer scalar v_f = (mu + mu_t)_f (gamma / Pr) |S_f|^2 /
+     * (rho_f Omega_f) to D and subtracts it from the neighbour block (an
+     * extension for high-Reynolds-number boundary layers; no effect on
+     * Euler) */
+    int32_t viscous_blocks;
+    /* pseudo time step of Section 4.1 ("c* times the local mesh width"):
+     * 0: dt* = c* Omega / (r_xi + r_eta); 1: dt* = c* Omega / max(r_xi,
+     * r_eta), i.e. c* times the smaller of the two directional CFL steps,
+     * which on a Cartesian cell at alpha = 0 is c* dx / (|v_1| + a), the
+     * step of the Fourier analysis section */
+    int32_t dt_form;
+    /* stall test of fas_cycle / fas_batch_solve: a solve whose fine
+     * residual norm gained fewer than stall_orders orders over the last
+     * stall_window cycles stops with FAS_STALLED (stall_window 0: off) */
+    int32_t stall_window;
+    double  stall_orders;
+    /* growth test: a norm above growth_limit times the norm before the
+     * first cycle counts as divergence (0: off; non-finite norms always
+     * do).  A diverged solve restores the fine-level solution from before
+     * the cycle that diverged (the last iterate with a finite, not grown
+     * norm) */
+    double  growth_limit;
 } fas_params;
 
 typedef struct fas_grid_s *fas_grid;     /* opaque, library owned */
 typedef struct fas_state_s *fas_state;   /* opaque, bound to one device and stream */
 
-/* Fill *p with defaults: AW3, robust mode (eta 0.5, d 0.5, c* 1e4). */
+/* Fill *p with defaults: AW3, robust mode (eta 0.5, d 0.5, c* 1e4), the
+ * printed convective blocks (viscous_blocks 0), dt_form 1, no stall test,
+ * growth limit 1e8. */
 void fas_params_default(fas_params *p);
 
 /*
@@ -105,10 +133,32 @@ fas_status fas_state_create(fas_grid g, const fas_params *p, const double *u0,
 void fas_state_destroy(fas_state s);
 fas_status fas_state_set_params(fas_state s, const fas_params *p);
 
-/* Copy in / out the fine-level solution, and (nullable) the eddy viscosity
- * of the last fine-level smoother iteration ([nj][ni]). */
-fas_status fas_set_state(fas_state s, const double *u);
+/*
+ * Checkpoint and resume.  A state is its fine-level solution u, the
+ * physical time levels of dual time stepping (eq. "nonlin-eq": u^n and
+ * u^{n-1} of the BDF2 step in progress), the clock (time t, step dt,
+ * physical steps taken) and the count of FAS cycles of the current solve
+ * (it sets c* on the start-up ramp).  Flow parameters and mesh motion are
+ * the caller's (fas_state_set_params, fas_set_motion).
+ *
+ * fas_set_state: step = 0 makes the state steady (un, unm1, t, dt
+ * ignored); step = 1 restores the first physical step (implicit Euler,
+ * un required, unm1 ignored); step >= 2 a BDF2 step (un and unm1
+ * required).  dt must be > 0 when step > 0.  The coarse levels' time
+ * levels are restricted from the fine ones, as fas_dual_time_step does,
+ * so a state restored from fas_get_state / fas_get_time_levels continues
+ * bitwise as the uninterrupted one would.  n_cycles >= 0.
+ * fas_get_state: u and (nullable) the eddy viscosity of the last
+ * fine-level smoother iteration ([nj][ni]).
+ * fas_get_time_levels: un, unm1 (device [4][nj][ni], nullable; written
+ * only when the state holds them) and the clock (host, nullable).
+ * Errors: FAS_EINVAL, FAS_EDEVICE.
+ */
+fas_status fas_set_state(fas_state s, const double *u, const double *un, const double *unm1, double t,
+                         double dt, int32_t step, int32_t n_cycles);
 fas_status fas_get_state(fas_state s, double *u, double *mu_t);
+fas_status fas_get_time_levels(fas_state s, double *un, double *unm1, double *t, double *dt, int32_t *step,
+                               int32_t *n_cycles);
 /* Solution and FAS source term of any level ([4][nj_l][ni_l]; source may be NULL). */
 fas_status fas_get_level(fas_state s, int32_t level, double *u, double *source);
 
@@ -145,7 +195,10 @@ fas_status fas_sgs_apply(fas_state s, int32_t level, const double *r, double *x)
  * fine residual has dropped by drop_orders (<= 0: run max_cycles) or
  * max_cycles were run.  res_hist (host, may be NULL) receives the norm
  * before the first and after every cycle (max_cycles + 1 entries).
- * Returns FAS_OK, FAS_NOT_CONVERGED or FAS_DIVERGED; *n_done cycles ran.
+ * Returns FAS_OK, FAS_NOT_CONVERGED, FAS_STALLED (the params' stall test)
+ * or FAS_DIVERGED (a non-finite norm, or one above growth_limit times the
+ * first; the fine-level solution is then restored to the iterate before
+ * the cycle that diverged); *n_done cycles ran, the diverged one included.
  */
 fas_status fas_cycle(fas_state s, int32_t max_cycles, double drop_orders,
                      double *res_hist, int32_t *n_done);
@@ -218,7 +271,8 @@ void fas_batch_destroy(fas_batch b);
  * use_graph = 1 captures one batched cycle (cycle, norm, status update) in a
  * HIP graph once and replays it; 0 launches the same kernels directly.
  * Outputs (host, nullable): n_done[n] cycles run per case, status[n]
- * (FAS_OK, FAS_NOT_CONVERGED, FAS_DIVERGED), res_hist[n][max_cycles + 1]
+ * (FAS_OK, FAS_NOT_CONVERGED, FAS_STALLED, FAS_DIVERGED, with the
+ * diverged case rolled back as in fas_cycle), res_hist[n][max_cycles + 1]
  * norms before the first and after every cycle (entries after n_done are
  * unspecified).  Returns the worst per-case status.
  */
@@ -279,6 +333,19 @@ fas_status fas_batch_profile_read(fas_batch b, double *ms, int64_t *count);
  */
 fas_status fas_forces(fas_state s, double *cl, double *cd, double *dcl_du);
 fas_status fas_vjp(fas_state s, const double *lam, double *out);
+/*
+ * out = (dS/du)^T lam for the map S: u -> one fine-level smoother
+ * iteration from u (Section 4: the stages of the state's scheme with the
+ * split f^c / f^v blending of Section 4.1), with the quantities a smoother
+ * iteration freezes at its starting state held fixed: dt*, the SGS blocks
+ * and the eddy viscosity.  The transpose runs the stages backwards: each
+ * stage applies P^-T (the transposed sweeps of eq. "sgs-precon") and the
+ * transposed Jacobians of f^c and f^v at the stored stage states.  Steady
+ * fixed-mesh states only; the state's solution is left unchanged.  lam,
+ * out: device [4][nj][ni].  Errors: FAS_EINVAL (null, moving mesh, a dual
+ * time step taken), FAS_ENOMEM, FAS_EDEVICE.
+ */
+fas_status fas_vjp_smooth(fas_state s, const double *lam, double *out);
 fas_status fas_param_partials(fas_state s, double *dF_dalpha, double *dF_dmach, double *dcl_dparam);
 fas_status fas_sgs_apply_transpose(fas_state s, const double *r, double *x);
 fas_status fas_adjoint_solve(fas_state s, const double *rhs, double *lam, int32_t max_iter,
@@ -338,6 +405,17 @@ typedef struct {
 } fas_dfa_case;
 fas_status fas_dfa(const fas_dfa_case *cases, int32_t n_cases, double *amp, double *smooth, double *radius,
                    void *stream);
+
+/*
+ * Launch-size rule of the residual and preconditioner-block kernels: a
+ * launch of at most max_cells cells (over all cases of a batch) runs the
+ * four-lanes-per-cell variants (one face per lane), a larger one the
+ * one-lane-per-cell variants.  Both give bitwise the same results.
+ * max_cells < 0 restores the default (65536).  Process-wide; takes
+ * effect for launches enqueued after the call (graphs captured earlier
+ * keep their kernels).  Returns the previous value.
+ */
+int64_t fas_set_four_lane_limit(int64_t max_cells);
 
 /* Message of the last failing call on this thread (never NULL). */
 const char *fas_last_error(void);

@@ -108,6 +108,7 @@ struct Ctx {
     D4 mu_inf;
     double pr, prt, kappa2c;
     int rans, noslip, fine, viscous;
+    int part;             // 0: F = f^c + f^v; 1: f^c alone; 2: f^v alone (Section 4.1 split)
     int si, sj;
     int gp[4], gs[4];     // geometry seeds: plane and slot of derivative lane k (-1: none)
 };
@@ -440,7 +441,9 @@ __device__ void cell_residual(const Ctx &c, int i, int j, D4 F[4]) {
     for (int k = 0; k < 4; ++k) {
         D4 fc = (eC[k] - wC[k]) + (nC[k] - sC[k]);
         D4 fv = (eV[k] - wV[k]) + (nV[k] - sV[k]);
-        F[k] = fc / vol + fv / vol;
+        if (c.part == 0) F[k] = fc / vol + fv / vol;
+        else if (c.part == 1) F[k] = fc / vol;
+        else F[k] = fv / vol;
     }
 }
 
@@ -460,6 +463,7 @@ __device__ void make_ctx(Ctx &c, const Lay &L, const double *geo, const double *
     c.noslip = ph.rans;
     c.fine = 1;
     c.viscous = ph.rans;
+    c.part = 0;
     c.si = c.sj = -1000000;
 #pragma unroll
     for (int k = 0; k < 4; ++k) c.gp[k] = c.gs[k] = -1;
@@ -468,9 +472,11 @@ __device__ void make_ctx(Ctx &c, const Lay &L, const double *geo, const double *
 // ------------------------------------------------------------------ kernels
 // out += (dF/du)^T lam: every cell scatters (dF_c/du_s)^T lam_c to each
 // interior cell s its residual depends on (13 stencil positions mapped
-// through the boundary conditions).  out must be zeroed first.
+// through the boundary conditions).  out must be zeroed first.  part
+// selects F, its convective part f^c or its dissipative and viscous part
+// f^v.
 __global__ __launch_bounds__(TPB) void k_vjp(Lay L, const double *geo, const double *u, const double *mut,
-                                             Phys ph, const double *lam, double *out) {
+                                             Phys ph, const double *lam, double *out, int part) {
     int s, i, j;
     if (!interior_cell(L, blockIdx.x * blockDim.x + threadIdx.x, s, i, j)) return;
     const int NS = L.NS;
@@ -479,6 +485,7 @@ __global__ __launch_bounds__(TPB) void k_vjp(Lay L, const double *geo, const dou
     for (int k = 0; k < 4; ++k) lc[k] = lam[k * NS + s];
     Ctx c;
     make_ctx(c, L, geo, u, mut, ph);
+    c.part = part;
     const int di[13] = {0, -1, 1, -2, 2, 0, 0, 0, 0, -1, 1, -1, 1};
     const int dj[13] = {0, 0, 0, 0, 0, -1, 1, -2, 2, -1, -1, 1, 1};
     int srci[13], srcj[13], n = 0;
@@ -1011,8 +1018,8 @@ __global__ void k_zero(double *p, size_t n) {
 
 // =================================================================== launchers
 void launch_vjp(const Lay &L, const double *geo, const double *u, const double *mut, const Phys &ph,
-                const double *lam, double *out, hipStream_t st) {
-    hipLaunchKernelGGL(k_vjp, dim3(nblocks(L.ni * L.nj)), dim3(TPB), 0, st, L, geo, u, mut, ph, lam, out);
+                const double *lam, double *out, hipStream_t st, int part) {
+    hipLaunchKernelGGL(k_vjp, dim3(nblocks(L.ni * L.nj)), dim3(TPB), 0, st, L, geo, u, mut, ph, lam, out, part);
 }
 
 void launch_param_partials(const Lay &L, const double *geo, const double *u, const double *mut,

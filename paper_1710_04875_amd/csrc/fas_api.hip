@@ -86,7 +86,11 @@ struct Engine {
     int has_src[8] = {0, 0, 0, 0, 0, 0, 0, 0};
     int bdf = 0;
     double dt = 0.0;
+    int vblk = 0;               // viscous term in the preconditioner blocks (RANS)
+    int stall_window = 0;       // stall test (0: off)
+    double stall_orders = 0.0, growth_limit = 0.0;
     int *d_cyc = nullptr;       // [n]
+    int *d_rb = nullptr;        // [n] roll-back flags of the status update
     double *d_norm = nullptr;   // [n]
     // optional per-kernel-class timing with HIP events on the stream
     int prof = 0;
@@ -117,6 +121,8 @@ struct fas_state_s {
     std::vector<LevelDev> lv;
     Engine e;
     int have_un = 0;
+    double t = 0.0;             // physical time and steps taken (dual time stepping)
+    int step = 0;
     Phys *d_ph = nullptr;
     LevelDev *d_lv = nullptr;             // device copy of lv
     // rigidly rotating mesh: per-level rotated geometry and the motion
@@ -129,6 +135,7 @@ struct fas_state_s {
     double *a_lam = nullptr, *a_g = nullptr, *a_r = nullptr, *a_z = nullptr, *a_jt = nullptr,
            *a_lam0 = nullptr, *a_zeta = nullptr, *a_dFa = nullptr, *a_dFm = nullptr, *a_dcl = nullptr,
            *a_red = nullptr, *a_out = nullptr, *a_basis = nullptr;
+    double *a_smv = nullptr;    // smoother VJP: stage states and work vectors (lazy)
     // graph-replayed cycles: activity flag (read by every kernel of the
     // state), cycles done, status, initial norm, history; a private stream
     // to capture on (the state's own stream may be the legacy default)
@@ -176,6 +183,11 @@ extern "C" void fas_params_default(fas_params *p) {
     p->cycle_gamma = 1;
     p->nu1 = 1;
     p->precond_fp32 = 0;
+    p->viscous_blocks = 0;
+    p->dt_form = 1;
+    p->stall_window = 0;
+    p->stall_orders = 0.0;
+    p->growth_limit = 1.0e8;
 }
 
 // upload the nodes of every level (every 2^l-th node of the fine grid) and
@@ -299,6 +311,10 @@ static fas_status check_params(const fas_params *p, int grid_levels) {
     if (!(p->mach > 0.0) || (p->model == FAS_RANS_BL && !(p->reynolds > 0.0)))
         return fail(FAS_EINVAL, "bad flow parameters");
     if (p->precond_fp32 != 0 && p->precond_fp32 != 1) return fail(FAS_EINVAL, "bad precond_fp32");
+    if (p->viscous_blocks != 0 && p->viscous_blocks != 1) return fail(FAS_EINVAL, "bad viscous_blocks");
+    if (p->dt_form != 0 && p->dt_form != 1) return fail(FAS_EINVAL, "bad dt_form");
+    if (p->stall_window < 0 || !(p->stall_orders >= 0.0) || !(p->growth_limit >= 0.0))
+        return fail(FAS_EINVAL, "bad stall or growth test");
     return FAS_OK;
 }
 
@@ -323,6 +339,7 @@ static void fill_phys(const fas_params &p, Phys &ph) {
     ph.cfl_ramp = p.cfl_ramp;
     ph.ramp_growth = p.ramp_growth;
     ph.n_ramp = p.n_ramp;
+    ph.dt_form = p.dt_form;
     ph.rans = p.model == FAS_RANS_BL;
     ph.ale = 0;
     ph.omega = ph.px = ph.py = 0.0;
@@ -342,6 +359,10 @@ static fas_status set_phys(fas_state s) {
     e.gamma = s->p.cycle_gamma;
     e.nu1 = s->p.nu1;
     e.sc = SCHEMES[s->p.scheme];
+    e.vblk = s->p.viscous_blocks;
+    e.stall_window = s->p.stall_window;
+    e.stall_orders = s->p.stall_orders;
+    e.growth_limit = s->p.growth_limit;
     HIPCHK(hipStreamSynchronize(e.st));
     HIPCHK(hipMemcpyAsync(s->d_ph, &s->ph, sizeof(Phys), hipMemcpyHostToDevice, e.st));
     HIPCHK(hipStreamSynchronize(e.st));
@@ -400,7 +421,7 @@ extern "C" fas_status fas_state_create(fas_grid g, const fas_params *p, const do
         d.L = g->lay[l];
         d.geo = g->geo[l];
         const size_t NS = d.L.NS;
-        const size_t nd = (size_t)(4 * 8 + 2 + Q_NPLANES + V_NPLANES) * NS + 256;
+        const size_t nd = (size_t)(4 * 9 + 2 + Q_NPLANES + V_NPLANES) * NS + 256;
         const size_t nb = (size_t)BLK_NPLANES * NS * 8 + (size_t)8 * NS * 8 + bnd_count(d.L) * 8;
         double *base = nullptr;
         char *bb = nullptr;
@@ -414,7 +435,7 @@ extern "C" fas_status fas_state_create(fas_grid g, const fas_params *p, const do
         double *q = base;
         auto take = [&](size_t n) { double *r = q; q += n * NS; return r; };
         d.u = take(4); d.u0 = take(4); d.acc = take(4); d.F = take(4);
-        d.src = take(4); d.ut = take(4); d.un = take(4); d.unm1 = take(4);
+        d.src = take(4); d.ut = take(4); d.un = take(4); d.unm1 = take(4); d.ulast = take(4);
         d.dts = take(1); d.mut = take(1); d.cq = take(Q_NPLANES); d.vg = take(V_NPLANES);
         d.red = q;
         d.blk = bb;
@@ -445,7 +466,9 @@ extern "C" fas_status fas_state_create(fas_grid g, const fas_params *p, const do
     s->d_act = reinterpret_cast<int *>(gc + 16);
     s->d_ndone = reinterpret_cast<int *>(gc + 20);
     s->d_stat = reinterpret_cast<int *>(gc + 24);
+    e.d_rb = reinterpret_cast<int *>(gc + 28);
     launch_fill_int(s->d_act, 1, 1, e.st);
+    launch_fill_int(e.d_rb, 1, 0, e.st);
     if (hipHostMalloc(reinterpret_cast<void **>(&s->h_act), sizeof(int), hipHostMallocDefault) != hipSuccess)
         return cleanup(fail(FAS_ENOMEM, "pinned allocation failed"));
     for (int l = 0; l < s->nlev; ++l)
@@ -498,10 +521,53 @@ extern "C" fas_status fas_set_motion(fas_state s, double dalpha_deg, double rate
     return set_phys(s);
 }
 
-extern "C" fas_status fas_set_state(fas_state s, const double *u) {
+extern "C" fas_status fas_set_state(fas_state s, const double *u, const double *un, const double *unm1, double t,
+                                    double dt, int32_t step, int32_t n_cycles) {
     if (!s || !u) return fail(FAS_EINVAL, "null argument");
-    launch_unpack(s->lv[0].L, u, s->lv[0].u, 4, s->e.st);
+    if (step < 0 || n_cycles < 0) return fail(FAS_EINVAL, "negative step or cycle count");
+    if (step > 0 && (!(dt > 0.0) || !std::isfinite(t) || !un || (step > 1 && !unm1)))
+        return fail(FAS_EINVAL, "a time-accurate state needs dt > 0, a finite t, un and (step > 1) unm1");
+    Engine &e = s->e;
+    launch_unpack(s->lv[0].L, u, s->lv[0].u, 4, e.st);
+    if (step > 0) {
+        // the time levels of the step in progress, restricted to the coarse
+        // levels exactly as fas_dual_time_step restricts them
+        launch_unpack(s->lv[0].L, un, s->lv[0].un, 4, e.st);
+        for (int l = 1; l < s->nlev; ++l) launch_restrict(e.lev[l - 1], e.lev[l], FLD_UN, FLD_UN, FLD_NONE, e.st);
+        if (step > 1) {
+            launch_unpack(s->lv[0].L, unm1, s->lv[0].unm1, 4, e.st);
+            for (int l = 1; l < s->nlev; ++l)
+                launch_restrict(e.lev[l - 1], e.lev[l], FLD_UNM1, FLD_UNM1, FLD_NONE, e.st);
+        }
+        e.bdf = step > 1 ? 2 : 1;
+        e.dt = dt;
+        s->have_un = 1;
+        s->t = t;
+    } else {
+        e.bdf = 0;
+        e.dt = 0.0;
+        s->have_un = 0;
+        s->t = 0.0;
+    }
+    s->step = step;
+    launch_fill_int(e.d_cyc, 1, n_cycles, e.st);
     HIPCHK(hipGetLastError());
+    return FAS_OK;
+}
+
+extern "C" fas_status fas_get_time_levels(fas_state s, double *un, double *unm1, double *t, double *dt,
+                                          int32_t *step, int32_t *n_cycles) {
+    if (!s) return fail(FAS_EINVAL, "null state");
+    Engine &e = s->e;
+    if (un && s->step > 0) launch_pack(s->lv[0].L, s->lv[0].un, un, 4, e.st);
+    if (unm1 && s->step > 1) launch_pack(s->lv[0].L, s->lv[0].unm1, unm1, 4, e.st);
+    int nc = 0;
+    HIPCHK(hipMemcpyAsync(&nc, e.d_cyc, sizeof(int), hipMemcpyDeviceToHost, e.st));
+    HIPCHK(hipStreamSynchronize(e.st));
+    if (t) *t = s->t;
+    if (dt) *dt = e.dt;
+    if (step) *step = s->step;
+    if (n_cycles) *n_cycles = nc;
     return FAS_OK;
 }
 
@@ -619,7 +685,7 @@ void prepare_iteration(Engine &e, int l, bool prepped = false, bool copy_u0 = fa
     const BLev &B = e.lev[l];
     if (!prepped) prep(e, l, fine_rans(e, l));
     Prof pr(e, FAS_PROF_BLOCKS);
-    launch_blocks(B, e.sc.aw, tau_of(e), rans(e), e.fp32, e.st, copy_u0 ? 1 : 0);
+    launch_blocks(B, e.sc.aw, tau_of(e), rans(e) && e.vblk, e.fp32, e.st, copy_u0 ? 1 : 0);
 }
 
 // one smoother iteration (Section 4 low-storage stages)
@@ -755,14 +821,70 @@ extern "C" fas_status fas_sgs_apply(fas_state s, int32_t level, const double *r,
     return FAS_OK;
 }
 
-// fas_cycle by graph replay: the cycle, its norm and the stopping test are
-// captured once per call (so every host-side setting in force is the one
-// replayed) on the state's private stream and replayed on its own stream;
-// the activity flag turns the replays after the stop into no-ops, so the
-// iterates, history and count are those of the direct launches.  The host
-// reads the flag every few cycles.
-static fas_status cycle_graph(fas_state s, int32_t max_cycles, double drop_orders, double *res_hist,
-                              int32_t *n_done) {
+namespace {
+
+// Convergence control of a solve (single state or batch): norms, history,
+// activity, cycle counts and status live on the device and are updated by
+// the status kernel after every cycle, so graph-replayed and directly
+// launched cycles behave the same.
+BatchCtl make_ctl(const Engine &e, double *h0, double *hist, int hcap, int *act, int *ndone, int *stat,
+                  int max_cycles, double drop_orders) {
+    BatchCtl ctl;
+    ctl.nrm = e.d_norm;
+    ctl.h0 = h0;
+    ctl.hist = hist;
+    ctl.hcap = hcap;
+    ctl.act = act;
+    ctl.cyc = e.d_cyc;
+    ctl.ndone = ndone;
+    ctl.stat = stat;
+    ctl.drop_factor = drop_orders > 0.0 ? std::pow(10.0, -drop_orders) : 0.0;
+    ctl.max_cycles = max_cycles;
+    ctl.stall_window = e.stall_window;
+    ctl.stall_factor = std::pow(10.0, -e.stall_orders);
+    ctl.growth_limit = e.growth_limit;
+    ctl.rb = e.d_rb;
+    return ctl;
+}
+
+// one controlled cycle: keep the fine solution, cycle (right after a norm
+// evaluation), norm, status update, roll-back of a case that diverged
+void controlled_cycle(Engine &e, const BatchCtl &ctl) {
+    launch_save_u(e.lev[0], e.st);
+    cycle(e, 0, true);
+    eval_norm(e);
+    launch_batch_status(ctl, e.n, e.st);
+    launch_rollback(e.lev[0], ctl.rb, e.st);
+}
+
+// refill every level's band hand-off array with the sentinel (after a
+// diverged solve: a sweep whose bounded wait ran out may have left a
+// value in a slot)
+void rearm_handoff(const std::vector<LevelDev> &lv, hipStream_t st) {
+    for (const LevelDev &d : lv)
+        launch_fill_int(reinterpret_cast<int *>(d.bnd), (int)(2 * bnd_count(d.L)), (int)BND_SENTINEL32, st);
+}
+
+const char *status_message(int st) {
+    switch (st) {
+        case FAS_DIVERGED: return "residual norm is not finite or grew beyond the limit (solution rolled back)";
+        case FAS_STALLED: return "residual drop stalled";
+        case FAS_NOT_CONVERGED: return "cycle cap reached before the requested residual drop";
+        default: return "no error";
+    }
+}
+
+}  // namespace
+
+// FAS cycles of one state under the device convergence control.  With
+// use_graph the cycle, its norm and the status update are captured once per
+// call (so every host-side setting in force is the one replayed) on the
+// state's private stream and replayed on its own stream; the activity flag
+// turns the replays after the stop into no-ops, so the iterates, history
+// and count are those of the direct launches.  The host reads the flag
+// every few cycles.
+static fas_status run_cycles(fas_state s, int32_t max_cycles, double drop_orders, double *res_hist,
+                             int32_t *n_done, bool use_graph) {
     Engine &e = s->e;
     if (max_cycles + 1 > s->hcap) {
         HIPCHK(hipStreamSynchronize(e.st));
@@ -776,58 +898,53 @@ static fas_status cycle_graph(fas_state s, int32_t max_cycles, double drop_order
         s->allocs.push_back(s->d_hist);
         s->hcap = max_cycles + 1;
     }
-    if (!s->cap_st) HIPCHK(hipStreamCreateWithFlags(&s->cap_st, hipStreamNonBlocking));
-    BatchCtl ctl;
-    ctl.nrm = e.d_norm;
-    ctl.h0 = s->d_h0;
-    ctl.hist = s->d_hist;
-    ctl.hcap = s->hcap;
-    ctl.act = s->d_act;
-    ctl.cyc = e.d_cyc;
-    ctl.ndone = s->d_ndone;
-    ctl.stat = s->d_stat;
-    ctl.drop_factor = drop_orders > 0.0 ? std::pow(10.0, -drop_orders) : 0.0;
-    ctl.max_cycles = max_cycles;
+    const BatchCtl ctl = make_ctl(e, s->d_h0, s->d_hist, s->hcap, s->d_act, s->d_ndone, s->d_stat, max_cycles,
+                                  drop_orders);
     launch_fill_int(s->d_act, 1, 1, e.st);
     eval_norm(e);
     launch_batch_init(ctl, 1, e.st);
     HIPCHK(hipGetLastError());
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
-    const hipStream_t own = e.st;
-    e.st = s->cap_st;
-    hipError_t er = hipStreamBeginCapture(e.st, hipStreamCaptureModeThreadLocal);
-    if (er == hipSuccess) {
-        cycle(e, 0, true);       // the norm before the capture, then each replay's own
-        eval_norm(e);
-        launch_batch_status(ctl, 1, e.st);
-        er = hipStreamEndCapture(e.st, &graph);
-    }
-    e.st = own;
-    if (er == hipSuccess) er = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
-    if (er != hipSuccess) {
-        if (graph) (void)hipGraphDestroy(graph);
-        return fail(FAS_EDEVICE, std::string("graph capture failed: ") + hipGetErrorString(er));
+    if (use_graph) {
+        if (!s->cap_st) HIPCHK(hipStreamCreateWithFlags(&s->cap_st, hipStreamNonBlocking));
+        const hipStream_t own = e.st;
+        e.st = s->cap_st;
+        hipError_t er = hipStreamBeginCapture(e.st, hipStreamCaptureModeThreadLocal);
+        if (er == hipSuccess) {
+            controlled_cycle(e, ctl);
+            er = hipStreamEndCapture(e.st, &graph);
+        }
+        e.st = own;
+        if (er == hipSuccess) er = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+        if (er != hipSuccess) {
+            if (graph) (void)hipGraphDestroy(graph);
+            return fail(FAS_EDEVICE, std::string("graph capture failed: ") + hipGetErrorString(er));
+        }
     }
     const int check = 4;
     fas_status st = FAS_OK;
     for (int k = 0; k < max_cycles; ++k) {
-        if (hipGraphLaunch(exec, e.st) != hipSuccess) {
-            st = fail(FAS_EDEVICE, "graph launch failed");
-            break;
+        if (use_graph) {
+            if (hipGraphLaunch(exec, e.st) != hipSuccess) {
+                st = fail(FAS_EDEVICE, "graph launch failed");
+                break;
+            }
+        } else {
+            controlled_cycle(e, ctl);
         }
         if ((k + 1) % check == 0 || k + 1 == max_cycles) {
             if (hipMemcpyAsync(s->h_act, s->d_act, sizeof(int), hipMemcpyDeviceToHost, e.st) != hipSuccess ||
                 hipStreamSynchronize(e.st) != hipSuccess) {
-                st = fail(FAS_EDEVICE, "graph replay failed");
+                st = fail(FAS_EDEVICE, "cycle replay failed");
                 break;
             }
             if (!*s->h_act) break;
         }
     }
     (void)hipStreamSynchronize(e.st);
-    (void)hipGraphExecDestroy(exec);
-    (void)hipGraphDestroy(graph);
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
     if (st != FAS_OK) return st;
     int nd = 0, stv = 0;
     HIPCHK(hipMemcpyAsync(&nd, s->d_ndone, sizeof(int), hipMemcpyDeviceToHost, e.st));
@@ -837,41 +954,19 @@ static fas_status cycle_graph(fas_state s, int32_t max_cycles, double drop_order
                               e.st));
     launch_fill_int(s->d_act, 1, 1, e.st);
     HIPCHK(hipStreamSynchronize(e.st));
+    if (stv == FAS_DIVERGED) rearm_handoff(s->lv, e.st);
     HIPCHK(hipGetLastError());
     if (n_done) *n_done = nd;
-    if (stv == FAS_DIVERGED) g_err = "residual norm is not finite";
-    if (stv == FAS_NOT_CONVERGED) g_err = "cycle cap reached before the requested residual drop";
+    if (stv != FAS_OK) g_err = status_message(stv);
     return (fas_status)stv;
 }
 
 extern "C" fas_status fas_cycle(fas_state s, int32_t max_cycles, double drop_orders, double *res_hist,
                                 int32_t *n_done) {
     if (!s || max_cycles < 0) return fail(FAS_EINVAL, "bad argument");
-    Engine &e = s->e;
-    // enough cycles to repay a capture, and no per-launch profiling events
-    if (max_cycles >= 4 && !e.prof) return cycle_graph(s, max_cycles, drop_orders, res_hist, n_done);
-    double h0 = 0.0, h = 0.0;
-    STCHK(norm(s, &h0));
-    if (res_hist) res_hist[0] = h0;
-    int done = 0;
-    fas_status st = FAS_OK;
-    if (!std::isfinite(h0)) st = FAS_DIVERGED;
-    for (int k = 0; k < max_cycles && st == FAS_OK; ++k) {
-        cycle(e, 0, true);       // right after a norm evaluation
-        launch_count_cycle(e.lev[0], e.d_cyc, e.st);
-        ++done;
-        STCHK(norm(s, &h));
-        if (res_hist) res_hist[k + 1] = h;
-        if (!std::isfinite(h)) { st = FAS_DIVERGED; break; }
-        if (drop_orders > 0.0 && h <= h0 * std::pow(10.0, -drop_orders)) break;
-    }
-    if (n_done) *n_done = done;
-    HIPCHK(hipGetLastError());
-    if (st == FAS_OK && drop_orders > 0.0 && !(h <= h0 * std::pow(10.0, -drop_orders)) && done == max_cycles)
-        st = FAS_NOT_CONVERGED;
-    if (st == FAS_DIVERGED) g_err = "residual norm is not finite";
-    if (st == FAS_NOT_CONVERGED) g_err = "cycle cap reached before the requested residual drop";
-    return st;
+    // graph replay when there are enough cycles to repay a capture and no
+    // per-launch profiling events
+    return run_cycles(s, max_cycles, drop_orders, res_hist, n_done, max_cycles >= 4 && !s->e.prof);
 }
 
 extern "C" fas_status fas_dual_time_step(fas_state s, double dt, double alpha_deg, int32_t max_inner,
@@ -885,6 +980,8 @@ extern "C" fas_status fas_dual_time_step(fas_state s, double dt, double alpha_de
     e.bdf = s->have_un ? 2 : 1;
     s->have_un = 1;
     e.dt = dt;
+    s->t += dt;
+    s->step += 1;
     launch_fill_int(e.d_cyc, 1, 0, e.st);
     s->p.alpha_deg = alpha_deg;
     STCHK(set_phys(s));
@@ -1092,6 +1189,89 @@ extern "C" fas_status fas_vjp(fas_state s, const double *lam, double *out) {
     return FAS_OK;
 }
 
+// Transpose of one fine-level smoother iteration at frozen dt*, blocks and
+// eddy viscosity (the quantities the iteration fixes at its start).  With
+// u_0 = u, acc_0 = f^v(u_0) and, per stage i = 1..s,
+//     u_i = u_0 - alpha_i x_i,  x_i = W^-1 (dt* r_{i-1}) (AW) or dt* P^-1 r_{i-1}
+//     r_{i-1} = f^c(u_{i-1}) + acc_{i-1},
+//     acc_i = beta_{i+1} f^v(u_i) + (1 - beta_{i+1}) acc_{i-1}   (i < s),
+// the reverse sweep carries w = adjoint of u_i and a = adjoint of acc_i:
+//     i = s .. 1:  (i < s) w += beta_{i+1} J_v(u_i)^T a, a *= 1 - beta_{i+1}
+//                  out += w;  xbar = -alpha_i w
+//                  rbar = dt* P^-T xbar (AW) or P^-T (dt* xbar)
+//                  w = J_c(u_{i-1})^T rbar;  a += rbar
+//     out += w + J_v(u_0)^T a.
+extern "C" fas_status fas_vjp_smooth(fas_state s, const double *lam, double *out) {
+    if (!s || !lam || !out) return fail(FAS_EINVAL, "null argument");
+    if (s->ale) return fail(FAS_EINVAL, "the adjoint is for fixed meshes");
+    if (s->e.bdf != 0) return fail(FAS_EINVAL, "the smoother adjoint is for steady states");
+    STCHK(ensure_adjoint(s));
+    Engine &e = s->e;
+    const LevelDev &d = s->lv[0];
+    const size_t V = (size_t)4 * d.L.NS;
+    const int ns = e.sc.s;
+    if (!s->a_smv) {
+        HIPCHK(hipMalloc(&s->a_smv, (size_t)(5 + 6) * V * sizeof(double)));
+        s->allocs.push_back(s->a_smv);
+        launch_zero(s->a_smv, (size_t)(5 + 6) * V, e.st);
+    }
+    double *stage[5];
+    for (int k = 0; k < 5; ++k) stage[k] = s->a_smv + (size_t)k * V;
+    double *w = s->a_smv + 5 * V, *ab = w + V, *rb = ab + V, *xb = rb + V, *tmp = xb + V, *acc = tmp + V;
+    // forward iteration from the current solution, keeping u_0 .. u_{s-1}
+    const BLev &B = e.lev[0];
+    prepare_iteration(e, 0, false, true);
+    launch_axpby_ptr(d.L, 1.0, d.u, 0.0, nullptr, stage[0], e.st);
+    for (int k = 0; k < ns; ++k) {
+        if (k > 0) prep(e, 0, false);
+        ResArgs a = res_args(e, 0, 1, 1);
+        a.stage = k;
+        a.beta = e.sc.beta[k];
+        launch_residual(B, a, e.st);
+        SweepArgs sw;
+        std::memset(&sw, 0, sizeof(sw));
+        sw.update = 1;
+        sw.alpha = e.sc.alpha[k];
+        sw.aw = e.sc.aw;
+        launch_sgs(B, sw, e.fp32, e.st);
+        if (k + 1 < ns) launch_axpby_ptr(d.L, 1.0, d.u, 0.0, nullptr, stage[k + 1], e.st);
+    }
+    // the state keeps its solution
+    launch_axpby(B, 1.0, FLD_U0, 0.0, FLD_NONE, FLD_U, e.st);
+    // reverse sweep
+    launch_unpack(d.L, lam, w, 4, e.st);
+    launch_zero(ab, V, e.st);
+    launch_zero(acc, V, e.st);
+    for (int i = ns; i >= 1; --i) {
+        if (i < ns) {
+            const double b = e.sc.beta[i];      // beta_{i+1} in the paper's 1-based stage count
+            launch_zero(tmp, V, e.st);
+            launch_vjp(d.L, d.geo, stage[i], d.mut, s->ph, ab, tmp, e.st, 2);
+            launch_axpby_ptr(d.L, 1.0, w, b, tmp, w, e.st);
+            launch_axpby_ptr(d.L, 1.0 - b, ab, 0.0, nullptr, ab, e.st);
+        }
+        launch_axpby_ptr(d.L, 1.0, acc, 1.0, w, acc, e.st);
+        launch_axpby_ptr(d.L, -e.sc.alpha[i - 1], w, 0.0, nullptr, xb, e.st);
+        if (e.sc.aw) {
+            launch_sgs_transpose(d.L, d.blk, xb, s->a_zeta, s->a_z, e.fp32, e.st);
+            launch_adj_update(d.L, nullptr, 1.0, d.dts, s->a_z, rb, e.st);
+        } else {
+            launch_adj_update(d.L, nullptr, 1.0, d.dts, xb, s->a_z, e.st);
+            launch_sgs_transpose(d.L, d.blk, s->a_z, s->a_zeta, rb, e.fp32, e.st);
+        }
+        launch_zero(w, V, e.st);
+        launch_vjp(d.L, d.geo, stage[i - 1], d.mut, s->ph, rb, w, e.st, 1);
+        launch_axpby_ptr(d.L, 1.0, ab, 1.0, rb, ab, e.st);
+    }
+    launch_zero(tmp, V, e.st);
+    launch_vjp(d.L, d.geo, stage[0], d.mut, s->ph, ab, tmp, e.st, 2);
+    launch_axpby_ptr(d.L, 1.0, acc, 1.0, w, acc, e.st);
+    launch_axpby_ptr(d.L, 1.0, acc, 1.0, tmp, acc, e.st);
+    launch_pack(d.L, acc, out, 4, e.st);
+    HIPCHK(hipGetLastError());
+    return FAS_OK;
+}
+
 // dx, dy = (dG/dX)^T ((dF/dG)^T lam (+ dC_L/dG)) at the prepared fine level
 static fas_status node_gradient(fas_state s, const double *lam, bool with_lift, double *dx, double *dy) {
     const LevelDev &d = s->lv[0];
@@ -1268,8 +1448,11 @@ extern "C" fas_status fas_batch_create(int32_t n, const fas_state *states, void 
         if (s->g->device != s0->g->device) return fail(FAS_EINVAL, "states on different devices");
         if (s->p.model != s0->p.model || s->p.scheme != s0->p.scheme || s->nlev != s0->nlev ||
             s->p.cycle_gamma != s0->p.cycle_gamma || s->p.nu1 != s0->p.nu1 ||
-            s->p.precond_fp32 != s0->p.precond_fp32)
-            return fail(FAS_EINVAL, "batched states must share model, scheme, levels, cycle and precision");
+            s->p.precond_fp32 != s0->p.precond_fp32 || s->p.viscous_blocks != s0->p.viscous_blocks ||
+            s->p.stall_window != s0->p.stall_window || s->p.stall_orders != s0->p.stall_orders ||
+            s->p.growth_limit != s0->p.growth_limit)
+            return fail(FAS_EINVAL, "batched states must share model, scheme, levels, cycle, precision, "
+                                    "preconditioner form and stopping tests");
         if (s->e.bdf != 0 || s->ale)
             return fail(FAS_EINVAL, "batched states must be steady on fixed meshes (no dual time step, no motion)");
         for (int k = 0; k < c; ++k)
@@ -1297,9 +1480,13 @@ extern "C" fas_status fas_batch_create(int32_t n, const fas_state *states, void 
     e.gamma = s0->p.cycle_gamma;
     e.nu1 = s0->p.nu1;
     e.sc = SCHEMES[s0->p.scheme];
+    e.vblk = s0->p.viscous_blocks;
+    e.stall_window = s0->p.stall_window;
+    e.stall_orders = s0->p.stall_orders;
+    e.growth_limit = s0->p.growth_limit;
     // device arrays: per level n descriptors, n physics records, control
     const size_t nl = (size_t)e.nlev * n;
-    const size_t bytes = nl * sizeof(LevelDev) + (size_t)n * sizeof(Phys) + (size_t)n * (4 * sizeof(int) + 2 * sizeof(double)) + 256;
+    const size_t bytes = nl * sizeof(LevelDev) + (size_t)n * sizeof(Phys) + (size_t)n * (5 * sizeof(int) + 2 * sizeof(double)) + 256;
     char *dd = nullptr;
     if (hipMalloc(&dd, bytes) != hipSuccess) return cleanup(fail(FAS_ENOMEM, "batch allocation failed"));
     b->allocs.push_back(dd);
@@ -1312,7 +1499,8 @@ extern "C" fas_status fas_batch_create(int32_t n, const fas_state *states, void 
     e.d_cyc = reinterpret_cast<int *>(q); q += n * sizeof(int);
     b->d_act = reinterpret_cast<int *>(q); q += n * sizeof(int);
     b->d_ndone = reinterpret_cast<int *>(q); q += n * sizeof(int);
-    b->d_stat = reinterpret_cast<int *>(q);
+    b->d_stat = reinterpret_cast<int *>(q); q += n * sizeof(int);
+    e.d_rb = reinterpret_cast<int *>(q);
     std::vector<LevelDev> hV(nl);
     std::vector<Phys> hPH(n);
     for (int l = 0; l < e.nlev; ++l)
@@ -1324,6 +1512,7 @@ extern "C" fas_status fas_batch_create(int32_t n, const fas_state *states, void 
     if (hipHostMalloc(reinterpret_cast<void **>(&b->h_act), n * sizeof(int), hipHostMallocDefault) != hipSuccess)
         return cleanup(fail(FAS_ENOMEM, "pinned allocation failed"));
     launch_fill_int(b->d_act, n, 1, e.st);
+    launch_fill_int(e.d_rb, n, 0, e.st);
     for (int l = 0; l < e.nlev; ++l) {
         std::vector<Lay> lays;
         for (int c = 0; c < n; ++c) lays.push_back(states[c]->lv[l].L);
@@ -1398,14 +1587,6 @@ extern "C" fas_status fas_batch_set_sweep_config(fas_batch b, int32_t level, int
     return FAS_OK;
 }
 
-// one batched cycle followed by the norm and the per-case status update
-static void batch_step(fas_batch b, const BatchCtl &ctl) {
-    Engine &e = b->e;
-    cycle(e, 0, true);           // the norm before the loop, then each step's own
-    eval_norm(e);
-    launch_batch_status(ctl, e.n, e.st);
-}
-
 extern "C" fas_status fas_batch_solve(fas_batch b, int32_t max_cycles, double drop_orders, int32_t use_graph,
                                       int32_t *n_done, int32_t *status, double *res_hist) {
     if (!b || max_cycles < 0) return fail(FAS_EINVAL, "bad argument");
@@ -1424,17 +1605,8 @@ extern "C" fas_status fas_batch_solve(fas_batch b, int32_t max_cycles, double dr
         b->allocs.push_back(b->d_hist);
         b->hcap = max_cycles + 1;
     }
-    BatchCtl ctl;
-    ctl.nrm = e.d_norm;
-    ctl.h0 = b->d_h0;
-    ctl.hist = b->d_hist;
-    ctl.hcap = b->hcap;
-    ctl.act = b->d_act;
-    ctl.cyc = e.d_cyc;
-    ctl.ndone = b->d_ndone;
-    ctl.stat = b->d_stat;
-    ctl.drop_factor = drop_orders > 0.0 ? std::pow(10.0, -drop_orders) : 0.0;
-    ctl.max_cycles = max_cycles;
+    const BatchCtl ctl = make_ctl(e, b->d_h0, b->d_hist, b->hcap, b->d_act, b->d_ndone, b->d_stat, max_cycles,
+                                  drop_orders);
     // every case starts active; its c* ramp continues from its own count
     launch_fill_int(b->d_act, n, 1, e.st);
     for (int c = 0; c < n; ++c)
@@ -1448,7 +1620,7 @@ extern "C" fas_status fas_batch_solve(fas_batch b, int32_t max_cycles, double dr
         const int prof = e.prof;
         e.prof = 0;
         HIPCHK(hipStreamBeginCapture(e.st, hipStreamCaptureModeThreadLocal));
-        batch_step(b, ctl);
+        controlled_cycle(e, ctl);
         hipError_t er = hipStreamEndCapture(e.st, &b->graph);
         e.prof = prof;
         if (er != hipSuccess) return fail(FAS_EDEVICE, std::string("graph capture failed: ") + hipGetErrorString(er));
@@ -1459,7 +1631,7 @@ extern "C" fas_status fas_batch_solve(fas_batch b, int32_t max_cycles, double dr
     const int check = 4;
     for (int k = 0; k < max_cycles; ++k) {
         if (use_graph) HIPCHK(hipGraphLaunch(b->exec, e.st));
-        else batch_step(b, ctl);
+        else controlled_cycle(e, ctl);
         if ((k + 1) % check == 0 || k + 1 == max_cycles) {
             HIPCHK(hipMemcpyAsync(b->h_act, b->d_act, n * sizeof(int), hipMemcpyDeviceToHost, e.st));
             HIPCHK(hipStreamSynchronize(e.st));
@@ -1478,15 +1650,19 @@ extern "C" fas_status fas_batch_solve(fas_batch b, int32_t max_cycles, double dr
         HIPCHK(hipMemcpyAsync(res_hist, b->d_hist, (size_t)n * (max_cycles + 1) * sizeof(double),
                               hipMemcpyDeviceToHost, e.st));
     HIPCHK(hipStreamSynchronize(e.st));
+    // worst status: diverged, stalled, not converged, ok
+    auto rank = [](int st) {
+        return st == FAS_DIVERGED ? 3 : st == FAS_STALLED ? 2 : st == FAS_NOT_CONVERGED ? 1 : 0;
+    };
     int worst = FAS_OK;
     for (int c = 0; c < n; ++c) {
         if (n_done) n_done[c] = nd[c];
         if (status) status[c] = stv[c];
-        if (stv[c] == FAS_DIVERGED) worst = FAS_DIVERGED;
-        else if (stv[c] == FAS_NOT_CONVERGED && worst == FAS_OK) worst = FAS_NOT_CONVERGED;
+        if (rank(stv[c]) > rank(worst)) worst = stv[c];
+        if (stv[c] == FAS_DIVERGED) rearm_handoff(b->states[c]->lv, e.st);
     }
-    if (worst == FAS_DIVERGED) g_err = "residual norm of a batched case is not finite";
-    if (worst == FAS_NOT_CONVERGED) g_err = "cycle cap reached before the requested drop in a batched case";
+    HIPCHK(hipStreamSynchronize(e.st));
+    if (worst != FAS_OK) g_err = std::string("batched case: ") + status_message(worst);
     return (fas_status)worst;
 }
 
@@ -1499,6 +1675,8 @@ extern "C" fas_status fas_batch_profile_read(fas_batch b, double *ms, int64_t *c
     if (!b) return fail(FAS_EINVAL, "null batch");
     return profile_read(b->e, ms, count);
 }
+
+extern "C" int64_t fas_set_four_lane_limit(int64_t max_cells) { return set_four_lane_limit(max_cells); }
 
 extern "C" const char *fas_last_error(void) { return g_err.c_str(); }
 

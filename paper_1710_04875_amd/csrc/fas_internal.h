@@ -81,6 +81,7 @@ struct Phys {
     // ramp_growth per cycle up to cfl
     double cfl, cfl_ramp, ramp_growth;
     int n_ramp;
+    int dt_form;      // 0: dt* = c* Omega / (r_xi + r_eta); 1: c* Omega / max(r_xi, r_eta)
     int rans;
     // rigidly rotating mesh (ALE): rate omega about (px, py); grid
     // velocities omega x (r - pivot) are in the G_W* planes
@@ -98,6 +99,7 @@ struct LevelDev {
     double *src;      // 4 * NS   FAS source s_l (coarse levels)
     double *ut;       // 4 * NS   restricted solution u~ (coarse levels)
     double *un, *unm1;// 4 * NS   physical time levels
+    double *ulast;    // 4 * NS   solution before the current cycle (roll-back of a diverged cycle)
     double *dts;      // NS
     double *mut;      // NS       eddy viscosity (fine: Baldwin-Lomax; coarse: restricted)
     double *cq;       // Q_NPLANES * NS
@@ -124,7 +126,7 @@ constexpr unsigned long long BND_SENTINEL64 = 0x7FF5A5A57FF5A5A5ull;
 
 // 4-component vector fields of a level, addressed by name in batched
 // launches (each case has its own pointers)
-enum Field { FLD_U, FLD_U0, FLD_ACC, FLD_F, FLD_SRC, FLD_UT, FLD_UN, FLD_UNM1, FLD_NONE };
+enum Field { FLD_U, FLD_U0, FLD_ACC, FLD_F, FLD_SRC, FLD_UT, FLD_UN, FLD_UNM1, FLD_ULAST, FLD_NONE };
 
 __host__ __device__ inline double *field(const LevelDev &d, int f) {
     switch (f) {
@@ -136,6 +138,7 @@ __host__ __device__ inline double *field(const LevelDev &d, int f) {
         case FLD_UT: return d.ut;
         case FLD_UN: return d.un;
         case FLD_UNM1: return d.unm1;
+        case FLD_ULAST: return d.ulast;
         default: return nullptr;
     }
 }
@@ -235,8 +238,9 @@ void launch_fill_int(int *p, int n, int v, hipStream_t st);
 int norm_scratch_size();
 
 // discrete adjoint of the steady fine-level residual (frozen eddy viscosity)
+// out += (dF/du)^T lam (part 0), (df^c/du)^T lam (1) or (df^v/du)^T lam (2)
 void launch_vjp(const Lay &L, const double *geo, const double *u, const double *mut, const Phys &ph,
-                const double *lam, double *out, hipStream_t st);      // out += (dF/du)^T lam
+                const double *lam, double *out, hipStream_t st, int part = 0);
 void launch_param_partials(const Lay &L, const double *geo, const double *u, const double *mut,
                            const Phys &ph, double reynolds, double *dFa, double *dFm, hipStream_t st);
 // grid-node sensitivities: gbar (metric planes G_SXI_X .. G_YC, zeroed)
@@ -274,8 +278,21 @@ struct BatchCtl {
     int *act, *cyc, *ndone, *stat;
     double drop_factor;   // 10^-drop (0: run to max_cycles)
     int max_cycles;
+    int stall_window;     // > 0: stall test over this many cycles
+    double stall_factor;  // 10^-stall_orders
+    double growth_limit;  // > 0: a norm above growth_limit h0 is divergence
+    int *rb;              // [n] 1: the case diverged in this cycle (roll back its solution)
 };
+// status of the stall test (fas_status value)
+constexpr int ST_STALLED_CODE = -5;
 void launch_batch_init(const BatchCtl &c, int n, hipStream_t st);
 void launch_batch_status(const BatchCtl &c, int n, hipStream_t st);
+// fine level: ulast = u for the active cases (before a cycle); u = ulast
+// for the cases whose flag rb is set (after the status update)
+void launch_save_u(const BLev &B, hipStream_t st);
+void launch_rollback(const BLev &B, const int *rb, hipStream_t st);
+// four-lane residual / block kernels up to this many cells per launch
+long long four_lane_limit();
+long long set_four_lane_limit(long long cells);
 
 }  // namespace fas

@@ -88,7 +88,7 @@ __device__ inline void ld4(const double *a, int NS, int s, double v[4]) {
 #define FAS_GLOBAL __attribute__((address_space(1)))
 struct LevelDevG {
     Lay L;
-    FAS_GLOBAL double *geo, *u, *u0, *acc, *F, *src, *ut, *un, *unm1, *dts, *mut, *cq, *vg;
+    FAS_GLOBAL double *geo, *u, *u0, *acc, *F, *src, *ut, *un, *unm1, *ulast, *dts, *mut, *cq, *vg;
     FAS_GLOBAL char *blk, *g, *y, *bnd;
     FAS_GLOBAL double *red;
 };
@@ -109,6 +109,7 @@ __device__ inline bool take(const BK &b, int c, LevelDev &d) {
     d.ut = (double *)s.ut;
     d.un = (double *)s.un;
     d.unm1 = (double *)s.unm1;
+    d.ulast = (double *)s.ulast;
     d.dts = (double *)s.dts;
     d.mut = (double *)s.mut;
     d.cq = (double *)s.cq;
@@ -492,7 +493,9 @@ __device__ inline double cfl_of(const Phys &ph, int n) {
     return ph.cfl;
 }
 
-// Section 4.1: dt* = c* Omega / (r_xi + r_eta) of interior cell s
+// Section 4.1, dt* = c* times the local mesh width (reading): c* Omega /
+// (r_xi + r_eta), or with dt_form 1 c* Omega / max(r_xi, r_eta), the
+// smaller of the two directional CFL steps, of interior cell s
 __device__ inline double local_dt(const Phys &ph, double cfl, const double *geo, const double *u, int NS, int s) {
     double r = u[s], mx = u[NS + s], my = u[2 * NS + s], E = u[3 * NS + s];
     double vx = mx / r, vy = my / r;
@@ -504,7 +507,7 @@ __device__ inline double local_dt(const Phys &ph, double cfl, const double *geo,
     rel_normal(ph, geo, NS, s, vx, vy, sb0, sb1, sb2, sb3, vnx, vne);
     double rxi = fabs(vnx) + a * sqrt(sb0 * sb0 + sb1 * sb1);
     double reta = fabs(vne) + a * sqrt(sb2 * sb2 + sb3 * sb3);
-    return cfl * geo[G_VOL * NS + s] / (rxi + reta);
+    return cfl * geo[G_VOL * NS + s] / (ph.dt_form ? fmax(rxi, reta) : rxi + reta);
 }
 
 // Section 2: velocity and temperature gradients at vertices, Green-Gauss
@@ -1868,6 +1871,19 @@ __global__ void k_axpby(BK bk, double a, int fx, double b, int fy, int fout) {
     }
 }
 
+// roll-back of a diverged cycle: u = ulast on the interior cells of every
+// case flagged by the status update (the activity flag is already 0)
+__global__ void k_rollback(BK bk, const int *rb) {
+    if (rb[blockIdx.y] == 0) return;
+    const LevelDevG &g = reinterpret_cast<const LevelDevG *>(bk.V)[blockIdx.y];
+    const Lay L = g.L;
+    int s = blockIdx.x * blockDim.x + threadIdx.x;
+    int i, j;
+    if (!decode(L, s, i, j) || !interior(L, i, j)) return;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) g.u[k * L.NS + s] = g.ulast[k * L.NS + s];
+}
+
 __global__ void k_pack(Lay L, const double *p, double *n, int nc) {
     int t = blockIdx.x * blockDim.x + threadIdx.x;
     int N = L.ni * L.nj;
@@ -1931,7 +1947,7 @@ __global__ void k_fill_int(int *p, int n, int v) {
 }
 
 // status codes (fas_status values)
-constexpr int ST_OK = 0, ST_DIVERGED = -4, ST_NOT_CONVERGED = -6;
+constexpr int ST_OK = 0, ST_DIVERGED = -4, ST_STALLED = ST_STALLED_CODE, ST_NOT_CONVERGED = -6;
 
 __global__ void k_batch_init(BatchCtl c, int n) {
     int k = blockIdx.x * blockDim.x + threadIdx.x;
@@ -1946,17 +1962,29 @@ __global__ void k_batch_init(BatchCtl c, int n) {
 }
 
 // after the norm of a cycle: record it, count the cycle, stop the case when
-// the drop is reached, the norm is not finite or the cap is reached
+// the drop is reached, the norm is not finite or has grown beyond the limit
+// (flagging the case for the roll-back of its solution), the stall test
+// fails or the cap is reached
 __global__ void k_batch_status(BatchCtl c, int n) {
     int k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= n || c.act[k] == 0) return;
+    if (k >= n) return;
+    c.rb[k] = 0;
+    if (c.act[k] == 0) return;
     const double h = c.nrm[k];
     const int m = c.ndone[k] + 1;
     c.ndone[k] = m;
     c.cyc[k] = c.cyc[k] + 1;
     if (m < c.hcap) c.hist[(size_t)k * c.hcap + m] = h;
-    if (!isfinite(h)) {
+    if (!isfinite(h) || (c.growth_limit > 0.0 && h > c.growth_limit * c.h0[k])) {
         c.stat[k] = ST_DIVERGED;
+        c.act[k] = 0;
+        c.rb[k] = 1;
+    } else if (c.drop_factor > 0.0 && h <= c.h0[k] * c.drop_factor) {
+        c.stat[k] = ST_OK;
+        c.act[k] = 0;
+    } else if (c.stall_window > 0 && m >= c.stall_window && m < c.hcap &&
+               h > c.hist[(size_t)k * c.hcap + (m - c.stall_window)] * c.stall_factor) {
+        c.stat[k] = ST_STALLED;
         c.act[k] = 0;
     } else if (c.drop_factor > 0.0 && h <= c.h0[k] * c.drop_factor) {
         c.stat[k] = ST_OK;
@@ -2436,9 +2464,17 @@ void launch_mut_ghosts(const BLev &B, hipStream_t st) {
 // residual: they leave most of the chip idle, so the flux chain's latency
 // sets their time.
 constexpr long long RES_QUAD_MAX_CELLS = 65536;
+static long long g_four_lane_cells = RES_QUAD_MAX_CELLS;
+
+long long four_lane_limit() { return g_four_lane_cells; }
+long long set_four_lane_limit(long long cells) {
+    const long long old = g_four_lane_cells;
+    g_four_lane_cells = cells < 0 ? RES_QUAD_MAX_CELLS : cells;
+    return old;
+}
 
 void launch_residual(const BLev &B, const ResArgs &a, hipStream_t st) {
-    if ((long long)B.max_ni * B.max_nj * B.n <= RES_QUAD_MAX_CELLS) {
+    if ((long long)B.max_ni * B.max_nj * B.n <= g_four_lane_cells) {
         const dim3 grid(nblocks(4 * B.max_ni * B.max_nj, CELL_TPB), B.n);
         if (a.fp32)
             hipLaunchKernelGGL(k_residual_q<float>, grid, dim3(CELL_TPB), 0, st, B.k, a);
@@ -2453,7 +2489,7 @@ void launch_residual(const BLev &B, const ResArgs &a, hipStream_t st) {
 }
 
 void launch_blocks(const BLev &B, int aw, double tau, int viscous, int fp32, hipStream_t st, int copy_u0) {
-    if ((long long)B.max_ni * B.max_nj * B.n <= RES_QUAD_MAX_CELLS) {   // the residual's small-launch rule
+    if ((long long)B.max_ni * B.max_nj * B.n <= g_four_lane_cells) {   // the residual's small-launch rule
         const dim3 grid(nblocks(4 * B.max_ni * B.max_nj, CELL_TPB), B.n);
         if (fp32)
             hipLaunchKernelGGL(k_blocks_q<float>, grid, dim3(CELL_TPB), 0, st, B.k, aw, tau, viscous, copy_u0);
@@ -2647,6 +2683,15 @@ void launch_restrict_jobs(const BLev &Bf, const BLev &Bc, const RJob *jobs, int 
 
 void launch_prolong(const BLev &Bf, const BLev &Bc, hipStream_t st) {
     hipLaunchKernelGGL(k_prolong, cells_grid(Bf), dim3(CELL_TPB), 0, st, Bf.k, Bc.k);
+}
+
+void launch_save_u(const BLev &B, hipStream_t st) {
+    hipLaunchKernelGGL(k_axpby, cells_grid(B), dim3(CELL_TPB), 0, st, B.k, 1.0, (int)FLD_U, 0.0, (int)FLD_NONE,
+                       (int)FLD_ULAST);
+}
+
+void launch_rollback(const BLev &B, const int *rb, hipStream_t st) {
+    hipLaunchKernelGGL(k_rollback, cells_grid(B), dim3(CELL_TPB), 0, st, B.k, rb);
 }
 
 void launch_axpby(const BLev &B, double a, int fx, double b, int fy, int fout, hipStream_t st) {

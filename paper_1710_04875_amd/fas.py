@@ -15,11 +15,11 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libfas.so")
 
-FAS_OK, FAS_EINVAL, FAS_ENOMEM, FAS_EDEVICE, FAS_DIVERGED, FAS_NOT_CONVERGED = 0, -1, -2, -3, -4, -6
+FAS_OK, FAS_EINVAL, FAS_ENOMEM, FAS_EDEVICE, FAS_DIVERGED, FAS_STALLED, FAS_NOT_CONVERGED = 0, -1, -2, -3, -4, -5, -6
 FAS_BOX, FAS_CGRID = 0, 1
 FAS_EULER, FAS_RANS_BL = 0, 1
 FAS_AW3, FAS_PARK3J, FAS_AW5J, FAS_AW51, FAS_AW52, FAS_PARK51 = range(6)
-PARAMS_VERSION = 1
+PARAMS_VERSION = 2
 
 _lib = None
 
@@ -39,7 +39,8 @@ class _Params(ctypes.Structure):
         ("mach", ctypes.c_double), ("alpha_deg", ctypes.c_double), ("reynolds", ctypes.c_double),
         ("prandtl", ctypes.c_double), ("prandtl_t", ctypes.c_double),
         ("n_levels", ctypes.c_int32), ("cycle_gamma", ctypes.c_int32), ("nu1", ctypes.c_int32),
-        ("precond_fp32", ctypes.c_int32),
+        ("precond_fp32", ctypes.c_int32), ("viscous_blocks", ctypes.c_int32), ("dt_form", ctypes.c_int32),
+        ("stall_window", ctypes.c_int32), ("stall_orders", ctypes.c_double), ("growth_limit", ctypes.c_double),
     ]
 
 
@@ -64,6 +65,11 @@ class Params:
     cycle_gamma: int = 1
     nu1: int = 1
     precond_fp32: int = 0
+    viscous_blocks: int = 0
+    dt_form: int = 1
+    stall_window: int = 0
+    stall_orders: float = 0.0
+    growth_limit: float = 1.0e8
 
     def c(self) -> _Params:
         p = _Params()
@@ -75,14 +81,14 @@ class Params:
 
 EXPORTS = [
     "fas_params_default", "fas_grid_create", "fas_grid_destroy", "fas_grid_set_nodes", "fas_state_create",
-    "fas_state_destroy", "fas_state_set_params", "fas_set_state", "fas_get_state",
+    "fas_state_destroy", "fas_state_set_params", "fas_set_state", "fas_get_state", "fas_get_time_levels",
     "fas_get_level", "fas_handoff_pending", "fas_residual", "fas_smooth", "fas_sgs_apply", "fas_cycle",
     "fas_dual_time_step", "fas_profile", "fas_profile_read", "fas_batch_create",
     "fas_batch_destroy", "fas_batch_solve", "fas_batch_sweep_config", "fas_batch_set_sweep_config",
     "fas_sweep_config_count", "fas_sweep_config_info", "fas_batch_profile",
     "fas_batch_profile_read", "fas_forces", "fas_vjp", "fas_param_partials",
     "fas_sgs_apply_transpose", "fas_adjoint_solve", "fas_lift_gradient", "fas_vjp_nodes",
-    "fas_lift_gradient_nodes", "fas_set_motion", "fas_dfa",
+    "fas_lift_gradient_nodes", "fas_set_motion", "fas_dfa", "fas_vjp_smooth", "fas_set_four_lane_limit",
     "fas_last_error",
 ]
 PROF_CLASSES = ("sweep", "residual", "blocks")
@@ -106,7 +112,10 @@ def load(path: str = LIB_PATH):
         "fas_state_create": (i32, [vp, ctypes.POINTER(_Params), vp, vp, ctypes.POINTER(vp)]),
         "fas_state_destroy": (None, [vp]),
         "fas_state_set_params": (i32, [vp, ctypes.POINTER(_Params)]),
-        "fas_set_state": (i32, [vp, vp]),
+        "fas_set_state": (i32, [vp, vp, vp, vp, f64, f64, i32, i32]),
+        "fas_get_time_levels": (i32, [vp, vp, vp, dp, dp, ip, ip]),
+        "fas_vjp_smooth": (i32, [vp, vp, vp]),
+        "fas_set_four_lane_limit": (ctypes.c_int64, [ctypes.c_int64]),
         "fas_get_state": (i32, [vp, vp, vp]),
         "fas_get_level": (i32, [vp, i32, vp, vp]),
         "fas_handoff_pending": (i32, [vp, i32, ctypes.POINTER(ctypes.c_int64)]),
@@ -226,10 +235,36 @@ class State:
         self._pc = params.c()
         _check(_lib.fas_state_set_params(self.h, ctypes.byref(self._pc)))
 
-    def set_state(self, u):
-        u = u.to(torch_dtype()).contiguous()
-        _check(_lib.fas_set_state(self.h, _dptr(u)))
-        self._keep = u
+    def set_state(self, u, un=None, unm1=None, t=0.0, dt=0.0, step=0, n_cycles=0):
+        """Restore a checkpoint: the solution, the time levels of the BDF
+        step in progress (step >= 1: un; step >= 2: unm1), the clock and the
+        cycle count of the current solve (step 0: a steady state)."""
+        keep = [u.to(torch_dtype()).contiguous()]
+        for v in (un, unm1):
+            keep.append(None if v is None else v.to(torch_dtype()).contiguous())
+        _check(_lib.fas_set_state(self.h, _dptr(keep[0]), _dptr(keep[1]) if keep[1] is not None else None,
+                                  _dptr(keep[2]) if keep[2] is not None else None, float(t), float(dt),
+                                  int(step), int(n_cycles)))
+        self._keep = keep
+
+    def get_time_levels(self):
+        """(un, unm1, t, dt, step, n_cycles); un / unm1 are None when the
+        state does not hold them."""
+        import torch
+        t, dt = ctypes.c_double(0.0), ctypes.c_double(0.0)
+        step, nc = ctypes.c_int32(0), ctypes.c_int32(0)
+        _check(_lib.fas_get_time_levels(self.h, None, None, ctypes.byref(t), ctypes.byref(dt),
+                                        ctypes.byref(step), ctypes.byref(nc)))
+        un = torch.empty(self.shape(), dtype=torch.float64, device=self.device) if step.value > 0 else None
+        unm1 = torch.empty(self.shape(), dtype=torch.float64, device=self.device) if step.value > 1 else None
+        _check(_lib.fas_get_time_levels(self.h, _dptr(un) if un is not None else None,
+                                        _dptr(unm1) if unm1 is not None else None, None, None, None, None))
+        return un, unm1, t.value, dt.value, step.value, nc.value
+
+    def checkpoint(self):
+        """Everything fas_set_state needs to resume this state bitwise."""
+        un, unm1, t, dt, step, nc = self.get_time_levels()
+        return dict(u=self.get_state(), un=un, unm1=unm1, t=t, dt=dt, step=step, n_cycles=nc)
 
     def get_state(self, with_mut=False):
         import torch
@@ -273,7 +308,7 @@ class State:
         n = ctypes.c_int32(0)
         st = _check(_lib.fas_cycle(self.h, max_cycles, drop_orders,
                                    hist.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), ctypes.byref(n)),
-                    allow=(FAS_NOT_CONVERGED, FAS_DIVERGED))
+                    allow=(FAS_NOT_CONVERGED, FAS_DIVERGED, FAS_STALLED))
         return hist[:n.value + 1], st
 
     def profile(self, enable=True):
@@ -306,6 +341,15 @@ class State:
         lam = lam.to(torch.float64).contiguous()
         out = torch.empty_like(lam)
         _check(_lib.fas_vjp(self.h, _dptr(lam), _dptr(out)))
+        return out
+
+    def vjp_smooth(self, lam):
+        """(dS/du)^T lam for one fine-level smoother iteration S at frozen
+        dt*, blocks and eddy viscosity (the state is left unchanged)."""
+        import torch
+        lam = lam.to(torch.float64).contiguous()
+        out = torch.empty_like(lam)
+        _check(_lib.fas_vjp_smooth(self.h, _dptr(lam), _dptr(out)))
         return out
 
     def param_partials(self):
@@ -381,8 +425,15 @@ class State:
         st = _check(_lib.fas_dual_time_step(self.h, dt, alpha_deg, max_inner, drop_orders,
                                             hist.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
                                             ctypes.byref(n)),
-                    allow=(FAS_NOT_CONVERGED, FAS_DIVERGED))
+                    allow=(FAS_NOT_CONVERGED, FAS_DIVERGED, FAS_STALLED))
         return hist[:n.value + 1], st
+
+
+def set_four_lane_limit(max_cells):
+    """Launch-size rule of the residual and block kernels (cells per launch
+    up to which the four-lane variants run; < 0: default).  Returns the
+    previous value."""
+    return int(load().fas_set_four_lane_limit(int(max_cells)))
 
 
 def torch_dtype():
@@ -488,7 +539,7 @@ class Batch:
         st = _check(_lib.fas_batch_solve(self.h, max_cycles, drop_orders, 1 if use_graph else 0,
                                          nd.ctypes.data_as(ip), stv.ctypes.data_as(ip),
                                          hist.ctypes.data_as(ctypes.POINTER(ctypes.c_double))),
-                    allow=(FAS_NOT_CONVERGED, FAS_DIVERGED))
+                    allow=(FAS_NOT_CONVERGED, FAS_DIVERGED, FAS_STALLED))
         return [hist[c, :nd[c] + 1].copy() for c in range(n)], stv, st
 
     def sweep_config(self, level):
@@ -521,7 +572,8 @@ def _steady_lift_fn():
         the nodes are inputs, dC_L/d(x, y) of every node."""
 
         @staticmethod
-        def forward(ctx, mach, alpha_deg, x_nodes, y_nodes, state, max_cycles, drop_orders, adj_iter, adj_drop):
+        def forward(ctx, mach, alpha_deg, x_nodes, y_nodes, state, max_cycles, drop_orders, adj_iter, adj_drop,
+                    allow_unconverged):
             p = state.params
             p.mach = float(mach)
             p.alpha_deg = float(alpha_deg)
@@ -532,10 +584,14 @@ def _steady_lift_fn():
                 x = x_nodes.detach().cpu().numpy() if x_nodes is not None else g.x
                 y = y_nodes.detach().cpu().numpy() if y_nodes is not None else g.y
                 g.set_nodes(x, y)
-            state.cycle(max_cycles, drop_orders)
+            _, st = state.cycle(max_cycles, drop_orders)
+            if st != FAS_OK and not allow_unconverged:
+                raise FasError(st, "steady_lift: the primal solve did not reach the requested drop "
+                                   "(pass allow_unconverged=True to accept it)")
             cl, _ = state.forces()
             ctx.state = state
             ctx.adj = (adj_iter, adj_drop)
+            ctx.allow = allow_unconverged
             ctx.node_meta = [(t.device, t.dtype) if t is not None else None for t in (x_nodes, y_nodes)]
             return torch.tensor(cl, dtype=torch.float64)
 
@@ -543,7 +599,7 @@ def _steady_lift_fn():
         def backward(ctx, g):
             gx = gy = None
             if ctx.nodes:
-                _, grad, dx, dy, _, _ = ctx.state.lift_gradient_nodes(*ctx.adj)
+                _, grad, dx, dy, _, st = ctx.state.lift_gradient_nodes(*ctx.adj)
                 mx, my = ctx.node_meta
                 if mx is not None:
                     gx = g.to(dx.device) * dx
@@ -552,16 +608,23 @@ def _steady_lift_fn():
                     gy = g.to(dy.device) * dy
                     gy = gy.to(device=my[0], dtype=my[1])
             else:
-                _, grad, _, _ = ctx.state.lift_gradient(*ctx.adj)
-            return (g * grad[1], g * grad[0], gx, gy, None, None, None, None, None)
+                _, grad, _, st = ctx.state.lift_gradient(*ctx.adj)
+            if st != FAS_OK and not ctx.allow:
+                raise FasError(st, "steady_lift: the adjoint solve did not reach the requested drop "
+                                   "(pass allow_unconverged=True to accept it)")
+            return (g * grad[1], g * grad[0], gx, gy, None, None, None, None, None, None)
 
     return SteadyLift
 
 
 def steady_lift(mach, alpha_deg, state, max_cycles=400, drop_orders=10.0, adj_iter=2000, adj_drop=10.0,
-                x_nodes=None, y_nodes=None):
+                x_nodes=None, y_nodes=None, allow_unconverged=False):
     """Differentiable C_L(M, alpha) (torch scalars) of a converged State; with
     x_nodes / y_nodes ((nj + 1, ni + 1) tensors) also differentiable in the
-    grid-node coordinates (the forward pass moves the State's grid there)."""
+    grid-node coordinates (the forward pass moves the State's grid there).
+    Raises FasError when the primal (forward) or the adjoint (backward) does
+    not reach its drop, unless allow_unconverged.  For RANS the gradient is
+    that of the frozen-turbulence adjoint: the Baldwin-Lomax eddy viscosity
+    is held at the converged state, so its own sensitivity is left out."""
     return _steady_lift_fn().apply(mach, alpha_deg, x_nodes, y_nodes, state, max_cycles, drop_orders, adj_iter,
-                                   adj_drop)
+                                   adj_drop, allow_unconverged)

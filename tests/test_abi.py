@@ -43,7 +43,26 @@ def test_params_layout_and_defaults():
     assert p.scheme == fas.FAS_AW3 and p.model == fas.FAS_EULER
     # robust mode of the paper: eta 0.5, d 0.5, c* 1e4 after 2 cycles at 20
     assert (p.eta, p.d_cut, p.cfl, p.cfl_ramp, p.n_ramp) == (0.5, 0.5, 1.0e4, 20.0, 2)
-    assert ctypes.sizeof(fas._Params) == 120
+    # the printed convective blocks, the directional pseudo time step, no
+    # stall test, divergence beyond a 1e8 growth
+    assert (p.viscous_blocks, p.dt_form, p.stall_window, p.growth_limit) == (0, 1, 0, 1.0e8)
+    assert ctypes.sizeof(fas._Params) == 152
+    # the binding's defaults are the library's
+    dflt = fas.Params()
+    for name, _ in fas._Params._fields_:
+        if name != "version":
+            assert getattr(dflt, name) == getattr(p, name), name
+
+
+def test_four_lane_limit_setting():
+    from paper_1710_04875_amd import fas
+    old = fas.set_four_lane_limit(0)
+    try:
+        assert old == 65536
+        assert fas.set_four_lane_limit(-1) == 0
+        assert fas.set_four_lane_limit(123) == 65536
+    finally:
+        fas.set_four_lane_limit(-1)
 
 
 def test_argument_errors_without_device():
@@ -65,6 +84,9 @@ def test_argument_errors_without_device():
     assert lib.fas_batch_solve(None, 1, 0.0, 0, None, None, None) == fas.FAS_EINVAL
     assert lib.fas_cycle(None, 1, 0.0, None, None) == fas.FAS_EINVAL
     assert lib.fas_residual(None, 0, None) == fas.FAS_EINVAL
+    assert lib.fas_set_state(None, None, None, None, 0.0, 0.0, 0, 0) == fas.FAS_EINVAL
+    assert lib.fas_get_time_levels(None, None, None, None, None, None, None) == fas.FAS_EINVAL
+    assert lib.fas_vjp_smooth(None, None, None) == fas.FAS_EINVAL
 
 
 def test_missing_library_fails_loudly(tmp_path):

@@ -190,7 +190,10 @@ def test_steady_lift_autograd():
     g, st = _converged_state(alpha, mach)
     m = torch.tensor(mach, dtype=torch.float64, requires_grad=True)
     a = torch.tensor(alpha, dtype=torch.float64, requires_grad=True)
-    cl = fas.steady_lift(m, a, st, max_cycles=50, drop_orders=11.0, adj_iter=3000, adj_drop=11.0)
+    # the state is converged already (its norm sits at the 12-order floor, so
+    # no further drop is reachable in the forward pass); the adjoint converges
+    cl = fas.steady_lift(m, a, st, max_cycles=50, drop_orders=11.0, adj_iter=3000, adj_drop=11.0,
+                         allow_unconverged=True)
     cl.backward()
     _, grad, _, _ = st.lift_gradient(3000, 11.0)
     assert abs(a.grad.item() - grad[0]) <= 1e-10 * abs(grad[0])
@@ -214,7 +217,7 @@ def test_converged_state_is_a_fixed_point():
     assert state_err_local(_np(st.get_state()), u) < 1e-10
 
 
-@pytest.mark.parametrize("variant", [dict(cycle_gamma=2, n_levels=2), dict(d_cut=0.75),
+@pytest.mark.parametrize("variant", [dict(cycle_gamma=2, n_levels=2, dt_form=0), dict(d_cut=0.75),
                                      dict(cfl=50.0, cfl_ramp=5.0), dict(precond_fp32=1), dict(eta=0.75)])
 def test_converged_solution_does_not_depend_on_the_smoother(variant):
     """The fixed point F(u) = 0 is a property of the discretisation alone."""
@@ -351,7 +354,7 @@ def test_steady_lift_autograd_in_the_nodes():
     yn = torch.tensor(g.y, dtype=torch.float64, requires_grad=True)
     m = torch.tensor(mach, dtype=torch.float64, requires_grad=True)
     cl = fas.steady_lift(m, torch.tensor(alpha, dtype=torch.float64), st, max_cycles=50, drop_orders=11.0,
-                         adj_iter=3000, adj_drop=11.0, y_nodes=yn)
+                         adj_iter=3000, adj_drop=11.0, y_nodes=yn, allow_unconverged=True)
     cl.backward()
     _, grad, dx, dy, _, status = st.lift_gradient_nodes(3000, 11.0)
     assert status == 0
@@ -365,3 +368,55 @@ def test_steady_lift_autograd_in_the_nodes():
     assert np.isfinite(yn.grad.numpy()).all()
     assert abs(got - ref) <= 1e-8 * abs(ref)
     assert abs(m.grad.item() - grad[1]) <= 1e-8 * abs(grad[1])
+
+
+def _small_case(kind):
+    if kind == "box_euler":
+        x, y = fi.box_grid(12, 10)
+        u = fi.perturbed_state(fi.box_initial_state(x, y), 0.01, seed=12)
+        return dict(topo=fi.BOX, x=x, y=y, nw=0, u=u, model=0, mach=0.8, alpha=0.0)
+    model = 0 if kind.endswith("euler") else 1
+    x, y = fi.cgrid(16, 8, 2)
+    u = fi.perturbed_state(fi.uniform_state(16, 8, 0.7, 1.3), 0.01, seed=11)
+    return dict(topo=fi.CGRID, x=x, y=y, nw=2, u=u, model=model, mach=0.7, alpha=1.3)
+
+
+@pytest.mark.parametrize("kind,scheme", [("box_euler", 0), ("box_euler", 1), ("cgrid_euler", 0),
+                                         ("cgrid_rans", 0), ("cgrid_rans", 2)])
+def test_smoother_vjp_matches_oracle_dense_transpose(kind, scheme):
+    """(dS/du)^T lam of one smoother iteration at frozen dt*, blocks and eddy
+    viscosity against the transpose of the oracle's complex-step Jacobian of
+    the same map, element by element; the state is left unchanged."""
+    c = _small_case(kind)
+    cfl = 1.0 if scheme == 1 else 50.0
+    g, st, S = _pair(c, scheme=scheme, cfl=cfl, cfl_ramp=cfl)
+    J = oadj.smoother_jacobian(S, c["u"])
+    lam = np.random.default_rng(7).standard_normal(c["u"].shape)
+    ref = (J.T @ lam.reshape(-1)).reshape(lam.shape)
+    u_before = _np(st.get_state())
+    out = _np(st.vjp_smooth(torch.from_numpy(lam).cuda()))
+    assert _rel(out, ref) < TOL_ADJ
+    assert np.array_equal(_np(st.get_state()), u_before)
+
+
+def test_steady_lift_raises_on_an_unconverged_primal():
+    from paper_1710_04875_amd import fas
+    c = _case("cgrid_euler")
+    g, st, S = _pair(c, cfl=20.0, cfl_ramp=20.0)
+    m = torch.tensor(0.7, dtype=torch.float64, requires_grad=True)
+    a = torch.tensor(1.3, dtype=torch.float64, requires_grad=True)
+    with pytest.raises(fas.FasError):
+        fas.steady_lift(m, a, st, max_cycles=3, drop_orders=10.0)
+    cl = fas.steady_lift(m, a, st, max_cycles=3, drop_orders=10.0, allow_unconverged=True)
+    assert np.isfinite(float(cl.detach()))
+
+
+def test_steady_lift_raises_on_an_unconverged_adjoint():
+    from paper_1710_04875_amd import fas
+    c = _case("cgrid_euler")
+    g, st, S = _pair(c, cfl=20.0, cfl_ramp=20.0)
+    m = torch.tensor(0.7, dtype=torch.float64, requires_grad=True)
+    a = torch.tensor(1.3, dtype=torch.float64, requires_grad=True)
+    cl = fas.steady_lift(m, a, st, max_cycles=4000, drop_orders=11.0, adj_iter=2, adj_drop=10.0)
+    with pytest.raises(fas.FasError):
+        cl.backward()

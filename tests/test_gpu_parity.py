@@ -51,6 +51,37 @@ def test_one_smoother_iteration(kind, scheme):
     assert state_err(_np(st.get_state()), S.u(0)) < TOL_STATE
 
 
+@pytest.mark.parametrize("kind", ["cgrid_small_rans", "cgrid_c2_rans"])
+@pytest.mark.parametrize("vblk,dt_form", [(0, 1), (1, 1), (0, 0)])
+def test_one_iteration_both_block_forms(kind, vblk, dt_form):
+    """One AW3 iteration on RANS grids with the printed convective blocks
+    (viscous_blocks 0) and with the thin-layer viscous term (1), and with
+    both pseudo-time-step readings."""
+    inp = case_inputs(kind)
+    g, st, S = make_pair(inp, cfl=1e4, cfl_ramp=1e4, viscous_blocks=vblk, dt_form=dt_form)
+    st.smooth(0, 1)
+    S.smooth(0)
+    assert state_err(_np(st.get_state()), S.u(0)) < TOL_STATE
+
+
+@pytest.mark.parametrize("vblk", [0, 1])
+def test_c2_size_v_cycle_both_block_forms(vblk):
+    """One 3-level V-cycle on the 256 x 128 RANS C-grid (the benchmark's
+    grid size and banded sweeps on every level) in both block forms; every
+    level is compared."""
+    inp = case_inputs("cgrid_c2_rans")
+    # c* = 1, the benchmark's start-up value (the perturbed parity state
+    # diverges at large c* in both paths)
+    g, st, S = make_pair(inp, n_levels=3, cycle_gamma=1, cfl=1.0, cfl_ramp=1.0, viscous_blocks=vblk)
+    hist, status = st.cycle(1)
+    ho = S.run_cycles(1)
+    assert state_err(_np(st.get_state()), S.u(0)) < TOL_STATE
+    for l in range(1, 3):
+        ug, sg = st.get_level(l)
+        assert state_err(_np(ug), S.u(l)) < TOL_STATE
+    assert abs(hist[1] - ho[1]) <= 1e-10 * ho[1]
+
+
 @pytest.mark.parametrize("kind,levels,gamma", [("box_small", 2, 1), ("cgrid_small_rans", 3, 1),
                                                ("cgrid_small_euler", 3, 2)])
 def test_one_fas_cycle(kind, levels, gamma):
@@ -98,13 +129,16 @@ def test_five_stage_smoothers(kind, scheme):
     """AW5J, AW51, AW52 and pARK51 (the five-stage rows of the coefficient
     table) run on the same kernels: one iteration and one V-cycle."""
     inp = case_inputs(kind)
-    cfl = 1.0 if scheme == 5 else 50.0
+    cfl = 0.5 if scheme == 5 else 50.0
     g, st, S = make_pair(inp, scheme=scheme, cfl=cfl, cfl_ramp=cfl)
     st.smooth(0, 1)
     S.smooth(0)
     assert state_err(_np(st.get_state()), S.u(0)) < TOL_STATE
     levels = 2 if kind == "box_small" else 3
-    g, st, S = make_pair(inp, scheme=scheme, n_levels=levels, cfl=cfl, cfl_ramp=cfl)
+    # the V-cycle on the RANS C-grid with the viscous block term (with the
+    # convective blocks alone these c* diverge on its coarse levels)
+    g, st, S = make_pair(inp, scheme=scheme, n_levels=levels, cfl=cfl, cfl_ramp=cfl,
+                         viscous_blocks=1 if kind.endswith("rans") else 0)
     st.cycle(1)
     S.run_cycles(1)
     assert state_err(_np(st.get_state()), S.u(0)) < TOL_STATE
@@ -126,3 +160,51 @@ def test_pitching_moving_mesh_parity(kind):
         S.set_motion(da, rate)
         S.run_cycles(2)
         assert state_err(_np(st.get_state()), S.u(0)) < TOL_STATE, step
+
+
+@pytest.mark.parametrize("kind", ["cgrid_small_rans", "cgrid_c2_rans", "box"])
+def test_fp32_preconditioner_iteration_against_oracle(kind):
+    """One AW3 iteration with the FP32 preconditioner (blocks, D^-1, both
+    sweeps and x in FP32; residual and update in FP64) against the FP64
+    oracle.  The FP32 path changes only x, the increment of the iteration,
+    so the difference is measured against the increment's size per
+    component; the bound is FP32_INCREMENT_TOL (derivation in the design
+    notes: FP32 rounding, u32 = 6e-8, of the blocks, of g and of every
+    sweep product, carried along the sweep's dependency chain; measured
+    0.9e-6 to 1.8e-6 on these grids)."""
+    inp = case_inputs(kind)
+    g, st, S = make_pair(inp, cfl=100.0, cfl_ramp=100.0, precond_fp32=1)
+    st.smooth(0, 1)
+    S.smooth(0)
+    ug = _np(st.get_state())
+    uo = S.u(0)
+    inc = np.abs(uo - inp["u0"]).max(axis=(1, 2))
+    err = float((np.abs(ug - uo).max(axis=(1, 2)) / inc).max())
+    print("fp32 increment error %s: %.3e" % (kind, err))
+    assert err < FP32_INCREMENT_TOL
+
+
+FP32_INCREMENT_TOL = 2e-5
+
+
+def test_fp32_and_fp64_preconditioners_converge_to_the_same_solution():
+    """The 256 x 128 RANS C-grid solved to 11 orders with the FP32 and with
+    the FP64 preconditioner (W-cycles): the fixed point F(u) = 0 does not
+    depend on the preconditioner's precision (within 1e-8 per cell)."""
+    import fas_inputs as fi
+    from paper_1710_04875_amd import fas
+    case = fi.steady_cgrid_case()
+    x, y = case.grid()
+    u0 = torch.from_numpy(case.initial_state(x, y)).cuda()
+    out = []
+    for fp32 in (0, 1):
+        g = fas.Grid(case.topology, x, y, case.n_wake, 3)
+        p = fas.Params(model=fas.FAS_RANS_BL, mach=case.mach, alpha_deg=case.alpha_deg, reynolds=case.reynolds,
+                       n_levels=3, cycle_gamma=2, cfl=100.0, cfl_ramp=1.0, n_ramp=4, ramp_growth=1.5,
+                       precond_fp32=fp32)
+        st = fas.State(g, p, u0)
+        h, status = st.cycle(1500, 11.0)
+        print("precision fp32=%d: %d cycles, %.2f orders" % (fp32, len(h) - 1, np.log10(h[0] / h[-1])))
+        assert status == fas.FAS_OK
+        out.append(_np(st.get_state()))
+    assert state_err(out[1], out[0]) < 1e-8
