@@ -381,10 +381,12 @@ fas_status fas_lift_gradient_nodes(fas_state s, int32_t max_iter, double drop_or
  * with the cutoff splitting, on a periodic Cartesian mesh; every pair of
  * phase angles gives one 4x4 complex iteration matrix.
  * cases: host array of n_cases descriptors.  Mesh: nx cells of width 1/nx
- * in x, dy = ar dx; nx and ny (phase angles in y, normally nx ar) even and
- * >= 2; phase angles 2 pi k / n, k = -n/2 + 1 .. n/2.  Steps: dt* = cstar
- * dx / (|v_1| + a) and, with unsteady = 1, the BDF2 terms 3/(2 dt) with
- * dt = c dx / (|v_1| + a).  The amplification factor is the largest
+ * in x, dy = ar dx (or dx / ar); nx and ny (phase angles in y, normally
+ * nx ar) even and >= 2; phase angles 2 pi k / n, k = -n/2 + 1 .. n/2.
+ * Steps: dt* = cstar b and, with unsteady = 1, the BDF2 terms 3/(2 dt)
+ * with dt = c b, b = min(dx / (|v_1| + a), dy / (|v_2| + a)) (the smaller
+ * directional CFL step).  Preconditioner P: the SGS factorisation (eq.
+ * "sgs-precon"), the exact first-order operator D + L + U, or none.  The amplification factor is the largest
  * spectral radius over all pairs, the smoothing factor over the pairs with
  * max(|Theta_x|, |Theta_y|) >= pi/2.
  * amp, smooth: device [n_cases]; radius: device, nullable, the spectral
@@ -400,9 +402,18 @@ typedef struct {
     double cstar;           /* pseudo CFL c* (> 0) */
     double d;               /* eigenvalue cutoff (>= 0) */
     double eta;             /* W parameter (additive W schemes) */
-    double ar;              /* aspect ratio dy / dx (> 0) */
+    double ar;              /* aspect ratio (> 0), see mesh */
     double c;               /* physical CFL (> 0 when unsteady) */
+    int32_t precond;        /* FAS_DFA_SGS, FAS_DFA_EXACT (P = D + L + U, the
+                             * tables' exact-preconditioner columns) or
+                             * FAS_DFA_NONE (P = I, the explicit schemes) */
+    int32_t unsplit;        /* 1: every beta = 1 (the unsplit ERK / W forms) */
+    int32_t mesh;           /* FAS_DFA_MESH_AR_DX: dy = ar dx; FAS_DFA_MESH_DX_OVER_AR:
+                             * dy = dx / ar (the ny cells fill the unit height) */
+    int32_t reserved;       /* 0 */
 } fas_dfa_case;
+enum { FAS_DFA_SGS = 0, FAS_DFA_EXACT = 1, FAS_DFA_NONE = 2 };
+enum { FAS_DFA_MESH_AR_DX = 0, FAS_DFA_MESH_DX_OVER_AR = 1 };
 fas_status fas_dfa(const fas_dfa_case *cases, int32_t n_cases, double *amp, double *smooth, double *radius,
                    void *stream);
 

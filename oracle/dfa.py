@@ -24,20 +24,40 @@ The operators follow the section's subsections:
   V_i = beta_{i+1} P^-1 H_v U_i + (1 - beta_{i+1}) V_{i-1}; G = U_s.
 Shift operators become E_x = exp(i Theta_x), E_y = exp(i Theta_y).
 
+Preconditioners: the SGS factorisation above, the exact first-order
+operator P = D + L + U (the tables' "exact precond." columns: W = I +
+eta dt* J with J the flux-split linearisation, or P = J), or none (P = I,
+the explicit schemes of Table "ERK-ARK"); with every beta set to 1 the
+additive schemes become the unsplit ERK / W forms.
+
 Readings (the text leaves these open; they reproduce the printed AR = 1
 amplification factors of the ARK3J, AW3 and AW5 tables at alpha = 0 to all
-four printed digits):
+four printed digits, and the exact-preconditioner AW3 factors at AR 1
+(d = 0, 0.1, 0.25 and 1), 100 and 10000 (d = 0 and 0.1)):
 * mesh: nx = 8 cells of width 1/8 in x, dy = AR dx, ny = 8 AR; phase angles
-  2 pi k / n for k = -n/2 + 1 .. n/2;
-* steps: dt* = c* dx / (|v_1| + a) and dt = c dx / (|v_1| + a);
+  2 pi k / n for k = -n/2 + 1 .. n/2 (the alternative dy = dx / AR, the
+  8 AR cells filling the unit height, is an option; it fits fewer printed
+  values);
+* steps: dt* = c* min(dx / (|v_1| + a), dy / (|v_2| + a)) and dt with c in
+  place of c*: the smaller directional CFL step, which is dx / (|v_1| + a)
+  for every printed case of the default mesh;
 * JST coefficients: the pressure sensor of the constant state is zero, so
   eps2 = 0 and eps4 = r / 32 per direction, r = |v_k| + a;
 * the amplification factor is the largest spectral radius over every pair of
   phase angles; the smoothing factor takes the pairs with max(|Theta_x|,
   |Theta_y|) >= pi/2.  Parity unpinned for the smoothing factor: the printed
   smoothing factors are smaller than the spectral radius of every high
-  frequency mode of these symbols, so the paper's definition differs in a way
-  the text does not state.
+  frequency mode of these symbols, and in two rows of the exact-preconditioner
+  ARK3J columns the printed smoothing factor exceeds the printed
+  amplification factor, which no maximum over a subset of the modes gives,
+  so the paper's definition differs in a way the text does not state.
+
+Not reproduced with these readings (nor with dy = dx / AR, a step from
+either width or speed, or the identity in the steady ARK diagonal): Table
+"ERK-ARK" (the explicit three-stage schemes are unstable at c* = 0.9, where
+the printed factor 0.9933 is exactly G at Theta = 0), the
+exact-preconditioner ARK3J columns, and the SGS columns at AR 100 and
+10000 beyond d = 0.1 (AW3 within 1.2e-3 up to d = 0.1).
 """
 from __future__ import annotations
 
@@ -53,6 +73,10 @@ U_ALPHA45 = (1.0, np.sqrt(2.0) / 2.0, np.sqrt(2.0) / 2.0, 3.290)
 U_ALPHA0 = (1.0, 1.0, 0.0, 3.290)
 
 
+SGS, EXACT, NONE = 0, 1, 2       # preconditioner of the stages
+MESH_AR_DX, MESH_DX_OVER_AR = 0, 1
+
+
 @dataclass
 class DfaCase:
     u: tuple = U_ALPHA0     # linearisation state (rho, rho v1, rho v2, rho E)
@@ -60,10 +84,13 @@ class DfaCase:
     cstar: float = 3.0      # pseudo CFL c*
     d: float = 0.5          # eigenvalue cutoff
     eta: float = 0.8        # W parameter (additive W schemes)
-    ar: float = 1.0         # aspect ratio dy / dx
+    ar: float = 1.0         # aspect ratio (the mesh reading below)
     c: float = 200.0        # physical CFL
     nx: int = 8
     unsteady: bool = True
+    precond: int = SGS      # SGS, EXACT (P = D + L + U) or NONE (P = I)
+    unsplit: bool = False   # every beta = 1 (the ERK / unsplit W forms)
+    mesh: int = MESH_AR_DX  # dy = AR dx, or dy = dx / AR
 
     @property
     def ny(self) -> int:
@@ -80,11 +107,27 @@ def _state(U):
 
 def steps(case: DfaCase):
     """(dx, dy, dt*, dt) of the reading above."""
-    _, v1, _, a = _state(case.u)
+    _, v1, v2, a = _state(case.u)
     dx = 1.0 / case.nx
-    dy = case.ar * dx
-    base = dx / (abs(v1) + a)
+    dy = dx / case.ar if case.mesh == MESH_DX_OVER_AR else case.ar * dx
+    base = min(dx / (abs(v1) + a), dy / (abs(v2) + a))
     return dx, dy, case.cstar * base, case.c * base
+
+
+def coefficients(case: DfaCase):
+    """(alpha, beta, W form) of the case's scheme (beta = 1 if unsplit)."""
+    alpha, beta, wform = SCHEMES[case.scheme]
+    if case.unsplit:
+        beta = tuple(1.0 for _ in beta)
+    return alpha, beta, wform
+
+
+def _preconditioner(case, L, D, Uu):
+    if case.precond == EXACT:
+        return D + L + Uu
+    if case.precond == NONE:
+        return np.broadcast_to(np.eye(4, dtype=complex), D.shape).copy()
+    return (D + L) @ np.linalg.solve(D, D + Uu)
 
 
 def phase_angles(case: DfaCase):
@@ -102,7 +145,7 @@ def symbols(case: DfaCase, tx, ty):
     U, v1, v2, a = _state(case.u)
     dx, dy, dts, dt = steps(case)
     vol = dx * dy
-    _, beta_unused, wform = SCHEMES[case.scheme]
+    _, beta_unused, wform = coefficients(case)
     A = flux_jacobian(U, 1.0, 0.0)
     B = flux_jacobian(U, 0.0, 1.0)
     Ap, Am = split_jacobians(U, 1.0, 0.0, case.d)
@@ -133,10 +176,10 @@ def symbols(case: DfaCase, tx, ty):
 
 def iteration_matrices(case: DfaCase, tx, ty):
     """G (n, 4, 4) of one smoother iteration per pair of phase angles."""
-    alpha, beta, _ = SCHEMES[case.scheme]
+    alpha, beta, _ = coefficients(case)
     _, _, dts, _ = steps(case)
     Hc, Hv, L, D, Uu = symbols(case, tx, ty)
-    P = (D + L) @ np.linalg.solve(D, D + Uu)
+    P = _preconditioner(case, L, D, Uu)
     Hcb = np.linalg.solve(P, Hc)
     Hvb = np.linalg.solve(P, Hv)
     I4 = np.broadcast_to(np.eye(4, dtype=complex), Hc.shape)
@@ -166,7 +209,7 @@ def full_iteration_matrix(case: DfaCase):
     U, v1, v2, a = _state(case.u)
     dx, dy, dts, dt = steps(case)
     vol = dx * dy
-    alpha, beta, wform = SCHEMES[case.scheme]
+    alpha, beta, wform = coefficients(case)
     nx, ny = case.nx, case.ny
     N = nx * ny
     A = flux_jacobian(U, 1.0, 0.0)
@@ -206,7 +249,12 @@ def full_iteration_matrix(case: DfaCase):
         D = D + (1.0 + (1.5 * case.eta * dts / dt if case.unsteady else 0.0)) * I
     elif case.unsteady:
         D = D + (1.5 / dt) * I
-    P = (D + L) @ np.linalg.solve(D, D + Uu)
+    if case.precond == EXACT:
+        P = D + L + Uu
+    elif case.precond == NONE:
+        P = np.eye(4 * N)
+    else:
+        P = (D + L) @ np.linalg.solve(D, D + Uu)
     Hcb = np.linalg.solve(P, Hc)
     Hvb = np.linalg.solve(P, Hv)
     Ui, V = I, Hvb

@@ -1681,10 +1681,8 @@ extern "C" int64_t fas_set_four_lane_limit(int64_t max_cells) { return set_four_
 extern "C" const char *fas_last_error(void) { return g_err.c_str(); }
 
 // ------------------------------------------------- discrete Fourier analysis
-extern "C" fas_status fas_dfa(const fas_dfa_case *cases, int32_t n_cases, double *amp, double *smooth,
-                              double *radius, void *stream) {
-    if (!cases || n_cases <= 0 || !amp || !smooth) return fail(FAS_EINVAL, "bad argument");
-    std::vector<DfaCase> h(n_cases);
+// descriptors of fas_dfa's cases into h (n_cases entries); *total = pairs
+static fas_status dfa_descriptors(const fas_dfa_case *cases, int32_t n_cases, DfaCase *h, long long *total_out) {
     long long total = 0;
     for (int k = 0; k < n_cases; ++k) {
         const fas_dfa_case &c = cases[k];
@@ -1692,7 +1690,9 @@ extern "C" fas_status fas_dfa(const fas_dfa_case *cases, int32_t n_cases, double
         const double p = (1.4 - 1.0) * (c.u[3] - 0.5 * (c.u[1] * c.u[1] + c.u[2] * c.u[2]) / rho);
         if (c.scheme < 0 || c.scheme > FAS_PARK51 || c.nx < 2 || c.ny < 2 || (c.nx & 1) || (c.ny & 1) ||
             !(rho > 0.0) || !(p > 0.0) || !(c.cstar > 0.0) || !(c.d >= 0.0) || !(c.ar > 0.0) ||
-            !(c.eta > 0.0) || (c.unsteady && !(c.c > 0.0)) || !std::isfinite(c.cstar) || !std::isfinite(c.c))
+            !(c.eta > 0.0) || (c.unsteady && !(c.c > 0.0)) || !std::isfinite(c.cstar) || !std::isfinite(c.c) ||
+            c.precond < FAS_DFA_SGS || c.precond > FAS_DFA_NONE || (c.unsplit != 0 && c.unsplit != 1) ||
+            (c.mesh != FAS_DFA_MESH_AR_DX && c.mesh != FAS_DFA_MESH_DX_OVER_AR))
             return fail(FAS_EINVAL, "bad Fourier analysis case");
         const Scheme &sc = SCHEMES[c.scheme];
         DfaCase &d = h[k];
@@ -1700,8 +1700,10 @@ extern "C" fas_status fas_dfa(const fas_dfa_case *cases, int32_t n_cases, double
         for (int q = 0; q < 4; ++q) d.u[q] = c.u[q];
         for (int q = 0; q < sc.s; ++q) {
             d.alpha[q] = sc.alpha[q];
-            d.beta[q] = sc.beta[q];
+            d.beta[q] = c.unsplit ? 1.0 : sc.beta[q];
         }
+        d.precond = c.precond;
+        d.mesh = c.mesh;
         d.s = sc.s;
         d.wform = sc.aw;
         d.nx = c.nx;
@@ -1716,17 +1718,32 @@ extern "C" fas_status fas_dfa(const fas_dfa_case *cases, int32_t n_cases, double
         total += (long long)c.nx * c.ny;
     }
     if (total > (1ll << 31)) return fail(FAS_EINVAL, "too many phase angles");
+    *total_out = total;
+    return FAS_OK;
+}
+
+// upload the descriptors to dc, run the analysis, wait for the results
+static fas_status dfa_run(const DfaCase *h, DfaCase *dc, int32_t n_cases, long long total, double *amp,
+                          double *smooth, double *radius, hipStream_t st) {
+    if (hipMemcpyAsync(dc, h, (size_t)n_cases * sizeof(DfaCase), hipMemcpyHostToDevice, st) != hipSuccess)
+        return fail(FAS_EDEVICE, "descriptor upload failed");
+    launch_dfa(dc, n_cases, total, radius, amp, smooth, st);
+    if (hipGetLastError() != hipSuccess || hipStreamSynchronize(st) != hipSuccess)
+        return fail(FAS_EDEVICE, "Fourier analysis kernel failed");
+    return FAS_OK;
+}
+
+extern "C" fas_status fas_dfa(const fas_dfa_case *cases, int32_t n_cases, double *amp, double *smooth,
+                              double *radius, void *stream) {
+    if (!cases || n_cases <= 0 || !amp || !smooth) return fail(FAS_EINVAL, "bad argument");
+    std::vector<DfaCase> h(n_cases);
+    long long total = 0;
+    STCHK(dfa_descriptors(cases, n_cases, h.data(), &total));
     hipStream_t st = (hipStream_t)stream;
     DfaCase *dc = nullptr;
     HIPCHK(hipMalloc(&dc, h.size() * sizeof(DfaCase)));
-    fas_status out = FAS_OK;
-    if (hipMemcpyAsync(dc, h.data(), h.size() * sizeof(DfaCase), hipMemcpyHostToDevice, st) != hipSuccess) {
-        out = fail(FAS_EDEVICE, "descriptor upload failed");
-    } else {
-        launch_dfa(dc, n_cases, total, radius, amp, smooth, st);
-        if (hipGetLastError() != hipSuccess || hipStreamSynchronize(st) != hipSuccess)
-            out = fail(FAS_EDEVICE, "Fourier analysis kernel failed");
-    }
+    const fas_status out = dfa_run(h.data(), dc, n_cases, total, amp, smooth, radius, st);
     (void)hipFree(dc);
     return out;
 }
+

@@ -12,6 +12,8 @@ struct DfaCase {
     double u[4];
     double alpha[5], beta[5];
     int s, wform, nx, ny, unsteady;
+    int precond;      // 0: SGS, 1: exact D + L + U, 2: none
+    int mesh;         // 0: dy = ar dx, 1: dy = dx / ar
     double cstar, d, eta, ar, c;
     long long start;
 };

@@ -2291,8 +2291,8 @@ __global__ __launch_bounds__(64, 2) void k_dfa(const DfaCase *cases, int n_cases
     // state, steps
     const double rho = P.u[0], v1 = P.u[1] / rho, v2 = P.u[2] / rho;
     const double a = sqrt(GAM * pres(P.u[0], P.u[1], P.u[2], P.u[3]) / rho);
-    const double dx = 1.0 / (double)P.nx, dy = P.ar * dx, vol = dx * dy;
-    const double base = dx / (fabs(v1) + a);
+    const double dx = 1.0 / (double)P.nx, dy = P.mesh ? dx / P.ar : P.ar * dx, vol = dx * dy;
+    const double base = fmin(dx / (fabs(v1) + a), dy / (fabs(v2) + a));
     const double dts = P.cstar * base, dt = P.c * base;
     const cx ex = cx{cos(tx), sin(tx)}, ey = cx{cos(ty), sin(ty)};
     const cx exi = conjx(ex), eyi = conjx(ey);
@@ -2304,9 +2304,14 @@ __global__ __launch_bounds__(64, 2) void k_dfa(const DfaCase *cases, int n_cases
     const double f = P.wform ? P.eta * dts : 1.0;
     const double diag = P.wform ? 1.0 + (P.unsteady ? 1.5 * P.eta * dts / dt : 0.0) : (P.unsteady ? 1.5 / dt : 0.0);
     // D + L, and X = D + U, then X := D^-1 (D + U) with the real D (split
-    // Jacobians of the unit normals (1, 0) and (0, 1), dead afterwards)
-    cx DL[16], X[16];
-    {
+    // Jacobians of the unit normals (1, 0) and (0, 1), dead afterwards);
+    // P = (D + L) D^-1 (D + U) (SGS), D + L + U (exact) or I (none)
+    cx Pm[16];
+    if (P.precond == 2) {
+#pragma unroll
+        for (int k = 0; k < 16; ++k) Pm[k] = cx{k % 5 == 0 ? 1.0 : 0.0, 0.0};
+    } else {
+        cx DL[16], X[16];
         double Ap[16], Am[16], Bp[16], Bm[16], D[16];
         split_face(P.u, P.u, 1.0, 0.0, P.d, 0.0, 0, Ap, Am);
         split_face(P.u, P.u, 0.0, 1.0, P.d, 0.0, 0, Bp, Bm);
@@ -2318,10 +2323,14 @@ __global__ __launch_bounds__(64, 2) void k_dfa(const DfaCase *cases, int n_cases
             DL[k] = cx{D[k], 0.0} + lk;
             X[k] = cx{D[k], 0.0} + uk;
         }
-        rsolve4(D, X);
+        if (P.precond == 1) {
+#pragma unroll
+            for (int k = 0; k < 16; ++k) Pm[k] = DL[k] + (X[k] - cx{D[k], 0.0});
+        } else {
+            rsolve4(D, X);
+            cmul4(DL, X, Pm);
+        }
     }
-    cx Pm[16];
-    cmul4(DL, X, Pm);                                    // P = (D + L) D^-1 (D + U)
     // H_c and H_v side by side as 8 right-hand columns, from the flux
     // Jacobians of the constant state; then [P^-1 H_c | P^-1 H_v]
     cx RHS[32];

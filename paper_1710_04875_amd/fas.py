@@ -448,7 +448,12 @@ class _DfaCase(ctypes.Structure):
     _fields_ = [("u", ctypes.c_double * 4), ("scheme", ctypes.c_int32), ("nx", ctypes.c_int32),
                 ("ny", ctypes.c_int32), ("unsteady", ctypes.c_int32), ("cstar", ctypes.c_double),
                 ("d", ctypes.c_double), ("eta", ctypes.c_double), ("ar", ctypes.c_double),
-                ("c", ctypes.c_double)]
+                ("c", ctypes.c_double), ("precond", ctypes.c_int32), ("unsplit", ctypes.c_int32),
+                ("mesh", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+DFA_SGS, DFA_EXACT, DFA_NONE = 0, 1, 2
+DFA_MESH_AR_DX, DFA_MESH_DX_OVER_AR = 0, 1
 
 
 @dataclass
@@ -466,6 +471,9 @@ class DfaCase:
     nx: int = 8
     ny: int = 0
     unsteady: int = 1
+    precond: int = 0
+    unsplit: int = 0
+    mesh: int = 0
 
     def c_struct(self) -> _DfaCase:
         x = _DfaCase()
@@ -475,6 +483,7 @@ class DfaCase:
         x.ny = int(self.ny) if self.ny else int(round(self.nx * self.ar))
         x.unsteady = int(self.unsteady)
         x.cstar, x.d, x.eta, x.ar, x.c = float(self.cstar), float(self.d), float(self.eta), float(self.ar), float(self.c)
+        x.precond, x.unsplit, x.mesh, x.reserved = int(self.precond), int(self.unsplit), int(self.mesh), 0
         return x
 
 

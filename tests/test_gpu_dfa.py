@@ -18,10 +18,13 @@ TOL = 1e-10
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "dfa_amplification_alpha0_ar1.txt")
 
 
-def _pair(scheme, cstar, d, eta, ar=1.0, u=odfa.U_ALPHA0, unsteady=True, c=200.0):
+def _pair(scheme, cstar, d, eta, ar=1.0, u=odfa.U_ALPHA0, unsteady=True, c=200.0, precond=0, unsplit=0,
+          mesh=0):
     from paper_1710_04875_amd import fas
-    g = fas.DfaCase(u=u, scheme=scheme, cstar=cstar, d=d, eta=eta, ar=ar, c=c, unsteady=int(unsteady))
-    o = odfa.DfaCase(u=u, scheme=scheme, cstar=cstar, d=d, eta=eta, ar=ar, c=c, unsteady=unsteady)
+    g = fas.DfaCase(u=u, scheme=scheme, cstar=cstar, d=d, eta=eta, ar=ar, c=c, unsteady=int(unsteady),
+                    precond=precond, unsplit=unsplit, mesh=mesh)
+    o = odfa.DfaCase(u=u, scheme=scheme, cstar=cstar, d=d, eta=eta, ar=ar, c=c, unsteady=unsteady,
+                     precond=precond, unsplit=bool(unsplit), mesh=mesh)
     return g, o
 
 
@@ -33,6 +36,12 @@ CASES = [
     (osm.AW5J, 1e6, 0.5, 0.5, 100.0, odfa.U_ALPHA0, True),
     (osm.PARK51, 2, 0.0, 0.8, 1.0, odfa.U_ALPHA45, True),
     (osm.AW3, 12, 0.1, 0.8, 100.0, odfa.U_ALPHA0, True),
+    # exact preconditioner, no preconditioner (unsplit: ERK3), dy = dx / AR
+    (osm.AW3, 7, 1.0, 0.8, 1.0, odfa.U_ALPHA0, True, 200.0, odfa.EXACT),
+    (osm.PARK3J, 14, 0.5, 0.8, 4.0, odfa.U_ALPHA45, True, 200.0, odfa.EXACT),
+    (osm.PARK3J, 0.9, 0.5, 0.8, 1.0, odfa.U_ALPHA0, True, 200.0, odfa.NONE, 1),
+    (osm.PARK3J, 0.9, 0.5, 0.8, 4.0, odfa.U_ALPHA0, False, 200.0, odfa.NONE, 0),
+    (osm.PARK3J, 900, 0.1, 0.8, 100.0, odfa.U_ALPHA0, True, 200.0, odfa.SGS, 0, odfa.MESH_DX_OVER_AR),
 ]
 
 
@@ -70,6 +79,21 @@ def test_printed_amplification_factors():
         assert abs(amp[k] - rho) <= 5e-5, (k, amp[k], rho)
 
 
+def test_printed_exact_preconditioner_factors():
+    from paper_1710_04875_amd import fas
+    path = os.path.join(os.path.dirname(__file__), "golden", "dfa_exact_preconditioner_aw3.txt")
+    rows = []
+    with open(path) as f:
+        for line in f:
+            if line.strip() and not line.startswith("#"):
+                rows.append(tuple(float(v) for v in line.split()))
+    amp, _ = fas.dfa([fas.DfaCase(scheme=osm.AW3, cstar=cs, d=d, eta=0.8, ar=ar, precond=fas.DFA_EXACT)
+                      for ar, cs, d, _ in rows])
+    amp = amp.cpu().numpy()
+    for k, (_, _, _, rho) in enumerate(rows):
+        assert abs(amp[k] - rho) <= 5e-5, (k, amp[k], rho)
+
+
 def test_aspect_ratio_10000_sampled_pairs():
     """The 8 x 80000 mesh at full size: sampled pairs against the oracle,
     one by one, and the factors against the maximum of the radii."""
@@ -92,6 +116,7 @@ def test_aspect_ratio_10000_sampled_pairs():
 def test_argument_checks():
     from paper_1710_04875_amd import fas
     for bad in (dict(nx=7), dict(ny=3), dict(u=(0.0, 1.0, 0.0, 3.29)), dict(u=(1.0, 1.0, 0.0, 0.1)),
-                dict(cstar=0.0), dict(d=-1.0), dict(ar=0.0), dict(scheme=9)):
+                dict(cstar=0.0), dict(d=-1.0), dict(ar=0.0), dict(scheme=9), dict(precond=3),
+                dict(mesh=2), dict(unsplit=2)):
         with pytest.raises(fas.FasError):
             fas.dfa([fas.DfaCase(**bad)])
