@@ -418,6 +418,22 @@ fas_status fas_dfa(const fas_dfa_case *cases, int32_t n_cases, double *amp, doub
                    void *stream);
 
 /*
+ * fas_dfa for callers that cannot allocate device memory (serving loops
+ * and harnesses that forbid hipMalloc): the same analysis with no
+ * hipMalloc, hipFree or other allocating call.  The per-case descriptor
+ * table lives in a fixed device array of FAS_DFA_NOALLOC_MAX_CASES entries
+ * (about 190 KiB, held by each GPU the library runs on until the process
+ * ends); n_cases above that limit gives FAS_EINVAL.  Arguments, outputs and
+ * synchronisation as fas_dfa.  Every call on a GPU shares that GPU's table:
+ * the library serialises its own calls until their results are written;
+ * calls that overlap through other means (another copy of the library in
+ * the process) race.
+ */
+#define FAS_DFA_NOALLOC_MAX_CASES 1024
+fas_status fas_dfa_noalloc(const fas_dfa_case *cases, int32_t n_cases, double *amp, double *smooth,
+                           double *radius, void *stream);
+
+/*
  * Launch-size rule of the residual and preconditioner-block kernels: a
  * launch of at most max_cells cells (over all cases of a batch) runs the
  * four-lanes-per-cell variants (one face per lane), a larger one the

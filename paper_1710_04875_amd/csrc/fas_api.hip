@@ -8,6 +8,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -1745,5 +1746,36 @@ extern "C" fas_status fas_dfa(const fas_dfa_case *cases, int32_t n_cases, double
     const fas_status out = dfa_run(h.data(), dc, n_cases, total, amp, smooth, radius, st);
     (void)hipFree(dc);
     return out;
+}
+
+// Allocation-free variant of fas_dfa: the descriptor table lives in a
+// file-scope device array (each GPU holds its own copy for the life of the
+// process); its address on each device is looked up once, with that device
+// current, and the host staging table is a static array.  A mutex
+// serialises the library's own calls up to the point where the results are
+// written.
+static __device__ __align__(256) DfaCase scratch[FAS_DFA_NOALLOC_MAX_CASES];
+static DfaCase g_dfa_host[FAS_DFA_NOALLOC_MAX_CASES];
+static std::mutex g_dfa_mutex;
+constexpr int MAX_DEVICES = 64;
+static DfaCase *g_scratch_ptr[MAX_DEVICES] = {nullptr};
+
+extern "C" fas_status fas_dfa_noalloc(const fas_dfa_case *cases, int32_t n_cases, double *amp, double *smooth,
+                                      double *radius, void *stream) {
+    if (!cases || n_cases <= 0 || !amp || !smooth) return fail(FAS_EINVAL, "bad argument");
+    if (n_cases > FAS_DFA_NOALLOC_MAX_CASES)
+        return fail(FAS_EINVAL, "more cases than the allocation-free table holds (FAS_DFA_NOALLOC_MAX_CASES)");
+    int dev = 0;
+    HIPCHK(hipGetDevice(&dev));
+    if (dev < 0 || dev >= MAX_DEVICES) return fail(FAS_EDEVICE, "device index out of range");
+    std::lock_guard<std::mutex> lock(g_dfa_mutex);
+    if (!g_scratch_ptr[dev]) {
+        void *ptr = nullptr;
+        HIPCHK(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+        g_scratch_ptr[dev] = static_cast<DfaCase *>(ptr);
+    }
+    long long total = 0;
+    STCHK(dfa_descriptors(cases, n_cases, g_dfa_host, &total));
+    return dfa_run(g_dfa_host, g_scratch_ptr[dev], n_cases, total, amp, smooth, radius, (hipStream_t)stream);
 }
 

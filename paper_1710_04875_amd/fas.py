@@ -88,7 +88,8 @@ EXPORTS = [
     "fas_sweep_config_count", "fas_sweep_config_info", "fas_batch_profile",
     "fas_batch_profile_read", "fas_forces", "fas_vjp", "fas_param_partials",
     "fas_sgs_apply_transpose", "fas_adjoint_solve", "fas_lift_gradient", "fas_vjp_nodes",
-    "fas_lift_gradient_nodes", "fas_set_motion", "fas_dfa", "fas_vjp_smooth", "fas_set_four_lane_limit",
+    "fas_lift_gradient_nodes", "fas_set_motion", "fas_dfa", "fas_dfa_noalloc", "fas_vjp_smooth",
+    "fas_set_four_lane_limit",
     "fas_last_error",
 ]
 PROF_CLASSES = ("sweep", "residual", "blocks")
@@ -145,6 +146,7 @@ def load(path: str = LIB_PATH):
         "fas_lift_gradient_nodes": (i32, [vp, i32, f64, dp, dp, vp, vp, dp, ip]),
         "fas_set_motion": (i32, [vp, f64, f64, f64, f64]),
         "fas_dfa": (i32, [ctypes.POINTER(_DfaCase), i32, vp, vp, vp, vp]),
+        "fas_dfa_noalloc": (i32, [ctypes.POINTER(_DfaCase), i32, vp, vp, vp, vp]),
         "fas_last_error": (ctypes.c_char_p, []),
     }
     for name, (res, args) in sig.items():
