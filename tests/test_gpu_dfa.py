@@ -15,6 +15,15 @@ from oracle import smoother as osm
 pytestmark = pytest.mark.gpu
 
 TOL = 1e-10
+# With the exact or no preconditioner the iteration matrices of some pairs
+# have multiple, defective eigenvalues (G is a multiple of I at zero phase
+# and nearly so around it): their moduli are determined only to about the
+# square root of the rounding of G, so those cases are compared at 1e-7
+TOL_DEFECTIVE = 1e-7
+
+
+def _tol(precond):
+    return TOL if precond == odfa.SGS else TOL_DEFECTIVE
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "dfa_amplification_alpha0_ar1.txt")
 
 
@@ -57,9 +66,10 @@ def test_every_phase_angle_pair_matches_the_oracle():
         n = r.size
         got = rad[off:off + n]
         off += n
-        assert np.abs(got - r).max() <= TOL * max(1.0, r.max()), (k, np.abs(got - r).max())
-        assert abs(float(amp[k]) - a) <= TOL * max(1.0, a), k
-        assert abs(float(smooth[k]) - s) <= TOL * max(1.0, s), k
+        tol = _tol(o.precond)
+        assert np.abs(got - r).max() <= tol * max(1.0, r.max()), (k, np.abs(got - r).max())
+        assert abs(float(amp[k]) - a) <= tol * max(1.0, a), k
+        assert abs(float(smooth[k]) - s) <= tol * max(1.0, s), k
         assert float(smooth[k]) <= float(amp[k])
     assert off == rad.size
 
