@@ -227,3 +227,96 @@ def smoother_jacobian(S, u):
         uc[k] += 1j * H_CS
         J[:, k] = smoother_map(S, uc.reshape(u.shape), frozen).imag.reshape(-1) / H_CS
     return J
+
+
+# ------------------------------------------------- dual time stepping
+# Eq. "nonlin-eq" with the start of Section 6: step n solves
+#   F(u^n; alpha_n, M) + T^n = 0,  T^1 = (u^1 - u^0)/dt,
+#   T^n = (3 u^n - 4 u^{n-1} + u^{n-2})/(2 dt) (n >= 2),
+# from the steady solution u^0 of F(u; alpha_0, M) = 0.  The functional is
+# the time-averaged lift J = (1/N) sum_{n=1..N} C_L(u^n, alpha_n).
+
+def unsteady_states(S, dt, alphas, max_cycles, drop):
+    """u^0 .. u^N of the oracle's dual time stepping from its current
+    (converged, steady) state, the far-field angle set to alphas[n] at step n."""
+    states = [S.u(0)]
+    for n in range(1, len(alphas)):
+        S.begin_time_step(dt, alphas[n])
+        S.run_cycles(max_cycles, drop)
+        states.append(S.u(0))
+    return states
+
+
+def _jacobian_at(S, u, mutp, alpha):
+    n = u.size
+    J = np.empty((n, n))
+    flat = u.reshape(-1)
+    for k in range(n):
+        uc = flat.astype(complex)
+        uc[k] += 1j * H_CS
+        J[:, k] = fine_residual(S, uc.reshape(u.shape), mutp, alpha_deg=alpha).imag.reshape(-1) / H_CS
+    return J
+
+
+def _lift_grad_u(S, u, alpha):
+    flat = u.reshape(-1)
+    g = np.empty(flat.size)
+    for k in range(flat.size):
+        uc = flat.astype(complex)
+        uc[k] += 1j * H_CS
+        g[k] = forces(S, uc.reshape(u.shape), alpha_deg=alpha)[0].imag / H_CS
+    return g
+
+
+def unsteady_direct_gradient(S, states, dt, alphas):
+    """(J, dJ/dM, dJ/dalpha_n per degree for n = 0..N) by forward
+    (direct) sensitivities through the steps: for a parameter q,
+    v^0 = -F_u^-1 F_q at the steady start, and for n >= 1
+    (F_u + tau_n I) v^n = -F_q - dT^n/du^{n-1} v^{n-1} - dT^n/du^{n-2} v^{n-2},
+    dJ/dq = (1/N) sum_n (dC_L/du . v^n + dC_L/dq).  Dense Jacobians by the
+    complex step (small grids only), the eddy viscosity frozen at each
+    state.  Independent of any transposed (adjoint) product."""
+    N = len(states) - 1
+    w = 1.0 / N
+    mach = S.par.mach
+    nu = states[0].size
+    Jn, Fa, Fm, g, cla, clm, cl = [], [], [], [], [], [], []
+    for n, u in enumerate(states):
+        a = alphas[n]
+        uinf = gas.freestream(mach, a)
+        mutp = None
+        if S.par.model == 1:
+            lev = S.levels[0]
+            mutp = padded_eddy_viscosity(lev, baldwin_lomax(lev, _padded(S, u, uinf),
+                                                            dataclasses.replace(S.par, alpha_deg=a)))
+        Jn.append(_jacobian_at(S, u, mutp, a))
+        Fa.append((fine_residual(S, u, mutp, alpha_deg=a + 1j * H_CS).imag / H_CS).reshape(-1))
+        Fm.append((fine_residual(S, u, mutp, mach=mach + 1j * H_CS, alpha_deg=a).imag / H_CS).reshape(-1))
+        g.append(_lift_grad_u(S, u, a))
+        cla.append(forces(S, u, alpha_deg=a + 1j * H_CS)[0].imag / H_CS)
+        clm.append(forces(S, u, mach=mach + 1j * H_CS, alpha_deg=a)[0].imag / H_CS)
+        cl.append(forces(S, u, alpha_deg=a)[0])
+    I = np.eye(nu)
+
+    def sensitivity(Fq):
+        # Fq[n]: dF_n/dq (zero vector where q does not enter step n)
+        v = [np.linalg.solve(Jn[0], -Fq[0])]
+        for n in range(1, N + 1):
+            tau = 1.0 / dt if n == 1 else 1.5 / dt
+            rhs = -Fq[n]
+            if n == 1:
+                rhs = rhs + v[0] / dt                     # dT^1/du^0 = -1/dt
+            else:
+                rhs = rhs + (2.0 / dt) * v[n - 1] - (0.5 / dt) * v[n - 2]
+            v.append(np.linalg.solve(Jn[n] + tau * I, rhs))
+        return v
+
+    z = np.zeros(nu)
+    vm = sensitivity(Fm)
+    dJ_dm = w * sum(g[n] @ vm[n] + clm[n] for n in range(1, N + 1))
+    dJ_da = []
+    for k in range(N + 1):
+        va = sensitivity([Fa[n] if n == k else z for n in range(N + 1)])
+        dJ_da.append(w * sum(g[n] @ va[n] + (cla[n] if n == k else 0.0) for n in range(1, N + 1)))
+    J = w * sum(cl[1:])
+    return J, dJ_dm, np.array(dJ_da)

@@ -202,7 +202,12 @@ class Solver:
         if self.n_cycles < par.n_ramp:
             return min(par.cfl, par.cfl_ramp)
         if par.ramp_growth > 1.0:
-            return min(par.cfl, par.cfl_ramp * par.ramp_growth ** (self.n_cycles - par.n_ramp + 1))
+            k = self.n_cycles - par.n_ramp + 1
+            # once the ramp has reached c* it stays there (the power is not
+            # formed past that point, where it would overflow)
+            if par.cfl_ramp <= 0.0 or k * np.log(par.ramp_growth) >= np.log(par.cfl / par.cfl_ramp):
+                return par.cfl
+            return min(par.cfl, par.cfl_ramp * par.ramp_growth ** k)
         return par.cfl
 
     # -------------------------------------------------------------- smoother

@@ -181,3 +181,49 @@ def test_smoother_jacobian_matches_central_differences(model, scheme):
     h = 1e-7
     fd = (adj.smoother_map(S, u + h * v, frozen) - adj.smoother_map(S, u - h * v, frozen)) / (2 * h)
     assert np.abs(J @ v.reshape(-1) - fd.reshape(-1)).max() < 1e-7 * np.abs(fd).max()
+
+
+def _unsteady_setup(mach, alpha0):
+    """16 x 8 Euler C-grid: the steady start converged by 2-level V-cycles,
+    the physical steps on one level (whose inner solves converge quickly)."""
+    x, y = fi.cgrid(16, 8, 2)
+    p2 = fas.Params(model=0, mach=mach, alpha_deg=alpha0, n_levels=2, cfl=10.0, cfl_ramp=5.0, n_ramp=1,
+                    ramp_growth=1.5, dt_form=0)
+    S = fas.Solver(x, y, fi.CGRID, 2, p2, fi.uniform_state(16, 8, mach, alpha0))
+    S.run_cycles(3000, 13.0)
+    p1 = fas.Params(**{**p2.__dict__, "n_levels": 1})
+    return fas.Solver(x, y, fi.CGRID, 2, p1, S.u(0))
+
+
+def test_unsteady_direct_gradient_matches_central_differences():
+    """Dual time stepping (implicit Euler start, then BDF2; eq.
+    "nonlin-eq"): the forward-sensitivity gradient of the time-averaged lift
+    equals central differences of whole runs for the angle of the first
+    step (the Mach number, which also moves the steady start, is checked by
+    central differences on the GPU, where the runs are cheap)."""
+    dt, mach, alphas = 0.1, 0.5, [1.0, 1.3, 1.6]
+
+    def J_of(m, al, S=None):
+        S = _unsteady_setup(m, al[0]) if S is None else S
+        # the inner solves of this tiny grid settle into a limit cycle of
+        # the sensor switches at about 3e-11 (7.5 orders below the step's
+        # first norm): they stop at 7 orders
+        st = adj.unsteady_states(S, dt, al, 1500, 7.0)
+        return np.mean([adj.forces(S, u, mach=m, alpha_deg=a)[0] for u, a in zip(st[1:], al[1:])]), st
+
+    S0 = _unsteady_setup(mach, alphas[0])
+    u0 = S0.u(0)
+    J, states = J_of(mach, alphas, S0)
+    Jd, dm, da = adj.unsteady_direct_gradient(S0, states, dt, alphas)
+    assert abs(Jd - J) < 1e-14
+    ha = 1e-3
+    x, y = fi.cgrid(16, 8, 2)
+
+    def from_start(al):
+        S = fas.Solver(x, y, fi.CGRID, 2, S0.par.__class__(**{**S0.par.__dict__, "alpha_deg": al[0]}), u0)
+        return J_of(mach, al, S)[0]
+
+    fd_a1 = (from_start([1.0, 1.3 + ha, 1.6]) - from_start([1.0, 1.3 - ha, 1.6])) / (2 * ha)
+    # central differences of inner solves stopped at 7 orders: O(h^2) and
+    # O(1e-11 / h) errors, both below 1e-4 of the derivative here
+    assert abs(da[1] - fd_a1) <= 1e-4 * abs(fd_a1)
