@@ -354,6 +354,40 @@ fas_status fas_lift_gradient(fas_state s, int32_t max_iter, double drop_orders, 
                              double *grad, double *res_hist, int32_t *n_iter);
 
 /*
+ * Discrete adjoint of dual time stepping (eq. "nonlin-eq", implicit Euler on
+ * the first step and BDF2 after it) on a fixed mesh, with checkpointing.
+ * Functional: the time-averaged lift J = (1/N) sum_{n=1..N} C_L(u^n) of
+ * N = n_steps physical steps of size dt started from the state's current
+ * solution u^0, which must be the converged steady solution at
+ * alpha_deg[0] (fas_cycle first); step n sets the far-field angle to
+ * alpha_deg[n] (host, n_steps + 1 entries) and runs inner FAS cycles as
+ * fas_dual_time_step (max_inner, inner_drop).  The adjoint runs backwards
+ * through the steps and the steady start, each step an adjoint solve of
+ * (dF/du + tau I)^T (tau = 1/dt, then 3/(2 dt); 0 for the steady start) as
+ * in fas_adjoint_solve (adj_max_iter, adj_drop) with the eddy viscosity
+ * frozen at that step's state (frozen turbulence).  Only every
+ * checkpoint_every-th step's state is kept (with its previous time level):
+ * the reverse pass recomputes the steps in between from the checkpoint
+ * before them (checkpoint_every = 1 keeps every state, larger values trade
+ * recomputation for memory).  Outputs (host): J, dJ/dM, dJ/dalpha_n per
+ * degree for n = 0..N (dJ_dalpha, n_steps + 1 entries; entry 0 through the
+ * steady start), the adjoint iterations per step and the orders of adjoint
+ * residual drop each reached (adj_iters, adj_orders, nullable, n_steps + 1
+ * entries; a step short of adj_drop leaves its gradient terms unconverged)
+ * and the number of recomputed steps (nullable).  The adjoint solves use the
+ * preconditioner at the full c*.  On
+ * return the state holds the last step's solution and time levels, as after
+ * fas_dual_time_step.  Errors: FAS_EINVAL (bad arguments, a moving mesh, a
+ * state that has taken dual time steps), FAS_ENOMEM, FAS_DIVERGED,
+ * FAS_EDEVICE.
+ */
+fas_status fas_unsteady_lift_gradient(fas_state s, int32_t n_steps, double dt, const double *alpha_deg,
+                                      int32_t max_inner, double inner_drop, int32_t checkpoint_every,
+                                      int32_t adj_max_iter, double adj_drop, double *J, double *dJ_dmach,
+                                      double *dJ_dalpha, int32_t *adj_iters, double *adj_orders,
+                                      int32_t *recomputed_steps);
+
+/*
  * Grid-node sensitivities of the steady fine-level residual and the lift.
  * The residual depends on the nodes through the metrics of Section 2 (face
  * vectors, mean face vectors, volumes, cell centres, and the ghost cells'

@@ -137,6 +137,8 @@ struct fas_state_s {
            *a_lam0 = nullptr, *a_zeta = nullptr, *a_dFa = nullptr, *a_dFm = nullptr, *a_dcl = nullptr,
            *a_red = nullptr, *a_out = nullptr, *a_basis = nullptr;
     double *a_smv = nullptr;    // smoother VJP: stage states and work vectors (lazy)
+    double adj_tau = 0.0;       // diagonal of the physical-time term in the adjoint operator
+    std::vector<double *> a_ck; // unsteady adjoint: checkpoints and the recomputation window
     // graph-replayed cycles: activity flag (read by every kernel of the
     // state), cycles done, status, initial norm, history; a private stream
     // to capture on (the state's own stream may be the legacy default)
@@ -1028,12 +1030,21 @@ fas_status fine_dot(fas_state s, const double *a, const double *b, double *out) 
     return FAS_OK;
 }
 
-// a_r = a_g - (dF/du)^T a_lam at the prepared state
+// out = (dF/du + tau I)^T v at the prepared state: the steady Jacobian's
+// transpose, plus the diagonal of the physical-time term of eq.
+// "nonlin-eq" (s->adj_tau: 3/(2 dt) for a BDF2 step, 1/dt for the implicit
+// Euler start, 0 for the steady adjoint entry points); out is overwritten
+void adj_operator(fas_state s, const double *v, double *out) {
+    const LevelDev &d = s->lv[0];
+    launch_zero(out, (size_t)4 * d.L.NS, s->e.st);
+    launch_vjp(d.L, d.geo, d.u, d.mut, s->ph, v, out, s->e.st);
+    if (s->adj_tau != 0.0) launch_axpby_ptr(d.L, 1.0, out, s->adj_tau, v, out, s->e.st);
+}
+
+// a_r = a_g - (dF/du + tau I)^T a_lam at the prepared state
 void adj_residual(fas_state s, const double *lam) {
     const LevelDev &d = s->lv[0];
-    const size_t V = (size_t)4 * d.L.NS;
-    launch_zero(s->a_jt, V, s->e.st);
-    launch_vjp(d.L, d.geo, d.u, d.mut, s->ph, lam, s->a_jt, s->e.st);
+    adj_operator(s, lam, s->a_jt);
     launch_axpby_ptr(d.L, 1.0, s->a_g, -1.0, s->a_jt, s->a_r, s->e.st);
 }
 
@@ -1097,10 +1108,9 @@ fas_status adj_solve(fas_state s, int max_iter, double drop, double *hist, int *
         gg[0] = res;
         int k = 0;
         for (; k < M && it < max_iter; ++k) {
-            // w = J^T M v_k
+            // w = (J + tau I)^T M v_k
             adj_precond(s, vb(k), s->a_r);
-            launch_zero(vb(k + 1), V, e.st);
-            launch_vjp(d.L, d.geo, d.u, d.mut, s->ph, s->a_r, vb(k + 1), e.st);
+            adj_operator(s, s->a_r, vb(k + 1));
             // classical Gram-Schmidt, twice (all k + 1 products in one launch)
             for (int pass = 0; pass < 2; ++pass) {
                 launch_mdot(d.L, vb(k + 1), vb(0), V, k + 1, d_red, d_h, e.st);
@@ -1392,6 +1402,197 @@ extern "C" fas_status fas_lift_gradient_nodes(fas_state s, int32_t max_iter, dou
     STCHK(node_gradient(s, s->a_lam, true, dcl_dx, dcl_dy));
     HIPCHK(hipStreamSynchronize(s->e.st));
     return st;
+}
+
+// Discrete adjoint of dual time stepping (eq. "nonlin-eq": implicit Euler on
+// the first step, BDF2 after it) on a fixed mesh, for the time-averaged lift
+// J = (1/N) sum_{n=1..N} C_L(u^n, alpha_n) of N steps started from the
+// state's steady solution u^0 at alpha_0.  Step n solves
+//     R^n = F(u^n; alpha_n, M) + T^n = 0,
+//     T^1 = (u^1 - u^0) / dt,  T^n = (3 u^n - 4 u^{n-1} + u^{n-2}) / (2 dt),
+// and u^0 solves F(u^0; alpha_0, M) = 0.  Backwards from n = N to 0:
+//     (dF/du|_n + tau_n I)^T lam^n = -(1/N) dC_L/du|_n (n >= 1)
+//         - (dT^{n+1}/du^n) lam^{n+1} - (dT^{n+2}/du^n) lam^{n+2}
+// with tau_1 = 1/dt, tau_n = 3/(2 dt), tau_0 = 0, dT^{n+1}/du^n = -2/dt
+// (-1/dt for n = 0) and dT^{n+2}/du^n = 1/(2 dt); then
+//     dJ/dM = sum_n [(1/N) dC_L/dM|_n + lam^n . dF/dM|_n],
+//     dJ/dalpha_n = (1/N) dC_L/dalpha|_n + lam^n . dF/dalpha|_n.
+// States are kept at every checkpoint_every-th step (each checkpoint holds
+// u^k and u^{k-1}); the reverse pass recomputes the states between two
+// checkpoints from the earlier one (the same dual time steps, so bitwise the
+// same states) into a window and runs the adjoint steps of that segment.
+extern "C" fas_status fas_unsteady_lift_gradient(fas_state s, int32_t n_steps, double dt, const double *alpha_deg,
+                                                 int32_t max_inner, double inner_drop, int32_t checkpoint_every,
+                                                 int32_t adj_max_iter, double adj_drop, double *J, double *dJ_dmach,
+                                                 double *dJ_dalpha, int32_t *adj_iters, double *adj_orders,
+                                                 int32_t *recomputed_steps) {
+    if (!s || !alpha_deg || !J || !dJ_dmach || !dJ_dalpha || n_steps < 1 || !(dt > 0.0) || max_inner < 1 ||
+        checkpoint_every < 1 || adj_max_iter < 0)
+        return fail(FAS_EINVAL, "bad argument");
+    if (s->ale) return fail(FAS_EINVAL, "the adjoint is for fixed meshes");
+    if (s->e.bdf != 0 || s->step != 0) return fail(FAS_EINVAL, "the unsteady adjoint starts from a steady state");
+    for (int n = 0; n <= n_steps; ++n)
+        if (!std::isfinite(alpha_deg[n])) return fail(FAS_EINVAL, "bad angle");
+    STCHK(ensure_adjoint(s));
+    Engine &e = s->e;
+    const LevelDev &d = s->lv[0];
+    const size_t V = (size_t)4 * d.L.NS;
+    const int N = n_steps, K = checkpoint_every;
+    const int nck = N / K + 1;                 // checkpoints at steps 0, K, 2K, ... <= N
+    // buffers: per checkpoint u^k and u^{k-1}; a window of K states; the
+    // adjoints lam^{n+1} and lam^{n+2}; the final state and its time levels
+    const size_t need = (size_t)2 * nck + K + 2 + 3;
+    for (double *p : s->a_ck) (void)hipFree(p);
+    s->a_ck.clear();
+    for (size_t k = 0; k < need; ++k) {
+        double *p = nullptr;
+        if (hipMalloc(&p, V * sizeof(double)) != hipSuccess) {
+            for (double *q : s->a_ck) (void)hipFree(q);
+            s->a_ck.clear();
+            return fail(FAS_ENOMEM, "unsteady adjoint storage");
+        }
+        s->a_ck.push_back(p);
+        launch_zero(p, V, e.st);
+    }
+    double **ck = s->a_ck.data();                          // [2 nck]: u^k, u^{k-1}
+    double **win = ck + 2 * nck;                           // [K]
+    double *l1 = win[K], *l2 = win[K + 1];                 // lam^{n+1}, lam^{n+2}
+    double *fin_u = win[K + 2], *fin_un = win[K + 3], *fin_unm1 = win[K + 4];
+    const fas_params p0 = s->p;
+    auto set_alpha = [&](double a) {
+        s->p.alpha_deg = a;
+        return set_phys(s);
+    };
+    auto copy = [&](const double *src, double *dst) { launch_axpby_ptr(d.L, 1.0, src, 0.0, nullptr, dst, e.st); };
+    // ------------------------------------------------------------ forward
+    const double w = 1.0 / N;
+    double Jsum = 0.0;
+    copy(d.u, ck[0]);
+    STCHK(set_alpha(alpha_deg[0]));
+    for (int n = 1; n <= N; ++n) {
+        int nd = 0;
+        const fas_status st = fas_dual_time_step(s, dt, alpha_deg[n], max_inner, inner_drop, nullptr, &nd);
+        if (st == FAS_DIVERGED || st == FAS_EDEVICE || st == FAS_EINVAL || st == FAS_ENOMEM) return st;
+        launch_forces(d.L, d.geo, d.u, s->ph, s->a_out, nullptr, e.st);
+        double h[6];
+        HIPCHK(hipMemcpyAsync(h, s->a_out, sizeof(h), hipMemcpyDeviceToHost, e.st));
+        HIPCHK(hipStreamSynchronize(e.st));
+        Jsum += w * h[0];
+        if (n % K == 0) {
+            copy(d.u, ck[2 * (n / K)]);
+            copy(d.un, ck[2 * (n / K) + 1]);
+        }
+    }
+    copy(d.u, fin_u);
+    copy(d.un, fin_un);
+    if (N >= 2) copy(d.unm1, fin_unm1);
+    const double fin_t = s->t;
+    int fin_cyc = 0;
+    HIPCHK(hipMemcpyAsync(&fin_cyc, e.d_cyc, sizeof(int), hipMemcpyDeviceToHost, e.st));
+    HIPCHK(hipStreamSynchronize(e.st));
+    std::vector<double> hist((size_t)adj_max_iter + 1);
+    // ------------------------------------------------------------ reverse
+    launch_zero(l1, V, e.st);
+    launch_zero(l2, V, e.st);
+    double dM = 0.0;
+    for (int n = 0; n <= N; ++n) dJ_dalpha[n] = 0.0;
+    int recomputed = 0;
+    for (int seg = N / K; seg >= 0; --seg) {
+        const int k0 = seg * K, k1 = std::min(k0 + K, N + 1);
+        // the segment's states u^{k0} .. u^{k1 - 1} into the window
+        if (k0 == 0) {
+            copy(ck[0], d.u);
+            e.bdf = 0;
+            e.dt = 0.0;
+            s->have_un = 0;
+            s->t = 0.0;
+            s->step = 0;
+        } else {
+            copy(ck[2 * seg], d.u);
+            copy(ck[2 * seg + 1], d.un);
+            for (int l = 1; l < s->nlev; ++l) launch_restrict(e.lev[l - 1], e.lev[l], FLD_UN, FLD_UN, FLD_NONE, e.st);
+            e.bdf = k0 > 1 ? 2 : 1;
+            e.dt = dt;
+            s->have_un = 1;
+            s->t = k0 * dt;
+            s->step = k0;
+        }
+        STCHK(set_alpha(alpha_deg[k0]));
+        copy(d.u, win[0]);
+        for (int n = k0 + 1; n < k1; ++n) {
+            int nd = 0;
+            const fas_status st = fas_dual_time_step(s, dt, alpha_deg[n], max_inner, inner_drop, nullptr, &nd);
+            if (st == FAS_DIVERGED || st == FAS_EDEVICE || st == FAS_EINVAL || st == FAS_ENOMEM) return st;
+            copy(d.u, win[n - k0]);
+            ++recomputed;
+        }
+        for (int n = k1 - 1; n >= k0; --n) {
+            copy(win[n - k0], d.u);
+            e.bdf = n >= 2 ? 2 : n;
+            e.dt = n >= 1 ? dt : 0.0;
+            s->adj_tau = n >= 2 ? 1.5 / dt : n == 1 ? 1.0 / dt : 0.0;
+            STCHK(set_alpha(alpha_deg[n]));
+            prep(e, 0, fine_rans(e, 0));          // eddy viscosity frozen at u^n
+            // right-hand side: -(1/N) dC_L/du + c1 lam^{n+1} - (1/(2 dt)) lam^{n+2}
+            launch_zero(s->a_dcl, V, e.st);
+            launch_forces(d.L, d.geo, d.u, s->ph, s->a_out, s->a_dcl, e.st);
+            double h[6];
+            HIPCHK(hipMemcpyAsync(h, s->a_out, sizeof(h), hipMemcpyDeviceToHost, e.st));
+            HIPCHK(hipStreamSynchronize(e.st));
+            const double c1 = n >= 1 ? 2.0 / dt : 1.0 / dt;
+            launch_axpby_ptr(d.L, n >= 1 ? -w : 0.0, s->a_dcl, c1, l1, s->a_g, e.st);
+            launch_axpby_ptr(d.L, 1.0, s->a_g, -0.5 / dt, l2, s->a_g, e.st);
+            copy(l1, s->a_lam);                   // initial guess: the later step's adjoint
+            // the preconditioner's dt* at the full c*, whatever cycle count
+            // the (re)computed step left behind
+            launch_fill_int(e.d_cyc, 1, 1 << 24, e.st);
+            int it = 0;
+            const fas_status st = adj_solve(s, adj_max_iter, adj_drop, hist.data(), &it);
+            if (adj_iters) adj_iters[n] = it;
+            if (adj_orders) {
+                double lo = hist[0];
+                for (int q = 0; q <= it; ++q) lo = std::min(lo, hist[q]);
+                adj_orders[n] = hist[0] > 0.0 && lo > 0.0 ? std::log10(hist[0] / lo) : 0.0;
+            }
+            if (st != FAS_OK && st != FAS_NOT_CONVERGED) {
+                s->adj_tau = 0.0;
+                s->p = p0;
+                (void)set_phys(s);
+                return st;
+            }
+            launch_param_partials(d.L, d.geo, d.u, d.mut, s->ph, s->p.reynolds, s->a_dFa, s->a_dFm, e.st);
+            double la = 0.0, lm = 0.0;
+            STCHK(fine_dot(s, s->a_lam, s->a_dFa, &la));
+            STCHK(fine_dot(s, s->a_lam, s->a_dFm, &lm));
+            dJ_dalpha[n] = la + (n >= 1 ? w * h[2] : 0.0);
+            dM += lm + (n >= 1 ? w * h[3] : 0.0);
+            copy(l1, l2);
+            copy(s->a_lam, l1);
+        }
+    }
+    s->adj_tau = 0.0;
+    // the state as the forward pass left it: u^N, its time levels and clock
+    copy(fin_u, d.u);
+    copy(fin_un, d.un);
+    for (int l = 1; l < s->nlev; ++l) launch_restrict(e.lev[l - 1], e.lev[l], FLD_UN, FLD_UN, FLD_NONE, e.st);
+    if (N >= 2) {
+        copy(fin_unm1, d.unm1);
+        for (int l = 1; l < s->nlev; ++l) launch_restrict(e.lev[l - 1], e.lev[l], FLD_UNM1, FLD_UNM1, FLD_NONE, e.st);
+    }
+    e.bdf = N >= 2 ? 2 : 1;
+    e.dt = dt;
+    s->have_un = 1;
+    s->t = fin_t;
+    s->step = N;
+    launch_fill_int(e.d_cyc, 1, fin_cyc, e.st);
+    STCHK(set_alpha(alpha_deg[N]));
+    for (double *q : s->a_ck) (void)hipFree(q);
+    s->a_ck.clear();
+    HIPCHK(hipStreamSynchronize(e.st));
+    *J = Jsum;
+    *dJ_dmach = dM;
+    if (recomputed_steps) *recomputed_steps = recomputed;
+    return FAS_OK;
 }
 
 // -------------------------------------------------------------------- batch

@@ -89,6 +89,7 @@ EXPORTS = [
     "fas_batch_profile_read", "fas_forces", "fas_vjp", "fas_param_partials",
     "fas_sgs_apply_transpose", "fas_adjoint_solve", "fas_lift_gradient", "fas_vjp_nodes",
     "fas_lift_gradient_nodes", "fas_set_motion", "fas_dfa", "fas_dfa_noalloc", "fas_vjp_smooth",
+    "fas_unsteady_lift_gradient",
     "fas_set_four_lane_limit",
     "fas_last_error",
 ]
@@ -116,6 +117,7 @@ def load(path: str = LIB_PATH):
         "fas_set_state": (i32, [vp, vp, vp, vp, f64, f64, i32, i32]),
         "fas_get_time_levels": (i32, [vp, vp, vp, dp, dp, ip, ip]),
         "fas_vjp_smooth": (i32, [vp, vp, vp]),
+        "fas_unsteady_lift_gradient": (i32, [vp, i32, f64, dp, i32, f64, i32, i32, f64, dp, dp, dp, ip, dp, ip]),
         "fas_set_four_lane_limit": (ctypes.c_int64, [ctypes.c_int64]),
         "fas_get_state": (i32, [vp, vp, vp]),
         "fas_get_level": (i32, [vp, i32, vp, vp]),
@@ -420,6 +422,28 @@ class State:
                                                  hist.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
                                                  ctypes.byref(n)), allow=(FAS_NOT_CONVERGED,))
         return cl.value, g, dx, dy, hist[:n.value + 1], st
+
+    def unsteady_lift_gradient(self, dt, alpha_deg, max_inner=200, inner_drop=11.0, checkpoint_every=1,
+                               adj_max_iter=2000, adj_drop=10.0):
+        """Time-averaged lift J of len(alpha_deg) - 1 dual time steps from this
+        (converged, steady) state and its gradient by the checkpointed
+        unsteady adjoint: (J, dJ/dM, dJ/dalpha_n per degree (n = 0..N),
+        adjoint iterations per step, adjoint orders reached per step,
+        recomputed steps)."""
+        a = np.ascontiguousarray(alpha_deg, dtype=np.float64)
+        n = len(a) - 1
+        J, dm = ctypes.c_double(0.0), ctypes.c_double(0.0)
+        da = np.zeros(n + 1)
+        its = np.zeros(n + 1, dtype=np.int32)
+        orders = np.zeros(n + 1)
+        rec = ctypes.c_int32(0)
+        dp = ctypes.POINTER(ctypes.c_double)
+        _check(_lib.fas_unsteady_lift_gradient(self.h, n, dt, a.ctypes.data_as(dp), max_inner, inner_drop,
+                                               checkpoint_every, adj_max_iter, adj_drop, ctypes.byref(J),
+                                               ctypes.byref(dm), da.ctypes.data_as(dp),
+                                               its.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                                               orders.ctypes.data_as(dp), ctypes.byref(rec)))
+        return J.value, dm.value, da, its, orders, rec.value
 
     def dual_time_step(self, dt, alpha_deg, max_inner, drop_orders):
         hist = np.zeros(max_inner + 1)

@@ -13,6 +13,9 @@ converges poorly or diverges there.
   mode the benchmark uses (d = 0.5, c* = 100 after a ramp) and in the
   paper's robust mode (d = 0.5, c* = 20 for two cycles then 1e4), each set
   solved together as one batch;
+* smoothers: AW3 against AW5J, AW51 and AW52 (rate per cycle and per
+  second, cost per cycle) and preconditioned ARK3J over c* on the
+  256 x 128 case;
 * flow angle: alpha = 0, 1, 2, 4 degrees on the 256 x 128 grid, 100 steady
   V-cycles (one batch of four cases) in the benchmark mode and in the
   paper's fast mode (d = 0.05, c* = 100), and the inner iterations of the
@@ -108,8 +111,54 @@ def flow_angle(cycles=100, mach=0.8, mesh=(256, 128)):
     return out
 
 
+def smoother_comparison(cap=600, drop=6.0, park_cstars=(0.25, 0.5, 1.0, 2.0, 4.0)):
+    """The relative comparisons of Section 6 (the steady columns of the
+    tables of smoother rates and times) on the 256 x 128 workload: AW3,
+    AW5J, AW51 and AW52 at the benchmark setting (d = 0.5, eta = 0.5,
+    c* = 100 after the ramp, V-cycles), each to a 6-order drop: cycles,
+    seconds, rate per cycle and per second, and the cost of a cycle relative
+    to AW3; and preconditioned ARK3J over a range of c*, where the paper
+    finds it unstable above c* = 1."""
+    import time
+    import torch
+    import fas_inputs as fi
+    from paper_1710_04875_amd import fas
+    case = fi.steady_cgrid_case()
+    x, y = case.grid()
+    g = fas.Grid(case.topology, x, y, case.n_wake, 3)
+    u0 = torch.from_numpy(case.initial_state(x, y)).cuda()
+    out = {"workload": "steady RANS 256x128 C-grid (the benchmark case), V-cycles, 6-order drop"}
+    schemes = (("AW3", fas.FAS_AW3), ("AW5J", fas.FAS_AW5J), ("AW51", fas.FAS_AW51), ("AW52", fas.FAS_AW52))
+    for name, sc in schemes:
+        st = fas.State(g, _params(fas, case.mach, case.alpha_deg, scheme=sc), u0)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        h, s = st.cycle(cap, drop)
+        torch.cuda.synchronize()
+        t = time.perf_counter() - t0
+        n = len(h) - 1
+        r = _rate(h)
+        out[name] = {"status": int(s), "cycles": n, "seconds": round(t, 4), "ms_per_cycle": round(1e3 * t / n, 4),
+                     "rate_per_cycle": round(r, 4),
+                     "rate_per_second": float("%.4g" % (r ** (n / t))) if np.isfinite(r) else None,
+                     "orders": round(float(np.log10(h[0] / np.nanmin(h))), 2)}
+    base = out["AW3"]["ms_per_cycle"]
+    for name, _ in schemes:
+        out[name]["cycle_cost_vs_aw3"] = round(out[name]["ms_per_cycle"] / base, 3)
+    park = {}
+    for cs in park_cstars:
+        st = fas.State(g, _params(fas, case.mach, case.alpha_deg, scheme=fas.FAS_PARK3J, cfl=cs, cfl_ramp=min(cs, 1.0)),
+                       u0)
+        h, s = st.cycle(300, drop)
+        park[str(cs)] = {"status": int(s), "cycles": len(h) - 1, "rate_per_cycle": round(_rate(h), 4),
+                         "orders": round(float(np.log10(h[0] / np.nanmin(h))), 2)}
+    out["PARK3J_by_cstar"] = park
+    return out
+
+
 def main():
-    res = {"mesh_independence": mesh_independence(), "flow_angle": flow_angle()}
+    res = {"mesh_independence": mesh_independence(), "flow_angle": flow_angle(),
+           "smoother_comparison": smoother_comparison()}
     json.dump(res, sys.stdout, indent=1)
     print()
 

@@ -420,3 +420,100 @@ def test_steady_lift_raises_on_an_unconverged_adjoint():
     cl = fas.steady_lift(m, a, st, max_cycles=4000, drop_orders=11.0, adj_iter=2, adj_drop=10.0)
     with pytest.raises(fas.FasError):
         cl.backward()
+
+
+# ------------------------------------------------- unsteady adjoint
+UNS_DT = 0.1
+
+
+def _unsteady_state(mach, alpha0):
+    """16 x 8 Euler C-grid: the steady start converged by 2-level V-cycles on
+    the GPU, the physical steps on one level (as in the oracle's pin)."""
+    from paper_1710_04875_amd import fas
+    x, y = fi.cgrid(16, 8, 2)
+    kw = dict(model=0, mach=mach, alpha_deg=alpha0, cfl=10.0, cfl_ramp=5.0, n_ramp=1, ramp_growth=1.5, dt_form=0)
+    g2 = fas.Grid(fi.CGRID, x, y, 2, 2)
+    s2 = fas.State(g2, fas.Params(n_levels=2, **kw), torch.from_numpy(fi.uniform_state(16, 8, mach, alpha0)).cuda())
+    h, status = s2.cycle(3000, 13.0)
+    g1 = fas.Grid(fi.CGRID, x, y, 2, 1)
+    s1 = fas.State(g1, fas.Params(n_levels=1, **kw), s2.get_state())
+    return g1, s1
+
+
+def _uns_gradient(mach, alphas, k=1):
+    g, st = _unsteady_state(mach, alphas[0])
+    return st.unsteady_lift_gradient(UNS_DT, alphas, max_inner=1500, inner_drop=7.0, checkpoint_every=k,
+                                     adj_max_iter=3000, adj_drop=12.0)
+
+
+def test_unsteady_adjoint_matches_oracle_direct_sensitivity():
+    """The checkpointed unsteady adjoint (implicit Euler start, then BDF2)
+    against the oracle's forward sensitivities through its own run of the
+    same steps; both inner solves stop at 7 orders (the tiny grid's limit
+    cycle sits near 7.5), so the states agree to about 1e-11."""
+    from oracle.adjoint import unsteady_direct_gradient, unsteady_states
+    mach, alphas = 0.5, [1.0, 1.3, 1.6]
+    J, dm, da, its, orders, rec = _uns_gradient(mach, alphas)
+    assert (orders >= 12.0).all(), orders
+    x, y = fi.cgrid(16, 8, 2)
+    p2 = ofas.Params(model=0, mach=mach, alpha_deg=alphas[0], n_levels=2, cfl=10.0, cfl_ramp=5.0, n_ramp=1,
+                     ramp_growth=1.5, dt_form=0)
+    S = ofas.Solver(x, y, fi.CGRID, 2, p2, fi.uniform_state(16, 8, mach, alphas[0]))
+    S.run_cycles(3000, 13.0)
+    S1 = ofas.Solver(x, y, fi.CGRID, 2, ofas.Params(**{**p2.__dict__, "n_levels": 1}), S.u(0))
+    states = unsteady_states(S1, UNS_DT, alphas, 1500, 7.0)
+    Jo, dmo, dao = unsteady_direct_gradient(S1, states, UNS_DT, alphas)
+    assert abs(J - Jo) <= 1e-9 * abs(Jo)
+    assert abs(dm - dmo) <= 1e-7 * abs(dmo), (dm, dmo)
+    assert np.abs(da - dao).max() <= 1e-7 * np.abs(dao).max(), (da, dao)
+
+
+def test_unsteady_adjoint_checkpointing():
+    """Keeping every state or every second, third or fifth one (recomputing
+    the steps in between from the checkpoint before them) gives the same
+    functional (bitwise: the forward pass) and gradient.  The transposed
+    residual product scatters with floating-point atomics, so adjoint
+    solves agree to their convergence, not bitwise, from run to run (two
+    runs with every state kept are compared the same way)."""
+    alphas = [1.0, 1.2, 1.4, 1.5, 1.3]
+    ref = _uns_gradient(0.5, alphas, 1)
+    assert ref[5] == 0
+    for k, recomputed in ((1, 0), (2, 2), (3, 3), (5, 4)):
+        out = _uns_gradient(0.5, alphas, k)
+        assert out[5] == recomputed, (k, out[5])
+        assert out[0] == ref[0], k
+        assert abs(out[1] - ref[1]) <= 1e-10 * abs(ref[1]), k
+        assert np.abs(out[2] - ref[2]).max() <= 1e-10 * np.abs(ref[2]).max(), k
+
+
+def test_unsteady_adjoint_matches_central_differences():
+    """dJ/dM (through the steady start and every step) and dJ/dalpha_1
+    against central differences of whole GPU runs."""
+    mach, alphas = 0.5, [1.0, 1.3, 1.6]
+    J, dm, da, _, _, _ = _uns_gradient(mach, alphas)
+
+    def J_of(m, al):
+        g, st = _unsteady_state(m, al[0])
+        cls = []
+        for n in range(1, len(al)):
+            st.dual_time_step(UNS_DT, al[n], 1500, 7.0)
+            cls.append(st.forces()[0])
+        return float(np.mean(cls))
+
+    assert abs(J_of(mach, alphas) - J) <= 1e-12 * abs(J)
+    h = 1e-5
+    fd_m = (J_of(mach + h, alphas) - J_of(mach - h, alphas)) / (2 * h)
+    assert abs(dm - fd_m) <= 1e-4 * abs(fd_m), (dm, fd_m)
+    ha = 1e-3
+    fd_a = (J_of(mach, [1.0, 1.3 + ha, 1.6]) - J_of(mach, [1.0, 1.3 - ha, 1.6])) / (2 * ha)
+    assert abs(da[1] - fd_a) <= 1e-4 * abs(fd_a), (da[1], fd_a)
+
+
+def test_unsteady_adjoint_rejects_bad_input():
+    from paper_1710_04875_amd import fas
+    g, st = _unsteady_state(0.5, 1.0)
+    with pytest.raises(fas.FasError):
+        st.unsteady_lift_gradient(0.0, [1.0, 1.2])
+    st.dual_time_step(UNS_DT, 1.1, 10, 0.0)
+    with pytest.raises(fas.FasError):        # not a steady state any more
+        st.unsteady_lift_gradient(UNS_DT, [1.0, 1.2])

@@ -209,17 +209,22 @@ def test_autotuned_configuration_covers_the_tallest_grid():
         assert rows >= max(nj for _, nj, _, _, _ in CASES) >> level
 
 
-def test_batched_case_matches_oracle_after_one_cycle():
+@pytest.mark.parametrize("cases,which", [(CASES, 1), (CASES[:2] + [(512, 256, 64, 0.7, 1.1)], 2)],
+                         ids=["96x48", "512x256"])
+def test_batched_case_matches_oracle_after_one_cycle(cases, which):
+    """A case of a batch against the oracle after one V-cycle, every level,
+    at the 1e-12 bar (the batch's largest grid size among them)."""
     from oracle import fas as ofas
-    us, _, _, _ = _run_batch(cycles=1)
-    ni, nj, nw, m, a = CASES[1]
+    us, _, _, _ = _run_batch(cycles=1, cases=cases)
+    ni, nj, nw, m, a = cases[which]
     x, y = fi.cgrid(ni, nj, nw)
     p = _params(m, a)
     op = ofas.Params(model=1, scheme=0, mach=m, alpha_deg=a, n_levels=3, cycle_gamma=1, nu1=1,
-                     eta=0.5, d_cut=0.5, cfl=50.0, cfl_ramp=5.0, n_ramp=1, ramp_growth=1.5)
-    S = ofas.Solver(x, y, fi.CGRID, nw, op, _u0(ni, nj, m, a, 21))
+                     eta=0.5, d_cut=0.5, cfl=50.0, cfl_ramp=5.0, n_ramp=1, ramp_growth=1.5,
+                     viscous_blocks=p.viscous_blocks, dt_form=p.dt_form)
+    S = ofas.Solver(x, y, fi.CGRID, nw, op, _u0(ni, nj, m, a, 20 + which))
     S.cycle(0)
-    assert state_err(us[1], S.u()) < 10 * TOL_STATE
+    assert state_err(us[which], S.u()) < TOL_STATE
     assert p.n_levels == 3
 
 
