@@ -213,7 +213,7 @@ def sweep_source_hash():
     a = k.index("// ------------------------------------------------------------- SGS sweeps")
     b = k.index("// ------------------------------------------------------------ transfers")
     c = k.index("// Sweep configurations:")
-    d = k.index("#undef FAS_SGS1", c)
+    d = k.index("void launch_sgs(", c)
     h = hashlib.sha256()
     with open(os.path.join(csrc, "fas_internal.h"), "rb") as f:
         h.update(f.read())
@@ -663,6 +663,41 @@ def cpu_baseline(seconds_target=12.0):
                       % (cores, min(r[0] for r in res), max(r[0] for r in res), seconds_target)}
 
 
+def kernels_only(fas, torch, which, cycles):
+    """A few cycles of one workload and nothing else, for profiler runs
+    (every dispatch is traced or counted): 'c2' / 'c2-fp32' is the 256 x 128
+    RANS throughput case, 'batch' / 'batch-fp32' the 64-case batch with the
+    default sweep configurations (no autotuning).  Cycles are launched
+    directly, not from a captured graph."""
+    if which.startswith("c2"):
+        case, p = workload_params(fas, which.endswith("fp32"))
+        x, y = case.grid()
+        g = fas.Grid(case.topology, x, y, case.n_wake, p.n_levels)
+        st = fas.State(g, p, torch.from_numpy(case.initial_state(x, y)).cuda())
+        st.cycle(1)
+        torch.cuda.synchronize()
+        log("%s: %d cycles" % (which, cycles))
+        st.profile(True)                 # per-launch events: keeps the cycles out of the graph
+        st.cycle(cycles)
+        st.profile(False)
+    else:
+        import fas_inputs as fi
+        fp32 = which.endswith("fp32")
+        cases = fi.batch_cases(64, seed=4)
+        sts = []
+        for c in cases:
+            x, y = c.grid()
+            sts.append(fas.State(fas.Grid(c.topology, x, y, c.n_wake, 3), batch_params(fas, c, fp32),
+                                 torch.from_numpy(c.initial_state(x, y)).cuda()))
+        b = fas.Batch(sts, autotune=False)
+        b.solve(1, 0.0, False)
+        torch.cuda.synchronize()
+        log("%s: %d cycles" % (which, cycles))
+        b.solve(cycles, 0.0, False)
+    torch.cuda.synchronize()
+    print(json.dumps({"kernels_only": which, "cycles": cycles}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -688,6 +723,8 @@ def main():
     ap.add_argument("--primal-cap", type=int, default=1000)
     ap.add_argument("--adjoint-cap", type=int, default=200)
     ap.add_argument("--dfa-only", action="store_true", help="run only the Fourier analysis section")
+    ap.add_argument("--kernels-only", choices=("c2", "c2-fp32", "batch", "batch-fp32"),
+                    help="run only a few cycles of one workload (for rocprofv3 counter runs)")
     ap.add_argument("--traffic-summary", nargs=4, metavar=("FETCH_DIR", "WRITE_DIR", "CALF_DIR", "CALW_DIR"),
                     help="summarise four rocprofv3 --pmc output folders into the sweep's traffic record")
     args = ap.parse_args()
@@ -699,7 +736,7 @@ def main():
               "(--gpus %d requested)" % args.gpus, file=sys.stderr)
         sys.exit(2)
     cpu = None
-    if not (args.no_cpu or args.calibrate_copy or args.dfa_only or args.adjoint_only):
+    if not (args.no_cpu or args.calibrate_copy or args.dfa_only or args.adjoint_only or args.kernels_only):
         log("cpu baseline (oracle, every host core, before the GPU is used)")
         cpu = cpu_baseline()
     import numpy as np
@@ -717,6 +754,9 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     if args.dfa_only:
         print(json.dumps({"dfa": dfa_section(fas, torch)}), flush=True)
+        return
+    if args.kernels_only:
+        kernels_only(fas, torch, args.kernels_only, args.steps)
         return
     if args.adjoint_only:
         print(json.dumps({"adjoint_1024x256": adjoint_section(fas, torch, args.primal_cap, args.adjoint_cap)}),

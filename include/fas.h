@@ -283,7 +283,7 @@ fas_status fas_batch_solve(fas_batch b, int32_t max_cycles, double drop_orders, 
  * per case), and a manual override (cfg -1: pick by grid height; FAS_EINVAL
  * if the configuration covers fewer rows than the level's tallest grid).
  * Configurations 0 .. fas_sweep_config_count() - 1: one workgroup per case
- * (four threads per row, or one thread per row), or row bands of one
+ * (four or eight threads per row, or one thread per row), or row bands of one
  * workgroup each, several per case, handing the band-boundary rows on
  * through device memory (the forward and backward sweeps of Section 4.4 keep
  * their exact order).  A banded configuration whose workgroups cannot all
@@ -292,7 +292,9 @@ fas_status fas_batch_sweep_config(fas_batch b, int32_t level, int32_t *cfg, int3
 fas_status fas_batch_set_sweep_config(fas_batch b, int32_t level, int32_t cfg);
 int32_t fas_sweep_config_count(void);
 /* Configuration cfg: kind (0: four threads per row, one workgroup per
- * case; 1: one thread per row; 2: row bands), threads per workgroup, rows
+ * case; 1: one thread per row; 2: row bands of four-thread rows; 3: eight
+ * threads per row, one workgroup per case; 4: row bands of eight-thread
+ * rows), threads per workgroup, rows
  * per workgroup, prefetch depth (hyperplanes per batch) for FP64 and FP32
  * blocks.  Errors: FAS_EINVAL. */
 fas_status fas_sweep_config_info(int32_t cfg, int32_t *kind, int32_t *threads, int32_t *rows_per_workgroup,

@@ -477,8 +477,9 @@ __device__ void make_ctx(Ctx &c, const Lay &L, const double *geo, const double *
 // f^v.
 __global__ __launch_bounds__(TPB) void k_vjp(Lay L, const double *geo, const double *u, const double *mut,
                                              Phys ph, const double *lam, double *out, int part) {
+    const BlockXY cb = xcd_block();
     int s, i, j;
-    if (!interior_cell(L, blockIdx.x * blockDim.x + threadIdx.x, s, i, j)) return;
+    if (!interior_cell(L, cb.x * blockDim.x + threadIdx.x, s, i, j)) return;
     const int NS = L.NS;
     double lc[4];
 #pragma unroll
@@ -524,8 +525,9 @@ constexpr int MAX_GSEEDS = 96;
 
 __global__ __launch_bounds__(TPB) void k_vjp_geo(Lay L, const double *geo, const double *u, const double *mut,
                                                  Phys ph, const double *lam, double *gbar) {
+    const BlockXY cb = xcd_block();
     int s, i, j;
-    if (!interior_cell(L, blockIdx.x * blockDim.x + threadIdx.x, s, i, j)) return;
+    if (!interior_cell(L, cb.x * blockDim.x + threadIdx.x, s, i, j)) return;
     const int NS = L.NS;
     double lc[4];
 #pragma unroll
@@ -721,8 +723,9 @@ __global__ __launch_bounds__(TPB) void k_geo_nodes(Lay L, const double *xn, cons
 __global__ __launch_bounds__(TPB) void k_param_partials(Lay L, const double *geo, const double *u,
                                                         const double *mut, Phys ph, double reynolds,
                                                         double *dFa, double *dFm) {
+    const BlockXY cb = xcd_block();
     int s, i, j;
-    if (!interior_cell(L, blockIdx.x * blockDim.x + threadIdx.x, s, i, j)) return;
+    if (!interior_cell(L, cb.x * blockDim.x + threadIdx.x, s, i, j)) return;
     const int NS = L.NS;
     Ctx c;
     make_ctx(c, L, geo, u, mut, ph);

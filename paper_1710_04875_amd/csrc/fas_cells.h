@@ -43,6 +43,34 @@ __device__ inline bool rect_cell(const Lay &L, int t, int ri, int rj, int o, int
     s = L.slot(i, j);
     return true;
 }
+// Workgroups of a launch go to the eight XCDs in turn by linear number, and
+// each XCD has its own L2.  For a launch over one grid (gridDim.y == 1)
+// xcd_block renumbers the workgroups so that each XCD takes runs of
+// consecutive ones instead: cells of neighbouring hyperplanes, whose
+// stencils share states and metrics, then meet in one L2 rather than being
+// fetched once per XCD.  Complete rounds of eight runs are permuted and the
+// remaining workgroups keep their numbers; the map is a bijection, so it
+// changes which workgroup computes a cell and nothing else.  Batched
+// launches (one grid row per case, padded to the largest case) keep the
+// hardware's order: there the real work sits at the start of every row, and
+// runs would hand it to a few XCDs (measured: fewer HBM bytes, longer
+// launches).
+constexpr unsigned XCD_COUNT = 8, XCD_RUN_MAX = 64;
+struct BlockXY {
+    int x, y;
+};
+__device__ inline BlockXY xcd_block() {
+    const unsigned gx = gridDim.x, G = gx * gridDim.y;
+    const unsigned w = blockIdx.x + blockIdx.y * gx;
+    const unsigned run = gridDim.y == 1 ? min(XCD_RUN_MAX, G / XCD_COUNT) : 0;
+    unsigned v = w;
+    if (run > 0 && w < G / (XCD_COUNT * run) * (XCD_COUNT * run)) {
+        const unsigned x = w % XCD_COUNT, k = w / XCD_COUNT;
+        v = ((k / run) * XCD_COUNT + x) * run + k % run;
+    }
+    return {(int)(v % gx), (int)(v / gx)};
+}
+
 // interior cells: 0 <= i < ni, 0 <= j < nj
 __device__ inline bool interior_cell(const Lay &L, int t, int &s, int &i, int &j) {
     return rect_cell(L, t, L.ni, L.nj, 0, s, i, j);

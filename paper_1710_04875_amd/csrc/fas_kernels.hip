@@ -10,6 +10,7 @@
 
 #include <cmath>
 #include <type_traits>
+#include <utility>
 
 namespace fas {
 
@@ -406,11 +407,12 @@ __device__ double jrow_mut(const Lay &L, const double *mut, int i, int j) {
 }
 
 __global__ void k_mut_ghosts(BK b) {
+    const BlockXY cb = xcd_block();
     LevelDev d;
-    if (!take(b, blockIdx.y, d)) return;
+    if (!take(b, cb.y, d)) return;
     const Lay L = d.L;
     double *mut = d.mut;
-    int s = blockIdx.x * blockDim.x + threadIdx.x;
+    int s = cb.x * blockDim.x + threadIdx.x;
     int i, j;
     if (!decode(L, s, i, j) || interior(L, i, j)) return;
     double v;
@@ -465,12 +467,13 @@ __device__ inline void cell_quantities(const Phys &ph, const double *geo, int NS
 // ghost states and cell quantities in one pass: a ghost cell's quantities
 // need only its own (just computed) state
 __global__ void k_ghost_cq(BK b, int noslip, int rans) {
+    const BlockXY cb = xcd_block();
     LevelDev d;
-    if (!take(b, blockIdx.y, d)) return;
+    if (!take(b, cb.y, d)) return;
     const Lay L = d.L;
-    const Phys ph = b.PH[blockIdx.y];
+    const Phys ph = b.PH[cb.y];
     int s, i, j;   // every padded cell, -NG <= i < ni + NG, -NG <= j < nj + NG
-    if (!rect_cell(L, blockIdx.x * blockDim.x + threadIdx.x, L.NI, L.NJ, NG, s, i, j)) return;
+    if (!rect_cell(L, cb.x * blockDim.x + threadIdx.x, L.NI, L.NJ, NG, s, i, j)) return;
     const int NS = L.NS;
     double U[4];
     if (interior(L, i, j)) {
@@ -513,13 +516,14 @@ __device__ inline double local_dt(const Phys &ph, double cfl, const double *geo,
 // Section 2: velocity and temperature gradients at vertices, Green-Gauss
 // over the quadrilateral of the four surrounding cell centres.
 __global__ void k_vertex_gradients(BK b) {
+    const BlockXY cb = xcd_block();
     LevelDev d;
-    if (!take(b, blockIdx.y, d)) return;
+    if (!take(b, cb.y, d)) return;
     const Lay L = d.L;
     const double *geo = d.geo, *u = d.u, *cq = d.cq;
     double *vg = d.vg;
     int s, i, j;   // every vertex, 0 <= i <= ni, 0 <= j <= nj
-    if (!rect_cell(L, blockIdx.x * blockDim.x + threadIdx.x, L.ni + 1, L.nj + 1, 0, s, i, j)) return;
+    if (!rect_cell(L, cb.x * blockDim.x + threadIdx.x, L.ni + 1, L.nj + 1, 0, s, i, j)) return;
     const int NS = L.NS, NJ = L.NJ;
     const int c[4] = {s - (2 * NJ + 1), s - (NJ + 1), s, s - NJ};   // SW, SE, NE, NW
     double X[4], Y[4], U[4], V[4], T[4];
@@ -800,13 +804,14 @@ __device__ inline void residual_cell(const LevelDev &d, const ResArgs &a, int NS
 
 template <typename BT>
 __global__ __launch_bounds__(TPB) void k_residual(BK b, ResArgs a) {
+    const BlockXY cb = xcd_block();
     LevelDev d;
-    if (!take(b, blockIdx.y, d)) return;
+    if (!take(b, cb.y, d)) return;
     const Lay L = d.L;
     const double *geo = d.geo, *u = d.u, *cq = d.cq, *vg = d.vg, *mut = d.mut;
-    const Phys ph = b.PH[blockIdx.y];
+    const Phys ph = b.PH[cb.y];
     int s, i, j;
-    if (!interior_cell(L, blockIdx.x * blockDim.x + threadIdx.x, s, i, j)) return;
+    if (!interior_cell(L, cb.x * blockDim.x + threadIdx.x, s, i, j)) return;
     const int NS = L.NS, NJ = L.NJ;
     FaceOut w, e, so, n;
     face_flux(L, geo, u, cq, vg, mut, ph, a, s - NJ, s, NJ, geo[G_SXI_X * NS + s],
@@ -838,11 +843,12 @@ __global__ __launch_bounds__(TPB) void k_residual(BK b, ResArgs a) {
 // nothing, so every lane takes part in the shuffles.
 template <typename BT>
 __global__ __launch_bounds__(TPB) void k_residual_q(BK b, ResArgs a) {
+    const BlockXY cb = xcd_block();
     LevelDev d;
-    if (!take(b, blockIdx.y, d)) return;
+    if (!take(b, cb.y, d)) return;
     const Lay L = d.L;
-    const Phys ph = b.PH[blockIdx.y];
-    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    const Phys ph = b.PH[cb.y];
+    const int t = cb.x * blockDim.x + threadIdx.x;
     const int q = t & 3;
     int s, i, j;
     const bool valid = interior_cell(L, t >> 2, s, i, j);
@@ -972,17 +978,18 @@ __device__ void face_blocks(const Lay &L, const double *geo, const double *u, co
 
 template <typename BT>
 __global__ __launch_bounds__(TPB) void k_blocks(BK b, int aw, double tau, int viscous, int copy_u0) {
+    const BlockXY cb = xcd_block();
     LevelDev dv;
-    if (!take(b, blockIdx.y, dv)) return;
+    if (!take(b, cb.y, dv)) return;
     const Lay L = dv.L;
     const double *geo = dv.geo, *u = dv.u, *cq = dv.cq, *mut = dv.mut;
     BT *blk = (BT *)dv.blk;
-    const Phys ph = b.PH[blockIdx.y];
+    const Phys ph = b.PH[cb.y];
     int s, i, j;
-    if (!interior_cell(L, blockIdx.x * blockDim.x + threadIdx.x, s, i, j)) return;
+    if (!interior_cell(L, cb.x * blockDim.x + threadIdx.x, s, i, j)) return;
     const int NS = L.NS, NJ = L.NJ;
     // the iteration's frozen dt* (read by the stages' residuals and sweeps)
-    const double dt_s = local_dt(ph, cfl_of(ph, b.cyc[blockIdx.y]), geo, u, NS, s);
+    const double dt_s = local_dt(ph, cfl_of(ph, b.cyc[cb.y]), geo, u, NS, s);
     dv.dts[s] = dt_s;
     if (copy_u0) {
 #pragma unroll
@@ -1092,19 +1099,20 @@ __global__ __launch_bounds__(TPB) void k_blocks(BK b, int aw, double tau, int vi
 // the last cell redo cell 0 and store nothing.
 template <typename BT>
 __global__ __launch_bounds__(TPB) void k_blocks_q(BK b, int aw, double tau, int viscous, int copy_u0) {
+    const BlockXY cb = xcd_block();
     LevelDev dv;
-    if (!take(b, blockIdx.y, dv)) return;
+    if (!take(b, cb.y, dv)) return;
     const Lay L = dv.L;
     const double *geo = dv.geo, *u = dv.u, *cq = dv.cq, *mut = dv.mut;
     BT *blk = (BT *)dv.blk;
-    const Phys ph = b.PH[blockIdx.y];
-    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    const Phys ph = b.PH[cb.y];
+    const int t = cb.x * blockDim.x + threadIdx.x;
     const int q = t & 3;
     int s, i, j;
     const bool valid = interior_cell(L, t >> 2, s, i, j);
     if (!valid) interior_cell(L, 0, s, i, j);
     const int NS = L.NS, NJ = L.NJ;
-    const double dt_s = local_dt(ph, cfl_of(ph, b.cyc[blockIdx.y]), geo, u, NS, s);
+    const double dt_s = local_dt(ph, cfl_of(ph, b.cyc[cb.y]), geo, u, NS, s);
     if (valid && q == 0) {
         dv.dts[s] = dt_s;
         if (copy_u0) {
@@ -1320,13 +1328,14 @@ __global__ __launch_bounds__(BS) void k_sgs(BK bk, SweepArgs a) {
 
 template <typename BT>
 __global__ void k_dinv(BK b) {
+    const BlockXY cb = xcd_block();
     LevelDev d;
-    if (!take(b, blockIdx.y, d)) return;
+    if (!take(b, cb.y, d)) return;
     const Lay L = d.L;
     const BT *blk = (const BT *)d.blk;
     const double *r = d.F;
     BT *g = (BT *)d.g;
-    int s = blockIdx.x * blockDim.x + threadIdx.x;
+    int s = cb.x * blockDim.x + threadIdx.x;
     int i, j;
     if (!decode(L, s, i, j) || !interior(L, i, j)) return;
     const int NS = L.NS;
@@ -1510,7 +1519,7 @@ __global__ __launch_bounds__(NT) void k_sgs4(BK bk, SweepArgs a) {
     constexpr int NR = NT / 4 * R;            // rows handled by the workgroup
     constexpr int XS = 4 * NR + 8;            // guard row at both ends
     __shared__ __attribute__((aligned(16))) T xb[2][XS];
-    __shared__ T sink[BANDED ? NT : 1];       // guard-row writes of lanes without the consumer role
+    __shared__ T sink[NT];                    // guard-row and wake-row writes of lanes without that role
     extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
     LevelDev dv;
     const int nbands = BANDED ? a.bands : 1;
@@ -1625,8 +1634,13 @@ __global__ __launch_bounds__(NT) void k_sgs4(BK bk, SweepArgs a) {
             for (int q = 0; q < R; ++q) {
                 const int jj = jq[q] - j0;                          // row within the band
                 const T *xs = prev + 4 * jj;                        // row below (guard row for jj = 0)
-                if (WAKE && h >= ni - nw && h < ni) {               // row 0 at i = h: wake-cut partner
-                    if (jq[q] == 0) xs = row0 + (ni - 1 - h) * 4;
+                // Wake-cut code is branch-free: lane- and step-dependent
+                // choices are selects (a branch here costs the compiler its
+                // count of the prefetch loads in flight, and every later step
+                // of the batch then waits for them).
+                if constexpr (WAKE) {                               // row 0 at i = h: wake-cut partner
+                    const bool part = jq[q] == 0 && h >= ni - nw && h < ni;
+                    xs = part ? row0 + (ni - 1 - h) * 4 : xs;
                 }
                 T xw[4], xsv[4];
                 LdsRow<T>::get(prev + 4 * jj + 4, xw);
@@ -1634,8 +1648,9 @@ __global__ __launch_bounds__(NT) void k_sgs4(BK bk, SweepArgs a) {
                 const T v = (gv[q] - dot4r(wv[q], xw)) - dot4r(sv[q], xsv);
                 cur[4 * jj + 4 + r] = v;
                 BufIO<T>::st(ry, cell(h, q) ? hv * (unsigned)sizeof(T) + ov[q] : OOB, v);
-                if (WAKE && h < nw) {
-                    if (jq[q] == 0) row0[h * 4 + r] = v;
+                if constexpr (WAKE) {
+                    const bool keep = jq[q] == 0 && h < nw;
+                    *(keep ? row0 + h * 4 + r : &sink[t]) = v;
                 }
                 // one store: the last row's value (producer lanes) and the
                 // sentinel back into the slot just consumed (consumer lanes)
@@ -1710,8 +1725,8 @@ __global__ __launch_bounds__(NT) void k_sgs4(BK bk, SweepArgs a) {
         T *const gd[2] = {cons ? &xb[0][4 * NR + 4 + r] : &sink[t], cons ? &xb[1][4 * NR + 4 + r] : &sink[t]};
         // step sl of a batch: buffers alternate with the step
         auto step = [&](auto wake, const T (&yv)[R], const T (&ev)[R][4], const T (&nv)[R][4],
-                        const double (&u0v)[R], const double (&dtv)[R], int sl, int h) {
-            constexpr bool WAKE = decltype(wake)::value;
+                        const double (&u0v)[R], const double (&dtv)[R], const T (&wz)[R], int sl, int h) {
+            constexpr int WK = decltype(wake)::value;
             const T *prev = xb[(sl + 1) & 1];
             T *cur = xb[sl & 1];
             const unsigned hv = (unsigned)((h + 2 * NG) * NJ);
@@ -1727,8 +1742,10 @@ __global__ __launch_bounds__(NT) void k_sgs4(BK bk, SweepArgs a) {
                 LdsRow<T>::get(prev + 4 * jj + 4, xe);
                 LdsRow<T>::get(prev + 4 * jj + 8, xn);
                 T v = (yv[q] - dot4r(ev[q], xe)) - dot4r(nv[q], xn);
-                if (WAKE && h >= 0 && h < nw) {                    // row 0 at i = h: wake-cut partner
-                    if (jq[q] == 0) {
+                if constexpr (WK == 1) {                           // row 0 at i = h: wake-cut partner
+                    v = jq[q] == 0 && h >= 0 && h < nw ? v - wz[q] : v;
+                } else if constexpr (WK == 2) {
+                    if (h >= 0 && h < nw && jq[q] == 0) {
                         T mp[4];
 #pragma unroll
                         for (int c = 0; c < 4; ++c) mp[c] = pblk[h * 16 + r * 4 + c];
@@ -1737,8 +1754,9 @@ __global__ __launch_bounds__(NT) void k_sgs4(BK bk, SweepArgs a) {
                 }
                 const bool valid = cell(h, q);
                 cur[4 * jj + 4 + r] = v;
-                if (WAKE && h >= ni - nw && h < ni) {
-                    if (jq[q] == 0) row0[(h - (ni - nw)) * 4 + r] = v;
+                if constexpr (WK != 0) {
+                    const bool keep = jq[q] == 0 && h >= ni - nw && h < ni;
+                    *(keep ? row0 + (h - (ni - nw)) * 4 + r : &sink[t]) = v;
                 }
                 if constexpr (BANDED)
                     if (q == 0)
@@ -1751,6 +1769,328 @@ __global__ __launch_bounds__(NT) void k_sgs4(BK bk, SweepArgs a) {
                     else un = u0v[q] - a.alpha * (dtv[q] * (double)v);
                     bst_d(ruu, oe, un);
                 }
+            }
+            step_sync<NT>();
+        };
+        if constexpr (BANDED) {
+#pragma unroll
+            for (int k = 0; k < P; ++k) ring[k] = Sent<T>::ld(rh, hplane(H - 1 - k) + hl);
+        }
+        // Partner terms of the row-0 wake cells of the D hyperplanes from
+        // backward position hb on (hyperplanes H - 1 - hb downwards), formed
+        // before the steps when every partner (hyperplane ni - 1 - h, at least
+        // ni - nw) lies above them, i.e. was swept in an earlier batch: the
+        // step then subtracts a register instead of waiting on two LDS reads
+        // and four products on its chain (the same operations in the same
+        // order, so the same value).
+        // (variant 1; clamped addresses, so that no lane branches)
+        auto wake_terms = [&](auto wake, T (&wz)[D][R], int hb) {
+            constexpr int WK = decltype(wake)::value;
+#pragma unroll
+            for (int k = 0; k < D; ++k) {
+                const int h = H - 1 - (hb + k);
+                const bool in = h >= 0 && h < nw;
+                const int hw = in ? h : 0;
+#pragma unroll
+                for (int q = 0; q < R; ++q) {
+                    T z = (T)0;
+                    if constexpr (WK == 1) {
+                        T mp[4];
+#pragma unroll
+                        for (int c = 0; c < 4; ++c) mp[c] = pblk[hw * 16 + r * 4 + c];
+                        z = dot4(mp, row0 + (in ? nw - 1 - h : 0) * 4);
+                    }
+                    wz[k][q] = z;
+                }
+            }
+        };
+        T wz[D][R];
+        auto batch = [&](auto wake, int h0) {
+            load(yB, eB, nB, uB, tB, h0 + D);
+            wake_terms(wake, wz, h0);
+#pragma unroll
+            for (int k = 0; k < D; ++k)
+                if (BANDED || h0 + k < H) step(wake, yA[k], eA[k], nA[k], uA[k], tA[k], wz[k], k, H - 1 - (h0 + k));
+            load(yA, eA, nA, uA, tA, h0 + 2 * D);
+            wake_terms(wake, wz, h0 + D);
+#pragma unroll
+            for (int k = 0; k < D; ++k)
+                if (BANDED || h0 + D + k < H)
+                    step(wake, yB[k], eB[k], nB[k], uB[k], tB[k], wz[k], D + k, H - 1 - (h0 + D + k));
+        };
+        load(yA, eA, nA, uA, tA, 0);
+        __syncthreads();
+        for (int h0 = 0; h0 < H; h0 += 2 * D) {
+            // the batch's hyperplanes H - 1 - h0 down to H - 2D - h0
+            const int hhi = H - 1 - h0, hlo = H - 2 * D - h0;
+            const bool plain = !cutg || hlo >= ni || hhi < 0 || (hlo >= nw && hhi < ni - nw);
+            // variant 1 when every wake partner of the batch (hyperplanes from
+            // ni - nw up) was swept in an earlier batch
+            if (plain) batch(std::integral_constant<int, 0>(), h0);
+            else if (ni - nw > hhi) batch(std::integral_constant<int, 1>(), h0);
+            else batch(std::integral_constant<int, 2>(), h0);
+        }
+    }
+}
+
+// Eight threads per cell row (k_sgs8): thread t = 8 g + 2 rr + hf of the
+// band's row g computes block row rr over the columns 2 hf and 2 hf + 1 of
+// each block: its half of the product, fma(m1, x1, m0 x0) or
+// fma(m3, x3, m2 x2), is exactly one of the two halves k_sgs4 adds, and the
+// lanes t and t ^ 1 exchange their halves with one DPP swap and add them in
+// either order (a + b = b + a exactly), so both lanes hold the row's value
+// bitwise as k_sgs4 forms it.  A lane's memory per hyperplane is one value
+// and one 16-byte (FP32: 8-byte) half row of each block, half of what a
+// four-thread lane moves, and its instruction stream per step is about half
+// as long; the band's rows are spread over NW waves of eight rows, which
+// meet at an LDS barrier after every step.  Layout, prefetch batches,
+// out-of-range offsets for absent cells, the hand-off between row bands
+// and the wake-cut coupling are those of k_sgs4.
+template <typename T> struct Half;
+template <> struct Half<double> {
+    // the two values of a half row: one 16-byte load
+    __device__ static void ld(Res r, unsigned off, int plane, double (&o)[2]) {
+        const double2 a = __builtin_bit_cast(double2, __builtin_amdgcn_raw_buffer_load_b128(r, off, plane, 0));
+        o[0] = a.x;
+        o[1] = a.y;
+    }
+    __device__ static void lds(const double *p, double (&o)[2]) {
+        const double2 a = *reinterpret_cast<const double2 *>(p);
+        o[0] = a.x;
+        o[1] = a.y;
+    }
+    // the partner lane's value (lanes t and t ^ 1: quad permutation 1 0 3 2)
+    __device__ static double swap(double x) {
+        const U32x2 v = __builtin_bit_cast(U32x2, x);
+        U32x2 o;
+        o.x = (unsigned)__builtin_amdgcn_mov_dpp((int)v.x, 0xB1, 0xF, 0xF, false);
+        o.y = (unsigned)__builtin_amdgcn_mov_dpp((int)v.y, 0xB1, 0xF, 0xF, false);
+        return __builtin_bit_cast(double, o);
+    }
+};
+template <> struct Half<float> {
+    __device__ static void ld(Res r, unsigned off, int plane, float (&o)[2]) {
+        // the whole result is bit-cast to a full-width type: element access
+        // on the builtin's own vector type reads element 0 twice here
+        const float2 a = __builtin_bit_cast(float2, __builtin_amdgcn_raw_buffer_load_b64(r, off, plane, 0));
+        o[0] = a.x;
+        o[1] = a.y;
+    }
+    __device__ static void lds(const float *p, float (&o)[2]) {
+        const float2 a = *reinterpret_cast<const float2 *>(p);
+        o[0] = a.x;
+        o[1] = a.y;
+    }
+    __device__ static float swap(float x) {
+        return __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, x), 0xB1, 0xF, 0xF, false));
+    }
+};
+
+template <typename T>
+__device__ inline T half_dot(const T (&m)[2], const T (&x)[2]) {
+    return fma(m[1], x[1], m[0] * x[0]);
+}
+
+template <typename T, int NW, int D, bool BANDED>
+__global__ __launch_bounds__(64 * NW) void k_sgs8(BK bk, SweepArgs a) {
+    constexpr int NT = 64 * NW;
+    constexpr int NR = 8 * NW;                // rows handled by the workgroup
+    constexpr int XS = 4 * NR + 8;            // guard row at both ends
+    __shared__ __attribute__((aligned(16))) T xb[2][XS];
+    __shared__ T sink[NT];                    // guard-row and wake-row writes of lanes without that role
+    extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
+    LevelDev dv;
+    const int nbands = BANDED ? a.bands : 1;
+    const int band = BANDED ? (int)blockIdx.x % nbands : 0;
+    if (!take(bk, BANDED ? (int)blockIdx.x / nbands : (int)blockIdx.x, dv)) return;
+    const Lay L = dv.L;
+    const int ni = L.ni, nj = L.nj, NS = L.NS, NJ = L.NJ, nw = L.nw;
+    const int j0 = band * NR;
+    if (BANDED && j0 >= nj) return;
+    const bool below = BANDED && band > 0;
+    const bool above = BANDED && j0 + NR < nj;
+    const T *blk = (const T *)dv.blk;
+    T *row0 = reinterpret_cast<T *>(smem);                 // n_wake x 4
+    T *pblk = row0 + (L.nw > 0 ? L.nw : 1) * 4;           // n_wake x 16: slot-2 blocks of (i, 0), i < n_wake
+    const int t = threadIdx.x, grp = t >> 3, rr = (t >> 1) & 3, hf = t & 1;
+    const bool cutg = L.topo == 1 && j0 == 0;
+    const int H = ni + nj - 1;
+    for (int q = t; q < XS; q += NT) {
+        xb[0][q] = (T)0;
+        xb[1][q] = (T)0;
+    }
+    if (cutg) {
+        for (int q = t; q < nw * 16; q += NT) {
+            const int ii = q >> 4, e = q & 15;
+            pblk[q] = blk[BL<T>::at(B_M0 + 2, NS, L.slot(ii, 0), e >> 2, e & 3)];
+        }
+    }
+    const size_t bstride = (size_t)NS * 16;
+    const int rec = sizeof(T) == 8 ? 8 : 16;               // values per cell in a plane
+    const Res rb = mkres(blk, (size_t)BLK_NBLOCKS * bstride * sizeof(T));
+    auto poff = [&](int b) { return (int)((size_t)b * bstride * sizeof(T)); };
+    const size_t vbytes = (size_t)4 * NS * sizeof(T), dbytes = (size_t)4 * NS * sizeof(double);
+    const Res rh = mkres(BANDED ? dv.bnd : dv.y, BANDED ? bnd_count(L) * sizeof(T) : 0);
+    // per-lane byte offsets at slot base 0 (a hyperplane adds (h + 4) NJ slots);
+    // the half row of block 0 at this lane's row, row rr and columns 2 hf ..
+    const int jq = j0 + grp;
+    const int jx = jq < nj ? jq : jq + (1 << 30);          // rows above the grid never have a cell
+    const int jr = jq < nj ? jq : 0;
+    const unsigned ov = (unsigned)((rr * NS + jr + NG) * sizeof(T));
+    const unsigned ob = (unsigned)(BL<T>::at(0, NS, jr + NG, rr, 2 * hf) * sizeof(T));
+    const unsigned od = (unsigned)((rr * NS + jr + NG) * sizeof(double));
+    const bool lead = hf == 0;                             // the lane of the pair that stores
+    auto cell = [&](int h) { return (unsigned)(h - jx) < (unsigned)ni; };
+    const bool first = grp == 0, last = grp == NR - 1;
+    const int HB = bnd_hb(L);
+    auto hrow = [&](bool on, int j) { return on ? (unsigned)((rr * HB * NJ + j) * sizeof(T)) : OOB; };
+    auto hplane = [&](int h) { return (unsigned)((h + BND_HOFF) * NJ * sizeof(T)); };
+    unsigned budget = BND_SPIN_BUDGET;
+    constexpr int NRING = BANDED ? 2 * D : 1;
+    constexpr int P = 2 * D - 1 < 3 ? 2 * D - 1 : 3;
+    T ring[NRING];
+    const int jj = jq - j0;                                // row within the band
+    // ---------------- forward
+    {
+        const Res rg = mkres(dv.g, vbytes), ry = mkres(dv.y, vbytes);
+        const int pw = poff(B_M0 + 0), ps = poff(B_M0 + 2);
+        const bool cons = below && first && lead, prod = above && last && lead;
+        const unsigned hl = hrow(cons, j0 - 1), hs = cons ? hl : hrow(prod, j0 + NR - 1);
+        T gA[D], wA[D][2], sA[D][2], gB[D], wB[D][2], sB[D][2];
+        auto load = [&](T (&gg)[D], T (&ww)[D][2], T (&ss)[D][2], int hb) {
+#pragma unroll
+            for (int k = 0; k < D; ++k) {
+                const int h = hb + k;
+                const unsigned hv = (unsigned)((h + 2 * NG) * NJ);
+                const bool ok = cell(h);
+                gg[k] = BufIO<T>::ld(rg, ok ? hv * (unsigned)sizeof(T) + ov : OOB);
+                const unsigned obk = ok ? hv * (unsigned)(rec * sizeof(T)) + ob : OOB;
+                Half<T>::ld(rb, obk, pw, ww[k]);
+                Half<T>::ld(rb, obk, ps, ss[k]);
+            }
+        };
+        T *const gd[2] = {cons ? &xb[0][rr] : &sink[t], cons ? &xb[1][rr] : &sink[t]};
+        auto step = [&](auto wake, const T gv, const T (&wv)[2], const T (&sv)[2], int sl, int h) {
+            constexpr bool WAKE = decltype(wake)::value;
+            const T *prev = xb[(sl + 1) & 1];
+            T *cur = xb[sl & 1];
+            const unsigned hv = (unsigned)((h + 2 * NG) * NJ);
+            if constexpr (BANDED) {
+                *gd[sl & 1] = bnd_wait(ring[sl], rh, hplane(h) + hl, budget);
+                ring[(sl + P) % NRING] = Sent<T>::ld(rh, hplane(h + P) + hl);
+            }
+            const T *xs = prev + 4 * jj + 2 * hf;                  // row below (guard row for jj = 0)
+            if (WAKE && h >= ni - nw && h < ni) {                  // row 0 at i = h: wake-cut partner
+                xs = jq == 0 ? row0 + (ni - 1 - h) * 4 + 2 * hf : xs;
+            }
+            T xw[2], xsv[2];
+            Half<T>::lds(prev + 4 * jj + 4 + 2 * hf, xw);
+            Half<T>::lds(xs, xsv);
+            const T pw_ = half_dot(wv, xw), ps_ = half_dot(sv, xsv);
+            const T dw = pw_ + Half<T>::swap(pw_), ds = ps_ + Half<T>::swap(ps_);
+            const T v = (gv - dw) - ds;
+            cur[4 * jj + 4 + rr] = v;
+            BufIO<T>::st(ry, cell(h) && lead ? hv * (unsigned)sizeof(T) + ov : OOB, v);
+            if (WAKE && h < nw) *(jq == 0 ? row0 + h * 4 + rr : &sink[t]) = v;
+            if constexpr (BANDED) Sent<T>::st(rh, hplane(h) + hs, cons ? Sent<T>::value() : v);
+            step_sync<NT>();
+        };
+        if constexpr (BANDED) {
+#pragma unroll
+            for (int k = 0; k < P; ++k) ring[k] = Sent<T>::ld(rh, hplane(k) + hl);
+        }
+        auto batch = [&](auto wake, int h0) {
+            load(gB, wB, sB, h0 + D);
+#pragma unroll
+            for (int k = 0; k < D; ++k)
+                if (BANDED || h0 + k < H) step(wake, gA[k], wA[k], sA[k], k, h0 + k);
+            load(gA, wA, sA, h0 + 2 * D);
+#pragma unroll
+            for (int k = 0; k < D; ++k)
+                if (BANDED || h0 + D + k < H) step(wake, gB[k], wB[k], sB[k], D + k, h0 + D + k);
+        };
+        load(gA, wA, sA, 0);
+        __syncthreads();
+        for (int h0 = 0; h0 < H; h0 += 2 * D) {
+            const bool plain = !cutg || h0 >= ni || (h0 >= nw && h0 + 2 * D <= ni - nw);
+            if (plain) batch(std::false_type(), h0);
+            else batch(std::true_type(), h0);
+        }
+    }
+    // ---------------- backward (+ stage update); the full barrier completes the y stores
+    __syncthreads();
+    for (int q = t; q < XS; q += NT) {
+        xb[0][q] = (T)0;
+        xb[1][q] = (T)0;
+    }
+    __syncthreads();
+    {
+        const Res ry = mkres(dv.y, vbytes);
+        const int pe = poff(B_M0 + 1), pn = poff(B_M0 + 3);
+        const Res ru0 = mkres(a.update ? dv.u0 : dv.u, dbytes), ruu = mkres(dv.u, dbytes);
+        const Res rx = mkres(dv.acc, dbytes);
+        const Res rdt = mkres(dv.dts, (size_t)NS * sizeof(double));
+        const bool cons = above && last && lead, prod = below && first && lead;
+        const unsigned hl = hrow(cons, j0 + NR), hs = cons ? hl : hrow(prod, j0);
+        T yA[D], eA[D][2], nA[D][2], yB[D], eB[D][2], nB[D][2];
+        double uA[D], uB[D], tA[D], tB[D];
+        const bool want_dt = a.update && !a.aw;
+        auto load = [&](T (&yy)[D], T (&ee)[D][2], T (&nn)[D][2], double (&u0r)[D], double (&dtr)[D], int hb) {
+#pragma unroll
+            for (int k = 0; k < D; ++k) {
+                const int h = H - 1 - (hb + k);
+                const unsigned hv = (unsigned)((h + 2 * NG) * NJ);
+                const bool ok = cell(h);
+                const unsigned obk = ok ? hv * (unsigned)(rec * sizeof(T)) + ob : OOB;
+                yy[k] = BufIO<T>::ld(ry, ok ? hv * (unsigned)sizeof(T) + ov : OOB);
+                u0r[k] = bld_d(ru0, ok && lead && a.update ? hv * 8u + od : OOB);
+                dtr[k] = bld_d(rdt, ok && lead && want_dt ? (hv + (unsigned)(jq + NG)) * 8u : OOB);
+                Half<T>::ld(rb, obk, pe, ee[k]);
+                Half<T>::ld(rb, obk, pn, nn[k]);
+            }
+        };
+        T *const gd[2] = {cons ? &xb[0][4 * NR + 4 + rr] : &sink[t], cons ? &xb[1][4 * NR + 4 + rr] : &sink[t]};
+        auto step = [&](auto wake, const T yv, const T (&ev)[2], const T (&nv)[2], const double u0v,
+                        const double dtv, int sl, int h) {
+            constexpr bool WAKE = decltype(wake)::value;
+            const T *prev = xb[(sl + 1) & 1];
+            T *cur = xb[sl & 1];
+            const unsigned hv = (unsigned)((h + 2 * NG) * NJ);
+            if constexpr (BANDED) {
+                *gd[sl & 1] = bnd_wait(ring[sl], rh, hplane(h) + hl, budget);
+                ring[(sl + P) % NRING] = Sent<T>::ld(rh, hplane(h - P) + hl);
+            }
+            T xe[2], xn[2];
+            Half<T>::lds(prev + 4 * jj + 4 + 2 * hf, xe);
+            Half<T>::lds(prev + 4 * jj + 8 + 2 * hf, xn);
+            const T pe_ = half_dot(ev, xe), pn_ = half_dot(nv, xn);
+            const T de = pe_ + Half<T>::swap(pe_), dn = pn_ + Half<T>::swap(pn_);
+            T v = (yv - de) - dn;
+            if constexpr (WAKE) {
+                // row 0 at i = h < n_wake: the wake-cut partner's term; every
+                // lane forms a half product (clamped addresses) so that the
+                // swap runs with all lanes, and row 0 keeps it
+                const bool wk = h >= 0 && h < nw;
+                const int hw = wk ? h : 0;
+                T mp[2], xp[2];
+                mp[0] = pblk[hw * 16 + rr * 4 + 2 * hf];
+                mp[1] = pblk[hw * 16 + rr * 4 + 2 * hf + 1];
+                Half<T>::lds(row0 + (wk ? nw - 1 - h : 0) * 4 + 2 * hf, xp);
+                const T pp = half_dot(mp, xp);
+                const T dp = pp + Half<T>::swap(pp);
+                if (wk && jq == 0) v = v - dp;
+            }
+            const bool valid = cell(h);
+            cur[4 * jj + 4 + rr] = v;
+            if (WAKE && h >= ni - nw && h < ni) *(jq == 0 ? row0 + (h - (ni - nw)) * 4 + rr : &sink[t]) = v;
+            if constexpr (BANDED) Sent<T>::st(rh, hplane(h) + hs, cons ? Sent<T>::value() : v);
+            const unsigned oe = valid && lead ? hv * 8u + od : OOB;
+            if (a.xout_acc) bst_d(rx, oe, (double)v);
+            if (a.update) {
+                double un;
+                if (a.aw) un = u0v - a.alpha * (double)v;
+                else un = u0v - a.alpha * (dtv * (double)v);
+                bst_d(ruu, oe, un);
             }
             step_sync<NT>();
         };
@@ -1772,7 +2112,6 @@ __global__ __launch_bounds__(NT) void k_sgs4(BK bk, SweepArgs a) {
         load(yA, eA, nA, uA, tA, 0);
         __syncthreads();
         for (int h0 = 0; h0 < H; h0 += 2 * D) {
-            // the batch's hyperplanes H - 1 - h0 down to H - 2D - h0
             const int hhi = H - 1 - h0, hlo = H - 2 * D - h0;
             const bool plain = !cutg || hlo >= ni || hhi < 0 || (hlo >= nw && hhi < ni - nw);
             if (plain) batch(std::false_type(), h0);
@@ -1786,11 +2125,12 @@ __global__ __launch_bounds__(NT) void k_sgs4(BK bk, SweepArgs a) {
 // Each job restricts the fine-level combination a x (+ b y), formed per
 // fine cell as the elementwise update of the same name would form it.
 __global__ void k_restrict(BK bf, BK bc, RJob j0, RJob j1, int njobs, int mut) {
+    const BlockXY cb = xcd_block();
     LevelDev df, dc;
-    if (!take(bf, blockIdx.y, df) || !take(bc, blockIdx.y, dc)) return;
+    if (!take(bf, cb.y, df) || !take(bc, cb.y, dc)) return;
     const Lay Lf = df.L, Lc = dc.L;
     const double *geof = df.geo, *geoc = dc.geo;
-    int s = blockIdx.x * blockDim.x + threadIdx.x;
+    int s = cb.x * blockDim.x + threadIdx.x;
     int i, j;
     if (!decode(Lc, s, i, j) || !interior(Lc, i, j)) return;
     const int NSf = Lf.NS, NSc = Lc.NS;
@@ -1824,12 +2164,13 @@ __global__ void k_restrict(BK bf, BK bc, RJob j0, RJob j1, int njobs, int mut) {
 // 9/16 (parent), 3/16, 3/16, 1/16 towards the fine cell's side; the wake-cut
 // partner across the cut, the parent's value where a neighbour is missing.
 __global__ void k_prolong(BK bf, BK bc) {
+    const BlockXY cb = xcd_block();
     LevelDev df, dc;
-    if (!take(bf, blockIdx.y, df) || !take(bc, blockIdx.y, dc)) return;
+    if (!take(bf, cb.y, df) || !take(bc, cb.y, dc)) return;
     const Lay Lf = df.L, Lc = dc.L;
     const double *uc = dc.u, *utc = dc.ut;
     double *uf = df.u;
-    int s = blockIdx.x * blockDim.x + threadIdx.x;
+    int s = cb.x * blockDim.x + threadIdx.x;
     int i, j;
     if (!decode(Lf, s, i, j) || !interior(Lf, i, j)) return;
     const int NSc = Lc.NS, NSf = Lf.NS;
@@ -1856,12 +2197,13 @@ __global__ void k_prolong(BK bf, BK bc) {
 
 // out = a x (+ b y) on the interior cells, fields named per case
 __global__ void k_axpby(BK bk, double a, int fx, double b, int fy, int fout) {
+    const BlockXY cb = xcd_block();
     LevelDev d;
-    if (!take(bk, blockIdx.y, d)) return;
+    if (!take(bk, cb.y, d)) return;
     const Lay L = d.L;
     const double *x = field(d, fx), *y = field(d, fy);
     double *out = field(d, fout);
-    int s = blockIdx.x * blockDim.x + threadIdx.x;
+    int s = cb.x * blockDim.x + threadIdx.x;
     int i, j;
     if (!decode(L, s, i, j) || !interior(L, i, j)) return;
 #pragma unroll
@@ -2517,10 +2859,12 @@ void launch_blocks(const BLev &B, int aw, double tau, int viscous, int fp32, hip
 // rows per four-thread group, prefetch batches of D hyperplanes, as deep as
 // the register file allows at that size and precision: FP32 rows take
 // half the registers), the one-thread-per-row kernel for grids taller than
-// 256 rows, and the banded form of k_sgs4 (kind 5: bands of NT / 4 * R
-// rows, one workgroup per band, as many bands as the tallest grid needs).
+// 256 rows, the banded form of k_sgs4 (kind 5: bands of NT / 4 * R rows,
+// one workgroup per band, as many bands as the tallest grid needs), and
+// eight threads per row (k_sgs8: kind 8 one workgroup of NT / 8 rows per
+// case, kind 9 bands of NT / 8 rows).
 struct SweepCfg {
-    int kind;        // 4: k_sgs4, 1: k_sgs, 5: banded k_sgs4
+    int kind;        // 4: k_sgs4, 1: k_sgs, 5: banded k_sgs4, 8: k_sgs8, 9: banded k_sgs8
     int nt, r;
     int d64, d32;    // prefetch depth for FP64 / FP32 blocks
 };
@@ -2533,6 +2877,10 @@ static constexpr SweepCfg SWEEP_CFGS[] = {
     {5, 128, 1, 3, 3},   {5, 128, 1, 4, 4},   {4, 128, 1, 3, 3},   {5, 128, 1, 2, 2},
     {5, 128, 1, 1, 1},   {5, 64, 1, 2, 2},    {5, 64, 1, 3, 3},    {4, 128, 1, 2, 2},
     {5, 64, 1, 4, 4},
+    {8, 64, 1, 4, 4},    {8, 128, 1, 4, 4},   {8, 256, 1, 4, 4},   {8, 512, 1, 4, 4},
+    {9, 64, 1, 4, 4},    {9, 128, 1, 4, 4},   {9, 256, 1, 4, 4},   {9, 128, 1, 3, 3},
+    {9, 128, 1, 6, 6},   {9, 256, 1, 6, 6},   {9, 64, 1, 6, 6},    {8, 256, 1, 6, 6},
+    {5, 64, 2, 2, 2},    {5, 64, 2, 3, 3},
 };
 constexpr int N_SWEEP_CFGS = (int)(sizeof(SWEEP_CFGS) / sizeof(SWEEP_CFGS[0]));
 
@@ -2540,21 +2888,21 @@ int sweep_cfg_count() { return N_SWEEP_CFGS; }
 
 static int cfg_group_rows(int cfg) {
     const SweepCfg &c = SWEEP_CFGS[cfg];
-    return c.kind == 1 ? c.nt : c.nt / 4 * c.r;
+    return c.kind == 1 ? c.nt : (c.kind == 8 || c.kind == 9) ? c.nt / 8 : c.nt / 4 * c.r;
 }
+
+bool sweep_cfg_banded(int cfg) { return SWEEP_CFGS[cfg].kind == 5 || SWEEP_CFGS[cfg].kind == 9; }
 
 int sweep_cfg_bands(int cfg, int max_nj) {
     const int nr = cfg_group_rows(cfg);
-    return SWEEP_CFGS[cfg].kind == 5 ? (max_nj + nr - 1) / nr : 1;
+    return sweep_cfg_banded(cfg) ? (max_nj + nr - 1) / nr : 1;
 }
 
 int sweep_cfg_rows(int cfg, int max_nj) { return cfg_group_rows(cfg) * sweep_cfg_bands(cfg, max_nj); }
 
-bool sweep_cfg_banded(int cfg) { return SWEEP_CFGS[cfg].kind == 5; }
-
 void sweep_cfg_info(int cfg, int *kind, int *threads, int *rows, int *d64, int *d32) {
     const SweepCfg &c = SWEEP_CFGS[cfg];
-    *kind = c.kind == 4 ? 0 : c.kind == 1 ? 1 : 2;
+    *kind = c.kind == 4 ? 0 : c.kind == 1 ? 1 : c.kind == 5 ? 2 : c.kind == 8 ? 3 : 4;
     *threads = c.nt;
     *rows = cfg_group_rows(cfg);
     *d64 = c.d64;
@@ -2595,77 +2943,55 @@ static int resident_blocks(K kernel, int nt, size_t shm) {
     return per * ncu;
 }
 
+template <typename T> static void sgs_dispatch(const BLev &B, const SweepArgs &a0, hipStream_t st);
+
+// one configuration of the table, instantiated at compile time; a banded
+// launch whose workgroups cannot all be resident falls back to one
+// workgroup per case
+template <typename T, int C>
+static void sgs_launch_cfg(const BLev &B, const SweepArgs &a0, hipStream_t st) {
+    constexpr SweepCfg c = SWEEP_CFGS[C];
+    constexpr int D = sizeof(T) == 4 ? c.d32 : c.d64;
+    const int nwl = B.max_nw > 0 ? B.max_nw : 1;
+    const size_t shm = (size_t)nwl * 4 * sizeof(T);
+    const size_t shm4 = (size_t)nwl * 20 * sizeof(T);
+    SweepArgs a = a0;
+    a.bands = sweep_cfg_bands(C, B.max_nj);
+    auto banded = [&](auto kernel) {
+        if (B.n * a.bands <= resident_blocks(kernel, c.nt, shm4)) {
+            hipLaunchKernelGGL(kernel, dim3(B.n * a.bands), dim3(c.nt), shm4, st, B.k, a);
+        } else {
+            BLev B1 = B;
+            B1.sweep_cfg = sweep_cfg_plain(B.max_nj);
+            sgs_dispatch<T>(B1, a0, st);
+        }
+    };
+    if constexpr (c.kind == 1) {
+        hipLaunchKernelGGL((k_sgs<T, c.nt>), dim3(B.n), dim3(c.nt), shm, st, B.k, a);
+    } else if constexpr (c.kind == 4) {
+        hipLaunchKernelGGL((k_sgs4<T, c.nt, c.r, D, false>), dim3(B.n), dim3(c.nt), shm4, st, B.k, a);
+    } else if constexpr (c.kind == 5) {
+        banded(k_sgs4<T, c.nt, c.r, D, true>);
+    } else if constexpr (c.kind == 8) {
+        hipLaunchKernelGGL((k_sgs8<T, c.nt / 64, D, false>), dim3(B.n), dim3(c.nt), shm4, st, B.k, a);
+    } else {
+        static_assert(c.kind == 9, "unknown sweep kind");
+        banded(k_sgs8<T, c.nt / 64, D, true>);
+    }
+}
+
+template <typename T, int... Cs>
+static void sgs_select(int cfg, const BLev &B, const SweepArgs &a0, hipStream_t st,
+                       std::integer_sequence<int, Cs...>) {
+    ((cfg == Cs ? (sgs_launch_cfg<T, Cs>(B, a0, st), 0) : 0), ...);
+}
+
 template <typename T>
 static void sgs_dispatch(const BLev &B, const SweepArgs &a0, hipStream_t st) {
     constexpr int FP32 = sizeof(T) == 4 ? 1 : 0;
     int cfg = B.sweep_cfg >= 0 ? B.sweep_cfg : sweep_cfg_default(B.max_nj, FP32);
-    if (sweep_cfg_rows(cfg, B.max_nj) < B.max_nj) cfg = sweep_cfg_default(B.max_nj, FP32);
-    const int nwl = B.max_nw > 0 ? B.max_nw : 1;
-    const size_t shm = (size_t)nwl * 4 * sizeof(T);
-    const size_t shm4 = (size_t)nwl * 20 * sizeof(T);
-    constexpr bool F32 = sizeof(T) == 4;
-    SweepArgs a = a0;
-    a.bands = sweep_cfg_bands(cfg, B.max_nj);
-#define FAS_K4(C_, BANDED_)                                                                           \
-    k_sgs4<T, SWEEP_CFGS[C_].nt, SWEEP_CFGS[C_].r, (F32 ? SWEEP_CFGS[C_].d32 : SWEEP_CFGS[C_].d64), \
-           BANDED_>
-#define FAS_SGS4(C_) hipLaunchKernelGGL((FAS_K4(C_, false)), dim3(B.n), dim3(SWEEP_CFGS[C_].nt), shm4, st, B.k, a)
-#define FAS_SGS5(C_)                                                                                   \
-    do {                                                                                               \
-        if (B.n * a.bands <= resident_blocks(FAS_K4(C_, true), SWEEP_CFGS[C_].nt, shm4)) {             \
-            hipLaunchKernelGGL((FAS_K4(C_, true)), dim3(B.n * a.bands), dim3(SWEEP_CFGS[C_].nt), shm4, \
-                               st, B.k, a);                                                            \
-        } else {                                                                                       \
-            BLev B1 = B;                                                                               \
-            B1.sweep_cfg = sweep_cfg_plain(B.max_nj);                                                  \
-            sgs_dispatch<T>(B1, a0, st);                                                               \
-        }                                                                                              \
-    } while (0)
-#define FAS_SGS1(C_) \
-    hipLaunchKernelGGL((k_sgs<T, SWEEP_CFGS[C_].nt>), dim3(B.n), dim3(SWEEP_CFGS[C_].nt), shm, st, B.k, a)
-    static_assert(N_SWEEP_CFGS == 32 && SWEEP_CFGS[31].kind == 5 && SWEEP_CFGS[30].kind == 4 && SWEEP_CFGS[27].kind == 5 && SWEEP_CFGS[9].kind == 4 && SWEEP_CFGS[10].kind == 1 &&
-                      SWEEP_CFGS[13].kind == 1 && SWEEP_CFGS[14].kind == 5 && SWEEP_CFGS[17].kind == 5 &&
-                      SWEEP_CFGS[18].kind == 4 && SWEEP_CFGS[19].kind == 4 && SWEEP_CFGS[20].kind == 5 &&
-                      SWEEP_CFGS[22].kind == 5 && SWEEP_CFGS[24].kind == 5 && SWEEP_CFGS[25].kind == 4,
-                  "the switch below follows the configuration table");
-    switch (cfg) {
-        case 0: FAS_SGS4(0); break;
-        case 1: FAS_SGS4(1); break;
-        case 2: FAS_SGS4(2); break;
-        case 3: FAS_SGS4(3); break;
-        case 4: FAS_SGS4(4); break;
-        case 5: FAS_SGS4(5); break;
-        case 6: FAS_SGS4(6); break;
-        case 7: FAS_SGS4(7); break;
-        case 8: FAS_SGS4(8); break;
-        case 9: FAS_SGS4(9); break;
-        case 10: FAS_SGS1(10); break;
-        case 11: FAS_SGS1(11); break;
-        case 12: FAS_SGS1(12); break;
-        case 13: FAS_SGS1(13); break;
-        case 14: FAS_SGS5(14); break;
-        case 15: FAS_SGS5(15); break;
-        case 16: FAS_SGS5(16); break;
-        case 17: FAS_SGS5(17); break;
-        case 18: FAS_SGS4(18); break;
-        case 19: FAS_SGS4(19); break;
-        case 20: FAS_SGS5(20); break;
-        case 21: FAS_SGS5(21); break;
-        case 22: FAS_SGS5(22); break;
-        case 23: FAS_SGS5(23); break;
-        case 24: FAS_SGS5(24); break;
-        case 25: FAS_SGS4(25); break;
-        case 26: FAS_SGS5(26); break;
-        case 27: FAS_SGS5(27); break;
-        case 28: FAS_SGS5(28); break;
-        case 29: FAS_SGS5(29); break;
-        case 31: FAS_SGS5(31); break;
-        default: FAS_SGS4(30); break;
-    }
-#undef FAS_K4
-#undef FAS_SGS4
-#undef FAS_SGS5
-#undef FAS_SGS1
+    if (cfg >= N_SWEEP_CFGS || sweep_cfg_rows(cfg, B.max_nj) < B.max_nj) cfg = sweep_cfg_default(B.max_nj, FP32);
+    sgs_select<T>(cfg, B, a0, st, std::make_integer_sequence<int, N_SWEEP_CFGS>());
 }
 
 void launch_sgs(const BLev &B, const SweepArgs &a, int fp32, hipStream_t st) {

@@ -467,7 +467,7 @@ def torch_dtype():
     return torch.float64
 
 
-SWEEP_FOUR_THREADS, SWEEP_ONE_THREAD, SWEEP_BANDED = 0, 1, 2
+SWEEP_FOUR_THREADS, SWEEP_ONE_THREAD, SWEEP_BANDED, SWEEP_EIGHT_THREADS, SWEEP_EIGHT_BANDED = 0, 1, 2, 3, 4
 
 
 class _DfaCase(ctypes.Structure):
@@ -538,8 +538,9 @@ def sweep_config_count():
 
 def sweep_config_info(cfg):
     """(kind, threads, rows per workgroup, FP64 depth, FP32 depth) of a sweep
-    configuration; kind is SWEEP_FOUR_THREADS, SWEEP_ONE_THREAD or
-    SWEEP_BANDED."""
+    configuration; kind is SWEEP_FOUR_THREADS, SWEEP_ONE_THREAD,
+    SWEEP_BANDED (row bands of four-thread rows), SWEEP_EIGHT_THREADS or
+    SWEEP_EIGHT_BANDED (row bands of eight-thread rows)."""
     v = [ctypes.c_int32(0) for _ in range(5)]
     _check(load().fas_sweep_config_info(cfg, *[ctypes.byref(x) for x in v]))
     return tuple(int(x.value) for x in v)

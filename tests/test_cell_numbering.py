@@ -1,5 +1,6 @@
 """Host check of the hyperplane-ordered cell numbering that the cell-parallel
-kernels launch over (rect_cell in fas_cells.h).
+kernels launch over (rect_cell in fas_cells.h), and of the XCD-aware
+renumbering of their workgroups (xcd_block).
 
 The device functions and the layout struct are taken verbatim from the
 sources, compiled for the host with g++, and run over every rectangle the
@@ -7,7 +8,8 @@ kernels use: interior cells, vertices and every padded cell, for all grids
 up to 48 x 48 plus a few large and thin ones.  For each, the numbering must
 hit every cell of the rectangle exactly once, give strictly increasing slots
 (hyperplane order, j ascending inside a hyperplane), agree with decode(),
-and reject numbers past the last cell."""
+and reject numbers past the last cell; the workgroup renumbering must be a
+bijection of every grid and hand one-row grids to the XCDs in runs."""
 import os
 import re
 import shutil
@@ -58,7 +60,35 @@ int main() {
         for (int nj = 1; nj <= 48; ++nj) all(ni, nj);
     const int big[][2] = {{512, 256}, {256, 512}, {1024, 64}, {16, 4096}, {4096, 8}};
     for (const auto &p : big) all(p[0], p[1]);
-    std::printf("rectangles %ld bad %ld\n", checked, bad);
+    // xcd_block: a bijection of every grid; one-row grids give each XCD
+    // (hardware number w mod 8) whole runs of consecutive workgroups
+    long grids = 0;
+    const int gs[][2] = {{1, 1}, {7, 1}, {8, 1}, {9, 1}, {63, 1}, {64, 1}, {128, 1}, {511, 1}, {512, 1},
+                         {513, 1}, {4096, 1}, {5000, 1}, {3, 5}, {512, 64}, {2048, 3}, {100, 7}};
+    for (const auto &g : gs) {
+        gridDim.x = g[0]; gridDim.y = g[1];
+        const long G = (long)g[0] * g[1];
+        std::vector<int> seen(G, 0), owner(G, -1);
+        for (unsigned y = 0; y < gridDim.y; ++y)
+            for (unsigned x = 0; x < gridDim.x; ++x) {
+                blockIdx.x = x; blockIdx.y = y;
+                const BlockXY b = xcd_block();
+                if (b.x < 0 || b.x >= g[0] || b.y < 0 || b.y >= g[1]) { ++bad; continue; }
+                const long v = (long)b.y * g[0] + b.x;
+                seen[v]++;
+                owner[v] = (int)((x + (long)y * g[0]) % XCD_COUNT);
+            }
+        for (int c : seen) if (c != 1) ++bad;
+        if (g[1] == 1 && G >= (long)XCD_COUNT) {
+            // inside the permuted rounds, runs of G / 8 (at most 64) share an XCD
+            const long run = std::min<long>(XCD_RUN_MAX, G / XCD_COUNT);
+            const long full = G / (XCD_COUNT * run) * (XCD_COUNT * run);
+            for (long v = 0; v < full; ++v)
+                if (owner[v] != owner[v - v % run]) ++bad;
+        }
+        ++grids;
+    }
+    std::printf("rectangles %ld grids %ld bad %ld\n", checked, grids, bad);
     return bad != 0;
 }
 """
@@ -80,7 +110,8 @@ def _source():
     funcs = kernels[a:b] + cells[c:d]
     host = lambda t: t.replace("__host__ ", "").replace("__device__ ", "")
     head = ("#include <algorithm>\n#include <cmath>\n#include <cstdio>\n#include <vector>\n"
-            "using std::max; using std::min;\nconstexpr int NG = %s;\n" % ng)
+            "using std::max; using std::min;\nconstexpr int NG = %s;\n"
+            "struct Dim3 { unsigned x = 0, y = 0; } gridDim, blockIdx;   // host stand-ins\n" % ng)
     return head + host(lay) + "\n" + host(funcs) + MAIN
 
 

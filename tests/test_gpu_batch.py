@@ -13,9 +13,9 @@ from gpu_common import TOL_STATE, state_err
 pytestmark = pytest.mark.gpu
 
 
-def _cfgs(kind):
+def _cfgs(*kinds):
     from paper_1710_04875_amd import fas
-    return [c for c in range(fas.sweep_config_count()) if fas.sweep_config_info(c)[0] == kind]
+    return [c for c in range(fas.sweep_config_count()) if fas.sweep_config_info(c)[0] in kinds]
 
 # (ni, nj, n_wake, mach, alpha): uneven grids and flow conditions
 CASES = [(64, 32, 8, 0.8, 1.3), (96, 48, 12, 0.6, 0.4), (128, 16, 16, 0.75, 2.5)]
@@ -140,8 +140,8 @@ def test_every_sweep_configuration_gives_the_same_iterate():
         for c, (_, s) in enumerate(pairs):
             u = s.get_state().cpu().numpy()
             if cfg not in one_thread:
-                # the four-thread sweeps, banded or not, share their
-                # arithmetic: bitwise equal
+                # the four- and eight-thread sweeps, banded or not, form
+                # every product and sum in the same order: bitwise equal
                 assert np.array_equal(u, ref[c][0]), (cfg, c)
             else:
                 # the one-thread-per-row sweep sums the block products in
@@ -161,7 +161,7 @@ def test_row_bands_equal_one_workgroup_per_case(fp32, scheme, cfl):
     from paper_1710_04875_amd import fas
     ref = _run_single(fp32=fp32, cycles=3, scheme=scheme, cfl=cfl, cfl_ramp=min(cfl, 5.0))
     assert all(np.isfinite(u).all() for u, _, _ in ref)
-    for cfg in _cfgs(fas.SWEEP_BANDED):
+    for cfg in _cfgs(fas.SWEEP_BANDED, fas.SWEEP_EIGHT_BANDED):
         pairs = _states(fp32=fp32, scheme=scheme, cfl=cfl, cfl_ramp=min(cfl, 5.0))
         b = fas.Batch([st for _, st in pairs], autotune=False)
         for level in range(3):
