@@ -261,7 +261,7 @@ def traffic_summary(fetch_dir, write_dir, calf_dir, calw_dir):
     ff, fw = copy_kib / calf, copy_kib / calw
     fetch, write = per_kernel(fetch_dir), per_kernel(write_dir)
     cells = level_cells(256, 128, 3)
-    keys = sorted(fetch, key=lambda k: -fetch[k])
+    keys = sorted((k for k in fetch if "k_sgs" in k[0]), key=lambda k: -fetch[k])
     assert len(keys) == 3, keys
     lines, per = [], []
     for k, c in zip(keys, cells):

@@ -389,7 +389,10 @@ static BLev make_blev(const std::vector<Lay> &lays, const LevelDev *dV, const Ph
     B.k.PH = dPH;
     B.k.act = act;
     B.k.cyc = cyc;
+    B.k.tile0 = nullptr;
     B.n = (int)lays.size();
+    B.k.n = B.n;
+    B.ntiles = 0;
     B.max_ns = B.max_ni = B.max_nj = B.max_nw = 0;
     for (const Lay &L : lays) {
         B.max_ns = std::max(B.max_ns, L.NS);
@@ -1715,11 +1718,24 @@ extern "C" fas_status fas_batch_create(int32_t n, const fas_state *states, void 
         return cleanup(fail(FAS_ENOMEM, "pinned allocation failed"));
     launch_fill_int(b->d_act, n, 1, e.st);
     launch_fill_int(e.d_rb, n, 0, e.st);
+    // per level the first residual tile of each case (n + 1 entries)
+    int *dtiles = nullptr;
+    if (hipMalloc(reinterpret_cast<void **>(&dtiles), (size_t)e.nlev * (n + 1) * sizeof(int)) != hipSuccess)
+        return cleanup(fail(FAS_ENOMEM, "batch allocation failed"));
+    b->allocs.push_back(dtiles);
+    std::vector<int> htiles((size_t)e.nlev * (n + 1));
     for (int l = 0; l < e.nlev; ++l) {
         std::vector<Lay> lays;
         for (int c = 0; c < n; ++c) lays.push_back(states[c]->lv[l].L);
         e.lev.push_back(make_blev(lays, dV + (size_t)l * n, dPH, b->d_act, e.d_cyc));
+        int *t0 = htiles.data() + (size_t)l * (n + 1);
+        t0[0] = 0;
+        for (int c = 0; c < n; ++c) t0[c + 1] = t0[c] + residual_tiles(lays[c]);
+        e.lev.back().k.tile0 = dtiles + (size_t)l * (n + 1);
+        e.lev.back().ntiles = t0[n];
     }
+    if (hipMemcpy(dtiles, htiles.data(), htiles.size() * sizeof(int), hipMemcpyHostToDevice) != hipSuccess)
+        return cleanup(fail(FAS_EDEVICE, "batch descriptor upload failed"));
     // autotuner: per level, the fastest sweep configuration that covers the
     // tallest grid (banded ones with 2 to 16 bands), timed on the batch itself
     if (autotune) {

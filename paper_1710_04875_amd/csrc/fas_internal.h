@@ -149,6 +149,8 @@ struct BK {
     const Phys *PH;       // [n]
     const int *act;       // [n] 0 = skip the case; nullptr = all active
     const int *cyc;       // [n] completed FAS cycles (c* ramp)
+    const int *tile0;     // [n + 1] first residual tile of each case (batches), nullptr for one state
+    int n;                // cases
 };
 
 // host descriptor of one level of a batch
@@ -157,7 +159,11 @@ struct BLev {
     int n;                // cases
     int max_ns, max_ni, max_nj, max_nw;   // launch sizing over the cases
     int sweep_cfg;        // sweep kernel configuration (-1: by max_nj)
+    int ntiles;           // residual tiles of all cases (k.tile0[n])
 };
+
+// residual tiles of one grid (the tiled residual's launch unit)
+int residual_tiles(const Lay &L);
 
 // ---------------------------------------------------------------- launchers
 // geometry (one grid, at creation)

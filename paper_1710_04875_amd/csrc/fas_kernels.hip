@@ -802,34 +802,97 @@ __device__ inline void residual_cell(const LevelDev &d, const ResArgs &a, int NS
     }
 }
 
+// Residual of a level (Section 2; eq. "split-rhs" for the stages): the face
+// fluxes of each cell's four faces, summed as (e - w) + (n - s) per
+// component and divided by the volume, then residual_cell.  A cell's west
+// face is the face between cells i - 1 and i, formed by face_flux from the
+// two cells' slots, the face vector stored at the cell and the two vertices
+// of the face; its east face is the west face of cell i + 1, argument for
+// argument, and likewise for the south and north faces.
+//
+// Large launches: one workgroup per tile of RT_I x RT_J cells, every face of
+// the tile computed once.  The i-faces ((RT_I + 1) x RT_J, the west face of
+// each cell and the east face of the tile's last column) and the j-faces
+// (RT_I x (RT_J + 1)) are written to LDS plane by plane, and each cell then
+// sums its four: the result is bitwise that of the four-lane kernel below,
+// with half the flux evaluations of a per-cell kernel and neighbouring
+// faces' gathers served by the same cache lines.
+// (16 x 15 cells: 255 i-faces and 256 j-faces, so each of the 256 threads
+// forms at most one face of each family)
+constexpr int RT_I = 16, RT_J = 15, RT_TPB = 256;
+constexpr int RT_NIF = (RT_I + 1) * RT_J, RT_NJF = RT_I * (RT_J + 1);
+
+// Batches launch one row of workgroups over the tiles of all cases in turn
+// (b.tile0: first tile of each case), so that the XCD runs of xcd_block
+// hold real tiles only and split them evenly over the XCDs; one state
+// launches its tiles (gridDim.x) for case blockIdx.y.
 template <typename BT>
-__global__ __launch_bounds__(TPB) void k_residual(BK b, ResArgs a) {
+__global__ __launch_bounds__(RT_TPB) void k_residual_t(BK b, ResArgs a) {
+    __shared__ double fi_c[4][RT_NIF], fi_v[4][RT_NIF], fj_c[4][RT_NJF], fj_v[4][RT_NJF];
     const BlockXY cb = xcd_block();
+    int c = cb.y, tile = cb.x;
+    if (b.tile0 != nullptr) {
+        int lo = 0, hi = b.n;                           // b.tile0[lo] <= tile < b.tile0[hi]
+        while (hi - lo > 1) {
+            const int mid = (lo + hi) >> 1;
+            if (b.tile0[mid] <= tile) lo = mid;
+            else hi = mid;
+        }
+        c = lo;
+        tile -= b.tile0[lo];
+    }
     LevelDev d;
-    if (!take(b, cb.y, d)) return;
+    if (!take(b, c, d)) return;
     const Lay L = d.L;
+    const int nti = (L.ni + RT_I - 1) / RT_I, ntj = (L.nj + RT_J - 1) / RT_J;
+    if (tile >= nti * ntj) return;                      // tile past this case's grid
+    const Phys ph = b.PH[c];
+    const int i0 = (tile % nti) * RT_I, j0 = (tile / nti) * RT_J;
+    const int ci = min(RT_I, L.ni - i0), cj = min(RT_J, L.nj - j0);
+    const int NS = L.NS, NJ = L.NJ, t = threadIdx.x;
     const double *geo = d.geo, *u = d.u, *cq = d.cq, *vg = d.vg, *mut = d.mut;
-    const Phys ph = b.PH[cb.y];
-    int s, i, j;
-    if (!interior_cell(L, cb.x * blockDim.x + threadIdx.x, s, i, j)) return;
-    const int NS = L.NS, NJ = L.NJ;
-    FaceOut w, e, so, n;
-    face_flux(L, geo, u, cq, vg, mut, ph, a, s - NJ, s, NJ, geo[G_SXI_X * NS + s],
-              geo[G_SXI_Y * NS + s], s, s + NJ + 1, false, s, G_WIX, w);
-    face_flux(L, geo, u, cq, vg, mut, ph, a, s, s + NJ, NJ, geo[G_SXI_X * NS + s + NJ],
-              geo[G_SXI_Y * NS + s + NJ], s + NJ, s + 2 * NJ + 1, false, s + NJ, G_WIX, e);
-    bool wall = (j == 0) && !cut_col(L, i);
-    face_flux(L, geo, u, cq, vg, mut, ph, a, s - NJ - 1, s, NJ + 1, geo[G_SETA_X * NS + s],
-              geo[G_SETA_Y * NS + s], s, s + NJ, wall, s, G_WJX, so);
-    face_flux(L, geo, u, cq, vg, mut, ph, a, s, s + NJ + 1, NJ + 1,
-              geo[G_SETA_X * NS + s + NJ + 1], geo[G_SETA_Y * NS + s + NJ + 1], s + NJ + 1,
-              s + 2 * NJ + 1, false, s + NJ + 1, G_WJX, n);
+    // i-faces: face (fi, fj) is the west face of cell (i0 + fi, j0 + fj)
+    static_assert(RT_NIF <= RT_TPB && RT_NJF <= RT_TPB, "one face of each family per thread");
+    if (t < (ci + 1) * cj) {
+        const int fi = t % (ci + 1), fj = t / (ci + 1);
+        const int s = L.slot(i0 + fi, j0 + fj);
+        FaceOut o;
+        face_flux(L, geo, u, cq, vg, mut, ph, a, s - NJ, s, NJ, geo[G_SXI_X * NS + s], geo[G_SXI_Y * NS + s], s,
+                  s + NJ + 1, false, s, G_WIX, o);
+        const int q = fj * (RT_I + 1) + fi;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            fi_c[k][q] = o.C[k];
+            fi_v[k][q] = o.V[k];
+        }
+    }
+    // j-faces: face (fi, fj) is the south face of cell (i0 + fi, j0 + fj)
+    if (t < ci * (cj + 1)) {
+        const int fi = t % ci, fj = t / ci;
+        const int i = i0 + fi, j = j0 + fj;
+        const int s = L.slot(i, j);
+        const bool wall = (j == 0) && !cut_col(L, i);
+        FaceOut o;
+        face_flux(L, geo, u, cq, vg, mut, ph, a, s - NJ - 1, s, NJ + 1, geo[G_SETA_X * NS + s],
+                  geo[G_SETA_Y * NS + s], s, s + NJ, wall, s, G_WJX, o);
+        const int q = fj * RT_I + fi;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            fj_c[k][q] = o.C[k];
+            fj_v[k][q] = o.V[k];
+        }
+    }
+    __syncthreads();
+    const int ti = t % RT_I, tj = t / RT_I;
+    if (ti >= ci || tj >= cj) return;
+    const int s = L.slot(i0 + ti, j0 + tj);
+    const int qw = tj * (RT_I + 1) + ti, qs = tj * RT_I + ti;
     const double vol = geo[G_VOL * NS + s];
     double Fc[4], Fv[4];
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
-        double fc = (e.C[k] - w.C[k]) + (n.C[k] - so.C[k]);
-        double fv = (e.V[k] - w.V[k]) + (n.V[k] - so.V[k]);
+        double fc = (fi_c[k][qw + 1] - fi_c[k][qw]) + (fj_c[k][qs + RT_I] - fj_c[k][qs]);
+        double fv = (fi_v[k][qw + 1] - fi_v[k][qw]) + (fj_v[k][qs + RT_I] - fj_v[k][qs]);
         Fc[k] = fc / vol;
         Fv[k] = fv / vol;
     }
@@ -838,7 +901,7 @@ __global__ __launch_bounds__(TPB) void k_residual(BK b, ResArgs a) {
 
 // Small launches: four lanes per cell, one face each (w, e, s, n), so the
 // flux chain each lane runs is a quarter as long.  The face sums are formed
-// by lane shuffles in the order of k_residual, (e - w) + (n - s), so the
+// by lane shuffles in the same order, (e - w) + (n - s), so the
 // result is bitwise the same; lanes past the last cell redo cell 0 and store
 // nothing, so every lane takes part in the shuffles.
 template <typename BT>
@@ -2824,6 +2887,8 @@ long long set_four_lane_limit(long long cells) {
     return old;
 }
 
+int residual_tiles(const Lay &L) { return ((L.ni + RT_I - 1) / RT_I) * ((L.nj + RT_J - 1) / RT_J); }
+
 void launch_residual(const BLev &B, const ResArgs &a, hipStream_t st) {
     if ((long long)B.max_ni * B.max_nj * B.n <= g_four_lane_cells) {
         const dim3 grid(nblocks(4 * B.max_ni * B.max_nj, CELL_TPB), B.n);
@@ -2833,10 +2898,13 @@ void launch_residual(const BLev &B, const ResArgs &a, hipStream_t st) {
             hipLaunchKernelGGL(k_residual_q<double>, grid, dim3(CELL_TPB), 0, st, B.k, a);
         return;
     }
+    const dim3 grid = B.k.tile0 != nullptr
+                          ? dim3((unsigned)B.ntiles, 1)
+                          : dim3((unsigned)(((B.max_ni + RT_I - 1) / RT_I) * ((B.max_nj + RT_J - 1) / RT_J)), B.n);
     if (a.fp32)
-        hipLaunchKernelGGL(k_residual<float>, interior_grid(B), dim3(CELL_TPB), 0, st, B.k, a);
+        hipLaunchKernelGGL(k_residual_t<float>, grid, dim3(RT_TPB), 0, st, B.k, a);
     else
-        hipLaunchKernelGGL(k_residual<double>, interior_grid(B), dim3(CELL_TPB), 0, st, B.k, a);
+        hipLaunchKernelGGL(k_residual_t<double>, grid, dim3(RT_TPB), 0, st, B.k, a);
 }
 
 void launch_blocks(const BLev &B, int aw, double tau, int viscous, int fp32, hipStream_t st, int copy_u0) {
