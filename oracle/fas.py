@@ -241,32 +241,59 @@ class Solver:
         self.set_u(l, u_new)
 
     # ------------------------------------------------------------------ FAS
-    def cycle(self, l: int = 0):
-        L = len(self.levels)
-        nsm = self.par.nu1 if l < L - 1 else 1
-        for _ in range(nsm):
-            self.smooth(l)
-        if l == L - 1:
-            return
+    # Section 3: level l + 1 (coarser; this module counts from the finest
+    # level 0) solves eq. "coarse-nonlin-eq", s_{l+1} - F_{l+1}(u_{l+1}) = 0,
+    # whose forcing makes the restricted fine state satisfy it up to the
+    # restricted fine residual; the change the coarse solve makes to that
+    # restricted state is the fine level's correction.
+    def transfer_eddy_viscosity(self, l: int):
+        """RANS: the eddy viscosity of level l at its current state (the
+        Baldwin-Lomax model on the finest level, the restricted one below),
+        restricted to level l + 1 and frozen there for the coarse solve."""
         lev_f, lev_c = self.levels[l], self.levels[l + 1]
-        if self.par.model == RANS:
-            # eddy viscosity of this level at its current state, restricted
-            if l == 0:
-                m = baldwin_lomax(lev_f, self.padded(0, self.u(0)), self.par)
-            else:
-                m = self.mutc[l][NG:NG + lev_f.nj, NG:NG + lev_f.ni]
-            self.mutc[l + 1] = padded_eddy_viscosity(lev_c, restrict_scalar(lev_f, lev_c, m))
+        if l == 0:
+            m = baldwin_lomax(lev_f, self.padded(0, self.u(0)), self.par)
+        else:
+            m = self.mutc[l][NG:NG + lev_f.nj, NG:NG + lev_f.ni]
+        self.mutc[l + 1] = padded_eddy_viscosity(lev_c, restrict_scalar(lev_f, lev_c, m))
+
+    def coarse_problem(self, l: int):
+        """Set up eq. "coarse-nonlin-eq" on level l + 1: its state starts at
+        the volume-weighted restriction u~ = R u_l, and its forcing is
+        s_{l+1} = F_{l+1}(u~) + R r_l with the defect r_l = s_l - F_l(u_l)
+        of level l (s_0 = 0 on the finest level).  Returns u~."""
+        lev_f, lev_c = self.levels[l], self.levels[l + 1]
         F = self.residual(l, with_forcing=False)
-        r = -F if self.s[l] is None else self.s[l] - F
-        ut = restrict(lev_f, lev_c, self.u(l))
-        self.set_u(l + 1, ut)
+        defect = -F if self.s[l] is None else self.s[l] - F
+        u_restricted = restrict(lev_f, lev_c, self.u(l))
+        self.set_u(l + 1, u_restricted)
         self.s[l + 1] = None
-        Fc = self.residual(l + 1, with_forcing=False, u=ut)
-        self.s[l + 1] = Fc + restrict(lev_f, lev_c, r)
+        self.s[l + 1] = (self.residual(l + 1, with_forcing=False, u=u_restricted)
+                         + restrict(lev_f, lev_c, defect))
+        return u_restricted
+
+    def correct(self, l: int, u_restricted):
+        """u_l += P (u_{l+1} - u~): the bilinear prolongation of what the
+        coarse solve changed."""
+        change = self.u(l + 1) - u_restricted
+        self.set_u(l, self.u(l) + prolong(self.levels[l], self.levels[l + 1], change))
+
+    def cycle(self, l: int = 0):
+        """One FAS cycle from level l: nu1 smoothing steps (one on the
+        coarsest level), then, above the coarsest level, the coarse problem,
+        cycle_gamma coarse cycles (1: V-cycle, 2: W-cycle) and the
+        correction."""
+        coarsest = l == len(self.levels) - 1
+        for _ in range(1 if coarsest else self.par.nu1):
+            self.smooth(l)
+        if coarsest:
+            return
+        if self.par.model == RANS:
+            self.transfer_eddy_viscosity(l)
+        u_restricted = self.coarse_problem(l)
         for _ in range(self.par.cycle_gamma):
             self.cycle(l + 1)
-        e = self.u(l + 1) - ut
-        self.set_u(l, self.u(l) + prolong(lev_f, lev_c, e))
+        self.correct(l, u_restricted)
 
     def norm(self, F=None):
         if F is None:
