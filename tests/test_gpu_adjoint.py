@@ -172,6 +172,32 @@ def test_lift_gradient_matches_central_differences():
     assert cl > 0.0 and grad[0] > 0.0        # lift grows with the angle of attack
 
 
+@pytest.mark.xfail(strict=True, reason="frozen turbulence: the adjoint holds the Baldwin-Lomax eddy viscosity "
+                   "at its converged value, so dC_L/dM lacks the model's dependence on M (through the wall "
+                   "viscosity in y+) and the state; measured gaps 1.2e-3 (alpha) and 0.10 (M) relative")
+def test_rans_lift_gradient_against_central_differences():
+    """RANS (Baldwin-Lomax) on the 32 x 16 C-grid: the frozen-turbulence
+    gradient against central differences of converged solutions, in which
+    the eddy viscosity follows the state.  Measured (steps 2e-3 .. 5e-4 in
+    alpha and 3e-6 .. 1e-4 in M agree to 1e-8): dC_L/dalpha 0.082035
+    against 0.081934, dC_L/dM 0.10947 against 0.09928.  Kept as a strict
+    expected failure so that an adjoint that linearises the model shows up
+    here; the frozen gradient itself is checked against the oracle's dense
+    frozen adjoint to 1e-10 (test_lift_gradient_matches_oracle_dense_adjoint)."""
+    alpha, mach = 1.5, 0.5
+
+    def cl(a, m):
+        return _converged_state(a, m, model=1)[1].forces()[0]
+
+    g, st = _converged_state(alpha, mach, model=1)
+    c0, grad, hist, status = st.lift_gradient(3000, 11.0)
+    assert status == 0
+    fd_a = (cl(alpha + 1e-3, mach) - cl(alpha - 1e-3, mach)) / 2e-3
+    fd_m = (cl(alpha, mach + 1e-5) - cl(alpha, mach - 1e-5)) / 2e-5
+    gaps = (abs(grad[0] - fd_a) / abs(fd_a), abs(grad[1] - fd_m) / abs(fd_m))
+    assert gaps[0] <= 1e-5 and gaps[1] <= 1e-5, gaps
+
+
 @pytest.mark.parametrize("model", [0, 1])
 def test_lift_gradient_matches_oracle_dense_adjoint(model):
     alpha, mach = 1.5, 0.5
