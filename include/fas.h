@@ -47,7 +47,7 @@ enum {                                         /* smoother (Table "RK smoothers"
     FAS_AW3 = 0, FAS_PARK3J = 1, FAS_AW5J = 2, FAS_AW51 = 3, FAS_AW52 = 4, FAS_PARK51 = 5
 };
 
-#define FAS_PARAMS_VERSION 2
+#define FAS_PARAMS_VERSION 3
 
 typedef struct {
     int32_t version;        /* FAS_PARAMS_VERSION */
@@ -90,6 +90,15 @@ typedef struct {
      * the cycle that diverged (the last iterate with a finite, not grown
      * norm) */
     double  growth_limit;
+    /* levels of the adjoint GMRES preconditioner (0: all n_levels, or
+     * 1 .. n_levels): 1 is the transposed smoother increment of the fine
+     * level; L adds, for every coarser level l < L, the coarse correction
+     * R^T M_l^T P^T built from the transposes of the FAS transfers
+     * (Section 3: P the bilinear prolongation, R the volume-weighted
+     * agglomeration) and the level's own transposed increment M_l^T (its
+     * SGS blocks and dt* at its state from the last cycle).  The
+     * preconditioner changes the iteration count, not the solution */
+    int32_t adjoint_levels;
 } fas_params;
 
 typedef struct fas_grid_s *fas_grid;     /* opaque, library owned */
@@ -97,7 +106,7 @@ typedef struct fas_state_s *fas_state;   /* opaque, bound to one device and stre
 
 /* Fill *p with defaults: AW3, robust mode (eta 0.5, d 0.5, c* 1e4), the
  * printed convective blocks (viscous_blocks 0), dt_form 1, no stall test,
- * growth limit 1e8. */
+ * growth limit 1e8, an adjoint preconditioner over every level. */
 void fas_params_default(fas_params *p);
 
 /*

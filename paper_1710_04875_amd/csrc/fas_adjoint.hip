@@ -954,6 +954,51 @@ __global__ void k_axpby_p(Lay L, double a, const double *x, double b, const doub
 }
 
 // out = x + a * dts * z (x may be null: out = a * dts * z)
+// Transposes of the FAS transfers (Section 3) for the adjoint's coarse
+// corrections.  The prolongation sets a fine correction to
+// (9 e_parent + 3 e_i-neighbour + 3 e_j-neighbour + e_diagonal) / 16 of the
+// coarse one (the parent standing in for a missing neighbour, the partner
+// across the wake cut for a missing south one); its transpose adds each fine
+// value with those weights to the same four coarse cells (atomically: the
+// coarse cells are shared).
+__global__ void k_adj_prolong_t(Lay Lf, Lay Lc, const double *lf, double *lc) {
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    int i, j;
+    if (!decode(Lf, s, i, j) || !interior(Lf, i, j)) return;
+    const int I = i / 2, J = j / 2;
+    const int In = I + ((i & 1) ? 1 : -1), Jn = J + ((j & 1) ? 1 : -1);
+    const bool vi = In >= 0 && In < Lc.ni, vj = Jn >= 0 && Jn < Lc.nj;
+    const int s0 = Lc.slot(I, J);
+    const int s1 = vi ? Lc.slot(In, J) : s0;
+    int s2 = s0, s3 = s0;
+    if (vj) s2 = Lc.slot(I, Jn);
+    else if (Jn < 0 && cut_col(Lc, I)) s2 = Lc.slot(Lc.ni - 1 - I, 0);
+    if (vi && vj) s3 = Lc.slot(In, Jn);
+    else if (vi && Jn < 0 && cut_col(Lc, In)) s3 = Lc.slot(Lc.ni - 1 - In, 0);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const double v = lf[k * Lf.NS + s] * 0.0625;
+        double *c = lc + (size_t)k * Lc.NS;
+        atomicAdd(c + s0, 9.0 * v);
+        atomicAdd(c + s1, 3.0 * v);
+        atomicAdd(c + s2, 3.0 * v);
+        atomicAdd(c + s3, v);
+    }
+}
+
+// The restriction is the volume-weighted mean of the four children; its
+// transpose adds V_fine / V_coarse times the parent's value to each child.
+__global__ void k_adj_restrict_t(Lay Lf, Lay Lc, const double *geof, const double *geoc, const double *lc,
+                                 double *lf) {
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    int i, j;
+    if (!decode(Lf, s, i, j) || !interior(Lf, i, j)) return;
+    const int sc = Lc.slot(i / 2, j / 2);
+    const double w = geof[G_VOL * Lf.NS + s] / geoc[G_VOL * Lc.NS + sc];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) lf[k * Lf.NS + s] += w * lc[k * Lc.NS + sc];
+}
+
 __global__ void k_adj_update(Lay L, const double *x, double a, const double *dts, const double *z,
                              double *out) {
     const int s = blockIdx.x * blockDim.x + threadIdx.x;
@@ -1081,6 +1126,15 @@ void launch_dot(const Lay &L, const double *a, const double *b, double *red, dou
 void launch_axpby_ptr(const Lay &L, double a, const double *x, double b, const double *y, double *out,
                       hipStream_t st) {
     hipLaunchKernelGGL(k_axpby_p, dim3(nblocks(L.NS)), dim3(TPB), 0, st, L, a, x, b, y, out);
+}
+
+void launch_adj_prolong_t(const Lay &Lf, const Lay &Lc, const double *lf, double *lc, hipStream_t st) {
+    hipLaunchKernelGGL(k_adj_prolong_t, dim3(nblocks(Lf.NS)), dim3(TPB), 0, st, Lf, Lc, lf, lc);
+}
+
+void launch_adj_restrict_t(const Lay &Lf, const Lay &Lc, const double *geof, const double *geoc, const double *lc,
+                           double *lf, hipStream_t st) {
+    hipLaunchKernelGGL(k_adj_restrict_t, dim3(nblocks(Lf.NS)), dim3(TPB), 0, st, Lf, Lc, geof, geoc, lc, lf);
 }
 
 void launch_adj_update(const Lay &L, const double *x, double a, const double *dts, const double *z,

@@ -137,6 +137,7 @@ struct fas_state_s {
            *a_lam0 = nullptr, *a_zeta = nullptr, *a_dFa = nullptr, *a_dFm = nullptr, *a_dcl = nullptr,
            *a_red = nullptr, *a_out = nullptr, *a_basis = nullptr;
     double *a_smv = nullptr;    // smoother VJP: stage states and work vectors (lazy)
+    double *a_mg = nullptr;     // multilevel adjoint preconditioner: 4 arrays per coarse level (lazy)
     double adj_tau = 0.0;       // diagonal of the physical-time term in the adjoint operator
     std::vector<double *> a_ck; // unsteady adjoint: checkpoints and the recomputation window
     // graph-replayed cycles: activity flag (read by every kernel of the
@@ -191,6 +192,7 @@ extern "C" void fas_params_default(fas_params *p) {
     p->stall_window = 0;
     p->stall_orders = 0.0;
     p->growth_limit = 1.0e8;
+    p->adjoint_levels = 0;
 }
 
 // upload the nodes of every level (every 2^l-th node of the fine grid) and
@@ -318,6 +320,7 @@ static fas_status check_params(const fas_params *p, int grid_levels) {
     if (p->dt_form != 0 && p->dt_form != 1) return fail(FAS_EINVAL, "bad dt_form");
     if (p->stall_window < 0 || !(p->stall_orders >= 0.0) || !(p->growth_limit >= 0.0))
         return fail(FAS_EINVAL, "bad stall or growth test");
+    if (p->adjoint_levels < 0 || p->adjoint_levels > p->n_levels) return fail(FAS_EINVAL, "bad adjoint_levels");
     return FAS_OK;
 }
 
@@ -1054,19 +1057,64 @@ void adj_residual(fas_state s, const double *lam) {
 // Krylov space of the adjoint GMRES (restart length)
 constexpr int ADJ_KRYLOV = 200;
 
-// Preconditioner of the adjoint system: the transpose of the primal
-// increment operator, D_t P^-T (AW: increment P^-1 D_t r) or P^-T D_t
-// (pARK: increment D_t P^-1 r).  out = M v; uses a_jt as scratch.
+// Transposed increment operator of level l: D_t P^-T (AW: increment
+// P^-1 D_t r) or P^-T D_t (pARK: increment D_t P^-1 r), with the level's
+// blocks and dt*; tmp and zeta are work arrays of the level.
+void increment_t(Engine &e, const LevelDev &dl, const double *in, double *tmp, double *zeta, double *out) {
+    if (e.sc.aw) {
+        launch_sgs_transpose(dl.L, dl.blk, in, zeta, tmp, e.fp32, e.st);
+        launch_adj_update(dl.L, nullptr, 1.0, dl.dts, tmp, out, e.st);
+    } else {
+        launch_adj_update(dl.L, nullptr, 1.0, dl.dts, in, tmp, e.st);
+        launch_sgs_transpose(dl.L, dl.blk, tmp, zeta, out, e.fp32, e.st);
+    }
+}
+
+int adjoint_levels(fas_state s) { return s->p.adjoint_levels > 0 ? std::min(s->p.adjoint_levels, s->nlev) : s->nlev; }
+
+// coarse level l's arrays of the multilevel preconditioner: restricted
+// residual, correction, and the two sweep work arrays
+double *mg_array(fas_state s, int l, int k) {
+    size_t off = 0;
+    for (int m = 1; m < l; ++m) off += (size_t)16 * s->lv[m].L.NS;
+    return s->a_mg + off + (size_t)k * 4 * s->lv[l].L.NS;
+}
+
+fas_status ensure_adjoint_mg(fas_state s, int L) {
+    if (s->a_mg || L < 2) return FAS_OK;
+    size_t n = 0;
+    for (int m = 1; m < s->nlev; ++m) n += (size_t)16 * s->lv[m].L.NS;
+    HIPCHK(hipMalloc(&s->a_mg, n * sizeof(double)));
+    s->allocs.push_back(s->a_mg);
+    launch_zero(s->a_mg, n, s->e.st);
+    return FAS_OK;
+}
+
+// Preconditioner of the adjoint system (right preconditioning of the
+// GMRES): out = M v with M = M_0^T + sum over coarse levels of
+// R_0^T .. R_{l-1}^T M_l^T P_{l-1}^T .. P_0^T, the additive multilevel
+// form of the FAS cycle's coarse corrections transposed (no coarse
+// Jacobian is needed: each level contributes its transposed increment).
+// With adjoint_levels 1 it is the fine level's transposed increment.  The
+// fine part uses a_z (AW) or a_jt (pARK) as scratch; out may be a_z.
 void adj_precond(fas_state s, const double *v, double *out) {
     Engine &e = s->e;
-    const LevelDev &d = s->lv[0];
-    if (e.sc.aw) {
-        launch_sgs_transpose(d.L, d.blk, v, s->a_zeta, s->a_z, e.fp32, e.st);
-        launch_adj_update(d.L, nullptr, 1.0, d.dts, s->a_z, out, e.st);
-    } else {
-        launch_adj_update(d.L, nullptr, 1.0, d.dts, v, s->a_jt, e.st);
-        launch_sgs_transpose(d.L, d.blk, s->a_jt, s->a_zeta, out, e.fp32, e.st);
+    increment_t(e, s->lv[0], v, e.sc.aw ? s->a_z : s->a_jt, s->a_zeta, out);
+    const int L = adjoint_levels(s);
+    if (L < 2) return;
+    for (int l = 1; l < L; ++l) {                 // g_l = P^T g_{l-1}, g_0 = v
+        double *g = mg_array(s, l, 0);
+        launch_zero(g, (size_t)4 * s->lv[l].L.NS, e.st);
+        launch_adj_prolong_t(s->lv[l - 1].L, s->lv[l].L, l == 1 ? v : mg_array(s, l - 1, 0), g, e.st);
     }
+    for (int l = L - 1; l >= 1; --l) {            // w_l = M_l^T g_l + R^T w_{l+1}
+        double *w = mg_array(s, l, 1);
+        increment_t(e, s->lv[l], mg_array(s, l, 0), mg_array(s, l, 2), mg_array(s, l, 3), w);
+        if (l + 1 < L)
+            launch_adj_restrict_t(s->lv[l].L, s->lv[l + 1].L, s->lv[l].geo, s->lv[l + 1].geo, mg_array(s, l + 1, 1),
+                                  w, e.st);
+    }
+    launch_adj_restrict_t(s->lv[0].L, s->lv[1].L, s->lv[0].geo, s->lv[1].geo, mg_array(s, 1, 1), out, e.st);
 }
 
 // (dF/du)^T lam = g on the padded work arrays (a_g, a_lam) by GMRES(200)
@@ -1094,6 +1142,11 @@ fas_status adj_solve(fas_state s, int max_iter, double drop, double *hist, int *
     double *d_red = d_h + (M + 1);                         // (M + 1) * RB partials
     std::vector<double> hh(M + 1), h2(M + 1);
     auto vb = [&](int k) { return s->a_basis + (size_t)k * V; };
+    // coarse levels of the preconditioner: blocks and dt* at their current
+    // states (the last cycle's coarse solutions)
+    const int Lmg = adjoint_levels(s);
+    STCHK(ensure_adjoint_mg(s, Lmg));
+    for (int l = 1; l < Lmg; ++l) prepare_iteration(e, l);
     prepare_iteration(e, 0);
     adj_residual(s, s->a_lam);
     double beta = 0.0;

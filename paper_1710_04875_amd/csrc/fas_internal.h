@@ -266,6 +266,11 @@ int dot_scratch_size();
 void launch_dot(const Lay &L, const double *a, const double *b, double *red, double *out, hipStream_t st);
 void launch_axpby_ptr(const Lay &L, double a, const double *x, double b, const double *y, double *out,
                       hipStream_t st);
+// lc += P^T lf (P: bilinear prolongation from Lc to Lf); lf += R^T lc (R:
+// volume-weighted agglomeration from Lf to Lc)
+void launch_adj_prolong_t(const Lay &Lf, const Lay &Lc, const double *lf, double *lc, hipStream_t st);
+void launch_adj_restrict_t(const Lay &Lf, const Lay &Lc, const double *geof, const double *geoc, const double *lc,
+                           double *lf, hipStream_t st);
 void launch_adj_update(const Lay &L, const double *x, double a, const double *dts, const double *z,
                        double *out, hipStream_t st);
 void launch_zero(double *p, size_t n, hipStream_t st);

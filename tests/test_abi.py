@@ -46,7 +46,8 @@ def test_params_layout_and_defaults():
     # the printed convective blocks, the directional pseudo time step, no
     # stall test, divergence beyond a 1e8 growth
     assert (p.viscous_blocks, p.dt_form, p.stall_window, p.growth_limit) == (0, 1, 0, 1.0e8)
-    assert ctypes.sizeof(fas._Params) == 152
+    assert p.adjoint_levels == 0             # adjoint preconditioner over every level
+    assert ctypes.sizeof(fas._Params) == 160
     # the binding's defaults are the library's
     dflt = fas.Params()
     for name, _ in fas._Params._fields_:

@@ -172,6 +172,26 @@ def test_lift_gradient_matches_central_differences():
     assert cl > 0.0 and grad[0] > 0.0        # lift grows with the angle of attack
 
 
+def test_multilevel_adjoint_preconditioner():
+    """The adjoint GMRES preconditioned over every level (the default) and
+    by the fine level's transposed increment alone reach the same gradient
+    (RANS 32 x 16 C-grid, 3 levels, primal converged to 12 orders); the
+    multilevel preconditioner needs fewer iterations for a 10-order drop."""
+    import dataclasses
+    g, st = _converged_state(1.5, 0.5, model=1)
+    p = st.params
+    out = {}
+    for levels in (1, 0):
+        st.set_params(dataclasses.replace(p, adjoint_levels=levels))
+        cl, grad, hist, status = st.lift_gradient(3000, 10.0)
+        assert status == 0, levels
+        out[levels] = (np.asarray(grad), len(hist) - 1)
+    g1, n1 = out[1]
+    g3, n3 = out[0]
+    assert np.abs(g3 - g1).max() <= 1e-8 * np.abs(g1).max(), (g1, g3)
+    assert n3 < n1, (n1, n3)
+
+
 @pytest.mark.xfail(strict=True, reason="frozen turbulence: the adjoint holds the Baldwin-Lomax eddy viscosity "
                    "at its converged value, so dC_L/dM lacks the model's dependence on M (through the wall "
                    "viscosity in y+) and the state; measured gaps 1.2e-3 (alpha) and 0.10 (M) relative")
