@@ -5,6 +5,7 @@
 #include "fas_internal.h"
 #include "fas_dfa.h"
 
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -393,6 +394,7 @@ static BLev make_blev(const std::vector<Lay> &lays, const LevelDev *dV, const Ph
     B.k.act = act;
     B.k.cyc = cyc;
     B.k.tile0 = nullptr;
+    B.k.order = nullptr;
     B.n = (int)lays.size();
     B.k.n = B.n;
     B.ntiles = 0;
@@ -1771,12 +1773,20 @@ extern "C" fas_status fas_batch_create(int32_t n, const fas_state *states, void 
         return cleanup(fail(FAS_ENOMEM, "pinned allocation failed"));
     launch_fill_int(b->d_act, n, 1, e.st);
     launch_fill_int(e.d_rb, n, 0, e.st);
-    // per level the first residual tile of each case (n + 1 entries)
+    // per level the first residual tile of each case (n + 1 entries), then
+    // the cases by descending hyperplane-chain length (ni + nj) for the
+    // sweep launches
     int *dtiles = nullptr;
-    if (hipMalloc(reinterpret_cast<void **>(&dtiles), (size_t)e.nlev * (n + 1) * sizeof(int)) != hipSuccess)
+    if (hipMalloc(reinterpret_cast<void **>(&dtiles), ((size_t)e.nlev * (n + 1) + n) * sizeof(int)) != hipSuccess)
         return cleanup(fail(FAS_ENOMEM, "batch allocation failed"));
     b->allocs.push_back(dtiles);
-    std::vector<int> htiles((size_t)e.nlev * (n + 1));
+    std::vector<int> htiles((size_t)e.nlev * (n + 1) + n);
+    int *horder = htiles.data() + (size_t)e.nlev * (n + 1);
+    for (int c = 0; c < n; ++c) horder[c] = c;
+    std::stable_sort(horder, horder + n, [&](int a, int b2) {
+        const Lay &La = states[a]->lv[0].L, &Lb = states[b2]->lv[0].L;
+        return La.ni + La.nj > Lb.ni + Lb.nj;
+    });
     for (int l = 0; l < e.nlev; ++l) {
         std::vector<Lay> lays;
         for (int c = 0; c < n; ++c) lays.push_back(states[c]->lv[l].L);
@@ -1785,6 +1795,7 @@ extern "C" fas_status fas_batch_create(int32_t n, const fas_state *states, void 
         t0[0] = 0;
         for (int c = 0; c < n; ++c) t0[c + 1] = t0[c] + residual_tiles(lays[c]);
         e.lev.back().k.tile0 = dtiles + (size_t)l * (n + 1);
+        e.lev.back().k.order = dtiles + (size_t)e.nlev * (n + 1);
         e.lev.back().ntiles = t0[n];
     }
     if (hipMemcpy(dtiles, htiles.data(), htiles.size() * sizeof(int), hipMemcpyHostToDevice) != hipSuccess)

@@ -150,6 +150,7 @@ struct BK {
     const int *act;       // [n] 0 = skip the case; nullptr = all active
     const int *cyc;       // [n] completed FAS cycles (c* ramp)
     const int *tile0;     // [n + 1] first residual tile of each case (batches), nullptr for one state
+    const int *order;     // [n] cases by descending chain length (sweep launches), nullptr: in turn
     int n;                // cases
 };
 

@@ -1587,7 +1587,11 @@ __global__ __launch_bounds__(NT) void k_sgs4(BK bk, SweepArgs a) {
     LevelDev dv;
     const int nbands = BANDED ? a.bands : 1;
     const int band = BANDED ? (int)blockIdx.x % nbands : 0;
-    if (!take(bk, BANDED ? (int)blockIdx.x / nbands : (int)blockIdx.x, dv)) return;
+    // the longest hyperplane chains first: workgroups are placed on CUs in
+    // turn, so a long chain's bands share their CUs with bands of shorter
+    // cases, which finish early
+    const int cidx = BANDED ? (int)blockIdx.x / nbands : (int)blockIdx.x;
+    if (!take(bk, bk.order != nullptr ? bk.order[cidx] : cidx, dv)) return;
     const Lay L = dv.L;
     const int ni = L.ni, nj = L.nj, NS = L.NS, NJ = L.NJ, nw = L.nw;
     const int j0 = band * NR;                 // first row of the band
@@ -1965,7 +1969,11 @@ __global__ __launch_bounds__(64 * NW) void k_sgs8(BK bk, SweepArgs a) {
     LevelDev dv;
     const int nbands = BANDED ? a.bands : 1;
     const int band = BANDED ? (int)blockIdx.x % nbands : 0;
-    if (!take(bk, BANDED ? (int)blockIdx.x / nbands : (int)blockIdx.x, dv)) return;
+    // the longest hyperplane chains first: workgroups are placed on CUs in
+    // turn, so a long chain's bands share their CUs with bands of shorter
+    // cases, which finish early
+    const int cidx = BANDED ? (int)blockIdx.x / nbands : (int)blockIdx.x;
+    if (!take(bk, bk.order != nullptr ? bk.order[cidx] : cidx, dv)) return;
     const Lay L = dv.L;
     const int ni = L.ni, nj = L.nj, NS = L.NS, NJ = L.NJ, nw = L.nw;
     const int j0 = band * NR;
