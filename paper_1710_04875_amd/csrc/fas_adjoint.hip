@@ -812,104 +812,64 @@ __global__ __launch_bounds__(TPB) void k_forces(Lay L, const double *geo, const 
 //     ascending:  zeta_c = r_c  - sum_{nb earlier} M_{nb->c}^T zeta_nb
 //     descending: xi_c   = zeta_c - sum_{nb later} M_{nb->c}^T xi_nb,
 //                 x_c    = D_c^-T xi_c,
-// where M_{nb->c} is neighbour nb's block toward c.  One thread per row,
-// hyperplane wavefront as in the primal sweep.
+// where M_{nb->c} is neighbour nb's block toward c.  Both passes are the
+// primal sweep's recurrences once cell c holds, in its own slot for the
+// direction of nb, the block M_{nb->c}^T: k_blocks_t writes that array
+// (the west slot of c holds the transposed east block of its west
+// neighbour, and so on; on the wake cut of a C-grid, row-0 cells couple to
+// their partner across the cut, whose south block is the one toward c), so
+// the banded hyperplane sweep runs the solve with g = r and y = zeta, and
+// k_dinv_t finishes with x = D^-T xi.
 template <typename T>
-__device__ inline void mtv_sub(const T *blk, int b, int NS, int s, const T v[4], T out[4]) {
+__device__ inline void put_transposed(const T *blk, int bsrc, int ssrc, bool on, T *bt, int bdst, int NS, int s) {
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-        T a = out[r];
+    for (int r = 0; r < 4; ++r)
 #pragma unroll
-        for (int k = 0; k < 4; ++k) a = fma(-blk[BL<T>::at(b, NS, s, k, r)], v[k], a);
-        out[r] = a;
+        for (int c = 0; c < 4; ++c)
+            bt[BL<T>::at(bdst, NS, s, r, c)] = on ? blk[BL<T>::at(bsrc, NS, ssrc, c, r)] : (T)0;
+}
+
+template <typename T>
+__global__ __launch_bounds__(TPB) void k_blocks_t(Lay L, const T *blk, T *bt) {
+    const BlockXY cb = xcd_block();
+    int s, i, j;
+    if (!interior_cell(L, cb.x * blockDim.x + threadIdx.x, s, i, j)) return;
+    const int ni = L.ni, nj = L.nj, NS = L.NS, NJ = L.NJ, nw = L.nw;
+    put_transposed(blk, B_M0 + 1, i > 0 ? s - NJ : s, i > 0, bt, B_M0 + 0, NS, s);            // west: its east block
+    put_transposed(blk, B_M0 + 0, i < ni - 1 ? s + NJ : s, i < ni - 1, bt, B_M0 + 1, NS, s);  // east: its west block
+    const bool cut = j == 0 && L.topo == 1 && (i < nw || i >= ni - nw);
+    const int ss = j > 0 ? s - NJ - 1 : cut ? L.slot(ni - 1 - i, 0) : s;
+    put_transposed(blk, j > 0 ? B_M0 + 3 : B_M0 + 2, ss, j > 0 || cut, bt, B_M0 + 2, NS, s);  // south (or partner)
+    put_transposed(blk, B_M0 + 2, j < nj - 1 ? s + NJ + 1 : s, j < nj - 1, bt, B_M0 + 3, NS, s);  // north: its south block
+}
+
+// x = D^-T xi over the interior, in the blocks' precision
+template <typename T>
+__global__ __launch_bounds__(TPB) void k_dinv_t(Lay L, const T *blk, const double *xi, double *x) {
+    const BlockXY cb = xcd_block();
+    int s, i, j;
+    if (!interior_cell(L, cb.x * blockDim.x + threadIdx.x, s, i, j)) return;
+    const int NS = L.NS;
+    T v[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) v[k] = (T)xi[k * NS + s];
+#pragma unroll
+    for (int rr = 0; rr < 4; ++rr) {
+        T acc = (T)0;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) acc = fma(blk[BL<T>::at(B_DINV, NS, s, k, rr)], v[k], acc);
+        x[rr * NS + s] = (double)acc;
     }
 }
 
-template <typename T, int BS>
-__global__ __launch_bounds__(BS) void k_sgs_t(Lay L, const T *blk, const double *r, T *zeta, double *x) {
-    __shared__ T nbuf[2][BS][4];
-    extern __shared__ unsigned char smem[];
-    T *row0 = reinterpret_cast<T *>(smem);          // n_wake x 4
-    const int j = threadIdx.x;
-    const int ni = L.ni, nj = L.nj, NS = L.NS, nw = L.nw, NJ = L.NJ;
-    const bool active = j < nj;
-    const int H = ni + nj - 1;
-    T zw[4] = {0, 0, 0, 0};
-    for (int h = 0; h < H; ++h) {
-        const int i = h - j;
-        if (active && i >= 0 && i < ni) {
-            const int s = L.slot(i, j);
-            T v[4];
+// the sweep's input g = r in the sweep precision (interior cells)
+template <typename T>
+__global__ __launch_bounds__(TPB) void k_to_sweep(Lay L, const double *r, T *g) {
+    const BlockXY cb = xcd_block();
+    int s, i, j;
+    if (!interior_cell(L, cb.x * blockDim.x + threadIdx.x, s, i, j)) return;
 #pragma unroll
-            for (int k = 0; k < 4; ++k) v[k] = (T)r[k * NS + s];
-            if (i > 0) mtv_sub(blk, B_M0 + 1, NS, s - NJ, zw, v);          // west cell's east block
-            if (j > 0) {
-                T zs[4];
-#pragma unroll
-                for (int k = 0; k < 4; ++k) zs[k] = nbuf[(h - 1) & 1][j - 1][k];
-                mtv_sub(blk, B_M0 + 3, NS, s - NJ - 1, zs, v);             // south cell's north block
-            } else if (L.topo == 1 && i >= ni - nw) {
-                const int p = ni - 1 - i;                                   // earlier partner
-                T zp[4];
-#pragma unroll
-                for (int k = 0; k < 4; ++k) zp[k] = row0[p * 4 + k];
-                mtv_sub(blk, B_M0 + 2, NS, L.slot(p, 0), zp, v);
-            }
-#pragma unroll
-            for (int k = 0; k < 4; ++k) {
-                nbuf[h & 1][j][k] = v[k];
-                zeta[k * NS + s] = v[k];
-                zw[k] = v[k];
-            }
-            if (j == 0 && L.topo == 1 && i < nw) {
-#pragma unroll
-                for (int k = 0; k < 4; ++k) row0[i * 4 + k] = v[k];
-            }
-        }
-        __syncthreads();
-    }
-    T xe[4] = {0, 0, 0, 0};
-    for (int h = H - 1; h >= 0; --h) {
-        const int i = h - j;
-        if (active && i >= 0 && i < ni) {
-            const int s = L.slot(i, j);
-            T v[4];
-#pragma unroll
-            for (int k = 0; k < 4; ++k) v[k] = zeta[k * NS + s];
-            if (i < ni - 1) mtv_sub(blk, B_M0 + 0, NS, s + NJ, xe, v);     // east cell's west block
-            if (j < nj - 1) {
-                T xn[4];
-#pragma unroll
-                for (int k = 0; k < 4; ++k) xn[k] = nbuf[(h + 1) & 1][j + 1][k];
-                mtv_sub(blk, B_M0 + 2, NS, s + NJ + 1, xn, v);             // north cell's south block
-            }
-            if (j == 0 && L.topo == 1 && i < nw) {
-                const int q = ni - 1 - i;                                   // later partner
-                T xq[4];
-#pragma unroll
-                for (int k = 0; k < 4; ++k) xq[k] = row0[(q - (ni - nw)) * 4 + k];
-                mtv_sub(blk, B_M0 + 2, NS, L.slot(q, 0), xq, v);
-            }
-#pragma unroll
-            for (int k = 0; k < 4; ++k) {
-                nbuf[h & 1][j][k] = v[k];
-                xe[k] = v[k];
-            }
-            if (j == 0 && L.topo == 1 && i >= ni - nw) {
-#pragma unroll
-                for (int k = 0; k < 4; ++k) row0[(i - (ni - nw)) * 4 + k] = v[k];
-            }
-            // x = D^-T xi
-#pragma unroll
-            for (int rr = 0; rr < 4; ++rr) {
-                T acc = (T)0;
-#pragma unroll
-                for (int k = 0; k < 4; ++k) acc = fma(blk[BL<T>::at(B_DINV, NS, s, k, rr)], v[k], acc);
-                x[rr * NS + s] = (double)acc;
-            }
-        }
-        __syncthreads();
-    }
+    for (int k = 0; k < 4; ++k) g[k * L.NS + s] = (T)r[k * L.NS + s];
 }
 
 // sum of squares of all four components over the interior, and dot
@@ -1096,24 +1056,22 @@ void launch_forces(const Lay &L, const double *geo, const double *u, const Phys 
     hipLaunchKernelGGL(k_forces, dim3(1), dim3(TPB), 0, st, L, geo, u, ph, out, dcl);
 }
 
-template <typename T>
-static void sgs_t_dispatch(const Lay &L, const void *blk, const double *r, void *zeta, double *x,
-                           hipStream_t st) {
-    const size_t shm = (size_t)(L.nw > 0 ? L.nw : 1) * 4 * sizeof(T);
-    if (L.nj <= 64)
-        hipLaunchKernelGGL((k_sgs_t<T, 64>), dim3(1), dim3(64), shm, st, L, (const T *)blk, r, (T *)zeta, x);
-    else if (L.nj <= 128)
-        hipLaunchKernelGGL((k_sgs_t<T, 128>), dim3(1), dim3(128), shm, st, L, (const T *)blk, r, (T *)zeta, x);
-    else if (L.nj <= 256)
-        hipLaunchKernelGGL((k_sgs_t<T, 256>), dim3(1), dim3(256), shm, st, L, (const T *)blk, r, (T *)zeta, x);
-    else
-        hipLaunchKernelGGL((k_sgs_t<T, 512>), dim3(1), dim3(512), shm, st, L, (const T *)blk, r, (T *)zeta, x);
+void launch_blocks_t(const Lay &L, const void *blk, void *bt, int fp32, hipStream_t st) {
+    const dim3 g(nblocks(L.ni * L.nj)), b(TPB);
+    if (fp32) hipLaunchKernelGGL(k_blocks_t<float>, g, b, 0, st, L, (const float *)blk, (float *)bt);
+    else hipLaunchKernelGGL(k_blocks_t<double>, g, b, 0, st, L, (const double *)blk, (double *)bt);
 }
 
-void launch_sgs_transpose(const Lay &L, const void *blk, const double *r, void *zeta, double *x, int fp32,
-                          hipStream_t st) {
-    if (fp32) sgs_t_dispatch<float>(L, blk, r, zeta, x, st);
-    else sgs_t_dispatch<double>(L, blk, r, zeta, x, st);
+void launch_to_sweep(const Lay &L, const double *r, void *g, int fp32, hipStream_t st) {
+    const dim3 gr(nblocks(L.ni * L.nj)), b(TPB);
+    if (fp32) hipLaunchKernelGGL(k_to_sweep<float>, gr, b, 0, st, L, r, (float *)g);
+    else hipLaunchKernelGGL(k_to_sweep<double>, gr, b, 0, st, L, r, (double *)g);
+}
+
+void launch_dinv_t(const Lay &L, const void *blk, const double *xi, double *x, int fp32, hipStream_t st) {
+    const dim3 g(nblocks(L.ni * L.nj)), b(TPB);
+    if (fp32) hipLaunchKernelGGL(k_dinv_t<float>, g, b, 0, st, L, (const float *)blk, xi, x);
+    else hipLaunchKernelGGL(k_dinv_t<double>, g, b, 0, st, L, (const double *)blk, xi, x);
 }
 
 int dot_scratch_size() { return RB; }

@@ -115,6 +115,17 @@ void engine_release_events(Engine &e) {
 
 }  // namespace
 
+// Transposed SGS solve of one level (adjoint): the level's neighbour blocks
+// transposed into the slots of the cells they act on, the sweep's input and
+// forward output in the sweep precision, its backward output in FP64, and
+// a launch descriptor of the primal sweep over these arrays
+struct TSweep {
+    void *bt = nullptr, *g = nullptr, *y = nullptr;
+    double *xi = nullptr;
+    LevelDev host;
+    BLev B;
+};
+
 struct fas_state_s {
     fas_grid g;
     fas_params p;
@@ -135,10 +146,11 @@ struct fas_state_s {
     // adjoint work arrays (padded fine level), allocated on first use
     double *a_gbar = nullptr;   // metric-plane adjoint of the node sensitivities (lazy)
     double *a_lam = nullptr, *a_g = nullptr, *a_r = nullptr, *a_z = nullptr, *a_jt = nullptr,
-           *a_lam0 = nullptr, *a_zeta = nullptr, *a_dFa = nullptr, *a_dFm = nullptr, *a_dcl = nullptr,
+           *a_lam0 = nullptr, *a_dFa = nullptr, *a_dFm = nullptr, *a_dcl = nullptr,
            *a_red = nullptr, *a_out = nullptr, *a_basis = nullptr;
     double *a_smv = nullptr;    // smoother VJP: stage states and work vectors (lazy)
-    double *a_mg = nullptr;     // multilevel adjoint preconditioner: 4 arrays per coarse level (lazy)
+    double *a_mg = nullptr;     // multilevel adjoint preconditioner: 3 arrays per coarse level (lazy)
+    std::vector<TSweep> a_ts;   // transposed SGS solve per level (lazy)
     double adj_tau = 0.0;       // diagonal of the physical-time term in the adjoint operator
     std::vector<double *> a_ck; // unsteady adjoint: checkpoints and the recomputation window
     // graph-replayed cycles: activity flag (read by every kernel of the
@@ -1015,15 +1027,14 @@ namespace {
 fas_status ensure_adjoint(fas_state s) {
     if (s->a_lam) return FAS_OK;
     const size_t V = (size_t)4 * s->lv[0].L.NS;
-    const size_t n = 10 * V + dot_scratch_size() + 16;
+    const size_t n = 9 * V + dot_scratch_size() + 16;
     double *b = nullptr;
     HIPCHK(hipMalloc(&b, n * sizeof(double)));
     s->allocs.push_back(b);
     launch_zero(b, n, s->e.st);
-    double **f[10] = {&s->a_lam, &s->a_g, &s->a_r, &s->a_z, &s->a_jt, &s->a_lam0, &s->a_zeta,
-                      &s->a_dFa, &s->a_dFm, &s->a_dcl};
-    for (int k = 0; k < 10; ++k) *f[k] = b + k * V;
-    s->a_red = b + 10 * V;
+    double **f[9] = {&s->a_lam, &s->a_g, &s->a_r, &s->a_z, &s->a_jt, &s->a_lam0, &s->a_dFa, &s->a_dFm, &s->a_dcl};
+    for (int k = 0; k < 9; ++k) *f[k] = b + k * V;
+    s->a_red = b + 9 * V;
     s->a_out = s->a_red + dot_scratch_size();
     HIPCHK(hipGetLastError());
     return FAS_OK;
@@ -1059,33 +1070,92 @@ void adj_residual(fas_state s, const double *lam) {
 // Krylov space of the adjoint GMRES (restart length)
 constexpr int ADJ_KRYLOV = 200;
 
+// Arrays of level l's transposed SGS solve (allocated on first use)
+fas_status ensure_tsweep(fas_state s, int l) {
+    if (s->a_ts.empty()) s->a_ts.resize(s->nlev);
+    TSweep &t = s->a_ts[l];
+    if (t.bt) return FAS_OK;
+    const LevelDev &d = s->lv[l];
+    const size_t NS = d.L.NS, es = s->e.fp32 ? sizeof(float) : sizeof(double);
+    const size_t nb = (size_t)BLK_NPLANES * NS * es, nv = 4 * NS * es;
+    const size_t n = nb + 2 * nv + 4 * NS * sizeof(double) + sizeof(LevelDev);
+    char *p = nullptr;
+    HIPCHK(hipMalloc(&p, n));
+    s->allocs.push_back(p);
+    HIPCHK(hipMemsetAsync(p, 0, n, s->e.st));
+    t.bt = p;
+    t.g = p + nb;
+    t.y = p + nb + nv;
+    t.xi = reinterpret_cast<double *>(p + nb + 2 * nv);
+    LevelDev *dv = reinterpret_cast<LevelDev *>(p + nb + 2 * nv + 4 * NS * sizeof(double));
+    t.host = d;
+    t.host.blk = t.bt;
+    t.host.g = t.g;
+    t.host.y = t.y;
+    t.host.acc = t.xi;
+    HIPCHK(hipMemcpyAsync(dv, &t.host, sizeof(LevelDev), hipMemcpyHostToDevice, s->e.st));
+    HIPCHK(hipStreamSynchronize(s->e.st));
+    t.B = s->e.lev[l];
+    t.B.k.V = dv;
+    t.B.k.act = nullptr;
+    t.B.k.tile0 = nullptr;
+    t.B.k.order = nullptr;
+    t.B.k.n = 1;
+    t.B.n = 1;
+    return FAS_OK;
+}
+
+// level l's transposed blocks from its current blocks; called after every
+// preparation of the level's blocks that a transposed solve then uses
+fas_status transpose_blocks(fas_state s, int l) {
+    STCHK(ensure_tsweep(s, l));
+    const LevelDev &d = s->lv[l];
+    launch_blocks_t(d.L, d.blk, s->a_ts[l].bt, s->e.fp32, s->e.st);
+    return FAS_OK;
+}
+
+// x = P^-T r on level l's interior (transpose_blocks first)
+void sgs_transpose(fas_state s, int l, const double *r, double *x) {
+    Engine &e = s->e;
+    const LevelDev &d = s->lv[l];
+    const TSweep &t = s->a_ts[l];
+    launch_to_sweep(d.L, r, t.g, e.fp32, e.st);
+    SweepArgs a;
+    std::memset(&a, 0, sizeof(a));
+    a.xout_acc = 1;
+    launch_sgs(t.B, a, e.fp32, e.st);
+    launch_dinv_t(d.L, d.blk, t.xi, x, e.fp32, e.st);
+}
+
 // Transposed increment operator of level l: D_t P^-T (AW: increment
 // P^-1 D_t r) or P^-T D_t (pARK: increment D_t P^-1 r), with the level's
-// blocks and dt*; tmp and zeta are work arrays of the level.
-void increment_t(Engine &e, const LevelDev &dl, const double *in, double *tmp, double *zeta, double *out) {
+// blocks and dt*; tmp is a work array of the level.
+void increment_t(fas_state s, int l, const double *in, double *tmp, double *out) {
+    const LevelDev &dl = s->lv[l];
+    Engine &e = s->e;
     if (e.sc.aw) {
-        launch_sgs_transpose(dl.L, dl.blk, in, zeta, tmp, e.fp32, e.st);
+        sgs_transpose(s, l, in, tmp);
         launch_adj_update(dl.L, nullptr, 1.0, dl.dts, tmp, out, e.st);
     } else {
         launch_adj_update(dl.L, nullptr, 1.0, dl.dts, in, tmp, e.st);
-        launch_sgs_transpose(dl.L, dl.blk, tmp, zeta, out, e.fp32, e.st);
+        sgs_transpose(s, l, tmp, out);
     }
 }
 
 int adjoint_levels(fas_state s) { return s->p.adjoint_levels > 0 ? std::min(s->p.adjoint_levels, s->nlev) : s->nlev; }
 
 // coarse level l's arrays of the multilevel preconditioner: restricted
-// residual, correction, and the two sweep work arrays
+// residual, correction, and the increment's work array
 double *mg_array(fas_state s, int l, int k) {
     size_t off = 0;
-    for (int m = 1; m < l; ++m) off += (size_t)16 * s->lv[m].L.NS;
+    for (int m = 1; m < l; ++m) off += (size_t)12 * s->lv[m].L.NS;
     return s->a_mg + off + (size_t)k * 4 * s->lv[l].L.NS;
 }
 
 fas_status ensure_adjoint_mg(fas_state s, int L) {
     if (s->a_mg || L < 2) return FAS_OK;
     size_t n = 0;
-    for (int m = 1; m < s->nlev; ++m) n += (size_t)16 * s->lv[m].L.NS;
+    for (int m = 1; m < s->nlev; ++m) n += (size_t)12 * s->lv[m].L.NS;
     HIPCHK(hipMalloc(&s->a_mg, n * sizeof(double)));
     s->allocs.push_back(s->a_mg);
     launch_zero(s->a_mg, n, s->e.st);
@@ -1101,7 +1171,7 @@ fas_status ensure_adjoint_mg(fas_state s, int L) {
 // fine part uses a_z (AW) or a_jt (pARK) as scratch; out may be a_z.
 void adj_precond(fas_state s, const double *v, double *out) {
     Engine &e = s->e;
-    increment_t(e, s->lv[0], v, e.sc.aw ? s->a_z : s->a_jt, s->a_zeta, out);
+    increment_t(s, 0, v, e.sc.aw ? s->a_z : s->a_jt, out);
     const int L = adjoint_levels(s);
     if (L < 2) return;
     for (int l = 1; l < L; ++l) {                 // g_l = P^T g_{l-1}, g_0 = v
@@ -1111,7 +1181,7 @@ void adj_precond(fas_state s, const double *v, double *out) {
     }
     for (int l = L - 1; l >= 1; --l) {            // w_l = M_l^T g_l + R^T w_{l+1}
         double *w = mg_array(s, l, 1);
-        increment_t(e, s->lv[l], mg_array(s, l, 0), mg_array(s, l, 2), mg_array(s, l, 3), w);
+        increment_t(s, l, mg_array(s, l, 0), mg_array(s, l, 2), w);
         if (l + 1 < L)
             launch_adj_restrict_t(s->lv[l].L, s->lv[l + 1].L, s->lv[l].geo, s->lv[l + 1].geo, mg_array(s, l + 1, 1),
                                   w, e.st);
@@ -1150,6 +1220,7 @@ fas_status adj_solve(fas_state s, int max_iter, double drop, double *hist, int *
     STCHK(ensure_adjoint_mg(s, Lmg));
     for (int l = 1; l < Lmg; ++l) prepare_iteration(e, l);
     prepare_iteration(e, 0);
+    for (int l = 0; l < Lmg; ++l) STCHK(transpose_blocks(s, l));
     adj_residual(s, s->a_lam);
     double beta = 0.0;
     STCHK(fine_dot(s, s->a_r, s->a_r, &beta));
@@ -1307,6 +1378,7 @@ extern "C" fas_status fas_vjp_smooth(fas_state s, const double *lam, double *out
     }
     // the state keeps its solution
     launch_axpby(B, 1.0, FLD_U0, 0.0, FLD_NONE, FLD_U, e.st);
+    STCHK(transpose_blocks(s, 0));
     // reverse sweep
     launch_unpack(d.L, lam, w, 4, e.st);
     launch_zero(ab, V, e.st);
@@ -1321,13 +1393,7 @@ extern "C" fas_status fas_vjp_smooth(fas_state s, const double *lam, double *out
         }
         launch_axpby_ptr(d.L, 1.0, acc, 1.0, w, acc, e.st);
         launch_axpby_ptr(d.L, -e.sc.alpha[i - 1], w, 0.0, nullptr, xb, e.st);
-        if (e.sc.aw) {
-            launch_sgs_transpose(d.L, d.blk, xb, s->a_zeta, s->a_z, e.fp32, e.st);
-            launch_adj_update(d.L, nullptr, 1.0, d.dts, s->a_z, rb, e.st);
-        } else {
-            launch_adj_update(d.L, nullptr, 1.0, d.dts, xb, s->a_z, e.st);
-            launch_sgs_transpose(d.L, d.blk, s->a_z, s->a_zeta, rb, e.fp32, e.st);
-        }
+        increment_t(s, 0, xb, s->a_z, rb);
         launch_zero(w, V, e.st);
         launch_vjp(d.L, d.geo, stage[i - 1], d.mut, s->ph, rb, w, e.st, 1);
         launch_axpby_ptr(d.L, 1.0, ab, 1.0, rb, ab, e.st);
@@ -1396,8 +1462,9 @@ extern "C" fas_status fas_sgs_apply_transpose(fas_state s, const double *r, doub
     STCHK(ensure_adjoint(s));
     const LevelDev &d = s->lv[0];
     prepare_iteration(s->e, 0);
+    STCHK(transpose_blocks(s, 0));
     launch_unpack(d.L, r, s->a_r, 4, s->e.st);
-    launch_sgs_transpose(d.L, d.blk, s->a_r, s->a_zeta, s->a_z, s->e.fp32, s->e.st);
+    sgs_transpose(s, 0, s->a_r, s->a_z);
     launch_pack(d.L, s->a_z, x, 4, s->e.st);
     HIPCHK(hipGetLastError());
     return FAS_OK;

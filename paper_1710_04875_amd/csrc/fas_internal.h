@@ -261,8 +261,12 @@ void launch_geo_nodes(const Lay &L, const double *xn, const double *yn, const do
                       double *dy, hipStream_t st);
 void launch_forces(const Lay &L, const double *geo, const double *u, const Phys &ph, double *out,
                    double *dcl, hipStream_t st);                       // out[6], dcl padded (zeroed)
-void launch_sgs_transpose(const Lay &L, const void *blk, const double *r, void *zeta, double *x, int fp32,
-                          hipStream_t st);
+// transposed SGS solve through the primal sweep: bt = the neighbour blocks
+// transposed into the slots of the cells they act on, g = r in the sweep
+// precision, and x = D^-T xi after the sweep
+void launch_blocks_t(const Lay &L, const void *blk, void *bt, int fp32, hipStream_t st);
+void launch_to_sweep(const Lay &L, const double *r, void *g, int fp32, hipStream_t st);
+void launch_dinv_t(const Lay &L, const void *blk, const double *xi, double *x, int fp32, hipStream_t st);
 int dot_scratch_size();
 void launch_dot(const Lay &L, const double *a, const double *b, double *red, double *out, hipStream_t st);
 void launch_axpby_ptr(const Lay &L, double a, const double *x, double b, const double *y, double *out,
