@@ -470,48 +470,90 @@ __device__ void make_ctx(Ctx &c, const Lay &L, const double *geo, const double *
 }
 
 // ------------------------------------------------------------------ kernels
-// out += (dF/du)^T lam: every cell scatters (dF_c/du_s)^T lam_c to each
-// interior cell s its residual depends on (13 stencil positions mapped
-// through the boundary conditions).  out must be zeroed first.  part
+// out += (dF/du)^T lam, face by face.  F_c is the sum of c's four face
+// fluxes (east and north added, west and south subtracted) over vol_c, and
+// an interior face's flux is the same value for both of its cells, so
+//     (dF/du)^T lam = sum over faces f of (dflux_f/du)^T mu_f,
+//     mu_f = lam_L / vol_L - lam_R / vol_R
+// (a side that is not an interior cell drops out: boundary faces belong to
+// their one interior cell; on the wake cut each row-0 cell keeps its own
+// south face, as in the residual).  A face's flux depends on the states of
+// its JST line (LL, L, R, RR) and, for viscous faces, of the four cells
+// around each of its two vertices: at most 8 cells, each mapped through the
+// boundary conditions to the interior cell its state comes from.  Thread
+// (face, q) seeds the q-th distinct such source cell, evaluates the flux
+// with dual numbers, and scatters the four products to that cell.  part
 // selects F, its convective part f^c or its dissipative and viscous part
-// f^v.
+// f^v.  out must be zeroed first.
+constexpr int VJP_SOURCES = 8;
+
 __global__ __launch_bounds__(TPB) void k_vjp(Lay L, const double *geo, const double *u, const double *mut,
                                              Phys ph, const double *lam, double *out, int part) {
-    const BlockXY cb = xcd_block();
-    int s, i, j;
-    if (!interior_cell(L, cb.x * blockDim.x + threadIdx.x, s, i, j)) return;
-    const int NS = L.NS;
-    double lc[4];
-#pragma unroll
-    for (int k = 0; k < 4; ++k) lc[k] = lam[k * NS + s];
-    Ctx c;
-    make_ctx(c, L, geo, u, mut, ph);
-    c.part = part;
-    const int di[13] = {0, -1, 1, -2, 2, 0, 0, 0, 0, -1, 1, -1, 1};
-    const int dj[13] = {0, 0, 0, 0, 0, -1, 1, -2, 2, -1, -1, 1, 1};
-    int srci[13], srcj[13], n = 0;
-    for (int p = 0; p < 13; ++p) {
-        int a, b;
-        source_of(L, i + di[p], j + dj[p], a, b);
+    const int q = blockIdx.y;
+    const int t = blockIdx.x * TPB + threadIdx.x;
+    const int nif = (L.ni + 1) * L.nj;
+    int sf, a, b;
+    bool xi = t < nif;
+    if (xi) rect_cell(L, t, L.ni + 1, L.nj, 0, sf, a, b);                 // face between (a - 1, b) and (a, b)
+    else if (!rect_cell(L, t - nif, L.ni, L.nj + 1, 0, sf, a, b)) return;  // face between (a, b - 1) and (a, b)
+    const int iL = xi ? a - 1 : a, jL = xi ? b : b - 1;
+    const int iLL = xi ? a - 2 : a, jLL = xi ? b : b - 2, iRR = xi ? a + 1 : a, jRR = xi ? b : b + 1;
+    const int vAi = a, vAj = b, vBi = xi ? a : a + 1, vBj = xi ? b + 1 : b;
+    // stencil: the JST line, then the remaining cells around the vertices
+    int pi[VJP_SOURCES] = {iLL, iL, a, iRR, 0, 0, 0, 0}, pj[VJP_SOURCES] = {jLL, jL, b, jRR, 0, 0, 0, 0};
+    if (xi) {
+        pi[4] = a - 1; pj[4] = b - 1; pi[5] = a; pj[5] = b - 1;
+        pi[6] = a - 1; pj[6] = b + 1; pi[7] = a; pj[7] = b + 1;
+    } else {
+        pi[4] = a - 1; pj[4] = b - 1; pi[5] = a - 1; pj[5] = b;
+        pi[6] = a + 1; pj[6] = b - 1; pi[7] = a + 1; pj[7] = b;
+    }
+    const int np = ph.rans ? 8 : 4;
+    int si = 0, sj = 0, n = 0;
+    for (int p = 0; p < np; ++p) {
+        int ci, cj;
+        source_of(L, pi[p], pj[p], ci, cj);
         bool dup = false;
-        for (int q = 0; q < n; ++q) dup = dup || (srci[q] == a && srcj[q] == b);
+        for (int r = 0; r < p; ++r) {
+            int di, dj;
+            source_of(L, pi[r], pj[r], di, dj);
+            dup = dup || (di == ci && dj == cj);
+        }
         if (!dup) {
-            srci[n] = a;
-            srcj[n] = b;
+            if (n == q) {
+                si = ci;
+                sj = cj;
+            }
             ++n;
         }
     }
-    for (int q = 0; q < n; ++q) {
-        c.si = srci[q];
-        c.sj = srcj[q];
-        D4 F[4];
-        cell_residual<double>(c, i, j, F);
-        const int t = L.slot(c.si, c.sj);
+    if (q >= n) return;
+    const int NS = L.NS;
+    const bool inL = interior(L, iL, jL), inR = interior(L, a, b);
+    const int sL = L.slot(iL, jL);
+    double mu[4];
 #pragma unroll
-        for (int m = 0; m < 4; ++m) {
-            const double v = ((lc[0] * F[0].d[m] + lc[1] * F[1].d[m]) + lc[2] * F[2].d[m]) + lc[3] * F[3].d[m];
-            atomicAdd(out + m * NS + t, v);
-        }
+    for (int k = 0; k < 4; ++k) {
+        const double l = inL ? lam[k * NS + sL] / geo[G_VOL * NS + sL] : 0.0;
+        const double r = inR ? lam[k * NS + sf] / geo[G_VOL * NS + sf] : 0.0;
+        mu[k] = l - r;
+    }
+    Ctx c;
+    make_ctx(c, L, geo, u, mut, ph);
+    c.si = si;
+    c.sj = sj;
+    const bool wall = !xi && b == 0 && !cut_col(L, a);
+    D4 C[4], V[4];
+    face<double>(c, iL, jL, a, b, iLL, jLL, iRR, jRR, xi, geo[(xi ? G_SXI_X : G_SETA_X) * NS + sf],
+                 geo[(xi ? G_SXI_Y : G_SETA_Y) * NS + sf], wall, vAi, vAj, vBi, vBj, C, V);
+    const int ts = L.slot(si, sj);
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+        double d[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) d[k] = part == 1 ? C[k].d[m] : part == 2 ? V[k].d[m] : C[k].d[m] + V[k].d[m];
+        const double v = ((mu[0] * d[0] + mu[1] * d[1]) + mu[2] * d[2]) + mu[3] * d[3];
+        atomicAdd(out + m * NS + ts, v);
     }
 }
 
@@ -1027,7 +1069,9 @@ __global__ void k_zero(double *p, size_t n) {
 // =================================================================== launchers
 void launch_vjp(const Lay &L, const double *geo, const double *u, const double *mut, const Phys &ph,
                 const double *lam, double *out, hipStream_t st, int part) {
-    hipLaunchKernelGGL(k_vjp, dim3(nblocks(L.ni * L.nj)), dim3(TPB), 0, st, L, geo, u, mut, ph, lam, out, part);
+    const int nf = (L.ni + 1) * L.nj + L.ni * (L.nj + 1);
+    hipLaunchKernelGGL(k_vjp, dim3(nblocks(nf), VJP_SOURCES), dim3(TPB), 0, st, L, geo, u, mut, ph, lam, out,
+                       part);
 }
 
 void launch_param_partials(const Lay &L, const double *geo, const double *u, const double *mut,
