@@ -1076,7 +1076,9 @@ fas_status ensure_tsweep(fas_state s, int l) {
     TSweep &t = s->a_ts[l];
     if (t.bt) return FAS_OK;
     const LevelDev &d = s->lv[l];
-    const size_t NS = d.L.NS, es = s->e.fp32 ? sizeof(float) : sizeof(double);
+    // FP64 extents, as the level's own blocks: the sweep precision can change
+    // with the parameters after the arrays exist
+    const size_t NS = d.L.NS, es = sizeof(double);
     const size_t nb = (size_t)BLK_NPLANES * NS * es, nv = 4 * NS * es;
     const size_t n = nb + 2 * nv + 4 * NS * sizeof(double) + sizeof(LevelDev);
     char *p = nullptr;
