@@ -1997,9 +1997,12 @@ extern "C" fas_status fas_batch_solve(fas_batch b, int32_t max_cycles, double dr
     std::vector<int> nd(n), stv(n);
     HIPCHK(hipMemcpyAsync(nd.data(), b->d_ndone, n * sizeof(int), hipMemcpyDeviceToHost, e.st));
     HIPCHK(hipMemcpyAsync(stv.data(), b->d_stat, n * sizeof(int), hipMemcpyDeviceToHost, e.st));
+    // a case's history is a row of hcap values (hcap can exceed this
+    // solve's max_cycles + 1 after a longer solve)
     if (res_hist)
-        HIPCHK(hipMemcpyAsync(res_hist, b->d_hist, (size_t)n * (max_cycles + 1) * sizeof(double),
-                              hipMemcpyDeviceToHost, e.st));
+        HIPCHK(hipMemcpy2DAsync(res_hist, (size_t)(max_cycles + 1) * sizeof(double), b->d_hist,
+                                (size_t)b->hcap * sizeof(double), (size_t)(max_cycles + 1) * sizeof(double), n,
+                                hipMemcpyDeviceToHost, e.st));
     HIPCHK(hipStreamSynchronize(e.st));
     // worst status: diverged, stalled, not converged, ok
     auto rank = [](int st) {

@@ -76,6 +76,28 @@ def test_batch_equals_single_states(use_graph):
         assert stat[c] == 0
 
 
+def test_shorter_solve_after_a_longer_one_returns_its_own_histories():
+    """The device history rows keep the capacity of the longest solve; a
+    later, shorter solve must still hand back each case's own history."""
+    from paper_1710_04875_amd import fas
+    singles = _states()
+    ref = []
+    for g, st in singles:
+        st.cycle(12)
+        h, _ = st.cycle(5)
+        torch.cuda.synchronize()
+        ref.append(h)
+    pairs = _states()
+    b = fas.Batch([st for _, st in pairs], autotune=False)
+    b.solve(12, 0.0, True)
+    hist, stat, _ = b.solve(5, 0.0, True)
+    # (the 128 x 16 case diverges at c* = 50 in the first solve: its second
+    # history is the norm before the cycle, then a NaN, in both paths)
+    for c in range(len(CASES)):
+        assert np.array_equal(hist[c], ref[c], equal_nan=True), c
+    assert len(hist[0]) == len(hist[1]) == 6
+
+
 def test_batch_fp32_preconditioner_equals_single_states():
     ref = _run_single(fp32=1)
     us, hist, stat, _ = _run_batch(fp32=1)
