@@ -357,6 +357,10 @@ def dfa_section(fas, torch):
                              "sample": "%d pairs of the aspect-ratio-100 cases (numpy, vectorised)" % npairs}}
 
 
+# concurrent case groups of the batched solves (fas_batch_create)
+BATCH_GROUPS = 2
+
+
 def batch_params(fas, c, fp32, vblk=1):
     # the batch's tall grids need the thin-layer viscous block term (the
     # printed blocks diverge on the 512 x 128 and 1024 x 256 grids)
@@ -380,13 +384,15 @@ def batch_section(fas, torch, cap, loop_cycles, full_loop):
     for c in cases:
         x, y = c.grid()
         grids.append((fas.Grid(c.topology, x, y, c.n_wake, 3), torch.from_numpy(c.initial_state(x, y)).cuda()))
-    out = {"cases": len(cases), "fine_cells": int(cells.sum()), "cycle_cap": cap}
+    out = {"cases": len(cases), "fine_cells": int(cells.sum()), "cycle_cap": cap, "groups": BATCH_GROUPS}
     finals, cycles, status = {}, {}, {}
-    for fp32 in (True, False):
-        tag = "fp32_precond" if fp32 else "fp64"
+    # the headline runs use concurrent case groups; the one-group runs give
+    # the batched kernels' own timing (a group's launch covers fewer cases)
+    for fp32, groups in ((True, BATCH_GROUPS), (False, BATCH_GROUPS), (True, 1), (False, 1)):
+        tag = ("fp32_precond" if fp32 else "fp64") + ("" if groups == BATCH_GROUPS else "_one_group")
         log("batch %s: create + autotune" % tag)
         sts = [fas.State(g, batch_params(fas, c, fp32), u0) for (g, u0), c in zip(grids, cases)]
-        b = fas.Batch(sts, autotune=True)
+        b = fas.Batch(sts, autotune=True, groups=groups)
         torch.cuda.synchronize()
         log("batch %s: solve to 6 orders (graph)" % tag)
         t0 = time.perf_counter()
@@ -405,6 +411,10 @@ def batch_section(fas, torch, cap, loop_cycles, full_loop):
              "median_rate": round(float(np.median([(h[-1] / h[0]) ** (1.0 / max(len(h) - 1, 1))
                                                    for h in hist])), 4),
              "sweep_cfg_rows": [b.sweep_config(l)[1] for l in range(3)]}
+        if groups > 1:
+            out[tag] = r
+            del b, sts
+            continue
         # kernel timing of the batched cycle: a few directly launched cycles
         b.profile(True)
         t0 = time.perf_counter()
@@ -425,6 +435,10 @@ def batch_section(fas, torch, cap, loop_cycles, full_loop):
                 "all 64 cases", "avg_launch_us": round(1e3 * ms / max(cnt, 1), 3), "launches": cnt}
         out[tag] = r
         del b, sts
+    # the grouping changes when cases run, not what they compute
+    out["groups_bitwise_equal_to_one_group"] = all(
+        np.array_equal(finals[t][k], finals[t + "_one_group"][k]) for t in ("fp32_precond", "fp64")
+        for k in range(len(cases)))
     # converged solutions of the two precisions, cases that reached the drop in both
     u64, u32 = finals["fp64"], finals["fp32_precond"]
     # at the 6-order stop the two runs differ by their remaining iteration
@@ -468,6 +482,9 @@ def batch_section(fas, torch, cap, loop_cycles, full_loop):
             "cell_cycles_per_s": round(float((cells * cycles["fp64"]).sum() / t_loop), 1)}
     out["speedup_fp32_batch_vs_fp64_loop"] = round(t_loop / out["fp32_precond"]["seconds"], 2)
     out["speedup_fp64_batch_vs_fp64_loop"] = round(t_loop / out["fp64"]["seconds"], 2)
+    out["speedup_groups_vs_one_group"] = {
+        "fp32_precond": round(out["fp32_precond_one_group"]["seconds"] / out["fp32_precond"]["seconds"], 3),
+        "fp64": round(out["fp64_one_group"]["seconds"] / out["fp64"]["seconds"], 3)}
     return out
 
 

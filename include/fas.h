@@ -265,12 +265,19 @@ fas_status fas_profile_read(fas_state s, double *ms, int64_t *count);
  * call runs.  stream: hipStream_t for the batch's work (NULL: the batch
  * creates its own non-blocking stream).  autotune = 1 times every sweep
  * configuration that covers the tallest grid of each level on the batch
- * itself and keeps the fastest; 0 picks one by grid height.
+ * itself and keeps the fastest; 0 picks one by grid height.  groups > 1
+ * splits the cases into that many groups (at most n; the cases in
+ * descending order of ni + nj, dealt to the groups in turn), each a batch of
+ * its own with its own stream, autotuning and captured cycle; fas_batch_solve
+ * then runs the groups' cycles concurrently, so kernels of one group fill
+ * the compute units another group's long sweep chains leave idle.  Every
+ * case's iterates are those of a solve on its own whatever the grouping.
+ * groups 0 or 1: one group.
  * Errors: FAS_EINVAL, FAS_ENOMEM, FAS_EDEVICE.
  */
 typedef struct fas_batch_s *fas_batch;
 fas_status fas_batch_create(int32_t n, const fas_state *states, void *stream, int32_t autotune,
-                            fas_batch *out);
+                            int32_t groups, fas_batch *out);
 void fas_batch_destroy(fas_batch b);
 
 /*
@@ -291,6 +298,8 @@ fas_status fas_batch_solve(fas_batch b, int32_t max_cycles, double drop_orders, 
 /* Sweep configuration chosen for a level (index, and rows one launch covers
  * per case), and a manual override (cfg -1: pick by grid height; FAS_EINVAL
  * if the configuration covers fewer rows than the level's tallest grid).
+ * With groups, the query reports the group holding the level's tallest
+ * grid and the override applies to every group.
  * Configurations 0 .. fas_sweep_config_count() - 1: one workgroup per case
  * (four or eight threads per row, or one thread per row), or row bands of one
  * workgroup each, several per case, handing the band-boundary rows on
@@ -310,7 +319,8 @@ fas_status fas_sweep_config_info(int32_t cfg, int32_t *kind, int32_t *threads, i
                                  int32_t *depth_fp64, int32_t *depth_fp32);
 
 /* Kernel-class timing of the batch's direct launches (as fas_profile;
- * launches replayed from a graph are not timed). */
+ * launches replayed from a graph are not timed).  With groups, the sums
+ * over the groups, whose launches overlap in time. */
 fas_status fas_batch_profile(fas_batch b, int32_t enable);
 fas_status fas_batch_profile_read(fas_batch b, double *ms, int64_t *count);
 

@@ -11,6 +11,7 @@
 #include <cstring>
 #include <mutex>
 #include <string>
+#include <thread>
 #include <vector>
 
 using namespace fas;
@@ -176,6 +177,13 @@ struct fas_batch_s {
     hipGraphExec_t exec = nullptr;
     int graph_cap = -1;         // max_cycles / drop the graph was captured for
     double graph_drop = 0.0;
+    // concurrent case groups: sub-batches on streams of their own (empty: the
+    // batch is one group), the batch's case number of each of their cases,
+    // and the solve's start on the batch stream, which every group waits for
+    std::vector<fas_batch> parts;
+    std::vector<std::vector<int>> part_cases;
+    hipEvent_t ev_start = nullptr;
+    int *h_flags = nullptr;     // pinned: two activity snapshots in flight
 };
 
 // --------------------------------------------------------------------- grid
@@ -1725,6 +1733,9 @@ extern "C" fas_status fas_unsteady_lift_gradient(fas_state s, int32_t n_steps, d
 // -------------------------------------------------------------------- batch
 extern "C" void fas_batch_destroy(fas_batch b) {
     if (!b) return;
+    for (fas_batch p : b->parts) fas_batch_destroy(p);
+    if (b->ev_start) (void)hipEventDestroy(b->ev_start);
+    if (b->h_flags) (void)hipHostFree(b->h_flags);
     if (b->e.st) (void)hipStreamSynchronize(b->e.st);
     if (b->exec) (void)hipGraphExecDestroy(b->exec);
     if (b->graph) (void)hipGraphDestroy(b->graph);
@@ -1766,7 +1777,7 @@ static fas_status time_sweep(Engine &e, int l, int cfg, int reps, float *ms) {
 }
 
 extern "C" fas_status fas_batch_create(int32_t n, const fas_state *states, void *stream, int32_t autotune,
-                                       fas_batch *out) {
+                                       int32_t groups, fas_batch *out) {
     if (!out || !states || n < 1) return fail(FAS_EINVAL, "bad argument");
     *out = nullptr;
     const fas_state s0 = states[0];
@@ -1787,6 +1798,7 @@ extern "C" fas_status fas_batch_create(int32_t n, const fas_state *states, void 
         for (int k = 0; k < c; ++k)
             if (states[k] == s) return fail(FAS_EINVAL, "a state appears twice in the batch");
     }
+    if (groups < 0) return fail(FAS_EINVAL, "bad group count");
     for (int c = 0; c < n; ++c) HIPCHK(hipStreamSynchronize(states[c]->e.st));
     fas_batch b = new fas_batch_s();
     b->states.assign(states, states + n);
@@ -1801,6 +1813,35 @@ extern "C" fas_status fas_batch_create(int32_t n, const fas_state *states, void 
         if (hipStreamCreateWithFlags(&e.st, hipStreamNonBlocking) != hipSuccess)
             return cleanup(fail(FAS_EDEVICE, "stream creation failed"));
         b->own_stream = 1;
+    }
+    if (groups > 1 && n > 1) {
+        // cases by descending hyperplane-chain length (ni + nj), dealt to the
+        // groups in turn, so every group holds long and short chains
+        const int G = std::min<int>(groups, n);
+        std::vector<int> ord(n);
+        for (int c = 0; c < n; ++c) ord[c] = c;
+        std::stable_sort(ord.begin(), ord.end(), [&](int a, int b2) {
+            const Lay &La = states[a]->lv[0].L, &Lb = states[b2]->lv[0].L;
+            return La.ni + La.nj > Lb.ni + Lb.nj;
+        });
+        b->part_cases.assign(G, {});
+        for (int k = 0; k < n; ++k) b->part_cases[k % G].push_back(ord[k]);
+        for (int g = 0; g < G; ++g) {
+            std::vector<fas_state> sub;
+            for (int c : b->part_cases[g]) sub.push_back(states[c]);
+            fas_batch p = nullptr;
+            const fas_status st = fas_batch_create((int32_t)sub.size(), sub.data(), nullptr, autotune, 1, &p);
+            if (st != FAS_OK) return cleanup(st);
+            b->parts.push_back(p);
+        }
+        e.n = n;
+        e.nlev = s0->nlev;
+        if (hipEventCreateWithFlags(&b->ev_start, hipEventDisableTiming) != hipSuccess ||
+            hipHostMalloc(reinterpret_cast<void **>(&b->h_flags), (size_t)2 * n * sizeof(int),
+                          hipHostMallocDefault) != hipSuccess)
+            return cleanup(fail(FAS_EDEVICE, "batch set-up failed"));
+        *out = b;
+        return FAS_OK;
     }
     e.n = n;
     e.nlev = s0->nlev;
@@ -1901,8 +1942,17 @@ extern "C" fas_status fas_batch_create(int32_t n, const fas_state *states, void 
     return FAS_OK;
 }
 
+// the group holding the batch's tallest grid of a level
+static fas_batch tallest_part(fas_batch b, int level) {
+    fas_batch t = b->parts[0];
+    for (fas_batch p : b->parts)
+        if (p->e.lev[level].max_nj > t->e.lev[level].max_nj) t = p;
+    return t;
+}
+
 extern "C" fas_status fas_batch_sweep_config(fas_batch b, int32_t level, int32_t *cfg, int32_t *rows) {
     if (!b || level < 0 || level >= b->e.nlev) return fail(FAS_EINVAL, "bad argument");
+    if (!b->parts.empty()) return fas_batch_sweep_config(tallest_part(b, level), level, cfg, rows);
     int c = b->e.lev[level].sweep_cfg;
     if (c < 0) c = sweep_cfg_default(b->e.lev[level].max_nj, b->e.fp32);
     if (cfg) *cfg = c;
@@ -1930,6 +1980,12 @@ extern "C" fas_status fas_sweep_config_info(int32_t cfg, int32_t *kind, int32_t 
 
 extern "C" fas_status fas_batch_set_sweep_config(fas_batch b, int32_t level, int32_t cfg) {
     if (!b || level < 0 || level >= b->e.nlev) return fail(FAS_EINVAL, "bad argument");
+    if (!b->parts.empty()) {
+        // checked against the tallest grid first, so no group is changed on a refusal
+        STCHK(fas_batch_set_sweep_config(tallest_part(b, level), level, cfg));
+        for (fas_batch p : b->parts) STCHK(fas_batch_set_sweep_config(p, level, cfg));
+        return FAS_OK;
+    }
     if (cfg < -1 || cfg >= sweep_cfg_count()) return fail(FAS_EINVAL, "bad sweep configuration");
     if (cfg >= 0 && sweep_cfg_rows(cfg, b->e.lev[level].max_nj) < b->e.lev[level].max_nj)
         return fail(FAS_EINVAL, "sweep configuration covers fewer rows than the tallest grid");
@@ -1938,9 +1994,11 @@ extern "C" fas_status fas_batch_set_sweep_config(fas_batch b, int32_t level, int
     return FAS_OK;
 }
 
-extern "C" fas_status fas_batch_solve(fas_batch b, int32_t max_cycles, double drop_orders, int32_t use_graph,
-                                      int32_t *n_done, int32_t *status, double *res_hist) {
-    if (!b || max_cycles < 0) return fail(FAS_EINVAL, "bad argument");
+// Start of a solve on one group: history rows, control record, every case
+// active, the norm before the first cycle, and (use_graph) the captured
+// cycle.
+static fas_status batch_begin(fas_batch b, int32_t max_cycles, double drop_orders, int32_t use_graph,
+                              BatchCtl &ctl) {
     Engine &e = b->e;
     const int n = e.n;
     if (max_cycles + 1 > b->hcap) {
@@ -1956,8 +2014,7 @@ extern "C" fas_status fas_batch_solve(fas_batch b, int32_t max_cycles, double dr
         b->allocs.push_back(b->d_hist);
         b->hcap = max_cycles + 1;
     }
-    const BatchCtl ctl = make_ctl(e, b->d_h0, b->d_hist, b->hcap, b->d_act, b->d_ndone, b->d_stat, max_cycles,
-                                  drop_orders);
+    ctl = make_ctl(e, b->d_h0, b->d_hist, b->hcap, b->d_act, b->d_ndone, b->d_stat, max_cycles, drop_orders);
     // every case starts active; its c* ramp continues from its own count
     launch_fill_int(b->d_act, n, 1, e.st);
     for (int c = 0; c < n; ++c)
@@ -1979,10 +2036,162 @@ extern "C" fas_status fas_batch_solve(fas_batch b, int32_t max_cycles, double dr
         b->graph_cap = max_cycles;
         b->graph_drop = drop_orders;
     }
+    return FAS_OK;
+}
+
+static fas_status batch_cycle(fas_batch b, const BatchCtl &ctl, int32_t use_graph) {
+    if (use_graph) HIPCHK(hipGraphLaunch(b->exec, b->e.st));
+    else controlled_cycle(b->e, ctl);
+    return FAS_OK;
+}
+
+// End of a solve on one group (its stream synchronised): cycle counts back
+// to the states, per-case counts, status and history rows (row pitch
+// max_cycles + 1), diverged cases' hand-off arrays re-armed.
+static fas_status batch_collect(fas_batch b, int32_t max_cycles, int *nd, int *stv, double *res_hist) {
+    Engine &e = b->e;
+    const int n = e.n;
+    for (int c = 0; c < n; ++c)
+        HIPCHK(hipMemcpyAsync(b->states[c]->e.d_cyc, e.d_cyc + c, sizeof(int), hipMemcpyDeviceToDevice, e.st));
+    HIPCHK(hipMemcpyAsync(nd, b->d_ndone, n * sizeof(int), hipMemcpyDeviceToHost, e.st));
+    HIPCHK(hipMemcpyAsync(stv, b->d_stat, n * sizeof(int), hipMemcpyDeviceToHost, e.st));
+    // a case's history is a row of hcap values (hcap can exceed this
+    // solve's max_cycles + 1 after a longer solve)
+    if (res_hist)
+        HIPCHK(hipMemcpy2DAsync(res_hist, (size_t)(max_cycles + 1) * sizeof(double), b->d_hist,
+                                (size_t)b->hcap * sizeof(double), (size_t)(max_cycles + 1) * sizeof(double), n,
+                                hipMemcpyDeviceToHost, e.st));
+    HIPCHK(hipStreamSynchronize(e.st));
+    for (int c = 0; c < n; ++c)
+        if (stv[c] == FAS_DIVERGED) rearm_handoff(b->states[c]->lv, e.st);
+    HIPCHK(hipStreamSynchronize(e.st));
+    return FAS_OK;
+}
+
+// worst status: diverged, stalled, not converged, ok
+static int status_rank(int st) {
+    return st == FAS_DIVERGED ? 3 : st == FAS_STALLED ? 2 : st == FAS_NOT_CONVERGED ? 1 : 0;
+}
+
+// Groups run concurrently, each replaying its own cycles on its own stream:
+// the host keeps up to two chunks of CHECK cycles queued per group, each
+// followed by an asynchronous copy of the group's activity flags, and polls
+// the chunks' events; a group stops once a snapshot shows no active case or
+// its cycles reach max_cycles.  Replays queued after a group's last case
+// stopped are no-ops (the device flags mask them), so every case's iterates
+// are those of a solve on its own.
+static fas_status grouped_solve(fas_batch b, int32_t max_cycles, double drop_orders, int32_t use_graph,
+                                int32_t *n_done, int32_t *status, double *res_hist) {
+    const int G = (int)b->parts.size();
+    constexpr int CHECK = 4;
+    struct Run {
+        BatchCtl ctl;
+        int launched = 0, queued = 0, head = 0;
+        bool done = false;
+        hipEvent_t ev[2] = {nullptr, nullptr};
+        int *snap[2] = {nullptr, nullptr};
+    };
+    std::vector<Run> runs(G);
+    fas_status st = FAS_OK;
+    int off = 0;
+    for (int g = 0; g < G && st == FAS_OK; ++g) {
+        Run &r = runs[g];
+        const int m = b->parts[g]->e.n;
+        r.snap[0] = b->h_flags + 2 * off;
+        r.snap[1] = b->h_flags + 2 * off + m;
+        off += m;
+        for (int k = 0; k < 2; ++k)
+            if (hipEventCreateWithFlags(&r.ev[k], hipEventDisableTiming) != hipSuccess)
+                st = fail(FAS_EDEVICE, "event creation failed");
+    }
+    // the groups start after the work already queued on the batch stream
+    if (st == FAS_OK && hipEventRecord(b->ev_start, b->e.st) != hipSuccess) st = fail(FAS_EDEVICE, "event record failed");
+    for (int g = 0; g < G && st == FAS_OK; ++g) {
+        if (hipStreamWaitEvent(b->parts[g]->e.st, b->ev_start, 0) != hipSuccess)
+            st = fail(FAS_EDEVICE, "stream wait failed");
+        else
+            st = batch_begin(b->parts[g], max_cycles, drop_orders, use_graph, runs[g].ctl);
+    }
+    while (st == FAS_OK) {
+        bool all = true;
+        for (int g = 0; g < G && st == FAS_OK; ++g) {
+            Run &r = runs[g];
+            fas_batch p = b->parts[g];
+            if (r.done) continue;
+            all = false;
+            if (r.queued > 0) {
+                const hipError_t q = hipEventQuery(r.ev[r.head]);
+                if (q == hipSuccess) {
+                    int any = 0;
+                    for (int c = 0; c < p->e.n; ++c) any |= r.snap[r.head][c];
+                    r.head ^= 1;
+                    --r.queued;
+                    if (!any) {
+                        r.done = true;
+                        continue;
+                    }
+                } else if (q != hipErrorNotReady) {
+                    st = fail(FAS_EDEVICE, std::string("cycle replay failed: ") + hipGetErrorString(q));
+                    break;
+                }
+            }
+            if (r.queued < 2 && r.launched < max_cycles) {
+                const int k = std::min(CHECK, max_cycles - r.launched);
+                for (int i = 0; i < k && st == FAS_OK; ++i) st = batch_cycle(p, r.ctl, use_graph);
+                r.launched += k;
+                const int slot = (r.head + r.queued) & 1;
+                if (st == FAS_OK &&
+                    (hipMemcpyAsync(r.snap[slot], p->d_act, p->e.n * sizeof(int), hipMemcpyDeviceToHost, p->e.st) !=
+                         hipSuccess ||
+                     hipEventRecord(r.ev[slot], p->e.st) != hipSuccess))
+                    st = fail(FAS_EDEVICE, "cycle replay failed");
+                ++r.queued;
+            } else if (r.queued == 0 && r.launched >= max_cycles) {
+                r.done = true;
+            }
+        }
+        if (all) break;
+        std::this_thread::yield();
+    }
+    // gather every group's results into the batch's case order
+    int worst = FAS_OK;
+    for (int g = 0; g < G; ++g) {
+        fas_batch p = b->parts[g];
+        const int m = p->e.n;
+        if (hipStreamSynchronize(p->e.st) != hipSuccess && st == FAS_OK) st = fail(FAS_EDEVICE, "batch solve failed");
+        if (st == FAS_OK) {
+            std::vector<int> nd(m), stv(m);
+            std::vector<double> h(res_hist ? (size_t)m * (max_cycles + 1) : 0);
+            st = batch_collect(p, max_cycles, nd.data(), stv.data(), res_hist ? h.data() : nullptr);
+            for (int k = 0; k < m && st == FAS_OK; ++k) {
+                const int c = b->part_cases[g][k];
+                if (n_done) n_done[c] = nd[k];
+                if (status) status[c] = stv[k];
+                if (status_rank(stv[k]) > status_rank(worst)) worst = stv[k];
+                if (res_hist)
+                    std::memcpy(res_hist + (size_t)c * (max_cycles + 1), h.data() + (size_t)k * (max_cycles + 1),
+                                (size_t)(max_cycles + 1) * sizeof(double));
+            }
+        }
+        for (int k = 0; k < 2; ++k)
+            if (runs[g].ev[k]) (void)hipEventDestroy(runs[g].ev[k]);
+    }
+    if (st != FAS_OK) return st;
+    if (worst != FAS_OK) g_err = std::string("batched case: ") + status_message(worst);
+    return (fas_status)worst;
+}
+
+extern "C" fas_status fas_batch_solve(fas_batch b, int32_t max_cycles, double drop_orders, int32_t use_graph,
+                                      int32_t *n_done, int32_t *status, double *res_hist) {
+    if (!b || max_cycles < 0) return fail(FAS_EINVAL, "bad argument");
+    if (!b->parts.empty()) return grouped_solve(b, max_cycles, drop_orders, use_graph, n_done, status, res_hist);
+    Engine &e = b->e;
+    const int n = e.n;
+    BatchCtl ctl;
+    STCHK(batch_begin(b, max_cycles, drop_orders, use_graph, ctl));
     const int check = 4;
     for (int k = 0; k < max_cycles; ++k) {
-        if (use_graph) HIPCHK(hipGraphLaunch(b->exec, e.st));
-        else controlled_cycle(e, ctl);
+        STCHK(batch_cycle(b, ctl, use_graph));
         if ((k + 1) % check == 0 || k + 1 == max_cycles) {
             HIPCHK(hipMemcpyAsync(b->h_act, b->d_act, n * sizeof(int), hipMemcpyDeviceToHost, e.st));
             HIPCHK(hipStreamSynchronize(e.st));
@@ -1991,43 +2200,43 @@ extern "C" fas_status fas_batch_solve(fas_batch b, int32_t max_cycles, double dr
             if (!any) break;
         }
     }
-    // hand the cycle counts back to the states
-    for (int c = 0; c < n; ++c)
-        HIPCHK(hipMemcpyAsync(b->states[c]->e.d_cyc, e.d_cyc + c, sizeof(int), hipMemcpyDeviceToDevice, e.st));
     std::vector<int> nd(n), stv(n);
-    HIPCHK(hipMemcpyAsync(nd.data(), b->d_ndone, n * sizeof(int), hipMemcpyDeviceToHost, e.st));
-    HIPCHK(hipMemcpyAsync(stv.data(), b->d_stat, n * sizeof(int), hipMemcpyDeviceToHost, e.st));
-    // a case's history is a row of hcap values (hcap can exceed this
-    // solve's max_cycles + 1 after a longer solve)
-    if (res_hist)
-        HIPCHK(hipMemcpy2DAsync(res_hist, (size_t)(max_cycles + 1) * sizeof(double), b->d_hist,
-                                (size_t)b->hcap * sizeof(double), (size_t)(max_cycles + 1) * sizeof(double), n,
-                                hipMemcpyDeviceToHost, e.st));
-    HIPCHK(hipStreamSynchronize(e.st));
-    // worst status: diverged, stalled, not converged, ok
-    auto rank = [](int st) {
-        return st == FAS_DIVERGED ? 3 : st == FAS_STALLED ? 2 : st == FAS_NOT_CONVERGED ? 1 : 0;
-    };
+    STCHK(batch_collect(b, max_cycles, nd.data(), stv.data(), res_hist));
     int worst = FAS_OK;
     for (int c = 0; c < n; ++c) {
         if (n_done) n_done[c] = nd[c];
         if (status) status[c] = stv[c];
-        if (rank(stv[c]) > rank(worst)) worst = stv[c];
-        if (stv[c] == FAS_DIVERGED) rearm_handoff(b->states[c]->lv, e.st);
+        if (status_rank(stv[c]) > status_rank(worst)) worst = stv[c];
     }
-    HIPCHK(hipStreamSynchronize(e.st));
     if (worst != FAS_OK) g_err = std::string("batched case: ") + status_message(worst);
     return (fas_status)worst;
 }
 
 extern "C" fas_status fas_batch_profile(fas_batch b, int32_t enable) {
     if (!b) return fail(FAS_EINVAL, "null batch");
+    for (fas_batch p : b->parts) STCHK(profile_on(p->e, enable));
+    if (!b->parts.empty()) return FAS_OK;
     return profile_on(b->e, enable);
 }
 
 extern "C" fas_status fas_batch_profile_read(fas_batch b, double *ms, int64_t *count) {
     if (!b) return fail(FAS_EINVAL, "null batch");
-    return profile_read(b->e, ms, count);
+    if (b->parts.empty()) return profile_read(b->e, ms, count);
+    // summed over the groups (concurrent groups overlap in time)
+    for (int k = 0; k < FAS_PROF_NCLASS; ++k) {
+        if (ms) ms[k] = 0.0;
+        if (count) count[k] = 0;
+    }
+    for (fas_batch p : b->parts) {
+        double pm[FAS_PROF_NCLASS];
+        int64_t pc[FAS_PROF_NCLASS];
+        STCHK(profile_read(p->e, pm, pc));
+        for (int k = 0; k < FAS_PROF_NCLASS; ++k) {
+            if (ms) ms[k] += pm[k];
+            if (count) count[k] += pc[k];
+        }
+    }
+    return FAS_OK;
 }
 
 extern "C" int64_t fas_set_four_lane_limit(int64_t max_cells) { return set_four_lane_limit(max_cells); }

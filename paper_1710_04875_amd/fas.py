@@ -131,7 +131,7 @@ def load(path: str = LIB_PATH):
         "fas_dual_time_step": (i32, [vp, f64, f64, i32, f64, dp, ip]),
         "fas_profile": (i32, [vp, i32]),
         "fas_profile_read": (i32, [vp, dp, ctypes.POINTER(ctypes.c_int64)]),
-        "fas_batch_create": (i32, [i32, ctypes.POINTER(vp), vp, i32, ctypes.POINTER(vp)]),
+        "fas_batch_create": (i32, [i32, ctypes.POINTER(vp), vp, i32, i32, ctypes.POINTER(vp)]),
         "fas_batch_destroy": (None, [vp]),
         "fas_batch_solve": (i32, [vp, i32, f64, i32, ip, ip, dp]),
         "fas_batch_sweep_config": (i32, [vp, i32, ip, ip]),
@@ -551,14 +551,15 @@ def sweep_config_info(cfg):
 class Batch:
     """Independent steady cases advanced together (one launch per kernel
     over all cases, optionally replayed from a captured HIP graph).  The
-    batch works in place on the states' buffers; keep them alive."""
+    batch works in place on the states' buffers; keep them alive.  groups > 1
+    runs that many case groups concurrently, each on its own stream."""
 
-    def __init__(self, states, autotune=True):
+    def __init__(self, states, autotune=True, groups=1):
         lib = load()
         self.states = list(states)
         arr = (ctypes.c_void_p * len(self.states))(*[st.h.value for st in self.states])
         h = ctypes.c_void_p()
-        _check(lib.fas_batch_create(len(self.states), arr, _stream(), 1 if autotune else 0,
+        _check(lib.fas_batch_create(len(self.states), arr, _stream(), 1 if autotune else 0, int(groups),
                                     ctypes.byref(h)))
         self.h = h
 

@@ -81,7 +81,7 @@ def test_argument_errors_without_device():
     assert b"n_wake" in lib.fas_last_error()
     assert lib.fas_grid_create(0, 8, 8, 0, None, dp, 1, ctypes.byref(h)) == fas.FAS_EINVAL
     assert lib.fas_state_create(None, None, None, None, ctypes.byref(h)) == fas.FAS_EINVAL
-    assert lib.fas_batch_create(0, None, None, 0, ctypes.byref(h)) == fas.FAS_EINVAL
+    assert lib.fas_batch_create(0, None, None, 0, 1, ctypes.byref(h)) == fas.FAS_EINVAL
     assert lib.fas_batch_solve(None, 1, 0.0, 0, None, None, None) == fas.FAS_EINVAL
     assert lib.fas_cycle(None, 1, 0.0, None, None) == fas.FAS_EINVAL
     assert lib.fas_residual(None, 0, None) == fas.FAS_EINVAL

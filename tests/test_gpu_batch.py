@@ -54,10 +54,10 @@ def _run_single(fp32=0, cycles=6, drop=0.0, **kw):
     return res
 
 
-def _run_batch(fp32=0, cycles=6, drop=0.0, use_graph=True, cfg=None, **kw):
+def _run_batch(fp32=0, cycles=6, drop=0.0, use_graph=True, cfg=None, groups=1, **kw):
     from paper_1710_04875_amd import fas
     pairs = _states(fp32, **kw)
-    b = fas.Batch([st for _, st in pairs], autotune=cfg is None)
+    b = fas.Batch([st for _, st in pairs], autotune=cfg is None, groups=groups)
     if cfg is not None:
         b.set_sweep_config(0, cfg)
     hist, stat, worst = b.solve(cycles, drop, use_graph)
@@ -66,17 +66,18 @@ def _run_batch(fp32=0, cycles=6, drop=0.0, use_graph=True, cfg=None, **kw):
     return us, hist, stat, b
 
 
-@pytest.mark.parametrize("use_graph", [True, False])
-def test_batch_equals_single_states(use_graph):
+@pytest.mark.parametrize("use_graph,groups", [(True, 1), (False, 1), (True, 2), (False, 3)])
+def test_batch_equals_single_states(use_graph, groups):
     ref = _run_single()
-    us, hist, stat, _ = _run_batch(use_graph=use_graph)
+    us, hist, stat, _ = _run_batch(use_graph=use_graph, groups=groups)
     for c in range(len(CASES)):
         assert np.array_equal(us[c], ref[c][0]), c
         assert np.array_equal(hist[c], ref[c][1]), c
         assert stat[c] == 0
 
 
-def test_shorter_solve_after_a_longer_one_returns_its_own_histories():
+@pytest.mark.parametrize("groups", [1, 2])
+def test_shorter_solve_after_a_longer_one_returns_its_own_histories(groups):
     """The device history rows keep the capacity of the longest solve; a
     later, shorter solve must still hand back each case's own history."""
     from paper_1710_04875_amd import fas
@@ -88,7 +89,7 @@ def test_shorter_solve_after_a_longer_one_returns_its_own_histories():
         torch.cuda.synchronize()
         ref.append(h)
     pairs = _states()
-    b = fas.Batch([st for _, st in pairs], autotune=False)
+    b = fas.Batch([st for _, st in pairs], autotune=False, groups=groups)
     b.solve(12, 0.0, True)
     hist, stat, _ = b.solve(5, 0.0, True)
     # (the 128 x 16 case diverges at c* = 50 in the first solve: its second
@@ -106,10 +107,11 @@ def test_batch_fp32_preconditioner_equals_single_states():
         assert np.array_equal(hist[c], ref[c][1]), c
 
 
-def test_batch_stops_each_case_at_its_own_drop():
+@pytest.mark.parametrize("groups", [1, 2])
+def test_batch_stops_each_case_at_its_own_drop(groups):
     from paper_1710_04875_amd import fas
     ref = _run_single(cycles=40, drop=3.0, cfl=20.0)
-    us, hist, stat, _ = _run_batch(cycles=40, drop=3.0, cfl=20.0)
+    us, hist, stat, _ = _run_batch(cycles=40, drop=3.0, cfl=20.0, groups=groups)
     for c in range(len(CASES)):
         assert len(hist[c]) == len(ref[c][1]), c
         assert np.array_equal(us[c], ref[c][0]), c
@@ -117,7 +119,8 @@ def test_batch_stops_each_case_at_its_own_drop():
     assert len({len(h) for h in hist}) > 1
 
 
-def test_diverging_case_stops_alone():
+@pytest.mark.parametrize("groups", [1, 2])
+def test_diverging_case_stops_alone(groups):
     """With the viscous block term and the sum-form pseudo time step at
     c* = 50, the 128 x 16 grid (4 rows on the coarsest level) diverges after
     about 17 cycles, in the oracle as well; the other cases go on.  The
@@ -127,7 +130,7 @@ def test_diverging_case_stops_alone():
     from paper_1710_04875_amd import fas
     kw = dict(viscous_blocks=1, dt_form=0)
     ref = _run_single(cycles=30, drop=0.0, **kw)
-    us, hist, stat, b = _run_batch(cycles=30, drop=0.0, **kw)
+    us, hist, stat, b = _run_batch(cycles=30, drop=0.0, groups=groups, **kw)
     assert stat[2] == ref[2][2] == fas.FAS_DIVERGED
     assert len(hist[2]) < 31
     for c in (0, 1):
