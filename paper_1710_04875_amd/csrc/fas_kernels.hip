@@ -951,8 +951,11 @@ __global__ __launch_bounds__(TPB) void k_residual_q(BK b, ResArgs a) {
 // states, |A|_c = R |Lambda|_c R^-1 with the cutoff of eq. "cutoff"; here
 // |A|_c = |l1| I + (|l3| - |l1|) r3 l3^T + (|l4| - |l1|) r4 l4^T (same
 // matrix, the two acoustic projections written out).
-__device__ void split_face(const double UL[4], const double UR[4], double sx, double sy, double d,
-                           double qf, int ale, double Ap[16], double Am[16]) {
+// HALF 0: both halves; 1: A+ only (into Ap); 2: A- only (into Am).  Each
+// entry is the same expression whichever halves are formed.
+template <int HALF>
+__device__ void split_face_h(const double UL[4], const double UR[4], double sx, double sy, double d,
+                             double qf, int ale, double Ap[16], double Am[16]) {
     double ln = sqrt(sx * sx + sy * sy);
     double nx = sx / ln, ny = sy / ln;
     double U0 = 0.5 * (UL[0] + UR[0]), U1 = 0.5 * (UL[1] + UR[1]);
@@ -997,10 +1000,15 @@ __device__ void split_face(const double UL[4], const double UR[4], double sx, do
 #pragma unroll
         for (int c = 0; c < 4; ++c) {
             double absA = (r == c ? al[0] : 0.0) + c3 * r3[r] * l3[c] + c4 * r4[r] * l4[c];
-            Ap[r * 4 + c] = ln * (0.5 * (A[r * 4 + c] + absA));
-            Am[r * 4 + c] = ln * (0.5 * (A[r * 4 + c] - absA));
+            if constexpr (HALF != 2) Ap[r * 4 + c] = ln * (0.5 * (A[r * 4 + c] + absA));
+            if constexpr (HALF != 1) Am[r * 4 + c] = ln * (0.5 * (A[r * 4 + c] - absA));
         }
     }
+}
+
+__device__ inline void split_face(const double UL[4], const double UR[4], double sx, double sy, double d,
+                                  double qf, int ale, double Ap[16], double Am[16]) {
+    split_face_h<0>(UL, UR, sx, sy, d, qf, ale, Ap, Am);
 }
 
 // scalar thin-layer estimate of the viscous flux Jacobian of a face
@@ -1015,6 +1023,7 @@ __device__ double visc_face(const Lay &L, const double *geo, const double *u, co
     return ((mue * (GAM / ph.pr)) * s2) / (rf * vf);
 }
 
+template <int HALF = 0>
 __device__ void face_blocks(const Lay &L, const double *geo, const double *u, const double *cq,
                             const double *mut, const Phys &ph, int viscous, int sL, int sR,
                             int plane_x, int plane_y, int sf, double Ap[16], double Am[16]) {
@@ -1028,19 +1037,38 @@ __device__ void face_blocks(const Lay &L, const double *geo, const double *u, co
         const int wp = plane_x == G_SXI_X ? G_WIX : G_WJX;
         qf = geo[wp * NS + sf] * sx + geo[(wp + 1) * NS + sf] * sy;
     }
-    split_face(UL, UR, sx, sy, ph.d_cut, qf, ph.ale, Ap, Am);
+    split_face_h<HALF>(UL, UR, sx, sy, ph.d_cut, qf, ph.ale, Ap, Am);
     if (viscous) {
         double v = visc_face(L, geo, u, cq, mut, ph, sL, sR, sx, sy);
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
-            Ap[k * 5] = Ap[k * 5] + v;
-            Am[k * 5] = Am[k * 5] - v;
+            if constexpr (HALF != 2) Ap[k * 5] = Ap[k * 5] + v;
+            if constexpr (HALF != 1) Am[k * 5] = Am[k * 5] - v;
         }
     }
 }
 
+// Row r of block b of cell s, written as wide stores: one 16-byte store in
+// FP32 (the row is contiguous), two in FP64 (one per half plane).  A lane's
+// stores go to its own cell's record, so a wave's store instruction touches
+// one cache line per lane whatever the width: wider stores mean fewer of
+// them.
+template <typename BT> struct RowStore;
+template <> struct RowStore<float> {
+    __device__ static void put(float *blk, int b, int NS, int s, int r, const double (&v)[4]) {
+        *reinterpret_cast<float4 *>(blk + BL<float>::at(b, NS, s, r, 0)) =
+            make_float4((float)v[0], (float)v[1], (float)v[2], (float)v[3]);
+    }
+};
+template <> struct RowStore<double> {
+    __device__ static void put(double *blk, int b, int NS, int s, int r, const double (&v)[4]) {
+        *reinterpret_cast<double2 *>(blk + BL<double>::at(b, NS, s, r, 0)) = make_double2(v[0], v[1]);
+        *reinterpret_cast<double2 *>(blk + BL<double>::at(b, NS, s, r, 2)) = make_double2(v[2], v[3]);
+    }
+};
+
 template <typename BT>
-__global__ __launch_bounds__(TPB) void k_blocks(BK b, int aw, double tau, int viscous, int copy_u0) {
+__global__ __launch_bounds__(TPB, 2) void k_blocks(BK b, int aw, double tau, int viscous, int copy_u0) {
     const BlockXY cb = xcd_block();
     LevelDev dv;
     if (!take(b, cb.y, dv)) return;
@@ -1067,33 +1095,21 @@ __global__ __launch_bounds__(TPB) void k_blocks(BK b, int aw, double tau, int vi
         c = 1.0 / geo[G_VOL * NS + s];
         diag = tau;
     }
-    // pass 1: D = c (((Xp_e - Xm_w) + Ep_n) - Em_s) + diag I; each face's
-    // other block is kept for its off-diagonal slot (pass 2)
-    double Ap[16], Am[16], acc[16], Bw[16], Be[16], Bs[16], Bn[16];
-    face_blocks(L, geo, u, cq, mut, ph, viscous, s, s + NJ, G_SXI_X, G_SXI_Y, s + NJ, Ap, Am);
+    // pass 1: D = c (((Xp_e - Xm_w) + Ep_n) - Em_s) + diag I, from the one
+    // half of each face's split Jacobian that falls on the diagonal
+    double H[16], acc[16];
+    face_blocks<1>(L, geo, u, cq, mut, ph, viscous, s, s + NJ, G_SXI_X, G_SXI_Y, s + NJ, H, nullptr);
 #pragma unroll
-    for (int k = 0; k < 16; ++k) {
-        acc[k] = Ap[k];
-        Be[k] = Am[k];
-    }
-    face_blocks(L, geo, u, cq, mut, ph, viscous, s - NJ, s, G_SXI_X, G_SXI_Y, s, Ap, Am);
+    for (int k = 0; k < 16; ++k) acc[k] = H[k];
+    face_blocks<2>(L, geo, u, cq, mut, ph, viscous, s - NJ, s, G_SXI_X, G_SXI_Y, s, nullptr, H);
 #pragma unroll
-    for (int k = 0; k < 16; ++k) {
-        acc[k] = acc[k] - Am[k];
-        Bw[k] = Ap[k];
-    }
-    face_blocks(L, geo, u, cq, mut, ph, viscous, s, s + NJ + 1, G_SETA_X, G_SETA_Y, s + NJ + 1, Ap, Am);
+    for (int k = 0; k < 16; ++k) acc[k] = acc[k] - H[k];
+    face_blocks<1>(L, geo, u, cq, mut, ph, viscous, s, s + NJ + 1, G_SETA_X, G_SETA_Y, s + NJ + 1, H, nullptr);
 #pragma unroll
-    for (int k = 0; k < 16; ++k) {
-        acc[k] = acc[k] + Ap[k];
-        Bn[k] = Am[k];
-    }
-    face_blocks(L, geo, u, cq, mut, ph, viscous, s - NJ - 1, s, G_SETA_X, G_SETA_Y, s, Ap, Am);
+    for (int k = 0; k < 16; ++k) acc[k] = acc[k] + H[k];
+    face_blocks<2>(L, geo, u, cq, mut, ph, viscous, s - NJ - 1, s, G_SETA_X, G_SETA_Y, s, nullptr, H);
 #pragma unroll
-    for (int k = 0; k < 16; ++k) {
-        acc[k] = acc[k] - Am[k];
-        Bs[k] = Ap[k];
-    }
+    for (int k = 0; k < 16; ++k) acc[k] = acc[k] - H[k];
     double D[16], Di[16];
 #pragma unroll
     for (int k = 0; k < 16; ++k) {
@@ -1123,23 +1139,40 @@ __global__ __launch_bounds__(TPB) void k_blocks(BK b, int aw, double tau, int vi
         }
     }
 #pragma unroll
-    for (int k = 0; k < 16; ++k) blk[BL<BT>::at(B_DINV, NS, s, k >> 2, k & 3)] = (BT)Di[k];
-    // pass 2: M_slot = D^-1 B_slot
+    for (int r = 0; r < 4; ++r) {
+        const double row[4] = {Di[r * 4], Di[r * 4 + 1], Di[r * 4 + 2], Di[r * 4 + 3]};
+        RowStore<BT>::put(blk, B_DINV, NS, s, r, row);
+    }
+    // pass 2: M_slot = D^-1 B_slot, each face's other half formed again (the
+    // same expressions, so the same values) instead of being kept live
+    // through the inversion: fewer registers, more waves per SIMD
     const bool has[4] = {i > 0, i < L.ni - 1, j > 0 || cut_col(L, i), j < L.nj - 1};
-#pragma unroll
+#pragma unroll 1
     for (int sl = 0; sl < 4; ++sl) {
         double B[16];
         if (has[sl]) {
+            if (sl == 0) {
+                face_blocks<1>(L, geo, u, cq, mut, ph, viscous, s - NJ, s, G_SXI_X, G_SXI_Y, s, H, nullptr);
 #pragma unroll
-            for (int k = 0; k < 16; ++k) {
-                if (sl == 0) B[k] = -(c * Bw[k]);
-                else if (sl == 1) B[k] = c * Be[k];
-                else if (sl == 2) B[k] = -(c * Bs[k]);
-                else B[k] = c * Bn[k];
+                for (int k = 0; k < 16; ++k) B[k] = -(c * H[k]);
+            } else if (sl == 1) {
+                face_blocks<2>(L, geo, u, cq, mut, ph, viscous, s, s + NJ, G_SXI_X, G_SXI_Y, s + NJ, nullptr, H);
+#pragma unroll
+                for (int k = 0; k < 16; ++k) B[k] = c * H[k];
+            } else if (sl == 2) {
+                face_blocks<1>(L, geo, u, cq, mut, ph, viscous, s - NJ - 1, s, G_SETA_X, G_SETA_Y, s, H, nullptr);
+#pragma unroll
+                for (int k = 0; k < 16; ++k) B[k] = -(c * H[k]);
+            } else {
+                face_blocks<2>(L, geo, u, cq, mut, ph, viscous, s, s + NJ + 1, G_SETA_X, G_SETA_Y, s + NJ + 1,
+                               nullptr, H);
+#pragma unroll
+                for (int k = 0; k < 16; ++k) B[k] = c * H[k];
             }
         }
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
+            double row[4];
 #pragma unroll
             for (int cc = 0; cc < 4; ++cc) {
                 double m = 0.0;
@@ -1147,8 +1180,9 @@ __global__ __launch_bounds__(TPB) void k_blocks(BK b, int aw, double tau, int vi
 #pragma unroll
                     for (int k = 0; k < 4; ++k) m = fma(Di[r * 4 + k], B[k * 4 + cc], m);
                 }
-                blk[BL<BT>::at(B_M0 + sl, NS, s, r, cc)] = (BT)m;
+                row[cc] = m;
             }
+            RowStore<BT>::put(blk, B_M0 + sl, NS, s, r, row);
         }
     }
 }
@@ -1238,9 +1272,13 @@ __global__ __launch_bounds__(TPB) void k_blocks_q(BK b, int aw, double tau, int 
         }
     }
     if (!valid) return;
+    {
+        double row[4];
 #pragma unroll
-    for (int k = 0; k < 16; ++k)
-        if ((k >> 2) == q) blk[BL<BT>::at(B_DINV, NS, s, k >> 2, k & 3)] = (BT)Di[k];
+        for (int k = 0; k < 16; ++k)
+            if ((k >> 2) == q) row[k & 3] = Di[k];
+        RowStore<BT>::put(blk, B_DINV, NS, s, q, row);
+    }
     // M_slot = D^-1 B_slot for this lane's face: slot 1 east, 0 west, 3 north,
     // 2 south; the west and south blocks enter with a minus sign
     const int sl = q == 0 ? 1 : q == 1 ? 0 : q == 2 ? 3 : 2;
@@ -1250,6 +1288,7 @@ __global__ __launch_bounds__(TPB) void k_blocks_q(BK b, int aw, double tau, int 
     for (int k = 0; k < 16; ++k) B[k] = plus ? c * Bf[k] : -(c * Bf[k]);
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
+        double row[4];
 #pragma unroll
         for (int cc = 0; cc < 4; ++cc) {
             double m = 0.0;
@@ -1257,8 +1296,9 @@ __global__ __launch_bounds__(TPB) void k_blocks_q(BK b, int aw, double tau, int 
 #pragma unroll
                 for (int k = 0; k < 4; ++k) m = fma(Di[r * 4 + k], B[k * 4 + cc], m);
             }
-            blk[BL<BT>::at(B_M0 + sl, NS, s, r, cc)] = (BT)m;
+            row[cc] = m;
         }
+        RowStore<BT>::put(blk, B_M0 + sl, NS, s, r, row);
     }
 }
 
