@@ -109,6 +109,7 @@ struct Ctx {
     double pr, prt, kappa2c;
     int rans, noslip, fine, viscous;
     int part;             // 0: F = f^c + f^v; 1: f^c alone; 2: f^v alone (Section 4.1 split)
+    int inv;              // 0: the face flux's inviscid part is left out (its derivative is zero)
     int si, sj;
     int gp[4], gs[4];     // geometry seeds: plane and slot of derivative lane k (-1: none)
 };
@@ -351,7 +352,13 @@ __device__ void face(const Ctx &c, int iL, int jL, int iR, int jR, int iLL, int 
     CQ L, R;
     cell_q<G>(c, iL, jL, L);
     cell_q<G>(c, iR, jR, R);
-    if (wall) {
+    if (!c.inv) {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            C[k] = dc(0.0);
+            V[k] = dc(0.0);
+        }
+    } else if (wall) {
         D4 pw = 0.5 * (L.p + R.p);
         C[0] = dc(0.0);
         C[1] = pw * sx;
@@ -464,6 +471,7 @@ __device__ void make_ctx(Ctx &c, const Lay &L, const double *geo, const double *
     c.fine = 1;
     c.viscous = ph.rans;
     c.part = 0;
+    c.inv = 1;
     c.si = c.sj = -1000000;
 #pragma unroll
     for (int k = 0; k < 4; ++k) c.gp[k] = c.gs[k] = -1;
@@ -528,6 +536,18 @@ __global__ __launch_bounds__(TPB) void k_vjp(Lay L, const double *geo, const dou
         }
     }
     if (q >= n) return;
+    // The inviscid part depends on the JST line (positions 0-3) only, the
+    // viscous part on L, R and the vertex cells (positions 1, 2, 4-7): a part
+    // whose cells do not include the seeded source has a zero derivative and
+    // is not evaluated.
+    bool dep_inv = false, dep_visc = false;
+    for (int p = 0; p < np; ++p) {
+        int ci, cj;
+        source_of(L, pi[p], pj[p], ci, cj);
+        const bool hit = ci == si && cj == sj;
+        if (p < 4) dep_inv = dep_inv || hit;
+        if (p == 1 || p == 2 || p >= 4) dep_visc = dep_visc || hit;
+    }
     const int NS = L.NS;
     const bool inL = interior(L, iL, jL), inR = interior(L, a, b);
     const int sL = L.slot(iL, jL);
@@ -542,6 +562,8 @@ __global__ __launch_bounds__(TPB) void k_vjp(Lay L, const double *geo, const dou
     make_ctx(c, L, geo, u, mut, ph);
     c.si = si;
     c.sj = sj;
+    c.inv = dep_inv;
+    c.viscous = ph.rans && dep_visc;
     const bool wall = !xi && b == 0 && !cut_col(L, a);
     D4 C[4], V[4];
     face<double>(c, iL, jL, a, b, iLL, jLL, iRR, jRR, xi, geo[(xi ? G_SXI_X : G_SETA_X) * NS + sf],
