@@ -160,7 +160,8 @@ struct fas_state_s {
     int *d_act = nullptr, *d_ndone = nullptr, *d_stat = nullptr;
     double *d_h0 = nullptr, *d_hist = nullptr;
     int hcap = 0;
-    int *h_act = nullptr;       // pinned
+    int *h_act = nullptr;       // pinned: two snapshots of the activity flag
+    hipEvent_t ev_chunk[2] = {nullptr, nullptr};
     hipStream_t cap_st = nullptr;
 };
 
@@ -171,7 +172,8 @@ struct fas_batch_s {
     int *d_act = nullptr, *d_ndone = nullptr, *d_stat = nullptr;
     double *d_h0 = nullptr, *d_hist = nullptr;
     int hcap = 0;
-    int *h_act = nullptr;       // pinned
+    int *h_act = nullptr;       // pinned: two snapshots of the activity flags
+    hipEvent_t ev_chunk[2] = {nullptr, nullptr};
     std::vector<void *> allocs;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
@@ -402,6 +404,8 @@ extern "C" void fas_state_destroy(fas_state s) {
     engine_release_events(s->e);
     if (s->cap_st) (void)hipStreamDestroy(s->cap_st);
     if (s->h_act) (void)hipHostFree(s->h_act);
+    for (hipEvent_t ev : s->ev_chunk)
+        if (ev) (void)hipEventDestroy(ev);
     for (auto p : s->allocs) (void)hipFree(p);
     delete s;
 }
@@ -500,8 +504,11 @@ extern "C" fas_status fas_state_create(fas_grid g, const fas_params *p, const do
     e.d_rb = reinterpret_cast<int *>(gc + 28);
     launch_fill_int(s->d_act, 1, 1, e.st);
     launch_fill_int(e.d_rb, 1, 0, e.st);
-    if (hipHostMalloc(reinterpret_cast<void **>(&s->h_act), sizeof(int), hipHostMallocDefault) != hipSuccess)
+    if (hipHostMalloc(reinterpret_cast<void **>(&s->h_act), 2 * sizeof(int), hipHostMallocDefault) != hipSuccess)
         return cleanup(fail(FAS_ENOMEM, "pinned allocation failed"));
+    for (hipEvent_t &ev : s->ev_chunk)
+        if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess)
+            return cleanup(fail(FAS_EDEVICE, "event creation failed"));
     for (int l = 0; l < s->nlev; ++l)
         e.lev.push_back(make_blev({s->lv[l].L}, dV + l, s->d_ph, s->d_act, e.d_cyc));
     if (set_phys(s) != FAS_OK) return cleanup(FAS_EDEVICE);
@@ -914,6 +921,41 @@ const char *status_message(int st) {
 // turns the replays after the stop into no-ops, so the iterates, history
 // and count are those of the direct launches.  The host reads the flag
 // every few cycles.
+// Up to max_cycles replays of one cycle (launch), in chunks of four with up
+// to two chunks queued: each chunk is followed by a copy of the m activity
+// flags into its own pinned slot and an event, and the host waits for the
+// older chunk while the newer one runs, so the device does not idle on the
+// host's check.  Stops once a snapshot shows no active case (the chunk still
+// queued then replays no-ops: every kernel skips inactive cases) or
+// max_cycles were launched; returns with every chunk complete.
+template <class Launch>
+static fas_status replay_chunks(hipStream_t st, int max_cycles, const int *d_act, int m, int *h_slots,
+                                hipEvent_t *ev, Launch launch) {
+    constexpr int CHECK = 4;
+    int launched = 0, queued = 0, head = 0;
+    for (;;) {
+        while (queued < 2 && launched < max_cycles) {
+            const int k = std::min(CHECK, max_cycles - launched);
+            for (int i = 0; i < k; ++i) STCHK(launch());
+            launched += k;
+            const int slot = (head + queued) & 1;
+            HIPCHK(hipMemcpyAsync(h_slots + slot * m, d_act, m * sizeof(int), hipMemcpyDeviceToHost, st));
+            HIPCHK(hipEventRecord(ev[slot], st));
+            ++queued;
+        }
+        if (queued == 0) return FAS_OK;
+        HIPCHK(hipEventSynchronize(ev[head]));
+        int any = 0;
+        for (int c = 0; c < m; ++c) any |= h_slots[head * m + c];
+        head ^= 1;
+        --queued;
+        if (!any) {
+            if (queued > 0) HIPCHK(hipEventSynchronize(ev[head]));
+            return FAS_OK;
+        }
+    }
+}
+
 static fas_status run_cycles(fas_state s, int32_t max_cycles, double drop_orders, double *res_hist,
                              int32_t *n_done, bool use_graph) {
     Engine &e = s->e;
@@ -953,26 +995,14 @@ static fas_status run_cycles(fas_state s, int32_t max_cycles, double drop_orders
             return fail(FAS_EDEVICE, std::string("graph capture failed: ") + hipGetErrorString(er));
         }
     }
-    const int check = 4;
-    fas_status st = FAS_OK;
-    for (int k = 0; k < max_cycles; ++k) {
+    fas_status st = replay_chunks(e.st, max_cycles, s->d_act, 1, s->h_act, s->ev_chunk, [&]() {
         if (use_graph) {
-            if (hipGraphLaunch(exec, e.st) != hipSuccess) {
-                st = fail(FAS_EDEVICE, "graph launch failed");
-                break;
-            }
+            if (hipGraphLaunch(exec, e.st) != hipSuccess) return fail(FAS_EDEVICE, "graph launch failed");
         } else {
             controlled_cycle(e, ctl);
         }
-        if ((k + 1) % check == 0 || k + 1 == max_cycles) {
-            if (hipMemcpyAsync(s->h_act, s->d_act, sizeof(int), hipMemcpyDeviceToHost, e.st) != hipSuccess ||
-                hipStreamSynchronize(e.st) != hipSuccess) {
-                st = fail(FAS_EDEVICE, "cycle replay failed");
-                break;
-            }
-            if (!*s->h_act) break;
-        }
-    }
+        return FAS_OK;
+    });
     (void)hipStreamSynchronize(e.st);
     if (exec) (void)hipGraphExecDestroy(exec);
     if (graph) (void)hipGraphDestroy(graph);
@@ -1742,6 +1772,8 @@ extern "C" void fas_batch_destroy(fas_batch b) {
     engine_release_events(b->e);
     for (auto p : b->allocs) (void)hipFree(p);
     if (b->h_act) (void)hipHostFree(b->h_act);
+    for (hipEvent_t ev : b->ev_chunk)
+        if (ev) (void)hipEventDestroy(ev);
     if (b->own_stream && b->e.st) (void)hipStreamDestroy(b->e.st);
     delete b;
 }
@@ -1879,8 +1911,11 @@ extern "C" fas_status fas_batch_create(int32_t n, const fas_state *states, void 
     if (hipMemcpy(dV, hV.data(), nl * sizeof(LevelDev), hipMemcpyHostToDevice) != hipSuccess ||
         hipMemcpy(dPH, hPH.data(), n * sizeof(Phys), hipMemcpyHostToDevice) != hipSuccess)
         return cleanup(fail(FAS_EDEVICE, "batch descriptor upload failed"));
-    if (hipHostMalloc(reinterpret_cast<void **>(&b->h_act), n * sizeof(int), hipHostMallocDefault) != hipSuccess)
+    if (hipHostMalloc(reinterpret_cast<void **>(&b->h_act), 2 * n * sizeof(int), hipHostMallocDefault) != hipSuccess)
         return cleanup(fail(FAS_ENOMEM, "pinned allocation failed"));
+    for (hipEvent_t &ev : b->ev_chunk)
+        if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess)
+            return cleanup(fail(FAS_EDEVICE, "event creation failed"));
     launch_fill_int(b->d_act, n, 1, e.st);
     launch_fill_int(e.d_rb, n, 0, e.st);
     // per level the first residual tile of each case (n + 1 entries), then
@@ -2189,17 +2224,8 @@ extern "C" fas_status fas_batch_solve(fas_batch b, int32_t max_cycles, double dr
     const int n = e.n;
     BatchCtl ctl;
     STCHK(batch_begin(b, max_cycles, drop_orders, use_graph, ctl));
-    const int check = 4;
-    for (int k = 0; k < max_cycles; ++k) {
-        STCHK(batch_cycle(b, ctl, use_graph));
-        if ((k + 1) % check == 0 || k + 1 == max_cycles) {
-            HIPCHK(hipMemcpyAsync(b->h_act, b->d_act, n * sizeof(int), hipMemcpyDeviceToHost, e.st));
-            HIPCHK(hipStreamSynchronize(e.st));
-            int any = 0;
-            for (int c = 0; c < n; ++c) any |= b->h_act[c];
-            if (!any) break;
-        }
-    }
+    STCHK(replay_chunks(e.st, max_cycles, b->d_act, n, b->h_act, b->ev_chunk,
+                        [&]() { return batch_cycle(b, ctl, use_graph); }));
     std::vector<int> nd(n), stv(n);
     STCHK(batch_collect(b, max_cycles, nd.data(), stv.data(), res_hist));
     int worst = FAS_OK;
