@@ -951,11 +951,8 @@ __global__ __launch_bounds__(TPB) void k_residual_q(BK b, ResArgs a) {
 // states, |A|_c = R |Lambda|_c R^-1 with the cutoff of eq. "cutoff"; here
 // |A|_c = |l1| I + (|l3| - |l1|) r3 l3^T + (|l4| - |l1|) r4 l4^T (same
 // matrix, the two acoustic projections written out).
-// HALF 0: both halves; 1: A+ only (into Ap); 2: A- only (into Am).  Each
-// entry is the same expression whichever halves are formed.
-template <int HALF>
-__device__ void split_face_h(const double UL[4], const double UR[4], double sx, double sy, double d,
-                             double qf, int ale, double Ap[16], double Am[16]) {
+__device__ void split_face(const double UL[4], const double UR[4], double sx, double sy, double d,
+                           double qf, int ale, double Ap[16], double Am[16]) {
     double ln = sqrt(sx * sx + sy * sy);
     double nx = sx / ln, ny = sy / ln;
     double U0 = 0.5 * (UL[0] + UR[0]), U1 = 0.5 * (UL[1] + UR[1]);
@@ -1000,15 +997,10 @@ __device__ void split_face_h(const double UL[4], const double UR[4], double sx, 
 #pragma unroll
         for (int c = 0; c < 4; ++c) {
             double absA = (r == c ? al[0] : 0.0) + c3 * r3[r] * l3[c] + c4 * r4[r] * l4[c];
-            if constexpr (HALF != 2) Ap[r * 4 + c] = ln * (0.5 * (A[r * 4 + c] + absA));
-            if constexpr (HALF != 1) Am[r * 4 + c] = ln * (0.5 * (A[r * 4 + c] - absA));
+            Ap[r * 4 + c] = ln * (0.5 * (A[r * 4 + c] + absA));
+            Am[r * 4 + c] = ln * (0.5 * (A[r * 4 + c] - absA));
         }
     }
-}
-
-__device__ inline void split_face(const double UL[4], const double UR[4], double sx, double sy, double d,
-                                  double qf, int ale, double Ap[16], double Am[16]) {
-    split_face_h<0>(UL, UR, sx, sy, d, qf, ale, Ap, Am);
 }
 
 // scalar thin-layer estimate of the viscous flux Jacobian of a face
@@ -1023,7 +1015,6 @@ __device__ double visc_face(const Lay &L, const double *geo, const double *u, co
     return ((mue * (GAM / ph.pr)) * s2) / (rf * vf);
 }
 
-template <int HALF = 0>
 __device__ void face_blocks(const Lay &L, const double *geo, const double *u, const double *cq,
                             const double *mut, const Phys &ph, int viscous, int sL, int sR,
                             int plane_x, int plane_y, int sf, double Ap[16], double Am[16]) {
@@ -1037,13 +1028,13 @@ __device__ void face_blocks(const Lay &L, const double *geo, const double *u, co
         const int wp = plane_x == G_SXI_X ? G_WIX : G_WJX;
         qf = geo[wp * NS + sf] * sx + geo[(wp + 1) * NS + sf] * sy;
     }
-    split_face_h<HALF>(UL, UR, sx, sy, ph.d_cut, qf, ph.ale, Ap, Am);
+    split_face(UL, UR, sx, sy, ph.d_cut, qf, ph.ale, Ap, Am);
     if (viscous) {
         double v = visc_face(L, geo, u, cq, mut, ph, sL, sR, sx, sy);
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
-            if constexpr (HALF != 2) Ap[k * 5] = Ap[k * 5] + v;
-            if constexpr (HALF != 1) Am[k * 5] = Am[k * 5] - v;
+            Ap[k * 5] = Ap[k * 5] + v;
+            Am[k * 5] = Am[k * 5] - v;
         }
     }
 }
@@ -1068,7 +1059,7 @@ template <> struct RowStore<double> {
 };
 
 template <typename BT>
-__global__ __launch_bounds__(TPB, 2) void k_blocks(BK b, int aw, double tau, int viscous, int copy_u0) {
+__global__ __launch_bounds__(TPB) void k_blocks(BK b, int aw, double tau, int viscous, int copy_u0) {
     const BlockXY cb = xcd_block();
     LevelDev dv;
     if (!take(b, cb.y, dv)) return;
@@ -1095,21 +1086,33 @@ __global__ __launch_bounds__(TPB, 2) void k_blocks(BK b, int aw, double tau, int
         c = 1.0 / geo[G_VOL * NS + s];
         diag = tau;
     }
-    // pass 1: D = c (((Xp_e - Xm_w) + Ep_n) - Em_s) + diag I, from the one
-    // half of each face's split Jacobian that falls on the diagonal
-    double H[16], acc[16];
-    face_blocks<1>(L, geo, u, cq, mut, ph, viscous, s, s + NJ, G_SXI_X, G_SXI_Y, s + NJ, H, nullptr);
+    // pass 1: D = c (((Xp_e - Xm_w) + Ep_n) - Em_s) + diag I; each face's
+    // other block is kept for its off-diagonal slot (pass 2)
+    double Ap[16], Am[16], acc[16], Bw[16], Be[16], Bs[16], Bn[16];
+    face_blocks(L, geo, u, cq, mut, ph, viscous, s, s + NJ, G_SXI_X, G_SXI_Y, s + NJ, Ap, Am);
 #pragma unroll
-    for (int k = 0; k < 16; ++k) acc[k] = H[k];
-    face_blocks<2>(L, geo, u, cq, mut, ph, viscous, s - NJ, s, G_SXI_X, G_SXI_Y, s, nullptr, H);
+    for (int k = 0; k < 16; ++k) {
+        acc[k] = Ap[k];
+        Be[k] = Am[k];
+    }
+    face_blocks(L, geo, u, cq, mut, ph, viscous, s - NJ, s, G_SXI_X, G_SXI_Y, s, Ap, Am);
 #pragma unroll
-    for (int k = 0; k < 16; ++k) acc[k] = acc[k] - H[k];
-    face_blocks<1>(L, geo, u, cq, mut, ph, viscous, s, s + NJ + 1, G_SETA_X, G_SETA_Y, s + NJ + 1, H, nullptr);
+    for (int k = 0; k < 16; ++k) {
+        acc[k] = acc[k] - Am[k];
+        Bw[k] = Ap[k];
+    }
+    face_blocks(L, geo, u, cq, mut, ph, viscous, s, s + NJ + 1, G_SETA_X, G_SETA_Y, s + NJ + 1, Ap, Am);
 #pragma unroll
-    for (int k = 0; k < 16; ++k) acc[k] = acc[k] + H[k];
-    face_blocks<2>(L, geo, u, cq, mut, ph, viscous, s - NJ - 1, s, G_SETA_X, G_SETA_Y, s, nullptr, H);
+    for (int k = 0; k < 16; ++k) {
+        acc[k] = acc[k] + Ap[k];
+        Bn[k] = Am[k];
+    }
+    face_blocks(L, geo, u, cq, mut, ph, viscous, s - NJ - 1, s, G_SETA_X, G_SETA_Y, s, Ap, Am);
 #pragma unroll
-    for (int k = 0; k < 16; ++k) acc[k] = acc[k] - H[k];
+    for (int k = 0; k < 16; ++k) {
+        acc[k] = acc[k] - Am[k];
+        Bs[k] = Ap[k];
+    }
     double D[16], Di[16];
 #pragma unroll
     for (int k = 0; k < 16; ++k) {
@@ -1143,31 +1146,18 @@ __global__ __launch_bounds__(TPB, 2) void k_blocks(BK b, int aw, double tau, int
         const double row[4] = {Di[r * 4], Di[r * 4 + 1], Di[r * 4 + 2], Di[r * 4 + 3]};
         RowStore<BT>::put(blk, B_DINV, NS, s, r, row);
     }
-    // pass 2: M_slot = D^-1 B_slot, each face's other half formed again (the
-    // same expressions, so the same values) instead of being kept live
-    // through the inversion: fewer registers, more waves per SIMD
+    // pass 2: M_slot = D^-1 B_slot
     const bool has[4] = {i > 0, i < L.ni - 1, j > 0 || cut_col(L, i), j < L.nj - 1};
-#pragma unroll 1
+#pragma unroll
     for (int sl = 0; sl < 4; ++sl) {
         double B[16];
         if (has[sl]) {
-            if (sl == 0) {
-                face_blocks<1>(L, geo, u, cq, mut, ph, viscous, s - NJ, s, G_SXI_X, G_SXI_Y, s, H, nullptr);
 #pragma unroll
-                for (int k = 0; k < 16; ++k) B[k] = -(c * H[k]);
-            } else if (sl == 1) {
-                face_blocks<2>(L, geo, u, cq, mut, ph, viscous, s, s + NJ, G_SXI_X, G_SXI_Y, s + NJ, nullptr, H);
-#pragma unroll
-                for (int k = 0; k < 16; ++k) B[k] = c * H[k];
-            } else if (sl == 2) {
-                face_blocks<1>(L, geo, u, cq, mut, ph, viscous, s - NJ - 1, s, G_SETA_X, G_SETA_Y, s, H, nullptr);
-#pragma unroll
-                for (int k = 0; k < 16; ++k) B[k] = -(c * H[k]);
-            } else {
-                face_blocks<2>(L, geo, u, cq, mut, ph, viscous, s, s + NJ + 1, G_SETA_X, G_SETA_Y, s + NJ + 1,
-                               nullptr, H);
-#pragma unroll
-                for (int k = 0; k < 16; ++k) B[k] = c * H[k];
+            for (int k = 0; k < 16; ++k) {
+                if (sl == 0) B[k] = -(c * Bw[k]);
+                else if (sl == 1) B[k] = c * Be[k];
+                else if (sl == 2) B[k] = -(c * Bs[k]);
+                else B[k] = c * Bn[k];
             }
         }
 #pragma unroll
