@@ -1058,6 +1058,53 @@ template <> struct RowStore<double> {
     }
 };
 
+// Block stores of k_blocks staged through the wave's LDS: every lane puts
+// its cell's record of a plane (64 bytes) into LDS, then each store
+// instruction writes 16 whole records, four lanes per record, so a cache
+// line is written by one instruction instead of in four partial pieces.
+// sc / vc: slot and validity of the cell whose record a lane writes in each
+// of the four rounds (cells 16 k + lane / 4).
+struct StageSlots {
+    int sc[4], vc[4];
+};
+// FP64: two half planes per block (columns 0-1 and 2-3)
+__device__ inline void block_out(double *blk, double *lds, const StageSlots &st, int b, int NS, int s,
+                                 const double (&v)[16]) {
+    const int lane = threadIdx.x & 63;
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        double2 *mine = reinterpret_cast<double2 *>(lds + lane * 8);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) mine[r] = make_double2(v[r * 4 + 2 * h], v[r * 4 + 2 * h + 1]);
+        __builtin_amdgcn_wave_barrier();
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const int c = k * 16 + (lane >> 2), q = lane & 3;
+            const double2 x = reinterpret_cast<const double2 *>(lds)[c * 4 + q];
+            if (st.vc[k]) reinterpret_cast<double2 *>(blk + ((size_t)(2 * b + h) * NS + st.sc[k]) * 8)[q] = x;
+        }
+        __builtin_amdgcn_wave_barrier();
+    }
+}
+// FP32: one plane per block, a cell's 16 values in 64 bytes
+__device__ inline void block_out(float *blk, double *ldsd, const StageSlots &st, int b, int NS, int s,
+                                 const double (&v)[16]) {
+    const int lane = threadIdx.x & 63;
+    float *lds = reinterpret_cast<float *>(ldsd);
+    float4 *mine = reinterpret_cast<float4 *>(lds + lane * 16);
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+        mine[r] = make_float4((float)v[r * 4], (float)v[r * 4 + 1], (float)v[r * 4 + 2], (float)v[r * 4 + 3]);
+    __builtin_amdgcn_wave_barrier();
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const int c = k * 16 + (lane >> 2), q = lane & 3;
+        const float4 x = reinterpret_cast<const float4 *>(lds)[c * 4 + q];
+        if (st.vc[k]) reinterpret_cast<float4 *>(blk + ((size_t)b * NS + st.sc[k]) * 16)[q] = x;
+    }
+    __builtin_amdgcn_wave_barrier();
+}
+
 template <typename BT>
 __global__ __launch_bounds__(TPB) void k_blocks(BK b, int aw, double tau, int viscous, int copy_u0) {
     const BlockXY cb = xcd_block();
@@ -1068,12 +1115,24 @@ __global__ __launch_bounds__(TPB) void k_blocks(BK b, int aw, double tau, int vi
     BT *blk = (BT *)dv.blk;
     const Phys ph = b.PH[cb.y];
     int s, i, j;
-    if (!interior_cell(L, cb.x * blockDim.x + threadIdx.x, s, i, j)) return;
+    // lanes past the last cell form cell 0 again and write nothing: the
+    // whole wave takes part in the staged block stores
+    const bool valid = interior_cell(L, cb.x * blockDim.x + threadIdx.x, s, i, j);
+    if (__builtin_amdgcn_ballot_w64(valid) == 0) return;
+    if (!valid) interior_cell(L, 0, s, i, j);
+    __shared__ __attribute__((aligned(16))) double lds[64 * 8];
+    StageSlots stg;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const int c = k * 16 + ((threadIdx.x & 63) >> 2);
+        stg.sc[k] = __shfl(s, c);
+        stg.vc[k] = __shfl((int)valid, c);
+    }
     const int NS = L.NS, NJ = L.NJ;
     // the iteration's frozen dt* (read by the stages' residuals and sweeps)
     const double dt_s = local_dt(ph, cfl_of(ph, b.cyc[cb.y]), geo, u, NS, s);
-    dv.dts[s] = dt_s;
-    if (copy_u0) {
+    if (valid) dv.dts[s] = dt_s;
+    if (copy_u0 && valid) {
 #pragma unroll
         for (int k = 0; k < 4; ++k) dv.u0[k * NS + s] = u[k * NS + s];
     }
@@ -1141,11 +1200,7 @@ __global__ __launch_bounds__(TPB) void k_blocks(BK b, int aw, double tau, int vi
             }
         }
     }
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-        const double row[4] = {Di[r * 4], Di[r * 4 + 1], Di[r * 4 + 2], Di[r * 4 + 3]};
-        RowStore<BT>::put(blk, B_DINV, NS, s, r, row);
-    }
+    block_out(blk, lds, stg, B_DINV, NS, s, Di);
     // pass 2: M_slot = D^-1 B_slot
     const bool has[4] = {i > 0, i < L.ni - 1, j > 0 || cut_col(L, i), j < L.nj - 1};
 #pragma unroll
@@ -1160,9 +1215,9 @@ __global__ __launch_bounds__(TPB) void k_blocks(BK b, int aw, double tau, int vi
                 else B[k] = c * Bn[k];
             }
         }
+        double M[16];
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-            double row[4];
 #pragma unroll
             for (int cc = 0; cc < 4; ++cc) {
                 double m = 0.0;
@@ -1170,10 +1225,10 @@ __global__ __launch_bounds__(TPB) void k_blocks(BK b, int aw, double tau, int vi
 #pragma unroll
                     for (int k = 0; k < 4; ++k) m = fma(Di[r * 4 + k], B[k * 4 + cc], m);
                 }
-                row[cc] = m;
+                M[r * 4 + cc] = m;
             }
-            RowStore<BT>::put(blk, B_M0 + sl, NS, s, r, row);
         }
+        block_out(blk, lds, stg, B_M0 + sl, NS, s, M);
     }
 }
 
