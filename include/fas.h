@@ -47,7 +47,7 @@ enum {                                         /* smoother (Table "RK smoothers"
     FAS_AW3 = 0, FAS_PARK3J = 1, FAS_AW5J = 2, FAS_AW51 = 3, FAS_AW52 = 4, FAS_PARK51 = 5
 };
 
-#define FAS_PARAMS_VERSION 3
+#define FAS_PARAMS_VERSION 4
 
 typedef struct {
     int32_t version;        /* FAS_PARAMS_VERSION */
@@ -99,6 +99,11 @@ typedef struct {
      * SGS blocks and dt* at its state from the last cycle).  The
      * preconditioner changes the iteration count, not the solution */
     int32_t adjoint_levels;
+    /* 1: the fine level's Baldwin-Lomax eddy viscosity is not evaluated
+     * again and keeps the values of its last evaluation (frozen
+     * turbulence: the model the adjoint differentiates); 0: evaluated at
+     * every residual evaluation's state, as in Section 2 */
+    int32_t freeze_mut;
 } fas_params;
 
 typedef struct fas_grid_s *fas_grid;     /* opaque, library owned */

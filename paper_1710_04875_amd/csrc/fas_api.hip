@@ -90,6 +90,7 @@ struct Engine {
     int bdf = 0;
     double dt = 0.0;
     int vblk = 0;               // viscous term in the preconditioner blocks (RANS)
+    int freeze_mut = 0;         // fine eddy viscosity kept at its last evaluation
     int stall_window = 0;       // stall test (0: off)
     double stall_orders = 0.0, growth_limit = 0.0;
     int *d_cyc = nullptr;       // [n]
@@ -216,6 +217,7 @@ extern "C" void fas_params_default(fas_params *p) {
     p->stall_orders = 0.0;
     p->growth_limit = 1.0e8;
     p->adjoint_levels = 0;
+    p->freeze_mut = 0;
 }
 
 // upload the nodes of every level (every 2^l-th node of the fine grid) and
@@ -344,6 +346,7 @@ static fas_status check_params(const fas_params *p, int grid_levels) {
     if (p->stall_window < 0 || !(p->stall_orders >= 0.0) || !(p->growth_limit >= 0.0))
         return fail(FAS_EINVAL, "bad stall or growth test");
     if (p->adjoint_levels < 0 || p->adjoint_levels > p->n_levels) return fail(FAS_EINVAL, "bad adjoint_levels");
+    if (p->freeze_mut != 0 && p->freeze_mut != 1) return fail(FAS_EINVAL, "bad freeze_mut");
     return FAS_OK;
 }
 
@@ -389,6 +392,7 @@ static fas_status set_phys(fas_state s) {
     e.nu1 = s->p.nu1;
     e.sc = SCHEMES[s->p.scheme];
     e.vblk = s->p.viscous_blocks;
+    e.freeze_mut = s->p.freeze_mut;
     e.stall_window = s->p.stall_window;
     e.stall_orders = s->p.stall_orders;
     e.growth_limit = s->p.growth_limit;
@@ -690,7 +694,7 @@ void prep(Engine &e, int l, bool with_bl) {
     const int rans = e.model == FAS_RANS_BL;
     launch_ghost_cq(B, rans, rans, e.st);
     if (rans) launch_vertex_gradients(B, e.st);
-    if (fine_rans(e, l) && with_bl) {
+    if (fine_rans(e, l) && with_bl && !e.freeze_mut) {
         launch_baldwin_lomax(B, e.st);
         launch_mut_ghosts(B, e.st);
     }
@@ -1821,10 +1825,11 @@ extern "C" fas_status fas_batch_create(int32_t n, const fas_state *states, void 
         if (s->p.model != s0->p.model || s->p.scheme != s0->p.scheme || s->nlev != s0->nlev ||
             s->p.cycle_gamma != s0->p.cycle_gamma || s->p.nu1 != s0->p.nu1 ||
             s->p.precond_fp32 != s0->p.precond_fp32 || s->p.viscous_blocks != s0->p.viscous_blocks ||
+            s->p.freeze_mut != s0->p.freeze_mut ||
             s->p.stall_window != s0->p.stall_window || s->p.stall_orders != s0->p.stall_orders ||
             s->p.growth_limit != s0->p.growth_limit)
             return fail(FAS_EINVAL, "batched states must share model, scheme, levels, cycle, precision, "
-                                    "preconditioner form and stopping tests");
+                                    "preconditioner form, turbulence freezing and stopping tests");
         if (s->e.bdf != 0 || s->ale)
             return fail(FAS_EINVAL, "batched states must be steady on fixed meshes (no dual time step, no motion)");
         for (int k = 0; k < c; ++k)
@@ -1883,6 +1888,7 @@ extern "C" fas_status fas_batch_create(int32_t n, const fas_state *states, void 
     e.nu1 = s0->p.nu1;
     e.sc = SCHEMES[s0->p.scheme];
     e.vblk = s0->p.viscous_blocks;
+    e.freeze_mut = s0->p.freeze_mut;
     e.stall_window = s0->p.stall_window;
     e.stall_orders = s0->p.stall_orders;
     e.growth_limit = s0->p.growth_limit;

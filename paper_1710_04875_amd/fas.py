@@ -19,7 +19,7 @@ FAS_OK, FAS_EINVAL, FAS_ENOMEM, FAS_EDEVICE, FAS_DIVERGED, FAS_STALLED, FAS_NOT_
 FAS_BOX, FAS_CGRID = 0, 1
 FAS_EULER, FAS_RANS_BL = 0, 1
 FAS_AW3, FAS_PARK3J, FAS_AW5J, FAS_AW51, FAS_AW52, FAS_PARK51 = range(6)
-PARAMS_VERSION = 3
+PARAMS_VERSION = 4
 
 _lib = None
 
@@ -42,6 +42,7 @@ class _Params(ctypes.Structure):
         ("precond_fp32", ctypes.c_int32), ("viscous_blocks", ctypes.c_int32), ("dt_form", ctypes.c_int32),
         ("stall_window", ctypes.c_int32), ("stall_orders", ctypes.c_double), ("growth_limit", ctypes.c_double),
         ("adjoint_levels", ctypes.c_int32),
+        ("freeze_mut", ctypes.c_int32),
     ]
 
 
@@ -72,6 +73,7 @@ class Params:
     stall_orders: float = 0.0
     growth_limit: float = 1.0e8
     adjoint_levels: int = 0
+    freeze_mut: int = 0
 
     def c(self) -> _Params:
         p = _Params()

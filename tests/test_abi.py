@@ -47,6 +47,7 @@ def test_params_layout_and_defaults():
     # stall test, divergence beyond a 1e8 growth
     assert (p.viscous_blocks, p.dt_form, p.stall_window, p.growth_limit) == (0, 1, 0, 1.0e8)
     assert p.adjoint_levels == 0             # adjoint preconditioner over every level
+    assert p.freeze_mut == 0                 # eddy viscosity follows the state
     assert ctypes.sizeof(fas._Params) == 160
     # the binding's defaults are the library's
     dflt = fas.Params()
