@@ -630,6 +630,68 @@ def adjoint_section(fas, torch, primal_cap, adj_cap):
                     "cell_products_per_s": round(cells / tv, 1)}}
 
 
+def adjoint_c2_section(fas, torch):
+    """A converged discrete adjoint on the 256 x 128 RANS workload (the
+    throughput case): the primal to 11 orders, the adjoint GMRES to 10
+    orders, and its lift gradient checked against central differences of
+    the frozen-turbulence primal (freeze_mut: the converged state's eddy
+    viscosity kept, the model the adjoint differentiates), each perturbed
+    solve started from the converged state and run to ten times its final
+    residual norm.  C_L(M) is strongly curved at this transonic condition,
+    so the Mach check extrapolates two step sizes (Richardson, O(h^2))."""
+    import dataclasses
+    import numpy as np
+    case, p = workload_params(fas, False)
+    x, y = case.grid()
+    g = fas.Grid(case.topology, x, y, case.n_wake, p.n_levels)
+    st = fas.State(g, p, torch.from_numpy(case.initial_state(x, y)).cuda())
+    log("adjoint 256x128: primal to 11 orders")
+    t0 = time.perf_counter()
+    hp, sp = st.cycle(3000, 11.0)
+    torch.cuda.synchronize()
+    tp = time.perf_counter() - t0
+    log("adjoint 256x128: lift gradient")
+    t0 = time.perf_counter()
+    cl0, grad, ha, sa = st.lift_gradient(3000, 10.0)
+    torch.cuda.synchronize()
+    tg = time.perf_counter() - t0
+    u0 = st.get_state().clone()
+    p0 = st.params
+    h_end = st.cycle(0)[0][0]
+    alpha, mach = p0.alpha_deg, p0.mach
+
+    def cl(a, m):
+        st.set_state(u0)
+        st.set_params(dataclasses.replace(p0, alpha_deg=a, mach=m, freeze_mut=1))
+        h0 = st.cycle(0)[0][0]
+        h, s = st.cycle(6000, float(np.log10(h0 / (10.0 * h_end))))
+        return st.forces()[0], int(s)
+
+    log("adjoint 256x128: frozen-turbulence central differences")
+    runs = {}
+    for key, (a, m) in {"a+": (alpha + 2e-2, mach), "a-": (alpha - 2e-2, mach), "m1+": (alpha, mach + 1e-3),
+                        "m1-": (alpha, mach - 1e-3), "m2+": (alpha, mach + 2e-3),
+                        "m2-": (alpha, mach - 2e-3)}.items():
+        runs[key] = cl(a, m)
+    fd_a = (runs["a+"][0] - runs["a-"][0]) / 4e-2
+    fd_m1 = (runs["m1+"][0] - runs["m1-"][0]) / 2e-3
+    fd_m2 = (runs["m2+"][0] - runs["m2-"][0]) / 4e-3
+    fd_m = (4.0 * fd_m1 - fd_m2) / 3.0
+    return {"workload": "steady RANS 256x128 C-grid (the throughput case), M=%.1f, alpha=%.4f deg; "
+                        "dC_L/d(alpha, M) by the discrete adjoint" % (mach, alpha),
+            "primal": {"cycles": len(hp) - 1, "status": int(sp), "seconds": round(tp, 3),
+                       "orders": round(float(np.log10(hp[0] / hp.min())), 2)},
+            "adjoint": {"iterations": len(ha) - 1, "status": int(sa), "seconds": round(tg, 3),
+                        "orders": round(float(np.log10(ha[0] / ha.min())), 2)},
+            "cl": cl0, "dcl_dalpha_deg": float(grad[0]), "dcl_dmach": float(grad[1]),
+            "frozen_turbulence_fd": {
+                "dcl_dalpha_deg": fd_a, "alpha_step_deg": 2e-2,
+                "rel_gap_alpha": abs(fd_a - grad[0]) / abs(fd_a),
+                "dcl_dmach_steps_1e-3_2e-3": [fd_m1, fd_m2], "dcl_dmach_extrapolated": fd_m,
+                "rel_gap_mach_extrapolated": abs(fd_m - grad[1]) / abs(fd_m),
+                "solves_converged": all(v[1] == 0 for v in runs.values())}}
+
+
 def _oracle_cycles(seconds_target):
     """The oracle (numpy + C sweep, one thread) on the first V-cycles of the
     workload: (cycles, seconds, fine cells)."""
@@ -736,7 +798,7 @@ def main():
     ap.add_argument("--no-dfa", action="store_true", help="skip the Fourier analysis section")
     ap.add_argument("--no-studies", action="store_true", help="skip the smoother comparison")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the 1024x256 adjoint section")
-    ap.add_argument("--adjoint-only", action="store_true", help="run only the 1024x256 adjoint section")
+    ap.add_argument("--adjoint-only", action="store_true", help="run only the two adjoint sections")
     ap.add_argument("--primal-cap", type=int, default=1000)
     ap.add_argument("--adjoint-cap", type=int, default=200)
     ap.add_argument("--dfa-only", action="store_true", help="run only the Fourier analysis section")
@@ -776,7 +838,8 @@ def main():
         kernels_only(fas, torch, args.kernels_only, args.steps)
         return
     if args.adjoint_only:
-        print(json.dumps({"adjoint_1024x256": adjoint_section(fas, torch, args.primal_cap, args.adjoint_cap)}),
+        print(json.dumps({"adjoint_256x128_converged": adjoint_c2_section(fas, torch),
+                          "adjoint_1024x256": adjoint_section(fas, torch, args.primal_cap, args.adjoint_cap)}),
               flush=True)
         return
     run_gpu.no_drop = args.no_drop
@@ -850,6 +913,7 @@ def main():
         log("discrete Fourier analysis")
         line["dfa"] = dfa_section(fas, torch)
     if not args.no_adjoint:
+        line["adjoint_256x128_converged"] = adjoint_c2_section(fas, torch)
         line["adjoint_1024x256"] = adjoint_section(fas, torch, args.primal_cap, args.adjoint_cap)
     if cpu is not None:
         line["cpu_baseline"] = cpu
