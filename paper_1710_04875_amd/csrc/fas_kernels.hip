@@ -568,7 +568,15 @@ __global__ __launch_bounds__(BL_TPB) void k_baldwin_lomax(BK b) {
     LevelDev d;
     if (!take(b, blockIdx.y, d)) return;
     const Lay L = d.L;
-    if ((int)blockIdx.x >= L.ni) return;
+    // Column order: workgroups go to the eight XCDs in turn, and a cache
+    // line of the skewed layout holds one cell of each of eight adjacent
+    // columns (slot(i - 1, j + 1) = slot(i, j) + 1), so each XCD takes a
+    // contiguous range of columns and its L2 serves their shared lines
+    // (with a row width that is a multiple of eight, the XCD of a workgroup
+    // is blockIdx.x mod 8; the map is a bijection of the row).
+    const int gx = gridDim.x;
+    const int i = gx % 8 == 0 ? (int)(blockIdx.x % 8) * (gx / 8) + (int)blockIdx.x / 8 : (int)blockIdx.x;
+    if (i >= L.ni) return;
     const double *geo = d.geo, *u = d.u, *cq = d.cq, *vg = d.vg;
     double *mut = d.mut;
     const Phys ph = b.PH[blockIdx.y];
@@ -576,7 +584,6 @@ __global__ __launch_bounds__(BL_TPB) void k_baldwin_lomax(BK b) {
     double *Fs = sh, *ys = sh + nj, *sp = sh + 2 * nj, *mi = sh + 3 * nj, *mo = sh + 4 * nj;
     __shared__ double s_fmax, s_ymax, s_udif;
     __shared__ int s_jc;
-    const int i = blockIdx.x;
     const bool cut = cut_col(L, i);
     auto omega = [&](int jj) {
         int s = L.slot(i, jj);
