@@ -558,32 +558,52 @@ __global__ void k_vertex_gradients(BK b) {
     for (int k = 0; k < 6; ++k) vg[k * NS + s] = g[k];
 }
 
-// Baldwin-Lomax algebraic eddy viscosity (Section 2), one workgroup per
-// i-column, j-cells walked from the wall / wake cut outward.  Ties in the
-// maximum of F and the first inner/outer crossover go to the lowest j; the
-// search is limited to the inner half of the column.
-constexpr int BL_TPB = 256;
+// Baldwin-Lomax algebraic eddy viscosity (Section 2), j-cells walked from
+// the wall / wake cut outward.  Ties in the maximum of F and the first
+// inner/outer crossover go to the lowest j; the search is limited to the
+// inner half of the column.
+//
+// A workgroup takes eight adjacent i-columns, 32 lanes each, lane l holding
+// rows l, l + 32, ... of its column in registers.  In the skewed layout a
+// cache line holds one cell of each of eight adjacent columns
+// (slot(i - 1, j + 1) = slot(i, j) + 1), so one load instruction of the
+// workgroup reads the same rows of eight adjacent columns from about 32
+// cache lines instead of 256.  The column searches are 32-lane reductions,
+// exact whatever their order (first j of the largest F, largest and
+// smallest speed, first crossover j), and every per-cell expression is the
+// scan's, so the eddy viscosity is that of a serial walk up the column.
+// Groups of eight columns go to the XCDs in contiguous ranges.
+constexpr int BL_TPB = 256, BL_COLS = 8, BL_LANES = 32;
+constexpr int BL_MAXK = 16;                 // rows per lane: nj <= 512
+
+// the scan's maximum of F: a NaN at the wall wins (a scan starting there
+// never moves on), other NaNs never win, otherwise the larger F and then the
+// smaller j; y is carried along with its row
+struct BlMax {
+    double f, y;
+    int j;
+};
+__device__ inline BlMax bl_better(BlMax a, BlMax b) {
+    const bool bn = b.f != b.f, an = a.f != a.f;
+    bool take;
+    if (bn || an) take = (bn && b.j == 0) || (!(an && a.j == 0) && !bn);
+    else take = b.f > a.f || (b.f == a.f && b.j < a.j);
+    return take ? b : a;
+}
+
 __global__ __launch_bounds__(BL_TPB) void k_baldwin_lomax(BK b) {
-    extern __shared__ double sh[];
     LevelDev d;
     if (!take(b, blockIdx.y, d)) return;
     const Lay L = d.L;
-    // Column order: workgroups go to the eight XCDs in turn, and a cache
-    // line of the skewed layout holds one cell of each of eight adjacent
-    // columns (slot(i - 1, j + 1) = slot(i, j) + 1), so each XCD takes a
-    // contiguous range of columns and its L2 serves their shared lines
-    // (with a row width that is a multiple of eight, the XCD of a workgroup
-    // is blockIdx.x mod 8; the map is a bijection of the row).
     const int gx = gridDim.x;
-    const int i = gx % 8 == 0 ? (int)(blockIdx.x % 8) * (gx / 8) + (int)blockIdx.x / 8 : (int)blockIdx.x;
-    if (i >= L.ni) return;
+    const int bx = gx % 8 == 0 ? (int)(blockIdx.x % 8) * (gx / 8) + (int)blockIdx.x / 8 : (int)blockIdx.x;
+    const int lane = threadIdx.x % BL_LANES;
+    const int i = bx * BL_COLS + (int)threadIdx.x / BL_LANES;
+    if (i >= L.ni) return;                  // a whole 32-lane group: its reductions stay inside it
     const double *geo = d.geo, *u = d.u, *cq = d.cq, *vg = d.vg;
     double *mut = d.mut;
     const Phys ph = b.PH[blockIdx.y];
     const int nj = L.nj, NS = L.NS, NJ = L.NJ;
-    double *Fs = sh, *ys = sh + nj, *sp = sh + 2 * nj, *mi = sh + 3 * nj, *mo = sh + 4 * nj;
-    __shared__ double s_fmax, s_ymax, s_udif;
-    __shared__ int s_jc;
     const bool cut = cut_col(L, i);
     auto omega = [&](int jj) {
         int s = L.slot(i, jj);
@@ -599,58 +619,69 @@ __global__ __launch_bounds__(BL_TPB) void k_baldwin_lomax(BK b) {
     const double rhow = u[s0];
     const double tauw = muw * omega(0);
     const double sq = sqrt(rhow * tauw);
-    for (int jj = threadIdx.x; jj < nj; jj += blockDim.x) {
-        int s = L.slot(i, jj);
-        double r = u[s];
-        double vx = u[NS + s] / r, vy = u[2 * NS + s] / r;
-        double om = omega(jj);
-        double y = geo[G_WD * NS + s];
-        double damp = 1.0;
-        if (!cut) {
-            double yplus = y * sq / muw;
-            damp = 1.0 - exp(-yplus / BL_APLUS);
+    const int jb = nj / 2, jlim = jb > 1 ? jb : 1;      // the scan starts at the wall cell
+    double yv[BL_MAXK], miv[BL_MAXK], rv[BL_MAXK];
+    BlMax m = {-INFINITY, 0.0, nj};
+    double smax = -INFINITY, smin = INFINITY;
+#pragma unroll
+    for (int k = 0; k < BL_MAXK; ++k) {
+        const int jj = lane + BL_LANES * k;
+        yv[k] = miv[k] = rv[k] = 0.0;
+        if (jj < nj) {
+            int s = L.slot(i, jj);
+            double r = u[s];
+            double vx = u[NS + s] / r, vy = u[2 * NS + s] / r;
+            double om = omega(jj);
+            double y = geo[G_WD * NS + s];
+            double damp = 1.0;
+            if (!cut) {
+                double yplus = y * sq / muw;
+                damp = 1.0 - exp(-yplus / BL_APLUS);
+            }
+            const double F = y * om * damp;
+            const double sp = sqrt(vx * vx + vy * vy);
+            double l = BL_KAPPA * y * damp;
+            yv[k] = y;
+            miv[k] = r * (l * l) * om;
+            rv[k] = r;
+            if (jj < jlim) {
+                m = bl_better(m, BlMax{F, y, jj});
+                smax = fmax(smax, sp);
+                smin = fmin(smin, sp);
+            }
         }
-        Fs[jj] = y * om * damp;
-        ys[jj] = y;
-        sp[jj] = sqrt(vx * vx + vy * vy);
-        double l = BL_KAPPA * y * damp;
-        mi[jj] = r * (l * l) * om;
     }
-    __syncthreads();
-    const int jb = nj / 2;
-    if (threadIdx.x == 0) {
-        int jm = 0;
-        double fbest = Fs[0], smax = sp[0], smin = sp[0];
-        for (int jj = 1; jj < jb; ++jj) {
-            if (Fs[jj] > fbest) { fbest = Fs[jj]; jm = jj; }
-            smax = fmax(smax, sp[jj]);
-            smin = fmin(smin, sp[jj]);
-        }
-        s_fmax = fbest;
-        s_ymax = ys[jm];
-        s_udif = smax - smin;
+#pragma unroll
+    for (int o = BL_LANES / 2; o > 0; o >>= 1) {
+        BlMax w;
+        w.f = __shfl_xor(m.f, o);
+        w.y = __shfl_xor(m.y, o);
+        w.j = __shfl_xor(m.j, o);
+        m = bl_better(m, w);
+        smax = fmax(smax, __shfl_xor(smax, o));
+        smin = fmin(smin, __shfl_xor(smin, o));
     }
-    __syncthreads();
-    const double fm = s_fmax, ymax = s_ymax, udif = s_udif;
+    const double fm = m.f, ymax = m.y, udif = smax - smin;
     const double fwake = fm > 0.0 ? fmin(ymax * fm, BL_CWK * ymax * udif * udif / fm) : 0.0;
-    for (int jj = threadIdx.x; jj < nj; jj += blockDim.x) {
-        double t = BL_CKLEB * ys[jj] / ymax;
+    auto outer = [&](int k) {
+        double t = BL_CKLEB * yv[k] / ymax;
         double t2 = t * t;
         double fk = 1.0 / (1.0 + 5.5 * (t2 * t2 * t2));
-        double r = u[L.slot(i, jj)];
-        mo[jj] = r * BL_K * BL_CCP * fwake * fk;
+        return rv[k] * BL_K * BL_CCP * fwake * fk;
+    };
+    int jc = jb;
+#pragma unroll
+    for (int k = 0; k < BL_MAXK; ++k) {
+        const int jj = lane + BL_LANES * k;
+        if (jj < jb && miv[k] >= outer(k)) jc = min(jc, jj);
     }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        int jc = jb;
-        for (int jj = 0; jj < jb; ++jj)
-            if (mi[jj] >= mo[jj]) { jc = jj; break; }
-        s_jc = jc;
+#pragma unroll
+    for (int o = BL_LANES / 2; o > 0; o >>= 1) jc = min(jc, __shfl_xor(jc, o));
+#pragma unroll
+    for (int k = 0; k < BL_MAXK; ++k) {
+        const int jj = lane + BL_LANES * k;
+        if (jj < nj) mut[L.slot(i, jj)] = jj < jc ? miv[k] : outer(k);
     }
-    __syncthreads();
-    const int jc = s_jc;
-    for (int jj = threadIdx.x; jj < nj; jj += blockDim.x)
-        mut[L.slot(i, jj)] = jj < jc ? mi[jj] : mo[jj];
 }
 
 // -------------------------------------------------------------- residual
@@ -2966,8 +2997,7 @@ void launch_vertex_gradients(const BLev &B, hipStream_t st) {
 }
 
 void launch_baldwin_lomax(const BLev &B, hipStream_t st) {
-    size_t shm = (size_t)5 * B.max_nj * sizeof(double);
-    hipLaunchKernelGGL(k_baldwin_lomax, dim3(B.max_ni, B.n), dim3(BL_TPB), shm, st, B.k);
+    hipLaunchKernelGGL(k_baldwin_lomax, dim3((B.max_ni + BL_COLS - 1) / BL_COLS, B.n), dim3(BL_TPB), 0, st, B.k);
 }
 
 void launch_mut_ghosts(const BLev &B, hipStream_t st) {
