@@ -2441,33 +2441,45 @@ __global__ void k_unpack(Lay L, const double *n, double *p, int nc) {
 // RMS of the density component of F over interior cells; fixed-order
 // two-pass reduction (deterministic).
 constexpr int RED_BLOCKS = 128;
+// RMS of the fine residual's first component over the interior: each
+// thread sums a strided share of the interior cells (hyperplane order, so a
+// wave's loads are consecutive slots), the wave adds its lanes by butterfly
+// shuffles, and lane 0's sum of the workgroup's waves (in wave order) is its
+// partial; k_norm2 adds the partials the same way.  Every order is fixed,
+// so the norm does not depend on scheduling.
 __global__ __launch_bounds__(TPB) void k_norm1(BK bk) {
-    __shared__ double sh[TPB];
+    __shared__ double sh[TPB / 64];
     LevelDev d;
     if (!take(bk, blockIdx.y, d)) return;
     const Lay L = d.L;
     const double *F = d.F;
+    const int n = L.ni * L.nj;
     double a = 0.0;
-    for (int s = blockIdx.x * blockDim.x + threadIdx.x; s < L.NS; s += gridDim.x * blockDim.x) {
-        int i, j;
-        if (decode(L, s, i, j) && interior(L, i, j)) a += F[s] * F[s];
+    for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < n; t += gridDim.x * blockDim.x) {
+        int s, i, j;
+        interior_cell(L, t, s, i, j);
+        a += F[s] * F[s];
     }
-    sh[threadIdx.x] = a;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) a += __shfl_xor(a, o);
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = a;
     __syncthreads();
-    for (int w = TPB / 2; w > 0; w >>= 1) {
-        if (threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
-        __syncthreads();
+    if (threadIdx.x == 0) {
+        double t = sh[0];
+#pragma unroll
+        for (int w = 1; w < TPB / 64; ++w) t += sh[w];
+        d.red[blockIdx.x] = t;
     }
-    if (threadIdx.x == 0) d.red[blockIdx.x] = sh[0];
 }
 
-__global__ void k_norm2(BK bk, double *out) {
+__global__ __launch_bounds__(64) void k_norm2(BK bk, double *out) {
     LevelDev d;
     if (!take(bk, blockIdx.x, d)) return;
-    if (threadIdx.x != 0) return;
     double a = 0.0;
-    for (int k = 0; k < RED_BLOCKS; ++k) a += d.red[k];
-    out[blockIdx.x] = sqrt(a / ((double)d.L.ni * d.L.nj));
+    for (int k = threadIdx.x; k < RED_BLOCKS; k += 64) a += d.red[k];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) a += __shfl_xor(a, o);
+    if (threadIdx.x == 0) out[blockIdx.x] = sqrt(a / ((double)d.L.ni * d.L.nj));
 }
 
 __global__ void k_count_cycle(BK bk, int *cyc, int n) {
