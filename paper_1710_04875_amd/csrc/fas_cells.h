@@ -71,6 +71,16 @@ __device__ inline BlockXY xcd_block() {
     return {(int)(v % gx), (int)(v / gx)};
 }
 
+// Column groups of the Baldwin-Lomax launch: a row of gx workgroups per
+// grid, gx a multiple of eight, so workgroup x of the row runs on XCD
+// x mod 8.  That XCD takes the contiguous range [(x mod 8) gx/8,
+// (x mod 8 + 1) gx/8) of column groups, whose cells share cache lines at
+// the range's interior; other widths keep their numbers.  A bijection of
+// 0 .. gx - 1.
+__device__ inline int xcd_range(int x, int gx) {
+    return gx % (int)XCD_COUNT == 0 ? x % (int)XCD_COUNT * (gx / (int)XCD_COUNT) + x / (int)XCD_COUNT : x;
+}
+
 // interior cells: 0 <= i < ni, 0 <= j < nj
 __device__ inline bool interior_cell(const Lay &L, int t, int &s, int &i, int &j) {
     return rect_cell(L, t, L.ni, L.nj, 0, s, i, j);

@@ -596,7 +596,7 @@ __global__ __launch_bounds__(BL_TPB) void k_baldwin_lomax(BK b) {
     if (!take(b, blockIdx.y, d)) return;
     const Lay L = d.L;
     const int gx = gridDim.x;
-    const int bx = gx % 8 == 0 ? (int)(blockIdx.x % 8) * (gx / 8) + (int)blockIdx.x / 8 : (int)blockIdx.x;
+    const int bx = xcd_range((int)blockIdx.x, gx);
     const int lane = threadIdx.x % BL_LANES;
     const int i = bx * BL_COLS + (int)threadIdx.x / BL_LANES;
     if (i >= L.ni) return;                  // a whole 32-lane group: its reductions stay inside it

@@ -9,7 +9,9 @@ up to 48 x 48 plus a few large and thin ones.  For each, the numbering must
 hit every cell of the rectangle exactly once, give strictly increasing slots
 (hyperplane order, j ascending inside a hyperplane), agree with decode(),
 and reject numbers past the last cell; the workgroup renumbering must be a
-bijection of every grid and hand one-row grids to the XCDs in runs."""
+bijection of every grid and hand one-row grids to the XCDs in runs, and the
+column-group map of the eddy-viscosity launch (xcd_range) must be a
+bijection that gives each XCD one contiguous range."""
 import os
 import re
 import shutil
@@ -86,6 +88,23 @@ int main() {
             for (long v = 0; v < full; ++v)
                 if (owner[v] != owner[v - v % run]) ++bad;
         }
+        ++grids;
+    }
+    // xcd_range: a bijection of every row width; for widths that are a
+    // multiple of eight, XCD x mod 8 holds one contiguous range of gx / 8
+    for (int gx = 1; gx <= 600; ++gx) {
+        std::vector<int> seen(gx, 0), lo(XCD_COUNT, gx), hi(XCD_COUNT, -1);
+        for (int x = 0; x < gx; ++x) {
+            const int v = xcd_range(x, gx);
+            if (v < 0 || v >= gx) { ++bad; continue; }
+            seen[v]++;
+            lo[x % XCD_COUNT] = std::min(lo[x % XCD_COUNT], v);
+            hi[x % XCD_COUNT] = std::max(hi[x % XCD_COUNT], v);
+        }
+        for (int c : seen) if (c != 1) ++bad;
+        if (gx % (int)XCD_COUNT == 0)
+            for (unsigned x = 0; x < XCD_COUNT; ++x)
+                if (hi[x] - lo[x] + 1 != gx / (int)XCD_COUNT || lo[x] != (int)x * (gx / (int)XCD_COUNT)) ++bad;
         ++grids;
     }
     std::printf("rectangles %ld grids %ld bad %ld\n", checked, grids, bad);
