@@ -793,6 +793,8 @@ def main():
                     help="solve every case of the FP64 per-case loop to the drop (minutes)")
     ap.add_argument("--no-unsteady", action="store_true", help="skip the pitching-airfoil section")
     ap.add_argument("--inner-cap", type=int, default=300)
+    ap.add_argument("--unsteady-adjoint-cap", type=int, default=100,
+                    help="adjoint iterations per step of the 512x128 unsteady adjoint")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only copy a 256 MiB buffer 5 times (HBM counter calibration)")
     ap.add_argument("--no-dfa", action="store_true", help="skip the Fourier analysis section")
@@ -908,7 +910,7 @@ def main():
                                                args.full_loop)
     if not args.no_unsteady:
         line["unsteady_pitching"] = unsteady_section(fas, torch, args.inner_cap)
-        line["unsteady_adjoint_512x128"] = unsteady_adjoint_section(fas, torch, 100, 100)
+        line["unsteady_adjoint_512x128"] = unsteady_adjoint_section(fas, torch, 100, args.unsteady_adjoint_cap)
     if not args.no_dfa:
         log("discrete Fourier analysis")
         line["dfa"] = dfa_section(fas, torch)
