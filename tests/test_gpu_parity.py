@@ -82,6 +82,24 @@ def test_c2_size_v_cycle_both_block_forms(vblk):
     assert abs(hist[1] - ho[1]) <= 1e-10 * ho[1]
 
 
+def test_c5_size_v_cycle():
+    """One 3-level V-cycle on the 1024 x 256 RANS C-grid of the adjoint
+    workload (262,144 fine cells: the tiled residual, the one-lane block
+    kernel and the banded sweeps of a 256-row grid), with the thin-layer
+    viscous blocks and the sum-form pseudo step that workload runs; every
+    level is compared."""
+    inp = case_inputs("cgrid_c5_rans")
+    g, st, S = make_pair(inp, n_levels=3, cycle_gamma=1, cfl=1.0, cfl_ramp=1.0, viscous_blocks=1, dt_form=0)
+    hist, status = st.cycle(1)
+    ho = S.run_cycles(1)
+    assert state_err(_np(st.get_state()), S.u(0)) < TOL_STATE
+    for l in range(1, 3):
+        ug, sg = st.get_level(l)
+        assert state_err(_np(ug), S.u(l)) < TOL_STATE
+    assert abs(hist[0] - ho[0]) <= 1e-12 * ho[0]
+    assert abs(hist[1] - ho[1]) <= 1e-10 * ho[1]
+
+
 @pytest.mark.parametrize("kind,levels,gamma", [("box_small", 2, 1), ("cgrid_small_rans", 3, 1),
                                                ("cgrid_small_euler", 3, 2)])
 def test_one_fas_cycle(kind, levels, gamma):
@@ -162,7 +180,7 @@ def test_pitching_moving_mesh_parity(kind):
         assert state_err(_np(st.get_state()), S.u(0)) < TOL_STATE, step
 
 
-@pytest.mark.parametrize("kind", ["cgrid_small_rans", "cgrid_c2_rans", "box"])
+@pytest.mark.parametrize("kind", ["cgrid_small_rans", "cgrid_c2_rans", "cgrid_c5_rans", "box"])
 def test_fp32_preconditioner_iteration_against_oracle(kind):
     """One AW3 iteration with the FP32 preconditioner (blocks, D^-1, both
     sweeps and x in FP32; residual and update in FP64) against the FP64
