@@ -22,7 +22,8 @@ def case_inputs(kind):
         return dict(topo=fi.BOX, x=x, y=y, nw=0, u0=fi.box_initial_state(x, y), model=0,
                     alpha=0.0)
     ni, nj, nw = {"cgrid_small": (64, 32, 8), "cgrid_mid": (128, 64, 16),
-                  "cgrid_c2": (256, 128, 32), "cgrid_c5": (1024, 256, 128)}[kind.rsplit("_", 1)[0] if kind.endswith(("_euler", "_rans")) else kind]
+                  "cgrid_c2": (256, 128, 32), "cgrid_c3": (512, 128, 64),
+                  "cgrid_c5": (1024, 256, 128)}[kind.rsplit("_", 1)[0] if kind.endswith(("_euler", "_rans")) else kind]
     x, y = fi.cgrid(ni, nj, nw)
     model = 0 if kind.endswith("_euler") else 1
     u0 = fi.perturbed_state(fi.uniform_state(ni, nj, 0.8, 1.3), 0.01, seed=11)

@@ -226,3 +226,25 @@ def test_fp32_and_fp64_preconditioners_converge_to_the_same_solution():
         assert status == fas.FAS_OK
         out.append(_np(st.get_state()))
     assert state_err(out[1], out[0]) < 1e-8
+
+
+def test_c3_size_pitching_steps():
+    """The pitching workload's grid at full size (512 x 128 RANS C-grid,
+    3 levels, viscous blocks and the sum-form pseudo step as that workload
+    runs them): two BDF time steps on the turning, spinning mesh, one inner
+    V-cycle each, against the oracle on every level."""
+    inp = case_inputs("cgrid_c3_rans")
+    g, st, S = make_pair(inp, n_levels=3, cycle_gamma=1, cfl=1.0, cfl_ramp=1.0, viscous_blocks=1, dt_form=0)
+    dt, amp, om = 0.46096, 1.0, 0.4
+    for step in range(2):
+        t = (step + 1) * dt
+        da, rate = amp * np.sin(om * t), amp * om * np.cos(om * t)
+        st.set_motion(da, rate)
+        st.dual_time_step(dt, inp["alpha"], 1, 0.0)
+        S.begin_time_step(dt, inp["alpha"])
+        S.set_motion(da, rate)
+        S.run_cycles(1)
+        assert state_err(_np(st.get_state()), S.u(0)) < TOL_STATE, step
+    for l in range(1, 3):
+        ug, sg = st.get_level(l)
+        assert state_err(_np(ug), S.u(l)) < TOL_STATE
