@@ -248,3 +248,18 @@ def test_c3_size_pitching_steps():
     for l in range(1, 3):
         ug, sg = st.get_level(l)
         assert state_err(_np(ug), S.u(l)) < TOL_STATE
+
+
+def test_c1_box_fifty_iterations():
+    """The single-grid smoother workload as the benchmark runs it: the 64 x 64
+    jittered Euler box from the bump-and-noise state, 50 AW3 iterations with
+    the SGS preconditioner (d 0.5, eta 0.5, c* 20 for two iterations, then
+    1e4); the state after all 50 and the residual history against the
+    oracle."""
+    inp = case_inputs("box")
+    g, st, S = make_pair(inp, n_levels=1, eta=0.5, d_cut=0.5, cfl=1.0e4, cfl_ramp=20.0, n_ramp=2)
+    hist, status = st.cycle(50)
+    ho = S.run_cycles(50)
+    assert len(hist) == len(ho) == 51
+    assert state_err(_np(st.get_state()), S.u(0)) < TOL_STATE
+    assert np.allclose(hist, ho, rtol=1e-10, atol=0.0)
