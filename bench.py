@@ -572,6 +572,46 @@ def unsteady_adjoint_section(fas, torch, inner_cap, adj_cap, steps=10, checkpoin
             "dJ_dalpha_deg": [float(v) for v in da] if (orders >= 8.0).all() else None}
 
 
+def unsteady_adjoint_c2_section(fas, torch, steps=10, checkpoint_every=2, adj_cap=2000):
+    """The checkpointed unsteady adjoint on the 256 x 128 RANS workload, whose
+    steady solve converges: the steady start to 11 orders, then 10 BDF steps
+    with the far-field angle alpha_0 + sin(2 k t) degrees (k = 0.2, dt =
+    0.460960, inner V-cycles to 11 orders or 300), the time-averaged lift and
+    its gradient with respect to M and every step's angle; every adjoint
+    solve to 8 orders or the cap, every second state kept.  The gradient is
+    reported only if every adjoint solve reached its drop."""
+    import numpy as np
+    case, p = workload_params(fas, False)
+    x, y = case.grid()
+    g = fas.Grid(case.topology, x, y, case.n_wake, p.n_levels)
+    st = fas.State(g, p, torch.from_numpy(case.initial_state(x, y)).cuda())
+    log("unsteady adjoint 256x128: steady start to 11 orders")
+    h0, s0 = st.cycle(3000, 11.0)
+    omega_t = 2 * 0.2 * p.mach * np.sqrt(1.4)
+    dt = 0.460960
+    alphas = [p.alpha_deg + float(np.sin(omega_t * n * dt)) for n in range(steps + 1)]
+    log("unsteady adjoint 256x128: %d steps forward, adjoint backward" % steps)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    J, dm, da, its, orders, rec = st.unsteady_lift_gradient(dt, alphas, max_inner=300, inner_drop=11.0,
+                                                            checkpoint_every=checkpoint_every,
+                                                            adj_max_iter=adj_cap, adj_drop=8.0)
+    torch.cuda.synchronize()
+    t = time.perf_counter() - t0
+    ok = bool((orders >= 8.0).all())
+    return {"workload": "RANS 256x128 C-grid (the throughput case), fixed mesh, far-field angle alpha0 + "
+                        "sin(2kt) deg, %d BDF steps (inner V-cycles to 11 orders or 300), time-averaged lift; "
+                        "adjoint solves to 8 orders or %d iterations, every %d-th state kept"
+                        % (steps, adj_cap, checkpoint_every),
+            "steady_start": {"cycles": len(h0) - 1, "status": int(s0),
+                             "orders": round(float(np.log10(h0[0] / np.nanmin(h0))), 2)},
+            "seconds": round(t, 3), "recomputed_steps": int(rec),
+            "adjoint_iterations_per_step": [int(v) for v in its],
+            "adjoint_orders_per_step": [round(float(v), 2) for v in orders],
+            "converged": ok, "J_mean_cl": J, "dJ_dmach": dm if ok else None,
+            "dJ_dalpha_deg": [float(v) for v in da] if ok else None}
+
+
 def adjoint_section(fas, torch, primal_cap, adj_cap):
     """Discrete adjoint of the lift on the 1024 x 256 C-grid (n_w = 128),
     RANS, M = 0.8, alpha ~ U[0, 2] deg (seed 5), FP64 residual with the FP32
@@ -911,6 +951,7 @@ def main():
     if not args.no_unsteady:
         line["unsteady_pitching"] = unsteady_section(fas, torch, args.inner_cap)
         line["unsteady_adjoint_512x128"] = unsteady_adjoint_section(fas, torch, 100, args.unsteady_adjoint_cap)
+        line["unsteady_adjoint_256x128_converged"] = unsteady_adjoint_c2_section(fas, torch)
     if not args.no_dfa:
         log("discrete Fourier analysis")
         line["dfa"] = dfa_section(fas, torch)
